@@ -1,0 +1,178 @@
+/*
+ * phg.h -- C ABI of the MI355X (gfx950) phylogenetic likelihood-gradient library.
+ *
+ * Computes, for a rooted bifurcating tree, a reversible or general CTMC given by
+ * its eigensystem, discrete rate categories and an alignment of weighted site
+ * patterns, the log-likelihood log P(Y) and its derivative with respect to every
+ * branch length, in time linear in the number of tips (Gangavarapu et al.,
+ * "Many-core algorithms for high-dimensional gradients on phylogenetic trees",
+ * arXiv:2303.04390, Methods section: pruning equation, sequence-likelihood
+ * equation, eq:preorder, eq:gradient and eq:gradientSumAcrossColumns).
+ *
+ * Conventions (Methods, labelling paragraph, written 0-based):
+ *   - N tips are nodes 0..N-1, internal nodes N..2N-3, the root is 2N-2.
+ *   - Every non-root node x owns the branch to its parent; branch lengths and
+ *     gradients are arrays of length 2N-2 indexed by child node x.
+ *   - An unrooted tree is a rooted one with one root branch of length zero.
+ *   - S states (2..64), R rate categories (1..16), C site patterns (>= 1).
+ *
+ * General rules for every call:
+ *   - Every call returns a phg_status; PHG_OK (0) on success, a negative code
+ *     otherwise, with a message available from phg_last_error().
+ *   - Every input array is copied before the call returns; the caller keeps
+ *     ownership of its memory and may free or reuse it at once.
+ *   - Output arrays are caller-allocated.  Host pointers unless stated.
+ *   - No C++ exception crosses this boundary.
+ *   - A context is used from one thread at a time; distinct contexts are
+ *     independent and may be used concurrently.
+ *   - Inputs are validated on the host (no device work) when they are set;
+ *     the device is first touched by a compute call (or phg_prepare).
+ */
+#ifndef PHG_H
+#define PHG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PHG_OK = 0,
+    PHG_ERR_ARG = -1,      /* invalid argument: sizes, topology, values out of range */
+    PHG_ERR_STATE = -2,    /* compute requested before every required input was set */
+    PHG_ERR_OOM = -3,      /* device allocation failed or bound workspace too small */
+    PHG_ERR_DEVICE = -4,   /* no usable gfx950 device, or a HIP runtime error */
+    PHG_ERR_NUMERIC = -5,  /* some weighted site likelihood is zero or not finite */
+    PHG_ERR_BUSY = -6      /* resource temporarily unavailable (serving queue full) */
+} phg_status;
+
+typedef enum {
+    PHG_FP64 = 0,          /* partials, P(t) and reductions in float64 */
+    PHG_FP32_SCALED = 1    /* partials and P(t) copies in float32 with per-node,
+                              per-pattern power-of-two rescaling shared across
+                              categories; P(t) built in float64; per-pattern
+                              ratios and all reductions in float64 */
+} phg_precision;
+
+typedef struct phg_context phg_context;
+
+/* Create a context for one (tree, alignment) problem of fixed sizes.
+ * n_tips >= 2, n_patterns >= 1, 2 <= n_states <= 64, 1 <= n_categories <= 16,
+ * device = HIP device ordinal.  *out receives the context (NULL on error).
+ * Host-only: no device work happens here. */
+phg_status phg_create(int n_tips, int n_patterns, int n_states, int n_categories,
+                      phg_precision prec, int device, phg_context **out);
+
+/* Release the context and every device buffer it allocated.  Accepts NULL. */
+phg_status phg_destroy(phg_context *ctx);
+
+/* Message describing the last error on ctx (or on context creation when ctx
+ * is NULL).  Owned by the library; valid until the next call on ctx. */
+const char *phg_last_error(const phg_context *ctx);
+
+/* Tree topology (Methods, labelling paragraph).  parent has 2N-1 entries:
+ * parent[root = 2N-2] = -1; every other node's parent is an internal node or
+ * the root; tips have no children; internal nodes and the root have exactly two;
+ * no cycles.  PHG_ERR_ARG otherwise. */
+phg_status phg_set_topology(phg_context *ctx, const int32_t *parent);
+
+/* Branch lengths b[x], x = 0..2N-3, indexed by child node (Methods).  Each
+ * must be finite and >= 0.  Cheap to call repeatedly (e.g. per HMC step). */
+phg_status phg_set_branch_lengths(phg_context *ctx, const double *b);
+
+/* Substitution model through its eigensystem: Q = V diag(lambda) Vinv, so
+ * P^(r)(b) = exp(gamma_r b Q) = V diag(exp(gamma_r b lambda)) Vinv (Methods,
+ * equation for P).  V and Vinv are S*S row-major, lambda has S entries; all
+ * finite.  The library does not check that Vinv inverts V. */
+phg_status phg_set_eigen(phg_context *ctx, const double *V, const double *Vinv,
+                         const double *lambda);
+
+/* Root prior pi (S entries, finite, >= 0), the q vector at the root
+ * (Methods, sequence-likelihood equation and eq:preorder). */
+phg_status phg_set_root_frequencies(phg_context *ctx, const double *pi);
+
+/* Discrete rate categories: rates gamma_r (finite, >= 0) and probabilities
+ * P(gamma_r) (finite, >= 0), R entries each (Methods, rate-variation
+ * paragraph; Q^(r) = gamma_r Q). */
+phg_status phg_set_categories(phg_context *ctx, const double *rates,
+                              const double *weights);
+
+/* Observed tip states (Methods, alignment paragraph; compact integer tip
+ * states of the gradient-kernel section).  codes is N*C, tip-major
+ * (codes[tip*C + c]); each value is 0..S-1, or S for a fully ambiguous
+ * entry whose partial is all ones. */
+phg_status phg_set_tip_states(phg_context *ctx, const int32_t *codes);
+
+/* Pattern weights W_c (C entries, finite, >= 0): the multiplicity of each
+ * unique column (Methods, pattern-compression remark).  A zero-weight
+ * pattern contributes nothing, even if its likelihood is zero.
+ * Defaults to all ones. */
+phg_status phg_set_pattern_weights(phg_context *ctx, const double *w);
+
+/* Allocate device memory and upload inputs without computing.  Optional. */
+phg_status phg_prepare(phg_context *ctx);
+
+/* log P(Y) = sum_c W_c log sum_r P(gamma_r) p_root,r,c . pi.  Synchronous.
+ * PHG_ERR_STATE until topology, branch lengths, eigensystem, root
+ * frequencies, categories and tip states are all set.  If a weighted site
+ * likelihood is zero or not finite, *logl = -inf and PHG_ERR_NUMERIC. */
+phg_status phg_log_likelihood(phg_context *ctx, double *logl);
+
+/* log P(Y) (if logl is not NULL) and grad[x] = d log P(Y) / d b_x for all
+ * 2N-2 branches (eq:gradient summed by eq:gradientSumAcrossColumns).
+ * Synchronous.  On PHG_ERR_NUMERIC, *logl = -inf and grad is all NaN. */
+phg_status phg_gradient(phg_context *ctx, double *logl, double *grad);
+
+/* ---- device-side variants (memory and streams owned by the caller) ---- */
+
+/* Bytes of device workspace a context of these sizes needs. */
+phg_status phg_workspace_size(int n_tips, int n_patterns, int n_states,
+                              int n_categories, phg_precision prec, size_t *bytes);
+
+/* Use caller-owned device memory (>= phg_workspace_size bytes, 256-byte
+ * aligned) instead of allocating.  It must outlive every later compute call.
+ * Must be called before the first compute call / phg_prepare. */
+phg_status phg_bind_workspace(phg_context *ctx, void *device_ptr, size_t bytes);
+
+/* Issue all later device work on this hipStream_t (NULL = the library's own
+ * stream).  The stream must outlive its use by the context. */
+phg_status phg_bind_stream(phg_context *ctx, void *hip_stream);
+
+/* Enqueue logL + gradient on the bound stream and return without waiting.
+ * d_logl (1 double) and d_grad (2N-2 doubles) are device pointers; they are
+ * valid once the stream reaches this point.  Host inputs set before this call
+ * are uploaded first, in stream order.  No numeric check is done (inspect
+ * *d_logl: -inf or NaN signals a zero site likelihood). */
+phg_status phg_gradient_async(phg_context *ctx, double *d_logl, double *d_grad);
+
+/* Wall-clock-free introspection: number of kernel launches one gradient call
+ * issues and the post-/pre-order level counts of the current topology. */
+phg_status phg_schedule_info(phg_context *ctx, int *n_post_levels,
+                             int *n_pre_levels, int *n_launches);
+
+/* ---- measurement ---- */
+
+/* Kernel classes timed by the profiler, in the order of one evaluation. */
+enum { PHG_PROF_PMAT = 0, PHG_PROF_POST = 1, PHG_PROF_PRE = 2, PHG_PROF_FINAL = 3,
+       PHG_PROF_CLASSES = 4 };
+
+/* on != 0: every later evaluation records HIP events on the context's stream
+ * around each kernel class (P(t); post-order levels incl. the root; pre-order
+ * + gradient levels; final sums).  on == 0 stops recording.  Recording adds
+ * event records between launches and nothing else. */
+phg_status phg_profile_enable(phg_context *ctx, int on);
+
+/* Wait for the recorded evaluations, then write the summed device time in
+ * milliseconds of each kernel class into ms[0..PHG_PROF_CLASSES-1], the
+ * number of evaluations recorded into *n_evals and the number of kernel
+ * launches per class per evaluation into launches[0..3] (either pointer may
+ * be NULL).  Clears the record. */
+phg_status phg_profile_read(phg_context *ctx, double *ms, int *n_evals, int *launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PHG_H */

@@ -1,0 +1,280 @@
+"""ctypes binding over libphg.so with the C ABI's names (argument marshalling only).
+
+Every function takes numpy arrays (host inputs) or integer device pointers
+(``phg_gradient_async``, ``phg_bind_workspace``, ``phg_bind_stream``) and
+raises ``PhgError`` carrying the status code and the library's message when
+a call does not return PHG_OK.  All computation happens in the library's HIP
+kernels; there is no Python or CPU fallback: if libphg.so is missing the
+import of this module's loader fails loudly.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libphg.so")
+
+PHG_OK = 0
+PHG_ERR_ARG = -1
+PHG_ERR_STATE = -2
+PHG_ERR_OOM = -3
+PHG_ERR_DEVICE = -4
+PHG_ERR_NUMERIC = -5
+PHG_ERR_BUSY = -6
+PHG_FP64 = 0
+PHG_FP32_SCALED = 1
+
+STATUS_NAMES = {0: "PHG_OK", -1: "PHG_ERR_ARG", -2: "PHG_ERR_STATE", -3: "PHG_ERR_OOM",
+                -4: "PHG_ERR_DEVICE", -5: "PHG_ERR_NUMERIC", -6: "PHG_ERR_BUSY"}
+
+
+class PhgError(RuntimeError):
+    def __init__(self, status: int, message: str, where: str):
+        self.status = status
+        self.message = message
+        super().__init__(f"{where}: {STATUS_NAMES.get(status, status)}: {message}")
+
+
+_lib = None
+_c = ctypes
+_dp = ctypes.POINTER(ctypes.c_double)
+_ip = ctypes.POINTER(ctypes.c_int32)
+_vp = ctypes.c_void_p
+
+_SIGS = {
+    "phg_create": [_c.c_int, _c.c_int, _c.c_int, _c.c_int, _c.c_int, _c.c_int, _c.POINTER(_vp)],
+    "phg_destroy": [_vp],
+    "phg_last_error": [_vp],
+    "phg_set_topology": [_vp, _ip],
+    "phg_set_branch_lengths": [_vp, _dp],
+    "phg_set_eigen": [_vp, _dp, _dp, _dp],
+    "phg_set_root_frequencies": [_vp, _dp],
+    "phg_set_categories": [_vp, _dp, _dp],
+    "phg_set_tip_states": [_vp, _ip],
+    "phg_set_pattern_weights": [_vp, _dp],
+    "phg_prepare": [_vp],
+    "phg_log_likelihood": [_vp, _dp],
+    "phg_gradient": [_vp, _dp, _dp],
+    "phg_workspace_size": [_c.c_int, _c.c_int, _c.c_int, _c.c_int, _c.c_int, _c.POINTER(_c.c_size_t)],
+    "phg_bind_workspace": [_vp, _vp, _c.c_size_t],
+    "phg_bind_stream": [_vp, _vp],
+    "phg_gradient_async": [_vp, _vp, _vp],
+    "phg_schedule_info": [_vp, _c.POINTER(_c.c_int), _c.POINTER(_c.c_int), _c.POINTER(_c.c_int)],
+    "phg_profile_enable": [_vp, _c.c_int],
+    "phg_profile_read": [_vp, _dp, _c.POINTER(_c.c_int), _c.POINTER(_c.c_int)],
+}
+
+PHG_PROF_CLASSES = 4
+PROF_NAMES = ("pmat", "post", "pre_grad", "finalize")
+
+
+def lib():
+    """Load libphg.so (built in-tree by paper_2303_04390_amd.build)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_2303_04390_amd.build` (no fallback exists)")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, args in _SIGS.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = ctypes.c_char_p if name == "phg_last_error" else ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _check(status: int, ctx, where: str):
+    if status != PHG_OK:
+        msg = lib().phg_last_error(ctx)
+        raise PhgError(status, (msg or b"").decode(), where)
+
+
+def _f64(a, n: Optional[int] = None):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if n is not None and a.size != n:
+        raise ValueError(f"expected {n} values, got {a.size}")
+    return a
+
+
+def _i32(a, n: Optional[int] = None):
+    a = np.ascontiguousarray(a, dtype=np.int32)
+    if n is not None and a.size != n:
+        raise ValueError(f"expected {n} values, got {a.size}")
+    return a
+
+
+def _p(a):
+    return a.ctypes.data_as(_dp if a.dtype == np.float64 else _ip)
+
+
+# ------------------------------------------------------------ C ABI, same names
+
+def phg_create(n_tips, n_patterns, n_states, n_categories, prec, device=0):
+    out = _vp()
+    st = lib().phg_create(n_tips, n_patterns, n_states, n_categories, prec, device,
+                          ctypes.byref(out))
+    _check(st, None, "phg_create")
+    return out
+
+
+def phg_destroy(ctx):
+    lib().phg_destroy(ctx)
+
+
+def phg_last_error(ctx=None) -> str:
+    return (lib().phg_last_error(ctx) or b"").decode()
+
+
+def phg_set_topology(ctx, parent):
+    a = _i32(parent)
+    _check(lib().phg_set_topology(ctx, _p(a)), ctx, "phg_set_topology")
+
+
+def phg_set_branch_lengths(ctx, b):
+    a = _f64(b)
+    _check(lib().phg_set_branch_lengths(ctx, _p(a)), ctx, "phg_set_branch_lengths")
+
+
+def phg_set_eigen(ctx, V, Vinv, lam):
+    a, b, c = _f64(V), _f64(Vinv), _f64(lam)
+    _check(lib().phg_set_eigen(ctx, _p(a), _p(b), _p(c)), ctx, "phg_set_eigen")
+
+
+def phg_set_root_frequencies(ctx, pi):
+    a = _f64(pi)
+    _check(lib().phg_set_root_frequencies(ctx, _p(a)), ctx, "phg_set_root_frequencies")
+
+
+def phg_set_categories(ctx, rates, weights):
+    a, b = _f64(rates), _f64(weights)
+    _check(lib().phg_set_categories(ctx, _p(a), _p(b)), ctx, "phg_set_categories")
+
+
+def phg_set_tip_states(ctx, codes):
+    a = _i32(codes)
+    _check(lib().phg_set_tip_states(ctx, _p(a)), ctx, "phg_set_tip_states")
+
+
+def phg_set_pattern_weights(ctx, w):
+    a = _f64(w)
+    _check(lib().phg_set_pattern_weights(ctx, _p(a)), ctx, "phg_set_pattern_weights")
+
+
+def phg_prepare(ctx):
+    _check(lib().phg_prepare(ctx), ctx, "phg_prepare")
+
+
+def phg_log_likelihood(ctx) -> float:
+    v = ctypes.c_double()
+    _check(lib().phg_log_likelihood(ctx, ctypes.byref(v)), ctx, "phg_log_likelihood")
+    return v.value
+
+
+def phg_gradient(ctx, n_branches: int, want_logl: bool = True):
+    """Returns (logl, grad[n_branches])."""
+    g = np.empty(n_branches, np.float64)
+    v = ctypes.c_double()
+    st = lib().phg_gradient(ctx, ctypes.byref(v) if want_logl else None, _p(g))
+    _check(st, ctx, "phg_gradient")
+    return v.value, g
+
+
+def phg_workspace_size(n_tips, n_patterns, n_states, n_categories, prec) -> int:
+    v = ctypes.c_size_t()
+    st = lib().phg_workspace_size(n_tips, n_patterns, n_states, n_categories, prec, ctypes.byref(v))
+    _check(st, None, "phg_workspace_size")
+    return v.value
+
+
+def phg_bind_workspace(ctx, device_ptr: int, nbytes: int):
+    _check(lib().phg_bind_workspace(ctx, _vp(device_ptr), nbytes), ctx, "phg_bind_workspace")
+
+
+def phg_bind_stream(ctx, hip_stream: int):
+    _check(lib().phg_bind_stream(ctx, _vp(hip_stream)), ctx, "phg_bind_stream")
+
+
+def phg_gradient_async(ctx, d_logl: int, d_grad: int):
+    _check(lib().phg_gradient_async(ctx, _vp(d_logl), _vp(d_grad)), ctx, "phg_gradient_async")
+
+
+def phg_schedule_info(ctx):
+    a, b, c = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    _check(lib().phg_schedule_info(ctx, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)), ctx,
+           "phg_schedule_info")
+    return a.value, b.value, c.value
+
+
+def phg_profile_enable(ctx, on: bool):
+    _check(lib().phg_profile_enable(ctx, 1 if on else 0), ctx, "phg_profile_enable")
+
+
+def phg_profile_read(ctx):
+    """Returns (ms[4] summed per kernel class, n_evals, launches[4] per eval)."""
+    ms = np.zeros(PHG_PROF_CLASSES, np.float64)
+    n = ctypes.c_int()
+    launches = np.zeros(PHG_PROF_CLASSES, np.int32)
+    _check(lib().phg_profile_read(ctx, _p(ms), ctypes.byref(n), _p(launches)), ctx,
+           "phg_profile_read")
+    return ms, n.value, launches
+
+
+# ------------------------------------------------------------ convenience
+
+def set_problem(h, prob):
+    """Marshal every input of a synthetic Problem (or any object with the
+    same fields) into context handle h."""
+    phg_set_topology(h, prob.parent)
+    phg_set_branch_lengths(h, prob.b)
+    phg_set_eigen(h, prob.V, prob.Vinv, prob.lam)
+    phg_set_root_frequencies(h, prob.pi)
+    phg_set_categories(h, prob.rates, prob.weights)
+    phg_set_tip_states(h, prob.codes)
+    phg_set_pattern_weights(h, prob.pattern_weights)
+
+
+class Context:
+    """Owns one phg_context; ``set_problem`` marshals every input of a
+    synthetic Problem (or any object with the same fields)."""
+
+    def __init__(self, n_tips, n_patterns, n_states, n_categories, prec=PHG_FP32_SCALED, device=0):
+        self.n_tips = n_tips
+        self.n_branches = 2 * n_tips - 2
+        self.handle = phg_create(n_tips, n_patterns, n_states, n_categories, prec, device)
+
+    @classmethod
+    def for_problem(cls, prob, prec=PHG_FP32_SCALED, device=0):
+        ctx = cls(prob.n_tips, prob.n_patterns, prob.n_states, prob.n_categories, prec, device)
+        ctx.set_problem(prob)
+        return ctx
+
+    def set_problem(self, prob):
+        set_problem(self.handle, prob)
+
+    def gradient(self):
+        return phg_gradient(self.handle, self.n_branches)
+
+    def log_likelihood(self):
+        return phg_log_likelihood(self.handle)
+
+    def close(self):
+        if self.handle:
+            phg_destroy(self.handle)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

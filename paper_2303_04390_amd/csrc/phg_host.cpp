@@ -1,0 +1,699 @@
+// Host runtime behind include/phg.h: input validation and host mirrors,
+// topology -> level schedule, workspace plan, device upload and the kernel
+// sequence of one log-likelihood / gradient evaluation.
+//
+// Every phg_set_* call validates and copies its input on the host only; the
+// device is first touched by a compute call (or phg_prepare), which allocates
+// the workspace (or uses a caller-bound one), uploads whatever changed and
+// enqueues: pmat -> post-order levels (height 1..H, the root last) ->
+// pre-order levels (depth 0..D) -> finalize.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/phg.h"
+#include "phg_internal.h"
+
+using phg::DeviceProblem;
+using phg::NodeTriple;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+thread_local std::string g_create_error;
+
+// Workspace plan: byte offsets of every device buffer inside one arena.
+struct Plan {
+    size_t codes, part, expo, P64, dP64, P32, dP32, b, V, Vinv, lam, rates, cw, pi, pw, sll, gpart,
+        out, sched, total;
+};
+
+Plan make_plan(int N, int C, int S, int R, phg_precision prec) {
+    const int Cpad = (C + phg::kLanes - 1) / phg::kLanes * phg::kLanes;
+    const int tiles = Cpad / phg::kLanes;
+    const int S4 = (S + 3) / 4;
+    const size_t E = 2 * static_cast<size_t>(N) - 2;
+    const size_t I = static_cast<size_t>(N) - 1;
+    const size_t tsz = prec == PHG_FP32_SCALED ? 4 : 8;
+    Plan p{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off = align_up(off + bytes);
+        return o;
+    };
+    p.codes = take(static_cast<size_t>(N) * Cpad);
+    p.part = take(I * tiles * R * S4 * phg::kLanes * 4 * tsz);
+    p.expo = take(I * Cpad * sizeof(int32_t));
+    p.P64 = take(E * R * S * S * 8);
+    p.dP64 = take(E * R * S * S * 8);
+    p.P32 = take(prec == PHG_FP32_SCALED ? E * R * S * S * 4 : 0);
+    p.dP32 = take(prec == PHG_FP32_SCALED ? E * R * S * S * 4 : 0);
+    p.b = take(E * 8);
+    p.V = take(static_cast<size_t>(S) * S * 8);
+    p.Vinv = take(static_cast<size_t>(S) * S * 8);
+    p.lam = take(S * 8);
+    p.rates = take(R * 8);
+    p.cw = take(R * 8);
+    p.pi = take(S * 8);
+    p.pw = take(static_cast<size_t>(Cpad) * 8);
+    p.sll = take(static_cast<size_t>(Cpad) * 8);
+    p.gpart = take(E * tiles * 8);
+    p.out = take((E + 1) * 8);
+    p.sched = take(2 * I * sizeof(NodeTriple));
+    p.total = off;
+    return p;
+}
+
+bool finite_all(const double* x, size_t n) {
+    for (size_t i = 0; i < n; ++i)
+        if (!std::isfinite(x[i])) return false;
+    return true;
+}
+
+}  // namespace
+
+enum InputBit : unsigned {
+    kTopo = 1u << 0,
+    kB = 1u << 1,
+    kEig = 1u << 2,
+    kPi = 1u << 3,
+    kCat = 1u << 4,
+    kTips = 1u << 5,
+    kPw = 1u << 6,
+    kRequired = kTopo | kB | kEig | kPi | kCat | kTips,
+};
+
+struct phg_context {
+    int N = 0, C = 0, S = 0, R = 0, device = 0;
+    phg_precision prec = PHG_FP64;
+    int Cpad = 0, tiles = 0, S4 = 0;
+    std::string err;
+
+    // host mirrors of every input
+    std::vector<int32_t> parent;
+    std::vector<double> b, V, Vinv, lam, pi, rates, cw, pw;
+    std::vector<uint8_t> codes;  // [N][Cpad], padding = S
+    unsigned have = 0;           // inputs set at least once
+    unsigned dirty = 0;          // inputs changed since the last upload
+
+    // schedule (host copy; uploaded to the sched region)
+    std::vector<NodeTriple> sched;          // post levels then pre levels
+    std::vector<int> post_off, pre_off;     // level start offsets (size levels+1)
+
+    // device state
+    bool dev_init = false;
+    bool own_arena = false;
+    char* arena = nullptr;
+    size_t arena_bytes = 0;
+    char* bound_ws = nullptr;
+    size_t bound_ws_bytes = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    double* host_out = nullptr;  // pinned (1 + E) doubles
+    Plan plan{};
+    DeviceProblem dp{};
+
+    // profiling: PHG_PROF_CLASSES + 1 events per recorded evaluation
+    bool prof_on = false;
+    std::vector<hipEvent_t> prof_pool;   // reusable events
+    size_t prof_used = 0;                // events in use (multiple of 5)
+
+    phg_status fail(phg_status s, const char* fmt, ...) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        err = buf;
+        return s;
+    }
+};
+
+#define PHG_HIP(ctx, call)                                                                  \
+    do {                                                                                    \
+        hipError_t e_ = (call);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return (ctx)->fail(e_ == hipErrorOutOfMemory ? PHG_ERR_OOM : PHG_ERR_DEVICE,    \
+                               "%s failed: %s", #call, hipGetErrorString(e_));              \
+    } while (0)
+
+namespace {
+
+phg_status check_sizes(int n_tips, int n_patterns, int n_states, int n_categories, int prec,
+                       std::string* why) {
+    if (n_tips < 2) return *why = "n_tips must be >= 2", PHG_ERR_ARG;
+    if (n_tips > (1 << 24)) return *why = "n_tips too large", PHG_ERR_ARG;
+    if (n_patterns < 1) return *why = "n_patterns must be >= 1", PHG_ERR_ARG;
+    if (n_patterns > (1 << 28)) return *why = "n_patterns too large", PHG_ERR_ARG;
+    if (n_states < 2 || n_states > 64) return *why = "n_states must be in [2, 64]", PHG_ERR_ARG;
+    if (n_categories < 1 || n_categories > 16)
+        return *why = "n_categories must be in [1, 16]", PHG_ERR_ARG;
+    if (prec != PHG_FP64 && prec != PHG_FP32_SCALED) return *why = "unknown precision", PHG_ERR_ARG;
+    return PHG_OK;
+}
+
+// Build post-order (by height) and pre-order (by depth) levels.
+void build_schedule(phg_context* ctx) {
+    const int N = ctx->N, n = 2 * N - 1, root = n - 1;
+    std::vector<int> c0(n, -1), c1(n, -1);
+    for (int v = 0; v < n; ++v) {
+        const int p = ctx->parent[v];
+        if (p < 0) continue;
+        if (c0[p] < 0)
+            c0[p] = v;
+        else
+            c1[p] = v;
+    }
+    for (int v = N; v < n; ++v)
+        if (c0[v] > c1[v]) std::swap(c0[v], c1[v]);
+    // depth by walking down from the root (iterative)
+    std::vector<int> depth(n, 0), order;
+    order.reserve(n);
+    order.push_back(root);
+    for (size_t h = 0; h < order.size(); ++h) {
+        const int v = order[h];
+        if (v >= N) {
+            depth[c0[v]] = depth[v] + 1;
+            depth[c1[v]] = depth[v] + 1;
+            order.push_back(c0[v]);
+            order.push_back(c1[v]);
+        }
+    }
+    std::vector<int> height(n, 0);
+    for (int h = static_cast<int>(order.size()) - 1; h >= 0; --h) {
+        const int v = order[h];
+        if (v >= N) height[v] = 1 + std::max(height[c0[v]], height[c1[v]]);
+    }
+    const int H = height[root];
+    int D = 0;
+    for (int v = N; v < n; ++v) D = std::max(D, depth[v]);
+    ctx->sched.clear();
+    ctx->post_off.assign(1, 0);
+    std::vector<std::vector<int>> by(H + 1);
+    for (int v = N; v < n; ++v) by[height[v]].push_back(v);
+    for (int h = 1; h <= H; ++h) {
+        for (int v : by[h]) ctx->sched.push_back(NodeTriple{v, c0[v], c1[v], 0});
+        ctx->post_off.push_back(static_cast<int>(ctx->sched.size()));
+    }
+    ctx->pre_off.assign(1, static_cast<int>(ctx->sched.size()));
+    std::vector<std::vector<int>> bd(D + 1);
+    for (int v = N; v < n; ++v) bd[depth[v]].push_back(v);
+    for (int d = 0; d <= D; ++d) {
+        for (int v : bd[d]) ctx->sched.push_back(NodeTriple{v, c0[v], c1[v], 0});
+        ctx->pre_off.push_back(static_cast<int>(ctx->sched.size()));
+    }
+}
+
+phg_status ensure_device(phg_context* ctx) {
+    if (ctx->dev_init) {
+        PHG_HIP(ctx, hipSetDevice(ctx->device));
+        return PHG_OK;
+    }
+    int count = 0;
+    hipError_t e = hipGetDeviceCount(&count);
+    if (e != hipSuccess || count == 0)
+        return ctx->fail(PHG_ERR_DEVICE, "no HIP device available (%s)", hipGetErrorString(e));
+    if (ctx->device >= count)
+        return ctx->fail(PHG_ERR_DEVICE, "device %d out of range (%d devices)", ctx->device, count);
+    PHG_HIP(ctx, hipSetDevice(ctx->device));
+    hipDeviceProp_t prop;
+    PHG_HIP(ctx, hipGetDeviceProperties(&prop, ctx->device));
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return ctx->fail(PHG_ERR_DEVICE, "device %d is %s; this library is built for gfx950 only",
+                         ctx->device, prop.gcnArchName);
+    if (!phg::kernels_support(ctx->S, ctx->R))
+        return ctx->fail(PHG_ERR_ARG, "no kernel for S=%d, R=%d in this build", ctx->S, ctx->R);
+
+    ctx->plan = make_plan(ctx->N, ctx->C, ctx->S, ctx->R, ctx->prec);
+    if (ctx->bound_ws) {
+        if (ctx->bound_ws_bytes < ctx->plan.total)
+            return ctx->fail(PHG_ERR_OOM, "bound workspace has %zu bytes, %zu needed",
+                             ctx->bound_ws_bytes, ctx->plan.total);
+        ctx->arena = ctx->bound_ws;
+        ctx->own_arena = false;
+    } else {
+        void* p = nullptr;
+        e = hipMalloc(&p, ctx->plan.total);
+        if (e != hipSuccess)
+            return ctx->fail(PHG_ERR_OOM, "hipMalloc(%zu) failed: %s", ctx->plan.total,
+                             hipGetErrorString(e));
+        ctx->arena = static_cast<char*>(p);
+        ctx->own_arena = true;
+    }
+    ctx->arena_bytes = ctx->plan.total;
+    if (!ctx->stream) {
+        PHG_HIP(ctx, hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking));
+        ctx->own_stream = true;
+    }
+    void* ho = nullptr;
+    PHG_HIP(ctx, hipHostMalloc(&ho, (2 * static_cast<size_t>(ctx->N) - 1) * sizeof(double),
+                               hipHostMallocDefault));
+    ctx->host_out = static_cast<double*>(ho);
+
+    const Plan& pl = ctx->plan;
+    char* a = ctx->arena;
+    DeviceProblem& d = ctx->dp;
+    d.N = ctx->N;
+    d.C = ctx->C;
+    d.Cpad = ctx->Cpad;
+    d.S = ctx->S;
+    d.S4 = ctx->S4;
+    d.R = ctx->R;
+    d.tiles = ctx->tiles;
+    d.codes = reinterpret_cast<const uint8_t*>(a + pl.codes);
+    d.part = a + pl.part;
+    d.expo = reinterpret_cast<int32_t*>(a + pl.expo);
+    d.P64 = reinterpret_cast<double*>(a + pl.P64);
+    d.dP64 = reinterpret_cast<double*>(a + pl.dP64);
+    d.P32 = reinterpret_cast<float*>(a + pl.P32);
+    d.dP32 = reinterpret_cast<float*>(a + pl.dP32);
+    d.b = reinterpret_cast<const double*>(a + pl.b);
+    d.V = reinterpret_cast<const double*>(a + pl.V);
+    d.Vinv = reinterpret_cast<const double*>(a + pl.Vinv);
+    d.lam = reinterpret_cast<const double*>(a + pl.lam);
+    d.rates = reinterpret_cast<const double*>(a + pl.rates);
+    d.cweights = reinterpret_cast<const double*>(a + pl.cw);
+    d.pi = reinterpret_cast<const double*>(a + pl.pi);
+    d.pw = reinterpret_cast<const double*>(a + pl.pw);
+    d.sll = reinterpret_cast<double*>(a + pl.sll);
+    d.gpart = reinterpret_cast<double*>(a + pl.gpart);
+    ctx->dev_init = true;
+    ctx->dirty = ctx->have | kPw;  // upload everything on first use
+    return PHG_OK;
+}
+
+phg_status upload(phg_context* ctx) {
+    const Plan& pl = ctx->plan;
+    char* a = ctx->arena;
+    hipStream_t st = ctx->stream;
+    const unsigned dirty = ctx->dirty;
+    auto put = [&](size_t off, const void* src, size_t bytes) {
+        return hipMemcpyAsync(a + off, src, bytes, hipMemcpyHostToDevice, st);
+    };
+    if (dirty & kTopo) {
+        PHG_HIP(ctx, put(pl.sched, ctx->sched.data(), ctx->sched.size() * sizeof(NodeTriple)));
+    }
+    if (dirty & kB) PHG_HIP(ctx, put(pl.b, ctx->b.data(), ctx->b.size() * 8));
+    if (dirty & kEig) {
+        PHG_HIP(ctx, put(pl.V, ctx->V.data(), ctx->V.size() * 8));
+        PHG_HIP(ctx, put(pl.Vinv, ctx->Vinv.data(), ctx->Vinv.size() * 8));
+        PHG_HIP(ctx, put(pl.lam, ctx->lam.data(), ctx->lam.size() * 8));
+    }
+    if (dirty & kPi) PHG_HIP(ctx, put(pl.pi, ctx->pi.data(), ctx->pi.size() * 8));
+    if (dirty & kCat) {
+        PHG_HIP(ctx, put(pl.rates, ctx->rates.data(), ctx->rates.size() * 8));
+        PHG_HIP(ctx, put(pl.cw, ctx->cw.data(), ctx->cw.size() * 8));
+    }
+    if (dirty & kTips) PHG_HIP(ctx, put(pl.codes, ctx->codes.data(), ctx->codes.size()));
+    if (dirty & kPw) PHG_HIP(ctx, put(pl.pw, ctx->pw.data(), ctx->pw.size() * 8));
+    // pageable sources: make sure the copies have consumed them before the
+    // host mirrors can change again
+    if (dirty) PHG_HIP(ctx, hipStreamSynchronize(st));
+    ctx->dirty = 0;
+    return PHG_OK;
+}
+
+constexpr int kProfEvents = PHG_PROF_CLASSES + 1;
+
+// Record the next profiling event of the current evaluation (no-op when off).
+phg_status prof_mark(phg_context* ctx) {
+    if (!ctx->prof_on) return PHG_OK;
+    if (ctx->prof_used == ctx->prof_pool.size()) {
+        hipEvent_t ev;
+        PHG_HIP(ctx, hipEventCreate(&ev));
+        ctx->prof_pool.push_back(ev);
+    }
+    PHG_HIP(ctx, hipEventRecord(ctx->prof_pool[ctx->prof_used++], ctx->stream));
+    return PHG_OK;
+}
+
+#define PHG_TRY(expr)                     \
+    do {                                  \
+        phg_status s_ = (expr);           \
+        if (s_ != PHG_OK) return s_;      \
+    } while (0)
+
+phg_status enqueue_eval(phg_context* ctx, double* d_logl, double* d_grad) {
+    const bool fp32 = ctx->prec == PHG_FP32_SCALED;
+    hipStream_t st = ctx->stream;
+    const DeviceProblem& d = ctx->dp;
+    const NodeTriple* sched = reinterpret_cast<const NodeTriple*>(ctx->arena + ctx->plan.sched);
+    PHG_TRY(prof_mark(ctx));
+    PHG_HIP(ctx, phg::launch_pmat(d, fp32, st));
+    PHG_TRY(prof_mark(ctx));
+    const int H = static_cast<int>(ctx->post_off.size()) - 1;
+    for (int h = 0; h < H; ++h) {
+        const int a = ctx->post_off[h], n = ctx->post_off[h + 1] - a;
+        PHG_HIP(ctx, phg::launch_post_level(d, fp32, sched + a, n, h == H - 1, st));
+    }
+    PHG_TRY(prof_mark(ctx));
+    const int D = static_cast<int>(ctx->pre_off.size()) - 1;
+    for (int l = 0; l < D; ++l) {
+        const int a = ctx->pre_off[l], n = ctx->pre_off[l + 1] - a;
+        PHG_HIP(ctx, phg::launch_pre_level(d, fp32, sched + a, n, st));
+    }
+    PHG_TRY(prof_mark(ctx));
+    PHG_HIP(ctx, phg::launch_finalize(d, d_logl, d_grad, st));
+    PHG_TRY(prof_mark(ctx));
+    return PHG_OK;
+}
+
+phg_status ready(phg_context* ctx) {
+    if ((ctx->have & kRequired) != kRequired) {
+        std::string miss;
+        if (!(ctx->have & kTopo)) miss += " topology";
+        if (!(ctx->have & kB)) miss += " branch_lengths";
+        if (!(ctx->have & kEig)) miss += " eigen";
+        if (!(ctx->have & kPi)) miss += " root_frequencies";
+        if (!(ctx->have & kCat)) miss += " categories";
+        if (!(ctx->have & kTips)) miss += " tip_states";
+        return ctx->fail(PHG_ERR_STATE, "inputs not set:%s", miss.c_str());
+    }
+    phg_status s = ensure_device(ctx);
+    if (s != PHG_OK) return s;
+    return upload(ctx);
+}
+
+}  // namespace
+
+extern "C" {
+
+phg_status phg_create(int n_tips, int n_patterns, int n_states, int n_categories,
+                      phg_precision prec, int device, phg_context** out) {
+    if (!out) {
+        g_create_error = "out is NULL";
+        return PHG_ERR_ARG;
+    }
+    *out = nullptr;
+    std::string why;
+    phg_status s = check_sizes(n_tips, n_patterns, n_states, n_categories, prec, &why);
+    if (s != PHG_OK) {
+        g_create_error = why;
+        return s;
+    }
+    if (device < 0) {
+        g_create_error = "device must be >= 0";
+        return PHG_ERR_ARG;
+    }
+    phg_context* ctx = new (std::nothrow) phg_context();
+    if (!ctx) {
+        g_create_error = "host allocation failed";
+        return PHG_ERR_OOM;
+    }
+    ctx->N = n_tips;
+    ctx->C = n_patterns;
+    ctx->S = n_states;
+    ctx->R = n_categories;
+    ctx->prec = prec;
+    ctx->device = device;
+    ctx->Cpad = (n_patterns + phg::kLanes - 1) / phg::kLanes * phg::kLanes;
+    ctx->tiles = ctx->Cpad / phg::kLanes;
+    ctx->S4 = (n_states + 3) / 4;
+    ctx->pw.assign(ctx->Cpad, 0.0);
+    std::fill(ctx->pw.begin(), ctx->pw.begin() + n_patterns, 1.0);
+    ctx->codes.assign(static_cast<size_t>(n_tips) * ctx->Cpad, static_cast<uint8_t>(n_states));
+    ctx->have = kPw;
+    g_create_error.clear();
+    *out = ctx;
+    return PHG_OK;
+}
+
+phg_status phg_destroy(phg_context* ctx) {
+    if (!ctx) return PHG_OK;
+    if (ctx->dev_init) {
+        (void)hipSetDevice(ctx->device);
+        if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+        for (hipEvent_t ev : ctx->prof_pool) (void)hipEventDestroy(ev);
+        if (ctx->own_arena && ctx->arena) (void)hipFree(ctx->arena);
+        if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
+        if (ctx->host_out) (void)hipHostFree(ctx->host_out);
+    }
+    delete ctx;
+    return PHG_OK;
+}
+
+const char* phg_last_error(const phg_context* ctx) {
+    return ctx ? ctx->err.c_str() : g_create_error.c_str();
+}
+
+phg_status phg_set_topology(phg_context* ctx, const int32_t* parent) {
+    if (!ctx) return PHG_ERR_ARG;
+    if (!parent) return ctx->fail(PHG_ERR_ARG, "parent is NULL");
+    const int N = ctx->N, n = 2 * N - 1, root = n - 1;
+    if (parent[root] != -1) return ctx->fail(PHG_ERR_ARG, "parent[root=%d] must be -1", root);
+    std::vector<int> nkids(n, 0);
+    for (int v = 0; v < root; ++v) {
+        const int p = parent[v];
+        if (p < N || p > root)
+            return ctx->fail(PHG_ERR_ARG, "parent[%d]=%d is not an internal node or the root", v, p);
+        nkids[p]++;
+    }
+    for (int v = N; v < n; ++v)
+        if (nkids[v] != 2)
+            return ctx->fail(PHG_ERR_ARG, "node %d has %d children (need exactly 2)", v, nkids[v]);
+    // acyclic: every node must reach the root within n steps
+    std::vector<char> ok(n, 0);
+    ok[root] = 1;
+    for (int v = 0; v < root; ++v) {
+        int x = v, steps = 0;
+        std::vector<int> path;
+        while (!ok[x]) {
+            path.push_back(x);
+            x = parent[x];
+            if (++steps > n) return ctx->fail(PHG_ERR_ARG, "topology has a cycle through node %d", v);
+        }
+        for (int y : path) ok[y] = 1;
+    }
+    ctx->parent.assign(parent, parent + n);
+    build_schedule(ctx);
+    ctx->have |= kTopo;
+    ctx->dirty |= kTopo;
+    return PHG_OK;
+}
+
+phg_status phg_set_branch_lengths(phg_context* ctx, const double* b) {
+    if (!ctx) return PHG_ERR_ARG;
+    if (!b) return ctx->fail(PHG_ERR_ARG, "b is NULL");
+    const size_t E = 2 * static_cast<size_t>(ctx->N) - 2;
+    for (size_t x = 0; x < E; ++x)
+        if (!std::isfinite(b[x]) || b[x] < 0.0)
+            return ctx->fail(PHG_ERR_ARG, "branch length b[%zu]=%g must be finite and >= 0", x, b[x]);
+    ctx->b.assign(b, b + E);
+    ctx->have |= kB;
+    ctx->dirty |= kB;
+    return PHG_OK;
+}
+
+phg_status phg_set_eigen(phg_context* ctx, const double* V, const double* Vinv, const double* lambda) {
+    if (!ctx) return PHG_ERR_ARG;
+    if (!V || !Vinv || !lambda) return ctx->fail(PHG_ERR_ARG, "NULL eigensystem array");
+    const size_t S = ctx->S;
+    if (!finite_all(V, S * S) || !finite_all(Vinv, S * S) || !finite_all(lambda, S))
+        return ctx->fail(PHG_ERR_ARG, "eigensystem has non-finite entries");
+    ctx->V.assign(V, V + S * S);
+    ctx->Vinv.assign(Vinv, Vinv + S * S);
+    ctx->lam.assign(lambda, lambda + S);
+    ctx->have |= kEig;
+    ctx->dirty |= kEig;
+    return PHG_OK;
+}
+
+phg_status phg_set_root_frequencies(phg_context* ctx, const double* pi) {
+    if (!ctx) return PHG_ERR_ARG;
+    if (!pi) return ctx->fail(PHG_ERR_ARG, "pi is NULL");
+    for (int s = 0; s < ctx->S; ++s)
+        if (!std::isfinite(pi[s]) || pi[s] < 0.0)
+            return ctx->fail(PHG_ERR_ARG, "pi[%d]=%g must be finite and >= 0", s, pi[s]);
+    ctx->pi.assign(pi, pi + ctx->S);
+    ctx->have |= kPi;
+    ctx->dirty |= kPi;
+    return PHG_OK;
+}
+
+phg_status phg_set_categories(phg_context* ctx, const double* rates, const double* weights) {
+    if (!ctx) return PHG_ERR_ARG;
+    if (!rates || !weights) return ctx->fail(PHG_ERR_ARG, "NULL category array");
+    for (int r = 0; r < ctx->R; ++r) {
+        if (!std::isfinite(rates[r]) || rates[r] < 0.0)
+            return ctx->fail(PHG_ERR_ARG, "rates[%d]=%g must be finite and >= 0", r, rates[r]);
+        if (!std::isfinite(weights[r]) || weights[r] < 0.0)
+            return ctx->fail(PHG_ERR_ARG, "weights[%d]=%g must be finite and >= 0", r, weights[r]);
+    }
+    ctx->rates.assign(rates, rates + ctx->R);
+    ctx->cw.assign(weights, weights + ctx->R);
+    ctx->have |= kCat;
+    ctx->dirty |= kCat;
+    return PHG_OK;
+}
+
+phg_status phg_set_tip_states(phg_context* ctx, const int32_t* codes) {
+    if (!ctx) return PHG_ERR_ARG;
+    if (!codes) return ctx->fail(PHG_ERR_ARG, "codes is NULL");
+    const int N = ctx->N, C = ctx->C, S = ctx->S, Cpad = ctx->Cpad;
+    for (size_t i = 0; i < static_cast<size_t>(N) * C; ++i)
+        if (codes[i] < 0 || codes[i] > S)
+            return ctx->fail(PHG_ERR_ARG, "tip code %d at tip %zu pattern %zu outside [0, %d]", codes[i],
+                             i / C, i % C, S);
+    for (int t = 0; t < N; ++t) {
+        uint8_t* row = ctx->codes.data() + static_cast<size_t>(t) * Cpad;
+        for (int c = 0; c < C; ++c) row[c] = static_cast<uint8_t>(codes[static_cast<size_t>(t) * C + c]);
+    }
+    ctx->have |= kTips;
+    ctx->dirty |= kTips;
+    return PHG_OK;
+}
+
+phg_status phg_set_pattern_weights(phg_context* ctx, const double* w) {
+    if (!ctx) return PHG_ERR_ARG;
+    if (!w) return ctx->fail(PHG_ERR_ARG, "w is NULL");
+    for (int c = 0; c < ctx->C; ++c)
+        if (!std::isfinite(w[c]) || w[c] < 0.0)
+            return ctx->fail(PHG_ERR_ARG, "pattern weight w[%d]=%g must be finite and >= 0", c, w[c]);
+    std::copy(w, w + ctx->C, ctx->pw.begin());
+    ctx->have |= kPw;
+    ctx->dirty |= kPw;
+    return PHG_OK;
+}
+
+phg_status phg_prepare(phg_context* ctx) {
+    if (!ctx) return PHG_ERR_ARG;
+    return ready(ctx);
+}
+
+phg_status phg_gradient(phg_context* ctx, double* logl, double* grad) {
+    if (!ctx) return PHG_ERR_ARG;
+    if (!grad) return ctx->fail(PHG_ERR_ARG, "grad is NULL");
+    phg_status s = ready(ctx);
+    if (s != PHG_OK) return s;
+    double* dout = reinterpret_cast<double*>(ctx->arena + ctx->plan.out);
+    s = enqueue_eval(ctx, dout, dout + 1);
+    if (s != PHG_OK) return s;
+    const size_t E = 2 * static_cast<size_t>(ctx->N) - 2;
+    PHG_HIP(ctx, hipMemcpyAsync(ctx->host_out, dout, (E + 1) * sizeof(double), hipMemcpyDeviceToHost,
+                                ctx->stream));
+    PHG_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    const double ll = ctx->host_out[0];
+    if (!(ll > -std::numeric_limits<double>::infinity()) || !std::isfinite(ll)) {
+        if (logl) *logl = -std::numeric_limits<double>::infinity();
+        for (size_t x = 0; x < E; ++x) grad[x] = std::numeric_limits<double>::quiet_NaN();
+        return ctx->fail(PHG_ERR_NUMERIC, "a weighted site likelihood is zero or not finite");
+    }
+    if (logl) *logl = ll;
+    std::memcpy(grad, ctx->host_out + 1, E * sizeof(double));
+    return PHG_OK;
+}
+
+phg_status phg_log_likelihood(phg_context* ctx, double* logl) {
+    if (!ctx) return PHG_ERR_ARG;
+    if (!logl) return ctx->fail(PHG_ERR_ARG, "logl is NULL");
+    std::vector<double> g(2 * static_cast<size_t>(ctx->N) - 2);
+    return phg_gradient(ctx, logl, g.data());
+}
+
+phg_status phg_workspace_size(int n_tips, int n_patterns, int n_states, int n_categories,
+                              phg_precision prec, size_t* bytes) {
+    std::string why;
+    if (!bytes) return PHG_ERR_ARG;
+    phg_status s = check_sizes(n_tips, n_patterns, n_states, n_categories, prec, &why);
+    if (s != PHG_OK) {
+        g_create_error = why;
+        return s;
+    }
+    *bytes = make_plan(n_tips, n_patterns, n_states, n_categories, prec).total;
+    return PHG_OK;
+}
+
+phg_status phg_bind_workspace(phg_context* ctx, void* device_ptr, size_t bytes) {
+    if (!ctx) return PHG_ERR_ARG;
+    if (ctx->dev_init) return ctx->fail(PHG_ERR_STATE, "workspace must be bound before first use");
+    if (!device_ptr) return ctx->fail(PHG_ERR_ARG, "device_ptr is NULL");
+    if (reinterpret_cast<uintptr_t>(device_ptr) % kAlign != 0)
+        return ctx->fail(PHG_ERR_ARG, "workspace must be %zu-byte aligned", kAlign);
+    ctx->bound_ws = static_cast<char*>(device_ptr);
+    ctx->bound_ws_bytes = bytes;
+    return PHG_OK;
+}
+
+phg_status phg_bind_stream(phg_context* ctx, void* hip_stream) {
+    if (!ctx) return PHG_ERR_ARG;
+    if (ctx->dev_init && ctx->own_stream && ctx->stream) {
+        (void)hipSetDevice(ctx->device);
+        (void)hipStreamSynchronize(ctx->stream);
+        (void)hipStreamDestroy(ctx->stream);
+    }
+    ctx->stream = static_cast<hipStream_t>(hip_stream);
+    ctx->own_stream = false;
+    if (!hip_stream && ctx->dev_init) {
+        PHG_HIP(ctx, hipSetDevice(ctx->device));
+        PHG_HIP(ctx, hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking));
+        ctx->own_stream = true;
+    }
+    return PHG_OK;
+}
+
+phg_status phg_gradient_async(phg_context* ctx, double* d_logl, double* d_grad) {
+    if (!ctx) return PHG_ERR_ARG;
+    if (!d_logl || !d_grad) return ctx->fail(PHG_ERR_ARG, "NULL device output pointer");
+    phg_status s = ready(ctx);
+    if (s != PHG_OK) return s;
+    return enqueue_eval(ctx, d_logl, d_grad);
+}
+
+phg_status phg_schedule_info(phg_context* ctx, int* n_post_levels, int* n_pre_levels,
+                             int* n_launches) {
+    if (!ctx) return PHG_ERR_ARG;
+    if (!(ctx->have & kTopo)) return ctx->fail(PHG_ERR_STATE, "topology not set");
+    const int H = static_cast<int>(ctx->post_off.size()) - 1;
+    const int D = static_cast<int>(ctx->pre_off.size()) - 1;
+    if (n_post_levels) *n_post_levels = H;
+    if (n_pre_levels) *n_pre_levels = D;
+    if (n_launches) *n_launches = H + D + 2;
+    return PHG_OK;
+}
+
+phg_status phg_profile_enable(phg_context* ctx, int on) {
+    if (!ctx) return PHG_ERR_ARG;
+    ctx->prof_on = on != 0;
+    return PHG_OK;
+}
+
+phg_status phg_profile_read(phg_context* ctx, double* ms, int* n_evals, int* launches) {
+    if (!ctx) return PHG_ERR_ARG;
+    const size_t n = ctx->prof_used / kProfEvents;
+    double tot[PHG_PROF_CLASSES] = {0, 0, 0, 0};
+    if (n > 0) {
+        PHG_HIP(ctx, hipSetDevice(ctx->device));
+        PHG_HIP(ctx, hipEventSynchronize(ctx->prof_pool[ctx->prof_used - 1]));
+        for (size_t e = 0; e < n; ++e)
+            for (int k = 0; k < PHG_PROF_CLASSES; ++k) {
+                float t = 0.f;
+                PHG_HIP(ctx, hipEventElapsedTime(&t, ctx->prof_pool[e * kProfEvents + k],
+                                                 ctx->prof_pool[e * kProfEvents + k + 1]));
+                tot[k] += t;
+            }
+    }
+    if (ms)
+        for (int k = 0; k < PHG_PROF_CLASSES; ++k) ms[k] = tot[k];
+    if (n_evals) *n_evals = static_cast<int>(n);
+    if (launches) {
+        launches[PHG_PROF_PMAT] = 1;
+        launches[PHG_PROF_POST] = static_cast<int>(ctx->post_off.size()) - 1;
+        launches[PHG_PROF_PRE] = static_cast<int>(ctx->pre_off.size()) - 1;
+        launches[PHG_PROF_FINAL] = 1;
+    }
+    ctx->prof_used = 0;
+    return PHG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,156 @@
+"""Host-side checks of the C ABI: the library loads, exports every function
+include/phg.h declares, validates inputs on the host, and reports states and
+errors with the documented codes.  No kernel is launched here."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2303_04390_amd import binding as B
+from paper_2303_04390_amd import synth
+from tests.conftest import gpu_available
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(__file__)), "include", "phg.h")
+
+
+def declared_functions():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(phg_[a-z_]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = B.lib()
+    names = declared_functions()
+    assert len(names) >= 18
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(B._SIGS), "binding and header disagree"
+
+
+def test_create_validates_sizes():
+    with pytest.raises(B.PhgError) as e:
+        B.phg_create(1, 10, 4, 4, B.PHG_FP64)
+    assert e.value.status == B.PHG_ERR_ARG
+    for args in [(10, 0, 4, 4, 0), (10, 10, 1, 4, 0), (10, 10, 65, 4, 0), (10, 10, 4, 0, 0),
+                 (10, 10, 4, 17, 0), (10, 10, 4, 4, 7)]:
+        with pytest.raises(B.PhgError) as e:
+            B.phg_create(*args)
+        assert e.value.status == B.PHG_ERR_ARG
+    with pytest.raises(B.PhgError):
+        B.phg_create(10, 10, 4, 4, 0, -1)
+
+
+def _ctx(N=6, C=10, S=4, R=4):
+    return B.phg_create(N, C, S, R, B.PHG_FP32_SCALED, 0)
+
+
+def test_topology_validation():
+    ctx = _ctx()
+    try:
+        good = synth.yule_topology(6, np.random.default_rng(0))
+        B.phg_set_topology(ctx, good)
+        bad = good.copy(); bad[10] = 3
+        with pytest.raises(B.PhgError) as e:
+            B.phg_set_topology(ctx, bad)
+        assert e.value.status == B.PHG_ERR_ARG and "root" in e.value.message
+        bad = good.copy(); bad[0] = 2                      # parent is a tip
+        with pytest.raises(B.PhgError):
+            B.phg_set_topology(ctx, bad)
+        bad = good.copy()                                   # three children under one node
+        other = [v for v in range(10) if good[v] != good[0]][0]
+        bad[other] = good[0]
+        with pytest.raises(B.PhgError) as e:
+            B.phg_set_topology(ctx, bad)
+        assert "children" in e.value.message
+        # nodes 6 and 7 are each other's parent; every degree is still 2
+        cyc = np.array([6, 7, 8, 8, 9, 9, 7, 6, 10, 10, -1], np.int32)
+        with pytest.raises(B.PhgError) as e:
+            B.phg_set_topology(ctx, cyc)
+        assert "cycle" in e.value.message
+    finally:
+        B.phg_destroy(ctx)
+
+
+def test_value_validation():
+    ctx = _ctx()
+    try:
+        b = np.full(10, 0.1)
+        B.phg_set_branch_lengths(ctx, b)
+        for bad in (-0.1, np.nan, np.inf):
+            bb = b.copy(); bb[3] = bad
+            with pytest.raises(B.PhgError) as e:
+                B.phg_set_branch_lengths(ctx, bb)
+            assert e.value.status == B.PHG_ERR_ARG
+        codes = np.zeros((6, 10), np.int32)
+        B.phg_set_tip_states(ctx, codes)
+        codes[2, 3] = 5
+        with pytest.raises(B.PhgError):
+            B.phg_set_tip_states(ctx, codes)
+        codes[2, 3] = -1
+        with pytest.raises(B.PhgError):
+            B.phg_set_tip_states(ctx, codes)
+        codes[2, 3] = 4                                    # S = fully ambiguous is allowed
+        B.phg_set_tip_states(ctx, codes)
+        with pytest.raises(B.PhgError):
+            B.phg_set_pattern_weights(ctx, np.r_[np.ones(9), -1.0])
+        with pytest.raises(B.PhgError):
+            B.phg_set_categories(ctx, np.ones(4), np.r_[np.ones(3), np.nan])
+        with pytest.raises(B.PhgError):
+            B.phg_set_root_frequencies(ctx, np.array([0.5, 0.5, -0.1, 0.1]))
+        V = np.eye(4); V[1, 1] = np.inf
+        with pytest.raises(B.PhgError):
+            B.phg_set_eigen(ctx, V, np.eye(4), np.zeros(4))
+    finally:
+        B.phg_destroy(ctx)
+
+
+def test_compute_before_inputs_is_state_error():
+    ctx = _ctx()
+    try:
+        B.phg_set_topology(ctx, synth.yule_topology(6, np.random.default_rng(1)))
+        with pytest.raises(B.PhgError) as e:
+            B.phg_gradient(ctx, 10)
+        assert e.value.status == B.PHG_ERR_STATE
+        assert "branch_lengths" in e.value.message and "eigen" in e.value.message
+    finally:
+        B.phg_destroy(ctx)
+
+
+def test_schedule_levels():
+    N = 200
+    ctx = B.phg_create(N, 10, 4, 4, B.PHG_FP32_SCALED, 0)
+    try:
+        parent = synth.caterpillar_topology(N)
+        B.phg_set_topology(ctx, parent)
+        post, pre, launches = B.phg_schedule_info(ctx)
+        assert post == N - 1 and pre == N - 1 and launches == 2 * N
+        parent = synth.yule_topology(N, np.random.default_rng(3))
+        B.phg_set_topology(ctx, parent)
+        post, pre, _ = B.phg_schedule_info(ctx)
+        assert post < 40 and pre < 40
+    finally:
+        B.phg_destroy(ctx)
+
+
+def test_workspace_size_scales():
+    a = B.phg_workspace_size(1000, 10000, 4, 4, B.PHG_FP32_SCALED)
+    b = B.phg_workspace_size(1000, 10000, 4, 4, B.PHG_FP64)
+    # internal partials dominate: (N-1) * Cpad * R * S * bytes
+    part32 = 999 * 10048 * 16 * 4
+    assert part32 < a < part32 * 1.2
+    assert 1.8 * a < b < 2.2 * a
+
+
+@pytest.mark.skipif(gpu_available(), reason="checks the no-GPU error path")
+def test_compute_without_gpu_is_device_error():
+    prob = synth.config_problem("hky16", seed=0, n_patterns=20)
+    ctx = B.Context.for_problem(prob)
+    try:
+        with pytest.raises(B.PhgError) as e:
+            ctx.gradient()
+        assert e.value.status == B.PHG_ERR_DEVICE
+    finally:
+        ctx.close()
