@@ -31,6 +31,22 @@ sys.path.insert(0, ROOT)
 
 METRIC = "branch-gradient evals/s at 1000 taxa x 10k patterns; p50/p99 request latency"
 HBM_PEAK_GBS = 8000.0
+KERNEL_SRC = os.path.join(ROOT, "paper_2303_04390_amd", "csrc", "phg_kernels.hip")
+
+# HBM bytes per evaluation by kernel class on the hky1000 FP32 workload, from two
+# rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE; scaled by a plain 1 GiB copy:
+# x2.0 and x1.0), recorded with the kernel source whose SHA-256 is given.  When
+# the kernel source changes the figure no longer applies and traffic is null.
+MEASURED_TRAFFIC = {
+    "kernel_source_sha256": "ffade6c5aa4b186e208b0c591e01b9e2f9c072d3244980e0f963a9c64f50ae26",
+    "bytes_per_eval": {"pre_grad": 1976587324, "post": 1386518026},
+}
+
+
+def kernel_source_sha256():
+    import hashlib
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
 
 
 def algorithmic_bytes(parent, n_tips, C, R, S, tsz):
@@ -75,6 +91,11 @@ def main():
     ap.add_argument("--cpu-sample-patterns", type=int, default=3000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--quick", action="store_true",
+                    help="throughput and kernel-class times only (for profiler runs)")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="first run a plain device copy of MIB MiB (read + write) three times, "
+                         "a known-size reference for HBM byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the path shards over "
@@ -93,6 +114,17 @@ def main():
     torch.cuda.set_device(dev)
     stream = torch.cuda.Stream(device=dev)
     out = torch.empty(1 + E, dtype=torch.float64, device=dev)
+
+    if args.calibrate_copy:
+        n = args.calibrate_copy * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.mul(src, 1.0, out=dst)
+        torch.cuda.synchronize()
+        print(f"[bench] calibration copy: {args.calibrate_copy} MiB read + written, 3 times",
+              file=sys.stderr, flush=True)
+        del src, dst
 
     def open_ctx(prec):
         h = B.phg_create(N, C, S, R, prec, 0)
@@ -129,14 +161,21 @@ def main():
     dominant = max(("post", "pre_grad"), key=lambda k: cls[k])
     dom_bytes = pre_bytes if dominant == "pre_grad" else post_bytes
     dom_ms = cls[dominant]
-    achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
+    n_launch = int(launches[B.PROF_NAMES.index(dominant)])
+    # per launch: algorithmic bytes / average launch duration (= per-eval totals)
+    achieved = (dom_bytes / n_launch) / (dom_ms * 1e-3 / n_launch) / 1e9
+    traffic = None
+    if (MEASURED_TRAFFIC["kernel_source_sha256"] == kernel_source_sha256()
+            and dominant in MEASURED_TRAFFIC["bytes_per_eval"]):
+        traffic = int(MEASURED_TRAFFIC["bytes_per_eval"][dominant] / n_launch)
     roofline = {
         "bound": "hbm", "kernel": "pre_s4_kernel<float,4>" if dominant == "pre_grad" else "post_s4_kernel<float,4>",
         "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-        "algorithmic_bytes_per_eval": int(dom_bytes),
-        "launches_per_eval": int(launches[B.PROF_NAMES.index(dominant)]),
-        "ms_per_eval": round(dom_ms, 4),
+        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+        "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+        "algorithmic_bytes_per_launch": int(dom_bytes / n_launch),
+        "launches_per_eval": n_launch,
+        "launch_avg_us": round(dom_ms * 1e3 / n_launch, 3),
     }
     m0 = (2 * N - 3) * R * S * 4 + 2 * N + (N - 1)
     path = {"ms_per_class": {k: round(v, 4) for k, v in cls.items()},
@@ -144,6 +183,14 @@ def main():
             "m0_bytes_per_eval": int(m0 * C),
             "m0_ceiling_evals_per_s": round(HBM_PEAK_GBS * 1e9 / (m0 * C), 1),
             "frac_of_m0_ceiling": round(value / (HBM_PEAK_GBS * 1e9 / (m0 * C)), 4)}
+
+    if args.quick:
+        B.phg_destroy(h)
+        rec = {"metric": METRIC, "value": round(value, 2), "unit": "evals/s", "n_gpus": 1,
+               "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
+               "quick": True, "roofline": roofline, "path": path}
+        print(json.dumps(rec), flush=True)
+        return
 
     # ------------------------------------------------ request latency (sync)
     rng = np.random.default_rng(123)

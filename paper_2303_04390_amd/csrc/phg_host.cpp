@@ -34,7 +34,7 @@ thread_local std::string g_create_error;
 
 // Workspace plan: byte offsets of every device buffer inside one arena.
 struct Plan {
-    size_t codes, part, expo, P64, dP64, P32, dP32, b, V, Vinv, lam, rates, cw, pi, pw, sll, gpart,
+    size_t codes, part, expo, P64, dP64, P32, dP32, b, V, Vinv, lam, rates, cw, pi, pw, sll, lpart, gpart,
         out, sched, total;
 };
 
@@ -68,6 +68,7 @@ Plan make_plan(int N, int C, int S, int R, phg_precision prec) {
     p.pi = take(S * 8);
     p.pw = take(static_cast<size_t>(Cpad) * 8);
     p.sll = take(static_cast<size_t>(Cpad) * 8);
+    p.lpart = take(static_cast<size_t>(tiles) * 8);
     p.gpart = take(E * tiles * 8);
     p.out = take((E + 1) * 8);
     p.sched = take(2 * I * sizeof(NodeTriple));
@@ -287,6 +288,7 @@ phg_status ensure_device(phg_context* ctx) {
     d.pi = reinterpret_cast<const double*>(a + pl.pi);
     d.pw = reinterpret_cast<const double*>(a + pl.pw);
     d.sll = reinterpret_cast<double*>(a + pl.sll);
+    d.lpart = reinterpret_cast<double*>(a + pl.lpart);
     d.gpart = reinterpret_cast<double*>(a + pl.gpart);
     ctx->dev_init = true;
     ctx->dirty = ctx->have | kPw;  // upload everything on first use

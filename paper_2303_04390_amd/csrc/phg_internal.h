@@ -29,6 +29,7 @@ struct NodeTriple {
 //                                            of the subtree below each node
 //   P,dP   double [E][R][S][S] (and float copies when T = float)
 //   sll    double [Cpad]                    per-pattern log site likelihood
+//   lpart  double [tiles]                   per-tile weighted log-likelihood sums
 //   gpart  double [E][tiles]                per-tile weighted gradient sums
 struct DeviceProblem {
     int N, C, Cpad, S, S4, R, tiles;
@@ -48,6 +49,7 @@ struct DeviceProblem {
     const double* pi;
     const double* pw;
     double* sll;
+    double* lpart;
     double* gpart;
 };
 

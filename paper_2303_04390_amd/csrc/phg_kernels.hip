@@ -110,7 +110,8 @@ __global__ __launch_bounds__(kBlock) void post_s4_kernel(
     const NodeTriple* __restrict__ level, int n_units, int tiles, int N, int Cpad,
     const uint8_t* __restrict__ codes, T* __restrict__ part, int32_t* __restrict__ expo,
     const T* __restrict__ P, const double* __restrict__ cw, const double* __restrict__ pi,
-    double* __restrict__ sll, int is_root) {
+    const double* __restrict__ pw, double* __restrict__ sll, double* __restrict__ lpart,
+    int is_root) {
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & (kLanes - 1);
     const int unit = blockIdx.x * kWavesPerBlock + wave;
@@ -163,7 +164,11 @@ __global__ __launch_bounds__(kBlock) void post_s4_kernel(
             site += cw[r] * acc;
         }
         // ln of a zero (or round-off negative) site likelihood is -inf
-        sll[c] = (site > 0.0 ? log(site) : -INFINITY) + static_cast<double>(ek) * 0.69314718055994530942;
+        const double ll = (site > 0.0 ? log(site) : -INFINITY) + static_cast<double>(ek) * 0.69314718055994530942;
+        sll[c] = ll;
+        const double W = pw[c];
+        const double tsum = wave_sum(W != 0.0 ? W * ll : 0.0);
+        if (lane == 0) lpart[tile] = tsum;
     }
 }
 
@@ -309,22 +314,17 @@ __global__ __launch_bounds__(256) void pmat_kernel(int E, int R, int S, const do
 
 // ---------------------------------------------------------------- final sums
 
+// Block x < E sums branch x's per-tile gradient partials; block E sums the
+// per-tile weighted log-likelihood partials.  Fixed order: deterministic.
 __global__ __launch_bounds__(256) void finalize_kernel(const double* __restrict__ gpart, int tiles,
-                                                       int E, const double* __restrict__ sll,
-                                                       const double* __restrict__ pw, int Cpad,
+                                                       int E, const double* __restrict__ lpart,
                                                        double* __restrict__ out_logl,
                                                        double* __restrict__ out_grad) {
     __shared__ double red[256];
     const int blk = blockIdx.x;
+    const double* src = blk < E ? gpart + static_cast<size_t>(blk) * tiles : lpart;
     double acc = 0.0;
-    if (blk < E) {
-        for (int t = threadIdx.x; t < tiles; t += 256) acc += gpart[static_cast<size_t>(blk) * tiles + t];
-    } else {
-        for (int c = threadIdx.x; c < Cpad; c += 256) {
-            const double w = pw[c];
-            if (w != 0.0) acc += w * sll[c];
-        }
-    }
+    for (int t = threadIdx.x; t < tiles; t += 256) acc += src[t];
     red[threadIdx.x] = acc;
     __syncthreads();
     for (int h = 128; h > 0; h >>= 1) {
@@ -359,7 +359,7 @@ hipError_t post_r(const DeviceProblem& d, const NodeTriple* level, int n_nodes, 
     const int blocks = (n_units + kWavesPerBlock - 1) / kWavesPerBlock;
     hipLaunchKernelGGL((post_s4_kernel<T, R>), dim3(blocks), dim3(kBlock), 0, st, level, n_units,
                        d.tiles, d.N, d.Cpad, d.codes, static_cast<T*>(d.part), d.expo, ptab<T>(d),
-                       d.cweights, d.pi, d.sll, is_root ? 1 : 0);
+                       d.cweights, d.pi, d.pw, d.sll, d.lpart, is_root ? 1 : 0);
     return hipGetLastError();
 }
 
@@ -422,8 +422,8 @@ hipError_t launch_pre_level(const DeviceProblem& d, bool fp32, const NodeTriple*
 hipError_t launch_finalize(const DeviceProblem& d, double* out_logl, double* out_grad,
                            hipStream_t st) {
     const int E = 2 * d.N - 2;
-    hipLaunchKernelGGL(finalize_kernel, dim3(E + 1), dim3(256), 0, st, d.gpart, d.tiles, E, d.sll,
-                       d.pw, d.Cpad, out_logl, out_grad);
+    hipLaunchKernelGGL(finalize_kernel, dim3(E + 1), dim3(256), 0, st, d.gpart, d.tiles, E, d.lpart,
+                       out_logl, out_grad);
     return hipGetLastError();
 }
 
