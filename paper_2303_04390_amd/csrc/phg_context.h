@@ -1,0 +1,109 @@
+// Internal: the context object behind the opaque phg_context handle, shared by
+// the single-request ABI (phg_host.cpp) and the serving engine (phg_server.cpp).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "../../include/phg.h"
+#include "phg_internal.h"
+
+namespace phg {
+
+// Workspace plan: byte offsets of every device buffer inside one arena.
+struct Plan {
+    size_t codes, part, expo, P64, dP64, P32, dP32, b, V, Vinv, lam, rates, cw, pi, pw, sll, lpart,
+        gpart, out, sched, desc, total;
+};
+Plan make_plan(int N, int C, int S, int R, phg_precision prec);
+
+enum InputBit : unsigned {
+    kTopo = 1u << 0,
+    kB = 1u << 1,
+    kEig = 1u << 2,
+    kPi = 1u << 3,
+    kCat = 1u << 4,
+    kTips = 1u << 5,
+    kPw = 1u << 6,
+    kRequired = kTopo | kB | kEig | kPi | kCat | kTips,
+};
+
+constexpr int kProfEvents = PHG_PROF_CLASSES + 1;
+
+}  // namespace phg
+
+struct phg_context {
+    int N = 0, C = 0, S = 0, R = 0, device = 0;
+    phg_precision prec = PHG_FP64;
+    int Cpad = 0, tiles = 0, S4 = 0;
+    std::string err;
+
+    // host mirrors of every input
+    std::vector<int32_t> parent;
+    std::vector<double> b, V, Vinv, lam, pi, rates, cw, pw;
+    std::vector<uint8_t> codes;  // [N][Cpad], padding = S
+    unsigned have = 0;           // inputs set at least once
+    unsigned dirty = 0;          // inputs changed since the last upload
+
+    // schedule (host copy; uploaded to the sched region)
+    std::vector<phg::NodeTriple> sched;     // post levels then pre levels
+    std::vector<int> post_off, pre_off;     // level start offsets (size levels+1)
+
+    // device state
+    bool dev_init = false;
+    bool own_arena = false;
+    char* arena = nullptr;
+    char* bound_ws = nullptr;
+    size_t bound_ws_bytes = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    double* host_out = nullptr;  // pinned (1 + E) doubles
+    phg::Plan plan{};
+    phg::ReqDesc rd{};           // host copy of this request's descriptor
+
+    // profiling: kProfEvents events per recorded evaluation
+    bool prof_on = false;
+    std::vector<hipEvent_t> prof_pool;
+    size_t prof_used = 0;
+
+    phg_status fail(phg_status s, const char* fmt, ...) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        err = buf;
+        return s;
+    }
+};
+
+#define PHG_HIP(ctx, call)                                                                  \
+    do {                                                                                    \
+        hipError_t e_ = (call);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return (ctx)->fail(e_ == hipErrorOutOfMemory ? PHG_ERR_OOM : PHG_ERR_DEVICE,    \
+                               "%s failed: %s", #call, hipGetErrorString(e_));              \
+    } while (0)
+
+#define PHG_TRY(expr)                \
+    do {                             \
+        phg_status s_ = (expr);      \
+        if (s_ != PHG_OK) return s_; \
+    } while (0)
+
+namespace phg {
+
+// Validate required inputs, allocate / bind device memory on first use and
+// upload whatever changed (on the context's stream).
+phg_status ctx_ready(phg_context* ctx);
+// Device pointer of this context's descriptor and of its output region.
+ReqDesc* ctx_desc_dev(phg_context* ctx);
+double* ctx_out_dev(phg_context* ctx);
+// Enqueue one whole evaluation of this context alone.
+phg_status ctx_enqueue_eval(phg_context* ctx, double* d_logl, double* d_grad);
+
+}  // namespace phg

@@ -11,36 +11,28 @@
 
 #include <algorithm>
 #include <cmath>
-#include <cstdarg>
-#include <cstdio>
 #include <cstring>
 #include <limits>
 #include <new>
 #include <string>
 #include <vector>
 
-#include "../../include/phg.h"
-#include "phg_internal.h"
+#include "phg_context.h"
 
-using phg::DeviceProblem;
 using phg::NodeTriple;
+using phg::ReqDesc;
+using phg::SegTable;
+
+namespace phg {
 
 namespace {
-
 constexpr size_t kAlign = 256;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
-
-thread_local std::string g_create_error;
-
-// Workspace plan: byte offsets of every device buffer inside one arena.
-struct Plan {
-    size_t codes, part, expo, P64, dP64, P32, dP32, b, V, Vinv, lam, rates, cw, pi, pw, sll, lpart, gpart,
-        out, sched, total;
-};
+}  // namespace
 
 Plan make_plan(int N, int C, int S, int R, phg_precision prec) {
-    const int Cpad = (C + phg::kLanes - 1) / phg::kLanes * phg::kLanes;
-    const int tiles = Cpad / phg::kLanes;
+    const int Cpad = (C + kLanes - 1) / kLanes * kLanes;
+    const int tiles = Cpad / kLanes;
     const int S4 = (S + 3) / 4;
     const size_t E = 2 * static_cast<size_t>(N) - 2;
     const size_t I = static_cast<size_t>(N) - 1;
@@ -53,7 +45,7 @@ Plan make_plan(int N, int C, int S, int R, phg_precision prec) {
         return o;
     };
     p.codes = take(static_cast<size_t>(N) * Cpad);
-    p.part = take(I * tiles * R * S4 * phg::kLanes * 4 * tsz);
+    p.part = take(I * tiles * R * S4 * kLanes * 4 * tsz);
     p.expo = take(I * Cpad * sizeof(int32_t));
     p.P64 = take(E * R * S * S * 8);
     p.dP64 = take(E * R * S * S * 8);
@@ -72,84 +64,24 @@ Plan make_plan(int N, int C, int S, int R, phg_precision prec) {
     p.gpart = take(E * tiles * 8);
     p.out = take((E + 1) * 8);
     p.sched = take(2 * I * sizeof(NodeTriple));
+    p.desc = take(sizeof(ReqDesc));
     p.total = off;
     return p;
 }
+
+}  // namespace phg
+
+using namespace phg;
+
+namespace {
+
+thread_local std::string g_create_error;
 
 bool finite_all(const double* x, size_t n) {
     for (size_t i = 0; i < n; ++i)
         if (!std::isfinite(x[i])) return false;
     return true;
 }
-
-}  // namespace
-
-enum InputBit : unsigned {
-    kTopo = 1u << 0,
-    kB = 1u << 1,
-    kEig = 1u << 2,
-    kPi = 1u << 3,
-    kCat = 1u << 4,
-    kTips = 1u << 5,
-    kPw = 1u << 6,
-    kRequired = kTopo | kB | kEig | kPi | kCat | kTips,
-};
-
-struct phg_context {
-    int N = 0, C = 0, S = 0, R = 0, device = 0;
-    phg_precision prec = PHG_FP64;
-    int Cpad = 0, tiles = 0, S4 = 0;
-    std::string err;
-
-    // host mirrors of every input
-    std::vector<int32_t> parent;
-    std::vector<double> b, V, Vinv, lam, pi, rates, cw, pw;
-    std::vector<uint8_t> codes;  // [N][Cpad], padding = S
-    unsigned have = 0;           // inputs set at least once
-    unsigned dirty = 0;          // inputs changed since the last upload
-
-    // schedule (host copy; uploaded to the sched region)
-    std::vector<NodeTriple> sched;          // post levels then pre levels
-    std::vector<int> post_off, pre_off;     // level start offsets (size levels+1)
-
-    // device state
-    bool dev_init = false;
-    bool own_arena = false;
-    char* arena = nullptr;
-    size_t arena_bytes = 0;
-    char* bound_ws = nullptr;
-    size_t bound_ws_bytes = 0;
-    hipStream_t stream = nullptr;
-    bool own_stream = false;
-    double* host_out = nullptr;  // pinned (1 + E) doubles
-    Plan plan{};
-    DeviceProblem dp{};
-
-    // profiling: PHG_PROF_CLASSES + 1 events per recorded evaluation
-    bool prof_on = false;
-    std::vector<hipEvent_t> prof_pool;   // reusable events
-    size_t prof_used = 0;                // events in use (multiple of 5)
-
-    phg_status fail(phg_status s, const char* fmt, ...) {
-        char buf[512];
-        va_list ap;
-        va_start(ap, fmt);
-        vsnprintf(buf, sizeof buf, fmt, ap);
-        va_end(ap);
-        err = buf;
-        return s;
-    }
-};
-
-#define PHG_HIP(ctx, call)                                                                  \
-    do {                                                                                    \
-        hipError_t e_ = (call);                                                             \
-        if (e_ != hipSuccess)                                                               \
-            return (ctx)->fail(e_ == hipErrorOutOfMemory ? PHG_ERR_OOM : PHG_ERR_DEVICE,    \
-                               "%s failed: %s", #call, hipGetErrorString(e_));              \
-    } while (0)
-
-namespace {
 
 phg_status check_sizes(int n_tips, int n_patterns, int n_states, int n_categories, int prec,
                        std::string* why) {
@@ -233,7 +165,7 @@ phg_status ensure_device(phg_context* ctx) {
     if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
         return ctx->fail(PHG_ERR_DEVICE, "device %d is %s; this library is built for gfx950 only",
                          ctx->device, prop.gcnArchName);
-    if (!phg::kernels_support(ctx->S, ctx->R))
+    if (!kernels_support(ctx->S, ctx->R))
         return ctx->fail(PHG_ERR_ARG, "no kernel for S=%d, R=%d in this build", ctx->S, ctx->R);
 
     ctx->plan = make_plan(ctx->N, ctx->C, ctx->S, ctx->R, ctx->prec);
@@ -252,7 +184,6 @@ phg_status ensure_device(phg_context* ctx) {
         ctx->arena = static_cast<char*>(p);
         ctx->own_arena = true;
     }
-    ctx->arena_bytes = ctx->plan.total;
     if (!ctx->stream) {
         PHG_HIP(ctx, hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking));
         ctx->own_stream = true;
@@ -264,7 +195,8 @@ phg_status ensure_device(phg_context* ctx) {
 
     const Plan& pl = ctx->plan;
     char* a = ctx->arena;
-    DeviceProblem& d = ctx->dp;
+    ReqDesc& d = ctx->rd;
+    d = ReqDesc{};
     d.N = ctx->N;
     d.C = ctx->C;
     d.Cpad = ctx->Cpad;
@@ -272,6 +204,8 @@ phg_status ensure_device(phg_context* ctx) {
     d.S4 = ctx->S4;
     d.R = ctx->R;
     d.tiles = ctx->tiles;
+    d.fp32 = ctx->prec == PHG_FP32_SCALED ? 1 : 0;
+    d.sched = reinterpret_cast<const NodeTriple*>(a + pl.sched);
     d.codes = reinterpret_cast<const uint8_t*>(a + pl.codes);
     d.part = a + pl.part;
     d.expo = reinterpret_cast<int32_t*>(a + pl.expo);
@@ -290,6 +224,8 @@ phg_status ensure_device(phg_context* ctx) {
     d.sll = reinterpret_cast<double*>(a + pl.sll);
     d.lpart = reinterpret_cast<double*>(a + pl.lpart);
     d.gpart = reinterpret_cast<double*>(a + pl.gpart);
+    PHG_HIP(ctx, hipMemcpyAsync(a + pl.desc, &ctx->rd, sizeof(ReqDesc), hipMemcpyHostToDevice,
+                                ctx->stream));
     ctx->dev_init = true;
     ctx->dirty = ctx->have | kPw;  // upload everything on first use
     return PHG_OK;
@@ -326,8 +262,6 @@ phg_status upload(phg_context* ctx) {
     return PHG_OK;
 }
 
-constexpr int kProfEvents = PHG_PROF_CLASSES + 1;
-
 // Record the next profiling event of the current evaluation (no-op when off).
 phg_status prof_mark(phg_context* ctx) {
     if (!ctx->prof_on) return PHG_OK;
@@ -340,38 +274,50 @@ phg_status prof_mark(phg_context* ctx) {
     return PHG_OK;
 }
 
-#define PHG_TRY(expr)                     \
-    do {                                  \
-        phg_status s_ = (expr);           \
-        if (s_ != PHG_OK) return s_;      \
-    } while (0)
+SegTable one_segment(int units, int sched_off, int n_nodes, int flags, double* out_logl,
+                     double* out_grad) {
+    SegTable t{};
+    t.n = 1;
+    t.unit_begin[0] = 0;
+    t.unit_begin[1] = units;
+    t.seg[0] = Segment{0, sched_off, n_nodes, flags, out_logl, out_grad};
+    return t;
+}
 
-phg_status enqueue_eval(phg_context* ctx, double* d_logl, double* d_grad) {
-    const bool fp32 = ctx->prec == PHG_FP32_SCALED;
+}  // namespace
+
+namespace phg {
+
+phg_status ctx_enqueue_eval(phg_context* ctx, double* d_logl, double* d_grad) {
     hipStream_t st = ctx->stream;
-    const DeviceProblem& d = ctx->dp;
-    const NodeTriple* sched = reinterpret_cast<const NodeTriple*>(ctx->arena + ctx->plan.sched);
+    const ReqDesc& d = ctx->rd;
+    const ReqDesc* descs = ctx_desc_dev(ctx);
     PHG_TRY(prof_mark(ctx));
-    PHG_HIP(ctx, phg::launch_pmat(d, fp32, st));
+    PHG_HIP(ctx, launch_class(kPmat, d, descs, one_segment(units_for(kPmat, d, 0), 0, 0, 0, nullptr, nullptr), st));
     PHG_TRY(prof_mark(ctx));
     const int H = static_cast<int>(ctx->post_off.size()) - 1;
     for (int h = 0; h < H; ++h) {
         const int a = ctx->post_off[h], n = ctx->post_off[h + 1] - a;
-        PHG_HIP(ctx, phg::launch_post_level(d, fp32, sched + a, n, h == H - 1, st));
+        PHG_HIP(ctx, launch_class(kPost, d, descs,
+                                  one_segment(units_for(kPost, d, n), a, n, h == H - 1 ? 1 : 0, nullptr, nullptr), st));
     }
     PHG_TRY(prof_mark(ctx));
     const int D = static_cast<int>(ctx->pre_off.size()) - 1;
     for (int l = 0; l < D; ++l) {
         const int a = ctx->pre_off[l], n = ctx->pre_off[l + 1] - a;
-        PHG_HIP(ctx, phg::launch_pre_level(d, fp32, sched + a, n, st));
+        PHG_HIP(ctx, launch_class(kPre, d, descs, one_segment(units_for(kPre, d, n), a, n, 0, nullptr, nullptr), st));
     }
     PHG_TRY(prof_mark(ctx));
-    PHG_HIP(ctx, phg::launch_finalize(d, d_logl, d_grad, st));
+    PHG_HIP(ctx, launch_class(kFinal, d, descs,
+                              one_segment(units_for(kFinal, d, 0), 0, 0, 0, d_logl, d_grad), st));
     PHG_TRY(prof_mark(ctx));
     return PHG_OK;
 }
 
-phg_status ready(phg_context* ctx) {
+ReqDesc* ctx_desc_dev(phg_context* ctx) { return reinterpret_cast<ReqDesc*>(ctx->arena + ctx->plan.desc); }
+double* ctx_out_dev(phg_context* ctx) { return reinterpret_cast<double*>(ctx->arena + ctx->plan.out); }
+
+phg_status ctx_ready(phg_context* ctx) {
     if ((ctx->have & kRequired) != kRequired) {
         std::string miss;
         if (!(ctx->have & kTopo)) miss += " topology";
@@ -387,7 +333,7 @@ phg_status ready(phg_context* ctx) {
     return upload(ctx);
 }
 
-}  // namespace
+}  // namespace phg
 
 extern "C" {
 
@@ -570,16 +516,16 @@ phg_status phg_set_pattern_weights(phg_context* ctx, const double* w) {
 
 phg_status phg_prepare(phg_context* ctx) {
     if (!ctx) return PHG_ERR_ARG;
-    return ready(ctx);
+    return ctx_ready(ctx);
 }
 
 phg_status phg_gradient(phg_context* ctx, double* logl, double* grad) {
     if (!ctx) return PHG_ERR_ARG;
     if (!grad) return ctx->fail(PHG_ERR_ARG, "grad is NULL");
-    phg_status s = ready(ctx);
+    phg_status s = ctx_ready(ctx);
     if (s != PHG_OK) return s;
-    double* dout = reinterpret_cast<double*>(ctx->arena + ctx->plan.out);
-    s = enqueue_eval(ctx, dout, dout + 1);
+    double* dout = ctx_out_dev(ctx);
+    s = ctx_enqueue_eval(ctx, dout, dout + 1);
     if (s != PHG_OK) return s;
     const size_t E = 2 * static_cast<size_t>(ctx->N) - 2;
     PHG_HIP(ctx, hipMemcpyAsync(ctx->host_out, dout, (E + 1) * sizeof(double), hipMemcpyDeviceToHost,
@@ -647,9 +593,9 @@ phg_status phg_bind_stream(phg_context* ctx, void* hip_stream) {
 phg_status phg_gradient_async(phg_context* ctx, double* d_logl, double* d_grad) {
     if (!ctx) return PHG_ERR_ARG;
     if (!d_logl || !d_grad) return ctx->fail(PHG_ERR_ARG, "NULL device output pointer");
-    phg_status s = ready(ctx);
+    phg_status s = ctx_ready(ctx);
     if (s != PHG_OK) return s;
-    return enqueue_eval(ctx, d_logl, d_grad);
+    return ctx_enqueue_eval(ctx, d_logl, d_grad);
 }
 
 phg_status phg_schedule_info(phg_context* ctx, int* n_post_levels, int* n_pre_levels,

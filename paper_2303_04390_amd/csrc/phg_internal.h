@@ -1,5 +1,5 @@
-// Internal declarations shared by the host runtime (phg_host.cpp) and the
-// gfx950 kernels (phg_kernels.hip).  Not part of the public ABI.
+// Internal declarations shared by the host runtime (phg_host.cpp, phg_server.cpp)
+// and the gfx950 kernels (phg_kernels.hip).  Not part of the public ABI.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -17,22 +17,24 @@ struct NodeTriple {
     int32_t k, i, j, pad;
 };
 
-// Device-side view of one problem: sizes plus pointers into the workspace.
-// Layouts (T = float or double, per precision):
-//   codes  uint8  [N][Cpad]                 tip states, S = all-ones, pad = S
-//   part   T      [N-1][tiles][R][S4][64][4] post-order partial of each
-//                                            internal node (slot = id - N);
-//                                            overwritten in place by the
-//                                            pre-order partial during the
-//                                            pre-order pass
-//   expo   int32  [N-1][Cpad]               cumulative power-of-two exponent
-//                                            of the subtree below each node
-//   P,dP   double [E][R][S][S] (and float copies when T = float)
-//   sll    double [Cpad]                    per-pattern log site likelihood
-//   lpart  double [tiles]                   per-tile weighted log-likelihood sums
-//   gpart  double [E][tiles]                per-tile weighted gradient sums
-struct DeviceProblem {
-    int N, C, Cpad, S, S4, R, tiles;
+// Device-resident description of one evaluation request (one tree and
+// alignment with its own workspace).  Layouts (T = float or double):
+//   codes  uint8  [N][Cpad]                  tip states, S = all-ones, pad = S
+//   part   T      [N-1][tiles][R][S4][64][4]  post-order partial of each
+//                                             internal node (slot = id - N);
+//                                             overwritten in place by the
+//                                             pre-order partial
+//   expo   int32  [N-1][Cpad]                cumulative power-of-two exponent
+//                                             of the subtree below each node
+//   P64,dP64 double [E][R][S][S]; P32,dP32 float copies (FP32 path only)
+//   sll    double [Cpad]                     per-pattern log site likelihood
+//   lpart  double [tiles]                    per-tile weighted log-likelihood
+//   gpart  double [E][tiles]                 per-tile weighted gradient sums
+//   sched  NodeTriple [2(N-1)]               post-order levels then pre-order
+//                                             levels of this request's tree
+struct ReqDesc {
+    int32_t N, C, Cpad, S, S4, R, tiles, fp32;
+    const NodeTriple* sched;
     const uint8_t* codes;
     void* part;
     int32_t* expo;
@@ -53,15 +55,33 @@ struct DeviceProblem {
     double* gpart;
 };
 
-// Kernel launchers (phg_kernels.hip).  All enqueue on `stream` and return the
-// launch status.  fp32 selects float partials.
-hipError_t launch_pmat(const DeviceProblem& d, bool fp32, hipStream_t stream);
-hipError_t launch_post_level(const DeviceProblem& d, bool fp32, const NodeTriple* level,
-                             int n_nodes, bool is_root, hipStream_t stream);
-hipError_t launch_pre_level(const DeviceProblem& d, bool fp32, const NodeTriple* level,
-                            int n_nodes, hipStream_t stream);
-hipError_t launch_finalize(const DeviceProblem& d, double* out_logl, double* out_grad,
-                           hipStream_t stream);
+// A launch processes the work units of up to kMaxSegs segments; a segment is
+// one request's slice of that launch (one level, or the whole pmat/finalize
+// stage).  Units of segment s are [unit_begin[s], unit_begin[s+1]).
+constexpr int kMaxSegs = 48;
+struct Segment {
+    int32_t desc;        // index into the descriptor table
+    int32_t sched_off;   // first NodeTriple of the level in `sched` (levels only)
+    int32_t n_nodes;     // nodes in the level (levels only)
+    int32_t flags;       // bit 0: this post-order level is the root level
+    double* out_logl;    // finalize only: where log P(Y) goes
+    double* out_grad;    // finalize only: where the 2N-2 derivatives go
+};
+struct SegTable {
+    int32_t n;
+    int32_t unit_begin[kMaxSegs + 1];
+    Segment seg[kMaxSegs];
+};
+
+enum KernelClass { kPmat = 0, kPost = 1, kPre = 2, kFinal = 3 };
+
+// Work units one segment contributes to a launch of the given class.
+int units_for(KernelClass k, const ReqDesc& d, int n_nodes);
+
+// Kernel launchers (phg_kernels.hip).  All requests in one table share S, R
+// and precision.  `descs` and `sched` are device pointers.
+hipError_t launch_class(KernelClass k, const ReqDesc& shape, const ReqDesc* descs,
+                        const SegTable& t, hipStream_t stream);
 bool kernels_support(int S, int R);
 
 }  // namespace phg

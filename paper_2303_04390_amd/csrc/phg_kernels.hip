@@ -17,14 +17,19 @@
 //             because dP_x = gamma_r P_x Q; weighted by W_c and reduced over
 //             the 64 patterns of the wavefront in float64.
 //   finalize  fixed-order float64 sums over pattern tiles
-//             (eq:gradientSumAcrossColumns) and over patterns for log P(Y).
+//             (eq:gradientSumAcrossColumns) and over tiles for log P(Y).
 //
-// Work unit: one wavefront = (one node, one tile of 64 consecutive patterns);
-// lane = pattern.  For S = 4 each lane keeps the R x 4 values of its pattern
-// in registers and loops over categories; P and dP of a branch are the same
-// for every lane, so they come through scalar loads.  Partials are stored
-// [slot][tile][r][lane][4], so each category of a unit is one contiguous
-// 1 KiB (float) wave access.
+// Every launch carries a segment table: each segment is one request's slice
+// (a level of its tree, or its whole pmat / finalize stage), so one launch
+// can advance several requests of different trees at once.  Per-request
+// pointers and sizes come from a device-resident descriptor table.
+//
+// Work unit of the level kernels: one wavefront = (one node, one tile of 64
+// consecutive patterns); lane = pattern.  For S = 4 each lane keeps the R x 4
+// values of its pattern in registers and loops over categories; P and dP of a
+// branch are the same for every lane, so they come through scalar loads.
+// Partials are stored [slot][tile][r][lane][4], so each category of a unit is
+// one contiguous 1 KiB (float) wave access.
 #include "phg_internal.h"
 
 #include <math.h>
@@ -35,10 +40,29 @@ namespace {
 constexpr int kWavesPerBlock = 4;
 constexpr int kBlock = kWavesPerBlock * kLanes;
 
+// Pointers read from a request descriptor are generic (flat) pointers; the
+// unit bodies take them in the global address space so that loads are global
+// loads and wave-uniform ones (P, dP, pi, weights) become scalar loads.
+#define GLOBAL __attribute__((address_space(1)))
 template <typename T>
-struct alignas(4 * sizeof(T)) Quad {
-    T v[4];
+__device__ __forceinline__ GLOBAL T* g(T* p) {
+    return (GLOBAL T*)p;
+}
+
+// Four consecutive values of one lane as a native vector (one 16 B / 32 B access).
+template <typename T>
+struct Vec4T;
+template <>
+struct Vec4T<float> {
+    typedef float type __attribute__((ext_vector_type(4)));
 };
+template <>
+struct Vec4T<double> {
+    typedef double type __attribute__((ext_vector_type(4)));
+};
+template <typename T>
+using Vec4 = typename Vec4T<T>::type;
+typedef int Int4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -59,18 +83,44 @@ __device__ __forceinline__ int exponent_of(double x) {
     return e;
 }
 
+template <typename T>
+__device__ __forceinline__ T* part_of(const ReqDesc& d) {
+    return static_cast<T*>(d.part);
+}
+template <typename T>
+__device__ __forceinline__ const T* ptab(const ReqDesc& d);
+template <>
+__device__ __forceinline__ const float* ptab<float>(const ReqDesc& d) { return d.P32; }
+template <>
+__device__ __forceinline__ const double* ptab<double>(const ReqDesc& d) { return d.P64; }
+template <typename T>
+__device__ __forceinline__ const T* dptab(const ReqDesc& d);
+template <>
+__device__ __forceinline__ const float* dptab<float>(const ReqDesc& d) { return d.dP32; }
+template <>
+__device__ __forceinline__ const double* dptab<double>(const ReqDesc& d) { return d.dP64; }
+
+// Segment of a (wave-uniform) unit index: linear scan of the table.
+__device__ __forceinline__ int find_segment(const SegTable& t, int unit) {
+    int s = 0;
+    while (s + 1 < t.n && unit >= t.unit_begin[s + 1]) ++s;
+    return s;
+}
+
 // Child partial of category r for this lane's pattern.  tip_code < 0 means an
 // internal child read from its slot; otherwise the one-hot (or all-ones for
 // code 4) tip vector is formed on the fly.
 template <typename T, int R>
-__device__ __forceinline__ void child_vec(const T* __restrict__ part, int slot, int tile, int tiles,
+__device__ __forceinline__ void child_vec(const GLOBAL T* __restrict__ part, int slot, int tile, int tiles,
                                           int r, int lane, int tip_code, T out[4]) {
     if (tip_code < 0) {
-        const Quad<T>* src = reinterpret_cast<const Quad<T>*>(part) +
-                             ((static_cast<size_t>(slot) * tiles + tile) * R + r) * kLanes + lane;
-        const Quad<T> q = *src;
-#pragma unroll
-        for (int t = 0; t < 4; ++t) out[t] = q.v[t];
+        const GLOBAL Vec4<T>* src = reinterpret_cast<const GLOBAL Vec4<T>*>(part) +
+                                    ((static_cast<size_t>(slot) * tiles + tile) * R + r) * kLanes + lane;
+        const Vec4<T> q = *src;
+        out[0] = q.x;
+        out[1] = q.y;
+        out[2] = q.z;
+        out[3] = q.w;
     } else {
 #pragma unroll
         for (int t = 0; t < 4; ++t) out[t] = (tip_code == t || tip_code >= 4) ? T(1) : T(0);
@@ -78,18 +128,20 @@ __device__ __forceinline__ void child_vec(const T* __restrict__ part, int slot, 
 }
 
 template <typename T, int R>
-__device__ __forceinline__ void store_vec(T* __restrict__ part, int slot, int tile, int tiles,
+__device__ __forceinline__ void store_vec(GLOBAL T* __restrict__ part, int slot, int tile, int tiles,
                                           int r, int lane, const T v[4]) {
-    Quad<T> q;
-#pragma unroll
-    for (int t = 0; t < 4; ++t) q.v[t] = v[t];
-    reinterpret_cast<Quad<T>*>(part)[((static_cast<size_t>(slot) * tiles + tile) * R + r) * kLanes +
-                                     lane] = q;
+    Vec4<T> q;
+    q.x = v[0];
+    q.y = v[1];
+    q.z = v[2];
+    q.w = v[3];
+    reinterpret_cast<GLOBAL Vec4<T>*>(part)[((static_cast<size_t>(slot) * tiles + tile) * R + r) * kLanes +
+                                            lane] = q;
 }
 
 // m = M v for a 4x4 row-major matrix (m_s = sum_t M_st v_t).
 template <typename T>
-__device__ __forceinline__ void matvec4(const T* __restrict__ M, const T v[4], T m[4]) {
+__device__ __forceinline__ void matvec4(const GLOBAL T* __restrict__ M, const T v[4], T m[4]) {
 #pragma unroll
     for (int s = 0; s < 4; ++s)
         m[s] = M[4 * s + 0] * v[0] + M[4 * s + 1] * v[1] + M[4 * s + 2] * v[2] + M[4 * s + 3] * v[3];
@@ -97,7 +149,7 @@ __device__ __forceinline__ void matvec4(const T* __restrict__ M, const T v[4], T
 
 // m = M^T v (m_t = sum_s M_st v_s).
 template <typename T>
-__device__ __forceinline__ void matvec4_t(const T* __restrict__ M, const T v[4], T m[4]) {
+__device__ __forceinline__ void matvec4_t(const GLOBAL T* __restrict__ M, const T v[4], T m[4]) {
 #pragma unroll
     for (int t = 0; t < 4; ++t)
         m[t] = M[t] * v[0] + M[4 + t] * v[1] + M[8 + t] * v[2] + M[12 + t] * v[3];
@@ -105,22 +157,21 @@ __device__ __forceinline__ void matvec4_t(const T* __restrict__ M, const T v[4],
 
 // ---------------------------------------------------------------- post-order
 
+// Body of one post-order unit.  Pointer parameters are __restrict__ so that,
+// once inlined, the compiler knows the stores to part/expo cannot alias the
+// matrices and keeps the wave-uniform P loads on the scalar unit.
 template <typename T, int R>
-__global__ __launch_bounds__(kBlock) void post_s4_kernel(
-    const NodeTriple* __restrict__ level, int n_units, int tiles, int N, int Cpad,
-    const uint8_t* __restrict__ codes, T* __restrict__ part, int32_t* __restrict__ expo,
-    const T* __restrict__ P, const double* __restrict__ cw, const double* __restrict__ pi,
-    const double* __restrict__ pw, double* __restrict__ sll, double* __restrict__ lpart,
-    int is_root) {
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int lane = threadIdx.x & (kLanes - 1);
-    const int unit = blockIdx.x * kWavesPerBlock + wave;
-    if (unit >= n_units) return;
-    const int node_ix = unit / tiles;
-    const int tile = unit - node_ix * tiles;
-    const NodeTriple nt = level[node_ix];
+__device__ __forceinline__ void post_unit(const NodeTriple nt, const int tile, const int tiles,
+                                          const int N, const int Cpad, const int lane, const int flags,
+                                          const GLOBAL uint8_t* __restrict__ codes,
+                                          GLOBAL T* __restrict__ part, GLOBAL int32_t* __restrict__ expo,
+                                          const GLOBAL T* __restrict__ P,
+                                          const GLOBAL double* __restrict__ cw,
+                                          const GLOBAL double* __restrict__ pi,
+                                          const GLOBAL double* __restrict__ pw,
+                                          GLOBAL double* __restrict__ sll,
+                                          GLOBAL double* __restrict__ lpart) {
     const int c = tile * kLanes + lane;
-
     const bool tip_i = nt.i < N, tip_j = nt.j < N;
     const int code_i = tip_i ? codes[static_cast<size_t>(nt.i) * Cpad + c] : -1;
     const int code_j = tip_j ? codes[static_cast<size_t>(nt.j) * Cpad + c] : -1;
@@ -150,7 +201,7 @@ __global__ __launch_bounds__(kBlock) void post_s4_kernel(
         for (int s = 0; s < 4; ++s) x[r][s] = exact_ldexp(x[r][s], -e);
     const int ek = e + ei + ej;
 
-    if (!is_root) {
+    if (!(flags & 1)) {
 #pragma unroll
         for (int r = 0; r < R; ++r) store_vec<T, R>(part, nt.k - N, tile, tiles, r, lane, x[r]);
         expo[static_cast<size_t>(nt.k - N) * Cpad + c] = ek;
@@ -164,7 +215,8 @@ __global__ __launch_bounds__(kBlock) void post_s4_kernel(
             site += cw[r] * acc;
         }
         // ln of a zero (or round-off negative) site likelihood is -inf
-        const double ll = (site > 0.0 ? log(site) : -INFINITY) + static_cast<double>(ek) * 0.69314718055994530942;
+        const double ll =
+            (site > 0.0 ? log(site) : -INFINITY) + static_cast<double>(ek) * 0.69314718055994530942;
         sll[c] = ll;
         const double W = pw[c];
         const double tsum = wave_sum(W != 0.0 ? W * ll : 0.0);
@@ -172,24 +224,41 @@ __global__ __launch_bounds__(kBlock) void post_s4_kernel(
     }
 }
 
-// ---------------------------------------------------------------- pre-order + gradient
-
 template <typename T, int R>
-__global__ __launch_bounds__(kBlock) void pre_s4_kernel(
-    const NodeTriple* __restrict__ level, int n_units, int tiles, int N, int Cpad,
-    const uint8_t* __restrict__ codes, T* __restrict__ part, const T* __restrict__ P,
-    const T* __restrict__ dP, const double* __restrict__ cw, const double* __restrict__ pi,
-    const double* __restrict__ pw, double* __restrict__ gpart) {
+__global__ __launch_bounds__(kBlock) void post_s4_kernel(const ReqDesc* __restrict__ descs,
+                                                         const SegTable segs) {
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & (kLanes - 1);
     const int unit = blockIdx.x * kWavesPerBlock + wave;
-    if (unit >= n_units) return;
-    const int node_ix = unit / tiles;
-    const int tile = unit - node_ix * tiles;
-    const NodeTriple nt = level[node_ix];
+    if (unit >= segs.unit_begin[segs.n]) return;
+    const int sidx = find_segment(segs, unit);
+    const Segment sg = segs.seg[sidx];
+    const ReqDesc& d = descs[sg.desc];
+    const int tiles = d.tiles;
+    const int local = unit - segs.unit_begin[sidx];
+    const int node_ix = local / tiles;
+    const int tile = local - node_ix * tiles;
+    const Int4 t4 = reinterpret_cast<const GLOBAL Int4*>(g(d.sched))[sg.sched_off + node_ix];
+    const NodeTriple nt{t4.x, t4.y, t4.z, 0};
+    post_unit<T, R>(nt, tile, tiles, d.N, d.Cpad, lane, sg.flags, g(d.codes), g(part_of<T>(d)),
+                    g(d.expo), g(ptab<T>(d)), g(d.cweights), g(d.pi), g(d.pw), g(d.sll), g(d.lpart));
+}
+
+// ---------------------------------------------------------------- pre-order + gradient
+
+// Body of one pre-order + gradient unit (restrict parameters: see post_unit).
+template <typename T, int R>
+__device__ __forceinline__ void pre_unit(const NodeTriple nt, const int tile, const int tiles,
+                                         const int N, const int Cpad, const int lane,
+                                         const GLOBAL uint8_t* __restrict__ codes,
+                                         GLOBAL T* __restrict__ part, const GLOBAL T* __restrict__ P,
+                                         const GLOBAL T* __restrict__ dP,
+                                         const GLOBAL double* __restrict__ cw,
+                                         const GLOBAL double* __restrict__ pi,
+                                         const GLOBAL double* __restrict__ pw,
+                                         GLOBAL double* __restrict__ gpart) {
     const int c = tile * kLanes + lane;
     const bool is_root = nt.k == 2 * N - 2;
-
     const bool tip_i = nt.i < N, tip_j = nt.j < N;
     const int code_i = tip_i ? codes[static_cast<size_t>(nt.i) * Cpad + c] : -1;
     const int code_j = tip_j ? codes[static_cast<size_t>(nt.j) * Cpad + c] : -1;
@@ -209,8 +278,8 @@ __global__ __launch_bounds__(kBlock) void pre_s4_kernel(
         T vi[4], vj[4], mi[4], mj[4], dmi[4], dmj[4], ui[4], uj[4];
         child_vec<T, R>(part, nt.i - N, tile, tiles, r, lane, code_i, vi);
         child_vec<T, R>(part, nt.j - N, tile, tiles, r, lane, code_j, vj);
-        const T* Pi = P + (static_cast<size_t>(nt.i) * R + r) * 16;
-        const T* Pj = P + (static_cast<size_t>(nt.j) * R + r) * 16;
+        const GLOBAL T* Pi = P + (static_cast<size_t>(nt.i) * R + r) * 16;
+        const GLOBAL T* Pj = P + (static_cast<size_t>(nt.j) * R + r) * 16;
         matvec4(Pi, vi, mi);
         matvec4(Pj, vj, mj);
         matvec4(dP + (static_cast<size_t>(nt.i) * R + r) * 16, vi, dmi);
@@ -271,26 +340,92 @@ __global__ __launch_bounds__(kBlock) void pre_s4_kernel(
     }
 }
 
+
+template <typename T, int R>
+__global__ __launch_bounds__(kBlock) void pre_s4_kernel(const ReqDesc* __restrict__ descs,
+                                                        const SegTable segs) {
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & (kLanes - 1);
+    const int unit = blockIdx.x * kWavesPerBlock + wave;
+    if (unit >= segs.unit_begin[segs.n]) return;
+    const int sidx = find_segment(segs, unit);
+    const Segment sg = segs.seg[sidx];
+    const ReqDesc& d = descs[sg.desc];
+    const int tiles = d.tiles;
+    const int local = unit - segs.unit_begin[sidx];
+    const int node_ix = local / tiles;
+    const int tile = local - node_ix * tiles;
+    const Int4 t4 = reinterpret_cast<const GLOBAL Int4*>(g(d.sched))[sg.sched_off + node_ix];
+    const NodeTriple nt{t4.x, t4.y, t4.z, 0};
+    pre_unit<T, R>(nt, tile, tiles, d.N, d.Cpad, lane, g(d.codes), g(part_of<T>(d)), g(ptab<T>(d)),
+                   g(dptab<T>(d)), g(d.cweights), g(d.pi), g(d.pw), g(d.gpart));
+}
+
 // ---------------------------------------------------------------- P(t), dP/dt
 
-template <bool kF32>
-__global__ __launch_bounds__(256) void pmat_kernel(int E, int R, int S, const double* __restrict__ b,
-                                                   const double* __restrict__ V,
-                                                   const double* __restrict__ Vinv,
-                                                   const double* __restrict__ lam,
-                                                   const double* __restrict__ rates,
-                                                   double* __restrict__ P64, double* __restrict__ dP64,
-                                                   float* __restrict__ P32, float* __restrict__ dP32) {
-    __shared__ double ex[64], dex[64];
-    const int pair = blockIdx.x;
+// Small S (<= 8): one thread per (branch, category) pair builds the whole
+// S x S pair of matrices.  Units are pairs; a block covers 256 of them.
+template <int S>
+__global__ __launch_bounds__(256) void pmat_small_kernel(const ReqDesc* __restrict__ descs,
+                                                         const SegTable segs) {
+    const int unit = blockIdx.x * 256 + threadIdx.x;
+    if (unit >= segs.unit_begin[segs.n]) return;
+    int sidx = 0;
+    while (sidx + 1 < segs.n && unit >= segs.unit_begin[sidx + 1]) ++sidx;
+    const ReqDesc& d = descs[segs.seg[sidx].desc];
+    const int pair = unit - segs.unit_begin[sidx];
+    const int R = d.R;
     const int x = pair / R;
     const int r = pair - x * R;
-    const double g = rates[r];
-    const double t = g * b[x];
-    for (int k = threadIdx.x; k < S; k += blockDim.x) {
-        const double e = exp(lam[k] * t);
+    const double g = d.rates[r];
+    const double t = g * d.b[x];
+    double ex[S], dex[S];
+#pragma unroll
+    for (int k = 0; k < S; ++k) {
+        const double e = exp(d.lam[k] * t);
         ex[k] = e;
-        dex[k] = g * lam[k] * e;
+        dex[k] = g * d.lam[k] * e;
+    }
+    const size_t base = static_cast<size_t>(pair) * S * S;
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+#pragma unroll
+        for (int u = 0; u < S; ++u) {
+            double acc = 0.0, dacc = 0.0;
+#pragma unroll
+            for (int k = 0; k < S; ++k) {
+                const double v = d.V[s * S + k] * d.Vinv[k * S + u];
+                acc += v * ex[k];
+                dacc += v * dex[k];
+            }
+            d.P64[base + s * S + u] = acc;
+            d.dP64[base + s * S + u] = dacc;
+            if (d.fp32) {
+                d.P32[base + s * S + u] = static_cast<float>(acc);
+                d.dP32[base + s * S + u] = static_cast<float>(dacc);
+            }
+        }
+    }
+}
+
+// Any S <= 64: one block per (branch, category) pair.
+__global__ __launch_bounds__(256) void pmat_block_kernel(const ReqDesc* __restrict__ descs,
+                                                         const SegTable segs) {
+    __shared__ double ex[64], dex[64];
+    const int unit = blockIdx.x;
+    if (unit >= segs.unit_begin[segs.n]) return;
+    const int sidx = find_segment(segs, unit);
+    const ReqDesc& d = descs[segs.seg[sidx].desc];
+    const int pair = unit - segs.unit_begin[sidx];
+    const int R = d.R, S = d.S;
+    const int x = pair / R;
+    const int r = pair - x * R;
+    const double g = d.rates[r];
+    const double t = g * d.b[x];
+    for (int k = threadIdx.x; k < S; k += blockDim.x) {
+        const double e = exp(d.lam[k] * t);
+        ex[k] = e;
+        dex[k] = g * d.lam[k] * e;
     }
     __syncthreads();
     const size_t base = static_cast<size_t>(pair) * S * S;
@@ -299,30 +434,34 @@ __global__ __launch_bounds__(256) void pmat_kernel(int E, int R, int S, const do
         const int u = e - s * S;
         double acc = 0.0, dacc = 0.0;
         for (int k = 0; k < S; ++k) {
-            const double v = V[s * S + k] * Vinv[k * S + u];
+            const double v = d.V[s * S + k] * d.Vinv[k * S + u];
             acc += v * ex[k];
             dacc += v * dex[k];
         }
-        P64[base + e] = acc;
-        dP64[base + e] = dacc;
-        if (kF32) {
-            P32[base + e] = static_cast<float>(acc);
-            dP32[base + e] = static_cast<float>(dacc);
+        d.P64[base + e] = acc;
+        d.dP64[base + e] = dacc;
+        if (d.fp32) {
+            d.P32[base + e] = static_cast<float>(acc);
+            d.dP32[base + e] = static_cast<float>(dacc);
         }
     }
 }
 
 // ---------------------------------------------------------------- final sums
 
-// Block x < E sums branch x's per-tile gradient partials; block E sums the
+// Unit x < E sums branch x's per-tile gradient partials; unit E sums the
 // per-tile weighted log-likelihood partials.  Fixed order: deterministic.
-__global__ __launch_bounds__(256) void finalize_kernel(const double* __restrict__ gpart, int tiles,
-                                                       int E, const double* __restrict__ lpart,
-                                                       double* __restrict__ out_logl,
-                                                       double* __restrict__ out_grad) {
+__global__ __launch_bounds__(256) void finalize_kernel(const ReqDesc* __restrict__ descs,
+                                                       const SegTable segs) {
     __shared__ double red[256];
-    const int blk = blockIdx.x;
-    const double* src = blk < E ? gpart + static_cast<size_t>(blk) * tiles : lpart;
+    const int unit = blockIdx.x;
+    if (unit >= segs.unit_begin[segs.n]) return;
+    const int sidx = find_segment(segs, unit);
+    const Segment& sg = segs.seg[sidx];
+    const ReqDesc& d = descs[sg.desc];
+    const int blk = unit - segs.unit_begin[sidx];
+    const int E = 2 * d.N - 2, tiles = d.tiles;
+    const double* src = blk < E ? d.gpart + static_cast<size_t>(blk) * tiles : d.lpart;
     double acc = 0.0;
     for (int t = threadIdx.x; t < tiles; t += 256) acc += src[t];
     red[threadIdx.x] = acc;
@@ -333,98 +472,74 @@ __global__ __launch_bounds__(256) void finalize_kernel(const double* __restrict_
     }
     if (threadIdx.x == 0) {
         if (blk < E)
-            out_grad[blk] = red[0];
+            sg.out_grad[blk] = red[0];
         else
-            *out_logl = red[0];
+            *sg.out_logl = red[0];
     }
 }
 
-template <typename T>
-const T* ptab(const DeviceProblem& d);
-template <>
-const float* ptab<float>(const DeviceProblem& d) { return d.P32; }
-template <>
-const double* ptab<double>(const DeviceProblem& d) { return d.P64; }
-template <typename T>
-const T* dptab(const DeviceProblem& d);
-template <>
-const float* dptab<float>(const DeviceProblem& d) { return d.dP32; }
-template <>
-const double* dptab<double>(const DeviceProblem& d) { return d.dP64; }
-
 template <typename T, int R>
-hipError_t post_r(const DeviceProblem& d, const NodeTriple* level, int n_nodes, bool is_root,
-                  hipStream_t st) {
-    const int n_units = n_nodes * d.tiles;
+hipError_t level_r(KernelClass k, const ReqDesc* descs, const SegTable& t, hipStream_t st) {
+    const int n_units = t.unit_begin[t.n];
     const int blocks = (n_units + kWavesPerBlock - 1) / kWavesPerBlock;
-    hipLaunchKernelGGL((post_s4_kernel<T, R>), dim3(blocks), dim3(kBlock), 0, st, level, n_units,
-                       d.tiles, d.N, d.Cpad, d.codes, static_cast<T*>(d.part), d.expo, ptab<T>(d),
-                       d.cweights, d.pi, d.pw, d.sll, d.lpart, is_root ? 1 : 0);
+    if (k == kPost)
+        hipLaunchKernelGGL((post_s4_kernel<T, R>), dim3(blocks), dim3(kBlock), 0, st, descs, t);
+    else
+        hipLaunchKernelGGL((pre_s4_kernel<T, R>), dim3(blocks), dim3(kBlock), 0, st, descs, t);
     return hipGetLastError();
 }
 
-template <typename T, int R>
-hipError_t pre_r(const DeviceProblem& d, const NodeTriple* level, int n_nodes, hipStream_t st) {
-    const int n_units = n_nodes * d.tiles;
-    const int blocks = (n_units + kWavesPerBlock - 1) / kWavesPerBlock;
-    hipLaunchKernelGGL((pre_s4_kernel<T, R>), dim3(blocks), dim3(kBlock), 0, st, level, n_units,
-                       d.tiles, d.N, d.Cpad, d.codes, static_cast<T*>(d.part), ptab<T>(d),
-                       dptab<T>(d), d.cweights, d.pi, d.pw, d.gpart);
-    return hipGetLastError();
-}
-
-#define PHG_DISPATCH_R(FN, T, ...)                  \
-    switch (d.R) {                                  \
-        case 1: return FN<T, 1>(d, __VA_ARGS__);    \
-        case 2: return FN<T, 2>(d, __VA_ARGS__);    \
-        case 3: return FN<T, 3>(d, __VA_ARGS__);    \
-        case 4: return FN<T, 4>(d, __VA_ARGS__);    \
-        case 5: return FN<T, 5>(d, __VA_ARGS__);    \
-        case 6: return FN<T, 6>(d, __VA_ARGS__);    \
-        case 7: return FN<T, 7>(d, __VA_ARGS__);    \
-        case 8: return FN<T, 8>(d, __VA_ARGS__);    \
-        default: return hipErrorInvalidValue;       \
+template <typename T>
+hipError_t level_t(KernelClass k, int R, const ReqDesc* descs, const SegTable& t, hipStream_t st) {
+    switch (R) {
+        case 1: return level_r<T, 1>(k, descs, t, st);
+        case 2: return level_r<T, 2>(k, descs, t, st);
+        case 3: return level_r<T, 3>(k, descs, t, st);
+        case 4: return level_r<T, 4>(k, descs, t, st);
+        case 5: return level_r<T, 5>(k, descs, t, st);
+        case 6: return level_r<T, 6>(k, descs, t, st);
+        case 7: return level_r<T, 7>(k, descs, t, st);
+        case 8: return level_r<T, 8>(k, descs, t, st);
+        default: return hipErrorInvalidValue;
     }
+}
 
 }  // namespace
 
 bool kernels_support(int S, int R) { return S == 4 && R >= 1 && R <= 8; }
 
-hipError_t launch_pmat(const DeviceProblem& d, bool fp32, hipStream_t st) {
-    const int E = 2 * d.N - 2;
-    if (fp32)
-        hipLaunchKernelGGL((pmat_kernel<true>), dim3(E * d.R), dim3(256), 0, st, E, d.R, d.S, d.b, d.V,
-                           d.Vinv, d.lam, d.rates, d.P64, d.dP64, d.P32, d.dP32);
-    else
-        hipLaunchKernelGGL((pmat_kernel<false>), dim3(E * d.R), dim3(256), 0, st, E, d.R, d.S, d.b,
-                           d.V, d.Vinv, d.lam, d.rates, d.P64, d.dP64, d.P32, d.dP32);
-    return hipGetLastError();
-}
-
-hipError_t launch_post_level(const DeviceProblem& d, bool fp32, const NodeTriple* level, int n_nodes,
-                             bool is_root, hipStream_t st) {
-    if (fp32) {
-        PHG_DISPATCH_R(post_r, float, level, n_nodes, is_root, st);
-    } else {
-        PHG_DISPATCH_R(post_r, double, level, n_nodes, is_root, st);
+int units_for(KernelClass k, const ReqDesc& d, int n_nodes) {
+    switch (k) {
+        case kPmat: return (2 * d.N - 2) * d.R;
+        case kPost:
+        case kPre: return n_nodes * d.tiles;
+        case kFinal: return 2 * d.N - 1;
     }
+    return 0;
 }
 
-hipError_t launch_pre_level(const DeviceProblem& d, bool fp32, const NodeTriple* level, int n_nodes,
-                            hipStream_t st) {
-    if (fp32) {
-        PHG_DISPATCH_R(pre_r, float, level, n_nodes, st);
-    } else {
-        PHG_DISPATCH_R(pre_r, double, level, n_nodes, st);
+hipError_t launch_class(KernelClass k, const ReqDesc& shape, const ReqDesc* descs, const SegTable& t,
+                        hipStream_t st) {
+    const int n_units = t.unit_begin[t.n];
+    if (t.n <= 0 || n_units <= 0) return hipSuccess;
+    switch (k) {
+        case kPmat:
+            if (shape.S == 4) {
+                hipLaunchKernelGGL((pmat_small_kernel<4>), dim3((n_units + 255) / 256), dim3(256), 0, st,
+                                   descs, t);
+            } else {
+                hipLaunchKernelGGL(pmat_block_kernel, dim3(n_units), dim3(256), 0, st, descs, t);
+            }
+            return hipGetLastError();
+        case kPost:
+        case kPre:
+            if (shape.fp32) return level_t<float>(k, shape.R, descs, t, st);
+            return level_t<double>(k, shape.R, descs, t, st);
+        case kFinal:
+            hipLaunchKernelGGL(finalize_kernel, dim3(n_units), dim3(256), 0, st, descs, t);
+            return hipGetLastError();
     }
-}
-
-hipError_t launch_finalize(const DeviceProblem& d, double* out_logl, double* out_grad,
-                           hipStream_t st) {
-    const int E = 2 * d.N - 2;
-    hipLaunchKernelGGL(finalize_kernel, dim3(E + 1), dim3(256), 0, st, d.gpart, d.tiles, E, d.lpart,
-                       out_logl, out_grad);
-    return hipGetLastError();
+    return hipErrorInvalidValue;
 }
 
 }  // namespace phg
