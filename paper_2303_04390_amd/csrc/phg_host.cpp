@@ -32,8 +32,8 @@ size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 Plan make_plan(int N, int C, int S, int R, phg_precision prec) {
     const int Cpad = (C + kLanes - 1) / kLanes * kLanes;
-    const int tiles = Cpad / kLanes;
-    const int S4 = (S + 3) / 4;
+    const int tp = tile_patterns(S, R, prec == PHG_FP32_SCALED);
+    const int tiles = Cpad / tp;
     const size_t E = 2 * static_cast<size_t>(N) - 2;
     const size_t I = static_cast<size_t>(N) - 1;
     const size_t tsz = prec == PHG_FP32_SCALED ? 4 : 8;
@@ -45,7 +45,7 @@ Plan make_plan(int N, int C, int S, int R, phg_precision prec) {
         return o;
     };
     p.codes = take(static_cast<size_t>(N) * Cpad);
-    p.part = take(I * tiles * R * S4 * kLanes * 4 * tsz);
+    p.part = take(I * tiles * R * S * tp * tsz);
     p.expo = take(I * Cpad * sizeof(int32_t));
     p.P64 = take(E * R * S * S * 8);
     p.dP64 = take(E * R * S * S * 8);
@@ -366,7 +366,7 @@ phg_status phg_create(int n_tips, int n_patterns, int n_states, int n_categories
     ctx->prec = prec;
     ctx->device = device;
     ctx->Cpad = (n_patterns + phg::kLanes - 1) / phg::kLanes * phg::kLanes;
-    ctx->tiles = ctx->Cpad / phg::kLanes;
+    ctx->tiles = ctx->Cpad / phg::tile_patterns(n_states, n_categories, prec == PHG_FP32_SCALED);
     ctx->S4 = (n_states + 3) / 4;
     ctx->pw.assign(ctx->Cpad, 0.0);
     std::fill(ctx->pw.begin(), ctx->pw.begin() + n_patterns, 1.0);

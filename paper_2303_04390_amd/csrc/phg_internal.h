@@ -20,7 +20,9 @@ struct NodeTriple {
 // Device-resident description of one evaluation request (one tree and
 // alignment with its own workspace).  Layouts (T = float or double):
 //   codes  uint8  [N][Cpad]                  tip states, S = all-ones, pad = S
-//   part   T      [N-1][tiles][R][S4][64][4]  post-order partial of each
+//   part   T      4 states: [N-1][tiles][R][64][4] (lane-major quads)
+//                 otherwise: [N-1][tiles][R][S][TP] (state rows of TP patterns)
+//                                             post-order partial of each
 //                                             internal node (slot = id - N);
 //                                             overwritten in place by the
 //                                             pre-order partial
@@ -83,5 +85,16 @@ int units_for(KernelClass k, const ReqDesc& d, int n_nodes);
 hipError_t launch_class(KernelClass k, const ReqDesc& shape, const ReqDesc* descs,
                         const SegTable& t, hipStream_t stream);
 bool kernels_support(int S, int R);
+
+// Patterns per work-unit tile: 64 for the 4-state kernels (R <= 8); for the
+// MFMA kernels of other state counts 32 (float) or 16 (double).
+int tile_patterns(int S, int R, bool fp32);
+// Whether (S, R) runs on the dedicated 4-state kernels.
+inline bool uses_s4_kernels(int S, int R) { return S == 4 && R <= 8; }
+
+// MFMA level kernels for other state counts (phg_kernels_gs.hip).
+int gs_tile_patterns(bool fp32);
+hipError_t launch_level_gs(KernelClass k, const ReqDesc& shape, const ReqDesc* descs,
+                           const SegTable& t, hipStream_t stream);
 
 }  // namespace phg

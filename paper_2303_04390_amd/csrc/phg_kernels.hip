@@ -506,7 +506,11 @@ hipError_t level_t(KernelClass k, int R, const ReqDesc* descs, const SegTable& t
 
 }  // namespace
 
-bool kernels_support(int S, int R) { return S == 4 && R >= 1 && R <= 8; }
+bool kernels_support(int S, int R) { return S >= 2 && S <= 64 && R >= 1 && R <= 16; }
+
+int tile_patterns(int S, int R, bool fp32) {
+    return uses_s4_kernels(S, R) ? kLanes : gs_tile_patterns(fp32);
+}
 
 int units_for(KernelClass k, const ReqDesc& d, int n_nodes) {
     switch (k) {
@@ -533,6 +537,7 @@ hipError_t launch_class(KernelClass k, const ReqDesc& shape, const ReqDesc* desc
             return hipGetLastError();
         case kPost:
         case kPre:
+            if (!uses_s4_kernels(shape.S, shape.R)) return launch_level_gs(k, shape, descs, t, st);
             if (shape.fp32) return level_t<float>(k, shape.R, descs, t, st);
             return level_t<double>(k, shape.R, descs, t, st);
         case kFinal:
