@@ -171,6 +171,79 @@ phg_status phg_profile_enable(phg_context *ctx, int on);
  * be NULL).  Clears the record. */
 phg_status phg_profile_read(phg_context *ctx, double *ms, int *n_evals, int *launches);
 
+/* ---- serving: many trees, continuous batching ----
+ *
+ * A server owns one device, a device-memory budget and a scheduler thread.
+ * Trees (topology, model, alignment) are registered once; each request
+ * brings new branch lengths for a registered tree (as an HMC sampler or
+ * several chains do) and asks for log P(Y) and all 2N-2 derivatives.
+ * Requests are admitted when a slot is free and the tree's workspace fits
+ * the budget (idle resident trees are evicted least-recently-used first);
+ * every scheduler step advances each in-flight request by one stage of the
+ * path (P(t), one post-order level, one pre-order level, or the final sums),
+ * and requests at the same stage kind share kernel launches, so requests that
+ * arrive while others run join at the next step.  Results do not depend on
+ * what else is in flight (every work unit's arithmetic is independent of the
+ * batch).  One evaluation per tree is in flight at a time; later requests for
+ * the same tree wait for it.  All server calls are thread-safe. */
+typedef struct phg_server phg_server;
+
+/* Everything that defines one tree's problem (host pointers, copied by
+ * phg_server_register_tree).  Layouts as for the phg_set_* calls above;
+ * pattern_weights may be NULL (all ones). */
+typedef struct {
+    int n_tips, n_patterns, n_states, n_categories;
+    phg_precision prec;
+    const int32_t *parent;
+    const double *V, *Vinv, *lambda;
+    const double *pi;
+    const double *rates, *weights;
+    const int32_t *codes;
+    const double *pattern_weights;
+} phg_tree_desc;
+
+/* max_slots in [1, 48] concurrent evaluations; mem_budget_bytes of device
+ * memory is reserved at creation for resident trees' workspaces. */
+phg_status phg_server_create(int device, size_t mem_budget_bytes, int max_slots,
+                             phg_server **out);
+phg_status phg_server_destroy(phg_server *srv);
+const char *phg_server_last_error(const phg_server *srv);
+
+/* Validate and copy a tree (no device work).  PHG_ERR_OOM if its workspace
+ * alone exceeds the budget. */
+phg_status phg_server_register_tree(phg_server *srv, const phg_tree_desc *desc,
+                                    uint64_t *tree_id);
+
+/* Queue one evaluation of tree_id at branch lengths b (2N-2 doubles, copied;
+ * finite and >= 0).  Never fails for lack of memory: the request waits. */
+phg_status phg_server_submit(phg_server *srv, uint64_t tree_id, const double *b,
+                             uint64_t *req_id);
+
+/* Non-blocking: *done = 1 and results written (logl may be NULL; grad has
+ * 2N-2 doubles) once the request finished, after which req_id is forgotten.
+ * A finished request whose site likelihood was zero returns PHG_ERR_NUMERIC
+ * with logl = -inf and NaN gradients. */
+phg_status phg_server_poll(phg_server *srv, uint64_t req_id, double *logl, double *grad,
+                           int *done);
+
+/* phg_server_poll that also reports, on the server's monotonic clock in
+ * nanoseconds, when the request was submitted and when its results were
+ * observed in host memory (either pointer may be NULL). */
+phg_status phg_server_poll_timed(phg_server *srv, uint64_t req_id, double *logl, double *grad,
+                                 int *done, uint64_t *t_submit_ns, uint64_t *t_done_ns);
+
+/* Blocking variant of phg_server_poll. */
+phg_status phg_server_wait(phg_server *srv, uint64_t req_id, double *logl, double *grad);
+
+/* Forget a tree: its device memory is released once no request for it is
+ * queued or in flight.  Requests submitted afterwards fail with PHG_ERR_ARG. */
+phg_status phg_server_release_tree(phg_server *srv, uint64_t tree_id);
+
+/* Counters since creation: stats[0] requests completed, [1] scheduler steps,
+ * [2] kernel launches, [3] resident trees now, [4] evictions, [5] peak bytes of
+ * the budget in use, [6] requests now queued, [7] requests now in flight. */
+phg_status phg_server_stats(phg_server *srv, uint64_t stats[8]);
+
 #ifdef __cplusplus
 }
 #endif

@@ -64,6 +64,17 @@ _SIGS = {
     "phg_bind_stream": [_vp, _vp],
     "phg_gradient_async": [_vp, _vp, _vp],
     "phg_schedule_info": [_vp, _c.POINTER(_c.c_int), _c.POINTER(_c.c_int), _c.POINTER(_c.c_int)],
+    "phg_server_create": [_c.c_int, _c.c_size_t, _c.c_int, _c.POINTER(_vp)],
+    "phg_server_destroy": [_vp],
+    "phg_server_last_error": [_vp],
+    "phg_server_register_tree": [_vp, _vp, _c.POINTER(_c.c_uint64)],
+    "phg_server_submit": [_vp, _c.c_uint64, _dp, _c.POINTER(_c.c_uint64)],
+    "phg_server_poll": [_vp, _c.c_uint64, _dp, _dp, _c.POINTER(_c.c_int)],
+    "phg_server_poll_timed": [_vp, _c.c_uint64, _dp, _dp, _c.POINTER(_c.c_int),
+                              _c.POINTER(_c.c_uint64), _c.POINTER(_c.c_uint64)],
+    "phg_server_wait": [_vp, _c.c_uint64, _dp, _dp],
+    "phg_server_release_tree": [_vp, _c.c_uint64],
+    "phg_server_stats": [_vp, _c.POINTER(_c.c_uint64)],
     "phg_profile_enable": [_vp, _c.c_int],
     "phg_profile_read": [_vp, _dp, _c.POINTER(_c.c_int), _c.POINTER(_c.c_int)],
 }
@@ -73,9 +84,20 @@ PROF_NAMES = ("pmat", "post", "pre_grad", "finalize")
 
 
 def lib():
-    """Load libphg.so (built in-tree by paper_2303_04390_amd.build)."""
+    """Load libphg.so (built in-tree by paper_2303_04390_amd.build).
+
+    PyTorch wheels for ROCm bundle their own HIP and HSA runtimes under the
+    same sonames as the system ones libphg.so links against.  torch is
+    imported first so that libphg.so binds to the runtime already in the
+    process: one HIP runtime, so torch streams and memory are valid handles
+    for the library.  (Loading libphg.so first would map a second runtime.)
+    """
     global _lib
     if _lib is None:
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with "
                                "`python -m paper_2303_04390_amd.build` (no fallback exists)")
@@ -83,7 +105,7 @@ def lib():
         for name, args in _SIGS.items():
             fn = getattr(L, name)
             fn.argtypes = args
-            fn.restype = ctypes.c_char_p if name == "phg_last_error" else ctypes.c_int
+            fn.restype = ctypes.c_char_p if name.endswith("last_error") else ctypes.c_int
         _lib = L
     return _lib
 
@@ -222,6 +244,97 @@ def phg_profile_read(ctx):
     _check(lib().phg_profile_read(ctx, _p(ms), ctypes.byref(n), _p(launches)), ctx,
            "phg_profile_read")
     return ms, n.value, launches
+
+
+# ------------------------------------------------------------ serving
+
+class phg_tree_desc(ctypes.Structure):
+    _fields_ = [("n_tips", _c.c_int), ("n_patterns", _c.c_int), ("n_states", _c.c_int),
+                ("n_categories", _c.c_int), ("prec", _c.c_int),
+                ("parent", _ip), ("V", _dp), ("Vinv", _dp), ("lambda_", _dp), ("pi", _dp),
+                ("rates", _dp), ("weights", _dp), ("codes", _ip), ("pattern_weights", _dp)]
+
+
+def _scheck(status: int, srv, where: str):
+    if status != PHG_OK:
+        msg = lib().phg_server_last_error(srv)
+        raise PhgError(status, (msg or b"").decode(), where)
+
+
+def phg_server_create(device: int, mem_budget_bytes: int, max_slots: int):
+    out = _vp()
+    _scheck(lib().phg_server_create(device, mem_budget_bytes, max_slots, ctypes.byref(out)), None,
+            "phg_server_create")
+    return out
+
+
+def phg_server_destroy(srv):
+    lib().phg_server_destroy(srv)
+
+
+def phg_server_register_tree(srv, prob, prec) -> int:
+    """Register a Problem-like object; returns the tree id."""
+    keep = dict(parent=_i32(prob.parent), V=_f64(prob.V), Vinv=_f64(prob.Vinv), lam=_f64(prob.lam),
+                pi=_f64(prob.pi), rates=_f64(prob.rates), weights=_f64(prob.weights),
+                codes=_i32(prob.codes), pw=_f64(prob.pattern_weights))
+    d = phg_tree_desc(prob.n_tips, prob.n_patterns, prob.n_states, prob.n_categories, prec,
+                      _p(keep["parent"]), _p(keep["V"]), _p(keep["Vinv"]), _p(keep["lam"]),
+                      _p(keep["pi"]), _p(keep["rates"]), _p(keep["weights"]), _p(keep["codes"]),
+                      _p(keep["pw"]))
+    tid = ctypes.c_uint64()
+    _scheck(lib().phg_server_register_tree(srv, ctypes.byref(d), ctypes.byref(tid)), srv,
+            "phg_server_register_tree")
+    return tid.value
+
+
+def phg_server_submit(srv, tree_id: int, b) -> int:
+    a = _f64(b)
+    rid = ctypes.c_uint64()
+    _scheck(lib().phg_server_submit(srv, tree_id, _p(a), ctypes.byref(rid)), srv, "phg_server_submit")
+    return rid.value
+
+
+def phg_server_poll(srv, req_id: int, n_branches: int):
+    """Returns (done, logl, grad); raises PhgError for a finished failed request."""
+    g = np.empty(n_branches, np.float64)
+    v = ctypes.c_double()
+    done = ctypes.c_int()
+    _scheck(lib().phg_server_poll(srv, req_id, ctypes.byref(v), _p(g), ctypes.byref(done)), srv,
+            "phg_server_poll")
+    return bool(done.value), v.value, g
+
+
+def phg_server_poll_timed(srv, req_id: int, n_branches: int):
+    """Returns (done, logl, grad, t_submit_ns, t_done_ns) or raises PhgError."""
+    g = np.empty(n_branches, np.float64)
+    v = ctypes.c_double()
+    done = ctypes.c_int()
+    ts, td = ctypes.c_uint64(), ctypes.c_uint64()
+    _scheck(lib().phg_server_poll_timed(srv, req_id, ctypes.byref(v), _p(g), ctypes.byref(done),
+                                        ctypes.byref(ts), ctypes.byref(td)), srv, "phg_server_poll_timed")
+    return bool(done.value), v.value, g, ts.value, td.value
+
+
+def phg_server_wait(srv, req_id: int, n_branches: int):
+    """Blocks until done; returns (logl, grad) or raises PhgError."""
+    g = np.empty(n_branches, np.float64)
+    v = ctypes.c_double()
+    _scheck(lib().phg_server_wait(srv, req_id, ctypes.byref(v), _p(g)), srv, "phg_server_wait")
+    return v.value, g
+
+
+def phg_server_release_tree(srv, tree_id: int):
+    _scheck(lib().phg_server_release_tree(srv, tree_id), srv, "phg_server_release_tree")
+
+
+SERVER_STATS = ("completed", "steps", "launches", "resident_trees", "evictions", "peak_bytes",
+                "queued", "in_flight")
+
+
+def phg_server_stats(srv) -> dict:
+    a = (ctypes.c_uint64 * 8)()
+    _scheck(lib().phg_server_stats(srv, a), srv, "phg_server_stats")
+    return dict(zip(SERVER_STATS, list(a)))
 
 
 # ------------------------------------------------------------ convenience

@@ -14,12 +14,12 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libphg.so")
 
-SOURCES = ["phg_host.cpp", "phg_kernels.hip", "phg_kernels_gs.hip"]
+SOURCES = ["phg_host.cpp", "phg_server.cpp", "phg_kernels.hip", "phg_kernels_gs.hip"]
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     # no packed-FP32 instructions in device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-    "-Wall", "-Wno-unused-function", "-Wno-unused-command-line-argument",
+    "-Wall", "-Wno-unused-function", "-Wno-unused-command-line-argument", "-pthread",
 ]
 
 

@@ -105,5 +105,9 @@ ReqDesc* ctx_desc_dev(phg_context* ctx);
 double* ctx_out_dev(phg_context* ctx);
 // Enqueue one whole evaluation of this context alone.
 phg_status ctx_enqueue_eval(phg_context* ctx, double* d_logl, double* d_grad);
+// Forget the device binding (workspace, pinned output) so the context can be
+// bound to new memory later; every input is uploaded again on next use.  The
+// caller guarantees no device work of this context is pending.
+void ctx_drop_device(phg_context* ctx);
 
 }  // namespace phg

@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <limits>
@@ -148,23 +149,31 @@ void build_schedule(phg_context* ctx) {
     }
 }
 
+// Devices already checked to be gfx950 (bit per ordinal < 64).
+std::atomic<uint64_t> g_verified{0};
+
 phg_status ensure_device(phg_context* ctx) {
     if (ctx->dev_init) {
         PHG_HIP(ctx, hipSetDevice(ctx->device));
         return PHG_OK;
     }
-    int count = 0;
-    hipError_t e = hipGetDeviceCount(&count);
-    if (e != hipSuccess || count == 0)
-        return ctx->fail(PHG_ERR_DEVICE, "no HIP device available (%s)", hipGetErrorString(e));
-    if (ctx->device >= count)
-        return ctx->fail(PHG_ERR_DEVICE, "device %d out of range (%d devices)", ctx->device, count);
+    const uint64_t bit = ctx->device < 64 ? (uint64_t{1} << ctx->device) : 0;
+    if (!(bit && (g_verified.load() & bit))) {
+        int count = 0;
+        hipError_t e = hipGetDeviceCount(&count);
+        if (e != hipSuccess || count == 0)
+            return ctx->fail(PHG_ERR_DEVICE, "no HIP device available (%s)", hipGetErrorString(e));
+        if (ctx->device >= count)
+            return ctx->fail(PHG_ERR_DEVICE, "device %d out of range (%d devices)", ctx->device, count);
+        PHG_HIP(ctx, hipSetDevice(ctx->device));
+        hipDeviceProp_t prop;
+        PHG_HIP(ctx, hipGetDeviceProperties(&prop, ctx->device));
+        if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+            return ctx->fail(PHG_ERR_DEVICE, "device %d is %s; this library is built for gfx950 only",
+                             ctx->device, prop.gcnArchName);
+        g_verified.fetch_or(bit);
+    }
     PHG_HIP(ctx, hipSetDevice(ctx->device));
-    hipDeviceProp_t prop;
-    PHG_HIP(ctx, hipGetDeviceProperties(&prop, ctx->device));
-    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
-        return ctx->fail(PHG_ERR_DEVICE, "device %d is %s; this library is built for gfx950 only",
-                         ctx->device, prop.gcnArchName);
     if (!kernels_support(ctx->S, ctx->R))
         return ctx->fail(PHG_ERR_ARG, "no kernel for S=%d, R=%d in this build", ctx->S, ctx->R);
 
@@ -177,7 +186,7 @@ phg_status ensure_device(phg_context* ctx) {
         ctx->own_arena = false;
     } else {
         void* p = nullptr;
-        e = hipMalloc(&p, ctx->plan.total);
+        const hipError_t e = hipMalloc(&p, ctx->plan.total);
         if (e != hipSuccess)
             return ctx->fail(PHG_ERR_OOM, "hipMalloc(%zu) failed: %s", ctx->plan.total,
                              hipGetErrorString(e));
@@ -188,11 +197,6 @@ phg_status ensure_device(phg_context* ctx) {
         PHG_HIP(ctx, hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking));
         ctx->own_stream = true;
     }
-    void* ho = nullptr;
-    PHG_HIP(ctx, hipHostMalloc(&ho, (2 * static_cast<size_t>(ctx->N) - 1) * sizeof(double),
-                               hipHostMallocDefault));
-    ctx->host_out = static_cast<double*>(ho);
-
     const Plan& pl = ctx->plan;
     char* a = ctx->arena;
     ReqDesc& d = ctx->rd;
@@ -312,6 +316,19 @@ phg_status ctx_enqueue_eval(phg_context* ctx, double* d_logl, double* d_grad) {
                               one_segment(units_for(kFinal, d, 0), 0, 0, 0, d_logl, d_grad), st));
     PHG_TRY(prof_mark(ctx));
     return PHG_OK;
+}
+
+void ctx_drop_device(phg_context* ctx) {
+    if (!ctx->dev_init) return;
+    if (ctx->own_arena && ctx->arena) (void)hipFree(ctx->arena);
+    if (ctx->host_out) (void)hipHostFree(ctx->host_out);
+    ctx->host_out = nullptr;
+    ctx->arena = nullptr;
+    ctx->own_arena = false;
+    ctx->bound_ws = nullptr;
+    ctx->bound_ws_bytes = 0;
+    ctx->dev_init = false;
+    ctx->dirty = ctx->have;
 }
 
 ReqDesc* ctx_desc_dev(phg_context* ctx) { return reinterpret_cast<ReqDesc*>(ctx->arena + ctx->plan.desc); }
@@ -524,6 +541,12 @@ phg_status phg_gradient(phg_context* ctx, double* logl, double* grad) {
     if (!grad) return ctx->fail(PHG_ERR_ARG, "grad is NULL");
     phg_status s = ctx_ready(ctx);
     if (s != PHG_OK) return s;
+    if (!ctx->host_out) {
+        void* ho = nullptr;
+        PHG_HIP(ctx, hipHostMalloc(&ho, (2 * static_cast<size_t>(ctx->N) - 1) * sizeof(double),
+                                   hipHostMallocDefault));
+        ctx->host_out = static_cast<double*>(ho);
+    }
     double* dout = ctx_out_dev(ctx);
     s = ctx_enqueue_eval(ctx, dout, dout + 1);
     if (s != PHG_OK) return s;

@@ -154,3 +154,17 @@ def test_compute_without_gpu_is_device_error():
         assert e.value.status == B.PHG_ERR_DEVICE
     finally:
         ctx.close()
+
+
+def test_one_hip_runtime_in_process():
+    """libphg.so must share torch's HIP runtime (a second copy would make
+    torch streams and memory foreign handles to the library)."""
+    import subprocess
+    import sys
+    code = ("from paper_2303_04390_amd import binding as B; B.lib(); import torch; "
+            "torch.cuda.device_count(); maps = open('/proc/self/maps').read().splitlines(); "
+            "print(len({l.split()[-1] for l in maps if 'libamdhip64' in l}))")
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True,
+                         cwd=os.path.dirname(os.path.dirname(__file__)), timeout=300)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.strip().splitlines()[-1] == "1"
