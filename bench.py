@@ -81,6 +81,165 @@ def algorithmic_bytes(parent, n_tips, C, R, S, tsz):
     return post * C, pre * C
 
 
+def serving_measurement(args, B, synth):
+    """Poisson stream of likelihood+gradient requests through the server.
+
+    Trees: Yule, taxa ~ round(LogUniform[64, 4096]), patterns ~ round(LogUniform[
+    500, 20000]), HKY+Gamma4 drawn as in the 1000-taxon workload, FP32 with
+    rescaling.  A pool of distinct synthetic trees stands in for the stream's
+    new trees: a "new tree" request registers a pool tree under a fresh id (so
+    it is uploaded and made resident like an unseen tree); a "step" request
+    (probability 1/2) perturbs a registered tree's branch lengths by
+    exp(N(0, 0.05)), as an HMC step does.  The 32 most recently registered trees
+    stay registered.  Latency = results in host memory minus submission, on the
+    server's clock; submission happens at the scheduled arrival time.
+    """
+    import math
+    import threading
+    rng = np.random.default_rng(args.seed + 1000)
+    pool = []
+    t0 = time.perf_counter()
+    for k in range(args.serving_pool):
+        N = int(round(math.exp(rng.uniform(math.log(64), math.log(4096)))))
+        C = int(round(math.exp(rng.uniform(math.log(500), math.log(20000)))))
+        pool.append(synth.config_problem("hky1000", seed=int(rng.integers(1 << 30)), n_tips=N, n_patterns=C))
+    gen_s = time.perf_counter() - t0
+    n_req = int(args.serving_rate * args.serving_seconds)
+    arrivals = np.cumsum(rng.exponential(1.0 / args.serving_rate, n_req))
+    kinds = rng.random(n_req) < 0.5          # True: perturb a registered tree
+    picks = rng.integers(0, 1 << 30, n_req)
+    noise_seed = int(rng.integers(1 << 30))
+    budget = 96 << 30
+    srv = B.phg_server_create(0, budget, 32)
+    window = []                              # (tree id, pool index), most recent last
+    submitted = []                           # (req id, n_branches)
+    lag = []
+    from concurrent.futures import ThreadPoolExecutor
+    regs = ThreadPoolExecutor(max_workers=4)
+    new_idx = [i for i in range(n_req) if not kinds[i]]
+    futs = {}
+    ahead = 48
+
+    def prefetch(upto):
+        # tree data is prepared (registered) before its request arrives
+        while prefetch.next < len(new_idx) and prefetch.next < upto:
+            i = new_idx[prefetch.next]
+            pk = int(picks[i] % len(pool))
+            futs[i] = regs.submit(B.phg_server_register_tree, srv, pool[pk], B.PHG_FP32_SCALED)
+            prefetch.next += 1
+    prefetch.next = 0
+    try:
+        nrng = np.random.default_rng(noise_seed)
+        prefetch(ahead)
+        for f in list(futs.values())[:8]:
+            f.result()
+        start = time.perf_counter()
+        n_new = 0
+        for i in range(n_req):
+            while True:
+                dt = arrivals[i] - (time.perf_counter() - start)
+                if dt <= 0:
+                    break
+                time.sleep(min(dt, 0.0005))
+            if kinds[i] and window:
+                tid, pk = window[int(picks[i] % len(window))]
+                b = pool[pk].b * np.exp(nrng.normal(0.0, 0.05, pool[pk].b.shape))
+            else:
+                if i not in futs:                    # a "step" before any tree exists
+                    pk = int(picks[i] % len(pool))
+                    tid = B.phg_server_register_tree(srv, pool[pk], B.PHG_FP32_SCALED)
+                else:
+                    pk = int(picks[i] % len(pool))
+                    tid = futs.pop(i).result()
+                    n_new += 1
+                    prefetch(n_new + ahead)
+                window.append((tid, pk))
+                if len(window) > 32:
+                    B.phg_server_release_tree(srv, window.pop(0)[0])
+                b = pool[pk].b
+            rid = B.phg_server_submit(srv, tid, b)
+            lag.append(time.perf_counter() - start - arrivals[i])
+            submitted.append((rid, 2 * pool[pk].n_tips - 2))
+        lat = []
+        t_first, t_last = None, None
+        for rid, E in submitted:
+            while True:
+                done, logl, grad, ts, td = B.phg_server_poll_timed(srv, rid, E)
+                if done:
+                    break
+                time.sleep(0.0002)
+            lat.append((td - ts) * 1e-6)
+            t_first = ts if t_first is None else min(t_first, ts)
+            t_last = td if t_last is None else max(t_last, td)
+        stats = B.phg_server_stats(srv)
+    finally:
+        regs.shutdown(wait=True)
+        B.phg_server_destroy(srv)
+    lat = np.array(lat)
+    span = (t_last - t_first) * 1e-9
+    return {
+        "workload": "Poisson arrivals; Yule trees, taxa LogUniform[64,4096], patterns LogUniform[500,20000], "
+                    "HKY+Gamma4, FP32 + rescaling; half new trees, half branch-length perturbations "
+                    "x exp(N(0,0.05)) of registered trees",
+        "rate_req_per_s": args.serving_rate, "requests": n_req, "pool_trees": len(pool),
+        "pool_mean_taxa_x_patterns": float(np.mean([p.n_tips * p.n_patterns for p in pool])),
+        "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3),
+                       "p99": round(float(np.percentile(lat, 99)), 3),
+                       "max": round(float(lat.max()), 3)},
+        "throughput_req_per_s": round(n_req / span, 1),
+        "submit_lag_ms_p99": round(float(np.percentile(lag, 99)) * 1e3, 3),
+        "server_stats": stats, "slots": 32, "budget_bytes": budget,
+        "pool_generation_s": round(gen_s, 1),
+    }
+
+
+def batched_vs_fp64(args, B, prob, fp64_evals_per_s):
+    """k chains of the 1000-taxon workload evaluated concurrently through the
+    server in FP32 (each chain resubmits as soon as its result returns, with
+    perturbed branch lengths), against the plain FP64 single-context rate."""
+    import threading
+    E = 2 * prob.n_tips - 2
+    srv = B.phg_server_create(0, 48 << 30, max(args.batched_chains, 1))
+    counts = [0] * args.batched_chains
+    stop = threading.Event()
+    errors = []
+    try:
+        tids = [B.phg_server_register_tree(srv, prob, B.PHG_FP32_SCALED) for _ in range(args.batched_chains)]
+        # warm: make every tree resident
+        for t in tids:
+            B.phg_server_wait(srv, B.phg_server_submit(srv, t, prob.b), E)
+
+        def chain(k):
+            rng = np.random.default_rng(k)
+            try:
+                while not stop.is_set():
+                    b = prob.b * np.exp(rng.normal(0.0, 0.05, E))
+                    B.phg_server_wait(srv, B.phg_server_submit(srv, tids[k], b), E)
+                    counts[k] += 1
+            except Exception as ex:  # noqa: BLE001
+                errors.append(repr(ex))
+
+        th = [threading.Thread(target=chain, args=(k,)) for k in range(args.batched_chains)]
+        t0 = time.perf_counter()
+        for t in th:
+            t.start()
+        time.sleep(args.batched_seconds)
+        stop.set()
+        for t in th:
+            t.join(timeout=60)
+        dt = time.perf_counter() - t0
+        stats = B.phg_server_stats(srv)
+    finally:
+        B.phg_server_destroy(srv)
+    if errors:
+        raise RuntimeError(errors[0])
+    rate = sum(counts) / dt
+    return {"chains": args.batched_chains, "fp32_batched_evals_per_s": round(rate, 1),
+            "fp64_single_evals_per_s": round(fp64_evals_per_s, 1),
+            "speedup": round(rate / fp64_evals_per_s, 2), "server_launches": stats["launches"],
+            "server_steps": stats["steps"]}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -93,6 +252,14 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--quick", action="store_true",
                     help="throughput and kernel-class times only (for profiler runs)")
+    ap.add_argument("--serving-seconds", type=float, default=8.0,
+                    help="length of the Poisson request stream for the serving measurement")
+    ap.add_argument("--serving-rate", type=float, default=500.0, help="mean arrivals per second")
+    ap.add_argument("--serving-pool", type=int, default=12,
+                    help="distinct synthetic trees the stream draws from")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--batched-chains", type=int, default=8)
+    ap.add_argument("--batched-seconds", type=float, default=3.0)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first run a plain device copy of MIB MiB (read + write) three times, "
                          "a known-size reference for HBM byte counters")
@@ -216,6 +383,15 @@ def main():
     B.phg_destroy(h64)
     fp64_ms = (t1 - t0) * 1e3 / args.fp64_steps
 
+    serving = None
+    batched = None
+    if not args.no_serving:
+        print("[bench] batched FP32 chains vs plain FP64", file=sys.stderr, flush=True)
+        batched = batched_vs_fp64(args, B, prob, 1e3 / fp64_ms)
+        print(f"[bench] serving stream {args.serving_rate}/s for {args.serving_seconds}s", file=sys.stderr,
+              flush=True)
+        serving = serving_measurement(args, B, synth)
+
     rec = {
         "metric": METRIC, "value": round(value, 2), "unit": "evals/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
@@ -226,13 +402,19 @@ def main():
                                "FP32 partials with power-of-two rescaling, FP64 P(t) and reductions",
                    "n_tips": N, "n_patterns": C, "n_states": S, "n_categories": R, "seed": args.seed},
         "branch_derivatives_per_s": round(value * E, 1),
-        "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 4),
-                       "p99": round(float(np.percentile(lat, 99)), 4),
-                       "requests": int(lat.size),
-                       "what": "synchronous request: new branch lengths in, logL + 1998 derivatives in host memory"},
+        "latency_ms": ({"p50": serving["latency_ms"]["p50"], "p99": serving["latency_ms"]["p99"],
+                        "what": "serving stream (see serving): arrival to logL + gradient in host memory"}
+                       if serving else None),
+        "sync_latency_ms": {"p50": round(float(np.percentile(lat, 50)), 4),
+                            "p99": round(float(np.percentile(lat, 99)), 4),
+                            "requests": int(lat.size),
+                            "what": "one synchronous request on the 1000-taxon workload: new branch lengths "
+                                    "in, logL + 1998 derivatives in host memory"},
         "roofline": roofline,
         "path": path,
         "fp64_path": {"ms_per_step": round(fp64_ms, 4), "evals_per_s": round(1e3 / fp64_ms, 2)},
+        "batched_fp32_vs_fp64": batched,
+        "serving": serving,
     }
 
     # ------------------------------------------------ oracle sample: accuracy + CPU baseline

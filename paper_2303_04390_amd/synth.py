@@ -351,19 +351,17 @@ def simulate_codes(parent, b, Q, pi, rates, weights, n_sites,
     states = np.empty((n_nodes, n_sites), np.int32)
     root = n_nodes - 1
     states[root] = rng.choice(S, size=n_sites, p=pi)
-    cum_pi = None
-    del cum_pi
+    # all transition matrices at once (scipy's expm accepts stacked matrices)
+    t = (np.asarray(b, float)[:, None] * np.asarray(rates, float)[None, :]).reshape(-1)
+    P = scipy.linalg.expm(t[:, None, None] * Q[None, :, :]).reshape(n_nodes - 1, R, S, S)
+    P = np.clip(P, 0.0, None)
+    P /= P.sum(axis=-1, keepdims=True)
+    cum = np.cumsum(P, axis=-1)
     for v in _children_order(parent):
         if v == root:
             continue
-        cum = np.empty((R, S, S))
-        for r in range(R):
-            P = scipy.linalg.expm(rates[r] * b[v] * Q)
-            P = np.clip(P, 0.0, None)
-            P /= P.sum(axis=1, keepdims=True)
-            cum[r] = np.cumsum(P, axis=1)
         u = rng.random(n_sites)
-        rows = cum[cat, states[parent[v]]]          # [C, S]
+        rows = cum[v][cat, states[parent[v]]]          # [C, S]
         states[v] = np.minimum((u[:, None] >= rows).sum(axis=1), S - 1)
     return np.ascontiguousarray(states[:n_tips])
 
