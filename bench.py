@@ -250,6 +250,8 @@ def main():
     ap.add_argument("--cpu-sample-patterns", type=int, default=3000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--schedule", choices=("auto", "levels", "blocks"), default="auto",
+                    help="traversal schedule of the 4-state path (default: blocks where supported)")
     ap.add_argument("--quick", action="store_true",
                     help="throughput and kernel-class times only (for profiler runs)")
     ap.add_argument("--serving-seconds", type=float, default=8.0,
@@ -293,8 +295,13 @@ def main():
               file=sys.stderr, flush=True)
         del src, dst
 
+    sched = {"auto": B.PHG_SCHEDULE_AUTO, "levels": B.PHG_SCHEDULE_LEVELS,
+             "blocks": B.PHG_SCHEDULE_BLOCKS}[args.schedule]
+
     def open_ctx(prec):
         h = B.phg_create(N, C, S, R, prec, 0)
+        if sched != B.PHG_SCHEDULE_AUTO:
+            B.phg_set_schedule(h, sched)
         B.phg_bind_stream(h, stream.cuda_stream)
         B.set_problem(h, prob)
         B.phg_prepare(h)

@@ -111,6 +111,17 @@ phg_status phg_set_tip_states(phg_context *ctx, const int32_t *codes);
  * Defaults to all ones. */
 phg_status phg_set_pattern_weights(phg_context *ctx, const double *w);
 
+/* Traversal schedule.  LEVELS: one launch per tree level, every internal
+ * node's partial stored in device memory.  BLOCKS (4 states, R <= 8): the tree
+ * is cut into blocks of depth 3 (a block root at
+ * every depth that is a multiple of 3, with its internal children and
+ * grandchildren); only block roots' partials go to device memory and the
+ * pre-order pass recomputes in-block post-order partials in registers, which
+ * moves about 2.5x fewer bytes on a Yule tree.  AUTO (default) picks BLOCKS
+ * where supported.  Same results up to rounding order. */
+typedef enum { PHG_SCHEDULE_AUTO = 0, PHG_SCHEDULE_LEVELS = 1, PHG_SCHEDULE_BLOCKS = 2 } phg_schedule;
+phg_status phg_set_schedule(phg_context *ctx, phg_schedule mode);
+
 /* Allocate device memory and upload inputs without computing.  Optional. */
 phg_status phg_prepare(phg_context *ctx);
 

@@ -27,6 +27,9 @@ PHG_ERR_NUMERIC = -5
 PHG_ERR_BUSY = -6
 PHG_FP64 = 0
 PHG_FP32_SCALED = 1
+PHG_SCHEDULE_AUTO = 0
+PHG_SCHEDULE_LEVELS = 1
+PHG_SCHEDULE_BLOCKS = 2
 
 STATUS_NAMES = {0: "PHG_OK", -1: "PHG_ERR_ARG", -2: "PHG_ERR_STATE", -3: "PHG_ERR_OOM",
                 -4: "PHG_ERR_DEVICE", -5: "PHG_ERR_NUMERIC", -6: "PHG_ERR_BUSY"}
@@ -57,6 +60,7 @@ _SIGS = {
     "phg_set_tip_states": [_vp, _ip],
     "phg_set_pattern_weights": [_vp, _dp],
     "phg_prepare": [_vp],
+    "phg_set_schedule": [_vp, _c.c_int],
     "phg_log_likelihood": [_vp, _dp],
     "phg_gradient": [_vp, _dp, _dp],
     "phg_workspace_size": [_c.c_int, _c.c_int, _c.c_int, _c.c_int, _c.c_int, _c.POINTER(_c.c_size_t)],
@@ -185,6 +189,10 @@ def phg_set_tip_states(ctx, codes):
 def phg_set_pattern_weights(ctx, w):
     a = _f64(w)
     _check(lib().phg_set_pattern_weights(ctx, _p(a)), ctx, "phg_set_pattern_weights")
+
+
+def phg_set_schedule(ctx, mode: int):
+    _check(lib().phg_set_schedule(ctx, mode), ctx, "phg_set_schedule")
 
 
 def phg_prepare(ctx):
@@ -361,8 +369,10 @@ class Context:
         self.handle = phg_create(n_tips, n_patterns, n_states, n_categories, prec, device)
 
     @classmethod
-    def for_problem(cls, prob, prec=PHG_FP32_SCALED, device=0):
+    def for_problem(cls, prob, prec=PHG_FP32_SCALED, device=0, schedule=PHG_SCHEDULE_AUTO):
         ctx = cls(prob.n_tips, prob.n_patterns, prob.n_states, prob.n_categories, prec, device)
+        if schedule != PHG_SCHEDULE_AUTO:
+            phg_set_schedule(ctx.handle, schedule)
         ctx.set_problem(prob)
         return ctx
 

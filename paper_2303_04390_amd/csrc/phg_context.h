@@ -16,8 +16,8 @@ namespace phg {
 
 // Workspace plan: byte offsets of every device buffer inside one arena.
 struct Plan {
-    size_t codes, part, expo, P64, dP64, P32, dP32, b, V, Vinv, lam, rates, cw, pi, pw, sll, lpart,
-        gpart, out, sched, desc, total;
+    size_t codes, part, expo, P64, dP64, P32, dP32, TT64, dTT64, TT32, dTT32, b, V, Vinv, lam, rates, cw,
+        pi, pw, sll, lpart, gpart, out, sched, desc, total;
 };
 Plan make_plan(int N, int C, int S, int R, phg_precision prec);
 
@@ -49,9 +49,13 @@ struct phg_context {
     unsigned have = 0;           // inputs set at least once
     unsigned dirty = 0;          // inputs changed since the last upload
 
-    // schedule (host copy; uploaded to the sched region)
-    std::vector<phg::NodeTriple> sched;     // post levels then pre levels
-    std::vector<int> post_off, pre_off;     // level start offsets (size levels+1)
+    // schedule (host copy; uploaded to the sched region): NodeTriple records
+    // (level schedule) or BlockRec records (blocked schedule), as raw words
+    int sched_mode = PHG_SCHEDULE_AUTO;
+    bool blocked = false;
+    std::vector<int32_t> sched;
+    // levels in execution order: (first record, record count)
+    std::vector<std::pair<int, int>> post_lv, pre_lv;
 
     // device state
     bool dev_init = false;

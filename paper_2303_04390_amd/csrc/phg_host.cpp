@@ -20,6 +20,7 @@
 
 #include "phg_context.h"
 
+using phg::BlockRec;
 using phg::NodeTriple;
 using phg::ReqDesc;
 using phg::SegTable;
@@ -52,6 +53,11 @@ Plan make_plan(int N, int C, int S, int R, phg_precision prec) {
     p.dP64 = take(E * R * S * S * 8);
     p.P32 = take(prec == PHG_FP32_SCALED ? E * R * S * S * 4 : 0);
     p.dP32 = take(prec == PHG_FP32_SCALED ? E * R * S * S * 4 : 0);
+    const size_t tt = S == 4 ? E * R * 20 : 0;
+    p.TT64 = take(tt * 8);
+    p.dTT64 = take(tt * 8);
+    p.TT32 = take(prec == PHG_FP32_SCALED ? tt * 4 : 0);
+    p.dTT32 = take(prec == PHG_FP32_SCALED ? tt * 4 : 0);
     p.b = take(E * 8);
     p.V = take(static_cast<size_t>(S) * S * 8);
     p.Vinv = take(static_cast<size_t>(S) * S * 8);
@@ -64,7 +70,7 @@ Plan make_plan(int N, int C, int S, int R, phg_precision prec) {
     p.lpart = take(static_cast<size_t>(tiles) * 8);
     p.gpart = take(E * tiles * 8);
     p.out = take((E + 1) * 8);
-    p.sched = take(2 * I * sizeof(NodeTriple));
+    p.sched = take(I * sizeof(BlockRec));   // >= 2 I NodeTriples or I block records
     p.desc = take(sizeof(ReqDesc));
     p.total = off;
     return p;
@@ -133,19 +139,58 @@ void build_schedule(phg_context* ctx) {
     int D = 0;
     for (int v = N; v < n; ++v) D = std::max(D, depth[v]);
     ctx->sched.clear();
-    ctx->post_off.assign(1, 0);
+    ctx->post_lv.clear();
+    ctx->pre_lv.clear();
+    const bool fp32 = ctx->prec == PHG_FP32_SCALED;
+    ctx->blocked = ctx->sched_mode == PHG_SCHEDULE_BLOCKS ||
+                   (ctx->sched_mode == PHG_SCHEDULE_AUTO && phg::blocked_supported(ctx->S, ctx->R, fp32));
+    if (ctx->blocked) {
+        // block roots: internal nodes at depths 0, 3, 6, ...; records grouped
+        // by block depth m (depth / 3), shallowest first
+        const int M = D / phg::kBlockDepth;
+        std::vector<std::vector<int>> bylev(M + 1);
+        for (int v = N; v < n; ++v)
+            if (depth[v] % phg::kBlockDepth == 0) bylev[depth[v] / phg::kBlockDepth].push_back(v);
+        std::vector<int> start(M + 2, 0);
+        for (int m = 0; m <= M; ++m) {
+            start[m] = static_cast<int>(ctx->sched.size() / 16);
+            for (int v : bylev[m]) {
+                int32_t heap[16];
+                std::fill(heap, heap + 16, -1);
+                heap[0] = 0;
+                heap[1] = v;
+                for (int pos = 1; pos < 8; ++pos) {
+                    const int k = heap[pos];
+                    if (k >= N) {
+                        heap[2 * pos] = c0[k];
+                        heap[2 * pos + 1] = c1[k];
+                    }
+                }
+                ctx->sched.insert(ctx->sched.end(), heap, heap + 16);
+            }
+        }
+        start[M + 1] = static_cast<int>(ctx->sched.size() / 16);
+        for (int m = M; m >= 0; --m) ctx->post_lv.emplace_back(start[m], start[m + 1] - start[m]);
+        for (int m = 0; m <= M; ++m) ctx->pre_lv.emplace_back(start[m], start[m + 1] - start[m]);
+        return;
+    }
     std::vector<std::vector<int>> by(H + 1);
     for (int v = N; v < n; ++v) by[height[v]].push_back(v);
+    auto put = [&](int v) {
+        const int32_t rec[4] = {v, c0[v], c1[v], 0};
+        ctx->sched.insert(ctx->sched.end(), rec, rec + 4);
+    };
     for (int h = 1; h <= H; ++h) {
-        for (int v : by[h]) ctx->sched.push_back(NodeTriple{v, c0[v], c1[v], 0});
-        ctx->post_off.push_back(static_cast<int>(ctx->sched.size()));
+        const int a = static_cast<int>(ctx->sched.size() / 4);
+        for (int v : by[h]) put(v);
+        ctx->post_lv.emplace_back(a, static_cast<int>(ctx->sched.size() / 4) - a);
     }
-    ctx->pre_off.assign(1, static_cast<int>(ctx->sched.size()));
     std::vector<std::vector<int>> bd(D + 1);
     for (int v = N; v < n; ++v) bd[depth[v]].push_back(v);
     for (int d = 0; d <= D; ++d) {
-        for (int v : bd[d]) ctx->sched.push_back(NodeTriple{v, c0[v], c1[v], 0});
-        ctx->pre_off.push_back(static_cast<int>(ctx->sched.size()));
+        const int a = static_cast<int>(ctx->sched.size() / 4);
+        for (int v : bd[d]) put(v);
+        ctx->pre_lv.emplace_back(a, static_cast<int>(ctx->sched.size() / 4) - a);
     }
 }
 
@@ -209,6 +254,7 @@ phg_status ensure_device(phg_context* ctx) {
     d.R = ctx->R;
     d.tiles = ctx->tiles;
     d.fp32 = ctx->prec == PHG_FP32_SCALED ? 1 : 0;
+    d.blocked = ctx->blocked ? 1 : 0;
     d.sched = reinterpret_cast<const NodeTriple*>(a + pl.sched);
     d.codes = reinterpret_cast<const uint8_t*>(a + pl.codes);
     d.part = a + pl.part;
@@ -217,6 +263,10 @@ phg_status ensure_device(phg_context* ctx) {
     d.dP64 = reinterpret_cast<double*>(a + pl.dP64);
     d.P32 = reinterpret_cast<float*>(a + pl.P32);
     d.dP32 = reinterpret_cast<float*>(a + pl.dP32);
+    d.TT64 = reinterpret_cast<double*>(a + pl.TT64);
+    d.dTT64 = reinterpret_cast<double*>(a + pl.dTT64);
+    d.TT32 = reinterpret_cast<float*>(a + pl.TT32);
+    d.dTT32 = reinterpret_cast<float*>(a + pl.dTT32);
     d.b = reinterpret_cast<const double*>(a + pl.b);
     d.V = reinterpret_cast<const double*>(a + pl.V);
     d.Vinv = reinterpret_cast<const double*>(a + pl.Vinv);
@@ -244,7 +294,9 @@ phg_status upload(phg_context* ctx) {
         return hipMemcpyAsync(a + off, src, bytes, hipMemcpyHostToDevice, st);
     };
     if (dirty & kTopo) {
-        PHG_HIP(ctx, put(pl.sched, ctx->sched.data(), ctx->sched.size() * sizeof(NodeTriple)));
+        PHG_HIP(ctx, put(pl.sched, ctx->sched.data(), ctx->sched.size() * sizeof(int32_t)));
+        ctx->rd.blocked = ctx->blocked ? 1 : 0;
+        PHG_HIP(ctx, put(pl.desc, &ctx->rd, sizeof(ReqDesc)));
     }
     if (dirty & kB) PHG_HIP(ctx, put(pl.b, ctx->b.data(), ctx->b.size() * 8));
     if (dirty & kEig) {
@@ -299,16 +351,15 @@ phg_status ctx_enqueue_eval(phg_context* ctx, double* d_logl, double* d_grad) {
     PHG_TRY(prof_mark(ctx));
     PHG_HIP(ctx, launch_class(kPmat, d, descs, one_segment(units_for(kPmat, d, 0), 0, 0, 0, nullptr, nullptr), st));
     PHG_TRY(prof_mark(ctx));
-    const int H = static_cast<int>(ctx->post_off.size()) - 1;
+    const int H = static_cast<int>(ctx->post_lv.size());
     for (int h = 0; h < H; ++h) {
-        const int a = ctx->post_off[h], n = ctx->post_off[h + 1] - a;
+        const int a = ctx->post_lv[h].first, n = ctx->post_lv[h].second;
         PHG_HIP(ctx, launch_class(kPost, d, descs,
                                   one_segment(units_for(kPost, d, n), a, n, h == H - 1 ? 1 : 0, nullptr, nullptr), st));
     }
     PHG_TRY(prof_mark(ctx));
-    const int D = static_cast<int>(ctx->pre_off.size()) - 1;
-    for (int l = 0; l < D; ++l) {
-        const int a = ctx->pre_off[l], n = ctx->pre_off[l + 1] - a;
+    for (const auto& lv : ctx->pre_lv) {
+        const int a = lv.first, n = lv.second;
         PHG_HIP(ctx, launch_class(kPre, d, descs, one_segment(units_for(kPre, d, n), a, n, 0, nullptr, nullptr), st));
     }
     PHG_TRY(prof_mark(ctx));
@@ -531,6 +582,21 @@ phg_status phg_set_pattern_weights(phg_context* ctx, const double* w) {
     return PHG_OK;
 }
 
+phg_status phg_set_schedule(phg_context* ctx, phg_schedule mode) {
+    if (!ctx) return PHG_ERR_ARG;
+    if (mode != PHG_SCHEDULE_AUTO && mode != PHG_SCHEDULE_LEVELS && mode != PHG_SCHEDULE_BLOCKS)
+        return ctx->fail(PHG_ERR_ARG, "unknown schedule %d", static_cast<int>(mode));
+    if (mode == PHG_SCHEDULE_BLOCKS &&
+        !phg::blocked_supported(ctx->S, ctx->R, ctx->prec == PHG_FP32_SCALED))
+        return ctx->fail(PHG_ERR_ARG, "the blocked schedule needs 4 states and R <= 8 (FP32) or R <= 4 (FP64)");
+    ctx->sched_mode = mode;
+    if (ctx->have & kTopo) {
+        build_schedule(ctx);
+        ctx->dirty |= kTopo;
+    }
+    return PHG_OK;
+}
+
 phg_status phg_prepare(phg_context* ctx) {
     if (!ctx) return PHG_ERR_ARG;
     return ctx_ready(ctx);
@@ -625,8 +691,8 @@ phg_status phg_schedule_info(phg_context* ctx, int* n_post_levels, int* n_pre_le
                              int* n_launches) {
     if (!ctx) return PHG_ERR_ARG;
     if (!(ctx->have & kTopo)) return ctx->fail(PHG_ERR_STATE, "topology not set");
-    const int H = static_cast<int>(ctx->post_off.size()) - 1;
-    const int D = static_cast<int>(ctx->pre_off.size()) - 1;
+    const int H = static_cast<int>(ctx->post_lv.size());
+    const int D = static_cast<int>(ctx->pre_lv.size());
     if (n_post_levels) *n_post_levels = H;
     if (n_pre_levels) *n_pre_levels = D;
     if (n_launches) *n_launches = H + D + 2;
@@ -659,8 +725,8 @@ phg_status phg_profile_read(phg_context* ctx, double* ms, int* n_evals, int* lau
     if (n_evals) *n_evals = static_cast<int>(n);
     if (launches) {
         launches[PHG_PROF_PMAT] = 1;
-        launches[PHG_PROF_POST] = static_cast<int>(ctx->post_off.size()) - 1;
-        launches[PHG_PROF_PRE] = static_cast<int>(ctx->pre_off.size()) - 1;
+        launches[PHG_PROF_POST] = static_cast<int>(ctx->post_lv.size());
+        launches[PHG_PROF_PRE] = static_cast<int>(ctx->pre_lv.size());
         launches[PHG_PROF_FINAL] = 1;
     }
     ctx->prof_used = 0;

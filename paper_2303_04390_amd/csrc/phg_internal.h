@@ -17,6 +17,16 @@ struct NodeTriple {
     int32_t k, i, j, pad;
 };
 
+// A block of the tree for the blocked 4-state schedule: a block root at a
+// depth that is a multiple of 3 with its internal children and grandchildren,
+// as a heap: node[1] is the root, node[2p], node[2p+1] are the children of
+// node[p] when node[p] is an internal node at a position p < 8, and -1
+// otherwise.  Positions 2..7 that hold internal nodes are inside the block;
+// positions 8..15 hold the frontier (tips or the roots of deeper blocks).
+struct BlockRec {
+    int32_t node[16];   // node[0] unused
+};
+
 // Device-resident description of one evaluation request (one tree and
 // alignment with its own workspace).  Layouts (T = float or double):
 //   codes  uint8  [N][Cpad]                  tip states, S = all-ones, pad = S
@@ -36,6 +46,7 @@ struct NodeTriple {
 //                                             levels of this request's tree
 struct ReqDesc {
     int32_t N, C, Cpad, S, S4, R, tiles, fp32;
+    int32_t blocked, pad0;  // blocked: sched holds BlockRec records, else NodeTriple
     const NodeTriple* sched;
     const uint8_t* codes;
     void* part;
@@ -44,6 +55,12 @@ struct ReqDesc {
     double* dP64;
     float* P32;
     float* dP32;
+    // 4 states: tip tables [E][R][5][4]: entry y (0..3) is column y of P (or
+    // dP), entry 4 its row sums (the ambiguous code), so P e_y is one load
+    double* TT64;
+    double* dTT64;
+    float* TT32;
+    float* dTT32;
     const double* b;
     const double* V;
     const double* Vinv;
@@ -91,6 +108,11 @@ bool kernels_support(int S, int R);
 int tile_patterns(int S, int R, bool fp32);
 // Whether (S, R) runs on the dedicated 4-state kernels.
 inline bool uses_s4_kernels(int S, int R) { return S == 4 && R <= 8; }
+// Tree depth spanned by one block of the blocked 4-state schedule.
+constexpr int kBlockDepth = 3;
+// Whether the blocked schedule has kernels for (S, R, precision) that keep
+// every in-block vector in registers.
+inline bool blocked_supported(int S, int R, bool /*fp32*/) { return S == 4 && R <= 8; }
 
 // MFMA level kernels for other state counts (phg_kernels_gs.hip).
 int gs_tile_patterns(bool fp32);

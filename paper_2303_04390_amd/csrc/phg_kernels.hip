@@ -100,6 +100,19 @@ __device__ __forceinline__ const float* dptab<float>(const ReqDesc& d) { return 
 template <>
 __device__ __forceinline__ const double* dptab<double>(const ReqDesc& d) { return d.dP64; }
 
+template <typename T>
+__device__ __forceinline__ const T* ttab(const ReqDesc& d);
+template <>
+__device__ __forceinline__ const float* ttab<float>(const ReqDesc& d) { return d.TT32; }
+template <>
+__device__ __forceinline__ const double* ttab<double>(const ReqDesc& d) { return d.TT64; }
+template <typename T>
+__device__ __forceinline__ const T* dttab(const ReqDesc& d);
+template <>
+__device__ __forceinline__ const float* dttab<float>(const ReqDesc& d) { return d.dTT32; }
+template <>
+__device__ __forceinline__ const double* dttab<double>(const ReqDesc& d) { return d.dTT64; }
+
 // Segment of a (wave-uniform) unit index: linear scan of the table.
 __device__ __forceinline__ int find_segment(const SegTable& t, int unit) {
     int s = 0;
@@ -361,6 +374,311 @@ __global__ __launch_bounds__(kBlock) void pre_s4_kernel(const ReqDesc* __restric
                    g(dptab<T>(d)), g(d.cweights), g(d.pi), g(d.pw), g(d.gpart));
 }
 
+// ---------------------------------------------------------------- blocked schedule (4 states)
+//
+// A block (BlockRec) is a block root with its internal children and
+// grandchildren, laid out as a heap of positions 1..15.  Only block roots'
+// partials live in HBM: the post-order unit computes the in-block partials in
+// registers (positions 7..1) and stores the block root's; the pre-order unit
+// recomputes the in-block partials from the frontier, then walks positions
+// 1..7 top-down keeping in-block pre-order partials in registers and writing
+// only the frontier block roots' q.  Heap positions are compile-time
+// constants after unrolling, so every in-block vector is a register.
+//
+// One workgroup = one (block, 64-pattern tile) unit with one wavefront per
+// rate category (lane = pattern), so a wave holds 4 values per vector and
+// only its own category's P and dP (scalar registers).  What couples the
+// categories -- the shared power-of-two exponent of each node's partial and
+// the category sums in the gradient ratio -- goes through LDS with one barrier
+// per node (every wave follows the same block shape, so the barrier is
+// uniform).  Tip children use the tip tables: P e_y and dP e_y are one load.
+
+template <typename T, int R>
+struct Xch {
+    T v[2][5][R][kLanes];     // double-buffered exchange: [buf][field][category][lane]
+};
+
+// m = P_x v for the child at heap position CP in category r: a tip-table load
+// for a tip, else P times the in-block partial (CP < 8) or the frontier
+// block root's stored partial (CP >= 8).
+template <typename T, int R>
+__device__ __forceinline__ void blk_m(const int cp, const int cn, const int N, const int r, const int tile,
+                                      const int tiles, const int lane, const int code,
+                                      const GLOBAL T* __restrict__ part, const GLOBAL T* __restrict__ M,
+                                      const GLOBAL T* __restrict__ TT, const T (&preg)[8][4], T m[4]) {
+    if (cn < N) {
+        const Vec4<T> t = reinterpret_cast<const GLOBAL Vec4<T>*>(TT)[(static_cast<size_t>(cn) * R + r) * 5 + code];
+        m[0] = t.x;
+        m[1] = t.y;
+        m[2] = t.z;
+        m[3] = t.w;
+        return;
+    }
+    T v[4];
+    if (cp < 8) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[u] = preg[cp][u];
+    } else {
+        child_vec<T, R>(part, cn - N, tile, tiles, r, lane, -1, v);
+    }
+    matvec4(M + (static_cast<size_t>(cn) * R + r) * 16, v, m);
+}
+
+// In-block post-order over heap positions 7..LO in this wave's category.
+// Returns the sum of exponents taken (in-block nodes and frontier roots).
+template <typename T, int R, int LO>
+__device__ __forceinline__ int blkc_postorder(const int (&nd)[16], const int r, const int tile, const int tiles,
+                                              const int N, const int Cpad, const int lane,
+                                              const GLOBAL uint8_t* __restrict__ codes,
+                                              const GLOBAL T* __restrict__ part,
+                                              const GLOBAL int32_t* __restrict__ expo,
+                                              const GLOBAL T* __restrict__ P, const GLOBAL T* __restrict__ TT,
+                                              T (&p)[8][4], Xch<T, R>& xch, int& buf) {
+    const int c = tile * kLanes + lane;
+    int esum = 0;
+#pragma unroll
+    for (int pos = 7; pos >= LO; --pos) {
+        const int k = nd[pos];
+        if (k < N) continue;                       // absent or a tip (uniform over the workgroup)
+        const int c0 = nd[2 * pos], c1 = nd[2 * pos + 1];
+        const int code0 = c0 < N ? codes[static_cast<size_t>(c0) * Cpad + c] : 0;
+        const int code1 = c1 < N ? codes[static_cast<size_t>(c1) * Cpad + c] : 0;
+        if (2 * pos >= 8) {
+            if (c0 >= N) esum += expo[static_cast<size_t>(c0 - N) * Cpad + c];
+            if (c1 >= N) esum += expo[static_cast<size_t>(c1 - N) * Cpad + c];
+        }
+        T m0[4], m1[4];
+        blk_m<T, R>(2 * pos, c0, N, r, tile, tiles, lane, code0, part, P, TT, p, m0);
+        blk_m<T, R>(2 * pos + 1, c1, N, r, tile, tiles, lane, code1, part, P, TT, p, m1);
+        T lmx = T(0);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            p[pos][u] = m0[u] * m1[u];
+            lmx = fmax(lmx, p[pos][u]);
+        }
+        xch.v[buf][0][r][lane] = lmx;
+        __syncthreads();
+        T mx = xch.v[buf][0][0][lane];
+#pragma unroll
+        for (int rr = 1; rr < R; ++rr) mx = fmax(mx, xch.v[buf][0][rr][lane]);
+        buf ^= 1;
+        const int e = exponent_of(mx);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) p[pos][u] = exact_ldexp(p[pos][u], -e);
+        esum += e;
+    }
+    return esum;
+}
+
+template <typename T, int R>
+__global__ __launch_bounds__(kLanes * R) void post_blk_kernel(const ReqDesc* __restrict__ descs,
+                                                              const SegTable segs) {
+    __shared__ Xch<T, R> xch;
+    __shared__ double sx[R][kLanes];
+    const int r = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & (kLanes - 1);
+    const int unit = blockIdx.x;
+    if (unit >= segs.unit_begin[segs.n]) return;
+    const int sidx = find_segment(segs, unit);
+    const Segment sg = segs.seg[sidx];
+    const ReqDesc& d = descs[sg.desc];
+    const int tiles = d.tiles, N = d.N, Cpad = d.Cpad;
+    const int local = unit - segs.unit_begin[sidx];
+    const int bix = local / tiles;
+    const int tile = local - bix * tiles;
+    const GLOBAL int32_t* heap =
+        reinterpret_cast<const GLOBAL int32_t*>(g(d.sched)) + static_cast<size_t>(sg.sched_off + bix) * 16;
+    int nd[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) nd[i] = heap[i];
+    GLOBAL T* part = g(part_of<T>(d));
+    GLOBAL int32_t* expo = g(d.expo);
+    const GLOBAL T* P = g(ptab<T>(d));
+    const GLOBAL T* TT = g(ttab<T>(d));
+    const int c = tile * kLanes + lane;
+    T p[8][4];
+    int buf = 0;
+    const int ek = blkc_postorder<T, R, 1>(nd, r, tile, tiles, N, Cpad, lane, g(d.codes), part, expo, P, TT,
+                                           p, xch, buf);
+    if (!(sg.flags & 1)) {
+        store_vec<T, R>(part, nd[1] - N, tile, tiles, r, lane, p[1]);
+        if (r == 0) expo[static_cast<size_t>(nd[1] - N) * Cpad + c] = ek;
+    } else {
+        const GLOBAL double* pi = g(d.pi);
+        double acc = 0.0;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc += pi[u] * static_cast<double>(p[1][u]);
+        sx[r][lane] = g(d.cweights)[r] * acc;
+        __syncthreads();
+        if (r == 0) {
+            double site = 0.0;
+#pragma unroll
+            for (int rr = 0; rr < R; ++rr) site += sx[rr][lane];
+            const double ll =
+                (site > 0.0 ? log(site) : -INFINITY) + static_cast<double>(ek) * 0.69314718055994530942;
+            g(d.sll)[c] = ll;
+            const double W = g(d.pw)[c];
+            const double tsum = wave_sum(W != 0.0 ? W * ll : 0.0);
+            if (lane == 0) g(d.lpart)[tile] = tsum;
+        }
+    }
+}
+
+template <typename T, int R>
+__global__ __launch_bounds__(kLanes * R) void pre_blk_kernel(const ReqDesc* __restrict__ descs,
+                                                             const SegTable segs) {
+    __shared__ Xch<T, R> xch;
+    const int r = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & (kLanes - 1);
+    const int unit = blockIdx.x;
+    if (unit >= segs.unit_begin[segs.n]) return;
+    const int sidx = find_segment(segs, unit);
+    const Segment sg = segs.seg[sidx];
+    const ReqDesc& d = descs[sg.desc];
+    const int tiles = d.tiles, N = d.N, Cpad = d.Cpad;
+    const int local = unit - segs.unit_begin[sidx];
+    const int bix = local / tiles;
+    const int tile = local - bix * tiles;
+    const GLOBAL int32_t* heap =
+        reinterpret_cast<const GLOBAL int32_t*>(g(d.sched)) + static_cast<size_t>(sg.sched_off + bix) * 16;
+    int nd[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) nd[i] = heap[i];
+    GLOBAL T* part = g(part_of<T>(d));
+    const GLOBAL uint8_t* codes = g(d.codes);
+    const GLOBAL T* P = g(ptab<T>(d));
+    const GLOBAL T* dP = g(dptab<T>(d));
+    const GLOBAL T* TT = g(ttab<T>(d));
+    const GLOBAL T* dTT = g(dttab<T>(d));
+    GLOBAL double* gpart = g(d.gpart);
+    const int c = tile * kLanes + lane;
+    T p[8][4];
+    int buf = 0;
+    (void)blkc_postorder<T, R, 2>(nd, r, tile, tiles, N, Cpad, lane, codes, part, g(d.expo), P, TT, p, xch, buf);
+    T q[8][4];
+    if (nd[1] == 2 * N - 2) {
+        const GLOBAL double* pi = g(d.pi);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) q[1][u] = static_cast<T>(pi[u]);
+    } else {
+        child_vec<T, R>(part, nd[1] - N, tile, tiles, r, lane, -1, q[1]);
+    }
+    const double W = g(d.pw)[c];
+    const T wr = static_cast<T>(g(d.cweights)[r]);
+#pragma unroll
+    for (int pos = 1; pos <= 7; ++pos) {
+        const int k = nd[pos];
+        if (k < N) continue;
+        const int c0 = nd[2 * pos], c1 = nd[2 * pos + 1];
+        const bool in0 = c0 >= N, in1 = c1 >= N;
+        const int code0 = in0 ? 0 : codes[static_cast<size_t>(c0) * Cpad + c];
+        const int code1 = in1 ? 0 : codes[static_cast<size_t>(c1) * Cpad + c];
+        T m0[4], m1[4], dm0[4], dm1[4], v0[4], v1[4];
+        if (in0) {
+            if (2 * pos < 8) {
+#pragma unroll
+                for (int u = 0; u < 4; ++u) v0[u] = p[2 * pos][u];
+            } else {
+                child_vec<T, R>(part, c0 - N, tile, tiles, r, lane, -1, v0);
+            }
+            matvec4(P + (static_cast<size_t>(c0) * R + r) * 16, v0, m0);
+            matvec4(dP + (static_cast<size_t>(c0) * R + r) * 16, v0, dm0);
+        } else {
+            const size_t ti = (static_cast<size_t>(c0) * R + r) * 5 + code0;
+            const Vec4<T> a = reinterpret_cast<const GLOBAL Vec4<T>*>(TT)[ti];
+            const Vec4<T> b = reinterpret_cast<const GLOBAL Vec4<T>*>(dTT)[ti];
+            m0[0] = a.x; m0[1] = a.y; m0[2] = a.z; m0[3] = a.w;
+            dm0[0] = b.x; dm0[1] = b.y; dm0[2] = b.z; dm0[3] = b.w;
+        }
+        if (in1) {
+            if (2 * pos + 1 < 8) {
+#pragma unroll
+                for (int u = 0; u < 4; ++u) v1[u] = p[2 * pos + 1][u];
+            } else {
+                child_vec<T, R>(part, c1 - N, tile, tiles, r, lane, -1, v1);
+            }
+            matvec4(P + (static_cast<size_t>(c1) * R + r) * 16, v1, m1);
+            matvec4(dP + (static_cast<size_t>(c1) * R + r) * 16, v1, dm1);
+        } else {
+            const size_t ti = (static_cast<size_t>(c1) * R + r) * 5 + code1;
+            const Vec4<T> a = reinterpret_cast<const GLOBAL Vec4<T>*>(TT)[ti];
+            const Vec4<T> b = reinterpret_cast<const GLOBAL Vec4<T>*>(dTT)[ti];
+            m1[0] = a.x; m1[1] = a.y; m1[2] = a.z; m1[3] = a.w;
+            dm1[0] = b.x; dm1[1] = b.y; dm1[2] = b.z; dm1[3] = b.w;
+        }
+        T u0[4], u1[4], a0 = T(0), a1 = T(0), dd = T(0);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            u0[u] = q[pos][u] * m1[u];
+            u1[u] = q[pos][u] * m0[u];
+            a0 += u0[u] * dm0[u];
+            a1 += u1[u] * dm1[u];
+            dd += u0[u] * m0[u];
+        }
+        T q0[4], q1[4], mx0 = T(0), mx1 = T(0);
+        if (in0) {
+            matvec4_t(P + (static_cast<size_t>(c0) * R + r) * 16, u0, q0);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) mx0 = fmax(mx0, q0[u]);
+        }
+        if (in1) {
+            matvec4_t(P + (static_cast<size_t>(c1) * R + r) * 16, u1, q1);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) mx1 = fmax(mx1, q1[u]);
+        }
+        xch.v[buf][0][r][lane] = wr * a0;
+        xch.v[buf][1][r][lane] = wr * a1;
+        xch.v[buf][2][r][lane] = wr * dd;
+        xch.v[buf][3][r][lane] = mx0;
+        xch.v[buf][4][r][lane] = mx1;
+        __syncthreads();
+        T num0 = T(0), num1 = T(0), den = T(0), MX0 = T(0), MX1 = T(0);
+#pragma unroll
+        for (int rr = 0; rr < R; ++rr) {
+            num0 += xch.v[buf][0][rr][lane];
+            num1 += xch.v[buf][1][rr][lane];
+            den += xch.v[buf][2][rr][lane];
+            MX0 = fmax(MX0, xch.v[buf][3][rr][lane]);
+            MX1 = fmax(MX1, xch.v[buf][4][rr][lane]);
+        }
+        buf ^= 1;
+        if (in0) {
+            const int e = exponent_of(MX0);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) q0[u] = exact_ldexp(q0[u], -e);
+            if (2 * pos < 8) {
+#pragma unroll
+                for (int u = 0; u < 4; ++u) q[2 * pos][u] = q0[u];
+            } else {
+                store_vec<T, R>(part, c0 - N, tile, tiles, r, lane, q0);
+            }
+        }
+        if (in1) {
+            const int e = exponent_of(MX1);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) q1[u] = exact_ldexp(q1[u], -e);
+            if (2 * pos + 1 < 8) {
+#pragma unroll
+                for (int u = 0; u < 4; ++u) q[2 * pos + 1][u] = q1[u];
+            } else {
+                store_vec<T, R>(part, c1 - N, tile, tiles, r, lane, q1);
+            }
+        }
+        // gradient contributions: wave 0 takes child 0, wave 1 (or 0 if R == 1) child 1
+        const double dden = static_cast<double>(den);
+        if (r == 0) {
+            const double g0 = (W != 0.0) ? W * (static_cast<double>(num0) / dden) : 0.0;
+            const double s0 = wave_sum(g0);
+            if (lane == 0) gpart[static_cast<size_t>(c0) * tiles + tile] = s0;
+        }
+        if (r == (R > 1 ? 1 : 0)) {
+            const double g1 = (W != 0.0) ? W * (static_cast<double>(num1) / dden) : 0.0;
+            const double s1 = wave_sum(g1);
+            if (lane == 0) gpart[static_cast<size_t>(c1) * tiles + tile] = s1;
+        }
+    }
+}
+
 // ---------------------------------------------------------------- P(t), dP/dt
 
 // Small S (<= 8): one thread per (branch, category) pair builds the whole
@@ -387,6 +705,7 @@ __global__ __launch_bounds__(256) void pmat_small_kernel(const ReqDesc* __restri
         dex[k] = g * d.lam[k] * e;
     }
     const size_t base = static_cast<size_t>(pair) * S * S;
+    double Pm[S][S], dPm[S][S];
 #pragma unroll
     for (int s = 0; s < S; ++s) {
 #pragma unroll
@@ -398,6 +717,8 @@ __global__ __launch_bounds__(256) void pmat_small_kernel(const ReqDesc* __restri
                 acc += v * ex[k];
                 dacc += v * dex[k];
             }
+            Pm[s][u] = acc;
+            dPm[s][u] = dacc;
             d.P64[base + s * S + u] = acc;
             d.dP64[base + s * S + u] = dacc;
             if (d.fp32) {
@@ -405,6 +726,32 @@ __global__ __launch_bounds__(256) void pmat_small_kernel(const ReqDesc* __restri
                 d.dP32[base + s * S + u] = static_cast<float>(dacc);
             }
         }
+    }
+    if (S == 4) {
+        // tip tables: entry y < 4 is column y (P e_y), entry 4 the row sums (P 1)
+        const size_t tb = static_cast<size_t>(pair) * 20;
+#pragma unroll
+        for (int y = 0; y <= S; ++y)
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                double v = 0.0, dv = 0.0;
+                if (y < S) {
+                    v = Pm[s][y];
+                    dv = dPm[s][y];
+                } else {
+#pragma unroll
+                    for (int u = 0; u < S; ++u) {
+                        v += Pm[s][u];
+                        dv += dPm[s][u];
+                    }
+                }
+                d.TT64[tb + 4 * y + s] = v;
+                d.dTT64[tb + 4 * y + s] = dv;
+                if (d.fp32) {
+                    d.TT32[tb + 4 * y + s] = static_cast<float>(v);
+                    d.dTT32[tb + 4 * y + s] = static_cast<float>(dv);
+                }
+            }
     }
 }
 
@@ -479,27 +826,34 @@ __global__ __launch_bounds__(256) void finalize_kernel(const ReqDesc* __restrict
 }
 
 template <typename T, int R>
-hipError_t level_r(KernelClass k, const ReqDesc* descs, const SegTable& t, hipStream_t st) {
+hipError_t level_r(KernelClass k, bool blocked, const ReqDesc* descs, const SegTable& t, hipStream_t st) {
     const int n_units = t.unit_begin[t.n];
     const int blocks = (n_units + kWavesPerBlock - 1) / kWavesPerBlock;
-    if (k == kPost)
+    if (blocked) {
+        if (k == kPost)
+            hipLaunchKernelGGL((post_blk_kernel<T, R>), dim3(n_units), dim3(kLanes * R), 0, st, descs, t);
+        else
+            hipLaunchKernelGGL((pre_blk_kernel<T, R>), dim3(n_units), dim3(kLanes * R), 0, st, descs, t);
+    } else if (k == kPost) {
         hipLaunchKernelGGL((post_s4_kernel<T, R>), dim3(blocks), dim3(kBlock), 0, st, descs, t);
-    else
+    } else {
         hipLaunchKernelGGL((pre_s4_kernel<T, R>), dim3(blocks), dim3(kBlock), 0, st, descs, t);
+    }
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t level_t(KernelClass k, int R, const ReqDesc* descs, const SegTable& t, hipStream_t st) {
+hipError_t level_t(KernelClass k, int R, bool blocked, const ReqDesc* descs, const SegTable& t,
+                   hipStream_t st) {
     switch (R) {
-        case 1: return level_r<T, 1>(k, descs, t, st);
-        case 2: return level_r<T, 2>(k, descs, t, st);
-        case 3: return level_r<T, 3>(k, descs, t, st);
-        case 4: return level_r<T, 4>(k, descs, t, st);
-        case 5: return level_r<T, 5>(k, descs, t, st);
-        case 6: return level_r<T, 6>(k, descs, t, st);
-        case 7: return level_r<T, 7>(k, descs, t, st);
-        case 8: return level_r<T, 8>(k, descs, t, st);
+        case 1: return level_r<T, 1>(k, blocked, descs, t, st);
+        case 2: return level_r<T, 2>(k, blocked, descs, t, st);
+        case 3: return level_r<T, 3>(k, blocked, descs, t, st);
+        case 4: return level_r<T, 4>(k, blocked, descs, t, st);
+        case 5: return level_r<T, 5>(k, blocked, descs, t, st);
+        case 6: return level_r<T, 6>(k, blocked, descs, t, st);
+        case 7: return level_r<T, 7>(k, blocked, descs, t, st);
+        case 8: return level_r<T, 8>(k, blocked, descs, t, st);
         default: return hipErrorInvalidValue;
     }
 }
@@ -538,8 +892,8 @@ hipError_t launch_class(KernelClass k, const ReqDesc& shape, const ReqDesc* desc
         case kPost:
         case kPre:
             if (!uses_s4_kernels(shape.S, shape.R)) return launch_level_gs(k, shape, descs, t, st);
-            if (shape.fp32) return level_t<float>(k, shape.R, descs, t, st);
-            return level_t<double>(k, shape.R, descs, t, st);
+            if (shape.fp32) return level_t<float>(k, shape.R, shape.blocked != 0, descs, t, st);
+            return level_t<double>(k, shape.R, shape.blocked != 0, descs, t, st);
         case kFinal:
             hipLaunchKernelGGL(finalize_kernel, dim3(n_units), dim3(256), 0, st, descs, t);
             return hipGetLastError();

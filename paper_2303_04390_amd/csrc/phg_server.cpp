@@ -318,19 +318,19 @@ bool launch_step(phg_server* s) {
             key = GroupKey{kPmat, d.S == 4, 0, 0};
             it.units = units_for(kPmat, d, 0);
         } else if (st <= t->H) {
-            const int l = st - 1, a = c->post_off[l], n = c->post_off[l + 1] - a;
+            const int l = st - 1, a = c->post_lv[l].first, n = c->post_lv[l].second;
             it.seg.sched_off = a;
             it.seg.n_nodes = n;
             it.seg.flags = (l == t->H - 1) ? 1 : 0;
             it.units = units_for(kPost, d, n);
-            key = GroupKey{kPost, uses_s4_kernels(d.S, d.R), d.fp32,
+            key = GroupKey{kPost, uses_s4_kernels(d.S, d.R) + 2 * d.blocked, d.fp32,
                            uses_s4_kernels(d.S, d.R) ? d.R : (d.S + 15) / 16};
         } else if (st <= t->H + t->D) {
-            const int l = st - t->H - 1, a = c->pre_off[l], n = c->pre_off[l + 1] - a;
+            const int l = st - t->H - 1, a = c->pre_lv[l].first, n = c->pre_lv[l].second;
             it.seg.sched_off = a;
             it.seg.n_nodes = n;
             it.units = units_for(kPre, d, n);
-            key = GroupKey{kPre, uses_s4_kernels(d.S, d.R), d.fp32,
+            key = GroupKey{kPre, uses_s4_kernels(d.S, d.R) + 2 * d.blocked, d.fp32,
                            uses_s4_kernels(d.S, d.R) ? d.R : (d.S + 15) / 16};
         } else {
             double* out = ctx_out_dev(c);
@@ -617,8 +617,8 @@ phg_status phg_server_register_tree(phg_server* s, const phg_tree_desc* d, uint6
         phg_destroy(ctx);
         return s->fail(PHG_ERR_OOM, "tree workspace exceeds the server memory budget");
     }
-    t->H = static_cast<int>(ctx->post_off.size()) - 1;
-    t->D = static_cast<int>(ctx->pre_off.size()) - 1;
+    t->H = static_cast<int>(ctx->post_lv.size());
+    t->D = static_cast<int>(ctx->pre_lv.size());
     t->id = s->next_tree++;
     *tree_id = t->id;
     s->trees[t->id] = std::move(t);

@@ -125,6 +125,9 @@ def test_schedule_levels():
     try:
         parent = synth.caterpillar_topology(N)
         B.phg_set_topology(ctx, parent)
+        post, pre, _ = B.phg_schedule_info(ctx)             # blocks: one per 3 depths
+        assert post == pre == (N - 2) // 3 + 1
+        B.phg_set_schedule(ctx, B.PHG_SCHEDULE_LEVELS)
         post, pre, launches = B.phg_schedule_info(ctx)
         assert post == N - 1 and pre == N - 1 and launches == 2 * N
         parent = synth.yule_topology(N, np.random.default_rng(3))
@@ -168,3 +171,32 @@ def test_one_hip_runtime_in_process():
                          cwd=os.path.dirname(os.path.dirname(__file__)), timeout=300)
     assert out.returncode == 0, out.stderr
     assert out.stdout.strip().splitlines()[-1] == "1"
+
+
+def test_block_schedule_shape():
+    N = 1000
+    parent = synth.yule_topology(N, np.random.default_rng(0))
+    ctx = B.phg_create(N, 10, 4, 4, B.PHG_FP32_SCALED, 0)
+    try:
+        B.phg_set_topology(ctx, parent)
+        post_b, pre_b, _ = B.phg_schedule_info(ctx)        # AUTO -> blocks for 4 states
+        B.phg_set_schedule(ctx, B.PHG_SCHEDULE_LEVELS)
+        post_l, pre_l, _ = B.phg_schedule_info(ctx)
+        assert post_b == pre_b and post_b < post_l / 2 and pre_b < pre_l / 2
+        B.phg_set_schedule(ctx, B.PHG_SCHEDULE_BLOCKS)
+        assert B.phg_schedule_info(ctx)[0] == post_b
+    finally:
+        B.phg_destroy(ctx)
+    ctx = B.phg_create(50, 10, 20, 4, B.PHG_FP32_SCALED, 0)
+    try:
+        with pytest.raises(B.PhgError) as e:
+            B.phg_set_schedule(ctx, B.PHG_SCHEDULE_BLOCKS)
+        assert e.value.status == B.PHG_ERR_ARG
+    finally:
+        B.phg_destroy(ctx)
+    ctx = B.phg_create(50, 10, 4, 9, B.PHG_FP64, 0)
+    try:
+        with pytest.raises(B.PhgError):
+            B.phg_set_schedule(ctx, B.PHG_SCHEDULE_BLOCKS)
+    finally:
+        B.phg_destroy(ctx)

@@ -19,17 +19,21 @@ TOL = {B.PHG_FP64: (1e-12, 1e-9), B.PHG_FP32_SCALED: (1e-6, 1e-4)}
 PREC_NAME = {B.PHG_FP64: "fp64", B.PHG_FP32_SCALED: "fp32"}
 
 
-def gpu_eval(prob, prec):
-    with B.Context.for_problem(prob, prec) as ctx:
+SCHED_NAME = {B.PHG_SCHEDULE_AUTO: "auto", B.PHG_SCHEDULE_LEVELS: "levels",
+              B.PHG_SCHEDULE_BLOCKS: "blocks"}
+
+
+def gpu_eval(prob, prec, schedule=B.PHG_SCHEDULE_AUTO):
+    with B.Context.for_problem(prob, prec, schedule=schedule) as ctx:
         return ctx.gradient()
 
 
-def compare(name, prob, prec, ref=None):
-    print(f"[case] {name} {PREC_NAME[prec]} N={prob.n_tips} C={prob.n_patterns} "
+def compare(name, prob, prec, ref=None, schedule=B.PHG_SCHEDULE_AUTO):
+    print(f"[case] {name} {PREC_NAME[prec]} {SCHED_NAME[schedule]} N={prob.n_tips} C={prob.n_patterns} "
           f"S={prob.n_states} R={prob.n_categories}", flush=True)
     ref = ref if ref is not None else oracle.evaluate_problem(prob)
-    logl, grad = gpu_eval(prob, prec)
-    check(f"{name}/{PREC_NAME[prec]}", logl, grad, ref, *TOL[prec])
+    logl, grad = gpu_eval(prob, prec, schedule)
+    check(f"{name}/{PREC_NAME[prec]}/{SCHED_NAME[schedule]}", logl, grad, ref, *TOL[prec])
     return logl, grad, ref
 
 
@@ -197,3 +201,36 @@ def test_async_with_torch_memory_and_stream(hky16):
         finally:
             B.phg_destroy(h)
         del ws
+
+
+@pytest.mark.parametrize("prec", [B.PHG_FP32_SCALED, B.PHG_FP64])
+def test_level_schedule_hky1000(hky1000, prec):
+    compare("hky1000", hky1000[0], prec, hky1000[1], schedule=B.PHG_SCHEDULE_LEVELS)
+
+
+@pytest.mark.parametrize("N,C,seed", [(2, 70, 1), (3, 64, 2), (7, 130, 3), (40, 65, 4), (300, 200, 5)])
+def test_blocked_and_level_schedules_agree(N, C, seed):
+    """Small and odd trees (down to two tips, block shapes with tips at every
+    heap position) under both schedules, both precisions."""
+    prob = synth.config_problem("hky1000", seed=seed, n_tips=N, n_patterns=C)
+    ref = oracle.evaluate_problem(prob)
+    for prec in (B.PHG_FP64, B.PHG_FP32_SCALED):
+        lb, gb, _ = compare(f"sched-N{N}", prob, prec, ref, schedule=B.PHG_SCHEDULE_BLOCKS)
+        ll, gl, _ = compare(f"sched-N{N}", prob, prec, ref, schedule=B.PHG_SCHEDULE_LEVELS)
+        print(f"[schedules] N={N} {PREC_NAME[prec]} bitwise-equal={lb == ll and np.array_equal(gb, gl)}",
+              flush=True)
+
+
+def test_blocked_caterpillar_levels():
+    """A caterpillar has one block per three levels and a tip at every
+    second heap position: stresses frontier and in-block tip handling."""
+    N, C = 200, 64
+    rng = np.random.default_rng(13)
+    parent = synth.caterpillar_topology(N)
+    b = rng.exponential(0.1, 2 * N - 2)
+    pi = np.array([0.2, 0.3, 0.1, 0.4])
+    Q = synth.hky_model(3.0, pi)
+    rates, w = synth.discrete_gamma(0.8, 4)
+    prob = synth.make_problem(parent, b, Q, pi, rates, w, C, rng, ambiguous_fraction=0.1)
+    for prec in (B.PHG_FP64, B.PHG_FP32_SCALED):
+        compare("caterpillar200", prob, prec, schedule=B.PHG_SCHEDULE_BLOCKS)
