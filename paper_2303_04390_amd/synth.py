@@ -34,7 +34,7 @@ import scipy.special
 __all__ = [
     "Problem", "yule_topology", "exponential_branch_lengths", "hky_model",
     "gtr_model", "gy94_model", "eigensystem", "discrete_gamma", "simulate_codes",
-    "make_problem", "config_problem", "sense_codons", "reroot",
+    "make_problem", "config_problem", "sense_codons", "reroot", "time_tree",
 ]
 
 NUC = "ACGT"
@@ -152,6 +152,30 @@ def caterpillar_topology(n_tips: int) -> np.ndarray:
 def exponential_branch_lengths(n_tips: int, mean: float,
                                rng: np.random.Generator) -> np.ndarray:
     return rng.exponential(mean, size=2 * n_tips - 2)
+
+
+def time_tree(parent: np.ndarray, rng: np.random.Generator, mean_interval: float = 0.02,
+              tip_spread: float = 0.05, rate_median: float = 1.0, rate_sigma: float = 0.3):
+    """Node heights and branch rate scalars for a topology (a dated tree with
+    an uncorrelated log-normal relaxed clock).
+
+    Tips are sampled at heights U[0, tip_spread] (heterochronous data); an
+    internal node sits Exponential(mean_interval) above its higher child; each
+    branch gets a rate scalar LogNormal(log rate_median, rate_sigma).
+    Returns (heights [2N-1], rates [2N-2]), indexed by node / child node.
+    """
+    n = parent.shape[0]
+    N = (n + 1) // 2
+    heights = np.zeros(n)
+    heights[:N] = rng.uniform(0.0, tip_spread, N)
+    kids = [[] for _ in range(n)]
+    for v in range(n - 1):
+        kids[parent[v]].append(v)
+    for v in reversed(_children_order(parent)):       # children before parents
+        if v >= N:
+            heights[v] = max(heights[c] for c in kids[v]) + rng.exponential(mean_interval)
+    rates = rate_median * np.exp(rng.normal(0.0, rate_sigma, n - 1))
+    return heights, rates
 
 
 def reroot(parent: np.ndarray, b: np.ndarray, new_edge_child: int,
