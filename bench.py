@@ -39,6 +39,7 @@ KERNEL_SRC = os.path.join(ROOT, "paper_2303_04390_amd", "csrc", "phg_kernels.hip
 # the kernel source changes the figure no longer applies and traffic is null.
 MEASURED_TRAFFIC = {
     "kernel_source_sha256": "ffade6c5aa4b186e208b0c591e01b9e2f9c072d3244980e0f963a9c64f50ae26",
+    "schedule": "levels",
     "bytes_per_eval": {"pre_grad": 1976587324, "post": 1386518026},
 }
 
@@ -50,19 +51,23 @@ def kernel_source_sha256():
 
 
 def algorithmic_bytes(parent, n_tips, C, R, S, tsz):
-    """Bytes each pass must move per evaluation in this design.
+    """Bytes each pass must move per evaluation under the level schedule.
 
     post: read each internal child's partial (R*S*tsz) and int32 exponent,
           each tip child's 1-byte code; write each non-root internal partial
-          and exponent; write the root's float64 log site likelihood.
+          and exponent; at the root read W_c and write the float64 log site
+          likelihood.
     pre+grad: read q of each non-root parent, read p and write q of each
-          internal child, read each tip child's code, read W_c once.
-    All per pattern, times C.
+          internal child, read each tip child's code, read W_c once per
+          level, write one float64 gradient partial per branch and tile.
+    All per pattern, times C (the partials per tile, times the tile count).
     """
     n = parent.shape[0]
     root = n - 1
     vec = R * S * tsz
     post = pre = 0
+    pre_levels = set()
+    depth = node_depths(parent)
     for k in range(n_tips, n):
         kids = np.nonzero(parent == k)[0]
         for x in kids:
@@ -76,9 +81,54 @@ def algorithmic_bytes(parent, n_tips, C, R, S, tsz):
             post += vec + 4
             pre += vec
         else:
-            post += 8
-    pre += 8
-    return post * C, pre * C
+            post += 16
+        pre_levels.add(depth[k])
+    pre += 8 * len(pre_levels)
+    tiles = -(-C // 64)
+    return post * C, pre * C + 8 * (n - 1) * tiles
+
+
+def algorithmic_bytes_blocked(parent, n_tips, C, R, S, tsz, block_depth=3):
+    """Bytes each pass must move per evaluation under the blocked schedule.
+
+    Block roots are the internal nodes at depths 0, 3, 6, ...; a workgroup
+    keeps everything inside its block in registers, so HBM sees only the
+    block roots' vectors and the tips' codes.
+    post: each tip's code once; each non-root block root's partial and
+          exponent written once (by its own block) and read once (by the
+          block above); at the root W_c read and the log site likelihood
+          written.
+    pre+grad: each tip's code once; for each non-root block root, its
+          partial read and its q written by the block above, and that q
+          read by its own block; W_c read once per block; one float64
+          gradient partial per branch and tile.
+    """
+    n = parent.shape[0]
+    root = n - 1
+    vec = R * S * tsz
+    depth = node_depths(parent)
+    roots = [v for v in range(n_tips, n) if depth[v] % block_depth == 0]
+    nb = len(roots) - 1                       # non-root block roots
+    post = n_tips + nb * 2 * (vec + 4) + 16
+    pre = n_tips + nb * 3 * vec + 8 * len(roots)
+    tiles = -(-C // 64)
+    return post * C, pre * C + 8 * (n - 1) * tiles
+
+
+def node_depths(parent):
+    n = parent.shape[0]
+    depth = np.full(n, -1, np.int64)
+    depth[n - 1] = 0
+    stack = [n - 1]
+    kids = [[] for _ in range(n)]
+    for x in range(n - 1):
+        kids[parent[x]].append(x)
+    while stack:
+        v = stack.pop()
+        for x in kids[v]:
+            depth[x] = depth[v] + 1
+            stack.append(x)
+    return depth
 
 
 def serving_measurement(args, B, synth):
@@ -330,7 +380,9 @@ def main():
 
     # ------------------------------------------------ live kernel-class times
     per_eval_ms = ms_cls / max(n_prof, 1)
-    post_bytes, pre_bytes = algorithmic_bytes(prob.parent, N, C, R, S, 4)
+    blocked = B.phg_get_schedule(h) == B.PHG_SCHEDULE_BLOCKS
+    post_bytes, pre_bytes = (algorithmic_bytes_blocked if blocked else algorithmic_bytes)(
+        prob.parent, N, C, R, S, 4)
     cls = dict(zip(B.PROF_NAMES, per_eval_ms.tolist()))
     dominant = max(("post", "pre_grad"), key=lambda k: cls[k])
     dom_bytes = pre_bytes if dominant == "pre_grad" else post_bytes
@@ -340,10 +392,14 @@ def main():
     achieved = (dom_bytes / n_launch) / (dom_ms * 1e-3 / n_launch) / 1e9
     traffic = None
     if (MEASURED_TRAFFIC["kernel_source_sha256"] == kernel_source_sha256()
+            and MEASURED_TRAFFIC["schedule"] == ("blocks" if blocked else "levels")
             and dominant in MEASURED_TRAFFIC["bytes_per_eval"]):
         traffic = int(MEASURED_TRAFFIC["bytes_per_eval"][dominant] / n_launch)
     roofline = {
-        "bound": "hbm", "kernel": "pre_s4_kernel<float,4>" if dominant == "pre_grad" else "post_s4_kernel<float,4>",
+        "bound": "hbm",
+        "kernel": (f"{'pre' if dominant == 'pre_grad' else 'post'}_bmf_kernel<{R}>" if blocked and R & (R - 1) == 0
+                   else f"{'pre' if dominant == 'pre_grad' else 'post'}_{'blk' if blocked else 's4'}_kernel<float,{R}>"),
+        "schedule": "blocks" if blocked else "levels",
         "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
         "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",

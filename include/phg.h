@@ -122,6 +122,11 @@ phg_status phg_set_pattern_weights(phg_context *ctx, const double *w);
 typedef enum { PHG_SCHEDULE_AUTO = 0, PHG_SCHEDULE_LEVELS = 1, PHG_SCHEDULE_BLOCKS = 2 } phg_schedule;
 phg_status phg_set_schedule(phg_context *ctx, phg_schedule mode);
 
+/* The schedule in effect for the current topology: *schedule is
+ * PHG_SCHEDULE_LEVELS or PHG_SCHEDULE_BLOCKS (AUTO resolved).  PHG_ERR_STATE
+ * before the topology is set. */
+phg_status phg_get_schedule(phg_context *ctx, int *schedule);
+
 /* Allocate device memory and upload inputs without computing.  Optional. */
 phg_status phg_prepare(phg_context *ctx);
 
@@ -135,6 +140,48 @@ phg_status phg_log_likelihood(phg_context *ctx, double *logl);
  * 2N-2 branches (eq:gradient summed by eq:gradientSumAcrossColumns).
  * Synchronous.  On PHG_ERR_NUMERIC, *logl = -inf and grad is all NaN. */
 phg_status phg_gradient(phg_context *ctx, double *logl, double *grad);
+
+/* ---- parameter chain rules: node heights, branch rates, branch sets ----
+ *
+ * The Methods section's problem statement allows a branch length to be the
+ * difference between the parent's and the child's node heights times a
+ * (possibly branch-specific) rate scalar, and the gradient-kernel section
+ * sums branch derivatives over a chosen set of branches (e.g. a strict
+ * clock).  These calls apply those chain rules on the device right after the
+ * gradient, g_i = d logL / d b_i:
+ *   d logL / d rate_i = (h_parent(i) - h_i) g_i
+ *   d logL / d h_k    = sum over children c of k of rate_c g_c
+ *                       - rate_k g_k   (the last term absent at the root)
+ *   set sums          = sum over the branches of a set, increasing index.
+ */
+
+/* b_i = (heights[parent(i)] - heights[i]) * rates[i].  heights: 2N-1 by node
+ * (root 2N-2); rates: 2N-2 by child node; both copied.  Replaces the branch
+ * lengths and keeps heights and rates for phg_time_tree_gradient until the
+ * next phg_set_branch_lengths or phg_set_topology.  PHG_ERR_STATE before the
+ * topology; PHG_ERR_ARG on NULL, a non-finite height, a rate that is
+ * negative or not finite, or a node above its parent. */
+phg_status phg_set_time_tree(phg_context *ctx, const double *heights, const double *rates);
+
+/* Branch sets: set_of[i] (2N-2 int32 by child node) in [0, n_sets), or -1 for
+ * a branch in no set; 1 <= n_sets <= 2N-2; copied.  n_sets = 0 clears
+ * (set_of may be NULL).  PHG_ERR_ARG on an entry out of range. */
+phg_status phg_set_branch_sets(phg_context *ctx, const int32_t *set_of, int n_sets);
+
+/* One evaluation under the time tree.  Writes (each nullable): logL;
+ * d_heights (2N-1) = d logL / d h; d_rates (2N-2) = d logL / d rate; d_sets
+ * (n_sets) = sum over set j of d_rates, the derivative with respect to one
+ * rate shared by the branches of set j (a strict clock is one set holding
+ * every branch).  Synchronous.  PHG_ERR_STATE without phg_set_time_tree, or
+ * with d_sets and no branch sets; PHG_ERR_NUMERIC as phg_gradient (outputs
+ * NaN, logL -inf). */
+phg_status phg_time_tree_gradient(phg_context *ctx, double *logl, double *d_heights,
+                                  double *d_rates, double *d_sets);
+
+/* One evaluation; d_sets[j] = sum over set j of d logL / d b_i (branch
+ * lengths tied within a set).  logl nullable, d_sets not.  PHG_ERR_STATE
+ * without branch sets; PHG_ERR_NUMERIC as phg_gradient. */
+phg_status phg_gradient_branch_sets(phg_context *ctx, double *logl, double *d_sets);
 
 /* ---- device-side variants (memory and streams owned by the caller) ---- */
 

@@ -67,6 +67,11 @@ _SIGS = {
     "phg_bind_workspace": [_vp, _vp, _c.c_size_t],
     "phg_bind_stream": [_vp, _vp],
     "phg_gradient_async": [_vp, _vp, _vp],
+    "phg_get_schedule": [_vp, _c.POINTER(_c.c_int)],
+    "phg_set_time_tree": [_vp, _dp, _dp],
+    "phg_set_branch_sets": [_vp, _ip, _c.c_int],
+    "phg_time_tree_gradient": [_vp, _dp, _dp, _dp, _dp],
+    "phg_gradient_branch_sets": [_vp, _dp, _dp],
     "phg_schedule_info": [_vp, _c.POINTER(_c.c_int), _c.POINTER(_c.c_int), _c.POINTER(_c.c_int)],
     "phg_server_create": [_c.c_int, _c.c_size_t, _c.c_int, _c.POINTER(_vp)],
     "phg_server_destroy": [_vp],
@@ -231,6 +236,48 @@ def phg_bind_stream(ctx, hip_stream: int):
 
 def phg_gradient_async(ctx, d_logl: int, d_grad: int):
     _check(lib().phg_gradient_async(ctx, _vp(d_logl), _vp(d_grad)), ctx, "phg_gradient_async")
+
+
+def phg_set_time_tree(ctx, heights, rates):
+    h = _f64(heights)
+    r = _f64(rates)
+    _check(lib().phg_set_time_tree(ctx, _p(h), _p(r)), ctx, "phg_set_time_tree")
+
+
+def phg_set_branch_sets(ctx, set_of, n_sets: int):
+    if n_sets == 0:
+        _check(lib().phg_set_branch_sets(ctx, None, 0), ctx, "phg_set_branch_sets")
+        return
+    a = _i32(set_of)
+    _check(lib().phg_set_branch_sets(ctx, _p(a), int(n_sets)), ctx, "phg_set_branch_sets")
+
+
+def phg_time_tree_gradient(ctx, n_tips: int, n_sets: int = 0):
+    """Returns (logL, d_heights [2N-1], d_rates [2N-2], d_sets [n_sets] or None)."""
+    E = 2 * n_tips - 2
+    logl = ctypes.c_double()
+    dh = np.empty(E + 1)
+    dr = np.empty(E)
+    ds = np.empty(n_sets) if n_sets else None
+    _check(lib().phg_time_tree_gradient(ctx, ctypes.byref(logl), _p(dh), _p(dr),
+                                        _p(ds) if ds is not None else None), ctx,
+           "phg_time_tree_gradient")
+    return logl.value, dh, dr, ds
+
+
+def phg_gradient_branch_sets(ctx, n_sets: int):
+    """Returns (logL, d_sets [n_sets])."""
+    logl = ctypes.c_double()
+    ds = np.empty(n_sets)
+    _check(lib().phg_gradient_branch_sets(ctx, ctypes.byref(logl), _p(ds)), ctx,
+           "phg_gradient_branch_sets")
+    return logl.value, ds
+
+
+def phg_get_schedule(ctx) -> int:
+    v = ctypes.c_int()
+    _check(lib().phg_get_schedule(ctx, ctypes.byref(v)), ctx, "phg_get_schedule")
+    return v.value
 
 
 def phg_schedule_info(ctx):

@@ -17,7 +17,8 @@ namespace phg {
 // Workspace plan: byte offsets of every device buffer inside one arena.
 struct Plan {
     size_t codes, part, expo, P64, dP64, P32, dP32, TT64, dTT64, TT32, dTT32, b, V, Vinv, lam, rates, cw,
-        pi, pw, sll, lpart, gpart, out, sched, desc, total;
+        pi, pw, sll, lpart, gpart, out, sched, desc, ch_parent, ch_kids, heights, trates, set_ptr, set_idx,
+        total;
 };
 Plan make_plan(int N, int C, int S, int R, phg_precision prec);
 
@@ -29,10 +30,19 @@ enum InputBit : unsigned {
     kCat = 1u << 4,
     kTips = 1u << 5,
     kPw = 1u << 6,
+    kTime = 1u << 7,   // node heights + branch rate scalars (time tree)
+    kSets = 1u << 8,   // branch sets
     kRequired = kTopo | kB | kEig | kPi | kCat | kTips,
 };
 
 constexpr int kProfEvents = PHG_PROF_CLASSES + 1;
+
+// Doubles in the output region (device) and its pinned host mirror:
+// logL, gradient [E], d/d heights [2N-1], d/d rates [E], set sums [<= E].
+inline size_t out_doubles(int N) {
+    const size_t E = 2 * static_cast<size_t>(N) - 2;
+    return 1 + E + (E + 1) + E + E;
+}
 
 }  // namespace phg
 
@@ -44,8 +54,13 @@ struct phg_context {
 
     // host mirrors of every input
     std::vector<int32_t> parent;
+    std::vector<int32_t> kids;   // [N-1][2] children of internal node N + k
     std::vector<double> b, V, Vinv, lam, pi, rates, cw, pw;
     std::vector<uint8_t> codes;  // [N][Cpad], padding = S
+    // time tree (heights [2N-1], rate scalars [2N-2]) and branch sets (CSR)
+    std::vector<double> heights, trates;
+    std::vector<int32_t> set_ptr, set_idx;
+    int n_sets = 0;
     unsigned have = 0;           // inputs set at least once
     unsigned dirty = 0;          // inputs changed since the last upload
 
@@ -65,7 +80,7 @@ struct phg_context {
     size_t bound_ws_bytes = 0;
     hipStream_t stream = nullptr;
     bool own_stream = false;
-    double* host_out = nullptr;  // pinned (1 + E) doubles
+    double* host_out = nullptr;  // pinned, out_doubles(N)
     phg::Plan plan{};
     phg::ReqDesc rd{};           // host copy of this request's descriptor
 
@@ -107,6 +122,8 @@ phg_status ctx_ready(phg_context* ctx);
 // Device pointer of this context's descriptor and of its output region.
 ReqDesc* ctx_desc_dev(phg_context* ctx);
 double* ctx_out_dev(phg_context* ctx);
+// Allocate the pinned host mirror of the output region on first use.
+phg_status ctx_host_out(phg_context* ctx);
 // Enqueue one whole evaluation of this context alone.
 phg_status ctx_enqueue_eval(phg_context* ctx, double* d_logl, double* d_grad);
 // Forget the device binding (workspace, pinned output) so the context can be

@@ -69,9 +69,15 @@ Plan make_plan(int N, int C, int S, int R, phg_precision prec) {
     p.sll = take(static_cast<size_t>(Cpad) * 8);
     p.lpart = take(static_cast<size_t>(tiles) * 8);
     p.gpart = take(E * tiles * 8);
-    p.out = take((E + 1) * 8);
+    p.out = take(out_doubles(N) * 8);
     p.sched = take(I * sizeof(BlockRec));   // >= 2 I NodeTriples or I block records
     p.desc = take(sizeof(ReqDesc));
+    p.ch_parent = take((E + 1) * 4);
+    p.ch_kids = take(2 * I * 4);
+    p.heights = take((E + 1) * 8);
+    p.trates = take(E * 8);
+    p.set_ptr = take((E + 1) * 4);
+    p.set_idx = take(E * 4);
     p.total = off;
     return p;
 }
@@ -117,6 +123,11 @@ void build_schedule(phg_context* ctx) {
     }
     for (int v = N; v < n; ++v)
         if (c0[v] > c1[v]) std::swap(c0[v], c1[v]);
+    ctx->kids.resize(2 * static_cast<size_t>(N - 1));
+    for (int v = N; v < n; ++v) {
+        ctx->kids[2 * (v - N)] = c0[v];
+        ctx->kids[2 * (v - N) + 1] = c1[v];
+    }
     // depth by walking down from the root (iterative)
     std::vector<int> depth(n, 0), order;
     order.reserve(n);
@@ -295,6 +306,8 @@ phg_status upload(phg_context* ctx) {
     };
     if (dirty & kTopo) {
         PHG_HIP(ctx, put(pl.sched, ctx->sched.data(), ctx->sched.size() * sizeof(int32_t)));
+        PHG_HIP(ctx, put(pl.ch_parent, ctx->parent.data(), ctx->parent.size() * sizeof(int32_t)));
+        PHG_HIP(ctx, put(pl.ch_kids, ctx->kids.data(), ctx->kids.size() * sizeof(int32_t)));
         ctx->rd.blocked = ctx->blocked ? 1 : 0;
         PHG_HIP(ctx, put(pl.desc, &ctx->rd, sizeof(ReqDesc)));
     }
@@ -311,6 +324,14 @@ phg_status upload(phg_context* ctx) {
     }
     if (dirty & kTips) PHG_HIP(ctx, put(pl.codes, ctx->codes.data(), ctx->codes.size()));
     if (dirty & kPw) PHG_HIP(ctx, put(pl.pw, ctx->pw.data(), ctx->pw.size() * 8));
+    if ((dirty & kTime) && !ctx->heights.empty()) {
+        PHG_HIP(ctx, put(pl.heights, ctx->heights.data(), ctx->heights.size() * 8));
+        PHG_HIP(ctx, put(pl.trates, ctx->trates.data(), ctx->trates.size() * 8));
+    }
+    if ((dirty & kSets) && ctx->n_sets > 0) {
+        PHG_HIP(ctx, put(pl.set_ptr, ctx->set_ptr.data(), ctx->set_ptr.size() * sizeof(int32_t)));
+        PHG_HIP(ctx, put(pl.set_idx, ctx->set_idx.data(), ctx->set_idx.size() * sizeof(int32_t)));
+    }
     // pageable sources: make sure the copies have consumed them before the
     // host mirrors can change again
     if (dirty) PHG_HIP(ctx, hipStreamSynchronize(st));
@@ -380,6 +401,14 @@ void ctx_drop_device(phg_context* ctx) {
     ctx->bound_ws_bytes = 0;
     ctx->dev_init = false;
     ctx->dirty = ctx->have;
+}
+
+phg_status ctx_host_out(phg_context* ctx) {
+    if (ctx->host_out) return PHG_OK;
+    void* ho = nullptr;
+    PHG_HIP(ctx, hipHostMalloc(&ho, out_doubles(ctx->N) * sizeof(double), hipHostMallocDefault));
+    ctx->host_out = static_cast<double*>(ho);
+    return PHG_OK;
 }
 
 ReqDesc* ctx_desc_dev(phg_context* ctx) { return reinterpret_cast<ReqDesc*>(ctx->arena + ctx->plan.desc); }
@@ -495,6 +524,7 @@ phg_status phg_set_topology(phg_context* ctx, const int32_t* parent) {
     build_schedule(ctx);
     ctx->have |= kTopo;
     ctx->dirty |= kTopo;
+    ctx->have &= ~kTime;     // heights must be set again for a new topology
     return PHG_OK;
 }
 
@@ -508,6 +538,7 @@ phg_status phg_set_branch_lengths(phg_context* ctx, const double* b) {
     ctx->b.assign(b, b + E);
     ctx->have |= kB;
     ctx->dirty |= kB;
+    ctx->have &= ~kTime;     // lengths no longer come from a time tree
     return PHG_OK;
 }
 
@@ -607,12 +638,7 @@ phg_status phg_gradient(phg_context* ctx, double* logl, double* grad) {
     if (!grad) return ctx->fail(PHG_ERR_ARG, "grad is NULL");
     phg_status s = ctx_ready(ctx);
     if (s != PHG_OK) return s;
-    if (!ctx->host_out) {
-        void* ho = nullptr;
-        PHG_HIP(ctx, hipHostMalloc(&ho, (2 * static_cast<size_t>(ctx->N) - 1) * sizeof(double),
-                                   hipHostMallocDefault));
-        ctx->host_out = static_cast<double*>(ho);
-    }
+    PHG_TRY(ctx_host_out(ctx));
     double* dout = ctx_out_dev(ctx);
     s = ctx_enqueue_eval(ctx, dout, dout + 1);
     if (s != PHG_OK) return s;
@@ -685,6 +711,13 @@ phg_status phg_gradient_async(phg_context* ctx, double* d_logl, double* d_grad) 
     phg_status s = ctx_ready(ctx);
     if (s != PHG_OK) return s;
     return ctx_enqueue_eval(ctx, d_logl, d_grad);
+}
+
+phg_status phg_get_schedule(phg_context* ctx, int* schedule) {
+    if (!ctx || !schedule) return PHG_ERR_ARG;
+    if (!(ctx->have & kTopo)) return ctx->fail(PHG_ERR_STATE, "topology not set");
+    *schedule = ctx->blocked ? PHG_SCHEDULE_BLOCKS : PHG_SCHEDULE_LEVELS;
+    return PHG_OK;
 }
 
 phg_status phg_schedule_info(phg_context* ctx, int* n_post_levels, int* n_pre_levels,

@@ -114,6 +114,25 @@ constexpr int kBlockDepth = 3;
 // every in-block vector in registers.
 inline bool blocked_supported(int S, int R, bool /*fp32*/) { return S == 4 && R <= 8; }
 
+// Chain rules on a finished branch gradient (phg_chain.hip).  All pointers
+// are device pointers into the context's workspace.
+struct ChainArgs {
+    int N, n_sets;
+    const int32_t* parent;   // [2N-1], parent of the root = -1
+    const int32_t* kids;     // [N-1][2] children of internal node N + k
+    const double* heights;   // [2N-1]
+    const double* rates;     // [2N-2] branch rate scalars
+    const double* grad;      // [2N-2] d logL / d b
+    double* d_heights;       // [2N-1]
+    double* d_rates;         // [2N-2]
+    const int32_t* set_ptr;  // [n_sets + 1] CSR offsets into set_idx
+    const int32_t* set_idx;  // branches of each set, increasing
+    double* d_sets;          // [n_sets]
+};
+// time_tree: heights / rates chain rule; then, if n_sets > 0, set sums of
+// d_rates (time_tree) or of grad.
+hipError_t launch_chain(const ChainArgs& a, bool time_tree, hipStream_t stream);
+
 // MFMA level kernels for other state counts (phg_kernels_gs.hip).
 int gs_tile_patterns(bool fp32);
 hipError_t launch_level_gs(KernelClass k, const ReqDesc& shape, const ReqDesc* descs,

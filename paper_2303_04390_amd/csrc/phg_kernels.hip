@@ -34,6 +34,8 @@
 
 #include <math.h>
 
+#include <type_traits>
+
 namespace phg {
 namespace {
 
@@ -63,6 +65,20 @@ struct Vec4T<double> {
 template <typename T>
 using Vec4 = typename Vec4T<T>::type;
 typedef int Int4 __attribute__((ext_vector_type(4)));
+
+// Compile-time loop: f(IntC<i>{}) for i = B .. E-1, so the index can size
+// and select register arrays.
+template <int I>
+struct IntC {
+    static constexpr int value = I;
+};
+template <int B, int E, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+    if constexpr (B < E) {
+        f(IntC<B>{});
+        static_for<B + 1, E>(f);
+    }
+}
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -565,17 +581,25 @@ __global__ __launch_bounds__(kLanes * R) void pre_blk_kernel(const ReqDesc* __re
     }
     const double W = g(d.pw)[c];
     const T wr = static_cast<T>(g(d.cweights)[r]);
+    constexpr int kSlots = (14 + R - 1) / R;
+    T gn[kSlots], gd[kSlots];
+    int gc[kSlots];
 #pragma unroll
-    for (int pos = 1; pos <= 7; ++pos) {
+    for (int i = 0; i < kSlots; ++i) {
+        gn[i] = gd[i] = T(0);
+        gc[i] = -1;
+    }
+    static_for<1, 8>([&](auto P_) {
+        constexpr int pos = decltype(P_)::value;
         const int k = nd[pos];
-        if (k < N) continue;
+        if (k < N) return;
         const int c0 = nd[2 * pos], c1 = nd[2 * pos + 1];
         const bool in0 = c0 >= N, in1 = c1 >= N;
         const int code0 = in0 ? 0 : codes[static_cast<size_t>(c0) * Cpad + c];
         const int code1 = in1 ? 0 : codes[static_cast<size_t>(c1) * Cpad + c];
         T m0[4], m1[4], dm0[4], dm1[4], v0[4], v1[4];
         if (in0) {
-            if (2 * pos < 8) {
+            if constexpr (2 * pos < 8) {
 #pragma unroll
                 for (int u = 0; u < 4; ++u) v0[u] = p[2 * pos][u];
             } else {
@@ -591,7 +615,7 @@ __global__ __launch_bounds__(kLanes * R) void pre_blk_kernel(const ReqDesc* __re
             dm0[0] = b.x; dm0[1] = b.y; dm0[2] = b.z; dm0[3] = b.w;
         }
         if (in1) {
-            if (2 * pos + 1 < 8) {
+            if constexpr (2 * pos + 1 < 8) {
 #pragma unroll
                 for (int u = 0; u < 4; ++u) v1[u] = p[2 * pos + 1][u];
             } else {
@@ -646,7 +670,7 @@ __global__ __launch_bounds__(kLanes * R) void pre_blk_kernel(const ReqDesc* __re
             const int e = exponent_of(MX0);
 #pragma unroll
             for (int u = 0; u < 4; ++u) q0[u] = exact_ldexp(q0[u], -e);
-            if (2 * pos < 8) {
+            if constexpr (2 * pos < 8) {
 #pragma unroll
                 for (int u = 0; u < 4; ++u) q[2 * pos][u] = q0[u];
             } else {
@@ -657,36 +681,410 @@ __global__ __launch_bounds__(kLanes * R) void pre_blk_kernel(const ReqDesc* __re
             const int e = exponent_of(MX1);
 #pragma unroll
             for (int u = 0; u < 4; ++u) q1[u] = exact_ldexp(q1[u], -e);
-            if (2 * pos + 1 < 8) {
+            if constexpr (2 * pos + 1 < 8) {
 #pragma unroll
                 for (int u = 0; u < 4; ++u) q[2 * pos + 1][u] = q1[u];
             } else {
                 store_vec<T, R>(part, c1 - N, tile, tiles, r, lane, q1);
             }
         }
-        // gradient contributions: wave 0 takes child 0, wave 1 (or 0 if R == 1) child 1
-        const double dden = static_cast<double>(den);
+        // gradient ratio terms, kept for the reduction after the loop: child
+        // slot j = 2 (pos - 1) + side belongs to wave j mod R
+        {
+            constexpr int j0 = 2 * (pos - 1), j1 = j0 + 1;
+            if (j0 % R == r) {
+                gn[j0 / R] = num0;
+                gd[j0 / R] = den;
+                gc[j0 / R] = c0;
+            }
+            if (j1 % R == r) {
+                gn[j1 / R] = num1;
+                gd[j1 / R] = den;
+                gc[j1 / R] = c1;
+            }
+        }
+    });
+    // per-tile sums of W_c * num / den, all of a wave's slots in lockstep so the
+    // cross-lane reductions overlap
+    double gs[kSlots];
+#pragma unroll
+    for (int i = 0; i < kSlots; ++i)
+        gs[i] = (gc[i] >= 0 && W != 0.0) ? W * (static_cast<double>(gn[i]) / static_cast<double>(gd[i])) : 0.0;
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+#pragma unroll
+        for (int i = 0; i < kSlots; ++i) gs[i] += __shfl_xor(gs[i], off, kLanes);
+    }
+    if (lane == 0) {
+#pragma unroll
+        for (int i = 0; i < kSlots; ++i)
+            if (gc[i] >= 0) gpart[static_cast<size_t>(gc[i]) * tiles + tile] = gs[i];
+    }
+}
+
+// ------------------------------------------- blocked schedule, categories in lanes
+//
+// FP32 variant of the blocked kernels for R in {1, 2, 4, 8}: a wave holds
+// 64 / R patterns x R categories (lane = r * (64 / R) + pattern), so the
+// per-(node, pattern) reductions over categories (the shared rescale maximum,
+// the gradient's numerator and denominator sums) are cross-lane operations
+// inside the wave and the waves of a workgroup never wait for each other until
+// the final per-tile gradient sums.  The 4x4 products P v, dP v and P^T u run on
+// the matrix cores as four rank-1 steps of v_mfma_f32_4x4x1f32: each group of
+// four lanes is one 4 x 4 block whose columns are its four patterns, lane
+// (i mod 4) supplies row i of the matrix, and the result lands with the states
+// in the four accumulator registers of the pattern's own lane.
+
+typedef float F4 __attribute__((ext_vector_type(4)));
+
+// m = M v (transposed = false) or M^T v (transposed = true) for this lane's
+// pattern and category; M is the lane's row-major 4x4 matrix.
+template <bool kTransposed>
+__device__ __forceinline__ void mfma_mv(const GLOBAL float* __restrict__ M, const int lane, const float v[4],
+                                        float m[4]) {
+    const int i = lane & 3;
+    float a[4];
+    if (kTransposed) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) a[k] = M[4 * k + i];
+    } else {
+        const F4 row = *reinterpret_cast<const GLOBAL F4*>(M + 4 * i);
+        a[0] = row.x;
+        a[1] = row.y;
+        a[2] = row.z;
+        a[3] = row.w;
+    }
+    F4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) acc = __builtin_amdgcn_mfma_f32_4x4x1f32(a[k], v[k], acc, 0, 0, 0);
+    m[0] = acc.x;
+    m[1] = acc.y;
+    m[2] = acc.z;
+    m[3] = acc.w;
+}
+
+// Combine v over the R lanes of one pattern (lane xor 32, 16, 8 partners).
+// Pairs are combined with a commutative operation, so every lane of the
+// pattern ends with the bitwise-same result.
+template <int R, bool kMax>
+__device__ __forceinline__ float over_categories(float v) {
+    auto op = [](float a, float b) { return kMax ? fmaxf(a, b) : a + b; };
+    if constexpr (R >= 8) {
+        const float o = __uint_as_float(static_cast<unsigned>(
+            __builtin_amdgcn_update_dpp(0, static_cast<int>(__float_as_uint(v)), 0x128, 0xF, 0xF, false)));
+        v = op(v, o);                                   // row_ror:8 = partner lane xor 8
+    }
+    if constexpr (R >= 4) {
+        const auto s = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+        v = op(__uint_as_float(s[0]), __uint_as_float(s[1]));
+    }
+    if constexpr (R >= 2) {
+        const auto s = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+        v = op(__uint_as_float(s[0]), __uint_as_float(s[1]));
+    }
+    return v;
+}
+
+// Stored partial (or pre-order vector) of internal slot SLOT, category r, for
+// pattern PAT of the tile (same layout as child_vec / store_vec).
+__device__ __forceinline__ void lane_load(const GLOBAL float* __restrict__ part, int slot, int tile, int tiles,
+                                          int R, int r, int pat, float out[4]) {
+    const F4 q = reinterpret_cast<const GLOBAL F4*>(part)[((static_cast<size_t>(slot) * tiles + tile) * R + r) *
+                                                              kLanes + pat];
+    out[0] = q.x;
+    out[1] = q.y;
+    out[2] = q.z;
+    out[3] = q.w;
+}
+__device__ __forceinline__ void lane_store(GLOBAL float* __restrict__ part, int slot, int tile, int tiles, int R,
+                                           int r, int pat, const float v[4]) {
+    F4 q;
+    q.x = v[0];
+    q.y = v[1];
+    q.z = v[2];
+    q.w = v[3];
+    reinterpret_cast<GLOBAL F4*>(part)[((static_cast<size_t>(slot) * tiles + tile) * R + r) * kLanes + pat] = q;
+}
+
+// Tip-table row (P or dP applied to the one-hot / all-ones vector of CODE).
+__device__ __forceinline__ void tip_row(const GLOBAL float* __restrict__ TT, int x, int R, int r, int code,
+                                        float m[4]) {
+    const F4 t = reinterpret_cast<const GLOBAL F4*>(TT)[(static_cast<size_t>(x) * R + r) * 5 + code];
+    m[0] = t.x;
+    m[1] = t.y;
+    m[2] = t.z;
+    m[3] = t.w;
+}
+
+// In-block post-order over heap positions 7..LO for this lane's (category,
+// pattern).  With kExpo, returns the sum of exponents taken (in-block nodes and
+// frontier block roots); otherwise exponents are not read.
+template <int R, int LO, bool kExpo>
+__device__ __forceinline__ int bmf_postorder(const int (&nd)[16], const int r, const int tile, const int tiles,
+                                             const int N, const int Cpad, const int lane, const int pat,
+                                             const GLOBAL uint8_t* __restrict__ codes,
+                                             const GLOBAL float* __restrict__ part,
+                                             const GLOBAL int32_t* __restrict__ expo,
+                                             const GLOBAL float* __restrict__ P, const GLOBAL float* __restrict__ TT,
+                                             float (&p)[8][4]) {
+    const int c = tile * kLanes + pat;
+    int esum = 0;
+    static_for<0, 8 - LO>([&](auto I_) {
+        constexpr int pos = 7 - decltype(I_)::value;
+        const int k = nd[pos];
+        if (k < N) return;
+        float m[2][4];
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            const int cp = 2 * pos + s;
+            const int cn = nd[cp];
+            if (cn < N) {
+                tip_row(TT, cn, R, r, codes[static_cast<size_t>(cn) * Cpad + c], m[s]);
+            } else {
+                float v[4];
+                if (cp < 8) {
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) v[u] = p[cp < 8 ? cp : 0][u];
+                } else {
+                    lane_load(part, cn - N, tile, tiles, R, r, pat, v);
+                    if (kExpo) esum += expo[static_cast<size_t>(cn - N) * Cpad + c];
+                }
+                mfma_mv<false>(P + (static_cast<size_t>(cn) * R + r) * 16, lane, v, m[s]);
+            }
+        }
+        float lmx = 0.0f;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            p[pos][u] = m[0][u] * m[1][u];
+            lmx = fmaxf(lmx, p[pos][u]);
+        }
+        const int e = exponent_of(over_categories<R, true>(lmx));
+#pragma unroll
+        for (int u = 0; u < 4; ++u) p[pos][u] = exact_ldexp(p[pos][u], -e);
+        esum += e;
+    });
+    return esum;
+}
+
+template <int R>
+__global__ __launch_bounds__(kLanes * R) __attribute__((amdgpu_waves_per_eu(4))) void post_bmf_kernel(const ReqDesc* __restrict__ descs,
+                                                              const SegTable segs) {
+    constexpr int PW = kLanes / R;                      // patterns per wave
+    __shared__ double sw[R];
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & (kLanes - 1);
+    const int r = lane / PW;
+    const int pat = w * PW + lane % PW;
+    const int unit = blockIdx.x;
+    if (unit >= segs.unit_begin[segs.n]) return;
+    const int sidx = find_segment(segs, unit);
+    const Segment sg = segs.seg[sidx];
+    const ReqDesc& d = descs[sg.desc];
+    const int tiles = d.tiles, N = d.N, Cpad = d.Cpad;
+    const int local = unit - segs.unit_begin[sidx];
+    const int bix = local / tiles;
+    const int tile = local - bix * tiles;
+    const GLOBAL int32_t* heap =
+        reinterpret_cast<const GLOBAL int32_t*>(g(d.sched)) + static_cast<size_t>(sg.sched_off + bix) * 16;
+    int nd[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) nd[i] = heap[i];
+    GLOBAL float* part = g(part_of<float>(d));
+    GLOBAL int32_t* expo = g(d.expo);
+    const int c = tile * kLanes + pat;
+    float p[8][4];
+    const int ek = bmf_postorder<R, 1, true>(nd, r, tile, tiles, N, Cpad, lane, pat, g(d.codes), part, expo,
+                                             g(d.P32), g(d.TT32), p);
+    if (!(sg.flags & 1)) {
+        lane_store(part, nd[1] - N, tile, tiles, R, r, pat, p[1]);
+        if (r == 0) expo[static_cast<size_t>(nd[1] - N) * Cpad + c] = ek;
+        return;
+    }
+    // the tree root: log site likelihood and this tile's weighted sum
+    const GLOBAL double* pi = g(d.pi);
+    double acc = 0.0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc += pi[u] * static_cast<double>(p[1][u]);
+    double site = g(d.cweights)[r] * acc;
+#pragma unroll
+    for (int off = kLanes / 2; off >= PW; off >>= 1) site += __shfl_xor(site, off, kLanes);
+    double contrib = 0.0;
+    if (r == 0) {
+        const double ll = (site > 0.0 ? log(site) : -INFINITY) + static_cast<double>(ek) * 0.69314718055994530942;
+        g(d.sll)[c] = ll;
+        const double W = g(d.pw)[c];
+        contrib = W != 0.0 ? W * ll : 0.0;
+    }
+    const double ws = wave_sum(contrib);
+    if (lane == 0) sw[w] = ws;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+#pragma unroll
+        for (int i = 0; i < R; ++i) t += sw[i];
+        g(d.lpart)[tile] = t;
+    }
+}
+
+template <int R>
+__global__ __launch_bounds__(kLanes * R) __attribute__((amdgpu_waves_per_eu(4))) void pre_bmf_kernel(const ReqDesc* __restrict__ descs,
+                                                             const SegTable segs) {
+    constexpr int PW = kLanes / R;
+    __shared__ float gnum[14][kLanes];                  // per child slot: sum_r w_r u . dm
+    __shared__ float gden[7][kLanes];                   // per position: sum_r w_r u . m
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & (kLanes - 1);
+    const int r = lane / PW;
+    const int pat = w * PW + lane % PW;
+    const int unit = blockIdx.x;
+    if (unit >= segs.unit_begin[segs.n]) return;
+    const int sidx = find_segment(segs, unit);
+    const Segment sg = segs.seg[sidx];
+    const ReqDesc& d = descs[sg.desc];
+    const int tiles = d.tiles, N = d.N, Cpad = d.Cpad;
+    const int local = unit - segs.unit_begin[sidx];
+    const int bix = local / tiles;
+    const int tile = local - bix * tiles;
+    const GLOBAL int32_t* heap =
+        reinterpret_cast<const GLOBAL int32_t*>(g(d.sched)) + static_cast<size_t>(sg.sched_off + bix) * 16;
+    int nd[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) nd[i] = heap[i];
+    GLOBAL float* part = g(part_of<float>(d));
+    const GLOBAL uint8_t* codes = g(d.codes);
+    const GLOBAL float* P = g(d.P32);
+    const GLOBAL float* dP = g(d.dP32);
+    const GLOBAL float* TT = g(d.TT32);
+    const GLOBAL float* dTT = g(d.dTT32);
+    const int c = tile * kLanes + pat;
+    float p[8][4];
+    (void)bmf_postorder<R, 2, false>(nd, r, tile, tiles, N, Cpad, lane, pat, codes, part, nullptr, P, TT, p);
+    float q[8][4];
+    if (nd[1] == 2 * N - 2) {
+        const GLOBAL double* pi = g(d.pi);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) q[1][u] = static_cast<float>(pi[u]);
+    } else {
+        lane_load(part, nd[1] - N, tile, tiles, R, r, pat, q[1]);
+    }
+    const float wr = static_cast<float>(g(d.cweights)[r]);
+    static_for<1, 8>([&](auto P_) {
+        constexpr int pos = decltype(P_)::value;
+        const int k = nd[pos];
+        if (k < N) return;
+        float m[2][4], dm[2][4];
+        bool in[2];
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            const int cp = 2 * pos + s;
+            const int cn = nd[cp];
+            in[s] = cn >= N;
+            if (!in[s]) {
+                const int code = codes[static_cast<size_t>(cn) * Cpad + c];
+                tip_row(TT, cn, R, r, code, m[s]);
+                tip_row(dTT, cn, R, r, code, dm[s]);
+            } else {
+                float v[4];
+                if (cp < 8) {
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) v[u] = p[cp < 8 ? cp : 0][u];
+                } else {
+                    lane_load(part, cn - N, tile, tiles, R, r, pat, v);
+                }
+                const size_t mo = (static_cast<size_t>(cn) * R + r) * 16;
+                mfma_mv<false>(P + mo, lane, v, m[s]);
+                mfma_mv<false>(dP + mo, lane, v, dm[s]);
+            }
+        }
+        float uu[2][4], a0 = 0.0f, a1 = 0.0f, dd = 0.0f;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            uu[0][u] = q[pos][u] * m[1][u];
+            uu[1][u] = q[pos][u] * m[0][u];
+            a0 += uu[0][u] * dm[0][u];
+            a1 += uu[1][u] * dm[1][u];
+            dd += uu[0][u] * m[0][u];
+        }
+        const float num0 = over_categories<R, false>(wr * a0);
+        const float num1 = over_categories<R, false>(wr * a1);
+        const float den = over_categories<R, false>(wr * dd);
         if (r == 0) {
-            const double g0 = (W != 0.0) ? W * (static_cast<double>(num0) / dden) : 0.0;
-            const double s0 = wave_sum(g0);
-            if (lane == 0) gpart[static_cast<size_t>(c0) * tiles + tile] = s0;
+            gnum[2 * pos - 2][pat] = num0;
+            gnum[2 * pos - 1][pat] = num1;
+            gden[pos - 1][pat] = den;
         }
-        if (r == (R > 1 ? 1 : 0)) {
-            const double g1 = (W != 0.0) ? W * (static_cast<double>(num1) / dden) : 0.0;
-            const double s1 = wave_sum(g1);
-            if (lane == 0) gpart[static_cast<size_t>(c1) * tiles + tile] = s1;
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            if (!in[s]) continue;
+            const int cp = 2 * pos + s;
+            const int cn = nd[cp];
+            float qn[4];
+            mfma_mv<true>(P + (static_cast<size_t>(cn) * R + r) * 16, lane, uu[s], qn);
+            float mx = 0.0f;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) mx = fmaxf(mx, qn[u]);
+            const int e = exponent_of(over_categories<R, true>(mx));
+#pragma unroll
+            for (int u = 0; u < 4; ++u) qn[u] = exact_ldexp(qn[u], -e);
+            if (cp < 8) {
+#pragma unroll
+                for (int u = 0; u < 4; ++u) q[cp < 8 ? cp : 0][u] = qn[u];
+            } else {
+                lane_store(part, cn - N, tile, tiles, R, r, pat, qn);
+            }
         }
+    });
+    __syncthreads();
+    // per-tile sums of W_c num / den: wave w takes child slots j = w, w + R, ...;
+    // lane = pattern of the tile; all of a wave's slots reduce in lockstep
+    constexpr int kSlots = (14 + R - 1) / R;
+    const double W = g(d.pw)[tile * kLanes + lane];
+    double gs[kSlots];
+    int gc[kSlots];
+#pragma unroll
+    for (int i = 0; i < kSlots; ++i) {
+        const int j = i * R + w;
+        gc[i] = -1;
+        gs[i] = 0.0;
+        if (j < 14 && heap[j / 2 + 1] >= N) {
+            gc[i] = heap[j + 2];
+            if (W != 0.0)
+                gs[i] = W * (static_cast<double>(gnum[j][lane]) / static_cast<double>(gden[j / 2][lane]));
+        }
+    }
+    // at most four slots in flight at a time (register pressure for small R)
+#pragma unroll
+    for (int i0 = 0; i0 < kSlots; i0 += 4) {
+#pragma unroll
+        for (int off = kLanes / 2; off >= 1; off >>= 1) {
+#pragma unroll
+            for (int i = i0; i < (i0 + 4 < kSlots ? i0 + 4 : kSlots); ++i) gs[i] += __shfl_xor(gs[i], off, kLanes);
+        }
+    }
+    if (lane == 0) {
+        GLOBAL double* gpart = g(d.gpart);
+#pragma unroll
+        for (int i = 0; i < kSlots; ++i)
+            if (gc[i] >= 0) gpart[static_cast<size_t>(gc[i]) * tiles + tile] = gs[i];
     }
 }
 
 // ---------------------------------------------------------------- P(t), dP/dt
 
-// Small S (<= 8): one thread per (branch, category) pair builds the whole
-// S x S pair of matrices.  Units are pairs; a block covers 256 of them.
-template <int S>
-__global__ __launch_bounds__(256) void pmat_small_kernel(const ReqDesc* __restrict__ descs,
-                                                         const SegTable segs) {
-    const int unit = blockIdx.x * 256 + threadIdx.x;
+// S = 4: one thread per row s of one (branch, category) pair, so a pair's
+// four rows come from four neighbouring lanes (contiguous stores) and even a
+// small tree spreads over many workgroups.  Row s of P and dP:
+//   P[s][u] = sum_k V[s][k] Vinv[k][u] exp(gamma b lam_k),
+//   dP[s][u] = sum_k V[s][k] Vinv[k][u] gamma lam_k exp(gamma b lam_k).
+// Also the tip tables: entry y < 4 is column y of P (P e_y), entry 4 the row
+// sums (P 1, a fully ambiguous tip); component s comes from row s.
+constexpr int kPmatBlock = 64;
+__global__ __launch_bounds__(kPmatBlock) void pmat4_kernel(const ReqDesc* __restrict__ descs,
+                                                           const SegTable segs) {
+    constexpr int S = 4;
+    const int gid = blockIdx.x * kPmatBlock + threadIdx.x;
+    const int unit = gid >> 2;
+    const int s = gid & 3;
     if (unit >= segs.unit_begin[segs.n]) return;
     int sidx = 0;
     while (sidx + 1 < segs.n && unit >= segs.unit_begin[sidx + 1]) ++sidx;
@@ -704,54 +1102,42 @@ __global__ __launch_bounds__(256) void pmat_small_kernel(const ReqDesc* __restri
         ex[k] = e;
         dex[k] = g * d.lam[k] * e;
     }
-    const size_t base = static_cast<size_t>(pair) * S * S;
-    double Pm[S][S], dPm[S][S];
+    const size_t base = static_cast<size_t>(pair) * S * S + s * S;
+    double Pr[S], dPr[S], rs = 0.0, drs = 0.0;
 #pragma unroll
-    for (int s = 0; s < S; ++s) {
+    for (int u = 0; u < S; ++u) {
+        double acc = 0.0, dacc = 0.0;
+#pragma unroll
+        for (int k = 0; k < S; ++k) {
+            const double v = d.V[s * S + k] * d.Vinv[k * S + u];
+            acc += v * ex[k];
+            dacc += v * dex[k];
+        }
+        Pr[u] = acc;
+        dPr[u] = dacc;
+        rs += acc;
+        drs += dacc;
+    }
+    const size_t tb = static_cast<size_t>(pair) * 20 + s;
+#pragma unroll
+    for (int u = 0; u < S; ++u) {
+        d.P64[base + u] = Pr[u];
+        d.dP64[base + u] = dPr[u];
+        d.TT64[tb + 4 * u] = Pr[u];
+        d.dTT64[tb + 4 * u] = dPr[u];
+    }
+    d.TT64[tb + 16] = rs;
+    d.dTT64[tb + 16] = drs;
+    if (d.fp32) {
 #pragma unroll
         for (int u = 0; u < S; ++u) {
-            double acc = 0.0, dacc = 0.0;
-#pragma unroll
-            for (int k = 0; k < S; ++k) {
-                const double v = d.V[s * S + k] * d.Vinv[k * S + u];
-                acc += v * ex[k];
-                dacc += v * dex[k];
-            }
-            Pm[s][u] = acc;
-            dPm[s][u] = dacc;
-            d.P64[base + s * S + u] = acc;
-            d.dP64[base + s * S + u] = dacc;
-            if (d.fp32) {
-                d.P32[base + s * S + u] = static_cast<float>(acc);
-                d.dP32[base + s * S + u] = static_cast<float>(dacc);
-            }
+            d.P32[base + u] = static_cast<float>(Pr[u]);
+            d.dP32[base + u] = static_cast<float>(dPr[u]);
+            d.TT32[tb + 4 * u] = static_cast<float>(Pr[u]);
+            d.dTT32[tb + 4 * u] = static_cast<float>(dPr[u]);
         }
-    }
-    if (S == 4) {
-        // tip tables: entry y < 4 is column y (P e_y), entry 4 the row sums (P 1)
-        const size_t tb = static_cast<size_t>(pair) * 20;
-#pragma unroll
-        for (int y = 0; y <= S; ++y)
-#pragma unroll
-            for (int s = 0; s < S; ++s) {
-                double v = 0.0, dv = 0.0;
-                if (y < S) {
-                    v = Pm[s][y];
-                    dv = dPm[s][y];
-                } else {
-#pragma unroll
-                    for (int u = 0; u < S; ++u) {
-                        v += Pm[s][u];
-                        dv += dPm[s][u];
-                    }
-                }
-                d.TT64[tb + 4 * y + s] = v;
-                d.dTT64[tb + 4 * y + s] = dv;
-                if (d.fp32) {
-                    d.TT32[tb + 4 * y + s] = static_cast<float>(v);
-                    d.dTT32[tb + 4 * y + s] = static_cast<float>(dv);
-                }
-            }
+        d.TT32[tb + 16] = static_cast<float>(rs);
+        d.dTT32[tb + 16] = static_cast<float>(drs);
     }
 }
 
@@ -829,6 +1215,15 @@ template <typename T, int R>
 hipError_t level_r(KernelClass k, bool blocked, const ReqDesc* descs, const SegTable& t, hipStream_t st) {
     const int n_units = t.unit_begin[t.n];
     const int blocks = (n_units + kWavesPerBlock - 1) / kWavesPerBlock;
+    if constexpr (std::is_same<T, float>::value && (R & (R - 1)) == 0) {
+        if (blocked) {
+            if (k == kPost)
+                hipLaunchKernelGGL((post_bmf_kernel<R>), dim3(n_units), dim3(kLanes * R), 0, st, descs, t);
+            else
+                hipLaunchKernelGGL((pre_bmf_kernel<R>), dim3(n_units), dim3(kLanes * R), 0, st, descs, t);
+            return hipGetLastError();
+        }
+    }
     if (blocked) {
         if (k == kPost)
             hipLaunchKernelGGL((post_blk_kernel<T, R>), dim3(n_units), dim3(kLanes * R), 0, st, descs, t);
@@ -883,8 +1278,8 @@ hipError_t launch_class(KernelClass k, const ReqDesc& shape, const ReqDesc* desc
     switch (k) {
         case kPmat:
             if (shape.S == 4) {
-                hipLaunchKernelGGL((pmat_small_kernel<4>), dim3((n_units + 255) / 256), dim3(256), 0, st,
-                                   descs, t);
+                hipLaunchKernelGGL(pmat4_kernel, dim3((4 * n_units + kPmatBlock - 1) / kPmatBlock),
+                                   dim3(kPmatBlock), 0, st, descs, t);
             } else {
                 hipLaunchKernelGGL(pmat_block_kernel, dim3(n_units), dim3(256), 0, st, descs, t);
             }

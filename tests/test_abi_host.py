@@ -180,7 +180,9 @@ def test_block_schedule_shape():
     try:
         B.phg_set_topology(ctx, parent)
         post_b, pre_b, _ = B.phg_schedule_info(ctx)        # AUTO -> blocks for 4 states
+        assert B.phg_get_schedule(ctx) == B.PHG_SCHEDULE_BLOCKS
         B.phg_set_schedule(ctx, B.PHG_SCHEDULE_LEVELS)
+        assert B.phg_get_schedule(ctx) == B.PHG_SCHEDULE_LEVELS
         post_l, pre_l, _ = B.phg_schedule_info(ctx)
         assert post_b == pre_b and post_b < post_l / 2 and pre_b < pre_l / 2
         B.phg_set_schedule(ctx, B.PHG_SCHEDULE_BLOCKS)
@@ -190,6 +192,11 @@ def test_block_schedule_shape():
     ctx = B.phg_create(50, 10, 20, 4, B.PHG_FP32_SCALED, 0)
     try:
         with pytest.raises(B.PhgError) as e:
+            B.phg_get_schedule(ctx)                        # no topology yet
+        assert e.value.status == B.PHG_ERR_STATE
+        B.phg_set_topology(ctx, synth.yule_topology(50, np.random.default_rng(1)))
+        assert B.phg_get_schedule(ctx) == B.PHG_SCHEDULE_LEVELS   # 20 states: levels only
+        with pytest.raises(B.PhgError) as e:
             B.phg_set_schedule(ctx, B.PHG_SCHEDULE_BLOCKS)
         assert e.value.status == B.PHG_ERR_ARG
     finally:
@@ -198,5 +205,56 @@ def test_block_schedule_shape():
     try:
         with pytest.raises(B.PhgError):
             B.phg_set_schedule(ctx, B.PHG_SCHEDULE_BLOCKS)
+    finally:
+        B.phg_destroy(ctx)
+
+
+def test_time_tree_and_branch_set_validation():
+    N = 6
+    parent = synth.yule_topology(N, np.random.default_rng(2))
+    heights, rates = synth.time_tree(parent, np.random.default_rng(3))
+    ctx = B.phg_create(N, 10, 4, 4, B.PHG_FP64, 0)
+    try:
+        with pytest.raises(B.PhgError) as e:
+            B.phg_set_time_tree(ctx, heights, rates)            # no topology yet
+        assert e.value.status == B.PHG_ERR_STATE
+        B.phg_set_topology(ctx, parent)
+        bad = heights.copy()
+        bad[0] = heights[parent[0]] + 1.0                       # tip above its parent
+        with pytest.raises(B.PhgError) as e:
+            B.phg_set_time_tree(ctx, bad, rates)
+        assert e.value.status == B.PHG_ERR_ARG and "above its parent" in str(e.value)
+        r = rates.copy()
+        r[3] = -0.1
+        with pytest.raises(B.PhgError):
+            B.phg_set_time_tree(ctx, heights, r)
+        r[3] = np.nan
+        with pytest.raises(B.PhgError):
+            B.phg_set_time_tree(ctx, heights, r)
+        with pytest.raises(B.PhgError) as e:
+            B.phg_time_tree_gradient(ctx, N)                     # no time tree
+        assert e.value.status == B.PHG_ERR_STATE
+        B.phg_set_time_tree(ctx, heights, rates)
+        with pytest.raises(B.PhgError) as e:
+            B.phg_time_tree_gradient(ctx, N, n_sets=2)           # sets wanted, none set
+        assert e.value.status == B.PHG_ERR_STATE
+        B.phg_set_branch_lengths(ctx, np.full(2 * N - 2, 0.1))  # leaves time-tree mode
+        with pytest.raises(B.PhgError) as e:
+            B.phg_time_tree_gradient(ctx, N)
+        assert e.value.status == B.PHG_ERR_STATE
+        E = 2 * N - 2
+        with pytest.raises(B.PhgError) as e:
+            B.phg_set_branch_sets(ctx, np.full(E, 2, np.int32), 2)   # entry out of range
+        assert e.value.status == B.PHG_ERR_ARG
+        with pytest.raises(B.PhgError):
+            B.phg_set_branch_sets(ctx, np.zeros(E, np.int32), E + 1)
+        with pytest.raises(B.PhgError) as e:
+            B.phg_gradient_branch_sets(ctx, 2)                   # no sets
+        assert e.value.status == B.PHG_ERR_STATE
+        B.phg_set_branch_sets(ctx, np.arange(E, dtype=np.int32) % 2, 2)
+        B.phg_set_branch_sets(ctx, None, 0)                      # clear
+        with pytest.raises(B.PhgError) as e:
+            B.phg_gradient_branch_sets(ctx, 2)
+        assert e.value.status == B.PHG_ERR_STATE
     finally:
         B.phg_destroy(ctx)
