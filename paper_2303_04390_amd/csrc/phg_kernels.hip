@@ -726,178 +726,326 @@ __global__ __launch_bounds__(kLanes * R) void pre_blk_kernel(const ReqDesc* __re
 //
 // FP32 variant of the blocked kernels for R in {1, 2, 4, 8}: a wave holds
 // 64 / R patterns x R categories (lane = r * (64 / R) + pattern), so the
-// per-(node, pattern) reductions over categories (the shared rescale maximum,
-// the gradient's numerator and denominator sums) are cross-lane operations
-// inside the wave and the waves of a workgroup never wait for each other until
-// the final per-tile gradient sums.  The 4x4 products P v, dP v and P^T u run on
-// the matrix cores as four rank-1 steps of v_mfma_f32_4x4x1f32: each group of
-// four lanes is one 4 x 4 block whose columns are its four patterns, lane
-// (i mod 4) supplies row i of the matrix, and the result lands with the states
-// in the four accumulator registers of the pattern's own lane.
+// shared per-(node, pattern) rescale maximum over categories is a cross-lane
+// operation inside the wave.  The 4x4 products P v, dP v and P^T u run on the
+// matrix cores as four rank-1 steps of v_mfma_f32_4x4x1f32: each group of four
+// lanes is one 4 x 4 block whose columns are its four patterns, lane (i mod 4)
+// supplies row i of the matrix, and the result lands with the states in the
+// four accumulator registers of the pattern's own lane.
+//
+// Latency: a prologue stages the matrices of the block's (up to 14) child
+// branches in LDS, each row padded to 8 floats with its row sum in column 4
+// (P 1, the vector of a fully ambiguous tip), and packs the block's tip codes
+// of the lane's pattern into two registers.  After one barrier every matrix
+// row, column or tip vector is an LDS read; the only global loads left in the
+// per-node chain are stored partials of frontier block roots.
 
 typedef float F4 __attribute__((ext_vector_type(4)));
 
-// m = M v (transposed = false) or M^T v (transposed = true) for this lane's
-// pattern and category; M is the lane's row-major 4x4 matrix.
-template <bool kTransposed>
-__device__ __forceinline__ void mfma_mv(const GLOBAL float* __restrict__ M, const int lane, const float v[4],
-                                        float m[4]) {
-    const int i = lane & 3;
-    float a[4];
-    if (kTransposed) {
-#pragma unroll
-        for (int k = 0; k < 4; ++k) a[k] = M[4 * k + i];
-    } else {
-        const F4 row = *reinterpret_cast<const GLOBAL F4*>(M + 4 * i);
-        a[0] = row.x;
-        a[1] = row.y;
-        a[2] = row.z;
-        a[3] = row.w;
-    }
-    F4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-    for (int k = 0; k < 4; ++k) acc = __builtin_amdgcn_mfma_f32_4x4x1f32(a[k], v[k], acc, 0, 0, 0);
-    m[0] = acc.x;
-    m[1] = acc.y;
-    m[2] = acc.z;
-    m[3] = acc.w;
+// LDS image of one branch-category matrix: rows of 8 floats, columns 0..3
+// the matrix, column 4 the row sum.
+constexpr int kRow = 8;
+constexpr int kMat = 4 * kRow;
+
+template <int R, int NM>
+struct BmfMats {
+    float m[14][R][NM][kMat];     // [child position - 2][category][P, dP][row][col]
+};
+
+// Per-lane constants of the categories-in-lanes layout.
+struct BmfLane {
+    int r;             // category
+    int pat;           // pattern within the 64-pattern tile
+    uint32_t part;     // byte offset of (r, pat) inside one (slot, tile) chunk of R * 64 float4
+    int i;             // row / column this lane supplies to a 4x4 MFMA block
+};
+
+template <int R>
+__device__ __forceinline__ BmfLane bmf_lane(int w, int lane) {
+    constexpr int PW = kLanes / R;
+    BmfLane L;
+    L.r = lane / PW;
+    L.pat = w * PW + lane % PW;
+    L.part = static_cast<uint32_t>(L.r * kLanes + L.pat) * 16u;
+    L.i = lane & 3;
+    return L;
 }
 
-// Combine v over the R lanes of one pattern (lane xor 32, 16, 8 partners).
-// Pairs are combined with a commutative operation, so every lane of the
-// pattern ends with the bitwise-same result.
-template <int R, bool kMax>
-__device__ __forceinline__ float over_categories(float v) {
-    auto op = [](float a, float b) { return kMax ? fmaxf(a, b) : a + b; };
-    if constexpr (R >= 8) {
-        const float o = __uint_as_float(static_cast<unsigned>(
-            __builtin_amdgcn_update_dpp(0, static_cast<int>(__float_as_uint(v)), 0x128, 0xF, 0xF, false)));
-        v = op(v, o);                                   // row_ror:8 = partner lane xor 8
-    }
-    if constexpr (R >= 4) {
-        const auto s = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
-        v = op(__uint_as_float(s[0]), __uint_as_float(s[1]));
-    }
-    if constexpr (R >= 2) {
-        const auto s = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
-        v = op(__uint_as_float(s[0]), __uint_as_float(s[1]));
-    }
-    return v;
+// Uniform base of the (slot, tile) chunk of the partials, as bytes.
+template <int R>
+__device__ __forceinline__ GLOBAL char* chunk(GLOBAL F4* part, unsigned slot, unsigned tile, unsigned tiles) {
+    return reinterpret_cast<GLOBAL char*>(part) +
+           (static_cast<size_t>(slot) * tiles + tile) * (static_cast<size_t>(R) * kLanes * 16);
 }
 
-// Stored partial (or pre-order vector) of internal slot SLOT, category r, for
-// pattern PAT of the tile (same layout as child_vec / store_vec).
-__device__ __forceinline__ void lane_load(const GLOBAL float* __restrict__ part, int slot, int tile, int tiles,
-                                          int R, int r, int pat, float out[4]) {
-    const F4 q = reinterpret_cast<const GLOBAL F4*>(part)[((static_cast<size_t>(slot) * tiles + tile) * R + r) *
-                                                              kLanes + pat];
+__device__ __forceinline__ void f4_to(const F4 q, float out[4]) {
     out[0] = q.x;
     out[1] = q.y;
     out[2] = q.z;
     out[3] = q.w;
 }
-__device__ __forceinline__ void lane_store(GLOBAL float* __restrict__ part, int slot, int tile, int tiles, int R,
-                                           int r, int pat, const float v[4]) {
+__device__ __forceinline__ F4 to_f4(const float v[4]) {
     F4 q;
     q.x = v[0];
     q.y = v[1];
     q.z = v[2];
     q.w = v[3];
-    reinterpret_cast<GLOBAL F4*>(part)[((static_cast<size_t>(slot) * tiles + tile) * R + r) * kLanes + pat] = q;
+    return q;
 }
 
-// Tip-table row (P or dP applied to the one-hot / all-ones vector of CODE).
-__device__ __forceinline__ void tip_row(const GLOBAL float* __restrict__ TT, int x, int R, int r, int code,
-                                        float m[4]) {
-    const F4 t = reinterpret_cast<const GLOBAL F4*>(TT)[(static_cast<size_t>(x) * R + r) * 5 + code];
-    m[0] = t.x;
-    m[1] = t.y;
-    m[2] = t.z;
-    m[3] = t.w;
+// v with lane J replaced by the wave-uniform value X (v_writelane_b32; X is
+// moved to a scalar register first).
+__device__ __forceinline__ int write_lane(int v, int x, const int j) {
+    const int xs = __builtin_amdgcn_readfirstlane(x);
+    asm volatile("v_writelane_b32 %0, %1, %2" : "+v"(v) : "s"(xs), "i"(j));
+    return v;
+}
+
+// Stage the matrices (NM = 1: P; NM = 2: P and dP) of every child branch of
+// the block in LDS, with row sums.  All threads of the workgroup take part,
+// every row load of a thread in flight at once; the caller synchronises.
+template <int R, int NM>
+__device__ __forceinline__ void stage_mats(BmfMats<R, NM>& S, const int (&nd)[16],
+                                           const GLOBAL float* __restrict__ P, const GLOBAL float* __restrict__ dP) {
+    // lanes 0..15 of every wave hold the heap record (from the wave-uniform
+    // copy, no memory access); a thread's child index comes from there by a
+    // cross-lane permute
+    int ndv = 0;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) ndv = write_lane(ndv, nd[j], j);
+    constexpr int kItems = 14 * R * NM * 4;          // one matrix row each
+    constexpr int kThreads = kLanes * R;
+    constexpr int kIters = (kItems + kThreads - 1) / kThreads;
+    F4 row[kIters];
+#pragma unroll
+    for (int k = 0; k < kIters; ++k) {
+        const int it = min(static_cast<int>(threadIdx.x) + k * kThreads, kItems - 1);
+        const int u = it & 3;
+        const int mm = (it >> 2) % NM;
+        const int r = (it / (4 * NM)) % R;
+        const int ch = it / (4 * NM * R);
+        const int cn = max(__builtin_amdgcn_ds_bpermute((ch + 2) << 2, ndv), 0);   // absent: branch 0, never read
+        row[k] = *reinterpret_cast<const GLOBAL F4*>((mm == 0 ? P : dP) + (static_cast<size_t>(cn) * R + r) * 16 +
+                                                     u * 4);
+    }
+#pragma unroll
+    for (int k = 0; k < kIters; ++k) {
+        const int it = static_cast<int>(threadIdx.x) + k * kThreads;
+        if (it >= kItems) continue;
+        const int u = it & 3;
+        const int mm = (it >> 2) % NM;
+        const int r = (it / (4 * NM)) % R;
+        const int ch = it / (4 * NM * R);
+        float* dst = &S.m[ch][r][mm][u * kRow];
+        dst[0] = row[k].x;
+        dst[1] = row[k].y;
+        dst[2] = row[k].z;
+        dst[3] = row[k].w;
+        dst[4] = ((row[k].x + row[k].y) + row[k].z) + row[k].w;
+    }
+}
+
+// The tip codes (0..4) of this lane's pattern for child positions 2..15,
+// four bits each: positions 2..9 in word 0, 10..15 in word 1.
+__device__ __forceinline__ void load_codes(const int (&nd)[16], const int N, const int Cpad, const int c,
+                                           const GLOBAL uint8_t* __restrict__ codes, uint32_t (&pk)[2]) {
+    // all fourteen loads are issued unconditionally (a non-tip reads tip 0's
+    // row) so that they are in flight together; the selection comes after
+    uint32_t cd[14];
+#pragma unroll
+    for (int cp = 2; cp < 16; ++cp) {
+        const int cn = nd[cp];
+        const size_t row = (cn >= 0 && cn < N) ? static_cast<size_t>(cn) : 0;
+        cd[cp - 2] = codes[row * Cpad + c];
+    }
+    pk[0] = pk[1] = 0;
+#pragma unroll
+    for (int j = 0; j < 14; ++j) {
+        const int cn = nd[j + 2];
+        if (cn >= 0 && cn < N) pk[j >> 3] |= cd[j] << (4 * (j & 7));
+    }
+}
+__device__ __forceinline__ int code_at(const uint32_t (&pk)[2], int cp) {
+    const int j = cp - 2;
+    return static_cast<int>((pk[j >> 3] >> (4 * (j & 7))) & 15u);
+}
+
+// Column CODE of a staged matrix (P e_code, or the row sums for code 4).
+__device__ __forceinline__ void lds_column(const float* M, int code, float m[4]) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) m[u] = M[u * kRow + code];
+}
+
+// m = M v (kTransposed = false) or M^T v (true) on the matrix cores for this
+// lane's pattern; M is the staged matrix of the lane's category.
+template <bool kTransposed>
+__device__ __forceinline__ void mfma_mv(const float* M, const BmfLane& L, const float v[4], float m[4]) {
+    float a[4];
+    if (kTransposed) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) a[k] = M[k * kRow + L.i];
+    } else {
+        f4_to(*reinterpret_cast<const F4*>(M + L.i * kRow), a);
+    }
+    F4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) acc = __builtin_amdgcn_mfma_f32_4x4x1f32(a[k], v[k], acc, 0, 0, 0);
+    f4_to(acc, m);
+}
+
+// Maximum over the R lanes of one pattern (lane xor 32, 16, 8 partners) of
+// values >= 0 given as their bit patterns: for IEEE floats >= 0 the signed
+// integer order is the float order, and any negative rounding residue (a
+// negative bit pattern) loses to a non-negative one.  Every lane of the
+// pattern ends with the same value.
+template <int R>
+__device__ __forceinline__ int max_over_categories(int v) {
+    if constexpr (R >= 8) v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x128, 0xF, 0xF, false));  // row_ror:8
+    if constexpr (R >= 4) {
+        const auto s = __builtin_amdgcn_permlane16_swap(static_cast<unsigned>(v), static_cast<unsigned>(v),
+                                                        false, false);
+        v = max(static_cast<int>(s[0]), static_cast<int>(s[1]));
+    }
+    if constexpr (R >= 2) {
+        const auto s = __builtin_amdgcn_permlane32_swap(static_cast<unsigned>(v), static_cast<unsigned>(v),
+                                                        false, false);
+        v = max(static_cast<int>(s[0]), static_cast<int>(s[1]));
+    }
+    return v;
+}
+
+// Sum over the R lanes of one pattern; pairs are combined commutatively, so
+// every lane of the pattern ends with the bitwise-same result.
+template <int R>
+__device__ __forceinline__ float sum_over_categories(float v) {
+    if constexpr (R >= 8)
+        v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x128, 0xF, 0xF, false));
+    if constexpr (R >= 4) {
+        const auto s = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+        v = __uint_as_float(s[0]) + __uint_as_float(s[1]);
+    }
+    if constexpr (R >= 2) {
+        const auto s = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+        v = __uint_as_float(s[0]) + __uint_as_float(s[1]);
+    }
+    return v;
+}
+
+// Exponent e of the per-pattern maximum of the four values over all R
+// categories, and the values scaled by 2^-e (exact).
+template <int R>
+__device__ __forceinline__ int rescale_shared(float x[4]) {
+    int b = 0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) b = max(b, __float_as_int(x[u]));
+    const int e = exponent_of(__int_as_float(max_over_categories<R>(b)));
+#pragma unroll
+    for (int u = 0; u < 4; ++u) x[u] = exact_ldexp(x[u], -e);
+    return e;
 }
 
 // In-block post-order over heap positions 7..LO for this lane's (category,
 // pattern).  With kExpo, returns the sum of exponents taken (in-block nodes and
 // frontier block roots); otherwise exponents are not read.
-template <int R, int LO, bool kExpo>
-__device__ __forceinline__ int bmf_postorder(const int (&nd)[16], const int r, const int tile, const int tiles,
-                                             const int N, const int Cpad, const int lane, const int pat,
-                                             const GLOBAL uint8_t* __restrict__ codes,
-                                             const GLOBAL float* __restrict__ part,
-                                             const GLOBAL int32_t* __restrict__ expo,
-                                             const GLOBAL float* __restrict__ P, const GLOBAL float* __restrict__ TT,
-                                             float (&p)[8][4]) {
-    const int c = tile * kLanes + pat;
+template <int R, int NM, int LO, bool kExpo>
+__device__ __forceinline__ int bmf_postorder(const int (&nd)[16], const BmfLane& L, const BmfMats<R, NM>& S,
+                                             const uint32_t (&pk)[2], const int tile, const int tiles,
+                                             const int N, const int Cpad, GLOBAL F4* __restrict__ part,
+                                             const GLOBAL int32_t* __restrict__ expo, float (&p)[8][4]) {
+    const int c = tile * kLanes + L.pat;
     int esum = 0;
     static_for<0, 8 - LO>([&](auto I_) {
         constexpr int pos = 7 - decltype(I_)::value;
         const int k = nd[pos];
         if (k < N) return;
-        float m[2][4];
+        float m[2][4], v[2][4];
+        if constexpr (pos >= 4) {
+            // frontier children: both stored partials (and exponents) are
+            // loaded before either is used; a tip child reads slot 0, unused
+            int ex[2];
+#pragma unroll
+            for (int s = 0; s < 2; ++s) {
+                const int cn = nd[2 * pos + s];
+                const int slot = cn >= N ? cn - N : 0;
+                f4_to(*reinterpret_cast<const GLOBAL F4*>(chunk<R>(part, slot, tile, tiles) + L.part), v[s]);
+                ex[s] = kExpo ? expo[static_cast<size_t>(slot) * Cpad + c] : 0;
+            }
+#pragma unroll
+            for (int s = 0; s < 2; ++s)
+                if (kExpo && nd[2 * pos + s] >= N) esum += ex[s];
+        } else {
+#pragma unroll
+            for (int s = 0; s < 2; ++s)
+#pragma unroll
+                for (int u = 0; u < 4; ++u) v[s][u] = p[pos < 4 ? 2 * pos + s : 0][u];
+        }
 #pragma unroll
         for (int s = 0; s < 2; ++s) {
             const int cp = 2 * pos + s;
-            const int cn = nd[cp];
-            if (cn < N) {
-                tip_row(TT, cn, R, r, codes[static_cast<size_t>(cn) * Cpad + c], m[s]);
-            } else {
-                float v[4];
-                if (cp < 8) {
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) v[u] = p[cp < 8 ? cp : 0][u];
-                } else {
-                    lane_load(part, cn - N, tile, tiles, R, r, pat, v);
-                    if (kExpo) esum += expo[static_cast<size_t>(cn - N) * Cpad + c];
-                }
-                mfma_mv<false>(P + (static_cast<size_t>(cn) * R + r) * 16, lane, v, m[s]);
-            }
+            const float* M = S.m[cp - 2][L.r][0];
+            if (nd[cp] < N)
+                lds_column(M, code_at(pk, cp), m[s]);
+            else
+                mfma_mv<false>(M, L, v[s], m[s]);
         }
-        float lmx = 0.0f;
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            p[pos][u] = m[0][u] * m[1][u];
-            lmx = fmaxf(lmx, p[pos][u]);
-        }
-        const int e = exponent_of(over_categories<R, true>(lmx));
-#pragma unroll
-        for (int u = 0; u < 4; ++u) p[pos][u] = exact_ldexp(p[pos][u], -e);
-        esum += e;
+        for (int u = 0; u < 4; ++u) p[pos][u] = m[0][u] * m[1][u];
+        esum += rescale_shared<R>(p[pos]);
     });
     return esum;
 }
 
+// Common prologue: unit -> (segment, block, tile), the block's heap record.
+struct BmfUnit {
+    const ReqDesc* d;
+    Segment sg;
+    int tile, tiles, N, Cpad;
+    const GLOBAL int32_t* heap;
+};
+__device__ __forceinline__ bool bmf_unit(const ReqDesc* __restrict__ descs, const SegTable& segs, BmfUnit& U) {
+    const int unit = blockIdx.x;
+    if (unit >= segs.unit_begin[segs.n]) return false;
+    const int sidx = find_segment(segs, unit);
+    U.sg = segs.seg[sidx];
+    U.d = &descs[U.sg.desc];
+    U.tiles = U.d->tiles;
+    U.N = U.d->N;
+    U.Cpad = U.d->Cpad;
+    const int local = unit - segs.unit_begin[sidx];
+    const int bix = local / U.tiles;
+    U.tile = local - bix * U.tiles;
+    U.heap = reinterpret_cast<const GLOBAL int32_t*>(g(U.d->sched)) + static_cast<size_t>(U.sg.sched_off + bix) * 16;
+    return true;
+}
+
 template <int R>
-__global__ __launch_bounds__(kLanes * R) __attribute__((amdgpu_waves_per_eu(4))) void post_bmf_kernel(const ReqDesc* __restrict__ descs,
-                                                              const SegTable segs) {
-    constexpr int PW = kLanes / R;                      // patterns per wave
+__global__ __launch_bounds__(kLanes * R) __attribute__((amdgpu_waves_per_eu(4))) void post_bmf_kernel(
+    const ReqDesc* __restrict__ descs, const SegTable segs) {
+    constexpr int PW = kLanes / R;
+    __shared__ BmfMats<R, 1> S;
     __shared__ double sw[R];
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & (kLanes - 1);
-    const int r = lane / PW;
-    const int pat = w * PW + lane % PW;
-    const int unit = blockIdx.x;
-    if (unit >= segs.unit_begin[segs.n]) return;
-    const int sidx = find_segment(segs, unit);
-    const Segment sg = segs.seg[sidx];
-    const ReqDesc& d = descs[sg.desc];
-    const int tiles = d.tiles, N = d.N, Cpad = d.Cpad;
-    const int local = unit - segs.unit_begin[sidx];
-    const int bix = local / tiles;
-    const int tile = local - bix * tiles;
-    const GLOBAL int32_t* heap =
-        reinterpret_cast<const GLOBAL int32_t*>(g(d.sched)) + static_cast<size_t>(sg.sched_off + bix) * 16;
+    const BmfLane L = bmf_lane<R>(w, lane);
+    BmfUnit U;
+    if (!bmf_unit(descs, segs, U)) return;
+    const ReqDesc& d = *U.d;
+    const int N = U.N, tile = U.tile;
     int nd[16];
 #pragma unroll
-    for (int i = 0; i < 16; ++i) nd[i] = heap[i];
-    GLOBAL float* part = g(part_of<float>(d));
+    for (int i = 0; i < 16; ++i) nd[i] = U.heap[i];
+    const int c = tile * kLanes + L.pat;
+    uint32_t pk[2];
+    load_codes(nd, N, U.Cpad, c, g(d.codes), pk);
+    stage_mats<R, 1>(S, nd, g(d.P32), nullptr);
+    __syncthreads();
+    GLOBAL F4* part = reinterpret_cast<GLOBAL F4*>(g(part_of<float>(d)));
     GLOBAL int32_t* expo = g(d.expo);
-    const int c = tile * kLanes + pat;
     float p[8][4];
-    const int ek = bmf_postorder<R, 1, true>(nd, r, tile, tiles, N, Cpad, lane, pat, g(d.codes), part, expo,
-                                             g(d.P32), g(d.TT32), p);
-    if (!(sg.flags & 1)) {
-        lane_store(part, nd[1] - N, tile, tiles, R, r, pat, p[1]);
-        if (r == 0) expo[static_cast<size_t>(nd[1] - N) * Cpad + c] = ek;
+    const int ek = bmf_postorder<R, 1, 1, true>(nd, L, S, pk, tile, U.tiles, N, U.Cpad, part, expo, p);
+    if (!(U.sg.flags & 1)) {
+        *reinterpret_cast<GLOBAL F4*>(chunk<R>(part, nd[1] - N, tile, U.tiles) + L.part) = to_f4(p[1]);
+        if (L.r == 0) expo[static_cast<size_t>(nd[1] - N) * U.Cpad + c] = ek;
         return;
     }
     // the tree root: log site likelihood and this tile's weighted sum
@@ -905,11 +1053,11 @@ __global__ __launch_bounds__(kLanes * R) __attribute__((amdgpu_waves_per_eu(4)))
     double acc = 0.0;
 #pragma unroll
     for (int u = 0; u < 4; ++u) acc += pi[u] * static_cast<double>(p[1][u]);
-    double site = g(d.cweights)[r] * acc;
+    double site = g(d.cweights)[L.r] * acc;
 #pragma unroll
     for (int off = kLanes / 2; off >= PW; off >>= 1) site += __shfl_xor(site, off, kLanes);
     double contrib = 0.0;
-    if (r == 0) {
+    if (L.r == 0) {
         const double ll = (site > 0.0 ? log(site) : -INFINITY) + static_cast<double>(ek) * 0.69314718055994530942;
         g(d.sll)[c] = ll;
         const double W = g(d.pw)[c];
@@ -927,73 +1075,75 @@ __global__ __launch_bounds__(kLanes * R) __attribute__((amdgpu_waves_per_eu(4)))
 }
 
 template <int R>
-__global__ __launch_bounds__(kLanes * R) __attribute__((amdgpu_waves_per_eu(4))) void pre_bmf_kernel(const ReqDesc* __restrict__ descs,
-                                                             const SegTable segs) {
-    constexpr int PW = kLanes / R;
-    __shared__ float gnum[14][kLanes];                  // per child slot: sum_r w_r u . dm
-    __shared__ float gden[7][kLanes];                   // per position: sum_r w_r u . m
+__global__ __launch_bounds__(kLanes * R) __attribute__((amdgpu_waves_per_eu(4))) void pre_bmf_kernel(
+    const ReqDesc* __restrict__ descs, const SegTable segs) {
+    __shared__ BmfMats<R, 2> S;
+    // per child slot j = 2 (pos - 1) + side: sum_r w_r u . dm; per position:
+    // sum_r w_r u . m (the same for both children); lane = pattern of the tile
+    __shared__ float gnum[14][kLanes];
+    __shared__ float gden[7][kLanes];
+    __shared__ double wl[kLanes];                       // pattern weights of the tile
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & (kLanes - 1);
-    const int r = lane / PW;
-    const int pat = w * PW + lane % PW;
-    const int unit = blockIdx.x;
-    if (unit >= segs.unit_begin[segs.n]) return;
-    const int sidx = find_segment(segs, unit);
-    const Segment sg = segs.seg[sidx];
-    const ReqDesc& d = descs[sg.desc];
-    const int tiles = d.tiles, N = d.N, Cpad = d.Cpad;
-    const int local = unit - segs.unit_begin[sidx];
-    const int bix = local / tiles;
-    const int tile = local - bix * tiles;
-    const GLOBAL int32_t* heap =
-        reinterpret_cast<const GLOBAL int32_t*>(g(d.sched)) + static_cast<size_t>(sg.sched_off + bix) * 16;
+    const BmfLane L = bmf_lane<R>(w, lane);
+    BmfUnit U;
+    if (!bmf_unit(descs, segs, U)) return;
+    const ReqDesc& d = *U.d;
+    const int N = U.N, tile = U.tile, tiles = U.tiles;
     int nd[16];
 #pragma unroll
-    for (int i = 0; i < 16; ++i) nd[i] = heap[i];
-    GLOBAL float* part = g(part_of<float>(d));
-    const GLOBAL uint8_t* codes = g(d.codes);
-    const GLOBAL float* P = g(d.P32);
-    const GLOBAL float* dP = g(d.dP32);
-    const GLOBAL float* TT = g(d.TT32);
-    const GLOBAL float* dTT = g(d.dTT32);
-    const int c = tile * kLanes + pat;
-    float p[8][4];
-    (void)bmf_postorder<R, 2, false>(nd, r, tile, tiles, N, Cpad, lane, pat, codes, part, nullptr, P, TT, p);
+    for (int i = 0; i < 16; ++i) nd[i] = U.heap[i];
+    const int c = tile * kLanes + L.pat;
+    GLOBAL F4* part = reinterpret_cast<GLOBAL F4*>(g(part_of<float>(d)));
+    uint32_t pk[2];
+    load_codes(nd, N, U.Cpad, c, g(d.codes), pk);
     float q[8][4];
     if (nd[1] == 2 * N - 2) {
         const GLOBAL double* pi = g(d.pi);
 #pragma unroll
         for (int u = 0; u < 4; ++u) q[1][u] = static_cast<float>(pi[u]);
     } else {
-        lane_load(part, nd[1] - N, tile, tiles, R, r, pat, q[1]);
+        f4_to(*reinterpret_cast<const GLOBAL F4*>(chunk<R>(part, nd[1] - N, tile, tiles) + L.part), q[1]);
     }
-    const float wr = static_cast<float>(g(d.cweights)[r]);
+    if (L.r == 0) wl[L.pat] = g(d.pw)[c];
+    stage_mats<R, 2>(S, nd, g(d.P32), g(d.dP32));
+    __syncthreads();
+    float p[8][4];
+    (void)bmf_postorder<R, 2, 2, false>(nd, L, S, pk, tile, tiles, N, U.Cpad, part, nullptr, p);
+    const float wr = static_cast<float>(g(d.cweights)[L.r]);
     static_for<1, 8>([&](auto P_) {
         constexpr int pos = decltype(P_)::value;
         const int k = nd[pos];
         if (k < N) return;
-        float m[2][4], dm[2][4];
+        float m[2][4], dm[2][4], v[2][4];
         bool in[2];
+        if constexpr (pos >= 4) {
+#pragma unroll
+            for (int s = 0; s < 2; ++s) {
+                const int cn = nd[2 * pos + s];
+                f4_to(*reinterpret_cast<const GLOBAL F4*>(chunk<R>(part, cn >= N ? cn - N : 0, tile, tiles) +
+                                                          L.part),
+                      v[s]);
+            }
+        } else {
+#pragma unroll
+            for (int s = 0; s < 2; ++s)
+#pragma unroll
+                for (int u = 0; u < 4; ++u) v[s][u] = p[pos < 4 ? 2 * pos + s : 0][u];
+        }
 #pragma unroll
         for (int s = 0; s < 2; ++s) {
             const int cp = 2 * pos + s;
-            const int cn = nd[cp];
-            in[s] = cn >= N;
+            const float* M = S.m[cp - 2][L.r][0];
+            const float* dM = S.m[cp - 2][L.r][1];
+            in[s] = nd[cp] >= N;
             if (!in[s]) {
-                const int code = codes[static_cast<size_t>(cn) * Cpad + c];
-                tip_row(TT, cn, R, r, code, m[s]);
-                tip_row(dTT, cn, R, r, code, dm[s]);
+                const int code = code_at(pk, cp);
+                lds_column(M, code, m[s]);
+                lds_column(dM, code, dm[s]);
             } else {
-                float v[4];
-                if (cp < 8) {
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) v[u] = p[cp < 8 ? cp : 0][u];
-                } else {
-                    lane_load(part, cn - N, tile, tiles, R, r, pat, v);
-                }
-                const size_t mo = (static_cast<size_t>(cn) * R + r) * 16;
-                mfma_mv<false>(P + mo, lane, v, m[s]);
-                mfma_mv<false>(dP + mo, lane, v, dm[s]);
+                mfma_mv<false>(M, L, v[s], m[s]);
+                mfma_mv<false>(dM, L, v[s], dm[s]);
             }
         }
         float uu[2][4], a0 = 0.0f, a1 = 0.0f, dd = 0.0f;
@@ -1005,13 +1155,13 @@ __global__ __launch_bounds__(kLanes * R) __attribute__((amdgpu_waves_per_eu(4)))
             a1 += uu[1][u] * dm[1][u];
             dd += uu[0][u] * m[0][u];
         }
-        const float num0 = over_categories<R, false>(wr * a0);
-        const float num1 = over_categories<R, false>(wr * a1);
-        const float den = over_categories<R, false>(wr * dd);
-        if (r == 0) {
-            gnum[2 * pos - 2][pat] = num0;
-            gnum[2 * pos - 1][pat] = num1;
-            gden[pos - 1][pat] = den;
+        const float num0 = sum_over_categories<R>(wr * a0);
+        const float num1 = sum_over_categories<R>(wr * a1);
+        const float den = sum_over_categories<R>(wr * dd);
+        if (L.r == 0) {
+            gnum[2 * pos - 2][L.pat] = num0;
+            gnum[2 * pos - 1][L.pat] = num1;
+            gden[pos - 1][L.pat] = den;
         }
 #pragma unroll
         for (int s = 0; s < 2; ++s) {
@@ -1019,57 +1169,44 @@ __global__ __launch_bounds__(kLanes * R) __attribute__((amdgpu_waves_per_eu(4)))
             const int cp = 2 * pos + s;
             const int cn = nd[cp];
             float qn[4];
-            mfma_mv<true>(P + (static_cast<size_t>(cn) * R + r) * 16, lane, uu[s], qn);
-            float mx = 0.0f;
-#pragma unroll
-            for (int u = 0; u < 4; ++u) mx = fmaxf(mx, qn[u]);
-            const int e = exponent_of(over_categories<R, true>(mx));
-#pragma unroll
-            for (int u = 0; u < 4; ++u) qn[u] = exact_ldexp(qn[u], -e);
+            mfma_mv<true>(S.m[cp - 2][L.r][0], L, uu[s], qn);
+            (void)rescale_shared<R>(qn);
             if (cp < 8) {
 #pragma unroll
                 for (int u = 0; u < 4; ++u) q[cp < 8 ? cp : 0][u] = qn[u];
             } else {
-                lane_store(part, cn - N, tile, tiles, R, r, pat, qn);
+                *reinterpret_cast<GLOBAL F4*>(chunk<R>(part, cn - N, tile, tiles) + L.part) = to_f4(qn);
             }
         }
     });
     __syncthreads();
-    // per-tile sums of W_c num / den: wave w takes child slots j = w, w + R, ...;
-    // lane = pattern of the tile; all of a wave's slots reduce in lockstep
-    constexpr int kSlots = (14 + R - 1) / R;
-    const double W = g(d.pw)[tile * kLanes + lane];
-    double gs[kSlots];
-    int gc[kSlots];
+    // per-tile sums of W_c num / den for the (up to) 14 child branches: sixteen
+    // threads per branch, four patterns each, then a sixteen-lane reduction;
+    // fixed order, so results are deterministic
+    constexpr int kThreads = kLanes * R;
+    GLOBAL double* gpart = g(d.gpart);
+    int ndv = 0;                                        // lanes 0..15: the heap record
 #pragma unroll
-    for (int i = 0; i < kSlots; ++i) {
-        const int j = i * R + w;
-        gc[i] = -1;
-        gs[i] = 0.0;
-        if (j < 14 && heap[j / 2 + 1] >= N) {
-            gc[i] = heap[j + 2];
-            if (W != 0.0)
-                gs[i] = W * (static_cast<double>(gnum[j][lane]) / static_cast<double>(gden[j / 2][lane]));
+    for (int j = 0; j < 16; ++j) ndv = write_lane(ndv, nd[j], j);
+#pragma unroll
+    for (int t0 = 0; t0 < 14 * 16; t0 += kThreads) {
+        const int t = t0 + static_cast<int>(threadIdx.x);
+        const int j = min(t >> 4, 13);
+        const int sub = t & 15;
+        double acc = 0.0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int pp = sub * 4 + i;
+            const double W = wl[pp];
+            if (W != 0.0) acc += W * (static_cast<double>(gnum[j][pp]) / static_cast<double>(gden[j >> 1][pp]));
         }
-    }
-    // at most four slots in flight at a time (register pressure for small R)
 #pragma unroll
-    for (int i0 = 0; i0 < kSlots; i0 += 4) {
-#pragma unroll
-        for (int off = kLanes / 2; off >= 1; off >>= 1) {
-#pragma unroll
-            for (int i = i0; i < (i0 + 4 < kSlots ? i0 + 4 : kSlots); ++i) gs[i] += __shfl_xor(gs[i], off, kLanes);
-        }
-    }
-    if (lane == 0) {
-        GLOBAL double* gpart = g(d.gpart);
-#pragma unroll
-        for (int i = 0; i < kSlots; ++i)
-            if (gc[i] >= 0) gpart[static_cast<size_t>(gc[i]) * tiles + tile] = gs[i];
+        for (int off = 8; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 16);
+        const int parent_node = __builtin_amdgcn_ds_bpermute(((j >> 1) + 1) << 2, ndv);
+        const int child = __builtin_amdgcn_ds_bpermute((j + 2) << 2, ndv);
+        if (sub == 0 && t < 14 * 16 && parent_node >= N) gpart[static_cast<size_t>(child) * tiles + tile] = acc;
     }
 }
-
-// ---------------------------------------------------------------- P(t), dP/dt
 
 // S = 4: one thread per row s of one (branch, category) pair, so a pair's
 // four rows come from four neighbouring lanes (contiguous stores) and even a
