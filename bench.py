@@ -33,14 +33,15 @@ METRIC = "branch-gradient evals/s at 1000 taxa x 10k patterns; p50/p99 request l
 HBM_PEAK_GBS = 8000.0
 KERNEL_SRC = os.path.join(ROOT, "paper_2303_04390_amd", "csrc", "phg_kernels.hip")
 
-# HBM bytes per evaluation by kernel class on the hky1000 FP32 workload, from two
-# rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE; scaled by a plain 1 GiB copy:
-# x2.0 and x1.0), recorded with the kernel source whose SHA-256 is given.  When
-# the kernel source changes the figure no longer applies and traffic is null.
+# HBM bytes per evaluation by kernel class on the hky1000 FP32 workload under the
+# blocked schedule, from two rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE;
+# scaled by a plain 1 GiB copy: x2.0 and x1.0; profiles/blocked_kernels_hky1000_fp32.md),
+# recorded with the kernel source whose SHA-256 is given.  When the kernel
+# source or the schedule differs the figure no longer applies and traffic is null.
 MEASURED_TRAFFIC = {
-    "kernel_source_sha256": "ffade6c5aa4b186e208b0c591e01b9e2f9c072d3244980e0f963a9c64f50ae26",
-    "schedule": "levels",
-    "bytes_per_eval": {"pre_grad": 1976587324, "post": 1386518026},
+    "kernel_source_sha256": "780d19545cddc6bca9b088ebcfd5a419e821b973e1ce4db7e1df111cdfb6a2d2",
+    "schedule": "blocks",
+    "bytes_per_eval": {"pre_grad": 733192226, "post": 524878042},
 }
 
 

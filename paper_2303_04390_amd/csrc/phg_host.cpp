@@ -351,13 +351,13 @@ phg_status prof_mark(phg_context* ctx) {
     return PHG_OK;
 }
 
-SegTable one_segment(int units, int sched_off, int n_nodes, int flags, double* out_logl,
+SegTable one_segment(const ReqDesc& d, int units, int sched_off, int n_nodes, int flags, double* out_logl,
                      double* out_grad) {
     SegTable t{};
     t.n = 1;
     t.unit_begin[0] = 0;
     t.unit_begin[1] = units;
-    t.seg[0] = Segment{0, sched_off, n_nodes, flags, out_logl, out_grad};
+    t.seg[0] = Segment{0, sched_off, n_nodes, flags, reinterpret_cast<const int32_t*>(d.sched), out_logl, out_grad};
     return t;
 }
 
@@ -370,22 +370,22 @@ phg_status ctx_enqueue_eval(phg_context* ctx, double* d_logl, double* d_grad) {
     const ReqDesc& d = ctx->rd;
     const ReqDesc* descs = ctx_desc_dev(ctx);
     PHG_TRY(prof_mark(ctx));
-    PHG_HIP(ctx, launch_class(kPmat, d, descs, one_segment(units_for(kPmat, d, 0), 0, 0, 0, nullptr, nullptr), st));
+    PHG_HIP(ctx, launch_class(kPmat, d, descs, one_segment(d, units_for(kPmat, d, 0), 0, 0, 0, nullptr, nullptr), st));
     PHG_TRY(prof_mark(ctx));
     const int H = static_cast<int>(ctx->post_lv.size());
     for (int h = 0; h < H; ++h) {
         const int a = ctx->post_lv[h].first, n = ctx->post_lv[h].second;
         PHG_HIP(ctx, launch_class(kPost, d, descs,
-                                  one_segment(units_for(kPost, d, n), a, n, h == H - 1 ? 1 : 0, nullptr, nullptr), st));
+                                  one_segment(d, units_for(kPost, d, n), a, n, h == H - 1 ? 1 : 0, nullptr, nullptr), st));
     }
     PHG_TRY(prof_mark(ctx));
     for (const auto& lv : ctx->pre_lv) {
         const int a = lv.first, n = lv.second;
-        PHG_HIP(ctx, launch_class(kPre, d, descs, one_segment(units_for(kPre, d, n), a, n, 0, nullptr, nullptr), st));
+        PHG_HIP(ctx, launch_class(kPre, d, descs, one_segment(d, units_for(kPre, d, n), a, n, 0, nullptr, nullptr), st));
     }
     PHG_TRY(prof_mark(ctx));
     PHG_HIP(ctx, launch_class(kFinal, d, descs,
-                              one_segment(units_for(kFinal, d, 0), 0, 0, 0, d_logl, d_grad), st));
+                              one_segment(d, units_for(kFinal, d, 0), 0, 0, 0, d_logl, d_grad), st));
     PHG_TRY(prof_mark(ctx));
     return PHG_OK;
 }

@@ -83,6 +83,7 @@ struct Segment {
     int32_t sched_off;   // first NodeTriple of the level in `sched` (levels only)
     int32_t n_nodes;     // nodes in the level (levels only)
     int32_t flags;       // bit 0: this post-order level is the root level
+    const int32_t* sched;  // the request's schedule records (device), as in its descriptor
     double* out_logl;    // finalize only: where log P(Y) goes
     double* out_grad;    // finalize only: where the 2N-2 derivatives go
 };

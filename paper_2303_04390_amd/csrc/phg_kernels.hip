@@ -742,9 +742,9 @@ __global__ __launch_bounds__(kLanes * R) void pre_blk_kernel(const ReqDesc* __re
 
 typedef float F4 __attribute__((ext_vector_type(4)));
 
-// LDS image of one branch-category matrix: rows of 8 floats, columns 0..3
-// the matrix, column 4 the row sum.
-constexpr int kRow = 8;
+// LDS image of one branch-category matrix: rows of 6 floats (8-byte
+// aligned), columns 0..3 the matrix, column 4 the row sum.
+constexpr int kRow = 6;
 constexpr int kMat = 4 * kRow;
 
 template <int R, int NM>
@@ -885,7 +885,13 @@ __device__ __forceinline__ void mfma_mv(const float* M, const BmfLane& L, const 
 #pragma unroll
         for (int k = 0; k < 4; ++k) a[k] = M[k * kRow + L.i];
     } else {
-        f4_to(*reinterpret_cast<const F4*>(M + L.i * kRow), a);
+        typedef float F2 __attribute__((ext_vector_type(2)));
+        const F2 lo = *reinterpret_cast<const F2*>(M + L.i * kRow);
+        const F2 hi = *reinterpret_cast<const F2*>(M + L.i * kRow + 2);
+        a[0] = lo.x;
+        a[1] = lo.y;
+        a[2] = hi.x;
+        a[3] = hi.y;
     }
     F4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
@@ -1008,13 +1014,15 @@ __device__ __forceinline__ bool bmf_unit(const ReqDesc* __restrict__ descs, cons
     const int sidx = find_segment(segs, unit);
     U.sg = segs.seg[sidx];
     U.d = &descs[U.sg.desc];
-    U.tiles = U.d->tiles;
+    // tiles from the segment's unit count (kernel argument), not the descriptor
+    U.tiles = (segs.unit_begin[sidx + 1] - segs.unit_begin[sidx]) / U.sg.n_nodes;
     U.N = U.d->N;
     U.Cpad = U.d->Cpad;
     const int local = unit - segs.unit_begin[sidx];
     const int bix = local / U.tiles;
     U.tile = local - bix * U.tiles;
-    U.heap = reinterpret_cast<const GLOBAL int32_t*>(g(U.d->sched)) + static_cast<size_t>(U.sg.sched_off + bix) * 16;
+    // from the segment (kernel argument), so this load does not wait for the descriptor
+    U.heap = reinterpret_cast<const GLOBAL int32_t*>(g(U.sg.sched)) + static_cast<size_t>(U.sg.sched_off + bix) * 16;
     return true;
 }
 

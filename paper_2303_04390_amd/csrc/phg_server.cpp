@@ -312,7 +312,7 @@ bool launch_step(phg_server* s) {
         phg_context* c = t->ctx;
         const ReqDesc& d = c->rd;
         const int st = r->stage;
-        Item it{i, 0, Segment{i, 0, 0, 0, nullptr, nullptr}, &d};
+        Item it{i, 0, Segment{i, 0, 0, 0, reinterpret_cast<const int32_t*>(d.sched), nullptr, nullptr}, &d};
         GroupKey key{};
         if (st == 0) {
             key = GroupKey{kPmat, d.S == 4, 0, 0};
