@@ -45,12 +45,22 @@ __all__ = [
 
 
 def rate_matrix(V, Vinv, lam):
-    """Q = V diag(lam) Vinv (infinitesimal generator, Methods)."""
-    return (np.asarray(V) * np.asarray(lam)[None, :]) @ np.asarray(Vinv)
+    """Q = V diag(lam) Vinv (infinitesimal generator, Methods).
+
+    With per-category eigensystems (V [R,S,S], lam [R,S]) returns the stack
+    of Q_r; the generator of category r is then gamma_r Q_r, the general
+    Q^(r) the gradient-kernel section allows.
+    """
+    V = np.asarray(V, np.float64)
+    lam = np.asarray(lam, np.float64)
+    return (V * lam[..., None, :]) @ np.asarray(Vinv, np.float64)
 
 
 def transition_matrices(V, Vinv, lam, rates, b):
     """P^(r)(b_x) = exp(gamma_r b_x Q) = V diag(exp(gamma_r b_x lam)) Vinv.
+
+    Per-category eigensystems (V, Vinv [R,S,S], lam [R,S]) give
+    P^(r)(b_x) = exp(gamma_r b_x Q_r).
 
     Returns an array [E, R, S, S] indexed by child node x and category r;
     entry [x, r, s, t] is the probability of state t at the child given s at
@@ -61,12 +71,14 @@ def transition_matrices(V, Vinv, lam, rates, b):
     lam = np.asarray(lam, np.float64)
     b = np.asarray(b, np.float64)
     rates = np.asarray(rates, np.float64)
-    E, R, S = b.shape[0], rates.shape[0], lam.shape[0]
+    E, R, S = b.shape[0], rates.shape[0], lam.shape[-1]
+    per_cat = V.ndim == 3                     # one eigensystem per category
     P = np.empty((E, R, S, S))
     for x in range(E):
         for r in range(R):
-            diag = np.exp(rates[r] * b[x] * lam)
-            P[x, r] = (V * diag[None, :]) @ Vinv
+            Vr, Vir, lr = (V[r], Vinv[r], lam[r]) if per_cat else (V, Vinv, lam)
+            diag = np.exp(rates[r] * b[x] * lr)
+            P[x, r] = (Vr * diag[None, :]) @ Vir
     return P
 
 
@@ -188,7 +200,8 @@ def preorder(parent, P, p, E, pi, R):
 def branch_gradients(parent, Q, p, q, rates, weights, pattern_weights):
     """Per-branch gradient of log P(Y) (eq:gradient, eq:gradientSumAcrossColumns).
 
-    d_ic = sum_r w_r gamma_r p_ir^T Q^T q_ir / sum_r w_r p_ir^T q_ir and
+    d_ic = sum_r w_r gamma_r p_ir^T Q^T q_ir / sum_r w_r p_ir^T q_ir (Q_r in
+    place of Q when Q is a per-category stack [R,S,S]) and
     g_i = sum_c W_c d_ic.  Also returns A_i = sum_c W_c |d_ic| (the scale of
     the cancelling sum, used to state gradient tolerances) and d itself.
     The per-node scale exponents of p and q cancel in the ratio.
@@ -202,7 +215,7 @@ def branch_gradients(parent, Q, p, q, rates, weights, pattern_weights):
     absg = np.zeros(n - 1)
     d_all = np.zeros((n - 1, W.shape[0]))
     for i in range(n - 1):
-        Qtq = np.matmul(q[i], Q)                  # (Q^T q)_s = sum_t Q_ts q_t
+        Qtq = np.matmul(q[i], Q)                  # (Q^T q)_s = sum_t Q_ts q_t (per r for a stack)
         num = np.einsum("r,r,rcs,rcs->c", w, g, p[i], Qtq)
         den = np.einsum("r,rcs,rcs->c", w, p[i], q[i])
         with np.errstate(divide="ignore", invalid="ignore"):
@@ -222,7 +235,7 @@ def evaluate(parent, b, V, Vinv, lam, pi, rates, weights, codes, pattern_weights
     with want_partials also p, E, q, F, P.
     """
     codes = np.asarray(codes)
-    S = np.asarray(lam).shape[0]
+    S = np.asarray(lam).shape[-1]
     R = np.asarray(rates).shape[0]
     P = transition_matrices(V, Vinv, lam, rates, b)
     p, E = postorder(parent, P, codes, S, R)

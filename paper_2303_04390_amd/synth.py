@@ -35,6 +35,7 @@ __all__ = [
     "Problem", "yule_topology", "exponential_branch_lengths", "hky_model",
     "gtr_model", "gy94_model", "eigensystem", "discrete_gamma", "simulate_codes",
     "make_problem", "config_problem", "sense_codons", "reroot", "time_tree",
+    "category_models",
 ]
 
 NUC = "ACGT"
@@ -47,13 +48,14 @@ class Problem:
     parent : int32 [2N-1]   parent[root] = -1, root = 2N-2
     b      : float64 [2N-2] branch length of the branch above each non-root node
     V, Vinv: float64 [S,S]  row-major eigenvectors, Q = V diag(lam) Vinv
+             (or [R,S,S] with lam [R,S]: one model Q_r per rate category)
     lam    : float64 [S]    eigenvalues (real, one of them 0)
     pi     : float64 [S]    root distribution (stationary here)
     rates  : float64 [R]    category rate multipliers gamma_r
     weights: float64 [R]    category probabilities P(gamma_r)
     codes  : int32 [N, C]   tip states 0..S-1, or S for a fully ambiguous entry
     pattern_weights: float64 [C]
-    Q      : float64 [S,S]  the generator itself (for tests and simulation)
+    Q      : float64 [S,S]  the generator itself (for tests and simulation; [R,S,S] per category)
     """
     parent: np.ndarray
     b: np.ndarray
@@ -322,6 +324,25 @@ def eigensystem(Q: np.ndarray, pi: np.ndarray):
     V = U / sq[:, None]
     Vinv = U.T * sq[None, :]
     return np.ascontiguousarray(V), np.ascontiguousarray(Vinv), lam
+
+
+def category_models(S: int, R: int, rng: np.random.Generator, spread: float = 1.0):
+    """One reversible model per rate category (general Q^(r)): GTR with its own
+    exchangeabilities ~Gamma(1/spread-ish) and frequencies ~Dir(4) for S = 4,
+    ~Dir(2) otherwise.  Returns (Qs [R,S,S], V [R,S,S], Vinv [R,S,S],
+    lam [R,S]), each category's eigensystem from its symmetric form."""
+    Qs, Vs, Vis, ls = [], [], [], []
+    for _ in range(R):
+        pi = rng.dirichlet([4.0 if S == 4 else 2.0] * S)
+        pi = np.maximum(pi, 1e-3)
+        pi /= pi.sum()
+        Q = gtr_model(rng.gamma(1.0 / spread, spread, S * (S - 1) // 2), pi)
+        V, Vinv, lam = eigensystem(Q, pi)
+        Qs.append(Q)
+        Vs.append(V)
+        Vis.append(Vinv)
+        ls.append(lam)
+    return np.stack(Qs), np.stack(Vs), np.stack(Vis), np.stack(ls)
 
 
 def discrete_gamma(alpha: float, n_cat: int):

@@ -14,14 +14,18 @@ import scipy.linalg
 
 
 def expm_P(Q, rates, b):
-    E, R, S = len(b), len(rates), Q.shape[0]
+    """P, dP/db for every (branch, category); Q may be one generator [S,S] or
+    one per category [R,S,S] (category r then evolves under rates[r] * Q[r])."""
+    Q = np.asarray(Q)
+    E, R, S = len(b), len(rates), Q.shape[-1]
     P = np.empty((E, R, S, S))
     dP = np.empty((E, R, S, S))
     for x in range(E):
         for r in range(R):
-            M = scipy.linalg.expm(rates[r] * b[x] * Q)
+            Qr = Q[r] if Q.ndim == 3 else Q
+            M = scipy.linalg.expm(rates[r] * b[x] * Qr)
             P[x, r] = M
-            dP[x, r] = rates[r] * (Q @ M)
+            dP[x, r] = rates[r] * (Qr @ M)
     return P, dP
 
 
