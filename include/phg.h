@@ -89,6 +89,16 @@ phg_status phg_set_branch_lengths(phg_context *ctx, const double *b);
 phg_status phg_set_eigen(phg_context *ctx, const double *V, const double *Vinv,
                          const double *lambda);
 
+/* One substitution model per rate category: category r evolves under
+ * Q^(r) = rates[r] * V_r diag(lambda_r) Vinv_r (the gradient-kernel section
+ * keeps the algorithm general for generators that vary across categories).
+ * V and Vinv are R*S*S (category-major, each S*S row-major), lambda R*S;
+ * all finite; copied.  Replaces any eigensystem set before, and
+ * phg_set_eigen replaces this one.  The serving engine takes one shared
+ * model per tree. */
+phg_status phg_set_category_eigen(phg_context *ctx, const double *V, const double *Vinv,
+                                  const double *lambda);
+
 /* Root prior pi (S entries, finite, >= 0), the q vector at the root
  * (Methods, sequence-likelihood equation and eq:preorder). */
 phg_status phg_set_root_frequencies(phg_context *ctx, const double *pi);

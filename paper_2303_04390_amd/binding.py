@@ -68,6 +68,7 @@ _SIGS = {
     "phg_bind_stream": [_vp, _vp],
     "phg_gradient_async": [_vp, _vp, _vp],
     "phg_get_schedule": [_vp, _c.POINTER(_c.c_int)],
+    "phg_set_category_eigen": [_vp, _dp, _dp, _dp],
     "phg_set_time_tree": [_vp, _dp, _dp],
     "phg_set_branch_sets": [_vp, _ip, _c.c_int],
     "phg_time_tree_gradient": [_vp, _dp, _dp, _dp, _dp],
@@ -174,6 +175,11 @@ def phg_set_branch_lengths(ctx, b):
 def phg_set_eigen(ctx, V, Vinv, lam):
     a, b, c = _f64(V), _f64(Vinv), _f64(lam)
     _check(lib().phg_set_eigen(ctx, _p(a), _p(b), _p(c)), ctx, "phg_set_eigen")
+
+
+def phg_set_category_eigen(ctx, V, Vinv, lam):
+    a, b, c = _f64(V), _f64(Vinv), _f64(lam)
+    _check(lib().phg_set_category_eigen(ctx, _p(a), _p(b), _p(c)), ctx, "phg_set_category_eigen")
 
 
 def phg_set_root_frequencies(ctx, pi):
@@ -399,7 +405,10 @@ def set_problem(h, prob):
     same fields) into context handle h."""
     phg_set_topology(h, prob.parent)
     phg_set_branch_lengths(h, prob.b)
-    phg_set_eigen(h, prob.V, prob.Vinv, prob.lam)
+    if np.ndim(prob.V) == 3:                 # one model per rate category
+        phg_set_category_eigen(h, prob.V, prob.Vinv, prob.lam)
+    else:
+        phg_set_eigen(h, prob.V, prob.Vinv, prob.lam)
     phg_set_root_frequencies(h, prob.pi)
     phg_set_categories(h, prob.rates, prob.weights)
     phg_set_tip_states(h, prob.codes)

@@ -32,6 +32,7 @@ enum InputBit : unsigned {
     kPw = 1u << 6,
     kTime = 1u << 7,   // node heights + branch rate scalars (time tree)
     kSets = 1u << 8,   // branch sets
+    kDesc = 1u << 9,   // descriptor fields changed (no input of its own)
     kRequired = kTopo | kB | kEig | kPi | kCat | kTips,
 };
 
@@ -57,6 +58,7 @@ struct phg_context {
     std::vector<int32_t> kids;   // [N-1][2] children of internal node N + k
     std::vector<double> b, V, Vinv, lam, pi, rates, cw, pw;
     std::vector<uint8_t> codes;  // [N][Cpad], padding = S
+    bool eig_cat = false;        // V, Vinv, lam hold one model per category
     // time tree (heights [2N-1], rate scalars [2N-2]) and branch sets (CSR)
     std::vector<double> heights, trates;
     std::vector<int32_t> set_ptr, set_idx;

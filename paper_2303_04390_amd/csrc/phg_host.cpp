@@ -59,9 +59,9 @@ Plan make_plan(int N, int C, int S, int R, phg_precision prec) {
     p.TT32 = take(prec == PHG_FP32_SCALED ? tt * 4 : 0);
     p.dTT32 = take(prec == PHG_FP32_SCALED ? tt * 4 : 0);
     p.b = take(E * 8);
-    p.V = take(static_cast<size_t>(S) * S * 8);
-    p.Vinv = take(static_cast<size_t>(S) * S * 8);
-    p.lam = take(S * 8);
+    p.V = take(static_cast<size_t>(R) * S * S * 8);       // room for one model per category
+    p.Vinv = take(static_cast<size_t>(R) * S * S * 8);
+    p.lam = take(static_cast<size_t>(R) * S * 8);
     p.rates = take(R * 8);
     p.cw = take(R * 8);
     p.pi = take(S * 8);
@@ -266,6 +266,7 @@ phg_status ensure_device(phg_context* ctx) {
     d.tiles = ctx->tiles;
     d.fp32 = ctx->prec == PHG_FP32_SCALED ? 1 : 0;
     d.blocked = ctx->blocked ? 1 : 0;
+    d.eig_cat = ctx->eig_cat ? 1 : 0;
     d.sched = reinterpret_cast<const NodeTriple*>(a + pl.sched);
     d.codes = reinterpret_cast<const uint8_t*>(a + pl.codes);
     d.part = a + pl.part;
@@ -308,7 +309,10 @@ phg_status upload(phg_context* ctx) {
         PHG_HIP(ctx, put(pl.sched, ctx->sched.data(), ctx->sched.size() * sizeof(int32_t)));
         PHG_HIP(ctx, put(pl.ch_parent, ctx->parent.data(), ctx->parent.size() * sizeof(int32_t)));
         PHG_HIP(ctx, put(pl.ch_kids, ctx->kids.data(), ctx->kids.size() * sizeof(int32_t)));
+    }
+    if (dirty & (kTopo | kDesc)) {
         ctx->rd.blocked = ctx->blocked ? 1 : 0;
+        ctx->rd.eig_cat = ctx->eig_cat ? 1 : 0;
         PHG_HIP(ctx, put(pl.desc, &ctx->rd, sizeof(ReqDesc)));
     }
     if (dirty & kB) PHG_HIP(ctx, put(pl.b, ctx->b.data(), ctx->b.size() * 8));
@@ -542,18 +546,31 @@ phg_status phg_set_branch_lengths(phg_context* ctx, const double* b) {
     return PHG_OK;
 }
 
-phg_status phg_set_eigen(phg_context* ctx, const double* V, const double* Vinv, const double* lambda) {
+namespace {
+phg_status set_eig(phg_context* ctx, const double* V, const double* Vinv, const double* lambda, size_t models) {
     if (!ctx) return PHG_ERR_ARG;
     if (!V || !Vinv || !lambda) return ctx->fail(PHG_ERR_ARG, "NULL eigensystem array");
     const size_t S = ctx->S;
-    if (!finite_all(V, S * S) || !finite_all(Vinv, S * S) || !finite_all(lambda, S))
+    if (!finite_all(V, models * S * S) || !finite_all(Vinv, models * S * S) || !finite_all(lambda, models * S))
         return ctx->fail(PHG_ERR_ARG, "eigensystem has non-finite entries");
-    ctx->V.assign(V, V + S * S);
-    ctx->Vinv.assign(Vinv, Vinv + S * S);
-    ctx->lam.assign(lambda, lambda + S);
+    ctx->V.assign(V, V + models * S * S);
+    ctx->Vinv.assign(Vinv, Vinv + models * S * S);
+    ctx->lam.assign(lambda, lambda + models * S);
+    ctx->eig_cat = models > 1;
+    ctx->rd.eig_cat = ctx->eig_cat ? 1 : 0;
     ctx->have |= kEig;
-    ctx->dirty |= kEig;
+    ctx->dirty |= kEig | kDesc;
     return PHG_OK;
+}
+}  // namespace
+
+phg_status phg_set_eigen(phg_context* ctx, const double* V, const double* Vinv, const double* lambda) {
+    return set_eig(ctx, V, Vinv, lambda, 1);
+}
+
+phg_status phg_set_category_eigen(phg_context* ctx, const double* V, const double* Vinv, const double* lambda) {
+    if (!ctx) return PHG_ERR_ARG;
+    return set_eig(ctx, V, Vinv, lambda, static_cast<size_t>(ctx->R));
 }
 
 phg_status phg_set_root_frequencies(phg_context* ctx, const double* pi) {

@@ -46,7 +46,8 @@ struct BlockRec {
 //                                             levels of this request's tree
 struct ReqDesc {
     int32_t N, C, Cpad, S, S4, R, tiles, fp32;
-    int32_t blocked, pad0;  // blocked: sched holds BlockRec records, else NodeTriple
+    int32_t blocked;        // sched holds BlockRec records, else NodeTriple
+    int32_t eig_cat;        // 1: V, Vinv [R][S][S] and lam [R][S], one model per category
     const NodeTriple* sched;
     const uint8_t* codes;
     void* part;

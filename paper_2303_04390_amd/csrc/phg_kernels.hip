@@ -1240,12 +1240,16 @@ __global__ __launch_bounds__(kPmatBlock) void pmat4_kernel(const ReqDesc* __rest
     const int r = pair - x * R;
     const double g = d.rates[r];
     const double t = g * d.b[x];
+    // per-category models: category r's eigensystem
+    const double* lam = d.lam + (d.eig_cat ? r * S : 0);
+    const double* V = d.V + (d.eig_cat ? r * S * S : 0);
+    const double* Vinv = d.Vinv + (d.eig_cat ? r * S * S : 0);
     double ex[S], dex[S];
 #pragma unroll
     for (int k = 0; k < S; ++k) {
-        const double e = exp(d.lam[k] * t);
+        const double e = exp(lam[k] * t);
         ex[k] = e;
-        dex[k] = g * d.lam[k] * e;
+        dex[k] = g * lam[k] * e;
     }
     const size_t base = static_cast<size_t>(pair) * S * S + s * S;
     double Pr[S], dPr[S], rs = 0.0, drs = 0.0;
@@ -1254,7 +1258,7 @@ __global__ __launch_bounds__(kPmatBlock) void pmat4_kernel(const ReqDesc* __rest
         double acc = 0.0, dacc = 0.0;
 #pragma unroll
         for (int k = 0; k < S; ++k) {
-            const double v = d.V[s * S + k] * d.Vinv[k * S + u];
+            const double v = V[s * S + k] * Vinv[k * S + u];
             acc += v * ex[k];
             dacc += v * dex[k];
         }
@@ -1300,10 +1304,14 @@ __global__ __launch_bounds__(256) void pmat_block_kernel(const ReqDesc* __restri
     const int r = pair - x * R;
     const double g = d.rates[r];
     const double t = g * d.b[x];
+    // per-category models: category r's eigensystem
+    const double* lam = d.lam + (d.eig_cat ? r * S : 0);
+    const double* V = d.V + (d.eig_cat ? static_cast<size_t>(r) * S * S : 0);
+    const double* Vinv = d.Vinv + (d.eig_cat ? static_cast<size_t>(r) * S * S : 0);
     for (int k = threadIdx.x; k < S; k += blockDim.x) {
-        const double e = exp(d.lam[k] * t);
+        const double e = exp(lam[k] * t);
         ex[k] = e;
-        dex[k] = g * d.lam[k] * e;
+        dex[k] = g * lam[k] * e;
     }
     __syncthreads();
     const size_t base = static_cast<size_t>(pair) * S * S;
@@ -1312,7 +1320,7 @@ __global__ __launch_bounds__(256) void pmat_block_kernel(const ReqDesc* __restri
         const int u = e - s * S;
         double acc = 0.0, dacc = 0.0;
         for (int k = 0; k < S; ++k) {
-            const double v = d.V[s * S + k] * d.Vinv[k * S + u];
+            const double v = V[s * S + k] * Vinv[k * S + u];
             acc += v * ex[k];
             dacc += v * dex[k];
         }

@@ -258,3 +258,17 @@ def test_time_tree_and_branch_set_validation():
         assert e.value.status == B.PHG_ERR_STATE
     finally:
         B.phg_destroy(ctx)
+
+
+def test_category_eigen_validation():
+    ctx = B.phg_create(5, 10, 4, 3, B.PHG_FP64, 0)
+    try:
+        V = np.stack([np.eye(4)] * 3)
+        lam = np.zeros((3, 4))
+        B.phg_set_category_eigen(ctx, V, V, lam)
+        lam[2, 1] = np.inf
+        with pytest.raises(B.PhgError) as e:
+            B.phg_set_category_eigen(ctx, V, V, lam)
+        assert e.value.status == B.PHG_ERR_ARG
+    finally:
+        B.phg_destroy(ctx)
