@@ -103,8 +103,8 @@ phg_status check_sizes(int n_tips, int n_patterns, int n_states, int n_categorie
     if (n_patterns < 1) return *why = "n_patterns must be >= 1", PHG_ERR_ARG;
     if (n_patterns > (1 << 28)) return *why = "n_patterns too large", PHG_ERR_ARG;
     if (n_states < 2 || n_states > 64) return *why = "n_states must be in [2, 64]", PHG_ERR_ARG;
-    if (n_categories < 1 || n_categories > 16)
-        return *why = "n_categories must be in [1, 16]", PHG_ERR_ARG;
+    if (n_categories < 1 || n_categories > 64)
+        return *why = "n_categories must be in [1, 64]", PHG_ERR_ARG;
     if (prec != PHG_FP64 && prec != PHG_FP32_SCALED) return *why = "unknown precision", PHG_ERR_ARG;
     return PHG_OK;
 }

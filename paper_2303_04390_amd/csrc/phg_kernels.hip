@@ -1408,7 +1408,10 @@ hipError_t level_t(KernelClass k, int R, bool blocked, const ReqDesc* descs, con
 
 }  // namespace
 
-bool kernels_support(int S, int R) { return S >= 2 && S <= 64 && R >= 1 && R <= 16; }
+// More than 8 categories (any S) run on the MFMA kernels, which take the
+// categories of a (node, tile) one at a time, so R is bounded only by this
+// check.
+bool kernels_support(int S, int R) { return S >= 2 && S <= 64 && R >= 1 && R <= 64; }
 
 int tile_patterns(int S, int R, bool fp32) {
     return uses_s4_kernels(S, R) ? kLanes : gs_tile_patterns(fp32);

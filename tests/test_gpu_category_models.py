@@ -65,3 +65,16 @@ def test_identical_category_models_match_the_shared_model_bitwise():
             l2, g2 = ctx.gradient()
         assert l0 == l1 and np.array_equal(g0, g1)
         assert l0 == l2 and np.array_equal(g0, g2)
+
+
+@pytest.mark.parametrize("S,R", [(4, 24), (4, 64), (20, 32)])
+def test_many_rate_categories(S, R):
+    """More categories than the 4-state kernels hold (they run one category at
+    a time on the MFMA kernels), with per-category models."""
+    prob = cat_problem(24, 150, S, R, seed=R + S)
+    ref = oracle.evaluate_problem(prob)
+    for prec in (B.PHG_FP64, B.PHG_FP32_SCALED):
+        print(f"[case] S={S} R={R} prec={prec}", flush=True)
+        with B.Context.for_problem(prob, prec) as ctx:
+            logl, grad = ctx.gradient()
+        check(f"many-categories-S{S}-R{R}/{prec}", logl, grad, ref, *TOL[prec])
