@@ -59,7 +59,7 @@ typedef enum {
 typedef struct phg_context phg_context;
 
 /* Create a context for one (tree, alignment) problem of fixed sizes.
- * n_tips >= 2, n_patterns >= 1, 2 <= n_states <= 64, 1 <= n_categories <= 64,
+ * n_tips >= 2, n_patterns >= 1, 2 <= n_states <= 255, 1 <= n_categories <= 64,
  * device = HIP device ordinal.  *out receives the context (NULL on error).
  * Host-only: no device work happens here. */
 phg_status phg_create(int n_tips, int n_patterns, int n_states, int n_categories,

@@ -102,7 +102,8 @@ phg_status check_sizes(int n_tips, int n_patterns, int n_states, int n_categorie
     if (n_tips > (1 << 24)) return *why = "n_tips too large", PHG_ERR_ARG;
     if (n_patterns < 1) return *why = "n_patterns must be >= 1", PHG_ERR_ARG;
     if (n_patterns > (1 << 28)) return *why = "n_patterns too large", PHG_ERR_ARG;
-    if (n_states < 2 || n_states > 64) return *why = "n_states must be in [2, 64]", PHG_ERR_ARG;
+    // codes are bytes and S itself is the ambiguous code
+    if (n_states < 2 || n_states > 255) return *why = "n_states must be in [2, 255]", PHG_ERR_ARG;
     if (n_categories < 1 || n_categories > 64)
         return *why = "n_categories must be in [1, 64]", PHG_ERR_ARG;
     if (prec != PHG_FP64 && prec != PHG_FP32_SCALED) return *why = "unknown precision", PHG_ERR_ARG;

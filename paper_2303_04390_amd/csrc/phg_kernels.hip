@@ -1290,10 +1290,10 @@ __global__ __launch_bounds__(kPmatBlock) void pmat4_kernel(const ReqDesc* __rest
     }
 }
 
-// Any S <= 64: one block per (branch, category) pair.
+// Any S: one block per (branch, category) pair.
 __global__ __launch_bounds__(256) void pmat_block_kernel(const ReqDesc* __restrict__ descs,
                                                          const SegTable segs) {
-    __shared__ double ex[64], dex[64];
+    __shared__ double ex[256], dex[256];
     const int unit = blockIdx.x;
     if (unit >= segs.unit_begin[segs.n]) return;
     const int sidx = find_segment(segs, unit);
@@ -1411,9 +1411,10 @@ hipError_t level_t(KernelClass k, int R, bool blocked, const ReqDesc* descs, con
 // More than 8 categories (any S) run on the MFMA kernels, which take the
 // categories of a (node, tile) one at a time, so R is bounded only by this
 // check.
-bool kernels_support(int S, int R) { return S >= 2 && S <= 64 && R >= 1 && R <= 64; }
+bool kernels_support(int S, int R) { return S >= 2 && S <= 255 && R >= 1 && R <= 64; }
 
 int tile_patterns(int S, int R, bool fp32) {
+    if (S > 64) return gl_tile_patterns();
     return uses_s4_kernels(S, R) ? kLanes : gs_tile_patterns(fp32);
 }
 
@@ -1442,6 +1443,7 @@ hipError_t launch_class(KernelClass k, const ReqDesc& shape, const ReqDesc* desc
             return hipGetLastError();
         case kPost:
         case kPre:
+            if (shape.S > 64) return launch_level_gl(k, shape, descs, t, st);
             if (!uses_s4_kernels(shape.S, shape.R)) return launch_level_gs(k, shape, descs, t, st);
             if (shape.fp32) return level_t<float>(k, shape.R, shape.blocked != 0, descs, t, st);
             return level_t<double>(k, shape.R, shape.blocked != 0, descs, t, st);

@@ -1,0 +1,567 @@
+// gfx950 level kernels for large state spaces (65..256 states: Markov-modulated
+// and phylogeographic models), on MFMA 16x16x4 tiles (f32 for the FP32 path,
+// f64 for the FP64 path).
+//
+// Same method as the other kernels (Methods: pruning equation, eq:preorder,
+// eq:gradient), as small matrix products over a tile of 16 patterns:
+//   forward   m[c][s] = sum_t P[s][t] p[c][t]      (P_x p_x, dP_x p_x)
+//   backward  q[c][t] = sum_s u[c][s] P[s][t]      (q_x = P_x^T u_x)
+// One workgroup of four waves takes one (node, 16-pattern tile); wave w owns
+// the output states [w * 16 NBW, (w + 1) * 16 NBW) of every product (NBW
+// column blocks of 16), and runs the full sum over input states itself:
+// inputs come from HBM/L2 (stored partials, matrices) or, for the vectors u
+// that feed P^T u, from LDS where all four waves wrote their parts.
+//
+// MFMA 16x16x4 computes D(16x16) += A(16x4) B(4x16); lane l holds A[l%16][l/16]
+// and B[l/16][l%16]; the four output registers hold D[4(l/16)+i][l%16] (f32)
+// or D[4i+l/16][l%16] (f64).  A rows are the tile's patterns, B is P, D rows
+// are patterns: lane (g = l/16, n = l%16) holds state (column base + 16cb + n)
+// of patterns dpat(g, 0..3).
+//
+// Partials are stored [slot][tile][r][state][16 patterns] (exact state count).
+// Scaling as everywhere: one power-of-two exponent per (node, pattern) shared
+// by all categories and states; outputs are written unscaled category by
+// category and rescaled in place once the exponent is known.
+#include "phg_internal.h"
+
+#include <math.h>
+
+namespace phg {
+namespace {
+
+#define GLOBAL __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ GLOBAL T* g(T* p) {
+    return (GLOBAL T*)p;
+}
+
+template <typename T>
+struct V4T;
+template <>
+struct V4T<float> {
+    typedef float type __attribute__((ext_vector_type(4)));
+};
+template <>
+struct V4T<double> {
+    typedef double type __attribute__((ext_vector_type(4)));
+};
+template <typename T>
+using V4 = typename V4T<T>::type;
+typedef int I4 __attribute__((ext_vector_type(4)));
+
+constexpr int kTP = 16;      // patterns per tile
+constexpr int kWaves = 4;    // waves per workgroup
+constexpr int kLS = kTP + 1; // LDS row stride of a [state][pattern] vector
+
+__device__ __forceinline__ V4<float> mma(float a, float b, V4<float> c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ V4<double> mma(double a, double b, V4<double> c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ float scale2(float x, int e) { return ldexpf(x, e); }
+__device__ __forceinline__ double scale2(double x, int e) { return ldexp(x, e); }
+__device__ __forceinline__ int exp_of(float x) {
+    int e = 0;
+    if (x > 0.0f) (void)frexpf(x, &e);
+    return e;
+}
+__device__ __forceinline__ int exp_of(double x) {
+    int e = 0;
+    if (x > 0.0) (void)frexp(x, &e);
+    return e;
+}
+
+// Pattern of output register i for lane group gq.
+template <typename T>
+__device__ __forceinline__ int opat(int gq, int i) {
+    return sizeof(T) == 4 ? 4 * gq + i : 4 * i + gq;
+}
+
+template <typename V>
+__device__ __forceinline__ V sum16(V v) {
+#pragma unroll
+    for (int off = 1; off < 16; off <<= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+template <typename V>
+__device__ __forceinline__ V max16(V v) {
+#pragma unroll
+    for (int off = 1; off < 16; off <<= 1) v = fmax(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+template <typename T>
+__device__ __forceinline__ const T* tabP(const ReqDesc& d);
+template <>
+__device__ __forceinline__ const float* tabP<float>(const ReqDesc& d) { return d.P32; }
+template <>
+__device__ __forceinline__ const double* tabP<double>(const ReqDesc& d) { return d.P64; }
+template <typename T>
+__device__ __forceinline__ const T* tabdP(const ReqDesc& d);
+template <>
+__device__ __forceinline__ const float* tabdP<float>(const ReqDesc& d) { return d.dP32; }
+template <>
+__device__ __forceinline__ const double* tabdP<double>(const ReqDesc& d) { return d.dP64; }
+
+__device__ __forceinline__ int seg_of(const SegTable& t, int unit) {
+    int s = 0;
+    while (s + 1 < t.n && unit >= t.unit_begin[s + 1]) ++s;
+    return s;
+}
+
+// This wave's columns of one vector: NBW blocks of 16 states, 4 patterns each.
+template <typename T, int NBW>
+struct Cols {
+    V4<T> v[NBW];
+};
+
+// Where a child's input vector comes from.
+template <typename T>
+struct Input {
+    const GLOBAL T* base;   // stored [state][16] block of (slot, tile, r), or null for a tip
+    int code;               // a tip's code for pattern n of the tile
+};
+
+// out = M v on this wave's columns: out[c][s] = sum_t M[s][t] in[c][t],
+// s = cb0 + 16 cb + n.
+template <typename T, int NBW>
+__device__ __forceinline__ void fwd(const GLOBAL T* __restrict__ M, const Input<T>& in, int S, int cb0,
+                                    int lane, Cols<T, NBW>& out) {
+    const int gq = lane >> 4, n = lane & 15;
+#pragma unroll
+    for (int cb = 0; cb < NBW; ++cb) out.v[cb] = V4<T>{0, 0, 0, 0};
+    const int KB = (S + 3) / 4;
+    for (int kk = 0; kk < KB; ++kk) {
+        const int t = 4 * kk + gq;
+        T a;
+        if (in.base)
+            a = t < S ? in.base[t * kTP + n] : T(0);
+        else
+            a = (t < S && (in.code == t || in.code >= S)) ? T(1) : T(0);
+#pragma unroll
+        for (int cb = 0; cb < NBW; ++cb) {
+            const int s = cb0 + 16 * cb + n;
+            const T b = (s < S && t < S) ? M[static_cast<size_t>(s) * S + t] : T(0);
+            out.v[cb] = mma(a, b, out.v[cb]);
+        }
+    }
+}
+
+// out = M^T u on this wave's columns: out[c][t] = sum_s u[c][s] M[s][t],
+// u from LDS laid out [state][kLS].
+template <typename T, int NBW>
+__device__ __forceinline__ void bwd(const GLOBAL T* __restrict__ M, const T* U, int S, int cb0, int lane,
+                                    Cols<T, NBW>& out) {
+    const int gq = lane >> 4, n = lane & 15;
+#pragma unroll
+    for (int cb = 0; cb < NBW; ++cb) out.v[cb] = V4<T>{0, 0, 0, 0};
+    const int KB = (S + 3) / 4;
+    for (int kk = 0; kk < KB; ++kk) {
+        const int s = 4 * kk + gq;
+        const T a = s < S ? U[s * kLS + n] : T(0);
+#pragma unroll
+        for (int cb = 0; cb < NBW; ++cb) {
+            const int t = cb0 + 16 * cb + n;
+            const T b = (s < S && t < S) ? M[static_cast<size_t>(s) * S + t] : T(0);
+            out.v[cb] = mma(a, b, out.v[cb]);
+        }
+    }
+}
+
+// Stored [state][16] block <-> this wave's columns.
+template <typename T, int NBW>
+__device__ __forceinline__ void load_cols(const GLOBAL T* __restrict__ base, int S, int cb0, int lane,
+                                          Cols<T, NBW>& x) {
+    const int gq = lane >> 4, n = lane & 15;
+#pragma unroll
+    for (int cb = 0; cb < NBW; ++cb) {
+        const int s = cb0 + 16 * cb + n;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) x.v[cb][i] = s < S ? base[s * kTP + opat<T>(gq, i)] : T(0);
+    }
+}
+template <typename T, int NBW>
+__device__ __forceinline__ void store_cols(GLOBAL T* __restrict__ base, int S, int cb0, int lane,
+                                           const Cols<T, NBW>& x) {
+    const int gq = lane >> 4, n = lane & 15;
+#pragma unroll
+    for (int cb = 0; cb < NBW; ++cb) {
+        const int s = cb0 + 16 * cb + n;
+        if (s < S) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) base[s * kTP + opat<T>(gq, i)] = x.v[cb][i];
+        }
+    }
+}
+template <typename T, int NBW>
+__device__ __forceinline__ void cols_to_lds(T* U, int S, int cb0, int lane, const Cols<T, NBW>& x) {
+    const int gq = lane >> 4, n = lane & 15;
+#pragma unroll
+    for (int cb = 0; cb < NBW; ++cb) {
+        const int s = cb0 + 16 * cb + n;
+        if (s < S) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) U[s * kLS + opat<T>(gq, i)] = x.v[cb][i];
+        }
+    }
+}
+
+// Per-pattern partial sum over this wave's columns of x * y.
+template <typename T, int NBW>
+__device__ __forceinline__ void dot_cols(const Cols<T, NBW>& x, const Cols<T, NBW>& y, T acc[4]) {
+#pragma unroll
+    for (int cb = 0; cb < NBW; ++cb)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) acc[i] += x.v[cb][i] * y.v[cb][i];
+}
+template <typename T, int NBW>
+__device__ __forceinline__ void max_cols(const Cols<T, NBW>& x, T mx[4]) {
+#pragma unroll
+    for (int cb = 0; cb < NBW; ++cb)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) mx[i] = fmax(mx[i], x.v[cb][i]);
+}
+
+// Maximum over the workgroup of per-pattern values held by lanes n == any of
+// group gq (after max16): via LDS, fixed order.  red has kWaves * 16 slots.
+template <typename T>
+__device__ __forceinline__ void wg_max(T mx[4], T* red, int w, int lane) {
+    const int gq = lane >> 4, n = lane & 15;
+    if (n == 0) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) red[w * 16 + opat<T>(gq, i)] = mx[i];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        T m = red[opat<T>(gq, i)];
+#pragma unroll
+        for (int ww = 1; ww < kWaves; ++ww) m = fmax(m, red[ww * 16 + opat<T>(gq, i)]);
+        mx[i] = m;
+    }
+    __syncthreads();
+}
+
+// Rescale this wave's columns of a stored (slot, tile) block, all categories.
+template <typename T, int NBW>
+__device__ __forceinline__ void rescale_cols(GLOBAL T* __restrict__ slot_tile, int R, int S, int cb0, int lane,
+                                             const int e[4]) {
+    for (int r = 0; r < R; ++r) {
+        GLOBAL T* base = slot_tile + static_cast<size_t>(r) * S * kTP;
+        Cols<T, NBW> x;
+        load_cols<T, NBW>(base, S, cb0, lane, x);
+#pragma unroll
+        for (int cb = 0; cb < NBW; ++cb)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) x.v[cb][i] = scale2(x.v[cb][i], -e[i]);
+        store_cols<T, NBW>(base, S, cb0, lane, x);
+    }
+}
+
+struct GlUnit {
+    const ReqDesc* d;
+    Segment sg;
+    NodeTriple nt;
+    int tile, tiles;
+};
+__device__ __forceinline__ bool gl_unit(const ReqDesc* __restrict__ descs, const SegTable& segs, GlUnit& U) {
+    const int unit = blockIdx.x;
+    if (unit >= segs.unit_begin[segs.n]) return false;
+    const int sidx = seg_of(segs, unit);
+    U.sg = segs.seg[sidx];
+    U.d = &descs[U.sg.desc];
+    U.tiles = U.d->tiles;
+    const int local = unit - segs.unit_begin[sidx];
+    const int node_ix = local / U.tiles;
+    U.tile = local - node_ix * U.tiles;
+    const I4 t4 = reinterpret_cast<const GLOBAL I4*>(g(U.sg.sched))[U.sg.sched_off + node_ix];
+    U.nt = NodeTriple{t4.x, t4.y, t4.z, 0};
+    return true;
+}
+
+// ---------------------------------------------------------------- post-order
+
+template <typename T, int NBW>
+__global__ __launch_bounds__(64 * kWaves) void post_gl_kernel(const ReqDesc* __restrict__ descs,
+                                                              const SegTable segs) {
+    __shared__ T red[kWaves * 16];
+    __shared__ double dred[kWaves * 16];
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int gq = lane >> 4, n = lane & 15;
+    GlUnit U;
+    if (!gl_unit(descs, segs, U)) return;
+    const ReqDesc& d = *U.d;
+    const int N = d.N, S = d.S, R = d.R, Cpad = d.Cpad, tile = U.tile, tiles = U.tiles;
+    const NodeTriple nt = U.nt;
+    const int cb0 = w * 16 * NBW;
+    const size_t rstride = static_cast<size_t>(S) * kTP;
+    const size_t tstride = rstride * R;
+    GLOBAL T* part = g(static_cast<T*>(d.part));
+    const GLOBAL T* P = g(tabP<T>(d));
+    const bool tip_i = nt.i < N, tip_j = nt.j < N;
+    const int c_n = tile * kTP + n;               // pattern of this lane's A row
+    Input<T> si{nullptr, tip_i ? static_cast<int>(g(d.codes)[static_cast<size_t>(nt.i) * Cpad + c_n]) : 0};
+    Input<T> sj{nullptr, tip_j ? static_cast<int>(g(d.codes)[static_cast<size_t>(nt.j) * Cpad + c_n]) : 0};
+    const GLOBAL T* pi_base = tip_i ? nullptr : part + (static_cast<size_t>(nt.i - N) * tiles + tile) * tstride;
+    const GLOBAL T* pj_base = tip_j ? nullptr : part + (static_cast<size_t>(nt.j - N) * tiles + tile) * tstride;
+    GLOBAL T* out_base = part + (static_cast<size_t>(nt.k - N) * tiles + tile) * tstride;
+    const bool root = U.sg.flags & 1;
+    T mx[4] = {T(0), T(0), T(0), T(0)};
+    double site[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int r = 0; r < R; ++r) {
+        si.base = pi_base ? pi_base + r * rstride : nullptr;
+        sj.base = pj_base ? pj_base + r * rstride : nullptr;
+        Cols<T, NBW> mi, mj;
+        fwd<T, NBW>(P + (static_cast<size_t>(nt.i) * R + r) * S * S, si, S, cb0, lane, mi);
+        fwd<T, NBW>(P + (static_cast<size_t>(nt.j) * R + r) * S * S, sj, S, cb0, lane, mj);
+#pragma unroll
+        for (int cb = 0; cb < NBW; ++cb) mi.v[cb] *= mj.v[cb];
+        if (!root) {
+            max_cols<T, NBW>(mi, mx);
+            store_cols<T, NBW>(out_base + r * rstride, S, cb0, lane, mi);
+        } else {
+            const double wr = g(d.cweights)[r];
+#pragma unroll
+            for (int cb = 0; cb < NBW; ++cb) {
+                const int s = cb0 + 16 * cb + n;
+                const double ps = s < S ? g(d.pi)[s] : 0.0;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) site[i] += wr * ps * static_cast<double>(mi.v[cb][i]);
+            }
+        }
+    }
+    int ec[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int c = tile * kTP + opat<T>(gq, i);
+        ec[i] = (tip_i ? 0 : g(d.expo)[static_cast<size_t>(nt.i - N) * Cpad + c]) +
+                (tip_j ? 0 : g(d.expo)[static_cast<size_t>(nt.j - N) * Cpad + c]);
+    }
+    if (!root) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) mx[i] = max16(mx[i]);
+        wg_max<T>(mx, red, w, lane);
+        int e[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) e[i] = exp_of(mx[i]);
+        __syncthreads();      // every wave's unscaled columns are stored
+        rescale_cols<T, NBW>(out_base, R, S, cb0, lane, e);
+        if (w == 0 && n == 0) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                g(d.expo)[static_cast<size_t>(nt.k - N) * Cpad + tile * kTP + opat<T>(gq, i)] = e[i] + ec[i];
+        }
+    } else {
+        // site likelihood: sum over this wave's states, then over waves (fixed order)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) site[i] = sum16(site[i]);
+        if (n == 0) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) dred[w * 16 + opat<T>(gq, i)] = site[i];
+        }
+        __syncthreads();
+        if (w == 0) {
+            double tsum = 0.0;
+            if (n == 0) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int p = opat<T>(gq, i);
+                    double sv = dred[p];
+#pragma unroll
+                    for (int ww = 1; ww < kWaves; ++ww) sv += dred[ww * 16 + p];
+                    const int c = tile * kTP + p;
+                    const double ll =
+                        (sv > 0.0 ? log(sv) : -INFINITY) + static_cast<double>(ec[i]) * 0.69314718055994530942;
+                    g(d.sll)[c] = ll;
+                    const double W = g(d.pw)[c];
+                    tsum += (W != 0.0) ? W * ll : 0.0;
+                }
+            }
+#pragma unroll
+            for (int off = 32; off >= 1; off >>= 1) tsum += __shfl_xor(tsum, off, 64);
+            if (lane == 0) g(d.lpart)[tile] = tsum;
+        }
+    }
+}
+
+// ---------------------------------------------------------------- pre-order + gradient
+
+template <typename T, int NBW>
+__global__ __launch_bounds__(64 * kWaves) void pre_gl_kernel(const ReqDesc* __restrict__ descs,
+                                                             const SegTable segs) {
+    constexpr int SP = 64 * NBW;                    // padded states held in LDS
+    __shared__ T Ui[SP * kLS];
+    __shared__ T Uj[SP * kLS];
+    __shared__ T red[3 * kWaves * 16];
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int gq = lane >> 4, n = lane & 15;
+    GlUnit U;
+    if (!gl_unit(descs, segs, U)) return;
+    const ReqDesc& d = *U.d;
+    const int N = d.N, S = d.S, R = d.R, Cpad = d.Cpad, tile = U.tile, tiles = U.tiles;
+    const NodeTriple nt = U.nt;
+    const int cb0 = w * 16 * NBW;
+    const size_t rstride = static_cast<size_t>(S) * kTP;
+    const size_t tstride = rstride * R;
+    GLOBAL T* part = g(static_cast<T*>(d.part));
+    const GLOBAL T* P = g(tabP<T>(d));
+    const GLOBAL T* dP = g(tabdP<T>(d));
+    const bool is_root = nt.k == 2 * N - 2;
+    const bool tip_i = nt.i < N, tip_j = nt.j < N;
+    const int c_n = tile * kTP + n;
+    Input<T> si{nullptr, tip_i ? static_cast<int>(g(d.codes)[static_cast<size_t>(nt.i) * Cpad + c_n]) : 0};
+    Input<T> sj{nullptr, tip_j ? static_cast<int>(g(d.codes)[static_cast<size_t>(nt.j) * Cpad + c_n]) : 0};
+    GLOBAL T* pi_base = tip_i ? nullptr : part + (static_cast<size_t>(nt.i - N) * tiles + tile) * tstride;
+    GLOBAL T* pj_base = tip_j ? nullptr : part + (static_cast<size_t>(nt.j - N) * tiles + tile) * tstride;
+    const GLOBAL T* qk_base = is_root ? nullptr : part + (static_cast<size_t>(nt.k - N) * tiles + tile) * tstride;
+    T num_i[4] = {}, num_j[4] = {}, den[4] = {}, mxi[4] = {}, mxj[4] = {};
+    for (int r = 0; r < R; ++r) {
+        si.base = pi_base ? pi_base + r * rstride : nullptr;
+        sj.base = pj_base ? pj_base + r * rstride : nullptr;
+        const size_t mo_i = (static_cast<size_t>(nt.i) * R + r) * S * S;
+        const size_t mo_j = (static_cast<size_t>(nt.j) * R + r) * S * S;
+        const T wr = static_cast<T>(g(d.cweights)[r]);
+        Cols<T, NBW> qk, a, b, acc;
+        if (is_root) {
+#pragma unroll
+            for (int cb = 0; cb < NBW; ++cb) {
+                const int s = cb0 + 16 * cb + n;
+                const T v = s < S ? static_cast<T>(g(d.pi)[s]) : T(0);
+                qk.v[cb] = V4<T>{v, v, v, v};
+            }
+        } else {
+            load_cols<T, NBW>(qk_base + r * rstride, S, cb0, lane, qk);
+        }
+        fwd<T, NBW>(P + mo_j, sj, S, cb0, lane, a);          // a = m_j
+#pragma unroll
+        for (int cb = 0; cb < NBW; ++cb) a.v[cb] *= qk.v[cb];   // a = u_i
+        cols_to_lds<T, NBW>(Ui, S, cb0, lane, a);
+        fwd<T, NBW>(P + mo_i, si, S, cb0, lane, b);          // b = m_i
+        T dd[4] = {}, ni[4] = {}, nj[4] = {};
+        dot_cols<T, NBW>(a, b, dd);                           // u_i . m_i
+#pragma unroll
+        for (int cb = 0; cb < NBW; ++cb) b.v[cb] *= qk.v[cb];   // b = u_j
+        cols_to_lds<T, NBW>(Uj, S, cb0, lane, b);
+        fwd<T, NBW>(dP + mo_i, si, S, cb0, lane, acc);       // dm_i
+        dot_cols<T, NBW>(a, acc, ni);
+        fwd<T, NBW>(dP + mo_j, sj, S, cb0, lane, acc);       // dm_j
+        dot_cols<T, NBW>(b, acc, nj);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            num_i[i] += wr * ni[i];
+            num_j[i] += wr * nj[i];
+            den[i] += wr * dd[i];
+        }
+        __syncthreads();      // u complete in LDS; every wave is done reading p_i, p_j of category r
+        if (!tip_i) {
+            bwd<T, NBW>(P + mo_i, Ui, S, cb0, lane, acc);    // q_i = P_i^T u_i, unscaled, over p_i
+            max_cols<T, NBW>(acc, mxi);
+            store_cols<T, NBW>(pi_base + r * rstride, S, cb0, lane, acc);
+        }
+        if (!tip_j) {
+            bwd<T, NBW>(P + mo_j, Uj, S, cb0, lane, acc);
+            max_cols<T, NBW>(acc, mxj);
+            store_cols<T, NBW>(pj_base + r * rstride, S, cb0, lane, acc);
+        }
+        __syncthreads();      // before the next category overwrites u
+    }
+    if (!tip_i) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) mxi[i] = max16(mxi[i]);
+        wg_max<T>(mxi, red, w, lane);
+        int e[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) e[i] = exp_of(mxi[i]);
+        rescale_cols<T, NBW>(pi_base, R, S, cb0, lane, e);
+    }
+    if (!tip_j) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) mxj[i] = max16(mxj[i]);
+        wg_max<T>(mxj, red, w, lane);
+        int e[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) e[i] = exp_of(mxj[i]);
+        rescale_cols<T, NBW>(pj_base, R, S, cb0, lane, e);
+    }
+    // per-pattern sums over all states: this wave's part, then the waves in order
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        num_i[i] = sum16(num_i[i]);
+        num_j[i] = sum16(num_j[i]);
+        den[i] = sum16(den[i]);
+    }
+    if (n == 0) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int p = opat<T>(gq, i);
+            red[(0 * kWaves + w) * 16 + p] = num_i[i];
+            red[(1 * kWaves + w) * 16 + p] = num_j[i];
+            red[(2 * kWaves + w) * 16 + p] = den[i];
+        }
+    }
+    __syncthreads();
+    if (w == 0) {
+        double gi = 0.0, gj = 0.0;
+        if (n == 0) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int p = opat<T>(gq, i);
+                T Ni = red[p], Nj = red[kWaves * 16 + p], Dn = red[2 * kWaves * 16 + p];
+#pragma unroll
+                for (int ww = 1; ww < kWaves; ++ww) {
+                    Ni += red[ww * 16 + p];
+                    Nj += red[(kWaves + ww) * 16 + p];
+                    Dn += red[(2 * kWaves + ww) * 16 + p];
+                }
+                const double W = g(d.pw)[tile * kTP + p];
+                if (W != 0.0) {
+                    gi += W * (static_cast<double>(Ni) / static_cast<double>(Dn));
+                    gj += W * (static_cast<double>(Nj) / static_cast<double>(Dn));
+                }
+            }
+        }
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+            gi += __shfl_xor(gi, off, 64);
+            gj += __shfl_xor(gj, off, 64);
+        }
+        if (lane == 0) {
+            g(d.gpart)[static_cast<size_t>(nt.i) * tiles + tile] = gi;
+            g(d.gpart)[static_cast<size_t>(nt.j) * tiles + tile] = gj;
+        }
+    }
+}
+
+template <typename T>
+hipError_t launch_gl_t(KernelClass k, int S, const ReqDesc* descs, const SegTable& t, hipStream_t st) {
+    const int n_units = t.unit_begin[t.n];
+    const int nbw = (S + 63) / 64;
+#define PHG_GL_CASE(NBV)                                                                                    \
+    case NBV:                                                                                               \
+        if (k == kPost)                                                                                     \
+            hipLaunchKernelGGL((post_gl_kernel<T, NBV>), dim3(n_units), dim3(64 * kWaves), 0, st, descs, t); \
+        else                                                                                                \
+            hipLaunchKernelGGL((pre_gl_kernel<T, NBV>), dim3(n_units), dim3(64 * kWaves), 0, st, descs, t);  \
+        return hipGetLastError();
+    switch (nbw) {
+        PHG_GL_CASE(2)
+        PHG_GL_CASE(3)
+        PHG_GL_CASE(4)
+        default: return hipErrorInvalidValue;
+    }
+#undef PHG_GL_CASE
+}
+
+}  // namespace
+
+hipError_t launch_level_gl(KernelClass k, const ReqDesc& shape, const ReqDesc* descs, const SegTable& t,
+                           hipStream_t st) {
+    if (shape.fp32) return launch_gl_t<float>(k, shape.S, descs, t, st);
+    return launch_gl_t<double>(k, shape.S, descs, t, st);
+}
+
+}  // namespace phg

@@ -34,7 +34,7 @@ def test_create_validates_sizes():
     with pytest.raises(B.PhgError) as e:
         B.phg_create(1, 10, 4, 4, B.PHG_FP64)
     assert e.value.status == B.PHG_ERR_ARG
-    for args in [(10, 0, 4, 4, 0), (10, 10, 1, 4, 0), (10, 10, 65, 4, 0), (10, 10, 4, 0, 0),
+    for args in [(10, 0, 4, 4, 0), (10, 10, 1, 4, 0), (10, 10, 256, 4, 0), (10, 10, 4, 0, 0),
                  (10, 10, 4, 65, 0), (10, 10, 4, 4, 7)]:
         with pytest.raises(B.PhgError) as e:
             B.phg_create(*args)

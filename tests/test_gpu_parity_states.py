@@ -137,3 +137,14 @@ def test_generic_repeatable_and_async(codon128):
         stream.synchronize()
         res = out.cpu().numpy()
         assert res[0] == l1 and np.array_equal(res[1:], g1)
+
+
+@pytest.mark.parametrize("S,N,C,R", [(65, 10, 37, 2), (122, 12, 40, 4), (128, 8, 16, 1), (129, 8, 33, 3),
+                                     (200, 6, 20, 2), (255, 6, 17, 2)])
+def test_large_state_spaces(S, N, C, R):
+    """65..255 states (Markov-modulated and phylogeographic state spaces) on
+    the large-state MFMA kernels, ragged 16-pattern tiles."""
+    prob = generic_problem(N, S, C, seed=S + C, R=R, mean_b=0.05)
+    ref = oracle.evaluate_problem(prob)
+    for prec in (B.PHG_FP64, B.PHG_FP32_SCALED):
+        compare(f"S{S}-N{N}-C{C}-R{R}", prob, prec, ref)

@@ -355,3 +355,40 @@ def test_oracle_matches_stored_regression_fixture():
     out = run(synth.config_problem("hky16", seed=0))
     assert abs(out["logl"] - rec["logl"]) <= 1e-13 * abs(rec["logl"])
     assert np.allclose(out["grad"], rec["grad"], rtol=1e-12, atol=1e-12)
+
+
+@pytest.mark.parametrize("S", [122, 255])
+def test_large_state_space_brute_force(S):
+    """Three taxa: log-likelihood and all four derivatives by summation over
+    every assignment of states to the two internal nodes (an S x S grid),
+    with scipy expm transition matrices."""
+    prob = small_problem(3, S=S, C=4, seed=S, R=2, ambiguous=0.0)
+    out = run(prob)
+    P, dP = brute.expm_P(prob.Q, prob.rates, prob.b)
+    L = _brute_grid(prob, P)
+    assert abs(out["logl"] - np.sum(prob.pattern_weights * np.log(L))) <= 1e-11 * abs(out["logl"])
+    for x in range(4):
+        dL = _brute_grid(prob, P, deriv=x, dP=dP)
+        g = np.sum(prob.pattern_weights * dL / L)
+        assert abs(out["grad"][x] - g) <= 1e-9 * max(abs(g), 1e-2 * out["absgrad"][x]) + 1e-13, \
+            (x, out["grad"][x], g)
+
+
+def _brute_grid(prob, P, deriv=None, dP=None):
+    """Three-taxon tree: L_c = sum_r w_r sum_{a, b} pi_a P_inner[a, b] times
+    each tip's factor P_x[parent state, y_x], over the full grid of root state
+    a and inner-node state b."""
+    parent = prob.parent
+    S = prob.n_states
+    root, inner = 4, 3
+    assert parent[inner] == root
+    out = np.zeros(prob.n_patterns)
+    for r in range(prob.n_categories):
+        M = [(dP if x == deriv else P)[x, r] for x in range(4)]
+        for c in range(prob.n_patterns):
+            grid = prob.pi[:, None] * M[inner]                      # [a, b]
+            for x in range(3):
+                col = M[x][:, prob.codes[x, c]]                     # P_x[parent state, y]
+                grid = grid * (col[:, None] if parent[x] == root else col[None, :])
+            out[c] += prob.weights[r] * grid.sum()
+    return out
