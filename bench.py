@@ -244,6 +244,77 @@ def serving_measurement(args, B, synth):
     }
 
 
+MFMA_PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6}      # MI355X dense MFMA peaks
+
+
+def matvec_flops(parent, n_tips, C, R, S):
+    """Algorithmic flops of one evaluation on the MFMA kernels (one S x S
+    matrix-vector product per pattern and category = 2 S^2 flops):
+    post-order 2 per internal node (P_i p_i, P_j p_j); pre-order 4 per
+    internal node (m_i, m_j, dm_i, dm_j) and 1 per internal child (q_x =
+    P_x^T u_x)."""
+    n = parent.shape[0]
+    internal = n - n_tips
+    internal_children = int(np.sum(np.arange(n - 1) >= n_tips))
+    post = 2 * internal
+    pre = 4 * internal + internal_children
+    per = 2.0 * S * S * C * R
+    return post * per, pre * per
+
+
+def state_space_measurement(args, B, synth, stream, out):
+    """Throughput and MFMA utilisation of the larger state spaces: the
+    500-taxon amino-acid and 128-taxon codon workloads, and a 122-state
+    (Markov-modulated size) case, in FP32 and FP64."""
+    import torch
+    res = {}
+    cases = [("aa500", synth.config_problem("aa500", seed=args.seed)),
+             ("codon128", synth.config_problem("codon128", seed=args.seed))]
+    rng = np.random.default_rng(args.seed + 5)
+    N122 = 128
+    parent = synth.yule_topology(N122, rng)
+    pi = rng.dirichlet([2.0] * 122)
+    Q = synth.gtr_model(rng.gamma(1.0, 1.0, 122 * 121 // 2), pi)
+    rates, w = synth.discrete_gamma(0.5, 4)
+    cases.append(("s122", synth.make_problem(parent, synth.exponential_branch_lengths(N122, 0.05, rng), Q, pi,
+                                             rates, w, 2000, rng)))
+    for name, prob in cases:
+        N, C, S, R = prob.n_tips, prob.n_patterns, prob.n_states, prob.n_categories
+        post_f, pre_f = matvec_flops(prob.parent, N, C, R, S)
+        for prec, tag in ((B.PHG_FP32_SCALED, "f32"), (B.PHG_FP64, "f64")):
+            h = B.phg_create(N, C, S, R, prec, 0)
+            try:
+                B.phg_bind_stream(h, stream.cuda_stream)
+                B.set_problem(h, prob)
+                B.phg_prepare(h)
+                for _ in range(2):
+                    B.phg_gradient_async(h, out.data_ptr(), out.data_ptr() + 8)
+                torch.cuda.synchronize()
+                B.phg_profile_enable(h, True)
+                k = args.state_steps
+                t0 = time.perf_counter()
+                for _ in range(k):
+                    B.phg_gradient_async(h, out.data_ptr(), out.data_ptr() + 8)
+                torch.cuda.synchronize()
+                dt = (time.perf_counter() - t0) / k
+                ms_cls, n_prof, _ = B.phg_profile_read(h)
+            finally:
+                B.phg_destroy(h)
+            cls = dict(zip(B.PROF_NAMES, (ms_cls / max(n_prof, 1)).tolist()))
+            t_mm = (cls["post"] + cls["pre_grad"]) * 1e-3
+            tflops = (post_f + pre_f) / t_mm / 1e12
+            res[f"{name}_{tag}"] = {
+                "n_tips": N, "n_patterns": C, "n_states": S, "n_categories": R,
+                "evals_per_s": round(1.0 / dt, 1), "ms_per_eval": round(dt * 1e3, 4),
+                "ms_per_class": {k2: round(v, 4) for k2, v in cls.items()},
+                "algorithmic_gflop_per_eval": round((post_f + pre_f) / 1e9, 2),
+                "mfma_tflops": round(tflops, 2), "mfma_peak_tflops": MFMA_PEAK_TFLOPS[tag],
+                "mfma_frac": round(tflops / MFMA_PEAK_TFLOPS[tag], 4)}
+            print(f"[bench] {name} {tag}: {1.0 / dt:.1f} evals/s, {tflops:.1f} TFLOP/s", file=sys.stderr,
+                  flush=True)
+    return res
+
+
 def batched_vs_fp64(args, B, prob, fp64_evals_per_s):
     """k chains of the 1000-taxon workload evaluated concurrently through the
     server in FP32 (each chain resubmits as soon as its result returns, with
@@ -311,6 +382,8 @@ def main():
     ap.add_argument("--serving-pool", type=int, default=12,
                     help="distinct synthetic trees the stream draws from")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-states", action="store_true", help="skip the 20/61/122-state measurements")
+    ap.add_argument("--state-steps", type=int, default=10)
     ap.add_argument("--batched-chains", type=int, default=8)
     ap.add_argument("--batched-seconds", type=float, default=3.0)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -449,6 +522,10 @@ def main():
 
     serving = None
     batched = None
+    states = None
+    if not args.no_states:
+        print("[bench] 20-, 61- and 122-state workloads", file=sys.stderr, flush=True)
+        states = state_space_measurement(args, B, synth, stream, out)
     if not args.no_serving:
         print("[bench] batched FP32 chains vs plain FP64", file=sys.stderr, flush=True)
         batched = batched_vs_fp64(args, B, prob, 1e3 / fp64_ms)
@@ -478,6 +555,7 @@ def main():
         "path": path,
         "fp64_path": {"ms_per_step": round(fp64_ms, 4), "evals_per_s": round(1e3 / fp64_ms, 2)},
         "batched_fp32_vs_fp64": batched,
+        "state_spaces": states,
         "serving": serving,
     }
 

@@ -135,7 +135,7 @@ struct ChainArgs {
 // d_rates (time_tree) or of grad.
 hipError_t launch_chain(const ChainArgs& a, bool time_tree, hipStream_t stream);
 
-// MFMA level kernels for 65..255 states (phg_kernels_gl.hip): one workgroup
+// MFMA level kernels for 17..255 states (phg_kernels_gl.hip): one workgroup
 // per (node, 16-pattern tile), the waves splitting the output states.
 inline int gl_tile_patterns() { return 16; }
 hipError_t launch_level_gl(KernelClass k, const ReqDesc& shape, const ReqDesc* descs,

@@ -1414,7 +1414,7 @@ hipError_t level_t(KernelClass k, int R, bool blocked, const ReqDesc* descs, con
 bool kernels_support(int S, int R) { return S >= 2 && S <= 255 && R >= 1 && R <= 64; }
 
 int tile_patterns(int S, int R, bool fp32) {
-    if (S > 64) return gl_tile_patterns();
+    if (S > 16 && !uses_s4_kernels(S, R)) return gl_tile_patterns();
     return uses_s4_kernels(S, R) ? kLanes : gs_tile_patterns(fp32);
 }
 
@@ -1443,7 +1443,7 @@ hipError_t launch_class(KernelClass k, const ReqDesc& shape, const ReqDesc* desc
             return hipGetLastError();
         case kPost:
         case kPre:
-            if (shape.S > 64) return launch_level_gl(k, shape, descs, t, st);
+            if (shape.S > 16 && !uses_s4_kernels(shape.S, shape.R)) return launch_level_gl(k, shape, descs, t, st);
             if (!uses_s4_kernels(shape.S, shape.R)) return launch_level_gs(k, shape, descs, t, st);
             if (shape.fp32) return level_t<float>(k, shape.R, shape.blocked != 0, descs, t, st);
             return level_t<double>(k, shape.R, shape.blocked != 0, descs, t, st);

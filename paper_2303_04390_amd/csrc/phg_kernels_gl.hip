@@ -1,16 +1,17 @@
-// gfx950 level kernels for large state spaces (65..256 states: Markov-modulated
-// and phylogeographic models), on MFMA 16x16x4 tiles (f32 for the FP32 path,
-// f64 for the FP64 path).
+// gfx950 level kernels for 17..255 states (amino acids, codons, Markov-
+// modulated and phylogeographic models), on MFMA 16x16x4 tiles (f32 for the
+// FP32 path, f64 for the FP64 path).
 //
 // Same method as the other kernels (Methods: pruning equation, eq:preorder,
 // eq:gradient), as small matrix products over a tile of 16 patterns:
 //   forward   m[c][s] = sum_t P[s][t] p[c][t]      (P_x p_x, dP_x p_x)
 //   backward  q[c][t] = sum_s u[c][s] P[s][t]      (q_x = P_x^T u_x)
-// One workgroup of four waves takes one (node, 16-pattern tile); wave w owns
-// the output states [w * 16 NBW, (w + 1) * 16 NBW) of every product (NBW
-// column blocks of 16), and runs the full sum over input states itself:
+// One workgroup of W waves takes one (node, 16-pattern tile); wave w owns the
+// output states [w * 16 NBW, (w + 1) * 16 NBW) of every product (NBW column
+// blocks of 16; W = ceil(S / 16) waves of one block up to 64 states, four
+// waves above), and runs the full sum over input states itself:
 // inputs come from HBM/L2 (stored partials, matrices) or, for the vectors u
-// that feed P^T u, from LDS where all four waves wrote their parts.
+// that feed P^T u, from LDS where all the waves wrote their parts.
 //
 // MFMA 16x16x4 computes D(16x16) += A(16x4) B(4x16); lane l holds A[l%16][l/16]
 // and B[l/16][l%16]; the four output registers hold D[4(l/16)+i][l%16] (f32)
@@ -50,7 +51,6 @@ using V4 = typename V4T<T>::type;
 typedef int I4 __attribute__((ext_vector_type(4)));
 
 constexpr int kTP = 16;      // patterns per tile
-constexpr int kWaves = 4;    // waves per workgroup
 constexpr int kLS = kTP + 1; // LDS row stride of a [state][pattern] vector
 
 __device__ __forceinline__ V4<float> mma(float a, float b, V4<float> c) {
@@ -226,7 +226,7 @@ __device__ __forceinline__ void max_cols(const Cols<T, NBW>& x, T mx[4]) {
 
 // Maximum over the workgroup of per-pattern values held by lanes n == any of
 // group gq (after max16): via LDS, fixed order.  red has kWaves * 16 slots.
-template <typename T>
+template <typename T, int W>
 __device__ __forceinline__ void wg_max(T mx[4], T* red, int w, int lane) {
     const int gq = lane >> 4, n = lane & 15;
     if (n == 0) {
@@ -238,7 +238,7 @@ __device__ __forceinline__ void wg_max(T mx[4], T* red, int w, int lane) {
     for (int i = 0; i < 4; ++i) {
         T m = red[opat<T>(gq, i)];
 #pragma unroll
-        for (int ww = 1; ww < kWaves; ++ww) m = fmax(m, red[ww * 16 + opat<T>(gq, i)]);
+        for (int ww = 1; ww < W; ++ww) m = fmax(m, red[ww * 16 + opat<T>(gq, i)]);
         mx[i] = m;
     }
     __syncthreads();
@@ -283,9 +283,10 @@ __device__ __forceinline__ bool gl_unit(const ReqDesc* __restrict__ descs, const
 
 // ---------------------------------------------------------------- post-order
 
-template <typename T, int NBW>
-__global__ __launch_bounds__(64 * kWaves) void post_gl_kernel(const ReqDesc* __restrict__ descs,
-                                                              const SegTable segs) {
+template <typename T, int NBW, int W>
+__global__ __launch_bounds__(64 * W) void post_gl_kernel(const ReqDesc* __restrict__ descs,
+                                                         const SegTable segs) {
+    constexpr int kWaves = W;
     __shared__ T red[kWaves * 16];
     __shared__ double dred[kWaves * 16];
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -343,7 +344,7 @@ __global__ __launch_bounds__(64 * kWaves) void post_gl_kernel(const ReqDesc* __r
     if (!root) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) mx[i] = max16(mx[i]);
-        wg_max<T>(mx, red, w, lane);
+        wg_max<T, W>(mx, red, w, lane);
         int e[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) e[i] = exp_of(mx[i]);
@@ -376,8 +377,8 @@ __global__ __launch_bounds__(64 * kWaves) void post_gl_kernel(const ReqDesc* __r
                     const double ll =
                         (sv > 0.0 ? log(sv) : -INFINITY) + static_cast<double>(ec[i]) * 0.69314718055994530942;
                     g(d.sll)[c] = ll;
-                    const double W = g(d.pw)[c];
-                    tsum += (W != 0.0) ? W * ll : 0.0;
+                    const double Wc = g(d.pw)[c];
+                    tsum += (Wc != 0.0) ? Wc * ll : 0.0;
                 }
             }
 #pragma unroll
@@ -389,10 +390,11 @@ __global__ __launch_bounds__(64 * kWaves) void post_gl_kernel(const ReqDesc* __r
 
 // ---------------------------------------------------------------- pre-order + gradient
 
-template <typename T, int NBW>
-__global__ __launch_bounds__(64 * kWaves) void pre_gl_kernel(const ReqDesc* __restrict__ descs,
-                                                             const SegTable segs) {
-    constexpr int SP = 64 * NBW;                    // padded states held in LDS
+template <typename T, int NBW, int W>
+__global__ __launch_bounds__(64 * W) void pre_gl_kernel(const ReqDesc* __restrict__ descs,
+                                                        const SegTable segs) {
+    constexpr int kWaves = W;
+    constexpr int SP = 16 * NBW * W;                // padded states held in LDS
     __shared__ T Ui[SP * kLS];
     __shared__ T Uj[SP * kLS];
     __shared__ T red[3 * kWaves * 16];
@@ -472,7 +474,7 @@ __global__ __launch_bounds__(64 * kWaves) void pre_gl_kernel(const ReqDesc* __re
     if (!tip_i) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) mxi[i] = max16(mxi[i]);
-        wg_max<T>(mxi, red, w, lane);
+        wg_max<T, W>(mxi, red, w, lane);
         int e[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) e[i] = exp_of(mxi[i]);
@@ -481,7 +483,7 @@ __global__ __launch_bounds__(64 * kWaves) void pre_gl_kernel(const ReqDesc* __re
     if (!tip_j) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) mxj[i] = max16(mxj[i]);
-        wg_max<T>(mxj, red, w, lane);
+        wg_max<T, W>(mxj, red, w, lane);
         int e[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) e[i] = exp_of(mxj[i]);
@@ -517,10 +519,10 @@ __global__ __launch_bounds__(64 * kWaves) void pre_gl_kernel(const ReqDesc* __re
                     Nj += red[(kWaves + ww) * 16 + p];
                     Dn += red[(2 * kWaves + ww) * 16 + p];
                 }
-                const double W = g(d.pw)[tile * kTP + p];
-                if (W != 0.0) {
-                    gi += W * (static_cast<double>(Ni) / static_cast<double>(Dn));
-                    gj += W * (static_cast<double>(Nj) / static_cast<double>(Dn));
+                const double Wc = g(d.pw)[tile * kTP + p];
+                if (Wc != 0.0) {
+                    gi += Wc * (static_cast<double>(Ni) / static_cast<double>(Dn));
+                    gj += Wc * (static_cast<double>(Nj) / static_cast<double>(Dn));
                 }
             }
         }
@@ -539,21 +541,26 @@ __global__ __launch_bounds__(64 * kWaves) void pre_gl_kernel(const ReqDesc* __re
 template <typename T>
 hipError_t launch_gl_t(KernelClass k, int S, const ReqDesc* descs, const SegTable& t, hipStream_t st) {
     const int n_units = t.unit_begin[t.n];
-    const int nbw = (S + 63) / 64;
-#define PHG_GL_CASE(NBV)                                                                                    \
-    case NBV:                                                                                               \
-        if (k == kPost)                                                                                     \
-            hipLaunchKernelGGL((post_gl_kernel<T, NBV>), dim3(n_units), dim3(64 * kWaves), 0, st, descs, t); \
-        else                                                                                                \
-            hipLaunchKernelGGL((pre_gl_kernel<T, NBV>), dim3(n_units), dim3(64 * kWaves), 0, st, descs, t);  \
-        return hipGetLastError();
-    switch (nbw) {
-        PHG_GL_CASE(2)
-        PHG_GL_CASE(3)
-        PHG_GL_CASE(4)
-        default: return hipErrorInvalidValue;
+    // up to 64 states: one 16-state block per wave, ceil(S / 16) waves;
+    // above: four waves of ceil(S / 64) blocks each
+    const int nbw = S > 64 ? (S + 63) / 64 : 1;
+    const int w = S > 64 ? 4 : (S + 15) / 16;
+#define PHG_GL_CASE(NBV, WV)                                                                                 \
+    if (nbw == NBV && w == WV) {                                                                             \
+        if (k == kPost)                                                                                      \
+            hipLaunchKernelGGL((post_gl_kernel<T, NBV, WV>), dim3(n_units), dim3(64 * WV), 0, st, descs, t); \
+        else                                                                                                 \
+            hipLaunchKernelGGL((pre_gl_kernel<T, NBV, WV>), dim3(n_units), dim3(64 * WV), 0, st, descs, t);  \
+        return hipGetLastError();                                                                            \
     }
+    PHG_GL_CASE(1, 2)
+    PHG_GL_CASE(1, 3)
+    PHG_GL_CASE(1, 4)
+    PHG_GL_CASE(2, 4)
+    PHG_GL_CASE(3, 4)
+    PHG_GL_CASE(4, 4)
 #undef PHG_GL_CASE
+    return hipErrorInvalidValue;
 }
 
 }  // namespace
