@@ -845,29 +845,30 @@ __device__ __forceinline__ void stage_mats(BmfMats<R, NM>& S, const int (&nd)[16
     }
 }
 
-// The tip codes (0..4) of this lane's pattern for child positions 2..15,
-// four bits each: positions 2..9 in word 0, 10..15 in word 1.
-__device__ __forceinline__ void load_codes(const int (&nd)[16], const int N, const int Cpad, const int c,
-                                           const GLOBAL uint8_t* __restrict__ codes, uint32_t (&pk)[2]) {
-    // all fourteen loads are issued unconditionally (a non-tip reads tip 0's
-    // row) so that they are in flight together; the selection comes after
-    uint32_t cd[14];
+// Tip codes of the block's child positions 2..15 for the tile's 64 patterns,
+// staged in LDS: row j = position j + 2, one byte per pattern.  Each row is 64
+// contiguous bytes of the code matrix, read as 16 dwords, so one wave
+// instruction fetches four rows (a non-tip row reads tip 0's codes, unused).
+// All threads take part; the caller synchronises.
+template <int R>
+__device__ __forceinline__ void stage_codes(uint32_t (&CL)[14][16], const int (&nd)[16], const int N,
+                                            const int Cpad, const int c0, const GLOBAL uint8_t* __restrict__ codes) {
+    int ndv = 0;                                        // lanes 0..15: the heap record
 #pragma unroll
-    for (int cp = 2; cp < 16; ++cp) {
-        const int cn = nd[cp];
+    for (int j = 0; j < 16; ++j) ndv = write_lane(ndv, nd[j], j);
+    constexpr int kRowsPerPass = 4 * R;
+#pragma unroll
+    for (int j0 = 0; j0 < 14; j0 += kRowsPerPass) {
+        const int j = j0 + static_cast<int>(threadIdx.x >> 4);
+        const int cn = __builtin_amdgcn_ds_bpermute((min(j, 13) + 2) << 2, ndv);
         const size_t row = (cn >= 0 && cn < N) ? static_cast<size_t>(cn) : 0;
-        cd[cp - 2] = codes[row * Cpad + c];
-    }
-    pk[0] = pk[1] = 0;
-#pragma unroll
-    for (int j = 0; j < 14; ++j) {
-        const int cn = nd[j + 2];
-        if (cn >= 0 && cn < N) pk[j >> 3] |= cd[j] << (4 * (j & 7));
+        const uint32_t wv =
+            *reinterpret_cast<const GLOBAL uint32_t*>(codes + row * Cpad + c0 + 4 * (threadIdx.x & 15));
+        if (j < 14) CL[j][threadIdx.x & 15] = wv;
     }
 }
-__device__ __forceinline__ int code_at(const uint32_t (&pk)[2], int cp) {
-    const int j = cp - 2;
-    return static_cast<int>((pk[j >> 3] >> (4 * (j & 7))) & 15u);
+__device__ __forceinline__ int code_at(const uint32_t (&CL)[14][16], int cp, int pat) {
+    return reinterpret_cast<const uint8_t*>(&CL[cp - 2][0])[pat];
 }
 
 // Column CODE of a staged matrix (P e_code, or the row sums for code 4).
@@ -955,7 +956,7 @@ __device__ __forceinline__ int rescale_shared(float x[4]) {
 // frontier block roots); otherwise exponents are not read.
 template <int R, int NM, int LO, bool kExpo>
 __device__ __forceinline__ int bmf_postorder(const int (&nd)[16], const BmfLane& L, const BmfMats<R, NM>& S,
-                                             const uint32_t (&pk)[2], const int tile, const int tiles,
+                                             const uint32_t (&CL)[14][16], const int tile, const int tiles,
                                              const int N, const int Cpad, GLOBAL F4* __restrict__ part,
                                              const GLOBAL int32_t* __restrict__ expo, float (&p)[8][4]) {
     const int c = tile * kLanes + L.pat;
@@ -990,7 +991,7 @@ __device__ __forceinline__ int bmf_postorder(const int (&nd)[16], const BmfLane&
             const int cp = 2 * pos + s;
             const float* M = S.m[cp - 2][L.r][0];
             if (nd[cp] < N)
-                lds_column(M, code_at(pk, cp), m[s]);
+                lds_column(M, code_at(CL, cp, L.pat), m[s]);
             else
                 mfma_mv<false>(M, L, v[s], m[s]);
         }
@@ -1031,6 +1032,7 @@ __global__ __launch_bounds__(kLanes * R) __attribute__((amdgpu_waves_per_eu(4)))
     const ReqDesc* __restrict__ descs, const SegTable segs) {
     constexpr int PW = kLanes / R;
     __shared__ BmfMats<R, 1> S;
+    __shared__ uint32_t CL[14][16];                     // tip codes of the block, [position - 2][pattern]
     __shared__ double sw[R];
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & (kLanes - 1);
@@ -1043,14 +1045,13 @@ __global__ __launch_bounds__(kLanes * R) __attribute__((amdgpu_waves_per_eu(4)))
 #pragma unroll
     for (int i = 0; i < 16; ++i) nd[i] = U.heap[i];
     const int c = tile * kLanes + L.pat;
-    uint32_t pk[2];
-    load_codes(nd, N, U.Cpad, c, g(d.codes), pk);
+    stage_codes<R>(CL, nd, N, U.Cpad, tile * kLanes, g(d.codes));
     stage_mats<R, 1>(S, nd, g(d.P32), nullptr);
     __syncthreads();
     GLOBAL F4* part = reinterpret_cast<GLOBAL F4*>(g(part_of<float>(d)));
     GLOBAL int32_t* expo = g(d.expo);
     float p[8][4];
-    const int ek = bmf_postorder<R, 1, 1, true>(nd, L, S, pk, tile, U.tiles, N, U.Cpad, part, expo, p);
+    const int ek = bmf_postorder<R, 1, 1, true>(nd, L, S, CL, tile, U.tiles, N, U.Cpad, part, expo, p);
     if (!(U.sg.flags & 1)) {
         *reinterpret_cast<GLOBAL F4*>(chunk<R>(part, nd[1] - N, tile, U.tiles) + L.part) = to_f4(p[1]);
         if (L.r == 0) expo[static_cast<size_t>(nd[1] - N) * U.Cpad + c] = ek;
@@ -1086,6 +1087,7 @@ template <int R>
 __global__ __launch_bounds__(kLanes * R) __attribute__((amdgpu_waves_per_eu(4))) void pre_bmf_kernel(
     const ReqDesc* __restrict__ descs, const SegTable segs) {
     __shared__ BmfMats<R, 2> S;
+    __shared__ uint32_t CL[14][16];                     // tip codes of the block, [position - 2][pattern]
     // per child slot j = 2 (pos - 1) + side: sum_r w_r u . dm; per position:
     // sum_r w_r u . m (the same for both children); lane = pattern of the tile
     __shared__ float gnum[14][kLanes];
@@ -1103,8 +1105,7 @@ __global__ __launch_bounds__(kLanes * R) __attribute__((amdgpu_waves_per_eu(4)))
     for (int i = 0; i < 16; ++i) nd[i] = U.heap[i];
     const int c = tile * kLanes + L.pat;
     GLOBAL F4* part = reinterpret_cast<GLOBAL F4*>(g(part_of<float>(d)));
-    uint32_t pk[2];
-    load_codes(nd, N, U.Cpad, c, g(d.codes), pk);
+    stage_codes<R>(CL, nd, N, U.Cpad, tile * kLanes, g(d.codes));
     float q[8][4];
     if (nd[1] == 2 * N - 2) {
         const GLOBAL double* pi = g(d.pi);
@@ -1117,7 +1118,7 @@ __global__ __launch_bounds__(kLanes * R) __attribute__((amdgpu_waves_per_eu(4)))
     stage_mats<R, 2>(S, nd, g(d.P32), g(d.dP32));
     __syncthreads();
     float p[8][4];
-    (void)bmf_postorder<R, 2, 2, false>(nd, L, S, pk, tile, tiles, N, U.Cpad, part, nullptr, p);
+    (void)bmf_postorder<R, 2, 2, false>(nd, L, S, CL, tile, tiles, N, U.Cpad, part, nullptr, p);
     const float wr = static_cast<float>(g(d.cweights)[L.r]);
     static_for<1, 8>([&](auto P_) {
         constexpr int pos = decltype(P_)::value;
@@ -1146,7 +1147,7 @@ __global__ __launch_bounds__(kLanes * R) __attribute__((amdgpu_waves_per_eu(4)))
             const float* dM = S.m[cp - 2][L.r][1];
             in[s] = nd[cp] >= N;
             if (!in[s]) {
-                const int code = code_at(pk, cp);
+                const int code = code_at(CL, cp, L.pat);
                 lds_column(M, code, m[s]);
                 lds_column(dM, code, dm[s]);
             } else {
