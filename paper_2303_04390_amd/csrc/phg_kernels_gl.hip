@@ -124,6 +124,10 @@ struct Input {
     int code;               // a tip's code for pattern n of the tile
 };
 
+// k-steps whose operands are loaded together before their MFMAs run (one
+// memory round trip per chunk instead of one per step).
+constexpr int kChunk = 8;
+
 // out = M v on this wave's columns: out[c][s] = sum_t M[s][t] in[c][t],
 // s = cb0 + 16 cb + n.
 template <typename T, int NBW>
@@ -133,19 +137,62 @@ __device__ __forceinline__ void fwd(const GLOBAL T* __restrict__ M, const Input<
 #pragma unroll
     for (int cb = 0; cb < NBW; ++cb) out.v[cb] = V4<T>{0, 0, 0, 0};
     const int KB = (S + 3) / 4;
-    for (int kk = 0; kk < KB; ++kk) {
-        const int t = 4 * kk + gq;
-        T a;
-        if (in.base)
-            a = t < S ? in.base[t * kTP + n] : T(0);
-        else
-            a = (t < S && (in.code == t || in.code >= S)) ? T(1) : T(0);
+    for (int k0 = 0; k0 < KB; k0 += kChunk) {
+        T a[kChunk], b[kChunk][NBW];
 #pragma unroll
-        for (int cb = 0; cb < NBW; ++cb) {
-            const int s = cb0 + 16 * cb + n;
-            const T b = (s < S && t < S) ? M[static_cast<size_t>(s) * S + t] : T(0);
-            out.v[cb] = mma(a, b, out.v[cb]);
+        for (int c = 0; c < kChunk; ++c) {
+            const int t = 4 * (k0 + c) + gq;           // t >= S past the last step
+            if (in.base)
+                a[c] = t < S ? in.base[t * kTP + n] : T(0);
+            else
+                a[c] = (t < S && (in.code == t || in.code >= S)) ? T(1) : T(0);
+#pragma unroll
+            for (int cb = 0; cb < NBW; ++cb) {
+                const int s = cb0 + 16 * cb + n;
+                b[c][cb] = (s < S && t < S) ? M[static_cast<size_t>(s) * S + t] : T(0);
+            }
         }
+#pragma unroll
+        for (int c = 0; c < kChunk; ++c)
+#pragma unroll
+            for (int cb = 0; cb < NBW; ++cb) out.v[cb] = mma(a[c], b[c][cb], out.v[cb]);
+    }
+}
+
+// out1 = M1 v and out2 = M2 v for the same input v (P p and dP p of one
+// child): one operand load of v per k-step feeds both products.
+template <typename T, int NBW>
+__device__ __forceinline__ void fwd2(const GLOBAL T* __restrict__ M1, const GLOBAL T* __restrict__ M2,
+                                     const Input<T>& in, int S, int cb0, int lane, Cols<T, NBW>& out1,
+                                     Cols<T, NBW>& out2) {
+    const int gq = lane >> 4, n = lane & 15;
+#pragma unroll
+    for (int cb = 0; cb < NBW; ++cb) out1.v[cb] = out2.v[cb] = V4<T>{0, 0, 0, 0};
+    const int KB = (S + 3) / 4;
+    for (int k0 = 0; k0 < KB; k0 += kChunk) {
+        T a[kChunk], b1[kChunk][NBW], b2[kChunk][NBW];
+#pragma unroll
+        for (int c = 0; c < kChunk; ++c) {
+            const int t = 4 * (k0 + c) + gq;
+            if (in.base)
+                a[c] = t < S ? in.base[t * kTP + n] : T(0);
+            else
+                a[c] = (t < S && (in.code == t || in.code >= S)) ? T(1) : T(0);
+#pragma unroll
+            for (int cb = 0; cb < NBW; ++cb) {
+                const int s = cb0 + 16 * cb + n;
+                const bool ok = s < S && t < S;
+                b1[c][cb] = ok ? M1[static_cast<size_t>(s) * S + t] : T(0);
+                b2[c][cb] = ok ? M2[static_cast<size_t>(s) * S + t] : T(0);
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < kChunk; ++c)
+#pragma unroll
+            for (int cb = 0; cb < NBW; ++cb) {
+                out1.v[cb] = mma(a[c], b1[c][cb], out1.v[cb]);
+                out2.v[cb] = mma(a[c], b2[c][cb], out2.v[cb]);
+            }
     }
 }
 
@@ -158,15 +205,22 @@ __device__ __forceinline__ void bwd(const GLOBAL T* __restrict__ M, const T* U, 
 #pragma unroll
     for (int cb = 0; cb < NBW; ++cb) out.v[cb] = V4<T>{0, 0, 0, 0};
     const int KB = (S + 3) / 4;
-    for (int kk = 0; kk < KB; ++kk) {
-        const int s = 4 * kk + gq;
-        const T a = s < S ? U[s * kLS + n] : T(0);
+    for (int k0 = 0; k0 < KB; k0 += kChunk) {
+        T a[kChunk], b[kChunk][NBW];
 #pragma unroll
-        for (int cb = 0; cb < NBW; ++cb) {
-            const int t = cb0 + 16 * cb + n;
-            const T b = (s < S && t < S) ? M[static_cast<size_t>(s) * S + t] : T(0);
-            out.v[cb] = mma(a, b, out.v[cb]);
+        for (int c = 0; c < kChunk; ++c) {
+            const int s = 4 * (k0 + c) + gq;
+            a[c] = s < S ? U[s * kLS + n] : T(0);
+#pragma unroll
+            for (int cb = 0; cb < NBW; ++cb) {
+                const int t = cb0 + 16 * cb + n;
+                b[c][cb] = (s < S && t < S) ? M[static_cast<size_t>(s) * S + t] : T(0);
+            }
         }
+#pragma unroll
+        for (int c = 0; c < kChunk; ++c)
+#pragma unroll
+            for (int cb = 0; cb < NBW; ++cb) out.v[cb] = mma(a[c], b[c][cb], out.v[cb]);
     }
 }
 
@@ -438,20 +492,19 @@ __global__ __launch_bounds__(64 * W) void pre_gl_kernel(const ReqDesc* __restric
         } else {
             load_cols<T, NBW>(qk_base + r * rstride, S, cb0, lane, qk);
         }
-        fwd<T, NBW>(P + mo_j, sj, S, cb0, lane, a);          // a = m_j
+        Cols<T, NBW> dmj;
+        fwd2<T, NBW>(P + mo_j, dP + mo_j, sj, S, cb0, lane, a, dmj);   // a = m_j, dm_j
 #pragma unroll
         for (int cb = 0; cb < NBW; ++cb) a.v[cb] *= qk.v[cb];   // a = u_i
         cols_to_lds<T, NBW>(Ui, S, cb0, lane, a);
-        fwd<T, NBW>(P + mo_i, si, S, cb0, lane, b);          // b = m_i
+        fwd2<T, NBW>(P + mo_i, dP + mo_i, si, S, cb0, lane, b, acc);   // b = m_i, acc = dm_i
         T dd[4] = {}, ni[4] = {}, nj[4] = {};
         dot_cols<T, NBW>(a, b, dd);                           // u_i . m_i
+        dot_cols<T, NBW>(a, acc, ni);                         // u_i . dm_i
 #pragma unroll
         for (int cb = 0; cb < NBW; ++cb) b.v[cb] *= qk.v[cb];   // b = u_j
         cols_to_lds<T, NBW>(Uj, S, cb0, lane, b);
-        fwd<T, NBW>(dP + mo_i, si, S, cb0, lane, acc);       // dm_i
-        dot_cols<T, NBW>(a, acc, ni);
-        fwd<T, NBW>(dP + mo_j, sj, S, cb0, lane, acc);       // dm_j
-        dot_cols<T, NBW>(b, acc, nj);
+        dot_cols<T, NBW>(b, dmj, nj);                         // u_j . dm_j
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             num_i[i] += wr * ni[i];
