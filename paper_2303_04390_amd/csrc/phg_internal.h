@@ -137,7 +137,11 @@ hipError_t launch_chain(const ChainArgs& a, bool time_tree, hipStream_t stream);
 
 // MFMA level kernels for 17..255 states (phg_kernels_gl.hip): one workgroup
 // per (node, 16-pattern tile), the waves splitting the output states.
-inline int gl_tile_patterns() { return 16; }
+// Row blocks of 16 patterns per tile: two for FP32 at 33..64 states (each
+// matrix operand then feeds two MFMAs), one otherwise (FP64 and wider state
+// spaces would need more registers than keep two waves per SIMD).
+inline int gl_row_blocks(int S, bool fp32) { return (fp32 && S > 32 && S <= 64) ? 2 : 1; }
+inline int gl_tile_patterns(int S, bool fp32) { return 16 * gl_row_blocks(S, fp32); }
 hipError_t launch_level_gl(KernelClass k, const ReqDesc& shape, const ReqDesc* descs,
                            const SegTable& t, hipStream_t stream);
 

@@ -1415,7 +1415,7 @@ hipError_t level_t(KernelClass k, int R, bool blocked, const ReqDesc* descs, con
 bool kernels_support(int S, int R) { return S >= 2 && S <= 255 && R >= 1 && R <= 64; }
 
 int tile_patterns(int S, int R, bool fp32) {
-    if (S > 16 && !uses_s4_kernels(S, R)) return gl_tile_patterns();
+    if (S > 16 && !uses_s4_kernels(S, R)) return gl_tile_patterns(S, fp32);
     return uses_s4_kernels(S, R) ? kLanes : gs_tile_patterns(fp32);
 }
 

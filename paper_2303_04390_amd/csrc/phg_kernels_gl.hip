@@ -3,10 +3,10 @@
 // FP32 path, f64 for the FP64 path).
 //
 // Same method as the other kernels (Methods: pruning equation, eq:preorder,
-// eq:gradient), as small matrix products over a tile of 16 patterns:
+// eq:gradient), as small matrix products over a tile of patterns:
 //   forward   m[c][s] = sum_t P[s][t] p[c][t]      (P_x p_x, dP_x p_x)
 //   backward  q[c][t] = sum_s u[c][s] P[s][t]      (q_x = P_x^T u_x)
-// One workgroup of W waves takes one (node, 16-pattern tile); wave w owns the
+// One workgroup of W waves takes one (node, pattern tile); wave w owns the
 // output states [w * 16 NBW, (w + 1) * 16 NBW) of every product (NBW column
 // blocks of 16; W = ceil(S / 16) waves of one block up to 64 states, four
 // waves above), and runs the full sum over input states itself:
@@ -17,9 +17,11 @@
 // and B[l/16][l%16]; the four output registers hold D[4(l/16)+i][l%16] (f32)
 // or D[4i+l/16][l%16] (f64).  A rows are the tile's patterns, B is P, D rows
 // are patterns: lane (g = l/16, n = l%16) holds state (column base + 16cb + n)
-// of patterns dpat(g, 0..3).
+// of patterns opat(rb, g, 0..3) for every row block rb.
 //
-// Partials are stored [slot][tile][r][state][16 patterns] (exact state count).
+// Partials are stored [slot][tile][r][state][TP patterns] (exact state count),
+// TP = 16 RB: RB = 2 row blocks for up to 64 states (each matrix operand then
+// feeds two MFMAs), 1 above.
 // Scaling as everywhere: one power-of-two exponent per (node, pattern) shared
 // by all categories and states; outputs are written unscaled category by
 // category and rescaled in place once the exponent is known.
@@ -50,8 +52,8 @@ template <typename T>
 using V4 = typename V4T<T>::type;
 typedef int I4 __attribute__((ext_vector_type(4)));
 
-constexpr int kTP = 16;      // patterns per tile
-constexpr int kLS = kTP + 1; // LDS row stride of a [state][pattern] vector
+// A tile is RB row blocks of 16 patterns (TP = 16 RB); a [state][pattern]
+// vector in LDS has row stride TP + 1.
 
 __device__ __forceinline__ V4<float> mma(float a, float b, V4<float> c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
@@ -73,10 +75,11 @@ __device__ __forceinline__ int exp_of(double x) {
     return e;
 }
 
-// Pattern of output register i for lane group gq.
+// Pattern (within the tile) of output register i of row block rb for lane
+// group gq.
 template <typename T>
-__device__ __forceinline__ int opat(int gq, int i) {
-    return sizeof(T) == 4 ? 4 * gq + i : 4 * i + gq;
+__device__ __forceinline__ int opat(int rb, int gq, int i) {
+    return 16 * rb + (sizeof(T) == 4 ? 4 * gq + i : 4 * i + gq);
 }
 
 template <typename V>
@@ -111,106 +114,90 @@ __device__ __forceinline__ int seg_of(const SegTable& t, int unit) {
     return s;
 }
 
-// This wave's columns of one vector: NBW blocks of 16 states, 4 patterns each.
-template <typename T, int NBW>
+// This wave's columns of one vector: RB x NBW blocks of 16 patterns x 16
+// states, 4 patterns per lane each.
+template <typename T, int RB, int NBW>
 struct Cols {
-    V4<T> v[NBW];
+    V4<T> v[RB][NBW];
 };
 
 // Where a child's input vector comes from.
-template <typename T>
+template <typename T, int RB>
 struct Input {
-    const GLOBAL T* base;   // stored [state][16] block of (slot, tile, r), or null for a tip
-    int code;               // a tip's code for pattern n of the tile
+    const GLOBAL T* base;   // stored [state][TP] block of (slot, tile, r), or null for a tip
+    int code[RB];           // a tip's codes for patterns 16 rb + n of the tile
 };
 
 // k-steps whose operands are loaded together before their MFMAs run (one
 // memory round trip per chunk instead of one per step).
 constexpr int kChunk = 8;
 
-// out = M v on this wave's columns: out[c][s] = sum_t M[s][t] in[c][t],
-// s = cb0 + 16 cb + n.
-template <typename T, int NBW>
-__device__ __forceinline__ void fwd(const GLOBAL T* __restrict__ M, const Input<T>& in, int S, int cb0,
-                                    int lane, Cols<T, NBW>& out) {
+template <typename T, int RB>
+__device__ __forceinline__ T a_operand(const Input<T, RB>& in, int t, int S, int rb, int n) {
+    constexpr int TP = 16 * RB;
+    if (in.base) return t < S ? in.base[t * TP + 16 * rb + n] : T(0);
+    return (t < S && (in.code[rb] == t || in.code[rb] >= S)) ? T(1) : T(0);
+}
+
+// out1 = M1 v (and, with M2, out2 = M2 v) on this wave's columns:
+// out[c][s] = sum_t M[s][t] in[c][t], s = cb0 + 16 cb + n.  One operand
+// stream of v feeds both products (P p and dP p of one child).
+template <typename T, int RB, int NBW, bool kTwo>
+__device__ __forceinline__ void fwd(const GLOBAL T* __restrict__ M1, const GLOBAL T* __restrict__ M2,
+                                    const Input<T, RB>& in, int S, int cb0, int lane, Cols<T, RB, NBW>& out1,
+                                    Cols<T, RB, NBW>& out2) {
     const int gq = lane >> 4, n = lane & 15;
 #pragma unroll
-    for (int cb = 0; cb < NBW; ++cb) out.v[cb] = V4<T>{0, 0, 0, 0};
+    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < NBW; ++cb) out1.v[rb][cb] = out2.v[rb][cb] = V4<T>{0, 0, 0, 0};
     const int KB = (S + 3) / 4;
     for (int k0 = 0; k0 < KB; k0 += kChunk) {
-        T a[kChunk], b[kChunk][NBW];
+        T a[kChunk][RB], b1[kChunk][NBW], b2[kChunk][NBW];
 #pragma unroll
         for (int c = 0; c < kChunk; ++c) {
             const int t = 4 * (k0 + c) + gq;           // t >= S past the last step
-            if (in.base)
-                a[c] = t < S ? in.base[t * kTP + n] : T(0);
-            else
-                a[c] = (t < S && (in.code == t || in.code >= S)) ? T(1) : T(0);
 #pragma unroll
-            for (int cb = 0; cb < NBW; ++cb) {
-                const int s = cb0 + 16 * cb + n;
-                b[c][cb] = (s < S && t < S) ? M[static_cast<size_t>(s) * S + t] : T(0);
-            }
-        }
-#pragma unroll
-        for (int c = 0; c < kChunk; ++c)
-#pragma unroll
-            for (int cb = 0; cb < NBW; ++cb) out.v[cb] = mma(a[c], b[c][cb], out.v[cb]);
-    }
-}
-
-// out1 = M1 v and out2 = M2 v for the same input v (P p and dP p of one
-// child): one operand load of v per k-step feeds both products.
-template <typename T, int NBW>
-__device__ __forceinline__ void fwd2(const GLOBAL T* __restrict__ M1, const GLOBAL T* __restrict__ M2,
-                                     const Input<T>& in, int S, int cb0, int lane, Cols<T, NBW>& out1,
-                                     Cols<T, NBW>& out2) {
-    const int gq = lane >> 4, n = lane & 15;
-#pragma unroll
-    for (int cb = 0; cb < NBW; ++cb) out1.v[cb] = out2.v[cb] = V4<T>{0, 0, 0, 0};
-    const int KB = (S + 3) / 4;
-    for (int k0 = 0; k0 < KB; k0 += kChunk) {
-        T a[kChunk], b1[kChunk][NBW], b2[kChunk][NBW];
-#pragma unroll
-        for (int c = 0; c < kChunk; ++c) {
-            const int t = 4 * (k0 + c) + gq;
-            if (in.base)
-                a[c] = t < S ? in.base[t * kTP + n] : T(0);
-            else
-                a[c] = (t < S && (in.code == t || in.code >= S)) ? T(1) : T(0);
+            for (int rb = 0; rb < RB; ++rb) a[c][rb] = a_operand<T, RB>(in, t, S, rb, n);
 #pragma unroll
             for (int cb = 0; cb < NBW; ++cb) {
                 const int s = cb0 + 16 * cb + n;
                 const bool ok = s < S && t < S;
                 b1[c][cb] = ok ? M1[static_cast<size_t>(s) * S + t] : T(0);
-                b2[c][cb] = ok ? M2[static_cast<size_t>(s) * S + t] : T(0);
+                if (kTwo) b2[c][cb] = ok ? M2[static_cast<size_t>(s) * S + t] : T(0);
             }
         }
 #pragma unroll
         for (int c = 0; c < kChunk; ++c)
 #pragma unroll
-            for (int cb = 0; cb < NBW; ++cb) {
-                out1.v[cb] = mma(a[c], b1[c][cb], out1.v[cb]);
-                out2.v[cb] = mma(a[c], b2[c][cb], out2.v[cb]);
-            }
+            for (int cb = 0; cb < NBW; ++cb)
+#pragma unroll
+                for (int rb = 0; rb < RB; ++rb) {
+                    out1.v[rb][cb] = mma(a[c][rb], b1[c][cb], out1.v[rb][cb]);
+                    if (kTwo) out2.v[rb][cb] = mma(a[c][rb], b2[c][cb], out2.v[rb][cb]);
+                }
     }
 }
 
 // out = M^T u on this wave's columns: out[c][t] = sum_s u[c][s] M[s][t],
-// u from LDS laid out [state][kLS].
-template <typename T, int NBW>
+// u from LDS laid out [state][TP + 1].
+template <typename T, int RB, int NBW>
 __device__ __forceinline__ void bwd(const GLOBAL T* __restrict__ M, const T* U, int S, int cb0, int lane,
-                                    Cols<T, NBW>& out) {
+                                    Cols<T, RB, NBW>& out) {
+    constexpr int LS = 16 * RB + 1;
     const int gq = lane >> 4, n = lane & 15;
 #pragma unroll
-    for (int cb = 0; cb < NBW; ++cb) out.v[cb] = V4<T>{0, 0, 0, 0};
+    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < NBW; ++cb) out.v[rb][cb] = V4<T>{0, 0, 0, 0};
     const int KB = (S + 3) / 4;
     for (int k0 = 0; k0 < KB; k0 += kChunk) {
-        T a[kChunk], b[kChunk][NBW];
+        T a[kChunk][RB], b[kChunk][NBW];
 #pragma unroll
         for (int c = 0; c < kChunk; ++c) {
             const int s = 4 * (k0 + c) + gq;
-            a[c] = s < S ? U[s * kLS + n] : T(0);
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb) a[c][rb] = s < S ? U[s * LS + 16 * rb + n] : T(0);
 #pragma unroll
             for (int cb = 0; cb < NBW; ++cb) {
                 const int t = cb0 + 16 * cb + n;
@@ -220,97 +207,128 @@ __device__ __forceinline__ void bwd(const GLOBAL T* __restrict__ M, const T* U, 
 #pragma unroll
         for (int c = 0; c < kChunk; ++c)
 #pragma unroll
-            for (int cb = 0; cb < NBW; ++cb) out.v[cb] = mma(a[c], b[c][cb], out.v[cb]);
+            for (int cb = 0; cb < NBW; ++cb)
+#pragma unroll
+                for (int rb = 0; rb < RB; ++rb) out.v[rb][cb] = mma(a[c][rb], b[c][cb], out.v[rb][cb]);
     }
 }
 
-// Stored [state][16] block <-> this wave's columns.
-template <typename T, int NBW>
+// Stored [state][TP] block <-> this wave's columns.
+template <typename T, int RB, int NBW>
 __device__ __forceinline__ void load_cols(const GLOBAL T* __restrict__ base, int S, int cb0, int lane,
-                                          Cols<T, NBW>& x) {
+                                          Cols<T, RB, NBW>& x) {
+    constexpr int TP = 16 * RB;
     const int gq = lane >> 4, n = lane & 15;
 #pragma unroll
     for (int cb = 0; cb < NBW; ++cb) {
         const int s = cb0 + 16 * cb + n;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) x.v[cb][i] = s < S ? base[s * kTP + opat<T>(gq, i)] : T(0);
+        for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) x.v[rb][cb][i] = s < S ? base[s * TP + opat<T>(rb, gq, i)] : T(0);
     }
 }
-template <typename T, int NBW>
+template <typename T, int RB, int NBW>
 __device__ __forceinline__ void store_cols(GLOBAL T* __restrict__ base, int S, int cb0, int lane,
-                                           const Cols<T, NBW>& x) {
+                                           const Cols<T, RB, NBW>& x) {
+    constexpr int TP = 16 * RB;
     const int gq = lane >> 4, n = lane & 15;
 #pragma unroll
     for (int cb = 0; cb < NBW; ++cb) {
         const int s = cb0 + 16 * cb + n;
         if (s < S) {
 #pragma unroll
-            for (int i = 0; i < 4; ++i) base[s * kTP + opat<T>(gq, i)] = x.v[cb][i];
+            for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) base[s * TP + opat<T>(rb, gq, i)] = x.v[rb][cb][i];
         }
     }
 }
-template <typename T, int NBW>
-__device__ __forceinline__ void cols_to_lds(T* U, int S, int cb0, int lane, const Cols<T, NBW>& x) {
+template <typename T, int RB, int NBW>
+__device__ __forceinline__ void cols_to_lds(T* U, int S, int cb0, int lane, const Cols<T, RB, NBW>& x) {
+    constexpr int LS = 16 * RB + 1;
     const int gq = lane >> 4, n = lane & 15;
 #pragma unroll
     for (int cb = 0; cb < NBW; ++cb) {
         const int s = cb0 + 16 * cb + n;
         if (s < S) {
 #pragma unroll
-            for (int i = 0; i < 4; ++i) U[s * kLS + opat<T>(gq, i)] = x.v[cb][i];
+            for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) U[s * LS + opat<T>(rb, gq, i)] = x.v[rb][cb][i];
         }
     }
+}
+
+template <typename T, int RB, int NBW>
+__device__ __forceinline__ void mul_cols(Cols<T, RB, NBW>& x, const Cols<T, RB, NBW>& y) {
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < NBW; ++cb) x.v[rb][cb] *= y.v[rb][cb];
 }
 
 // Per-pattern partial sum over this wave's columns of x * y.
-template <typename T, int NBW>
-__device__ __forceinline__ void dot_cols(const Cols<T, NBW>& x, const Cols<T, NBW>& y, T acc[4]) {
+template <typename T, int RB, int NBW>
+__device__ __forceinline__ void dot_cols(const Cols<T, RB, NBW>& x, const Cols<T, RB, NBW>& y, T acc[RB][4]) {
 #pragma unroll
-    for (int cb = 0; cb < NBW; ++cb)
+    for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
-        for (int i = 0; i < 4; ++i) acc[i] += x.v[cb][i] * y.v[cb][i];
+        for (int cb = 0; cb < NBW; ++cb)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) acc[rb][i] += x.v[rb][cb][i] * y.v[rb][cb][i];
 }
-template <typename T, int NBW>
-__device__ __forceinline__ void max_cols(const Cols<T, NBW>& x, T mx[4]) {
+template <typename T, int RB, int NBW>
+__device__ __forceinline__ void max_cols(const Cols<T, RB, NBW>& x, T mx[RB][4]) {
 #pragma unroll
-    for (int cb = 0; cb < NBW; ++cb)
+    for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
-        for (int i = 0; i < 4; ++i) mx[i] = fmax(mx[i], x.v[cb][i]);
+        for (int cb = 0; cb < NBW; ++cb)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) mx[rb][i] = fmax(mx[rb][i], x.v[rb][cb][i]);
 }
 
-// Maximum over the workgroup of per-pattern values held by lanes n == any of
-// group gq (after max16): via LDS, fixed order.  red has kWaves * 16 slots.
-template <typename T, int W>
-__device__ __forceinline__ void wg_max(T mx[4], T* red, int w, int lane) {
+// Maximum over the workgroup of per-pattern values (each lane's after max16):
+// via LDS, fixed order.  red has W * TP slots.
+template <typename T, int RB, int W>
+__device__ __forceinline__ void wg_max(T mx[RB][4], T* red, int w, int lane) {
+    constexpr int TP = 16 * RB;
     const int gq = lane >> 4, n = lane & 15;
     if (n == 0) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i) red[w * 16 + opat<T>(gq, i)] = mx[i];
+        for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) red[w * TP + opat<T>(rb, gq, i)] = mx[rb][i];
     }
     __syncthreads();
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        T m = red[opat<T>(gq, i)];
+    for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
-        for (int ww = 1; ww < W; ++ww) m = fmax(m, red[ww * 16 + opat<T>(gq, i)]);
-        mx[i] = m;
-    }
+        for (int i = 0; i < 4; ++i) {
+            T m = red[opat<T>(rb, gq, i)];
+#pragma unroll
+            for (int ww = 1; ww < W; ++ww) m = fmax(m, red[ww * TP + opat<T>(rb, gq, i)]);
+            mx[rb][i] = m;
+        }
     __syncthreads();
 }
 
 // Rescale this wave's columns of a stored (slot, tile) block, all categories.
-template <typename T, int NBW>
+template <typename T, int RB, int NBW>
 __device__ __forceinline__ void rescale_cols(GLOBAL T* __restrict__ slot_tile, int R, int S, int cb0, int lane,
-                                             const int e[4]) {
+                                             const int e[RB][4]) {
+    constexpr int TP = 16 * RB;
     for (int r = 0; r < R; ++r) {
-        GLOBAL T* base = slot_tile + static_cast<size_t>(r) * S * kTP;
-        Cols<T, NBW> x;
-        load_cols<T, NBW>(base, S, cb0, lane, x);
+        GLOBAL T* base = slot_tile + static_cast<size_t>(r) * S * TP;
+        Cols<T, RB, NBW> x;
+        load_cols<T, RB, NBW>(base, S, cb0, lane, x);
 #pragma unroll
-        for (int cb = 0; cb < NBW; ++cb)
+        for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
-            for (int i = 0; i < 4; ++i) x.v[cb][i] = scale2(x.v[cb][i], -e[i]);
-        store_cols<T, NBW>(base, S, cb0, lane, x);
+            for (int cb = 0; cb < NBW; ++cb)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) x.v[rb][cb][i] = scale2(x.v[rb][cb][i], -e[rb][i]);
+        store_cols<T, RB, NBW>(base, S, cb0, lane, x);
     }
 }
 
@@ -335,14 +353,23 @@ __device__ __forceinline__ bool gl_unit(const ReqDesc* __restrict__ descs, const
     return true;
 }
 
+template <typename T, int RB>
+__device__ __forceinline__ void tip_codes(Input<T, RB>& in, bool tip, int x, const ReqDesc& d, int tile, int n) {
+    constexpr int TP = 16 * RB;
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb)
+        in.code[rb] = tip ? static_cast<int>(g(d.codes)[static_cast<size_t>(x) * d.Cpad + tile * TP + 16 * rb + n])
+                          : 0;
+}
+
 // ---------------------------------------------------------------- post-order
 
-template <typename T, int NBW, int W>
+template <typename T, int RB, int NBW, int W>
 __global__ __launch_bounds__(64 * W) void post_gl_kernel(const ReqDesc* __restrict__ descs,
                                                          const SegTable segs) {
-    constexpr int kWaves = W;
-    __shared__ T red[kWaves * 16];
-    __shared__ double dred[kWaves * 16];
+    constexpr int TP = 16 * RB;
+    __shared__ T red[W * TP];
+    __shared__ double dred[W * TP];
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     const int gq = lane >> 4, n = lane & 15;
@@ -352,31 +379,32 @@ __global__ __launch_bounds__(64 * W) void post_gl_kernel(const ReqDesc* __restri
     const int N = d.N, S = d.S, R = d.R, Cpad = d.Cpad, tile = U.tile, tiles = U.tiles;
     const NodeTriple nt = U.nt;
     const int cb0 = w * 16 * NBW;
-    const size_t rstride = static_cast<size_t>(S) * kTP;
+    const size_t rstride = static_cast<size_t>(S) * TP;
     const size_t tstride = rstride * R;
     GLOBAL T* part = g(static_cast<T*>(d.part));
     const GLOBAL T* P = g(tabP<T>(d));
     const bool tip_i = nt.i < N, tip_j = nt.j < N;
-    const int c_n = tile * kTP + n;               // pattern of this lane's A row
-    Input<T> si{nullptr, tip_i ? static_cast<int>(g(d.codes)[static_cast<size_t>(nt.i) * Cpad + c_n]) : 0};
-    Input<T> sj{nullptr, tip_j ? static_cast<int>(g(d.codes)[static_cast<size_t>(nt.j) * Cpad + c_n]) : 0};
+    Input<T, RB> si, sj;
+    tip_codes<T, RB>(si, tip_i, nt.i, d, tile, n);
+    tip_codes<T, RB>(sj, tip_j, nt.j, d, tile, n);
     const GLOBAL T* pi_base = tip_i ? nullptr : part + (static_cast<size_t>(nt.i - N) * tiles + tile) * tstride;
     const GLOBAL T* pj_base = tip_j ? nullptr : part + (static_cast<size_t>(nt.j - N) * tiles + tile) * tstride;
     GLOBAL T* out_base = part + (static_cast<size_t>(nt.k - N) * tiles + tile) * tstride;
     const bool root = U.sg.flags & 1;
-    T mx[4] = {T(0), T(0), T(0), T(0)};
-    double site[4] = {0.0, 0.0, 0.0, 0.0};
+    T mx[RB][4] = {};
+    double site[RB][4] = {};
     for (int r = 0; r < R; ++r) {
         si.base = pi_base ? pi_base + r * rstride : nullptr;
         sj.base = pj_base ? pj_base + r * rstride : nullptr;
-        Cols<T, NBW> mi, mj;
-        fwd<T, NBW>(P + (static_cast<size_t>(nt.i) * R + r) * S * S, si, S, cb0, lane, mi);
-        fwd<T, NBW>(P + (static_cast<size_t>(nt.j) * R + r) * S * S, sj, S, cb0, lane, mj);
-#pragma unroll
-        for (int cb = 0; cb < NBW; ++cb) mi.v[cb] *= mj.v[cb];
+        Cols<T, RB, NBW> mi, mj, unused;
+        fwd<T, RB, NBW, false>(P + (static_cast<size_t>(nt.i) * R + r) * S * S, nullptr, si, S, cb0, lane, mi,
+                               unused);
+        fwd<T, RB, NBW, false>(P + (static_cast<size_t>(nt.j) * R + r) * S * S, nullptr, sj, S, cb0, lane, mj,
+                               unused);
+        mul_cols<T, RB, NBW>(mi, mj);
         if (!root) {
-            max_cols<T, NBW>(mi, mx);
-            store_cols<T, NBW>(out_base + r * rstride, S, cb0, lane, mi);
+            max_cols<T, RB, NBW>(mi, mx);
+            store_cols<T, RB, NBW>(out_base + r * rstride, S, cb0, lane, mi);
         } else {
             const double wr = g(d.cweights)[r];
 #pragma unroll
@@ -384,56 +412,72 @@ __global__ __launch_bounds__(64 * W) void post_gl_kernel(const ReqDesc* __restri
                 const int s = cb0 + 16 * cb + n;
                 const double ps = s < S ? g(d.pi)[s] : 0.0;
 #pragma unroll
-                for (int i = 0; i < 4; ++i) site[i] += wr * ps * static_cast<double>(mi.v[cb][i]);
+                for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) site[rb][i] += wr * ps * static_cast<double>(mi.v[rb][cb][i]);
             }
         }
     }
-    int ec[4];
+    int ec[RB][4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int c = tile * kTP + opat<T>(gq, i);
-        ec[i] = (tip_i ? 0 : g(d.expo)[static_cast<size_t>(nt.i - N) * Cpad + c]) +
-                (tip_j ? 0 : g(d.expo)[static_cast<size_t>(nt.j - N) * Cpad + c]);
-    }
+    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int c = tile * TP + opat<T>(rb, gq, i);
+            ec[rb][i] = (tip_i ? 0 : g(d.expo)[static_cast<size_t>(nt.i - N) * Cpad + c]) +
+                        (tip_j ? 0 : g(d.expo)[static_cast<size_t>(nt.j - N) * Cpad + c]);
+        }
     if (!root) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i) mx[i] = max16(mx[i]);
-        wg_max<T, W>(mx, red, w, lane);
-        int e[4];
+        for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
-        for (int i = 0; i < 4; ++i) e[i] = exp_of(mx[i]);
-        __syncthreads();      // every wave's unscaled columns are stored
-        rescale_cols<T, NBW>(out_base, R, S, cb0, lane, e);
+            for (int i = 0; i < 4; ++i) mx[rb][i] = max16(mx[rb][i]);
+        wg_max<T, RB, W>(mx, red, w, lane);
+        int e[RB][4];
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) e[rb][i] = exp_of(mx[rb][i]);
+        rescale_cols<T, RB, NBW>(out_base, R, S, cb0, lane, e);
         if (w == 0 && n == 0) {
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
-                g(d.expo)[static_cast<size_t>(nt.k - N) * Cpad + tile * kTP + opat<T>(gq, i)] = e[i] + ec[i];
+            for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    g(d.expo)[static_cast<size_t>(nt.k - N) * Cpad + tile * TP + opat<T>(rb, gq, i)] =
+                        e[rb][i] + ec[rb][i];
         }
     } else {
         // site likelihood: sum over this wave's states, then over waves (fixed order)
 #pragma unroll
-        for (int i = 0; i < 4; ++i) site[i] = sum16(site[i]);
+        for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) site[rb][i] = sum16(site[rb][i]);
         if (n == 0) {
 #pragma unroll
-            for (int i = 0; i < 4; ++i) dred[w * 16 + opat<T>(gq, i)] = site[i];
+            for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) dred[w * TP + opat<T>(rb, gq, i)] = site[rb][i];
         }
         __syncthreads();
         if (w == 0) {
             double tsum = 0.0;
             if (n == 0) {
 #pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const int p = opat<T>(gq, i);
-                    double sv = dred[p];
+                for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
-                    for (int ww = 1; ww < kWaves; ++ww) sv += dred[ww * 16 + p];
-                    const int c = tile * kTP + p;
-                    const double ll =
-                        (sv > 0.0 ? log(sv) : -INFINITY) + static_cast<double>(ec[i]) * 0.69314718055994530942;
-                    g(d.sll)[c] = ll;
-                    const double Wc = g(d.pw)[c];
-                    tsum += (Wc != 0.0) ? Wc * ll : 0.0;
-                }
+                    for (int i = 0; i < 4; ++i) {
+                        const int p = opat<T>(rb, gq, i);
+                        double sv = dred[p];
+#pragma unroll
+                        for (int ww = 1; ww < W; ++ww) sv += dred[ww * TP + p];
+                        const int c = tile * TP + p;
+                        const double ll = (sv > 0.0 ? log(sv) : -INFINITY) +
+                                          static_cast<double>(ec[rb][i]) * 0.69314718055994530942;
+                        g(d.sll)[c] = ll;
+                        const double Wc = g(d.pw)[c];
+                        tsum += (Wc != 0.0) ? Wc * ll : 0.0;
+                    }
             }
 #pragma unroll
             for (int off = 32; off >= 1; off >>= 1) tsum += __shfl_xor(tsum, off, 64);
@@ -444,140 +488,155 @@ __global__ __launch_bounds__(64 * W) void post_gl_kernel(const ReqDesc* __restri
 
 // ---------------------------------------------------------------- pre-order + gradient
 
-template <typename T, int NBW, int W>
+template <typename T, int RB, int NBW, int W>
 __global__ __launch_bounds__(64 * W) void pre_gl_kernel(const ReqDesc* __restrict__ descs,
                                                         const SegTable segs) {
-    constexpr int kWaves = W;
+    constexpr int TP = 16 * RB;
+    constexpr int LS = TP + 1;
     constexpr int SP = 16 * NBW * W;                // padded states held in LDS
-    __shared__ T Ui[SP * kLS];
-    __shared__ T Uj[SP * kLS];
-    __shared__ T red[3 * kWaves * 16];
+    __shared__ T Ui[SP * LS];
+    __shared__ T Uj[SP * LS];
+    __shared__ T red[3 * W * TP];
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     const int gq = lane >> 4, n = lane & 15;
     GlUnit U;
     if (!gl_unit(descs, segs, U)) return;
     const ReqDesc& d = *U.d;
-    const int N = d.N, S = d.S, R = d.R, Cpad = d.Cpad, tile = U.tile, tiles = U.tiles;
+    const int N = d.N, S = d.S, R = d.R, tile = U.tile, tiles = U.tiles;
     const NodeTriple nt = U.nt;
     const int cb0 = w * 16 * NBW;
-    const size_t rstride = static_cast<size_t>(S) * kTP;
+    const size_t rstride = static_cast<size_t>(S) * TP;
     const size_t tstride = rstride * R;
     GLOBAL T* part = g(static_cast<T*>(d.part));
     const GLOBAL T* P = g(tabP<T>(d));
     const GLOBAL T* dP = g(tabdP<T>(d));
     const bool is_root = nt.k == 2 * N - 2;
     const bool tip_i = nt.i < N, tip_j = nt.j < N;
-    const int c_n = tile * kTP + n;
-    Input<T> si{nullptr, tip_i ? static_cast<int>(g(d.codes)[static_cast<size_t>(nt.i) * Cpad + c_n]) : 0};
-    Input<T> sj{nullptr, tip_j ? static_cast<int>(g(d.codes)[static_cast<size_t>(nt.j) * Cpad + c_n]) : 0};
+    Input<T, RB> si, sj;
+    tip_codes<T, RB>(si, tip_i, nt.i, d, tile, n);
+    tip_codes<T, RB>(sj, tip_j, nt.j, d, tile, n);
     GLOBAL T* pi_base = tip_i ? nullptr : part + (static_cast<size_t>(nt.i - N) * tiles + tile) * tstride;
     GLOBAL T* pj_base = tip_j ? nullptr : part + (static_cast<size_t>(nt.j - N) * tiles + tile) * tstride;
     const GLOBAL T* qk_base = is_root ? nullptr : part + (static_cast<size_t>(nt.k - N) * tiles + tile) * tstride;
-    T num_i[4] = {}, num_j[4] = {}, den[4] = {}, mxi[4] = {}, mxj[4] = {};
+    T num_i[RB][4] = {}, num_j[RB][4] = {}, den[RB][4] = {}, mxi[RB][4] = {}, mxj[RB][4] = {};
     for (int r = 0; r < R; ++r) {
         si.base = pi_base ? pi_base + r * rstride : nullptr;
         sj.base = pj_base ? pj_base + r * rstride : nullptr;
         const size_t mo_i = (static_cast<size_t>(nt.i) * R + r) * S * S;
         const size_t mo_j = (static_cast<size_t>(nt.j) * R + r) * S * S;
         const T wr = static_cast<T>(g(d.cweights)[r]);
-        Cols<T, NBW> qk, a, b, acc;
+        Cols<T, RB, NBW> qk, a, b, acc, dmj;
         if (is_root) {
 #pragma unroll
             for (int cb = 0; cb < NBW; ++cb) {
                 const int s = cb0 + 16 * cb + n;
                 const T v = s < S ? static_cast<T>(g(d.pi)[s]) : T(0);
-                qk.v[cb] = V4<T>{v, v, v, v};
+#pragma unroll
+                for (int rb = 0; rb < RB; ++rb) qk.v[rb][cb] = V4<T>{v, v, v, v};
             }
         } else {
-            load_cols<T, NBW>(qk_base + r * rstride, S, cb0, lane, qk);
+            load_cols<T, RB, NBW>(qk_base + r * rstride, S, cb0, lane, qk);
         }
-        Cols<T, NBW> dmj;
-        fwd2<T, NBW>(P + mo_j, dP + mo_j, sj, S, cb0, lane, a, dmj);   // a = m_j, dm_j
+        fwd<T, RB, NBW, true>(P + mo_j, dP + mo_j, sj, S, cb0, lane, a, dmj);   // a = m_j, dm_j
+        mul_cols<T, RB, NBW>(a, qk);                                           // a = u_i
+        cols_to_lds<T, RB, NBW>(Ui, S, cb0, lane, a);
+        fwd<T, RB, NBW, true>(P + mo_i, dP + mo_i, si, S, cb0, lane, b, acc);  // b = m_i, acc = dm_i
+        T dd[RB][4] = {}, ni[RB][4] = {}, nj[RB][4] = {};
+        dot_cols<T, RB, NBW>(a, b, dd);                                        // u_i . m_i
+        dot_cols<T, RB, NBW>(a, acc, ni);                                      // u_i . dm_i
+        mul_cols<T, RB, NBW>(b, qk);                                           // b = u_j
+        cols_to_lds<T, RB, NBW>(Uj, S, cb0, lane, b);
+        dot_cols<T, RB, NBW>(b, dmj, nj);                                      // u_j . dm_j
 #pragma unroll
-        for (int cb = 0; cb < NBW; ++cb) a.v[cb] *= qk.v[cb];   // a = u_i
-        cols_to_lds<T, NBW>(Ui, S, cb0, lane, a);
-        fwd2<T, NBW>(P + mo_i, dP + mo_i, si, S, cb0, lane, b, acc);   // b = m_i, acc = dm_i
-        T dd[4] = {}, ni[4] = {}, nj[4] = {};
-        dot_cols<T, NBW>(a, b, dd);                           // u_i . m_i
-        dot_cols<T, NBW>(a, acc, ni);                         // u_i . dm_i
+        for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
-        for (int cb = 0; cb < NBW; ++cb) b.v[cb] *= qk.v[cb];   // b = u_j
-        cols_to_lds<T, NBW>(Uj, S, cb0, lane, b);
-        dot_cols<T, NBW>(b, dmj, nj);                         // u_j . dm_j
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            num_i[i] += wr * ni[i];
-            num_j[i] += wr * nj[i];
-            den[i] += wr * dd[i];
-        }
+            for (int i = 0; i < 4; ++i) {
+                num_i[rb][i] += wr * ni[rb][i];
+                num_j[rb][i] += wr * nj[rb][i];
+                den[rb][i] += wr * dd[rb][i];
+            }
         __syncthreads();      // u complete in LDS; every wave is done reading p_i, p_j of category r
         if (!tip_i) {
-            bwd<T, NBW>(P + mo_i, Ui, S, cb0, lane, acc);    // q_i = P_i^T u_i, unscaled, over p_i
-            max_cols<T, NBW>(acc, mxi);
-            store_cols<T, NBW>(pi_base + r * rstride, S, cb0, lane, acc);
+            bwd<T, RB, NBW>(P + mo_i, Ui, S, cb0, lane, acc);    // q_i = P_i^T u_i, unscaled, over p_i
+            max_cols<T, RB, NBW>(acc, mxi);
+            store_cols<T, RB, NBW>(pi_base + r * rstride, S, cb0, lane, acc);
         }
         if (!tip_j) {
-            bwd<T, NBW>(P + mo_j, Uj, S, cb0, lane, acc);
-            max_cols<T, NBW>(acc, mxj);
-            store_cols<T, NBW>(pj_base + r * rstride, S, cb0, lane, acc);
+            bwd<T, RB, NBW>(P + mo_j, Uj, S, cb0, lane, acc);
+            max_cols<T, RB, NBW>(acc, mxj);
+            store_cols<T, RB, NBW>(pj_base + r * rstride, S, cb0, lane, acc);
         }
         __syncthreads();      // before the next category overwrites u
     }
     if (!tip_i) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i) mxi[i] = max16(mxi[i]);
-        wg_max<T, W>(mxi, red, w, lane);
-        int e[4];
+        for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
-        for (int i = 0; i < 4; ++i) e[i] = exp_of(mxi[i]);
-        rescale_cols<T, NBW>(pi_base, R, S, cb0, lane, e);
+            for (int i = 0; i < 4; ++i) mxi[rb][i] = max16(mxi[rb][i]);
+        wg_max<T, RB, W>(mxi, red, w, lane);
+        int e[RB][4];
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) e[rb][i] = exp_of(mxi[rb][i]);
+        rescale_cols<T, RB, NBW>(pi_base, R, S, cb0, lane, e);
     }
     if (!tip_j) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i) mxj[i] = max16(mxj[i]);
-        wg_max<T, W>(mxj, red, w, lane);
-        int e[4];
+        for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
-        for (int i = 0; i < 4; ++i) e[i] = exp_of(mxj[i]);
-        rescale_cols<T, NBW>(pj_base, R, S, cb0, lane, e);
+            for (int i = 0; i < 4; ++i) mxj[rb][i] = max16(mxj[rb][i]);
+        wg_max<T, RB, W>(mxj, red, w, lane);
+        int e[RB][4];
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) e[rb][i] = exp_of(mxj[rb][i]);
+        rescale_cols<T, RB, NBW>(pj_base, R, S, cb0, lane, e);
     }
     // per-pattern sums over all states: this wave's part, then the waves in order
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        num_i[i] = sum16(num_i[i]);
-        num_j[i] = sum16(num_j[i]);
-        den[i] = sum16(den[i]);
-    }
-    if (n == 0) {
+    for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            const int p = opat<T>(gq, i);
-            red[(0 * kWaves + w) * 16 + p] = num_i[i];
-            red[(1 * kWaves + w) * 16 + p] = num_j[i];
-            red[(2 * kWaves + w) * 16 + p] = den[i];
+            num_i[rb][i] = sum16(num_i[rb][i]);
+            num_j[rb][i] = sum16(num_j[rb][i]);
+            den[rb][i] = sum16(den[rb][i]);
         }
+    if (n == 0) {
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int p = opat<T>(rb, gq, i);
+                red[(0 * W + w) * TP + p] = num_i[rb][i];
+                red[(1 * W + w) * TP + p] = num_j[rb][i];
+                red[(2 * W + w) * TP + p] = den[rb][i];
+            }
     }
     __syncthreads();
     if (w == 0) {
         double gi = 0.0, gj = 0.0;
         if (n == 0) {
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int p = opat<T>(gq, i);
-                T Ni = red[p], Nj = red[kWaves * 16 + p], Dn = red[2 * kWaves * 16 + p];
+            for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
-                for (int ww = 1; ww < kWaves; ++ww) {
-                    Ni += red[ww * 16 + p];
-                    Nj += red[(kWaves + ww) * 16 + p];
-                    Dn += red[(2 * kWaves + ww) * 16 + p];
+                for (int i = 0; i < 4; ++i) {
+                    const int p = opat<T>(rb, gq, i);
+                    T Ni = red[p], Nj = red[W * TP + p], Dn = red[2 * W * TP + p];
+#pragma unroll
+                    for (int ww = 1; ww < W; ++ww) {
+                        Ni += red[ww * TP + p];
+                        Nj += red[(W + ww) * TP + p];
+                        Dn += red[(2 * W + ww) * TP + p];
+                    }
+                    const double Wc = g(d.pw)[tile * TP + p];
+                    if (Wc != 0.0) {
+                        gi += Wc * (static_cast<double>(Ni) / static_cast<double>(Dn));
+                        gj += Wc * (static_cast<double>(Nj) / static_cast<double>(Dn));
+                    }
                 }
-                const double Wc = g(d.pw)[tile * kTP + p];
-                if (Wc != 0.0) {
-                    gi += Wc * (static_cast<double>(Ni) / static_cast<double>(Dn));
-                    gj += Wc * (static_cast<double>(Nj) / static_cast<double>(Dn));
-                }
-            }
         }
 #pragma unroll
         for (int off = 32; off >= 1; off >>= 1) {
@@ -594,24 +653,31 @@ __global__ __launch_bounds__(64 * W) void pre_gl_kernel(const ReqDesc* __restric
 template <typename T>
 hipError_t launch_gl_t(KernelClass k, int S, const ReqDesc* descs, const SegTable& t, hipStream_t st) {
     const int n_units = t.unit_begin[t.n];
-    // up to 64 states: one 16-state block per wave, ceil(S / 16) waves;
-    // above: four waves of ceil(S / 64) blocks each
+    // up to 64 states: one 16-state block per wave, ceil(S / 16) waves; above:
+    // four waves of ceil(S / 64) blocks
     const int nbw = S > 64 ? (S + 63) / 64 : 1;
     const int w = S > 64 ? 4 : (S + 15) / 16;
-#define PHG_GL_CASE(NBV, WV)                                                                                 \
-    if (nbw == NBV && w == WV) {                                                                             \
-        if (k == kPost)                                                                                      \
-            hipLaunchKernelGGL((post_gl_kernel<T, NBV, WV>), dim3(n_units), dim3(64 * WV), 0, st, descs, t); \
-        else                                                                                                 \
-            hipLaunchKernelGGL((pre_gl_kernel<T, NBV, WV>), dim3(n_units), dim3(64 * WV), 0, st, descs, t);  \
-        return hipGetLastError();                                                                            \
+    const int rb = gl_row_blocks(S, sizeof(T) == 4);
+#define PHG_GL_CASE(RBV, NBV, WV)                                                                           \
+    if (rb == RBV && nbw == NBV && w == WV) {                                                             \
+        if (k == kPost)                                                                                     \
+            hipLaunchKernelGGL((post_gl_kernel<T, RBV, NBV, WV>), dim3(n_units), dim3(64 * WV), 0, st, descs, \
+                               t);                                                                          \
+        else                                                                                                \
+            hipLaunchKernelGGL((pre_gl_kernel<T, RBV, NBV, WV>), dim3(n_units), dim3(64 * WV), 0, st, descs,  \
+                               t);                                                                          \
+        return hipGetLastError();                                                                           \
     }
-    PHG_GL_CASE(1, 2)
-    PHG_GL_CASE(1, 3)
-    PHG_GL_CASE(1, 4)
-    PHG_GL_CASE(2, 4)
-    PHG_GL_CASE(3, 4)
-    PHG_GL_CASE(4, 4)
+    if constexpr (sizeof(T) == 4) {
+        PHG_GL_CASE(2, 1, 3)
+        PHG_GL_CASE(2, 1, 4)
+    }
+    PHG_GL_CASE(1, 1, 2)
+    PHG_GL_CASE(1, 1, 3)
+    PHG_GL_CASE(1, 1, 4)
+    PHG_GL_CASE(1, 2, 4)
+    PHG_GL_CASE(1, 3, 4)
+    PHG_GL_CASE(1, 4, 4)
 #undef PHG_GL_CASE
     return hipErrorInvalidValue;
 }

@@ -67,7 +67,7 @@ def test_codon128_full(codon128, prec):
 
 @pytest.mark.parametrize("S,N,C", [(20, 9, 1), (20, 9, 37), (20, 9, 100), (61, 6, 33), (61, 6, 70),
                                    (2, 12, 50), (3, 12, 50), (5, 12, 50), (16, 12, 50), (17, 12, 50),
-                                   (33, 8, 50), (64, 6, 40)])
+                                   (33, 8, 50), (40, 7, 31), (48, 9, 97), (49, 7, 65), (64, 6, 40)])
 def test_state_counts_and_ragged_tiles(S, N, C):
     prob = generic_problem(N, S, C, seed=S * 100 + C)
     ref = oracle.evaluate_problem(prob)
