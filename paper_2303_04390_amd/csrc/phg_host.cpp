@@ -46,13 +46,29 @@ Plan make_plan(int N, int C, int S, int R, phg_precision prec) {
         off = align_up(off + bytes);
         return o;
     };
+    const bool fp32 = prec == PHG_FP32_SCALED;
     p.codes = take(static_cast<size_t>(N) * Cpad);
-    p.part = take(I * tiles * R * S * tp * tsz);
     p.expo = take(I * Cpad * sizeof(int32_t));
-    p.P64 = take(E * R * S * S * 8);
-    p.dP64 = take(E * R * S * S * 8);
-    p.P32 = take(prec == PHG_FP32_SCALED ? E * R * S * S * 4 : 0);
-    p.dP32 = take(prec == PHG_FP32_SCALED ? E * R * S * S * 4 : 0);
+    if (uses_gl_kernels(S, R)) {
+        // MFMA operand order: one forward table per matrix and a backward
+        // copy of P, in the path's own type only
+        const size_t mat = E * R * gl_mat_rows(S) * gl_row(S);
+        p.part = take(I * tiles * R * tp * gl_row(S) * tsz);
+        p.P64 = take(fp32 ? 0 : mat * 8);
+        p.dP64 = take(fp32 ? 0 : mat * 8);
+        p.PB64 = take(fp32 ? 0 : mat * 8);
+        p.P32 = take(fp32 ? mat * 4 : 0);
+        p.dP32 = take(fp32 ? mat * 4 : 0);
+        p.PB32 = take(fp32 ? mat * 4 : 0);
+    } else {
+        p.part = take(I * tiles * R * S * tp * tsz);
+        p.P64 = take(E * R * S * S * 8);
+        p.dP64 = take(E * R * S * S * 8);
+        p.P32 = take(fp32 ? E * R * S * S * 4 : 0);
+        p.dP32 = take(fp32 ? E * R * S * S * 4 : 0);
+        p.PB64 = take(0);
+        p.PB32 = take(0);
+    }
     const size_t tt = S == 4 ? E * R * 20 : 0;
     p.TT64 = take(tt * 8);
     p.dTT64 = take(tt * 8);
@@ -276,6 +292,8 @@ phg_status ensure_device(phg_context* ctx) {
     d.dP64 = reinterpret_cast<double*>(a + pl.dP64);
     d.P32 = reinterpret_cast<float*>(a + pl.P32);
     d.dP32 = reinterpret_cast<float*>(a + pl.dP32);
+    d.PB32 = reinterpret_cast<float*>(a + pl.PB32);
+    d.PB64 = reinterpret_cast<double*>(a + pl.PB64);
     d.TT64 = reinterpret_cast<double*>(a + pl.TT64);
     d.dTT64 = reinterpret_cast<double*>(a + pl.dTT64);
     d.TT32 = reinterpret_cast<float*>(a + pl.TT32);

@@ -31,6 +31,8 @@ struct BlockRec {
 // alignment with its own workspace).  Layouts (T = float or double):
 //   codes  uint8  [N][Cpad]                  tip states, S = all-ones, pad = S
 //   part   T      4 states: [N-1][tiles][R][64][4] (lane-major quads)
+//                 17..255 states: [N-1][tiles][R][TP][gl_row(S)] (pattern
+//                   rows in the MFMA operand order gl_col, zero-padded)
 //                 otherwise: [N-1][tiles][R][S][TP] (state rows of TP patterns)
 //                                             post-order partial of each
 //                                             internal node (slot = id - N);
@@ -38,7 +40,11 @@ struct BlockRec {
 //                                             pre-order partial
 //   expo   int32  [N-1][Cpad]                cumulative power-of-two exponent
 //                                             of the subtree below each node
-//   P64,dP64 double [E][R][S][S]; P32,dP32 float copies (FP32 path only)
+//   P64,dP64 double [E][R][S][S]; P32,dP32 float copies (FP32 path only);
+//                 17..255 states: only the table of the path's type T, as
+//                 [E][R][gl_mat_rows(S)][gl_row(S)] with row s holding P[s][t]
+//                 at column gl_col(t) (forward operand), and PB32 / PB64 the
+//                 same with row t holding P[s][t] at gl_col(s) (backward)
 //   sll    double [Cpad]                     per-pattern log site likelihood
 //   lpart  double [tiles]                    per-tile weighted log-likelihood
 //   gpart  double [E][tiles]                 per-tile weighted gradient sums
@@ -56,6 +62,8 @@ struct ReqDesc {
     double* dP64;
     float* P32;
     float* dP32;
+    float* PB32;
+    double* PB64;
     // 4 states: tip tables [E][R][5][4]: entry y (0..3) is column y of P (or
     // dP), entry 4 its row sums (the ambiguous code), so P e_y is one load
     double* TT64;
@@ -136,7 +144,23 @@ struct ChainArgs {
 hipError_t launch_chain(const ChainArgs& a, bool time_tree, hipStream_t stream);
 
 // MFMA level kernels for 17..255 states (phg_kernels_gl.hip): one workgroup
-// per (node, 16-pattern tile), the waves splitting the output states.
+// per (node, pattern tile), the waves splitting the output states.
+inline bool uses_gl_kernels(int S, int R) { return S > 16 && !uses_s4_kernels(S, R); }
+// Their operand order: a stored vector (one pattern's partial) or matrix row
+// holds state t at column gl_col(t) = (t mod 4) KBP + t / 4, so the states
+// 4k + g that MFMA lane group g consumes on k-steps k, k+1, ... are adjacent
+// and G of them arrive by one 8- or 16-byte load (G = gl_vec(S)); columns of
+// states >= S hold zeros.  Matrices have gl_mat_rows(S) rows (zero-padded to
+// the kernels' 16- or 64-state column blocks).
+__host__ __device__ constexpr inline int gl_vec(int S) { return S <= 32 ? 2 : 4; }
+__host__ __device__ constexpr inline int gl_kbp(int S) {
+    return ((S + 3) / 4 + gl_vec(S) - 1) / gl_vec(S) * gl_vec(S);
+}
+__host__ __device__ constexpr inline int gl_row(int S) { return 4 * gl_kbp(S); }
+__host__ __device__ constexpr inline int gl_col(int t, int kbp) { return (t & 3) * kbp + (t >> 2); }
+__host__ __device__ constexpr inline int gl_mat_rows(int S) {
+    return S <= 64 ? (S + 15) / 16 * 16 : (S + 63) / 64 * 64;
+}
 // Row blocks of 16 patterns per tile: two for FP32 at 33..64 states (each
 // matrix operand then feeds two MFMAs), one otherwise (FP64 and wider state
 // spaces would need more registers than keep two waves per SIMD).
@@ -144,6 +168,8 @@ inline int gl_row_blocks(int S, bool fp32) { return (fp32 && S > 32 && S <= 64) 
 inline int gl_tile_patterns(int S, bool fp32) { return 16 * gl_row_blocks(S, fp32); }
 hipError_t launch_level_gl(KernelClass k, const ReqDesc& shape, const ReqDesc* descs,
                            const SegTable& t, hipStream_t stream);
+// P(t) tables of those kernels (forward P, dP and backward P in operand order).
+hipError_t launch_pmat_gl(const ReqDesc& shape, const ReqDesc* descs, const SegTable& t, hipStream_t stream);
 
 // MFMA level kernels for other state counts (phg_kernels_gs.hip).
 int gs_tile_patterns(bool fp32);

@@ -1415,7 +1415,7 @@ hipError_t level_t(KernelClass k, int R, bool blocked, const ReqDesc* descs, con
 bool kernels_support(int S, int R) { return S >= 2 && S <= 255 && R >= 1 && R <= 64; }
 
 int tile_patterns(int S, int R, bool fp32) {
-    if (S > 16 && !uses_s4_kernels(S, R)) return gl_tile_patterns(S, fp32);
+    if (uses_gl_kernels(S, R)) return gl_tile_patterns(S, fp32);
     return uses_s4_kernels(S, R) ? kLanes : gs_tile_patterns(fp32);
 }
 
@@ -1438,13 +1438,15 @@ hipError_t launch_class(KernelClass k, const ReqDesc& shape, const ReqDesc* desc
             if (shape.S == 4) {
                 hipLaunchKernelGGL(pmat4_kernel, dim3((4 * n_units + kPmatBlock - 1) / kPmatBlock),
                                    dim3(kPmatBlock), 0, st, descs, t);
+            } else if (uses_gl_kernels(shape.S, shape.R)) {
+                return launch_pmat_gl(shape, descs, t, st);
             } else {
                 hipLaunchKernelGGL(pmat_block_kernel, dim3(n_units), dim3(256), 0, st, descs, t);
             }
             return hipGetLastError();
         case kPost:
         case kPre:
-            if (shape.S > 16 && !uses_s4_kernels(shape.S, shape.R)) return launch_level_gl(k, shape, descs, t, st);
+            if (uses_gl_kernels(shape.S, shape.R)) return launch_level_gl(k, shape, descs, t, st);
             if (!uses_s4_kernels(shape.S, shape.R)) return launch_level_gs(k, shape, descs, t, st);
             if (shape.fp32) return level_t<float>(k, shape.R, shape.blocked != 0, descs, t, st);
             return level_t<double>(k, shape.R, shape.blocked != 0, descs, t, st);

@@ -19,9 +19,13 @@
 // are patterns: lane (g = l/16, n = l%16) holds state (column base + 16cb + n)
 // of patterns opat(rb, g, 0..3) for every row block rb.
 //
-// Partials are stored [slot][tile][r][state][TP patterns] (exact state count),
-// TP = 16 RB: RB = 2 row blocks for up to 64 states (each matrix operand then
-// feeds two MFMAs), 1 above.
+// Operand order (gl_col): a stored vector or matrix row holds state t at
+// column (t mod 4) KBP + t / 4, so the states lane group g consumes on
+// consecutive k-steps (4k + g) are adjacent: G = 2 or 4 k-steps of an operand
+// arrive by one 8- or 16-byte load.  Partials are stored
+// [slot][tile][r][TP patterns][row], TP = 16 RB; the forward matrices P, dP
+// as [row s][column of t] and P a second time as [row t][column of s] for
+// the backward product, all zero-padded, so no operand load is masked.
 // Scaling as everywhere: one power-of-two exponent per (node, pattern) shared
 // by all categories and states; outputs are written unscaled category by
 // category and rescaled in place once the exponent is known.
@@ -95,18 +99,28 @@ __device__ __forceinline__ V max16(V v) {
     return v;
 }
 
+// Forward tables of P and dP and the backward table of P, in the path's type.
 template <typename T>
-__device__ __forceinline__ const T* tabP(const ReqDesc& d);
+__device__ __forceinline__ T* tabP(const ReqDesc& d);
 template <>
-__device__ __forceinline__ const float* tabP<float>(const ReqDesc& d) { return d.P32; }
+__device__ __forceinline__ float* tabP<float>(const ReqDesc& d) { return d.P32; }
 template <>
-__device__ __forceinline__ const double* tabP<double>(const ReqDesc& d) { return d.P64; }
+__device__ __forceinline__ double* tabP<double>(const ReqDesc& d) { return d.P64; }
 template <typename T>
-__device__ __forceinline__ const T* tabdP(const ReqDesc& d);
+__device__ __forceinline__ T* tabdP(const ReqDesc& d);
 template <>
-__device__ __forceinline__ const float* tabdP<float>(const ReqDesc& d) { return d.dP32; }
+__device__ __forceinline__ float* tabdP<float>(const ReqDesc& d) { return d.dP32; }
 template <>
-__device__ __forceinline__ const double* tabdP<double>(const ReqDesc& d) { return d.dP64; }
+__device__ __forceinline__ double* tabdP<double>(const ReqDesc& d) { return d.dP64; }
+template <typename T>
+__device__ __forceinline__ T* tabPB(const ReqDesc& d);
+template <>
+__device__ __forceinline__ float* tabPB<float>(const ReqDesc& d) { return d.PB32; }
+template <>
+__device__ __forceinline__ double* tabPB<double>(const ReqDesc& d) { return d.PB64; }
+
+template <typename T, int G>
+using VecG = T __attribute__((ext_vector_type(G)));
 
 __device__ __forceinline__ int seg_of(const SegTable& t, int unit) {
     int s = 0;
@@ -124,7 +138,7 @@ struct Cols {
 // Where a child's input vector comes from.
 template <typename T, int RB>
 struct Input {
-    const GLOBAL T* base;   // stored [state][TP] block of (slot, tile, r), or null for a tip
+    const GLOBAL T* base;   // stored [TP][row] block of (slot, tile, r), or null for a tip
     int code[RB];           // a tip's codes for patterns 16 rb + n of the tile
 };
 
@@ -132,43 +146,85 @@ struct Input {
 // memory round trip per chunk instead of one per step).
 constexpr int kChunk = 8;
 
-template <typename T, int RB>
-__device__ __forceinline__ T a_operand(const Input<T, RB>& in, int t, int S, int rb, int n) {
-    constexpr int TP = 16 * RB;
-    if (in.base) return t < S ? in.base[t * TP + 16 * rb + n] : T(0);
-    return (t < S && (in.code[rb] == t || in.code[rb] >= S)) ? T(1) : T(0);
+// Operand geometry shared by the products of one kernel.
+struct Geo {
+    int S;      // states
+    int kbp;    // k-steps per lane group in a row (gl_kbp)
+    int row;    // row length (4 kbp)
+};
+
+// G adjacent operand values (k-steps k .. k+G-1 of this lane) from a row.
+template <typename T, int G>
+__device__ __forceinline__ void load_run(const GLOBAL T* __restrict__ p, T (&out)[G]) {
+    const VecG<T, G> v = *reinterpret_cast<const GLOBAL VecG<T, G>*>(p);
+#pragma unroll
+    for (int j = 0; j < G; ++j) out[j] = v[j];
 }
 
 // out1 = M1 v (and, with M2, out2 = M2 v) on this wave's columns:
-// out[c][s] = sum_t M[s][t] in[c][t], s = cb0 + 16 cb + n.  One operand
-// stream of v feeds both products (P p and dP p of one child).
-template <typename T, int RB, int NBW, bool kTwo>
+// out[c][s] = sum_t M[s][t] in[c][t], s = cb0 + 16 cb + n, from forward
+// tables.  One operand stream of v feeds both products (P p and dP p of one
+// child).
+template <typename T, int RB, int NBW, int G, bool kTwo>
 __device__ __forceinline__ void fwd(const GLOBAL T* __restrict__ M1, const GLOBAL T* __restrict__ M2,
-                                    const Input<T, RB>& in, int S, int cb0, int lane, Cols<T, RB, NBW>& out1,
-                                    Cols<T, RB, NBW>& out2) {
+                                    const Input<T, RB>& in, const Geo& ge, int cb0, int lane,
+                                    Cols<T, RB, NBW>& out1, Cols<T, RB, NBW>& out2) {
     const int gq = lane >> 4, n = lane & 15;
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
         for (int cb = 0; cb < NBW; ++cb) out1.v[rb][cb] = out2.v[rb][cb] = V4<T>{0, 0, 0, 0};
-    const int KB = (S + 3) / 4;
-    for (int k0 = 0; k0 < KB; k0 += kChunk) {
+    const int off = gq * ge.kbp;
+    const GLOBAL T* ar[RB];
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb) ar[rb] = in.base ? in.base + (16 * rb + n) * ge.row + off : nullptr;
+    const GLOBAL T* br1[NBW];
+    const GLOBAL T* br2[NBW];
+#pragma unroll
+    for (int cb = 0; cb < NBW; ++cb) {
+        const size_t o = static_cast<size_t>(cb0 + 16 * cb + n) * ge.row + off;
+        br1[cb] = M1 + o;
+        br2[cb] = kTwo ? M2 + o : M1;
+    }
+    for (int k0 = 0; k0 < ge.kbp; k0 += kChunk) {
         T a[kChunk][RB], b1[kChunk][NBW], b2[kChunk][NBW];
 #pragma unroll
-        for (int c = 0; c < kChunk; ++c) {
-            const int t = 4 * (k0 + c) + gq;           // t >= S past the last step
+        for (int v = 0; v < kChunk / G; ++v) {
+            const int k = k0 + v * G;
+            if (k < ge.kbp) {             // uniform; rows are padded to whole runs
 #pragma unroll
-            for (int rb = 0; rb < RB; ++rb) a[c][rb] = a_operand<T, RB>(in, t, S, rb, n);
+                for (int rb = 0; rb < RB; ++rb) {
+                    if (in.base) {
+                        T x[G];
+                        load_run<T, G>(ar[rb] + k, x);
 #pragma unroll
-            for (int cb = 0; cb < NBW; ++cb) {
-                const int s = cb0 + 16 * cb + n;
-                const bool ok = s < S && t < S;
-                b1[c][cb] = ok ? M1[static_cast<size_t>(s) * S + t] : T(0);
-                if (kTwo) b2[c][cb] = ok ? M2[static_cast<size_t>(s) * S + t] : T(0);
+                        for (int j = 0; j < G; ++j) a[v * G + j][rb] = x[j];
+                    } else {
+#pragma unroll
+                        for (int j = 0; j < G; ++j) {
+                            const int t = 4 * (k + j) + gq;
+                            a[v * G + j][rb] =
+                                (t < ge.S && (in.code[rb] == t || in.code[rb] >= ge.S)) ? T(1) : T(0);
+                        }
+                    }
+                }
+#pragma unroll
+                for (int cb = 0; cb < NBW; ++cb) {
+                    T x[G];
+                    load_run<T, G>(br1[cb] + k, x);
+#pragma unroll
+                    for (int j = 0; j < G; ++j) b1[v * G + j][cb] = x[j];
+                    if (kTwo) {
+                        load_run<T, G>(br2[cb] + k, x);
+#pragma unroll
+                        for (int j = 0; j < G; ++j) b2[v * G + j][cb] = x[j];
+                    }
+                }
             }
         }
 #pragma unroll
-        for (int c = 0; c < kChunk; ++c)
+        for (int c = 0; c < kChunk; ++c) {
+            if (k0 + c >= ge.kbp) break;
 #pragma unroll
             for (int cb = 0; cb < NBW; ++cb)
 #pragma unroll
@@ -176,82 +232,97 @@ __device__ __forceinline__ void fwd(const GLOBAL T* __restrict__ M1, const GLOBA
                     out1.v[rb][cb] = mma(a[c][rb], b1[c][cb], out1.v[rb][cb]);
                     if (kTwo) out2.v[rb][cb] = mma(a[c][rb], b2[c][cb], out2.v[rb][cb]);
                 }
+        }
     }
 }
 
-// out = M^T u on this wave's columns: out[c][t] = sum_s u[c][s] M[s][t],
-// u from LDS laid out [state][TP + 1].
-template <typename T, int RB, int NBW>
-__device__ __forceinline__ void bwd(const GLOBAL T* __restrict__ M, const T* U, int S, int cb0, int lane,
-                                    Cols<T, RB, NBW>& out) {
+// out = M^T u on this wave's columns: out[c][t] = sum_s u[c][s] M[s][t], from
+// the backward table (row t), u from LDS laid out [state][TP + 1].
+template <typename T, int RB, int NBW, int G>
+__device__ __forceinline__ void bwd(const GLOBAL T* __restrict__ MB, const T* U, const Geo& ge, int cb0,
+                                    int lane, Cols<T, RB, NBW>& out) {
     constexpr int LS = 16 * RB + 1;
     const int gq = lane >> 4, n = lane & 15;
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
         for (int cb = 0; cb < NBW; ++cb) out.v[rb][cb] = V4<T>{0, 0, 0, 0};
-    const int KB = (S + 3) / 4;
-    for (int k0 = 0; k0 < KB; k0 += kChunk) {
+    const int off = gq * ge.kbp;
+    const GLOBAL T* br[NBW];
+#pragma unroll
+    for (int cb = 0; cb < NBW; ++cb) br[cb] = MB + static_cast<size_t>(cb0 + 16 * cb + n) * ge.row + off;
+    for (int k0 = 0; k0 < ge.kbp; k0 += kChunk) {
         T a[kChunk][RB], b[kChunk][NBW];
 #pragma unroll
-        for (int c = 0; c < kChunk; ++c) {
-            const int s = 4 * (k0 + c) + gq;
+        for (int v = 0; v < kChunk / G; ++v) {
+            const int k = k0 + v * G;
+            if (k < ge.kbp) {
 #pragma unroll
-            for (int rb = 0; rb < RB; ++rb) a[c][rb] = s < S ? U[s * LS + 16 * rb + n] : T(0);
+                for (int j = 0; j < G; ++j) {
+                    const int s = 4 * (k + j) + gq;      // < row: LDS rows cover it, zeros past S
 #pragma unroll
-            for (int cb = 0; cb < NBW; ++cb) {
-                const int t = cb0 + 16 * cb + n;
-                b[c][cb] = (s < S && t < S) ? M[static_cast<size_t>(s) * S + t] : T(0);
+                    for (int rb = 0; rb < RB; ++rb) a[v * G + j][rb] = U[s * LS + 16 * rb + n];
+                }
+#pragma unroll
+                for (int cb = 0; cb < NBW; ++cb) {
+                    T x[G];
+                    load_run<T, G>(br[cb] + k, x);
+#pragma unroll
+                    for (int j = 0; j < G; ++j) b[v * G + j][cb] = x[j];
+                }
             }
         }
 #pragma unroll
-        for (int c = 0; c < kChunk; ++c)
+        for (int c = 0; c < kChunk; ++c) {
+            if (k0 + c >= ge.kbp) break;
 #pragma unroll
             for (int cb = 0; cb < NBW; ++cb)
 #pragma unroll
                 for (int rb = 0; rb < RB; ++rb) out.v[rb][cb] = mma(a[c][rb], b[c][cb], out.v[rb][cb]);
+        }
     }
 }
 
-// Stored [state][TP] block <-> this wave's columns.
+// Stored [TP][row] block <-> this wave's columns (states past S are zeros in
+// both; states past the row do not exist).
 template <typename T, int RB, int NBW>
-__device__ __forceinline__ void load_cols(const GLOBAL T* __restrict__ base, int S, int cb0, int lane,
+__device__ __forceinline__ void load_cols(const GLOBAL T* __restrict__ base, const Geo& ge, int cb0, int lane,
                                           Cols<T, RB, NBW>& x) {
-    constexpr int TP = 16 * RB;
     const int gq = lane >> 4, n = lane & 15;
 #pragma unroll
     for (int cb = 0; cb < NBW; ++cb) {
         const int s = cb0 + 16 * cb + n;
+        const int col = gl_col(s, ge.kbp);
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
-            for (int i = 0; i < 4; ++i) x.v[rb][cb][i] = s < S ? base[s * TP + opat<T>(rb, gq, i)] : T(0);
+            for (int i = 0; i < 4; ++i) x.v[rb][cb][i] = s < ge.row ? base[opat<T>(rb, gq, i) * ge.row + col] : T(0);
     }
 }
 template <typename T, int RB, int NBW>
-__device__ __forceinline__ void store_cols(GLOBAL T* __restrict__ base, int S, int cb0, int lane,
+__device__ __forceinline__ void store_cols(GLOBAL T* __restrict__ base, const Geo& ge, int cb0, int lane,
                                            const Cols<T, RB, NBW>& x) {
-    constexpr int TP = 16 * RB;
     const int gq = lane >> 4, n = lane & 15;
 #pragma unroll
     for (int cb = 0; cb < NBW; ++cb) {
         const int s = cb0 + 16 * cb + n;
-        if (s < S) {
+        const int col = gl_col(s, ge.kbp);
+        if (s < ge.row) {
 #pragma unroll
             for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
-                for (int i = 0; i < 4; ++i) base[s * TP + opat<T>(rb, gq, i)] = x.v[rb][cb][i];
+                for (int i = 0; i < 4; ++i) base[opat<T>(rb, gq, i) * ge.row + col] = x.v[rb][cb][i];
         }
     }
 }
 template <typename T, int RB, int NBW>
-__device__ __forceinline__ void cols_to_lds(T* U, int S, int cb0, int lane, const Cols<T, RB, NBW>& x) {
+__device__ __forceinline__ void cols_to_lds(T* U, const Geo& ge, int cb0, int lane, const Cols<T, RB, NBW>& x) {
     constexpr int LS = 16 * RB + 1;
     const int gq = lane >> 4, n = lane & 15;
 #pragma unroll
     for (int cb = 0; cb < NBW; ++cb) {
         const int s = cb0 + 16 * cb + n;
-        if (s < S) {
+        if (s < ge.row) {
 #pragma unroll
             for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
@@ -315,20 +386,20 @@ __device__ __forceinline__ void wg_max(T mx[RB][4], T* red, int w, int lane) {
 
 // Rescale this wave's columns of a stored (slot, tile) block, all categories.
 template <typename T, int RB, int NBW>
-__device__ __forceinline__ void rescale_cols(GLOBAL T* __restrict__ slot_tile, int R, int S, int cb0, int lane,
-                                             const int e[RB][4]) {
+__device__ __forceinline__ void rescale_cols(GLOBAL T* __restrict__ slot_tile, int R, const Geo& ge, int cb0,
+                                             int lane, const int e[RB][4]) {
     constexpr int TP = 16 * RB;
     for (int r = 0; r < R; ++r) {
-        GLOBAL T* base = slot_tile + static_cast<size_t>(r) * S * TP;
+        GLOBAL T* base = slot_tile + static_cast<size_t>(r) * TP * ge.row;
         Cols<T, RB, NBW> x;
-        load_cols<T, RB, NBW>(base, S, cb0, lane, x);
+        load_cols<T, RB, NBW>(base, ge, cb0, lane, x);
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
             for (int cb = 0; cb < NBW; ++cb)
 #pragma unroll
                 for (int i = 0; i < 4; ++i) x.v[rb][cb][i] = scale2(x.v[rb][cb][i], -e[rb][i]);
-        store_cols<T, RB, NBW>(base, S, cb0, lane, x);
+        store_cols<T, RB, NBW>(base, ge, cb0, lane, x);
     }
 }
 
@@ -368,6 +439,7 @@ template <typename T, int RB, int NBW, int W>
 __global__ __launch_bounds__(64 * W) void post_gl_kernel(const ReqDesc* __restrict__ descs,
                                                          const SegTable segs) {
     constexpr int TP = 16 * RB;
+    constexpr int G = (NBW == 1 && W <= 2) ? 2 : 4;   // gl_vec: 2 up to 32 states
     __shared__ T red[W * TP];
     __shared__ double dred[W * TP];
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -379,8 +451,10 @@ __global__ __launch_bounds__(64 * W) void post_gl_kernel(const ReqDesc* __restri
     const int N = d.N, S = d.S, R = d.R, Cpad = d.Cpad, tile = U.tile, tiles = U.tiles;
     const NodeTriple nt = U.nt;
     const int cb0 = w * 16 * NBW;
-    const size_t rstride = static_cast<size_t>(S) * TP;
+    const Geo ge{S, gl_kbp(S), gl_row(S)};
+    const size_t rstride = static_cast<size_t>(TP) * ge.row;
     const size_t tstride = rstride * R;
+    const size_t mstride = static_cast<size_t>(gl_mat_rows(S)) * ge.row;   // one (branch, category) table
     GLOBAL T* part = g(static_cast<T*>(d.part));
     const GLOBAL T* P = g(tabP<T>(d));
     const bool tip_i = nt.i < N, tip_j = nt.j < N;
@@ -397,14 +471,14 @@ __global__ __launch_bounds__(64 * W) void post_gl_kernel(const ReqDesc* __restri
         si.base = pi_base ? pi_base + r * rstride : nullptr;
         sj.base = pj_base ? pj_base + r * rstride : nullptr;
         Cols<T, RB, NBW> mi, mj, unused;
-        fwd<T, RB, NBW, false>(P + (static_cast<size_t>(nt.i) * R + r) * S * S, nullptr, si, S, cb0, lane, mi,
-                               unused);
-        fwd<T, RB, NBW, false>(P + (static_cast<size_t>(nt.j) * R + r) * S * S, nullptr, sj, S, cb0, lane, mj,
-                               unused);
+        fwd<T, RB, NBW, G, false>(P + (static_cast<size_t>(nt.i) * R + r) * mstride, nullptr, si, ge, cb0, lane,
+                                  mi, unused);
+        fwd<T, RB, NBW, G, false>(P + (static_cast<size_t>(nt.j) * R + r) * mstride, nullptr, sj, ge, cb0, lane,
+                                  mj, unused);
         mul_cols<T, RB, NBW>(mi, mj);
         if (!root) {
             max_cols<T, RB, NBW>(mi, mx);
-            store_cols<T, RB, NBW>(out_base + r * rstride, S, cb0, lane, mi);
+            store_cols<T, RB, NBW>(out_base + r * rstride, ge, cb0, lane, mi);
         } else {
             const double wr = g(d.cweights)[r];
 #pragma unroll
@@ -438,7 +512,7 @@ __global__ __launch_bounds__(64 * W) void post_gl_kernel(const ReqDesc* __restri
         for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
             for (int i = 0; i < 4; ++i) e[rb][i] = exp_of(mx[rb][i]);
-        rescale_cols<T, RB, NBW>(out_base, R, S, cb0, lane, e);
+        rescale_cols<T, RB, NBW>(out_base, R, ge, cb0, lane, e);
         if (w == 0 && n == 0) {
 #pragma unroll
             for (int rb = 0; rb < RB; ++rb)
@@ -493,6 +567,7 @@ __global__ __launch_bounds__(64 * W) void pre_gl_kernel(const ReqDesc* __restric
                                                         const SegTable segs) {
     constexpr int TP = 16 * RB;
     constexpr int LS = TP + 1;
+    constexpr int G = (NBW == 1 && W <= 2) ? 2 : 4;   // gl_vec: 2 up to 32 states
     constexpr int SP = 16 * NBW * W;                // padded states held in LDS
     __shared__ T Ui[SP * LS];
     __shared__ T Uj[SP * LS];
@@ -506,11 +581,14 @@ __global__ __launch_bounds__(64 * W) void pre_gl_kernel(const ReqDesc* __restric
     const int N = d.N, S = d.S, R = d.R, tile = U.tile, tiles = U.tiles;
     const NodeTriple nt = U.nt;
     const int cb0 = w * 16 * NBW;
-    const size_t rstride = static_cast<size_t>(S) * TP;
+    const Geo ge{S, gl_kbp(S), gl_row(S)};
+    const size_t rstride = static_cast<size_t>(TP) * ge.row;
     const size_t tstride = rstride * R;
+    const size_t mstride = static_cast<size_t>(gl_mat_rows(S)) * ge.row;   // one (branch, category) table
     GLOBAL T* part = g(static_cast<T*>(d.part));
     const GLOBAL T* P = g(tabP<T>(d));
     const GLOBAL T* dP = g(tabdP<T>(d));
+    const GLOBAL T* PB = g(tabPB<T>(d));
     const bool is_root = nt.k == 2 * N - 2;
     const bool tip_i = nt.i < N, tip_j = nt.j < N;
     Input<T, RB> si, sj;
@@ -523,8 +601,8 @@ __global__ __launch_bounds__(64 * W) void pre_gl_kernel(const ReqDesc* __restric
     for (int r = 0; r < R; ++r) {
         si.base = pi_base ? pi_base + r * rstride : nullptr;
         sj.base = pj_base ? pj_base + r * rstride : nullptr;
-        const size_t mo_i = (static_cast<size_t>(nt.i) * R + r) * S * S;
-        const size_t mo_j = (static_cast<size_t>(nt.j) * R + r) * S * S;
+        const size_t mo_i = (static_cast<size_t>(nt.i) * R + r) * mstride;
+        const size_t mo_j = (static_cast<size_t>(nt.j) * R + r) * mstride;
         const T wr = static_cast<T>(g(d.cweights)[r]);
         Cols<T, RB, NBW> qk, a, b, acc, dmj;
         if (is_root) {
@@ -536,17 +614,17 @@ __global__ __launch_bounds__(64 * W) void pre_gl_kernel(const ReqDesc* __restric
                 for (int rb = 0; rb < RB; ++rb) qk.v[rb][cb] = V4<T>{v, v, v, v};
             }
         } else {
-            load_cols<T, RB, NBW>(qk_base + r * rstride, S, cb0, lane, qk);
+            load_cols<T, RB, NBW>(qk_base + r * rstride, ge, cb0, lane, qk);
         }
-        fwd<T, RB, NBW, true>(P + mo_j, dP + mo_j, sj, S, cb0, lane, a, dmj);   // a = m_j, dm_j
+        fwd<T, RB, NBW, G, true>(P + mo_j, dP + mo_j, sj, ge, cb0, lane, a, dmj);   // a = m_j, dm_j
         mul_cols<T, RB, NBW>(a, qk);                                           // a = u_i
-        cols_to_lds<T, RB, NBW>(Ui, S, cb0, lane, a);
-        fwd<T, RB, NBW, true>(P + mo_i, dP + mo_i, si, S, cb0, lane, b, acc);  // b = m_i, acc = dm_i
+        cols_to_lds<T, RB, NBW>(Ui, ge, cb0, lane, a);
+        fwd<T, RB, NBW, G, true>(P + mo_i, dP + mo_i, si, ge, cb0, lane, b, acc);  // b = m_i, acc = dm_i
         T dd[RB][4] = {}, ni[RB][4] = {}, nj[RB][4] = {};
         dot_cols<T, RB, NBW>(a, b, dd);                                        // u_i . m_i
         dot_cols<T, RB, NBW>(a, acc, ni);                                      // u_i . dm_i
         mul_cols<T, RB, NBW>(b, qk);                                           // b = u_j
-        cols_to_lds<T, RB, NBW>(Uj, S, cb0, lane, b);
+        cols_to_lds<T, RB, NBW>(Uj, ge, cb0, lane, b);
         dot_cols<T, RB, NBW>(b, dmj, nj);                                      // u_j . dm_j
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb)
@@ -558,14 +636,14 @@ __global__ __launch_bounds__(64 * W) void pre_gl_kernel(const ReqDesc* __restric
             }
         __syncthreads();      // u complete in LDS; every wave is done reading p_i, p_j of category r
         if (!tip_i) {
-            bwd<T, RB, NBW>(P + mo_i, Ui, S, cb0, lane, acc);    // q_i = P_i^T u_i, unscaled, over p_i
+            bwd<T, RB, NBW, G>(PB + mo_i, Ui, ge, cb0, lane, acc);    // q_i = P_i^T u_i, unscaled, over p_i
             max_cols<T, RB, NBW>(acc, mxi);
-            store_cols<T, RB, NBW>(pi_base + r * rstride, S, cb0, lane, acc);
+            store_cols<T, RB, NBW>(pi_base + r * rstride, ge, cb0, lane, acc);
         }
         if (!tip_j) {
-            bwd<T, RB, NBW>(P + mo_j, Uj, S, cb0, lane, acc);
+            bwd<T, RB, NBW, G>(PB + mo_j, Uj, ge, cb0, lane, acc);
             max_cols<T, RB, NBW>(acc, mxj);
-            store_cols<T, RB, NBW>(pj_base + r * rstride, S, cb0, lane, acc);
+            store_cols<T, RB, NBW>(pj_base + r * rstride, ge, cb0, lane, acc);
         }
         __syncthreads();      // before the next category overwrites u
     }
@@ -580,7 +658,7 @@ __global__ __launch_bounds__(64 * W) void pre_gl_kernel(const ReqDesc* __restric
         for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
             for (int i = 0; i < 4; ++i) e[rb][i] = exp_of(mxi[rb][i]);
-        rescale_cols<T, RB, NBW>(pi_base, R, S, cb0, lane, e);
+        rescale_cols<T, RB, NBW>(pi_base, R, ge, cb0, lane, e);
     }
     if (!tip_j) {
 #pragma unroll
@@ -593,7 +671,7 @@ __global__ __launch_bounds__(64 * W) void pre_gl_kernel(const ReqDesc* __restric
         for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
             for (int i = 0; i < 4; ++i) e[rb][i] = exp_of(mxj[rb][i]);
-        rescale_cols<T, RB, NBW>(pj_base, R, S, cb0, lane, e);
+        rescale_cols<T, RB, NBW>(pj_base, R, ge, cb0, lane, e);
     }
     // per-pattern sums over all states: this wave's part, then the waves in order
 #pragma unroll
@@ -650,6 +728,76 @@ __global__ __launch_bounds__(64 * W) void pre_gl_kernel(const ReqDesc* __restric
     }
 }
 
+// ---------------------------------------------------------------- P(t) tables
+
+// One workgroup per (branch, category) pair: P = V diag(exp(g lam b)) V^-1 and
+// dP = V diag(g lam exp(g lam b)) V^-1 (FP64 sums, stored in the path's
+// type), written as the forward tables of P and dP and the backward table of
+// P, zeros included.  A thread takes a 4 x 4 block of (s, t), so each V and
+// V^-1 value it loads feeds four products.
+template <typename T>
+__global__ __launch_bounds__(256) void pmat_gl_kernel(const ReqDesc* __restrict__ descs, const SegTable segs) {
+    __shared__ double ex[256], dex[256];
+    const int unit = blockIdx.x;
+    if (unit >= segs.unit_begin[segs.n]) return;
+    const int sidx = seg_of(segs, unit);
+    const ReqDesc& d = descs[segs.seg[sidx].desc];
+    const int pair = unit - segs.unit_begin[sidx];
+    const int R = d.R, S = d.S;
+    const int x = pair / R;
+    const int r = pair - x * R;
+    const double gr = d.rates[r];
+    const double bt = gr * d.b[x];
+    const double* lam = d.lam + (d.eig_cat ? r * S : 0);
+    const double* V = d.V + (d.eig_cat ? static_cast<size_t>(r) * S * S : 0);
+    const double* Vinv = d.Vinv + (d.eig_cat ? static_cast<size_t>(r) * S * S : 0);
+    for (int k = threadIdx.x; k < S; k += blockDim.x) {
+        const double e = exp(lam[k] * bt);
+        ex[k] = e;
+        dex[k] = gr * lam[k] * e;
+    }
+    __syncthreads();
+    const int rows = gl_mat_rows(S), row = gl_row(S), kbp = gl_kbp(S);
+    const size_t base = static_cast<size_t>(pair) * rows * row;
+    GLOBAL T* PF = g(tabP<T>(d)) + base;
+    GLOBAL T* dPF = g(tabdP<T>(d)) + base;
+    GLOBAL T* PB = g(tabPB<T>(d)) + base;
+    const int nb = rows / 4;
+    for (int blk = threadIdx.x; blk < nb * nb; blk += blockDim.x) {
+        const int s0 = (blk / nb) * 4, t0 = (blk % nb) * 4;
+        double acc[4][4] = {}, dacc[4][4] = {};
+        if (s0 < S && t0 < S) {
+            for (int k = 0; k < S; ++k) {
+                double vs[4], vt[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) vs[i] = s0 + i < S ? V[(s0 + i) * S + k] : 0.0;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) vt[j] = t0 + j < S ? Vinv[k * S + t0 + j] : 0.0;
+                const double e = ex[k], de = dex[k];
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const double v = vs[i] * vt[j];
+                        acc[i][j] += v * e;
+                        dacc[i][j] += v * de;
+                    }
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int sr = s0 + i, tc = t0 + j;
+                if (tc < row) {
+                    PF[static_cast<size_t>(sr) * row + gl_col(tc, kbp)] = static_cast<T>(acc[i][j]);
+                    dPF[static_cast<size_t>(sr) * row + gl_col(tc, kbp)] = static_cast<T>(dacc[i][j]);
+                }
+                if (sr < row) PB[static_cast<size_t>(tc) * row + gl_col(sr, kbp)] = static_cast<T>(acc[i][j]);
+            }
+    }
+}
+
 template <typename T>
 hipError_t launch_gl_t(KernelClass k, int S, const ReqDesc* descs, const SegTable& t, hipStream_t st) {
     const int n_units = t.unit_begin[t.n];
@@ -683,6 +831,15 @@ hipError_t launch_gl_t(KernelClass k, int S, const ReqDesc* descs, const SegTabl
 }
 
 }  // namespace
+
+hipError_t launch_pmat_gl(const ReqDesc& shape, const ReqDesc* descs, const SegTable& t, hipStream_t st) {
+    const int n_units = t.unit_begin[t.n];
+    if (shape.fp32)
+        hipLaunchKernelGGL(pmat_gl_kernel<float>, dim3(n_units), dim3(256), 0, st, descs, t);
+    else
+        hipLaunchKernelGGL(pmat_gl_kernel<double>, dim3(n_units), dim3(256), 0, st, descs, t);
+    return hipGetLastError();
+}
 
 hipError_t launch_level_gl(KernelClass k, const ReqDesc& shape, const ReqDesc* descs, const SegTable& t,
                            hipStream_t st) {
