@@ -16,7 +16,7 @@ namespace phg {
 
 // Workspace plan: byte offsets of every device buffer inside one arena.
 struct Plan {
-    size_t codes, part, expo, P64, dP64, P32, dP32, PB32, PB64, TT64, dTT64, TT32, dTT32, b, V, Vinv, lam, rates, cw,
+    size_t codes, part, expo, eloc, P64, dP64, P32, dP32, PB32, PB64, TT64, dTT64, TT32, dTT32, b, V, Vinv, lam, rates, cw,
         pi, pw, sll, lpart, gpart, out, sched, desc, ch_parent, ch_kids, heights, trates, set_ptr, set_idx,
         total;
 };

@@ -54,6 +54,7 @@ Plan make_plan(int N, int C, int S, int R, phg_precision prec) {
         // copy of P, in the path's own type only
         const size_t mat = E * R * gl_mat_rows(S) * gl_row(S);
         p.part = take(I * tiles * R * tp * gl_row(S) * tsz);
+        p.eloc = take(I * Cpad * sizeof(int32_t));
         p.P64 = take(fp32 ? 0 : mat * 8);
         p.dP64 = take(fp32 ? 0 : mat * 8);
         p.PB64 = take(fp32 ? 0 : mat * 8);
@@ -62,6 +63,7 @@ Plan make_plan(int N, int C, int S, int R, phg_precision prec) {
         p.PB32 = take(fp32 ? mat * 4 : 0);
     } else {
         p.part = take(I * tiles * R * S * tp * tsz);
+        p.eloc = take(0);
         p.P64 = take(E * R * S * S * 8);
         p.dP64 = take(E * R * S * S * 8);
         p.P32 = take(fp32 ? E * R * S * S * 4 : 0);
@@ -288,6 +290,7 @@ phg_status ensure_device(phg_context* ctx) {
     d.codes = reinterpret_cast<const uint8_t*>(a + pl.codes);
     d.part = a + pl.part;
     d.expo = reinterpret_cast<int32_t*>(a + pl.expo);
+    d.eloc = reinterpret_cast<int32_t*>(a + pl.eloc);
     d.P64 = reinterpret_cast<double*>(a + pl.P64);
     d.dP64 = reinterpret_cast<double*>(a + pl.dP64);
     d.P32 = reinterpret_cast<float*>(a + pl.P32);

@@ -40,6 +40,10 @@ struct BlockRec {
 //                                             pre-order partial
 //   expo   int32  [N-1][Cpad]                cumulative power-of-two exponent
 //                                             of the subtree below each node
+//   eloc   int32  [N-1][Cpad]                17..255 states: the node's own
+//                                             exponent e; its stored partial
+//                                             is 2^e times the normalised one
+//                                             (after the pre-order: that of q)
 //   P64,dP64 double [E][R][S][S]; P32,dP32 float copies (FP32 path only);
 //                 17..255 states: only the table of the path's type T, as
 //                 [E][R][gl_mat_rows(S)][gl_row(S)] with row s holding P[s][t]
@@ -58,6 +62,7 @@ struct ReqDesc {
     const uint8_t* codes;
     void* part;
     int32_t* expo;
+    int32_t* eloc;
     double* P64;
     double* dP64;
     float* P32;

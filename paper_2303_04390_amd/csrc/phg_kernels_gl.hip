@@ -26,9 +26,13 @@
 // [slot][tile][r][TP patterns][row], TP = 16 RB; the forward matrices P, dP
 // as [row s][column of t] and P a second time as [row t][column of s] for
 // the backward product, all zero-padded, so no operand load is masked.
-// Scaling as everywhere: one power-of-two exponent per (node, pattern) shared
-// by all categories and states; outputs are written unscaled category by
-// category and rescaled in place once the exponent is known.
+// Scaling: one power-of-two exponent e per (node, pattern), shared by all
+// categories and states, as in the other kernels, but applied by the
+// consumer: a kernel stores its outputs unscaled, category by category, and
+// records e (eloc); whoever reads them scales its MFMA outputs (rows =
+// patterns) by 2^-e.  Power-of-two scaling commutes exactly with the
+// products, so this equals storing normalised partials, without a second
+// pass over the outputs.
 #include "phg_internal.h"
 
 #include <math.h>
@@ -143,8 +147,12 @@ struct Input {
 };
 
 // k-steps whose operands are loaded together before their MFMAs run (one
-// memory round trip per chunk instead of one per step).
-constexpr int kChunk = 8;
+// memory round trip per chunk instead of one per step): 8, or 4 for f64 with
+// three or more column blocks per wave (registers).
+template <typename T, int NBW>
+constexpr int chunk_of() {
+    return (sizeof(T) == 8 && NBW >= 3) ? 4 : 8;
+}
 
 // Operand geometry shared by the products of one kernel.
 struct Geo {
@@ -186,6 +194,7 @@ __device__ __forceinline__ void fwd(const GLOBAL T* __restrict__ M1, const GLOBA
         br1[cb] = M1 + o;
         br2[cb] = kTwo ? M2 + o : M1;
     }
+    constexpr int kChunk = chunk_of<T, NBW>();
     for (int k0 = 0; k0 < ge.kbp; k0 += kChunk) {
         T a[kChunk][RB], b1[kChunk][NBW], b2[kChunk][NBW];
 #pragma unroll
@@ -251,6 +260,7 @@ __device__ __forceinline__ void bwd(const GLOBAL T* __restrict__ MB, const T* U,
     const GLOBAL T* br[NBW];
 #pragma unroll
     for (int cb = 0; cb < NBW; ++cb) br[cb] = MB + static_cast<size_t>(cb0 + 16 * cb + n) * ge.row + off;
+    constexpr int kChunk = chunk_of<T, NBW>();
     for (int k0 = 0; k0 < ge.kbp; k0 += kChunk) {
         T a[kChunk][RB], b[kChunk][NBW];
 #pragma unroll
@@ -384,22 +394,30 @@ __device__ __forceinline__ void wg_max(T mx[RB][4], T* red, int w, int lane) {
     __syncthreads();
 }
 
-// Rescale this wave's columns of a stored (slot, tile) block, all categories.
+// x *= 2^-e per pattern row, e from LDS (TP exponents of one node).
 template <typename T, int RB, int NBW>
-__device__ __forceinline__ void rescale_cols(GLOBAL T* __restrict__ slot_tile, int R, const Geo& ge, int cb0,
-                                             int lane, const int e[RB][4]) {
-    constexpr int TP = 16 * RB;
-    for (int r = 0; r < R; ++r) {
-        GLOBAL T* base = slot_tile + static_cast<size_t>(r) * TP * ge.row;
-        Cols<T, RB, NBW> x;
-        load_cols<T, RB, NBW>(base, ge, cb0, lane, x);
+__device__ __forceinline__ void scale_rows(Cols<T, RB, NBW>& x, const int* e, int lane) {
+    const int gq = lane >> 4;
 #pragma unroll
-        for (int rb = 0; rb < RB; ++rb)
+    for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
-            for (int cb = 0; cb < NBW; ++cb)
+        for (int i = 0; i < 4; ++i) {
+            const int ei = e[opat<T>(rb, gq, i)];
 #pragma unroll
-                for (int i = 0; i < 4; ++i) x.v[rb][cb][i] = scale2(x.v[rb][cb][i], -e[rb][i]);
-        store_cols<T, RB, NBW>(base, ge, cb0, lane, x);
+            for (int cb = 0; cb < NBW; ++cb) x.v[rb][cb][i] = scale2(x.v[rb][cb][i], -ei);
+        }
+}
+
+// Stage the own exponents (eloc) of up to three nodes for the tile's
+// patterns in LDS: row c holds node[c]'s, zeros for a tip or a negative id.
+// The caller synchronises.
+template <int TP, int NC>
+__device__ __forceinline__ void stage_exps(int (&esh)[NC][TP], const int (&node)[NC], const ReqDesc& d, int tile) {
+    const int N = d.N;
+    for (int t = threadIdx.x; t < NC * TP; t += blockDim.x) {
+        const int c = t / TP, p = t - c * TP;
+        const int x = node[c];
+        esh[c][p] = x >= N ? g(d.eloc)[static_cast<size_t>(x - N) * d.Cpad + tile * TP + p] : 0;
     }
 }
 
@@ -442,6 +460,7 @@ __global__ __launch_bounds__(64 * W) void post_gl_kernel(const ReqDesc* __restri
     constexpr int G = (NBW == 1 && W <= 2) ? 2 : 4;   // gl_vec: 2 up to 32 states
     __shared__ T red[W * TP];
     __shared__ double dred[W * TP];
+    __shared__ int esh[2][TP];                      // own exponents of the children
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     const int gq = lane >> 4, n = lane & 15;
@@ -465,6 +484,11 @@ __global__ __launch_bounds__(64 * W) void post_gl_kernel(const ReqDesc* __restri
     const GLOBAL T* pj_base = tip_j ? nullptr : part + (static_cast<size_t>(nt.j - N) * tiles + tile) * tstride;
     GLOBAL T* out_base = part + (static_cast<size_t>(nt.k - N) * tiles + tile) * tstride;
     const bool root = U.sg.flags & 1;
+    {
+        const int kids[2] = {nt.i, nt.j};
+        stage_exps<TP, 2>(esh, kids, d, tile);
+    }
+    __syncthreads();
     T mx[RB][4] = {};
     double site[RB][4] = {};
     for (int r = 0; r < R; ++r) {
@@ -473,8 +497,10 @@ __global__ __launch_bounds__(64 * W) void post_gl_kernel(const ReqDesc* __restri
         Cols<T, RB, NBW> mi, mj, unused;
         fwd<T, RB, NBW, G, false>(P + (static_cast<size_t>(nt.i) * R + r) * mstride, nullptr, si, ge, cb0, lane,
                                   mi, unused);
+        if (!tip_i) scale_rows<T, RB, NBW>(mi, esh[0], lane);
         fwd<T, RB, NBW, G, false>(P + (static_cast<size_t>(nt.j) * R + r) * mstride, nullptr, sj, ge, cb0, lane,
                                   mj, unused);
+        if (!tip_j) scale_rows<T, RB, NBW>(mj, esh[1], lane);
         mul_cols<T, RB, NBW>(mi, mj);
         if (!root) {
             max_cols<T, RB, NBW>(mi, mx);
@@ -512,14 +538,15 @@ __global__ __launch_bounds__(64 * W) void post_gl_kernel(const ReqDesc* __restri
         for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
             for (int i = 0; i < 4; ++i) e[rb][i] = exp_of(mx[rb][i]);
-        rescale_cols<T, RB, NBW>(out_base, R, ge, cb0, lane, e);
         if (w == 0 && n == 0) {
 #pragma unroll
             for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
-                for (int i = 0; i < 4; ++i)
-                    g(d.expo)[static_cast<size_t>(nt.k - N) * Cpad + tile * TP + opat<T>(rb, gq, i)] =
-                        e[rb][i] + ec[rb][i];
+                for (int i = 0; i < 4; ++i) {
+                    const size_t c = static_cast<size_t>(nt.k - N) * Cpad + tile * TP + opat<T>(rb, gq, i);
+                    g(d.eloc)[c] = e[rb][i];
+                    g(d.expo)[c] = e[rb][i] + ec[rb][i];
+                }
         }
     } else {
         // site likelihood: sum over this wave's states, then over waves (fixed order)
@@ -572,13 +599,14 @@ __global__ __launch_bounds__(64 * W) void pre_gl_kernel(const ReqDesc* __restric
     __shared__ T Ui[SP * LS];
     __shared__ T Uj[SP * LS];
     __shared__ T red[3 * W * TP];
+    __shared__ int esh[3][TP];                      // own exponents: p_i, p_j (post-order), q_k
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     const int gq = lane >> 4, n = lane & 15;
     GlUnit U;
     if (!gl_unit(descs, segs, U)) return;
     const ReqDesc& d = *U.d;
-    const int N = d.N, S = d.S, R = d.R, tile = U.tile, tiles = U.tiles;
+    const int N = d.N, S = d.S, R = d.R, Cpad = d.Cpad, tile = U.tile, tiles = U.tiles;
     const NodeTriple nt = U.nt;
     const int cb0 = w * 16 * NBW;
     const Geo ge{S, gl_kbp(S), gl_row(S)};
@@ -597,6 +625,11 @@ __global__ __launch_bounds__(64 * W) void pre_gl_kernel(const ReqDesc* __restric
     GLOBAL T* pi_base = tip_i ? nullptr : part + (static_cast<size_t>(nt.i - N) * tiles + tile) * tstride;
     GLOBAL T* pj_base = tip_j ? nullptr : part + (static_cast<size_t>(nt.j - N) * tiles + tile) * tstride;
     const GLOBAL T* qk_base = is_root ? nullptr : part + (static_cast<size_t>(nt.k - N) * tiles + tile) * tstride;
+    {
+        const int nodes[3] = {nt.i, nt.j, is_root ? -1 : nt.k};
+        stage_exps<TP, 3>(esh, nodes, d, tile);
+    }
+    __syncthreads();
     T num_i[RB][4] = {}, num_j[RB][4] = {}, den[RB][4] = {}, mxi[RB][4] = {}, mxj[RB][4] = {};
     for (int r = 0; r < R; ++r) {
         si.base = pi_base ? pi_base + r * rstride : nullptr;
@@ -615,11 +648,20 @@ __global__ __launch_bounds__(64 * W) void pre_gl_kernel(const ReqDesc* __restric
             }
         } else {
             load_cols<T, RB, NBW>(qk_base + r * rstride, ge, cb0, lane, qk);
+            scale_rows<T, RB, NBW>(qk, esh[2], lane);
         }
         fwd<T, RB, NBW, G, true>(P + mo_j, dP + mo_j, sj, ge, cb0, lane, a, dmj);   // a = m_j, dm_j
+        if (!tip_j) {
+            scale_rows<T, RB, NBW>(a, esh[1], lane);
+            scale_rows<T, RB, NBW>(dmj, esh[1], lane);
+        }
         mul_cols<T, RB, NBW>(a, qk);                                           // a = u_i
         cols_to_lds<T, RB, NBW>(Ui, ge, cb0, lane, a);
         fwd<T, RB, NBW, G, true>(P + mo_i, dP + mo_i, si, ge, cb0, lane, b, acc);  // b = m_i, acc = dm_i
+        if (!tip_i) {
+            scale_rows<T, RB, NBW>(b, esh[0], lane);
+            scale_rows<T, RB, NBW>(acc, esh[0], lane);
+        }
         T dd[RB][4] = {}, ni[RB][4] = {}, nj[RB][4] = {};
         dot_cols<T, RB, NBW>(a, b, dd);                                        // u_i . m_i
         dot_cols<T, RB, NBW>(a, acc, ni);                                      // u_i . dm_i
@@ -636,7 +678,7 @@ __global__ __launch_bounds__(64 * W) void pre_gl_kernel(const ReqDesc* __restric
             }
         __syncthreads();      // u complete in LDS; every wave is done reading p_i, p_j of category r
         if (!tip_i) {
-            bwd<T, RB, NBW, G>(PB + mo_i, Ui, ge, cb0, lane, acc);    // q_i = P_i^T u_i, unscaled, over p_i
+            bwd<T, RB, NBW, G>(PB + mo_i, Ui, ge, cb0, lane, acc);    // q_i = P_i^T u_i, over p_i
             max_cols<T, RB, NBW>(acc, mxi);
             store_cols<T, RB, NBW>(pi_base + r * rstride, ge, cb0, lane, acc);
         }
@@ -658,7 +700,13 @@ __global__ __launch_bounds__(64 * W) void pre_gl_kernel(const ReqDesc* __restric
         for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
             for (int i = 0; i < 4; ++i) e[rb][i] = exp_of(mxi[rb][i]);
-        rescale_cols<T, RB, NBW>(pi_base, R, ge, cb0, lane, e);
+        if (w == 0 && n == 0) {              // q_i is stored unscaled: record its exponent
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    g(d.eloc)[static_cast<size_t>(nt.i - N) * Cpad + tile * TP + opat<T>(rb, gq, i)] = e[rb][i];
+        }
     }
     if (!tip_j) {
 #pragma unroll
@@ -671,7 +719,13 @@ __global__ __launch_bounds__(64 * W) void pre_gl_kernel(const ReqDesc* __restric
         for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
             for (int i = 0; i < 4; ++i) e[rb][i] = exp_of(mxj[rb][i]);
-        rescale_cols<T, RB, NBW>(pj_base, R, ge, cb0, lane, e);
+        if (w == 0 && n == 0) {              // q_j is stored unscaled: record its exponent
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    g(d.eloc)[static_cast<size_t>(nt.j - N) * Cpad + tile * TP + opat<T>(rb, gq, i)] = e[rb][i];
+        }
     }
     // per-pattern sums over all states: this wave's part, then the waves in order
 #pragma unroll
