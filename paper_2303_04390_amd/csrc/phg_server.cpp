@@ -315,7 +315,11 @@ bool launch_step(phg_server* s) {
         Item it{i, 0, Segment{i, 0, 0, 0, reinterpret_cast<const int32_t*>(d.sched), nullptr, nullptr}, &d};
         GroupKey key{};
         if (st == 0) {
-            key = GroupKey{kPmat, d.S == 4, 0, 0};
+            // one P(t) kernel per launch: the 4-state one, the generic one
+            // (S <= 16) or the operand-order one of the MFMA kernels, which is
+            // typed by precision
+            const int kind = d.S == 4 ? 0 : (uses_gl_kernels(d.S, d.R) ? 1 : 2);
+            key = GroupKey{kPmat, kind, kind == 1 ? d.fp32 : 0, 0};
             it.units = units_for(kPmat, d, 0);
         } else if (st <= t->H) {
             const int l = st - 1, a = c->post_lv[l].first, n = c->post_lv[l].second;
