@@ -951,14 +951,42 @@ __device__ __forceinline__ int rescale_shared(float x[4]) {
     return e;
 }
 
+// The stored partials (and, with kExpo, exponents) of the block's frontier
+// block roots, heap positions 8..15, for this lane's (category, pattern), all
+// loads issued together: one memory round trip for the block's inputs, each
+// read once.  Tips and absent positions give zeros.  Costs 40 registers that
+// stay live through the kernel, so it pays only in launches too narrow to
+// fill the chip (near the root), where latency, not occupancy, bounds them.
+template <int R, bool kExpo>
+__device__ __forceinline__ void load_frontier(const int (&nd)[16], const BmfLane& L, const int tile,
+                                              const int tiles, const int N, const int Cpad,
+                                              GLOBAL F4* __restrict__ part, const GLOBAL int32_t* __restrict__ expo,
+                                              float (&fr)[8][4], int (&fe)[8]) {
+    const int c = tile * kLanes + L.pat;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const int cn = nd[8 + j];
+        F4 v = {0.0f, 0.0f, 0.0f, 0.0f};
+        int e = 0;
+        if (cn >= N) {
+            v = *reinterpret_cast<const GLOBAL F4*>(chunk<R>(part, cn - N, tile, tiles) + L.part);
+            if (kExpo) e = expo[static_cast<size_t>(cn - N) * Cpad + c];
+        }
+        f4_to(v, fr[j]);
+        fe[j] = e;
+    }
+}
+
 // In-block post-order over heap positions 7..LO for this lane's (category,
 // pattern).  With kExpo, returns the sum of exponents taken (in-block nodes and
-// frontier block roots); otherwise exponents are not read.
-template <int R, int NM, int LO, bool kExpo>
+// frontier block roots); otherwise exponents are not read.  Frontier inputs
+// come from load_frontier (kPre) or are loaded per position.
+template <int R, int NM, int LO, bool kExpo, bool kPre>
 __device__ __forceinline__ int bmf_postorder(const int (&nd)[16], const BmfLane& L, const BmfMats<R, NM>& S,
                                              const uint32_t (&CL)[14][16], const int tile, const int tiles,
                                              const int N, const int Cpad, GLOBAL F4* __restrict__ part,
-                                             const GLOBAL int32_t* __restrict__ expo, float (&p)[8][4]) {
+                                             const GLOBAL int32_t* __restrict__ expo, const float (&fr)[8][4],
+                                             const int (&fe)[8], float (&p)[8][4]) {
     const int c = tile * kLanes + L.pat;
     int esum = 0;
     static_for<0, 8 - LO>([&](auto I_) {
@@ -966,7 +994,14 @@ __device__ __forceinline__ int bmf_postorder(const int (&nd)[16], const BmfLane&
         const int k = nd[pos];
         if (k < N) return;
         float m[2][4], v[2][4];
-        if constexpr (pos >= 4) {
+        if constexpr (pos >= 4 && kPre) {
+#pragma unroll
+            for (int s = 0; s < 2; ++s) {
+#pragma unroll
+                for (int u = 0; u < 4; ++u) v[s][u] = fr[2 * pos + s - 8][u];
+                if (kExpo) esum += fe[2 * pos + s - 8];     // zero for a tip
+            }
+        } else if constexpr (pos >= 4) {
             // frontier children: both stored partials (and exponents) are
             // loaded before either is used; a tip child reads slot 0, unused
             int ex[2];
@@ -1027,7 +1062,7 @@ __device__ __forceinline__ bool bmf_unit(const ReqDesc* __restrict__ descs, cons
     return true;
 }
 
-template <int R>
+template <int R, bool kPre>
 __global__ __launch_bounds__(kLanes * R) __attribute__((amdgpu_waves_per_eu(4))) void post_bmf_kernel(
     const ReqDesc* __restrict__ descs, const SegTable segs) {
     constexpr int PW = kLanes / R;
@@ -1045,13 +1080,16 @@ __global__ __launch_bounds__(kLanes * R) __attribute__((amdgpu_waves_per_eu(4)))
 #pragma unroll
     for (int i = 0; i < 16; ++i) nd[i] = U.heap[i];
     const int c = tile * kLanes + L.pat;
+    GLOBAL F4* part = reinterpret_cast<GLOBAL F4*>(g(part_of<float>(d)));
+    GLOBAL int32_t* expo = g(d.expo);
+    float fr[8][4];
+    int fe[8];
+    if constexpr (kPre) load_frontier<R, true>(nd, L, tile, U.tiles, N, U.Cpad, part, expo, fr, fe);
     stage_codes<R>(CL, nd, N, U.Cpad, tile * kLanes, g(d.codes));
     stage_mats<R, 1>(S, nd, g(d.P32), nullptr);
     __syncthreads();
-    GLOBAL F4* part = reinterpret_cast<GLOBAL F4*>(g(part_of<float>(d)));
-    GLOBAL int32_t* expo = g(d.expo);
     float p[8][4];
-    const int ek = bmf_postorder<R, 1, 1, true>(nd, L, S, CL, tile, U.tiles, N, U.Cpad, part, expo, p);
+    const int ek = bmf_postorder<R, 1, 1, true, kPre>(nd, L, S, CL, tile, U.tiles, N, U.Cpad, part, expo, fr, fe, p);
     if (!(U.sg.flags & 1)) {
         *reinterpret_cast<GLOBAL F4*>(chunk<R>(part, nd[1] - N, tile, U.tiles) + L.part) = to_f4(p[1]);
         if (L.r == 0) expo[static_cast<size_t>(nd[1] - N) * U.Cpad + c] = ek;
@@ -1083,7 +1121,7 @@ __global__ __launch_bounds__(kLanes * R) __attribute__((amdgpu_waves_per_eu(4)))
     }
 }
 
-template <int R>
+template <int R, bool kPre>
 __global__ __launch_bounds__(kLanes * R) __attribute__((amdgpu_waves_per_eu(4))) void pre_bmf_kernel(
     const ReqDesc* __restrict__ descs, const SegTable segs) {
     __shared__ BmfMats<R, 2> S;
@@ -1105,6 +1143,9 @@ __global__ __launch_bounds__(kLanes * R) __attribute__((amdgpu_waves_per_eu(4)))
     for (int i = 0; i < 16; ++i) nd[i] = U.heap[i];
     const int c = tile * kLanes + L.pat;
     GLOBAL F4* part = reinterpret_cast<GLOBAL F4*>(g(part_of<float>(d)));
+    float fr[8][4];
+    int fe[8];
+    if constexpr (kPre) load_frontier<R, false>(nd, L, tile, tiles, N, U.Cpad, part, nullptr, fr, fe);
     stage_codes<R>(CL, nd, N, U.Cpad, tile * kLanes, g(d.codes));
     float q[8][4];
     if (nd[1] == 2 * N - 2) {
@@ -1118,7 +1159,7 @@ __global__ __launch_bounds__(kLanes * R) __attribute__((amdgpu_waves_per_eu(4)))
     stage_mats<R, 2>(S, nd, g(d.P32), g(d.dP32));
     __syncthreads();
     float p[8][4];
-    (void)bmf_postorder<R, 2, 2, false>(nd, L, S, CL, tile, tiles, N, U.Cpad, part, nullptr, p);
+    (void)bmf_postorder<R, 2, 2, false, kPre>(nd, L, S, CL, tile, tiles, N, U.Cpad, part, nullptr, fr, fe, p);
     const float wr = static_cast<float>(g(d.cweights)[L.r]);
     static_for<1, 8>([&](auto P_) {
         constexpr int pos = decltype(P_)::value;
@@ -1126,7 +1167,12 @@ __global__ __launch_bounds__(kLanes * R) __attribute__((amdgpu_waves_per_eu(4)))
         if (k < N) return;
         float m[2][4], dm[2][4], v[2][4];
         bool in[2];
-        if constexpr (pos >= 4) {
+        if constexpr (pos >= 4 && kPre) {
+#pragma unroll
+            for (int s = 0; s < 2; ++s)
+#pragma unroll
+                for (int u = 0; u < 4; ++u) v[s][u] = fr[2 * pos + s - 8][u];
+        } else if constexpr (pos >= 4) {
 #pragma unroll
             for (int s = 0; s < 2; ++s) {
                 const int cn = nd[2 * pos + s];
@@ -1371,10 +1417,21 @@ hipError_t level_r(KernelClass k, bool blocked, const ReqDesc* descs, const SegT
     const int blocks = (n_units + kWavesPerBlock - 1) / kWavesPerBlock;
     if constexpr (std::is_same<T, float>::value && (R & (R - 1)) == 0) {
         if (blocked) {
-            if (k == kPost)
-                hipLaunchKernelGGL((post_bmf_kernel<R>), dim3(n_units), dim3(kLanes * R), 0, st, descs, t);
-            else
-                hipLaunchKernelGGL((pre_bmf_kernel<R>), dim3(n_units), dim3(kLanes * R), 0, st, descs, t);
+            // launches whose workgroups all fit on the chip at once with the
+            // frontier held in registers (5 waves per SIMD, 4 SIMDs, 256 CUs)
+            // are latency-bound: take the variant with one load round trip
+            const bool narrow = n_units <= 256 * 4 * 5 / R;
+            if (k == kPost) {
+                if (narrow)
+                    hipLaunchKernelGGL((post_bmf_kernel<R, true>), dim3(n_units), dim3(kLanes * R), 0, st, descs, t);
+                else
+                    hipLaunchKernelGGL((post_bmf_kernel<R, false>), dim3(n_units), dim3(kLanes * R), 0, st, descs, t);
+            } else {
+                if (narrow)
+                    hipLaunchKernelGGL((pre_bmf_kernel<R, true>), dim3(n_units), dim3(kLanes * R), 0, st, descs, t);
+                else
+                    hipLaunchKernelGGL((pre_bmf_kernel<R, false>), dim3(n_units), dim3(kLanes * R), 0, st, descs, t);
+            }
             return hipGetLastError();
         }
     }
