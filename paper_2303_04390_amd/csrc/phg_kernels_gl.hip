@@ -10,8 +10,10 @@
 // output states [w * 16 NBW, (w + 1) * 16 NBW) of every product (NBW column
 // blocks of 16; W = ceil(S / 16) waves of one block up to 64 states, four
 // waves above), and runs the full sum over input states itself:
-// inputs come from HBM/L2 (stored partials, matrices) or, for the vectors u
-// that feed P^T u, from LDS where all the waves wrote their parts.
+// matrices come from HBM/L2; the input vectors of a category (stored partials
+// of the children, q of the parent) are staged once per workgroup in LDS by
+// 16-byte loads, and the vectors u that feed P^T u are written there by all
+// the waves.
 //
 // MFMA 16x16x4 computes D(16x16) += A(16x4) B(4x16); lane l holds A[l%16][l/16]
 // and B[l/16][l%16]; the four output registers hold D[4(l/16)+i][l%16] (f32)
@@ -142,7 +144,8 @@ struct Cols {
 // Where a child's input vector comes from.
 template <typename T, int RB>
 struct Input {
-    const GLOBAL T* base;   // stored [TP][row] block of (slot, tile, r), or null for a tip
+    const T* lds;           // staged [TP][la] vector of (child, tile, r) in LDS, or null
+    const GLOBAL T* base;   // or the stored [TP][row] block in HBM, or null; both null: a tip
     int code[RB];           // a tip's codes for patterns 16 rb + n of the tile
 };
 
@@ -158,34 +161,80 @@ constexpr int chunk_of() {
 struct Geo {
     int S;      // states
     int kbp;    // k-steps per lane group in a row (gl_kbp)
-    int row;    // row length (4 kbp)
+    int row;    // row length in HBM (4 kbp)
+    int la;     // row stride of a vector staged in LDS: row + 16 bytes (bank spread)
 };
 
-// G adjacent operand values (k-steps k .. k+G-1 of this lane) from a row.
+// G adjacent operand values (k-steps k .. k+G-1 of this lane) from a row in
+// HBM, one 8-, 16- or 32-byte load.
 template <typename T, int G>
 __device__ __forceinline__ void load_run(const GLOBAL T* __restrict__ p, T (&out)[G]) {
     const VecG<T, G> v = *reinterpret_cast<const GLOBAL VecG<T, G>*>(p);
 #pragma unroll
     for (int j = 0; j < G; ++j) out[j] = v[j];
 }
+// The same from a row staged in LDS, in pieces of at most 16 bytes.
+template <typename T, int G>
+__device__ __forceinline__ void lds_run(const T* p, T (&out)[G]) {
+    constexpr int E = (G * static_cast<int>(sizeof(T)) > 16) ? 16 / static_cast<int>(sizeof(T)) : G;
+#pragma unroll
+    for (int q = 0; q < G / E; ++q) {
+        const VecG<T, E> v = *reinterpret_cast<const VecG<T, E>*>(p + q * E);
+#pragma unroll
+        for (int j = 0; j < E; ++j) out[q * E + j] = v[j];
+    }
+}
+
+// Copy a stored [TP][row] block (contiguous in HBM) into an LDS [TP][la]
+// buffer in 16-byte pieces.  All threads take part; each issues all of its
+// (at most KIT) loads before its first LDS write.  The caller synchronises.
+template <typename T, int TP, int KIT>
+__device__ __forceinline__ void stage_vec(T* buf, const GLOBAL T* __restrict__ src, const Geo& ge) {
+    constexpr int E = 16 / static_cast<int>(sizeof(T));
+    const int per_row = ge.row / E;
+    const int n = TP * per_row;
+    VecG<T, E> v[KIT];
+#pragma unroll
+    for (int it = 0; it < KIT; ++it) {
+        const int t = static_cast<int>(threadIdx.x) + it * static_cast<int>(blockDim.x);
+        if (t < n) {
+            const int p = t / per_row, c = (t - p * per_row) * E;
+            v[it] = *reinterpret_cast<const GLOBAL VecG<T, E>*>(src + p * ge.row + c);
+        }
+    }
+#pragma unroll
+    for (int it = 0; it < KIT; ++it) {
+        const int t = static_cast<int>(threadIdx.x) + it * static_cast<int>(blockDim.x);
+        if (t < n) {
+            const int p = t / per_row, c = (t - p * per_row) * E;
+            *reinterpret_cast<VecG<T, E>*>(buf + p * ge.la + c) = v[it];
+        }
+    }
+}
 
 // out1 = M1 v (and, with M2, out2 = M2 v) on this wave's columns:
 // out[c][s] = sum_t M[s][t] in[c][t], s = cb0 + 16 cb + n, from forward
-// tables.  One operand stream of v feeds both products (P p and dP p of one
-// child).
-template <typename T, int RB, int NBW, int G, bool kTwo>
+// tables; v from LDS (kLds) or HBM, or a tip's code.  One operand stream of v
+// feeds both products (P p and dP p of one child).
+template <typename T, int RB, int NBW, int G, bool kTwo, bool kLds = true>
 __device__ __forceinline__ void fwd(const GLOBAL T* __restrict__ M1, const GLOBAL T* __restrict__ M2,
                                     const Input<T, RB>& in, const Geo& ge, int cb0, int lane,
                                     Cols<T, RB, NBW>& out1, Cols<T, RB, NBW>& out2) {
+    constexpr int kChunk = chunk_of<T, NBW>();
     const int gq = lane >> 4, n = lane & 15;
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
         for (int cb = 0; cb < NBW; ++cb) out1.v[rb][cb] = out2.v[rb][cb] = V4<T>{0, 0, 0, 0};
     const int off = gq * ge.kbp;
-    const GLOBAL T* ar[RB];
+    const bool tip = kLds ? in.lds == nullptr : in.base == nullptr;
+    const T* ar[RB];
+    const GLOBAL T* ag[RB];
 #pragma unroll
-    for (int rb = 0; rb < RB; ++rb) ar[rb] = in.base ? in.base + (16 * rb + n) * ge.row + off : nullptr;
+    for (int rb = 0; rb < RB; ++rb) {
+        ar[rb] = kLds && !tip ? in.lds + (16 * rb + n) * ge.la + off : nullptr;
+        ag[rb] = !kLds && !tip ? in.base + (16 * rb + n) * ge.row + off : nullptr;
+    }
     const GLOBAL T* br1[NBW];
     const GLOBAL T* br2[NBW];
 #pragma unroll
@@ -194,29 +243,12 @@ __device__ __forceinline__ void fwd(const GLOBAL T* __restrict__ M1, const GLOBA
         br1[cb] = M1 + o;
         br2[cb] = kTwo ? M2 + o : M1;
     }
-    constexpr int kChunk = chunk_of<T, NBW>();
     for (int k0 = 0; k0 < ge.kbp; k0 += kChunk) {
         T a[kChunk][RB], b1[kChunk][NBW], b2[kChunk][NBW];
 #pragma unroll
         for (int v = 0; v < kChunk / G; ++v) {
             const int k = k0 + v * G;
             if (k < ge.kbp) {             // uniform; rows are padded to whole runs
-#pragma unroll
-                for (int rb = 0; rb < RB; ++rb) {
-                    if (in.base) {
-                        T x[G];
-                        load_run<T, G>(ar[rb] + k, x);
-#pragma unroll
-                        for (int j = 0; j < G; ++j) a[v * G + j][rb] = x[j];
-                    } else {
-#pragma unroll
-                        for (int j = 0; j < G; ++j) {
-                            const int t = 4 * (k + j) + gq;
-                            a[v * G + j][rb] =
-                                (t < ge.S && (in.code[rb] == t || in.code[rb] >= ge.S)) ? T(1) : T(0);
-                        }
-                    }
-                }
 #pragma unroll
                 for (int cb = 0; cb < NBW; ++cb) {
                     T x[G];
@@ -227,6 +259,25 @@ __device__ __forceinline__ void fwd(const GLOBAL T* __restrict__ M1, const GLOBA
                         load_run<T, G>(br2[cb] + k, x);
 #pragma unroll
                         for (int j = 0; j < G; ++j) b2[v * G + j][cb] = x[j];
+                    }
+                }
+#pragma unroll
+                for (int rb = 0; rb < RB; ++rb) {
+                    if (!tip) {
+                        T x[G];
+                        if (kLds)
+                            lds_run<T, G>(ar[rb] + k, x);
+                        else
+                            load_run<T, G>(ag[rb] + k, x);
+#pragma unroll
+                        for (int j = 0; j < G; ++j) a[v * G + j][rb] = x[j];
+                    } else {
+#pragma unroll
+                        for (int j = 0; j < G; ++j) {
+                            const int t = 4 * (k + j) + gq;
+                            a[v * G + j][rb] =
+                                (t < ge.S && (in.code[rb] == t || in.code[rb] >= ge.S)) ? T(1) : T(0);
+                        }
                     }
                 }
             }
@@ -246,21 +297,23 @@ __device__ __forceinline__ void fwd(const GLOBAL T* __restrict__ M1, const GLOBA
 }
 
 // out = M^T u on this wave's columns: out[c][t] = sum_s u[c][s] M[s][t], from
-// the backward table (row t), u from LDS laid out [state][TP + 1].
+// the backward table (row t), u staged in LDS like an input vector.
 template <typename T, int RB, int NBW, int G>
 __device__ __forceinline__ void bwd(const GLOBAL T* __restrict__ MB, const T* U, const Geo& ge, int cb0,
                                     int lane, Cols<T, RB, NBW>& out) {
-    constexpr int LS = 16 * RB + 1;
+    constexpr int kChunk = chunk_of<T, NBW>();
     const int gq = lane >> 4, n = lane & 15;
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
         for (int cb = 0; cb < NBW; ++cb) out.v[rb][cb] = V4<T>{0, 0, 0, 0};
     const int off = gq * ge.kbp;
+    const T* ur[RB];
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb) ur[rb] = U + (16 * rb + n) * ge.la + off;
     const GLOBAL T* br[NBW];
 #pragma unroll
     for (int cb = 0; cb < NBW; ++cb) br[cb] = MB + static_cast<size_t>(cb0 + 16 * cb + n) * ge.row + off;
-    constexpr int kChunk = chunk_of<T, NBW>();
     for (int k0 = 0; k0 < ge.kbp; k0 += kChunk) {
         T a[kChunk][RB], b[kChunk][NBW];
 #pragma unroll
@@ -268,17 +321,18 @@ __device__ __forceinline__ void bwd(const GLOBAL T* __restrict__ MB, const T* U,
             const int k = k0 + v * G;
             if (k < ge.kbp) {
 #pragma unroll
-                for (int j = 0; j < G; ++j) {
-                    const int s = 4 * (k + j) + gq;      // < row: LDS rows cover it, zeros past S
-#pragma unroll
-                    for (int rb = 0; rb < RB; ++rb) a[v * G + j][rb] = U[s * LS + 16 * rb + n];
-                }
-#pragma unroll
                 for (int cb = 0; cb < NBW; ++cb) {
                     T x[G];
                     load_run<T, G>(br[cb] + k, x);
 #pragma unroll
                     for (int j = 0; j < G; ++j) b[v * G + j][cb] = x[j];
+                }
+#pragma unroll
+                for (int rb = 0; rb < RB; ++rb) {
+                    T x[G];
+                    lds_run<T, G>(ur[rb] + k, x);
+#pragma unroll
+                    for (int j = 0; j < G; ++j) a[v * G + j][rb] = x[j];
                 }
             }
         }
@@ -293,8 +347,8 @@ __device__ __forceinline__ void bwd(const GLOBAL T* __restrict__ MB, const T* U,
     }
 }
 
-// Stored [TP][row] block <-> this wave's columns (states past S are zeros in
-// both; states past the row do not exist).
+// A stored [TP][row] block in HBM -> this wave's columns, and back (states
+// past S are zeros; states past the row do not exist).
 template <typename T, int RB, int NBW>
 __device__ __forceinline__ void load_cols(const GLOBAL T* __restrict__ base, const Geo& ge, int cb0, int lane,
                                           Cols<T, RB, NBW>& x) {
@@ -325,18 +379,32 @@ __device__ __forceinline__ void store_cols(GLOBAL T* __restrict__ base, const Ge
         }
     }
 }
+// An LDS [TP][la] vector <-> this wave's columns.
 template <typename T, int RB, int NBW>
-__device__ __forceinline__ void cols_to_lds(T* U, const Geo& ge, int cb0, int lane, const Cols<T, RB, NBW>& x) {
-    constexpr int LS = 16 * RB + 1;
+__device__ __forceinline__ void vbuf_to_cols(const T* buf, const Geo& ge, int cb0, int lane, Cols<T, RB, NBW>& x) {
     const int gq = lane >> 4, n = lane & 15;
 #pragma unroll
     for (int cb = 0; cb < NBW; ++cb) {
         const int s = cb0 + 16 * cb + n;
+        const int col = gl_col(s, ge.kbp);
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) x.v[rb][cb][i] = s < ge.row ? buf[opat<T>(rb, gq, i) * ge.la + col] : T(0);
+    }
+}
+template <typename T, int RB, int NBW>
+__device__ __forceinline__ void cols_to_vbuf(T* buf, const Geo& ge, int cb0, int lane, const Cols<T, RB, NBW>& x) {
+    const int gq = lane >> 4, n = lane & 15;
+#pragma unroll
+    for (int cb = 0; cb < NBW; ++cb) {
+        const int s = cb0 + 16 * cb + n;
+        const int col = gl_col(s, ge.kbp);
         if (s < ge.row) {
 #pragma unroll
             for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
-                for (int i = 0; i < 4; ++i) U[s * LS + opat<T>(rb, gq, i)] = x.v[rb][cb][i];
+                for (int i = 0; i < 4; ++i) buf[opat<T>(rb, gq, i) * ge.la + col] = x.v[rb][cb][i];
         }
     }
 }
@@ -458,6 +526,11 @@ __global__ __launch_bounds__(64 * W) void post_gl_kernel(const ReqDesc* __restri
                                                          const SegTable segs) {
     constexpr int TP = 16 * RB;
     constexpr int G = (NBW == 1 && W <= 2) ? 2 : 4;   // gl_vec: 2 up to 32 states
+    constexpr int SP = 16 * NBW * W;                // padded states (>= the row length)
+    constexpr int E = 16 / static_cast<int>(sizeof(T));
+    constexpr int LA = SP + E;                      // LDS row stride bound
+    constexpr int KIT = (TP * NBW + 4 * E - 1) / (4 * E);   // staging pieces per thread
+    __shared__ __align__(16) T vb[2][TP * LA];      // staged p_i, p_j of one category
     __shared__ T red[W * TP];
     __shared__ double dred[W * TP];
     __shared__ int esh[2][TP];                      // own exponents of the children
@@ -470,7 +543,7 @@ __global__ __launch_bounds__(64 * W) void post_gl_kernel(const ReqDesc* __restri
     const int N = d.N, S = d.S, R = d.R, Cpad = d.Cpad, tile = U.tile, tiles = U.tiles;
     const NodeTriple nt = U.nt;
     const int cb0 = w * 16 * NBW;
-    const Geo ge{S, gl_kbp(S), gl_row(S)};
+    const Geo ge{S, gl_kbp(S), gl_row(S), gl_row(S) + E};
     const size_t rstride = static_cast<size_t>(TP) * ge.row;
     const size_t tstride = rstride * R;
     const size_t mstride = static_cast<size_t>(gl_mat_rows(S)) * ge.row;   // one (branch, category) table
@@ -486,14 +559,17 @@ __global__ __launch_bounds__(64 * W) void post_gl_kernel(const ReqDesc* __restri
     const bool root = U.sg.flags & 1;
     {
         const int kids[2] = {nt.i, nt.j};
-        stage_exps<TP, 2>(esh, kids, d, tile);
+        stage_exps<TP, 2>(esh, kids, d, tile);      // read after the first barrier below
     }
-    __syncthreads();
+    si.lds = tip_i ? nullptr : vb[0];
+    sj.lds = tip_j ? nullptr : vb[1];
+    si.base = sj.base = nullptr;
     T mx[RB][4] = {};
     double site[RB][4] = {};
     for (int r = 0; r < R; ++r) {
-        si.base = pi_base ? pi_base + r * rstride : nullptr;
-        sj.base = pj_base ? pj_base + r * rstride : nullptr;
+        if (!tip_i) stage_vec<T, TP, KIT>(vb[0], pi_base + r * rstride, ge);
+        if (!tip_j) stage_vec<T, TP, KIT>(vb[1], pj_base + r * rstride, ge);
+        __syncthreads();
         Cols<T, RB, NBW> mi, mj, unused;
         fwd<T, RB, NBW, G, false>(P + (static_cast<size_t>(nt.i) * R + r) * mstride, nullptr, si, ge, cb0, lane,
                                   mi, unused);
@@ -517,6 +593,7 @@ __global__ __launch_bounds__(64 * W) void post_gl_kernel(const ReqDesc* __restri
                     for (int i = 0; i < 4; ++i) site[rb][i] += wr * ps * static_cast<double>(mi.v[rb][cb][i]);
             }
         }
+        __syncthreads();      // every wave done with the staged inputs of category r
     }
     int ec[RB][4];
 #pragma unroll
@@ -589,15 +666,21 @@ __global__ __launch_bounds__(64 * W) void post_gl_kernel(const ReqDesc* __restri
 
 // ---------------------------------------------------------------- pre-order + gradient
 
+// Up to 32 states in FP32 the kernel fits in 128 registers: ask for 4 waves per SIMD.
 template <typename T, int RB, int NBW, int W>
-__global__ __launch_bounds__(64 * W) void pre_gl_kernel(const ReqDesc* __restrict__ descs,
+__global__ __launch_bounds__(64 * W, (W == 2 && sizeof(T) == 4) ? 4 : 1) void pre_gl_kernel(const ReqDesc* __restrict__ descs,
                                                         const SegTable segs) {
     constexpr int TP = 16 * RB;
-    constexpr int LS = TP + 1;
     constexpr int G = (NBW == 1 && W <= 2) ? 2 : 4;   // gl_vec: 2 up to 32 states
-    constexpr int SP = 16 * NBW * W;                // padded states held in LDS
-    __shared__ T Ui[SP * LS];
-    __shared__ T Uj[SP * LS];
+    constexpr int SP = 16 * NBW * W;                // padded states (>= the row length)
+    constexpr int E = 16 / static_cast<int>(sizeof(T));
+    constexpr int LA = SP + E;                      // LDS row stride bound
+    constexpr int KIT = (TP * NBW + 4 * E - 1) / (4 * E);   // staging pieces per thread
+    // With three or more waves the inputs of a category (p_i, p_j, q_k) are
+    // staged in LDS once instead of read by every wave; with two the extra
+    // barriers cost more than they save.  u_i, u_j go to vb[0], vb[1].
+    constexpr bool kStage = W >= 3;
+    __shared__ __align__(16) T vb[kStage ? 3 : 2][TP * LA];
     __shared__ T red[3 * W * TP];
     __shared__ int esh[3][TP];                      // own exponents: p_i, p_j (post-order), q_k
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -609,7 +692,7 @@ __global__ __launch_bounds__(64 * W) void pre_gl_kernel(const ReqDesc* __restric
     const int N = d.N, S = d.S, R = d.R, Cpad = d.Cpad, tile = U.tile, tiles = U.tiles;
     const NodeTriple nt = U.nt;
     const int cb0 = w * 16 * NBW;
-    const Geo ge{S, gl_kbp(S), gl_row(S)};
+    const Geo ge{S, gl_kbp(S), gl_row(S), gl_row(S) + E};
     const size_t rstride = static_cast<size_t>(TP) * ge.row;
     const size_t tstride = rstride * R;
     const size_t mstride = static_cast<size_t>(gl_mat_rows(S)) * ge.row;   // one (branch, category) table
@@ -629,11 +712,19 @@ __global__ __launch_bounds__(64 * W) void pre_gl_kernel(const ReqDesc* __restric
         const int nodes[3] = {nt.i, nt.j, is_root ? -1 : nt.k};
         stage_exps<TP, 3>(esh, nodes, d, tile);
     }
-    __syncthreads();
+    if constexpr (!kStage) __syncthreads();    // exponents in LDS (staging has its own barrier)
+    si.lds = kStage && !tip_i ? vb[0] : nullptr;
+    sj.lds = kStage && !tip_j ? vb[1] : nullptr;
     T num_i[RB][4] = {}, num_j[RB][4] = {}, den[RB][4] = {}, mxi[RB][4] = {}, mxj[RB][4] = {};
     for (int r = 0; r < R; ++r) {
-        si.base = pi_base ? pi_base + r * rstride : nullptr;
-        sj.base = pj_base ? pj_base + r * rstride : nullptr;
+        si.base = !kStage && pi_base ? pi_base + r * rstride : nullptr;
+        sj.base = !kStage && pj_base ? pj_base + r * rstride : nullptr;
+        if constexpr (kStage) {
+            if (!tip_i) stage_vec<T, TP, KIT>(vb[0], pi_base + r * rstride, ge);
+            if (!tip_j) stage_vec<T, TP, KIT>(vb[1], pj_base + r * rstride, ge);
+            if (!is_root) stage_vec<T, TP, KIT>(vb[kStage ? 2 : 0], qk_base + r * rstride, ge);
+            __syncthreads();  // inputs of category r staged
+        }
         const size_t mo_i = (static_cast<size_t>(nt.i) * R + r) * mstride;
         const size_t mo_j = (static_cast<size_t>(nt.j) * R + r) * mstride;
         const T wr = static_cast<T>(g(d.cweights)[r]);
@@ -647,17 +738,19 @@ __global__ __launch_bounds__(64 * W) void pre_gl_kernel(const ReqDesc* __restric
                 for (int rb = 0; rb < RB; ++rb) qk.v[rb][cb] = V4<T>{v, v, v, v};
             }
         } else {
-            load_cols<T, RB, NBW>(qk_base + r * rstride, ge, cb0, lane, qk);
+            if constexpr (kStage)
+                vbuf_to_cols<T, RB, NBW>(vb[kStage ? 2 : 0], ge, cb0, lane, qk);
+            else
+                load_cols<T, RB, NBW>(qk_base + r * rstride, ge, cb0, lane, qk);
             scale_rows<T, RB, NBW>(qk, esh[2], lane);
         }
-        fwd<T, RB, NBW, G, true>(P + mo_j, dP + mo_j, sj, ge, cb0, lane, a, dmj);   // a = m_j, dm_j
+        fwd<T, RB, NBW, G, true, kStage>(P + mo_j, dP + mo_j, sj, ge, cb0, lane, a, dmj);   // a = m_j, dm_j
         if (!tip_j) {
             scale_rows<T, RB, NBW>(a, esh[1], lane);
             scale_rows<T, RB, NBW>(dmj, esh[1], lane);
         }
         mul_cols<T, RB, NBW>(a, qk);                                           // a = u_i
-        cols_to_lds<T, RB, NBW>(Ui, ge, cb0, lane, a);
-        fwd<T, RB, NBW, G, true>(P + mo_i, dP + mo_i, si, ge, cb0, lane, b, acc);  // b = m_i, acc = dm_i
+        fwd<T, RB, NBW, G, true, kStage>(P + mo_i, dP + mo_i, si, ge, cb0, lane, b, acc);  // b = m_i, acc = dm_i
         if (!tip_i) {
             scale_rows<T, RB, NBW>(b, esh[0], lane);
             scale_rows<T, RB, NBW>(acc, esh[0], lane);
@@ -666,7 +759,6 @@ __global__ __launch_bounds__(64 * W) void pre_gl_kernel(const ReqDesc* __restric
         dot_cols<T, RB, NBW>(a, b, dd);                                        // u_i . m_i
         dot_cols<T, RB, NBW>(a, acc, ni);                                      // u_i . dm_i
         mul_cols<T, RB, NBW>(b, qk);                                           // b = u_j
-        cols_to_lds<T, RB, NBW>(Uj, ge, cb0, lane, b);
         dot_cols<T, RB, NBW>(b, dmj, nj);                                      // u_j . dm_j
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb)
@@ -676,18 +768,21 @@ __global__ __launch_bounds__(64 * W) void pre_gl_kernel(const ReqDesc* __restric
                 num_j[rb][i] += wr * nj[rb][i];
                 den[rb][i] += wr * dd[rb][i];
             }
-        __syncthreads();      // u complete in LDS; every wave is done reading p_i, p_j of category r
+        if constexpr (kStage) __syncthreads();   // every wave is done reading the staged p_i, p_j, q_k
+        if (!tip_i) cols_to_vbuf<T, RB, NBW>(vb[0], ge, cb0, lane, a);       // u_i over p_i
+        if (!tip_j) cols_to_vbuf<T, RB, NBW>(vb[1], ge, cb0, lane, b);       // u_j over p_j
+        __syncthreads();      // u complete in LDS
         if (!tip_i) {
-            bwd<T, RB, NBW, G>(PB + mo_i, Ui, ge, cb0, lane, acc);    // q_i = P_i^T u_i, over p_i
+            bwd<T, RB, NBW, G>(PB + mo_i, vb[0], ge, cb0, lane, acc);    // q_i = P_i^T u_i, stored over p_i
             max_cols<T, RB, NBW>(acc, mxi);
             store_cols<T, RB, NBW>(pi_base + r * rstride, ge, cb0, lane, acc);
         }
         if (!tip_j) {
-            bwd<T, RB, NBW, G>(PB + mo_j, Uj, ge, cb0, lane, acc);
+            bwd<T, RB, NBW, G>(PB + mo_j, vb[1], ge, cb0, lane, acc);
             max_cols<T, RB, NBW>(acc, mxj);
             store_cols<T, RB, NBW>(pj_base + r * rstride, ge, cb0, lane, acc);
         }
-        __syncthreads();      // before the next category overwrites u
+        __syncthreads();      // before the next category's staging overwrites u
     }
     if (!tip_i) {
 #pragma unroll
