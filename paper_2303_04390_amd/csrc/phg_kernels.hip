@@ -954,9 +954,11 @@ __device__ __forceinline__ int rescale_shared(float x[4]) {
 // The stored partials (and, with kExpo, exponents) of the block's frontier
 // block roots, heap positions 8..15, for this lane's (category, pattern), all
 // loads issued together: one memory round trip for the block's inputs, each
-// read once.  Tips and absent positions give zeros.  Costs 40 registers that
-// stay live through the kernel, so it pays only in launches too narrow to
-// fill the chip (near the root), where latency, not occupancy, bounds them.
+// read once.  Tips and absent positions give zeros.  The post-order kernel
+// always does this (it stays at 8 waves per SIMD); in the pre-order kernel the
+// registers stay live through the pre-order phase and cost occupancy, so it
+// pays only in launches too narrow to fill the chip (near the root), where
+// latency, not occupancy, bounds them.
 template <int R, bool kExpo>
 __device__ __forceinline__ void load_frontier(const int (&nd)[16], const BmfLane& L, const int tile,
                                               const int tiles, const int N, const int Cpad,
@@ -1062,7 +1064,7 @@ __device__ __forceinline__ bool bmf_unit(const ReqDesc* __restrict__ descs, cons
     return true;
 }
 
-template <int R, bool kPre>
+template <int R>
 __global__ __launch_bounds__(kLanes * R) __attribute__((amdgpu_waves_per_eu(4))) void post_bmf_kernel(
     const ReqDesc* __restrict__ descs, const SegTable segs) {
     constexpr int PW = kLanes / R;
@@ -1084,12 +1086,12 @@ __global__ __launch_bounds__(kLanes * R) __attribute__((amdgpu_waves_per_eu(4)))
     GLOBAL int32_t* expo = g(d.expo);
     float fr[8][4];
     int fe[8];
-    if constexpr (kPre) load_frontier<R, true>(nd, L, tile, U.tiles, N, U.Cpad, part, expo, fr, fe);
+    load_frontier<R, true>(nd, L, tile, U.tiles, N, U.Cpad, part, expo, fr, fe);
     stage_codes<R>(CL, nd, N, U.Cpad, tile * kLanes, g(d.codes));
     stage_mats<R, 1>(S, nd, g(d.P32), nullptr);
     __syncthreads();
     float p[8][4];
-    const int ek = bmf_postorder<R, 1, 1, true, kPre>(nd, L, S, CL, tile, U.tiles, N, U.Cpad, part, expo, fr, fe, p);
+    const int ek = bmf_postorder<R, 1, 1, true, true>(nd, L, S, CL, tile, U.tiles, N, U.Cpad, part, expo, fr, fe, p);
     if (!(U.sg.flags & 1)) {
         *reinterpret_cast<GLOBAL F4*>(chunk<R>(part, nd[1] - N, tile, U.tiles) + L.part) = to_f4(p[1]);
         if (L.r == 0) expo[static_cast<size_t>(nd[1] - N) * U.Cpad + c] = ek;
@@ -1417,15 +1419,13 @@ hipError_t level_r(KernelClass k, bool blocked, const ReqDesc* descs, const SegT
     const int blocks = (n_units + kWavesPerBlock - 1) / kWavesPerBlock;
     if constexpr (std::is_same<T, float>::value && (R & (R - 1)) == 0) {
         if (blocked) {
-            // launches whose workgroups all fit on the chip at once with the
-            // frontier held in registers (5 waves per SIMD, 4 SIMDs, 256 CUs)
-            // are latency-bound: take the variant with one load round trip
+            // pre-order launches whose workgroups all fit on the chip at once
+            // with the frontier held in registers (5 waves per SIMD, 4 SIMDs,
+            // 256 CUs) are latency-bound: take the variant with one load round
+            // trip (the post-order kernel holds it at full occupancy always)
             const bool narrow = n_units <= 256 * 4 * 5 / R;
             if (k == kPost) {
-                if (narrow)
-                    hipLaunchKernelGGL((post_bmf_kernel<R, true>), dim3(n_units), dim3(kLanes * R), 0, st, descs, t);
-                else
-                    hipLaunchKernelGGL((post_bmf_kernel<R, false>), dim3(n_units), dim3(kLanes * R), 0, st, descs, t);
+                hipLaunchKernelGGL((post_bmf_kernel<R>), dim3(n_units), dim3(kLanes * R), 0, st, descs, t);
             } else {
                 if (narrow)
                     hipLaunchKernelGGL((pre_bmf_kernel<R, true>), dim3(n_units), dim3(kLanes * R), 0, st, descs, t);
