@@ -115,6 +115,19 @@ phg_status phg_set_categories(phg_context *ctx, const double *rates,
  * entry whose partial is all ones. */
 phg_status phg_set_tip_states(phg_context *ctx, const int32_t *codes);
 
+/* General tip partial vector of one tip (Methods, pruning equation: a tip's
+ * partial vector in its general form, for partial ambiguity or observation
+ * error models).  partials is C*S, pattern-major: partials[c*S + s] is the
+ * probability of the tip's data at pattern c given state s; finite, >= 0.
+ * It replaces the tip's code (which must still be set and is then ignored);
+ * NULL reverts the tip to its code.  Copied.  Values are used as given
+ * (rounded to float in FP32 contexts; no rescaling at tips).  A context with
+ * any such tip evaluates on the level schedule: PHG_SCHEDULE_AUTO picks it
+ * and PHG_SCHEDULE_BLOCKS is rejected (PHG_ERR_ARG) while one is set.  The
+ * device copy lives in memory the context allocates itself, also when a
+ * workspace is bound.  Not available through the serving engine. */
+phg_status phg_set_tip_partials(phg_context *ctx, int tip, const double *partials);
+
 /* Pattern weights W_c (C entries, finite, >= 0): the multiplicity of each
  * unique column (Methods, pattern-compression remark).  A zero-weight
  * pattern contributes nothing, even if its likelihood is zero.

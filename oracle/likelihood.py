@@ -128,10 +128,12 @@ def _rescale(x, exps):
     return x, exps
 
 
-def postorder(parent, P, codes, S, R):
+def postorder(parent, P, codes, S, R, tip_vectors=None):
     """Post-order (Felsenstein pruning) partials for every node.
 
     p_k,r,c = [P^(r)(b_i)] p_i,r,c  o  [P^(r)(b_j)] p_j,r,c   (pruning Eq.)
+    A tip's partial is built from its code, or taken from tip_vectors[tip]
+    ([C, S], the general tip vector of the pruning recursion) when given.
     Returns (p, E) where p[v] is [R, C, S] and the true partial equals
     p[v] * 2^E[v] (E[v] is an int64 [C] exponent vector).
     """
@@ -142,7 +144,11 @@ def postorder(parent, P, codes, S, R):
     p = [None] * n
     E = [None] * n
     for v in range(n_tips):
-        p[v] = np.broadcast_to(tip_partials(codes[v], S), (R, C, S))
+        if tip_vectors is not None and v in tip_vectors:
+            tv = np.asarray(tip_vectors[v], dtype=np.float64).reshape(C, S)
+        else:
+            tv = tip_partials(codes[v], S)
+        p[v] = np.broadcast_to(tv, (R, C, S))
         E[v] = np.zeros(C, np.int64)
     for k in post:
         if k < n_tips:
@@ -228,7 +234,7 @@ def branch_gradients(parent, Q, p, q, rates, weights, pattern_weights):
 
 
 def evaluate(parent, b, V, Vinv, lam, pi, rates, weights, codes, pattern_weights,
-             want_partials=False):
+             want_partials=False, tip_vectors=None):
     """logL and all 2N-2 branch derivatives for one instance.
 
     Returns a dict with keys logl, grad [2N-2], absgrad [2N-2] and site_ll [C];
@@ -238,7 +244,7 @@ def evaluate(parent, b, V, Vinv, lam, pi, rates, weights, codes, pattern_weights
     S = np.asarray(lam).shape[-1]
     R = np.asarray(rates).shape[0]
     P = transition_matrices(V, Vinv, lam, rates, b)
-    p, E = postorder(parent, P, codes, S, R)
+    p, E = postorder(parent, P, codes, S, R, tip_vectors)
     root = len(p) - 1
     sll = site_log_likelihoods(p[root], E[root], pi, weights)
     logl = log_likelihood(sll, pattern_weights)
@@ -255,4 +261,4 @@ def evaluate_problem(prob, want_partials=False):
     """evaluate() on an object with the fields of a synthetic Problem."""
     return evaluate(prob.parent, prob.b, prob.V, prob.Vinv, prob.lam, prob.pi,
                     prob.rates, prob.weights, prob.codes, prob.pattern_weights,
-                    want_partials=want_partials)
+                    want_partials=want_partials, tip_vectors=getattr(prob, "tip_vectors", None))

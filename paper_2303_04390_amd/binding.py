@@ -58,6 +58,7 @@ _SIGS = {
     "phg_set_root_frequencies": [_vp, _dp],
     "phg_set_categories": [_vp, _dp, _dp],
     "phg_set_tip_states": [_vp, _ip],
+    "phg_set_tip_partials": [_vp, _c.c_int, _dp],
     "phg_set_pattern_weights": [_vp, _dp],
     "phg_prepare": [_vp],
     "phg_set_schedule": [_vp, _c.c_int],
@@ -195,6 +196,16 @@ def phg_set_categories(ctx, rates, weights):
 def phg_set_tip_states(ctx, codes):
     a = _i32(codes)
     _check(lib().phg_set_tip_states(ctx, _p(a)), ctx, "phg_set_tip_states")
+
+
+def phg_set_tip_partials(ctx, tip: int, partials):
+    """partials: [C, S] array (tip's general partial vector), or None to
+    revert the tip to its code."""
+    if partials is None:
+        _check(lib().phg_set_tip_partials(ctx, int(tip), None), ctx, "phg_set_tip_partials")
+        return
+    a = _f64(partials)
+    _check(lib().phg_set_tip_partials(ctx, int(tip), _p(a)), ctx, "phg_set_tip_partials")
 
 
 def phg_set_pattern_weights(ctx, w):
@@ -412,6 +423,8 @@ def set_problem(h, prob):
     phg_set_root_frequencies(h, prob.pi)
     phg_set_categories(h, prob.rates, prob.weights)
     phg_set_tip_states(h, prob.codes)
+    for tip, vec in sorted((getattr(prob, "tip_vectors", None) or {}).items()):
+        phg_set_tip_partials(h, tip, vec)
     phg_set_pattern_weights(h, prob.pattern_weights)
 
 

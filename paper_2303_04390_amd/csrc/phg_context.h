@@ -6,6 +6,7 @@
 
 #include <cstdarg>
 #include <cstdio>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -33,6 +34,7 @@ enum InputBit : unsigned {
     kTime = 1u << 7,   // node heights + branch rate scalars (time tree)
     kSets = 1u << 8,   // branch sets
     kDesc = 1u << 9,   // descriptor fields changed (no input of its own)
+    kTipVec = 1u << 10,  // general tip partial vectors
     kRequired = kTopo | kB | kEig | kPi | kCat | kTips,
 };
 
@@ -63,6 +65,13 @@ struct phg_context {
     std::vector<double> heights, trates;
     std::vector<int32_t> set_ptr, set_idx;
     int n_sets = 0;
+    // general tip partials: tip -> C x S values (pattern-major); on the device
+    // in the partials layout of the level kernels, one slot per such tip in
+    // ascending tip order, in memory the context allocates itself
+    std::map<int, std::vector<double>> tip_vectors;
+    void* d_tipvec = nullptr;
+    size_t d_tipvec_bytes = 0;
+    int32_t* d_tslot = nullptr;
     unsigned have = 0;           // inputs set at least once
     unsigned dirty = 0;          // inputs changed since the last upload
 

@@ -172,8 +172,10 @@ void build_schedule(phg_context* ctx) {
     ctx->post_lv.clear();
     ctx->pre_lv.clear();
     const bool fp32 = ctx->prec == PHG_FP32_SCALED;
+    // the blocked kernels take tips by their codes only
     ctx->blocked = ctx->sched_mode == PHG_SCHEDULE_BLOCKS ||
-                   (ctx->sched_mode == PHG_SCHEDULE_AUTO && phg::blocked_supported(ctx->S, ctx->R, fp32));
+                   (ctx->sched_mode == PHG_SCHEDULE_AUTO && phg::blocked_supported(ctx->S, ctx->R, fp32) &&
+                    ctx->tip_vectors.empty());
     if (ctx->blocked) {
         // block roots: internal nodes at depths 0, 3, 6, ...; records grouped
         // by block depth m (depth / 3), shallowest first
@@ -319,6 +321,107 @@ phg_status ensure_device(phg_context* ctx) {
     return PHG_OK;
 }
 
+// General tip partial vectors in the partials layout of the level kernel
+// family that (S, R) runs on, one slot per tip with such a vector, every
+// category (the vector does not depend on it); padding patterns are
+// all-ones like code S, padding states zero.
+template <typename T>
+void pack_tip_vectors(const phg_context* ctx, std::vector<T>& out, std::vector<int32_t>& tslot) {
+    const int N = ctx->N, C = ctx->C, S = ctx->S, R = ctx->R, Cpad = ctx->Cpad, tiles = ctx->tiles;
+    const bool fp32 = ctx->prec == PHG_FP32_SCALED;
+    const size_t G = ctx->tip_vectors.size();
+    tslot.assign(N, -1);
+    auto value = [&](const std::vector<double>& v, int c, int s) { return c < C ? v[static_cast<size_t>(c) * S + s] : 1.0; };
+    if (uses_s4_kernels(S, R)) {
+        // [slot][tile][R][64 lanes][4 states]
+        const size_t per = static_cast<size_t>(tiles) * R * kLanes * 4;
+        out.assign(G * per, T(0));
+        int gslot = 0;
+        for (const auto& kv : ctx->tip_vectors) {
+            tslot[kv.first] = gslot;
+            for (int c = 0; c < Cpad; ++c)
+                for (int r = 0; r < R; ++r)
+                    for (int st = 0; st < 4; ++st)
+                        out[((static_cast<size_t>(gslot) * tiles + c / kLanes) * R + r) * kLanes * 4 +
+                            (c % kLanes) * 4 + st] = static_cast<T>(value(kv.second, c, st));
+            ++gslot;
+        }
+    } else if (uses_gl_kernels(S, R)) {
+        // [slot][tile][R][TP][row], state t at column gl_col(t)
+        const int TP = gl_tile_patterns(S, fp32), row = gl_row(S), kbp = gl_kbp(S);
+        const size_t per = static_cast<size_t>(tiles) * R * TP * row;
+        out.assign(G * per, T(0));
+        int gslot = 0;
+        for (const auto& kv : ctx->tip_vectors) {
+            tslot[kv.first] = gslot;
+            for (int c = 0; c < Cpad; ++c)
+                for (int r = 0; r < R; ++r)
+                    for (int st = 0; st < S; ++st)
+                        out[(((static_cast<size_t>(gslot) * tiles + c / TP) * R + r) * TP + c % TP) * row +
+                            gl_col(st, kbp)] = static_cast<T>(value(kv.second, c, st));
+            ++gslot;
+        }
+    } else {
+        // [slot][tile][R][S][TP]
+        const int TP = gs_tile_patterns(fp32);
+        const size_t per = static_cast<size_t>(tiles) * R * S * TP;
+        out.assign(G * per, T(0));
+        int gslot = 0;
+        for (const auto& kv : ctx->tip_vectors) {
+            tslot[kv.first] = gslot;
+            for (int c = 0; c < Cpad; ++c)
+                for (int r = 0; r < R; ++r)
+                    for (int st = 0; st < S; ++st)
+                        out[(((static_cast<size_t>(gslot) * tiles + c / TP) * R + r) * S + st) * TP + c % TP] =
+                            static_cast<T>(value(kv.second, c, st));
+            ++gslot;
+        }
+    }
+}
+
+void free_tip_vectors(phg_context* ctx) {
+    if (ctx->d_tipvec) (void)hipFree(ctx->d_tipvec);
+    if (ctx->d_tslot) (void)hipFree(ctx->d_tslot);
+    ctx->d_tipvec = nullptr;
+    ctx->d_tslot = nullptr;
+    ctx->d_tipvec_bytes = 0;
+    ctx->rd.tslot = nullptr;
+    ctx->rd.tipvec = nullptr;
+}
+
+phg_status upload_tip_vectors(phg_context* ctx) {
+    if (ctx->tip_vectors.empty()) {
+        free_tip_vectors(ctx);
+        return PHG_OK;
+    }
+    std::vector<int32_t> tslot;
+    std::vector<float> v32;
+    std::vector<double> v64;
+    const bool fp32 = ctx->prec == PHG_FP32_SCALED;
+    if (fp32)
+        pack_tip_vectors<float>(ctx, v32, tslot);
+    else
+        pack_tip_vectors<double>(ctx, v64, tslot);
+    const void* src = fp32 ? static_cast<const void*>(v32.data()) : static_cast<const void*>(v64.data());
+    const size_t bytes = fp32 ? v32.size() * sizeof(float) : v64.size() * sizeof(double);
+    if (bytes != ctx->d_tipvec_bytes || !ctx->d_tslot) {
+        free_tip_vectors(ctx);
+        PHG_HIP(ctx, hipMalloc(&ctx->d_tipvec, bytes));
+        ctx->d_tipvec_bytes = bytes;
+        void* ts = nullptr;
+        PHG_HIP(ctx, hipMalloc(&ts, static_cast<size_t>(ctx->N) * sizeof(int32_t)));
+        ctx->d_tslot = static_cast<int32_t*>(ts);
+    }
+    PHG_HIP(ctx, hipMemcpyAsync(ctx->d_tipvec, src, bytes, hipMemcpyHostToDevice, ctx->stream));
+    PHG_HIP(ctx, hipMemcpyAsync(ctx->d_tslot, tslot.data(), tslot.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                                ctx->stream));
+    // the sources are pageable locals: finish the copies before they go
+    PHG_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    ctx->rd.tslot = ctx->d_tslot;
+    ctx->rd.tipvec = ctx->d_tipvec;
+    return PHG_OK;
+}
+
 phg_status upload(phg_context* ctx) {
     const Plan& pl = ctx->plan;
     char* a = ctx->arena;
@@ -327,12 +430,13 @@ phg_status upload(phg_context* ctx) {
     auto put = [&](size_t off, const void* src, size_t bytes) {
         return hipMemcpyAsync(a + off, src, bytes, hipMemcpyHostToDevice, st);
     };
+    if (dirty & kTipVec) PHG_TRY(upload_tip_vectors(ctx));
     if (dirty & kTopo) {
         PHG_HIP(ctx, put(pl.sched, ctx->sched.data(), ctx->sched.size() * sizeof(int32_t)));
         PHG_HIP(ctx, put(pl.ch_parent, ctx->parent.data(), ctx->parent.size() * sizeof(int32_t)));
         PHG_HIP(ctx, put(pl.ch_kids, ctx->kids.data(), ctx->kids.size() * sizeof(int32_t)));
     }
-    if (dirty & (kTopo | kDesc)) {
+    if (dirty & (kTopo | kDesc | kTipVec)) {
         ctx->rd.blocked = ctx->blocked ? 1 : 0;
         ctx->rd.eig_cat = ctx->eig_cat ? 1 : 0;
         PHG_HIP(ctx, put(pl.desc, &ctx->rd, sizeof(ReqDesc)));
@@ -418,6 +522,7 @@ phg_status ctx_enqueue_eval(phg_context* ctx, double* d_logl, double* d_grad) {
 
 void ctx_drop_device(phg_context* ctx) {
     if (!ctx->dev_init) return;
+    free_tip_vectors(ctx);
     if (ctx->own_arena && ctx->arena) (void)hipFree(ctx->arena);
     if (ctx->host_out) (void)hipHostFree(ctx->host_out);
     ctx->host_out = nullptr;
@@ -506,6 +611,7 @@ phg_status phg_destroy(phg_context* ctx) {
         (void)hipSetDevice(ctx->device);
         if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
         for (hipEvent_t ev : ctx->prof_pool) (void)hipEventDestroy(ev);
+        free_tip_vectors(ctx);
         if (ctx->own_arena && ctx->arena) (void)hipFree(ctx->arena);
         if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
         if (ctx->host_out) (void)hipHostFree(ctx->host_out);
@@ -640,6 +746,32 @@ phg_status phg_set_tip_states(phg_context* ctx, const int32_t* codes) {
     return PHG_OK;
 }
 
+phg_status phg_set_tip_partials(phg_context* ctx, int tip, const double* partials) {
+    if (!ctx) return PHG_ERR_ARG;
+    if (tip < 0 || tip >= ctx->N) return ctx->fail(PHG_ERR_ARG, "tip %d outside [0, %d)", tip, ctx->N);
+    if (partials && ctx->sched_mode == PHG_SCHEDULE_BLOCKS)
+        return ctx->fail(PHG_ERR_ARG, "general tip partials need the level schedule (schedule is BLOCKS)");
+    const size_t n = static_cast<size_t>(ctx->C) * ctx->S;
+    const bool had_any = !ctx->tip_vectors.empty();
+    if (partials) {
+        for (size_t i = 0; i < n; ++i)
+            if (!std::isfinite(partials[i]) || partials[i] < 0.0)
+                return ctx->fail(PHG_ERR_ARG, "tip %d partial [%zu][%zu]=%g must be finite and >= 0", tip,
+                                 i / ctx->S, i % ctx->S, partials[i]);
+        ctx->tip_vectors[tip].assign(partials, partials + n);
+    } else {
+        ctx->tip_vectors.erase(tip);
+    }
+    // the schedule depends on whether any tip has a general vector
+    if (had_any != !ctx->tip_vectors.empty() && (ctx->have & kTopo)) {
+        build_schedule(ctx);
+        ctx->dirty |= kTopo;
+    }
+    ctx->have |= kTipVec;
+    ctx->dirty |= kTipVec;
+    return PHG_OK;
+}
+
 phg_status phg_set_pattern_weights(phg_context* ctx, const double* w) {
     if (!ctx) return PHG_ERR_ARG;
     if (!w) return ctx->fail(PHG_ERR_ARG, "w is NULL");
@@ -659,6 +791,8 @@ phg_status phg_set_schedule(phg_context* ctx, phg_schedule mode) {
     if (mode == PHG_SCHEDULE_BLOCKS &&
         !phg::blocked_supported(ctx->S, ctx->R, ctx->prec == PHG_FP32_SCALED))
         return ctx->fail(PHG_ERR_ARG, "the blocked schedule needs 4 states and R <= 8 (FP32) or R <= 4 (FP64)");
+    if (mode == PHG_SCHEDULE_BLOCKS && !ctx->tip_vectors.empty())
+        return ctx->fail(PHG_ERR_ARG, "the blocked schedule does not take general tip partials");
     ctx->sched_mode = mode;
     if (ctx->have & kTopo) {
         build_schedule(ctx);

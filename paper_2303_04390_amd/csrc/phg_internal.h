@@ -86,6 +86,12 @@ struct ReqDesc {
     double* sll;
     double* lpart;
     double* gpart;
+    // General tip partials (level schedule only): tslot[tip] is -1 for a tip
+    // given by codes, else the tip's slot in tipvec, which holds its C x S
+    // vector in the partials layout of the kernels (T, every category).
+    // Null when no tip has one.
+    const int32_t* tslot;
+    const void* tipvec;
 };
 
 // A launch processes the work units of up to kMaxSegs segments; a segment is

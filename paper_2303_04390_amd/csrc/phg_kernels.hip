@@ -199,11 +199,20 @@ __device__ __forceinline__ void post_unit(const NodeTriple nt, const int tile, c
                                           const GLOBAL double* __restrict__ pi,
                                           const GLOBAL double* __restrict__ pw,
                                           GLOBAL double* __restrict__ sll,
-                                          GLOBAL double* __restrict__ lpart) {
+                                          GLOBAL double* __restrict__ lpart,
+                                          const GLOBAL int32_t* __restrict__ tslot,
+                                          const GLOBAL T* __restrict__ tipvec) {
     const int c = tile * kLanes + lane;
     const bool tip_i = nt.i < N, tip_j = nt.j < N;
-    const int code_i = tip_i ? codes[static_cast<size_t>(nt.i) * Cpad + c] : -1;
-    const int code_j = tip_j ? codes[static_cast<size_t>(nt.j) * Cpad + c] : -1;
+    // a tip reads its code, or its general partial vector (slot >= 0)
+    const int vsi = (tip_i && tslot) ? tslot[nt.i] : -1;
+    const int vsj = (tip_j && tslot) ? tslot[nt.j] : -1;
+    const int code_i = tip_i && vsi < 0 ? codes[static_cast<size_t>(nt.i) * Cpad + c] : -1;
+    const int code_j = tip_j && vsj < 0 ? codes[static_cast<size_t>(nt.j) * Cpad + c] : -1;
+    const GLOBAL T* src_i = tip_i ? tipvec : part;
+    const GLOBAL T* src_j = tip_j ? tipvec : part;
+    const int slot_i = tip_i ? vsi : nt.i - N;
+    const int slot_j = tip_j ? vsj : nt.j - N;
     const int ei = tip_i ? 0 : expo[static_cast<size_t>(nt.i - N) * Cpad + c];
     const int ej = tip_j ? 0 : expo[static_cast<size_t>(nt.j - N) * Cpad + c];
 
@@ -212,8 +221,8 @@ __device__ __forceinline__ void post_unit(const NodeTriple nt, const int tile, c
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         T vi[4], vj[4], mi[4], mj[4];
-        child_vec<T, R>(part, nt.i - N, tile, tiles, r, lane, code_i, vi);
-        child_vec<T, R>(part, nt.j - N, tile, tiles, r, lane, code_j, vj);
+        child_vec<T, R>(src_i, slot_i, tile, tiles, r, lane, code_i, vi);
+        child_vec<T, R>(src_j, slot_j, tile, tiles, r, lane, code_j, vj);
         matvec4(P + (static_cast<size_t>(nt.i) * R + r) * 16, vi, mi);
         matvec4(P + (static_cast<size_t>(nt.j) * R + r) * 16, vj, mj);
 #pragma unroll
@@ -270,7 +279,8 @@ __global__ __launch_bounds__(kBlock) void post_s4_kernel(const ReqDesc* __restri
     const Int4 t4 = reinterpret_cast<const GLOBAL Int4*>(g(d.sched))[sg.sched_off + node_ix];
     const NodeTriple nt{t4.x, t4.y, t4.z, 0};
     post_unit<T, R>(nt, tile, tiles, d.N, d.Cpad, lane, sg.flags, g(d.codes), g(part_of<T>(d)),
-                    g(d.expo), g(ptab<T>(d)), g(d.cweights), g(d.pi), g(d.pw), g(d.sll), g(d.lpart));
+                    g(d.expo), g(ptab<T>(d)), g(d.cweights), g(d.pi), g(d.pw), g(d.sll), g(d.lpart),
+                    g(d.tslot), g(static_cast<const T*>(d.tipvec)));
 }
 
 // ---------------------------------------------------------------- pre-order + gradient
@@ -285,12 +295,20 @@ __device__ __forceinline__ void pre_unit(const NodeTriple nt, const int tile, co
                                          const GLOBAL double* __restrict__ cw,
                                          const GLOBAL double* __restrict__ pi,
                                          const GLOBAL double* __restrict__ pw,
-                                         GLOBAL double* __restrict__ gpart) {
+                                         GLOBAL double* __restrict__ gpart,
+                                         const GLOBAL int32_t* __restrict__ tslot,
+                                         const GLOBAL T* __restrict__ tipvec) {
     const int c = tile * kLanes + lane;
     const bool is_root = nt.k == 2 * N - 2;
     const bool tip_i = nt.i < N, tip_j = nt.j < N;
-    const int code_i = tip_i ? codes[static_cast<size_t>(nt.i) * Cpad + c] : -1;
-    const int code_j = tip_j ? codes[static_cast<size_t>(nt.j) * Cpad + c] : -1;
+    const int vsi = (tip_i && tslot) ? tslot[nt.i] : -1;
+    const int vsj = (tip_j && tslot) ? tslot[nt.j] : -1;
+    const int code_i = tip_i && vsi < 0 ? codes[static_cast<size_t>(nt.i) * Cpad + c] : -1;
+    const int code_j = tip_j && vsj < 0 ? codes[static_cast<size_t>(nt.j) * Cpad + c] : -1;
+    const GLOBAL T* src_i = tip_i ? tipvec : part;
+    const GLOBAL T* src_j = tip_j ? tipvec : part;
+    const int slot_i = tip_i ? vsi : nt.i - N;
+    const int slot_j = tip_j ? vsj : nt.j - N;
 
     T qi[R][4], qj[R][4];
     T num_i = T(0), num_j = T(0), den = T(0);
@@ -305,8 +323,8 @@ __device__ __forceinline__ void pre_unit(const NodeTriple nt, const int tile, co
             child_vec<T, R>(part, nt.k - N, tile, tiles, r, lane, -1, q);
         }
         T vi[4], vj[4], mi[4], mj[4], dmi[4], dmj[4], ui[4], uj[4];
-        child_vec<T, R>(part, nt.i - N, tile, tiles, r, lane, code_i, vi);
-        child_vec<T, R>(part, nt.j - N, tile, tiles, r, lane, code_j, vj);
+        child_vec<T, R>(src_i, slot_i, tile, tiles, r, lane, code_i, vi);
+        child_vec<T, R>(src_j, slot_j, tile, tiles, r, lane, code_j, vj);
         const GLOBAL T* Pi = P + (static_cast<size_t>(nt.i) * R + r) * 16;
         const GLOBAL T* Pj = P + (static_cast<size_t>(nt.j) * R + r) * 16;
         matvec4(Pi, vi, mi);
@@ -387,7 +405,8 @@ __global__ __launch_bounds__(kBlock) void pre_s4_kernel(const ReqDesc* __restric
     const Int4 t4 = reinterpret_cast<const GLOBAL Int4*>(g(d.sched))[sg.sched_off + node_ix];
     const NodeTriple nt{t4.x, t4.y, t4.z, 0};
     pre_unit<T, R>(nt, tile, tiles, d.N, d.Cpad, lane, g(d.codes), g(part_of<T>(d)), g(ptab<T>(d)),
-                   g(dptab<T>(d)), g(d.cweights), g(d.pi), g(d.pw), g(d.gpart));
+                   g(dptab<T>(d)), g(d.cweights), g(d.pi), g(d.pw), g(d.gpart), g(d.tslot),
+                   g(static_cast<const T*>(d.tipvec)));
 }
 
 // ---------------------------------------------------------------- blocked schedule (4 states)

@@ -489,6 +489,19 @@ __device__ __forceinline__ void stage_exps(int (&esh)[NC][TP], const int (&node)
     }
 }
 
+// Where child x's input vector lives for (tile): an internal child's stored
+// partial, a tip's general partial vector (tslot >= 0), or null for a tip
+// given by its code.
+template <typename T>
+__device__ __forceinline__ const GLOBAL T* tip_src(const ReqDesc& d, int x, int tile, int tiles, size_t tstride,
+                                                   const GLOBAL T* part) {
+    const int N = d.N;
+    if (x >= N) return part + (static_cast<size_t>(x - N) * tiles + tile) * tstride;
+    const int gx = d.tslot ? g(d.tslot)[x] : -1;
+    return gx >= 0 ? g(static_cast<const T*>(d.tipvec)) + (static_cast<size_t>(gx) * tiles + tile) * tstride
+                   : nullptr;
+}
+
 struct GlUnit {
     const ReqDesc* d;
     Segment sg;
@@ -553,22 +566,23 @@ __global__ __launch_bounds__(64 * W) void post_gl_kernel(const ReqDesc* __restri
     Input<T, RB> si, sj;
     tip_codes<T, RB>(si, tip_i, nt.i, d, tile, n);
     tip_codes<T, RB>(sj, tip_j, nt.j, d, tile, n);
-    const GLOBAL T* pi_base = tip_i ? nullptr : part + (static_cast<size_t>(nt.i - N) * tiles + tile) * tstride;
-    const GLOBAL T* pj_base = tip_j ? nullptr : part + (static_cast<size_t>(nt.j - N) * tiles + tile) * tstride;
+    // inputs: stored partials, or a tip's general partial vector, or (null) its code
+    const GLOBAL T* pi_base = tip_src<T>(d, nt.i, tile, tiles, tstride, part);
+    const GLOBAL T* pj_base = tip_src<T>(d, nt.j, tile, tiles, tstride, part);
     GLOBAL T* out_base = part + (static_cast<size_t>(nt.k - N) * tiles + tile) * tstride;
     const bool root = U.sg.flags & 1;
     {
         const int kids[2] = {nt.i, nt.j};
         stage_exps<TP, 2>(esh, kids, d, tile);      // read after the first barrier below
     }
-    si.lds = tip_i ? nullptr : vb[0];
-    sj.lds = tip_j ? nullptr : vb[1];
+    si.lds = pi_base ? vb[0] : nullptr;
+    sj.lds = pj_base ? vb[1] : nullptr;
     si.base = sj.base = nullptr;
     T mx[RB][4] = {};
     double site[RB][4] = {};
     for (int r = 0; r < R; ++r) {
-        if (!tip_i) stage_vec<T, TP, KIT>(vb[0], pi_base + r * rstride, ge);
-        if (!tip_j) stage_vec<T, TP, KIT>(vb[1], pj_base + r * rstride, ge);
+        if (pi_base) stage_vec<T, TP, KIT>(vb[0], pi_base + r * rstride, ge);
+        if (pj_base) stage_vec<T, TP, KIT>(vb[1], pj_base + r * rstride, ge);
         __syncthreads();
         Cols<T, RB, NBW> mi, mj, unused;
         fwd<T, RB, NBW, G, false>(P + (static_cast<size_t>(nt.i) * R + r) * mstride, nullptr, si, ge, cb0, lane,
@@ -708,20 +722,23 @@ __global__ __launch_bounds__(64 * W, (W == 2 && sizeof(T) == 4) ? 4 : 1) void pr
     GLOBAL T* pi_base = tip_i ? nullptr : part + (static_cast<size_t>(nt.i - N) * tiles + tile) * tstride;
     GLOBAL T* pj_base = tip_j ? nullptr : part + (static_cast<size_t>(nt.j - N) * tiles + tile) * tstride;
     const GLOBAL T* qk_base = is_root ? nullptr : part + (static_cast<size_t>(nt.k - N) * tiles + tile) * tstride;
+    // inputs (q is written over p for internal children only)
+    const GLOBAL T* pi_src = tip_src<T>(d, nt.i, tile, tiles, tstride, part);
+    const GLOBAL T* pj_src = tip_src<T>(d, nt.j, tile, tiles, tstride, part);
     {
         const int nodes[3] = {nt.i, nt.j, is_root ? -1 : nt.k};
         stage_exps<TP, 3>(esh, nodes, d, tile);
     }
     if constexpr (!kStage) __syncthreads();    // exponents in LDS (staging has its own barrier)
-    si.lds = kStage && !tip_i ? vb[0] : nullptr;
-    sj.lds = kStage && !tip_j ? vb[1] : nullptr;
+    si.lds = kStage && pi_src ? vb[0] : nullptr;
+    sj.lds = kStage && pj_src ? vb[1] : nullptr;
     T num_i[RB][4] = {}, num_j[RB][4] = {}, den[RB][4] = {}, mxi[RB][4] = {}, mxj[RB][4] = {};
     for (int r = 0; r < R; ++r) {
-        si.base = !kStage && pi_base ? pi_base + r * rstride : nullptr;
-        sj.base = !kStage && pj_base ? pj_base + r * rstride : nullptr;
+        si.base = !kStage && pi_src ? pi_src + r * rstride : nullptr;
+        sj.base = !kStage && pj_src ? pj_src + r * rstride : nullptr;
         if constexpr (kStage) {
-            if (!tip_i) stage_vec<T, TP, KIT>(vb[0], pi_base + r * rstride, ge);
-            if (!tip_j) stage_vec<T, TP, KIT>(vb[1], pj_base + r * rstride, ge);
+            if (pi_src) stage_vec<T, TP, KIT>(vb[0], pi_src + r * rstride, ge);
+            if (pj_src) stage_vec<T, TP, KIT>(vb[1], pj_src + r * rstride, ge);
             if (!is_root) stage_vec<T, TP, KIT>(vb[kStage ? 2 : 0], qk_base + r * rstride, ge);
             __syncthreads();  // inputs of category r staged
         }

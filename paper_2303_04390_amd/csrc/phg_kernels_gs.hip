@@ -308,7 +308,8 @@ __device__ __forceinline__ void post_unit_gs(const NodeTriple nt, const int tile
                                              const GLOBAL double* __restrict__ pi,
                                              const GLOBAL double* __restrict__ pw,
                                              GLOBAL double* __restrict__ sll, GLOBAL double* __restrict__ lpart,
-                                             const int tiles) {
+                                             const int tiles, const GLOBAL int32_t* __restrict__ tslot,
+                                             const GLOBAL T* __restrict__ tipvec) {
     constexpr int TP = 16 * RB;
     const int gq = lane >> 4, n = lane & 15;
     const size_t rstride = static_cast<size_t>(S) * TP;          // one category
@@ -321,8 +322,15 @@ __device__ __forceinline__ void post_unit_gs(const NodeTriple nt, const int tile
         si.code[rb] = tip_i ? codes[static_cast<size_t>(nt.i) * Cpad + c] : 0;
         sj.code[rb] = tip_j ? codes[static_cast<size_t>(nt.j) * Cpad + c] : 0;
     }
-    const GLOBAL T* pi_base = tip_i ? nullptr : part + (static_cast<size_t>(nt.i - N) * tiles + tile) * tstride;
-    const GLOBAL T* pj_base = tip_j ? nullptr : part + (static_cast<size_t>(nt.j - N) * tiles + tile) * tstride;
+    // a tip's input: its code, or its general partial vector (slot >= 0)
+    const int vsi = (tip_i && tslot) ? tslot[nt.i] : -1;
+    const int vsj = (tip_j && tslot) ? tslot[nt.j] : -1;
+    const GLOBAL T* pi_base = !tip_i  ? part + (static_cast<size_t>(nt.i - N) * tiles + tile) * tstride
+                              : vsi >= 0 ? tipvec + (static_cast<size_t>(vsi) * tiles + tile) * tstride
+                                        : nullptr;
+    const GLOBAL T* pj_base = !tip_j  ? part + (static_cast<size_t>(nt.j - N) * tiles + tile) * tstride
+                              : vsj >= 0 ? tipvec + (static_cast<size_t>(vsj) * tiles + tile) * tstride
+                                        : nullptr;
     GLOBAL T* out_base = part + (static_cast<size_t>(nt.k - N) * tiles + tile) * tstride;
     const bool root = flags & 1;
 
@@ -427,7 +435,7 @@ __global__ __launch_bounds__(256) void post_gs_kernel(const ReqDesc* __restrict_
     const NodeTriple nt{t4.x, t4.y, t4.z, 0};
     post_unit_gs<T, RB, NB>(nt, tile, d.N, d.Cpad, d.S, d.R, lane, sg.flags, g(d.codes),
                             g(static_cast<T*>(d.part)), g(d.expo), g(ptab<T>(d)), g(d.cweights), g(d.pi),
-                            g(d.pw), g(d.sll), g(d.lpart), tiles);
+                            g(d.pw), g(d.sll), g(d.lpart), tiles, g(d.tslot), g(static_cast<const T*>(d.tipvec)));
 }
 
 // ---------------------------------------------------------------- pre-order + gradient
@@ -441,7 +449,9 @@ __device__ __forceinline__ void pre_unit_gs(const NodeTriple nt, const int tile,
                                             const GLOBAL double* __restrict__ cw,
                                             const GLOBAL double* __restrict__ pi,
                                             const GLOBAL double* __restrict__ pw,
-                                            GLOBAL double* __restrict__ gpart, const int tiles, T* lds) {
+                                            GLOBAL double* __restrict__ gpart, const int tiles, T* lds,
+                                            const GLOBAL int32_t* __restrict__ tslot,
+                                            const GLOBAL T* __restrict__ tipvec) {
     constexpr int TP = 16 * RB;
     constexpr int LS = TP + 16 * 4 / static_cast<int>(sizeof(T));   // LDS row stride (padded)
     const int gq = lane >> 4, n = lane & 15;
@@ -459,6 +469,12 @@ __device__ __forceinline__ void pre_unit_gs(const NodeTriple nt, const int tile,
     GLOBAL T* pi_base = tip_i ? nullptr : part + (static_cast<size_t>(nt.i - N) * tiles + tile) * tstride;
     GLOBAL T* pj_base = tip_j ? nullptr : part + (static_cast<size_t>(nt.j - N) * tiles + tile) * tstride;
     const GLOBAL T* qk_base = is_root ? nullptr : part + (static_cast<size_t>(nt.k - N) * tiles + tile) * tstride;
+    // inputs: stored partials, or a tip's general partial vector (slot >= 0),
+    // or (null) its code; q is written for internal children only
+    const int vsi = (tip_i && tslot) ? tslot[nt.i] : -1;
+    const int vsj = (tip_j && tslot) ? tslot[nt.j] : -1;
+    const GLOBAL T* pi_src = vsi >= 0 ? tipvec + (static_cast<size_t>(vsi) * tiles + tile) * tstride : pi_base;
+    const GLOBAL T* pj_src = vsj >= 0 ? tipvec + (static_cast<size_t>(vsj) * tiles + tile) * tstride : pj_base;
 
     T num_i[RB][4], num_j[RB][4], den[RB][4], mxi[RB][4], mxj[RB][4];
 #pragma unroll
@@ -467,8 +483,8 @@ __device__ __forceinline__ void pre_unit_gs(const NodeTriple nt, const int tile,
         for (int i = 0; i < 4; ++i) num_i[rb][i] = num_j[rb][i] = den[rb][i] = mxi[rb][i] = mxj[rb][i] = T(0);
 
     for (int r = 0; r < R; ++r) {
-        si.base = pi_base ? pi_base + r * rstride : nullptr;
-        sj.base = pj_base ? pj_base + r * rstride : nullptr;
+        si.base = pi_src ? pi_src + r * rstride : nullptr;
+        sj.base = pj_src ? pj_src + r * rstride : nullptr;
         const size_t moff = (static_cast<size_t>(0) + r) * S * S;
         const GLOBAL T* Pi = P + static_cast<size_t>(nt.i) * R * S * S + moff;
         const GLOBAL T* Pj = P + static_cast<size_t>(nt.j) * R * S * S + moff;
@@ -595,7 +611,7 @@ __global__ __launch_bounds__(256) void pre_gs_kernel(const ReqDesc* __restrict__
     const NodeTriple nt{t4.x, t4.y, t4.z, 0};
     pre_unit_gs<T, RB, NB>(nt, tile, d.N, d.Cpad, d.S, d.R, lane, g(d.codes), g(static_cast<T*>(d.part)),
                            g(ptab<T>(d)), g(dptab<T>(d)), g(d.cweights), g(d.pi), g(d.pw), g(d.gpart),
-                           tiles, lds_all[wave]);
+                           tiles, lds_all[wave], g(d.tslot), g(static_cast<const T*>(d.tipvec)));
 }
 
 template <typename T, int RB>

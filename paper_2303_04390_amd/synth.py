@@ -56,6 +56,8 @@ class Problem:
     codes  : int32 [N, C]   tip states 0..S-1, or S for a fully ambiguous entry
     pattern_weights: float64 [C]
     Q      : float64 [S,S]  the generator itself (for tests and simulation; [R,S,S] per category)
+    tip_vectors: optional {tip: float64 [C,S]} general tip partial vectors
+             that replace those tips' codes
     """
     parent: np.ndarray
     b: np.ndarray
@@ -69,6 +71,7 @@ class Problem:
     pattern_weights: np.ndarray
     Q: np.ndarray
     name: str = ""
+    tip_vectors: Optional[dict] = None
 
     @property
     def n_tips(self) -> int:

@@ -29,12 +29,14 @@ def expm_P(Q, rates, b):
     return P, dP
 
 
-def brute_site_likelihood(parent, P, codes, pi, weights, deriv_branch=None, dP=None):
+def brute_site_likelihood(parent, P, codes, pi, weights, deriv_branch=None, dP=None, tip_vectors=None):
     """L_c = sum_r w_r sum_{internal states} pi_root prod_branches P[x][s_par, s_x].
 
     Tip x with code y contributes P[x][s_par, y]; code S (ambiguous) sums over
-    the unobserved tip state.  With deriv_branch, that branch's factor uses
-    dP instead of P, giving d L_c / d b_x.
+    the unobserved tip state.  A tip with a general vector v (tip_vectors[x],
+    [C, S]) contributes sum_t P[x][s_par, t] v[c, t]: its state summed out,
+    weighted by v.  With deriv_branch, that branch's factor uses dP instead of
+    P, giving d L_c / d b_x.
     Returns [C] site values.
     """
     n = len(parent)
@@ -53,7 +55,9 @@ def brute_site_likelihood(parent, P, codes, pi, weights, deriv_branch=None, dP=N
             for x in range(n - 1):
                 M = (dP if x == deriv_branch else P)[x, r]
                 sp = st[int(parent[x])]
-                if x < n_tips:
+                if x < n_tips and tip_vectors is not None and x in tip_vectors:
+                    fac = np.asarray(tip_vectors[x]) @ M[sp]
+                elif x < n_tips:
                     y = codes[x]
                     row = M[sp]
                     fac = np.where(y < S, row[np.minimum(y, S - 1)], row.sum())

@@ -272,3 +272,38 @@ def test_category_eigen_validation():
         assert e.value.status == B.PHG_ERR_ARG
     finally:
         B.phg_destroy(ctx)
+
+
+def test_tip_partials_validation_and_schedule():
+    """phg_set_tip_partials: argument checks, and the schedule rule (a context
+    with any general tip vector runs the level schedule)."""
+    N, C, S = 40, 12, 4
+    ctx = B.phg_create(N, C, S, 4, B.PHG_FP32_SCALED, 0)
+    try:
+        B.phg_set_topology(ctx, synth.yule_topology(N, np.random.default_rng(2)))
+        assert B.phg_get_schedule(ctx) == B.PHG_SCHEDULE_BLOCKS
+        good = np.full((C, S), 0.25)
+        for tip in (-1, N):
+            with pytest.raises(B.PhgError) as e:
+                B.phg_set_tip_partials(ctx, tip, good)
+            assert e.value.status == B.PHG_ERR_ARG
+        for bad in (-1e-3, np.nan, np.inf):
+            v = good.copy()
+            v[3, 1] = bad
+            with pytest.raises(B.PhgError) as e:
+                B.phg_set_tip_partials(ctx, 5, v)
+            assert e.value.status == B.PHG_ERR_ARG and "finite" in str(e.value)
+        assert B.phg_get_schedule(ctx) == B.PHG_SCHEDULE_BLOCKS      # rejected calls change nothing
+        B.phg_set_tip_partials(ctx, 5, good)
+        assert B.phg_get_schedule(ctx) == B.PHG_SCHEDULE_LEVELS      # AUTO falls back to levels
+        with pytest.raises(B.PhgError) as e:
+            B.phg_set_schedule(ctx, B.PHG_SCHEDULE_BLOCKS)
+        assert e.value.status == B.PHG_ERR_ARG
+        B.phg_set_tip_partials(ctx, 5, None)                         # back to its code
+        assert B.phg_get_schedule(ctx) == B.PHG_SCHEDULE_BLOCKS
+        B.phg_set_schedule(ctx, B.PHG_SCHEDULE_BLOCKS)
+        with pytest.raises(B.PhgError) as e:
+            B.phg_set_tip_partials(ctx, 5, good)                     # forced blocks: rejected
+        assert e.value.status == B.PHG_ERR_ARG
+    finally:
+        B.phg_destroy(ctx)
