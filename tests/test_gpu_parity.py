@@ -234,3 +234,26 @@ def test_blocked_caterpillar_levels():
     prob = synth.make_problem(parent, b, Q, pi, rates, w, C, rng, ambiguous_fraction=0.1)
     for prec in (B.PHG_FP64, B.PHG_FP32_SCALED):
         compare("caterpillar200", prob, prec, schedule=B.PHG_SCHEDULE_BLOCKS)
+
+
+@pytest.fixture(scope="module")
+def hky20k():
+    prob = synth.config_problem("hky1000", seed=7, n_tips=20000, n_patterns=130)
+    return prob, oracle.evaluate_problem(prob)
+
+
+@pytest.mark.parametrize("prec,schedule", [(B.PHG_FP32_SCALED, B.PHG_SCHEDULE_BLOCKS),
+                                           (B.PHG_FP32_SCALED, B.PHG_SCHEDULE_LEVELS),
+                                           (B.PHG_FP64, B.PHG_SCHEDULE_AUTO)])
+def test_large_tree(hky20k, prec, schedule):
+    """20,000 taxa (39,998 branches, the paper's largest branch count) with a
+    ragged pattern count: many block levels and node levels, wide launches."""
+    compare("hky20k", hky20k[0], prec, hky20k[1], schedule=schedule)
+
+
+def test_large_tree_twenty_states():
+    from tests.test_gpu_parity_states import generic_problem
+    prob = generic_problem(5000, 20, 70, seed=3, R=2)
+    ref = oracle.evaluate_problem(prob)
+    for prec in (B.PHG_FP32_SCALED, B.PHG_FP64):
+        compare("aa5000", prob, prec, ref)
