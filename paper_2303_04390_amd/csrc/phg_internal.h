@@ -172,10 +172,14 @@ __host__ __device__ constexpr inline int gl_col(int t, int kbp) { return (t & 3)
 __host__ __device__ constexpr inline int gl_mat_rows(int S) {
     return S <= 64 ? (S + 15) / 16 * 16 : (S + 63) / 64 * 64;
 }
-// Row blocks of 16 patterns per tile: two for FP32 at 33..128 states (each
-// matrix operand then feeds two MFMAs; at 65..128 states this wins even at
-// one wave per SIMD), one otherwise.
-inline int gl_row_blocks(int S, bool fp32) { return (fp32 && S > 32 && S <= 128) ? 2 : 1; }
+// Row blocks of 16 patterns per tile: two (each matrix operand then feeds two
+// MFMAs) for FP32 at 33..128 states and FP64 at 65..128, one otherwise.
+// Measured: at 65..128 states two win even at one wave per SIMD; four at
+// 33..64 states (FP32) and two at 33..64 (FP64) lose to the lost occupancy.
+inline int gl_row_blocks(int S, bool fp32) {
+    if (S <= 32 || S > 128) return 1;
+    return (fp32 || S > 64) ? 2 : 1;
+}
 inline int gl_tile_patterns(int S, bool fp32) { return 16 * gl_row_blocks(S, fp32); }
 hipError_t launch_level_gl(KernelClass k, const ReqDesc& shape, const ReqDesc* descs,
                            const SegTable& t, hipStream_t stream);
