@@ -986,6 +986,7 @@ hipError_t launch_gl_t(KernelClass k, int S, const ReqDesc* descs, const SegTabl
         PHG_GL_CASE(2, 1, 3)
         PHG_GL_CASE(2, 1, 4)
         PHG_GL_CASE(2, 3, 4)
+        PHG_GL_CASE(2, 4, 4)
     }
     PHG_GL_CASE(2, 2, 4)
     PHG_GL_CASE(1, 1, 2)
