@@ -264,8 +264,10 @@ def matvec_flops(parent, n_tips, C, R, S):
 
 def state_space_measurement(args, B, synth, stream, out):
     """Throughput and MFMA utilisation of the larger state spaces: the
-    500-taxon amino-acid and 128-taxon codon workloads, and a 122-state
-    (Markov-modulated size) case, in FP32 and FP64."""
+    500-taxon amino-acid and 128-taxon codon workloads, a 122-state
+    (Markov-modulated size) case and a 240-state case (the largest state
+    count of byte tip codes, near the paper's 256-state phylogeographic
+    models), in FP32 and FP64."""
     import torch
     res = {}
     cases = [("aa500", synth.config_problem("aa500", seed=args.seed)),
@@ -278,6 +280,11 @@ def state_space_measurement(args, B, synth, stream, out):
     rates, w = synth.discrete_gamma(0.5, 4)
     cases.append(("s122", synth.make_problem(parent, synth.exponential_branch_lengths(N122, 0.05, rng), Q, pi,
                                              rates, w, 2000, rng)))
+    parent = synth.yule_topology(N122, rng)
+    pi = rng.dirichlet([2.0] * 240)
+    Q = synth.gtr_model(rng.gamma(1.0, 1.0, 240 * 239 // 2), pi)
+    cases.append(("s240", synth.make_problem(parent, synth.exponential_branch_lengths(N122, 0.05, rng), Q, pi,
+                                             rates, w, 1000, rng)))
     for name, prob in cases:
         N, C, S, R = prob.n_tips, prob.n_patterns, prob.n_states, prob.n_categories
         post_f, pre_f = matvec_flops(prob.parent, N, C, R, S)
@@ -382,7 +389,7 @@ def main():
     ap.add_argument("--serving-pool", type=int, default=12,
                     help="distinct synthetic trees the stream draws from")
     ap.add_argument("--no-serving", action="store_true")
-    ap.add_argument("--no-states", action="store_true", help="skip the 20/61/122-state measurements")
+    ap.add_argument("--no-states", action="store_true", help="skip the 20/61/122/240-state measurements")
     ap.add_argument("--state-steps", type=int, default=10)
     ap.add_argument("--batched-chains", type=int, default=8)
     ap.add_argument("--batched-seconds", type=float, default=3.0)
@@ -525,7 +532,7 @@ def main():
     batched = None
     states = None
     if not args.no_states:
-        print("[bench] 20-, 61- and 122-state workloads", file=sys.stderr, flush=True)
+        print("[bench] 20-, 61-, 122- and 240-state workloads", file=sys.stderr, flush=True)
         states = state_space_measurement(args, B, synth, stream, out)
     if not args.no_serving:
         print("[bench] batched FP32 chains vs plain FP64", file=sys.stderr, flush=True)
