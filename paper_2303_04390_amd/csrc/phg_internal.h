@@ -174,9 +174,8 @@ __host__ __device__ constexpr inline int gl_mat_rows(int S) {
 }
 // Row blocks of 16 patterns per tile: two (each matrix operand then feeds two
 // MFMAs) for FP32 above 32 states and FP64 at 65..128, one otherwise.
-// Measured: above 64 states two win even at one wave per SIMD (and, above
-// 192 states FP32, with a small register spill); four at 33..64 states
-// (FP32), two at 33..64 (FP64) and two at 17..32 (FP32) lose.
+// Measured: above 64 states two win even at one wave per SIMD; four at
+// 33..64 states (FP32), two at 33..64 (FP64) and two at 17..32 (FP32) lose.
 inline int gl_row_blocks(int S, bool fp32) {
     if (S <= 32) return 1;
     if (S > 128) return fp32 ? 2 : 1;

@@ -151,10 +151,10 @@ struct Input {
 
 // k-steps whose operands are loaded together before their MFMAs run (one
 // memory round trip per chunk instead of one per step): 8, or 4 for f64 with
-// three or more column blocks per wave (registers).
+// three or more column blocks per wave and for four (registers).
 template <typename T, int NBW>
 constexpr int chunk_of() {
-    return (sizeof(T) == 8 && NBW >= 3) ? 4 : 8;
+    return ((sizeof(T) == 8 && NBW >= 3) || NBW >= 4) ? 4 : 8;
 }
 
 // Operand geometry shared by the products of one kernel.
