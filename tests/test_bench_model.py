@@ -62,3 +62,14 @@ def test_headline_figures():
     post, pre = bench.algorithmic_bytes_blocked(prob.parent, 1000, 10000, 4, 4, 4)
     assert abs(post / 1e6 - 466) < 1 and abs(pre / 1e6 - 683) < 1
     assert abs(pre / 8 - 85323686) < 1e-6 * pre   # the per-launch figure bench reports
+
+
+def test_bench_refuses_more_than_one_gpu():
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and r.stdout == ""
