@@ -8,7 +8,7 @@
 //   backward  q[c][t] = sum_s u[c][s] P[s][t]      (q_x = P_x^T u_x)
 // One workgroup of W waves takes one (node, pattern tile); wave w owns the
 // output states [w * 16 NBW, (w + 1) * 16 NBW) of every product (NBW column
-// blocks of 16; W = ceil(S / 16) waves of one block up to 64 states, four
+// blocks of 16; W = ceil(S / 16) waves of one block up to 128 states, four
 // waves above), and runs the full sum over input states itself:
 // matrices come from HBM/L2; the input vectors of a category (stored partials
 // of the children, q of the parent) are staged once per workgroup in LDS by
@@ -967,10 +967,11 @@ __global__ __launch_bounds__(256) void pmat_gl_kernel(const ReqDesc* __restrict_
 template <typename T>
 hipError_t launch_gl_t(KernelClass k, int S, const ReqDesc* descs, const SegTable& t, hipStream_t st) {
     const int n_units = t.unit_begin[t.n];
-    // up to 64 states: one 16-state block per wave, ceil(S / 16) waves; above:
-    // four waves of ceil(S / 64) blocks
-    const int nbw = S > 64 ? (S + 63) / 64 : 1;
-    const int w = S > 64 ? 4 : (S + 15) / 16;
+    // up to 128 states: one 16-state block per wave, ceil(S / 16) waves (at
+    // 65..128 eight waves of one block beat four of two: fewer registers and
+    // matrix loads per wave); above: four waves of ceil(S / 64) blocks
+    const int nbw = S > 128 ? (S + 63) / 64 : 1;
+    const int w = S > 128 ? 4 : (S + 15) / 16;
     const int rb = gl_row_blocks(S, sizeof(T) == 4);
 #define PHG_GL_CASE(RBV, NBV, WV)                                                                           \
     if (rb == RBV && nbw == NBV && w == WV) {                                                             \
@@ -988,7 +989,10 @@ hipError_t launch_gl_t(KernelClass k, int S, const ReqDesc* descs, const SegTabl
         PHG_GL_CASE(2, 3, 4)
         PHG_GL_CASE(2, 4, 4)
     }
-    PHG_GL_CASE(2, 2, 4)
+    PHG_GL_CASE(2, 1, 5)
+    PHG_GL_CASE(2, 1, 6)
+    PHG_GL_CASE(2, 1, 7)
+    PHG_GL_CASE(2, 1, 8)
     PHG_GL_CASE(1, 1, 2)
     PHG_GL_CASE(1, 1, 3)
     PHG_GL_CASE(1, 1, 4)
