@@ -969,9 +969,12 @@ hipError_t launch_gl_t(KernelClass k, int S, const ReqDesc* descs, const SegTabl
     const int n_units = t.unit_begin[t.n];
     // up to 128 states: one 16-state block per wave, ceil(S / 16) waves (at
     // 65..128 eight waves of one block beat four of two: fewer registers and
-    // matrix loads per wave); above: four waves of ceil(S / 64) blocks
-    const int nbw = S > 128 ? (S + 63) / 64 : 1;
-    const int w = S > 128 ? 4 : (S + 15) / 16;
+    // matrix loads per wave).  Above: FP32 four waves of ceil(S / 64) blocks
+    // (two row blocks), FP64 ceil(S / 32) waves of two blocks (one row
+    // block).  Rows read, 16 NBW W, stay within the table's rows.
+    const bool f32 = sizeof(T) == 4;
+    const int nbw = S <= 128 ? 1 : (f32 ? (S + 63) / 64 : 2);
+    const int w = S <= 128 ? (S + 15) / 16 : (f32 ? 4 : (S + 31) / 32);
     const int rb = gl_row_blocks(S, sizeof(T) == 4);
 #define PHG_GL_CASE(RBV, NBV, WV)                                                                           \
     if (rb == RBV && nbw == NBV && w == WV) {                                                             \
@@ -988,6 +991,11 @@ hipError_t launch_gl_t(KernelClass k, int S, const ReqDesc* descs, const SegTabl
         PHG_GL_CASE(2, 1, 4)
         PHG_GL_CASE(2, 3, 4)
         PHG_GL_CASE(2, 4, 4)
+    } else {
+        PHG_GL_CASE(1, 2, 5)
+        PHG_GL_CASE(1, 2, 6)
+        PHG_GL_CASE(1, 2, 7)
+        PHG_GL_CASE(1, 2, 8)
     }
     PHG_GL_CASE(2, 1, 5)
     PHG_GL_CASE(2, 1, 6)
@@ -996,8 +1004,6 @@ hipError_t launch_gl_t(KernelClass k, int S, const ReqDesc* descs, const SegTabl
     PHG_GL_CASE(1, 1, 2)
     PHG_GL_CASE(1, 1, 3)
     PHG_GL_CASE(1, 1, 4)
-    PHG_GL_CASE(1, 3, 4)
-    PHG_GL_CASE(1, 4, 4)
 #undef PHG_GL_CASE
     return hipErrorInvalidValue;
 }
