@@ -896,20 +896,29 @@ __global__ __launch_bounds__(64 * W, (W == 2 && sizeof(T) == 4) ? 4 : 1) void pr
 
 // ---------------------------------------------------------------- P(t) tables
 
-// One workgroup per (branch, category) pair: P = V diag(exp(g lam b)) V^-1 and
-// dP = V diag(g lam exp(g lam b)) V^-1 (FP64 sums, stored in the path's
-// type), written as the forward tables of P and dP and the backward table of
-// P, zeros included.  A thread takes a 4 x 4 block of (s, t), so each V and
-// V^-1 value it loads feeds four products.
+// P = V diag(exp(g lam b)) V^-1 and dP = V diag(g lam exp(g lam b)) V^-1 for
+// one (branch, category) pair (blockIdx.x) and one 64 x 64 tile of (s, t)
+// (blockIdx.y), FP64 sums stored in the path's type, written as the forward
+// tables of P and dP and the backward table of P, zeros included.  V's
+// columns and V^-1's rows pass through LDS in chunks of 16 k, V^-1 already
+// scaled by exp and its derivative; a thread accumulates a 4 x 4 block.
+constexpr int kPmTile = 64, kPmK = 16;
+
+__host__ __device__ inline int pmat_gl_tiles(int S) { return (gl_mat_rows(S) + kPmTile - 1) / kPmTile; }
+
 template <typename T>
 __global__ __launch_bounds__(256) void pmat_gl_kernel(const ReqDesc* __restrict__ descs, const SegTable segs) {
     __shared__ double ex[256], dex[256];
+    __shared__ __align__(16) double As[kPmK][kPmTile], Be[kPmK][kPmTile], Bd[kPmK][kPmTile];
     const int unit = blockIdx.x;
     if (unit >= segs.unit_begin[segs.n]) return;
     const int sidx = seg_of(segs, unit);
     const ReqDesc& d = descs[segs.seg[sidx].desc];
     const int pair = unit - segs.unit_begin[sidx];
     const int R = d.R, S = d.S;
+    const int nt = pmat_gl_tiles(S);
+    if (static_cast<int>(blockIdx.y) >= nt * nt) return;  // whole workgroup: smaller S in a shared launch
+    const int ts = blockIdx.y / nt, tt = blockIdx.y - ts * nt;
     const int x = pair / R;
     const int r = pair - x * R;
     const double gr = d.rates[r];
@@ -917,51 +926,71 @@ __global__ __launch_bounds__(256) void pmat_gl_kernel(const ReqDesc* __restrict_
     const double* lam = d.lam + (d.eig_cat ? r * S : 0);
     const double* V = d.V + (d.eig_cat ? static_cast<size_t>(r) * S * S : 0);
     const double* Vinv = d.Vinv + (d.eig_cat ? static_cast<size_t>(r) * S * S : 0);
-    for (int k = threadIdx.x; k < S; k += blockDim.x) {
+    const int tid = threadIdx.x;
+    for (int k = tid; k < S; k += blockDim.x) {
         const double e = exp(lam[k] * bt);
         ex[k] = e;
         dex[k] = gr * lam[k] * e;
     }
-    __syncthreads();
+    const int bs = tid / 16, bq = tid % 16;
+    const int s_base = ts * kPmTile, t_base = tt * kPmTile;
+    const int s0 = s_base + bs * 4, t0 = t_base + bq * 4;
+    double acc[4][4] = {}, dacc[4][4] = {};
+    for (int k0 = 0; k0 < S; k0 += kPmK) {
+        __syncthreads();  // ex ready (first chunk); previous chunk consumed
+#pragma unroll
+        for (int m = 0; m < kPmK * kPmTile / 256; ++m) {
+            const int idx = tid + 256 * m;
+            const int kk = idx % kPmK, si = idx / kPmK;  // V: k contiguous in a row
+            const int sv = s_base + si, kv = k0 + kk;
+            As[kk][si] = (sv < S && kv < S) ? V[static_cast<size_t>(sv) * S + kv] : 0.0;
+            const int ti = idx % kPmTile, kb = idx / kPmTile;  // V^-1: t contiguous in a row
+            const int tv = t_base + ti, kw = k0 + kb;
+            double vb = 0.0, e = 0.0, de = 0.0;
+            if (tv < S && kw < S) {
+                vb = Vinv[static_cast<size_t>(kw) * S + tv];
+                e = ex[kw];
+                de = dex[kw];
+            }
+            Be[kb][ti] = vb * e;
+            Bd[kb][ti] = vb * de;
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int kk = 0; kk < kPmK; ++kk) {
+            double vs[4], ve[4], vd[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                vs[i] = As[kk][bs * 4 + i];
+                ve[i] = Be[kk][bq * 4 + i];
+                vd[i] = Bd[kk][bq * 4 + i];
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    acc[i][j] += vs[i] * ve[j];
+                    dacc[i][j] += vs[i] * vd[j];
+                }
+        }
+    }
     const int rows = gl_mat_rows(S), row = gl_row(S), kbp = gl_kbp(S);
+    if (s0 >= rows || t0 >= rows) return;  // after the last barrier
     const size_t base = static_cast<size_t>(pair) * rows * row;
     GLOBAL T* PF = g(tabP<T>(d)) + base;
     GLOBAL T* dPF = g(tabdP<T>(d)) + base;
     GLOBAL T* PB = g(tabPB<T>(d)) + base;
-    const int nb = rows / 4;
-    for (int blk = threadIdx.x; blk < nb * nb; blk += blockDim.x) {
-        const int s0 = (blk / nb) * 4, t0 = (blk % nb) * 4;
-        double acc[4][4] = {}, dacc[4][4] = {};
-        if (s0 < S && t0 < S) {
-            for (int k = 0; k < S; ++k) {
-                double vs[4], vt[4];
 #pragma unroll
-                for (int i = 0; i < 4; ++i) vs[i] = s0 + i < S ? V[(s0 + i) * S + k] : 0.0;
+    for (int i = 0; i < 4; ++i)
 #pragma unroll
-                for (int j = 0; j < 4; ++j) vt[j] = t0 + j < S ? Vinv[k * S + t0 + j] : 0.0;
-                const double e = ex[k], de = dex[k];
-#pragma unroll
-                for (int i = 0; i < 4; ++i)
-#pragma unroll
-                    for (int j = 0; j < 4; ++j) {
-                        const double v = vs[i] * vt[j];
-                        acc[i][j] += v * e;
-                        dacc[i][j] += v * de;
-                    }
+        for (int j = 0; j < 4; ++j) {
+            const int sr = s0 + i, tc = t0 + j;
+            if (tc < row) {
+                PF[static_cast<size_t>(sr) * row + gl_col(tc, kbp)] = static_cast<T>(acc[i][j]);
+                dPF[static_cast<size_t>(sr) * row + gl_col(tc, kbp)] = static_cast<T>(dacc[i][j]);
             }
+            if (sr < row) PB[static_cast<size_t>(tc) * row + gl_col(sr, kbp)] = static_cast<T>(acc[i][j]);
         }
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int sr = s0 + i, tc = t0 + j;
-                if (tc < row) {
-                    PF[static_cast<size_t>(sr) * row + gl_col(tc, kbp)] = static_cast<T>(acc[i][j]);
-                    dPF[static_cast<size_t>(sr) * row + gl_col(tc, kbp)] = static_cast<T>(dacc[i][j]);
-                }
-                if (sr < row) PB[static_cast<size_t>(tc) * row + gl_col(sr, kbp)] = static_cast<T>(acc[i][j]);
-            }
-    }
 }
 
 template <typename T>
@@ -1011,11 +1040,12 @@ hipError_t launch_gl_t(KernelClass k, int S, const ReqDesc* descs, const SegTabl
 }  // namespace
 
 hipError_t launch_pmat_gl(const ReqDesc& shape, const ReqDesc* descs, const SegTable& t, hipStream_t st) {
-    const int n_units = t.unit_begin[t.n];
+    // every request of one launch has shape.S's tile count or fewer
+    const int n_units = t.unit_begin[t.n], nt = pmat_gl_tiles(shape.S);
     if (shape.fp32)
-        hipLaunchKernelGGL(pmat_gl_kernel<float>, dim3(n_units), dim3(256), 0, st, descs, t);
+        hipLaunchKernelGGL(pmat_gl_kernel<float>, dim3(n_units, nt * nt), dim3(256), 0, st, descs, t);
     else
-        hipLaunchKernelGGL(pmat_gl_kernel<double>, dim3(n_units), dim3(256), 0, st, descs, t);
+        hipLaunchKernelGGL(pmat_gl_kernel<double>, dim3(n_units, nt * nt), dim3(256), 0, st, descs, t);
     return hipGetLastError();
 }
 

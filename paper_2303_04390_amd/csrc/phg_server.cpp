@@ -317,9 +317,9 @@ bool launch_step(phg_server* s) {
         if (st == 0) {
             // one P(t) kernel per launch: the 4-state one, the generic one
             // (S <= 16) or the operand-order one of the MFMA kernels, which is
-            // typed by precision
+            // typed by precision and launched over a grid of output tiles
             const int kind = d.S == 4 ? 0 : (uses_gl_kernels(d.S, d.R) ? 1 : 2);
-            key = GroupKey{kPmat, kind, kind == 1 ? d.fp32 : 0, 0};
+            key = GroupKey{kPmat, kind, kind == 1 ? d.fp32 : 0, kind == 1 ? (gl_mat_rows(d.S) + 63) / 64 : 0};
             it.units = units_for(kPmat, d, 0);
         } else if (st <= t->H) {
             const int l = st - 1, a = c->post_lv[l].first, n = c->post_lv[l].second;
