@@ -19,8 +19,20 @@ pytestmark = pytest.mark.gpu
 GiB = 1 << 30
 
 
+def states122_problem(seed, N=12, C=150):
+    rng = np.random.default_rng(seed)
+    pi = rng.dirichlet([2.0] * 122)
+    Q = synth.gtr_model(rng.gamma(1.0, 1.0, 122 * 121 // 2), pi)
+    rates, w = synth.discrete_gamma(0.5, 4)
+    return synth.make_problem(synth.yule_topology(N, rng), synth.exponential_branch_lengths(N, 0.05, rng), Q,
+                              pi, rates, w, C, rng)
+
+
 def trees_mix(seed=0):
-    """Trees of uneven taxon and pattern counts, 4 and 20 states, both precisions."""
+    """Trees of uneven taxon and pattern counts, 4, 20, 61 and 122 states,
+    both precisions.  The 122-state trees' P(t) tables span 2 x 2 output
+    tiles of the P(t) kernel and the 20- and 61-state ones a single tile, so
+    their P(t) work must not share a launch."""
     out = []
     for k, (N, C) in enumerate([(64, 500), (300, 2000), (1000, 3000), (20, 7000), (500, 1200)]):
         out.append((synth.config_problem("hky1000", seed=seed + k, n_tips=N, n_patterns=C),
@@ -28,6 +40,8 @@ def trees_mix(seed=0):
     out.append((synth.config_problem("hky1000", seed=seed + 9, n_tips=200, n_patterns=900), B.PHG_FP64))
     out.append((synth.config_problem("aa500", seed=seed + 3, n_tips=60, n_patterns=400), B.PHG_FP32_SCALED))
     out.append((synth.config_problem("codon128", seed=seed + 4, n_tips=24, n_patterns=300), B.PHG_FP64))
+    out.append((states122_problem(seed + 5), B.PHG_FP32_SCALED))
+    out.append((states122_problem(seed + 6, N=9, C=70), B.PHG_FP64))
     return out
 
 
