@@ -14,7 +14,7 @@
  *   - Every non-root node x owns the branch to its parent; branch lengths and
  *     gradients are arrays of length 2N-2 indexed by child node x.
  *   - An unrooted tree is a rooted one with one root branch of length zero.
- *   - S states (2..64), R rate categories (1..16), C site patterns (>= 1).
+ *   - S states (2..255), R rate categories (1..64), C site patterns (>= 1).
  *
  * General rules for every call:
  *   - Every call returns a phg_status; PHG_OK (0) on success, a negative code
@@ -53,7 +53,10 @@ typedef enum {
     PHG_FP32_SCALED = 1    /* partials and P(t) copies in float32 with per-node,
                               per-pattern power-of-two rescaling shared across
                               categories; P(t) built in float64; per-pattern
-                              ratios and all reductions in float64 */
+                              ratios and all reductions in float64.  Subject
+                              to the FP32 precision guard (phg_set_fp32_guard):
+                              a tree too saturated for float32 partials is
+                              evaluated in FP64 */
 } phg_precision;
 
 typedef struct phg_context phg_context;
@@ -154,6 +157,7 @@ phg_status phg_get_schedule(phg_context *ctx, int *schedule);
 phg_status phg_prepare(phg_context *ctx);
 
 /* log P(Y) = sum_c W_c log sum_r P(gamma_r) p_root,r,c . pi.  Synchronous.
+ * Runs P(t), the post-order pass and the final sum only (no pre-order pass).
  * PHG_ERR_STATE until topology, branch lengths, eigensystem, root
  * frequencies, categories and tip states are all set.  If a weighted site
  * likelihood is zero or not finite, *logl = -inf and PHG_ERR_NUMERIC. */
@@ -163,6 +167,36 @@ phg_status phg_log_likelihood(phg_context *ctx, double *logl);
  * 2N-2 branches (eq:gradient summed by eq:gradientSumAcrossColumns).
  * Synchronous.  On PHG_ERR_NUMERIC, *logl = -inf and grad is all NaN. */
 phg_status phg_gradient(phg_context *ctx, double *logl, double *grad);
+
+/* ---- FP32 precision guard ----
+ *
+ * Float32 partials carry a gradient component to ~1e-4 of itself only while
+ * the pre-order vector reaching a branch and its sibling's vector keep some
+ * distance from the stationary and the flat vector.  Where both neighbours
+ * of a branch are long, the component becomes a small difference of nearly
+ * equal terms (rows of dP sum to zero, eq:gradient) and a single float32
+ * rounding of the stored partials moves it by more than that.  The guard
+ * measures this on the host before every evaluation of an FP32 context:
+ *   saturation = max over internal nodes k and children x' of k of
+ *                min(L_k, L_x'),   L_v = b_v * max_r(gamma_r * mu_r),
+ * mu_r the smallest non-zero |lambda| of category r's generator (the slowest
+ * decay of the fastest category), L_root = infinity.  Above the threshold
+ * the evaluation runs on an FP64 twin of the context (same inputs, its own
+ * device memory, same stream), so results keep the FP64 bar.  The default
+ * threshold is 1.5.  Contexts with a bound workspace never route (they
+ * allocate nothing of their own); the serving engine does not route. */
+
+/* threshold >= 0; 0 disables the guard.  Applies to FP32 contexts only. */
+phg_status phg_set_fp32_guard(phg_context *ctx, double threshold);
+
+/* The guard's saturation statistic for the current inputs (host only).
+ * PHG_ERR_STATE before topology, branch lengths, eigensystem and categories
+ * are set. */
+phg_status phg_fp32_saturation(phg_context *ctx, double *saturation);
+
+/* Precision the last evaluation ran in (PHG_FP64 or PHG_FP32_SCALED), or -1
+ * before the first. */
+phg_status phg_last_precision(phg_context *ctx, int *prec);
 
 /* ---- parameter chain rules: node heights, branch rates, branch sets ----
  *

@@ -88,6 +88,9 @@ _SIGS = {
     "phg_server_stats": [_vp, _c.POINTER(_c.c_uint64)],
     "phg_profile_enable": [_vp, _c.c_int],
     "phg_profile_read": [_vp, _dp, _c.POINTER(_c.c_int), _c.POINTER(_c.c_int)],
+    "phg_set_fp32_guard": [_vp, _c.c_double],
+    "phg_fp32_saturation": [_vp, _dp],
+    "phg_last_precision": [_vp, _c.POINTER(_c.c_int)],
 }
 
 PHG_PROF_CLASSES = 4
@@ -318,6 +321,22 @@ def phg_profile_read(ctx):
     return ms, n.value, launches
 
 
+def phg_set_fp32_guard(ctx, threshold: float):
+    _check(lib().phg_set_fp32_guard(ctx, float(threshold)), ctx, "phg_set_fp32_guard")
+
+
+def phg_fp32_saturation(ctx) -> float:
+    v = ctypes.c_double()
+    _check(lib().phg_fp32_saturation(ctx, ctypes.byref(v)), ctx, "phg_fp32_saturation")
+    return v.value
+
+
+def phg_last_precision(ctx) -> int:
+    v = ctypes.c_int()
+    _check(lib().phg_last_precision(ctx, ctypes.byref(v)), ctx, "phg_last_precision")
+    return v.value
+
+
 # ------------------------------------------------------------ serving
 
 class phg_tree_desc(ctypes.Structure):
@@ -435,6 +454,7 @@ class Context:
     def __init__(self, n_tips, n_patterns, n_states, n_categories, prec=PHG_FP32_SCALED, device=0):
         self.n_tips = n_tips
         self.n_branches = 2 * n_tips - 2
+        self.prec = prec
         self.handle = phg_create(n_tips, n_patterns, n_states, n_categories, prec, device)
 
     @classmethod

@@ -36,21 +36,32 @@ ChainArgs chain_args(phg_context* ctx) {
     return c;
 }
 
-// One evaluation followed by the chain kernels; the whole output region is
-// copied back into the pinned mirror.  Numeric failure as phg_gradient.
-phg_status eval_with_chain(phg_context* ctx, bool time_tree) {
-    PHG_TRY(ctx_ready(ctx));
-    PHG_TRY(ctx_host_out(ctx));
-    double* dout = ctx_out_dev(ctx);
-    PHG_TRY(ctx_enqueue_eval(ctx, dout, dout + 1));
-    PHG_HIP(ctx, launch_chain(chain_args(ctx), time_tree, ctx->stream));
-    PHG_HIP(ctx, hipMemcpyAsync(ctx->host_out, dout, out_doubles(ctx->N) * sizeof(double),
-                                hipMemcpyDeviceToHost, ctx->stream));
-    PHG_HIP(ctx, hipStreamSynchronize(ctx->stream));
-    const double ll = ctx->host_out[0];
+// One evaluation followed by the chain kernels on t (the context or its FP64
+// twin); the whole output region is copied back into t's pinned mirror.
+// Numeric failure as phg_gradient.
+phg_status eval_chain_on(phg_context* t, bool time_tree) {
+    PHG_TRY(ctx_ready(t));
+    PHG_TRY(ctx_host_out(t));
+    double* dout = ctx_out_dev(t);
+    PHG_TRY(ctx_enqueue_eval(t, dout, dout + 1));
+    PHG_HIP(t, launch_chain(chain_args(t), time_tree, t->stream));
+    PHG_HIP(t, hipMemcpyAsync(t->host_out, dout, out_doubles(t->N) * sizeof(double),
+                              hipMemcpyDeviceToHost, t->stream));
+    PHG_HIP(t, hipStreamSynchronize(t->stream));
+    const double ll = t->host_out[0];
     if (!std::isfinite(ll))
-        return ctx->fail(PHG_ERR_NUMERIC, "a weighted site likelihood is zero or not finite");
+        return t->fail(PHG_ERR_NUMERIC, "a weighted site likelihood is zero or not finite");
     return PHG_OK;
+}
+
+// *host receives the pinned mirror that holds the results.
+phg_status eval_with_chain(phg_context* ctx, bool time_tree, const double** host) {
+    phg_status s;
+    phg_context* t = eval_target(ctx, &s);
+    if (!t) return s;
+    s = from_twin(ctx, t, eval_chain_on(t, time_tree));
+    *host = t->host_out;
+    return s;
 }
 
 void fill_nan(double* p, size_t n) {
@@ -85,6 +96,7 @@ phg_status phg_set_time_tree(phg_context* ctx, const double* heights, const doub
     ctx->trates.assign(rates, rates + n - 1);
     ctx->have |= kB | kTime;
     ctx->dirty |= kB | kTime;
+    ctx->sdirty |= kB | kTime;
     return PHG_OK;
 }
 
@@ -115,6 +127,7 @@ phg_status phg_set_branch_sets(phg_context* ctx, const int32_t* set_of, int n_se
     ctx->n_sets = n_sets;
     ctx->have |= kSets;
     ctx->dirty |= kSets;
+    ctx->sdirty |= kSets;
     return PHG_OK;
 }
 
@@ -126,7 +139,8 @@ phg_status phg_time_tree_gradient(phg_context* ctx, double* logl, double* d_heig
     const int n_sets = d_sets ? ctx->n_sets : 0;
     const int saved = ctx->n_sets;
     ctx->n_sets = n_sets;     // skip the set kernel when its result is not wanted
-    const phg_status s = eval_with_chain(ctx, true);
+    const double* h = nullptr;
+    const phg_status s = eval_with_chain(ctx, true, &h);
     ctx->n_sets = saved;
     const size_t E = 2 * static_cast<size_t>(ctx->N) - 2;
     if (s != PHG_OK) {
@@ -138,7 +152,6 @@ phg_status phg_time_tree_gradient(phg_context* ctx, double* logl, double* d_heig
         }
         return s;
     }
-    const double* h = ctx->host_out;
     if (logl) *logl = h[0];
     if (d_heights) std::memcpy(d_heights, h + 1 + E, (E + 1) * sizeof(double));
     if (d_rates) std::memcpy(d_rates, h + 1 + E + (E + 1), E * sizeof(double));
@@ -150,7 +163,8 @@ phg_status phg_gradient_branch_sets(phg_context* ctx, double* logl, double* d_se
     if (!ctx) return PHG_ERR_ARG;
     if (!d_sets) return ctx->fail(PHG_ERR_ARG, "d_sets is NULL");
     if (!(ctx->have & kSets)) return ctx->fail(PHG_ERR_STATE, "no branch sets set (phg_set_branch_sets)");
-    const phg_status s = eval_with_chain(ctx, false);
+    const double* h = nullptr;
+    const phg_status s = eval_with_chain(ctx, false, &h);
     const size_t E = 2 * static_cast<size_t>(ctx->N) - 2;
     if (s != PHG_OK) {
         if (s == PHG_ERR_NUMERIC) {
@@ -159,8 +173,8 @@ phg_status phg_gradient_branch_sets(phg_context* ctx, double* logl, double* d_se
         }
         return s;
     }
-    if (logl) *logl = ctx->host_out[0];
-    std::memcpy(d_sets, ctx->host_out + 1 + E + (E + 1) + E, ctx->n_sets * sizeof(double));
+    if (logl) *logl = h[0];
+    std::memcpy(d_sets, h + 1 + E + (E + 1) + E, ctx->n_sets * sizeof(double));
     return PHG_OK;
 }
 

@@ -74,6 +74,14 @@ struct phg_context {
     int32_t* d_tslot = nullptr;
     unsigned have = 0;           // inputs set at least once
     unsigned dirty = 0;          // inputs changed since the last upload
+    unsigned sdirty = 0;         // inputs changed since the FP64 twin was last synchronised
+
+    // FP32 precision guard: an FP32 context whose tree is more saturated
+    // than fp32_guard (phg::fp32_saturation) evaluates on an FP64 twin
+    // context holding copies of the same inputs; fp32_guard <= 0 disables.
+    double fp32_guard = phg::kDefaultFp32Guard;
+    phg_context* twin = nullptr;
+    int last_prec = -1;          // precision of the last evaluation issued (-1: none)
 
     // schedule (host copy; uploaded to the sched region): NodeTriple records
     // (level schedule) or BlockRec records (blocked schedule), as raw words
@@ -137,6 +145,15 @@ double* ctx_out_dev(phg_context* ctx);
 phg_status ctx_host_out(phg_context* ctx);
 // Enqueue one whole evaluation of this context alone.
 phg_status ctx_enqueue_eval(phg_context* ctx, double* d_logl, double* d_grad);
+// Saturation statistic of the FP32 precision guard for the context's current
+// tree, branch lengths, eigensystem and rates (host only).
+double fp32_saturation(const phg_context* ctx);
+// The context that evaluates ctx's next request: ctx itself, or its FP64 twin
+// (created and synchronised here) when the guard routes it.  Records the
+// precision in ctx->last_prec.  Sets *st and returns nullptr on failure.
+phg_context* eval_target(phg_context* ctx, phg_status* st);
+// Copy the twin's error message into ctx when a routed call failed.
+phg_status from_twin(phg_context* ctx, phg_context* t, phg_status s);
 // Forget the device binding (workspace, pinned output) so the context can be
 // bound to new memory later; every input is uploaded again on next use.  The
 // caller guarantees no device work of this context is pending.

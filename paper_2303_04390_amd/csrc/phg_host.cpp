@@ -509,13 +509,18 @@ phg_status ctx_enqueue_eval(phg_context* ctx, double* d_logl, double* d_grad) {
                                   one_segment(d, units_for(kPost, d, n), a, n, h == H - 1 ? 1 : 0, nullptr, nullptr), st));
     }
     PHG_TRY(prof_mark(ctx));
-    for (const auto& lv : ctx->pre_lv) {
-        const int a = lv.first, n = lv.second;
-        PHG_HIP(ctx, launch_class(kPre, d, descs, one_segment(d, units_for(kPre, d, n), a, n, 0, nullptr, nullptr), st));
+    if (d_grad) {
+        for (const auto& lv : ctx->pre_lv) {
+            const int a = lv.first, n = lv.second;
+            PHG_HIP(ctx, launch_class(kPre, d, descs, one_segment(d, units_for(kPre, d, n), a, n, 0, nullptr, nullptr), st));
+        }
     }
     PHG_TRY(prof_mark(ctx));
+    // without d_grad: log-likelihood only (no pre-order pass; one final unit)
     PHG_HIP(ctx, launch_class(kFinal, d, descs,
-                              one_segment(d, units_for(kFinal, d, 0), 0, 0, 0, d_logl, d_grad), st));
+                              d_grad ? one_segment(d, units_for(kFinal, d, 0), 0, 0, 0, d_logl, d_grad)
+                                     : one_segment(d, 1, 0, 0, 1, d_logl, nullptr),
+                              st));
     PHG_TRY(prof_mark(ctx));
     return PHG_OK;
 }
@@ -559,6 +564,101 @@ phg_status ctx_ready(phg_context* ctx) {
     phg_status s = ensure_device(ctx);
     if (s != PHG_OK) return s;
     return upload(ctx);
+}
+
+double fp32_saturation(const phg_context* ctx) {
+    const int N = ctx->N, n = 2 * N - 1, root = n - 1, S = ctx->S, R = ctx->R;
+    // fastest category's slowest decay: max_r gamma_r * mu_r, mu_r the
+    // smallest |lambda| of category r once its zero eigenvalue is dropped
+    double rate = 0.0;
+    for (int r = 0; r < R; ++r) {
+        const double* lam = ctx->lam.data() + (ctx->eig_cat ? static_cast<size_t>(r) * S : 0);
+        int i0 = 0;
+        double big = 0.0;
+        for (int s = 0; s < S; ++s) {
+            big = std::max(big, std::fabs(lam[s]));
+            if (std::fabs(lam[s]) < std::fabs(lam[i0])) i0 = s;
+        }
+        const bool zero = std::fabs(lam[i0]) <= 1e-9 * big;
+        double mu = std::numeric_limits<double>::infinity();
+        for (int s = 0; s < S; ++s)
+            if (!(zero && s == i0)) mu = std::min(mu, std::fabs(lam[s]));
+        if (std::isfinite(mu)) rate = std::max(rate, ctx->rates[r] * mu);
+    }
+    auto L = [&](int v) { return v == root ? std::numeric_limits<double>::infinity() : ctx->b[v] * rate; };
+    double stat = 0.0;
+    for (int k = N; k < n; ++k) {
+        const double lk = L(k);
+        for (int j = 0; j < 2; ++j) stat = std::max(stat, std::min(lk, L(ctx->kids[2 * (k - N) + j])));
+    }
+    return stat;
+}
+
+phg_context* eval_target(phg_context* ctx, phg_status* st) {
+    *st = PHG_OK;
+    // a bound workspace means the caller owns every byte: never route then
+    const bool route = ctx->prec == PHG_FP32_SCALED && ctx->fp32_guard > 0.0 && !ctx->bound_ws &&
+                       (ctx->have & kRequired) == kRequired && fp32_saturation(ctx) > ctx->fp32_guard;
+    if (!route) {
+        ctx->last_prec = ctx->prec;
+        return ctx;
+    }
+    phg_context* t = ctx->twin;
+    if (!t) {
+        *st = phg_create(ctx->N, ctx->C, ctx->S, ctx->R, PHG_FP64, ctx->device, &t);
+        if (*st != PHG_OK) {
+            ctx->fail(*st, "creating the FP64 twin failed: %s", phg_last_error(nullptr));
+            return nullptr;
+        }
+        ctx->twin = t;
+        ctx->sdirty = ~0u;
+        if (ctx->stream && !ctx->own_stream) t->stream = ctx->stream;   // caller's stream
+    }
+    const unsigned sd = ctx->sdirty;
+    if (sd & (kTopo | kTipVec)) {
+        t->parent = ctx->parent;
+        t->tip_vectors = ctx->tip_vectors;
+        t->sched_mode = ctx->sched_mode;
+        if (ctx->have & kTopo) build_schedule(t);
+        t->dirty |= kTopo | kTipVec;
+    }
+    if (sd & kEig) {
+        t->V = ctx->V;
+        t->Vinv = ctx->Vinv;
+        t->lam = ctx->lam;
+        t->eig_cat = ctx->eig_cat;
+        t->rd.eig_cat = ctx->rd.eig_cat;
+        t->dirty |= kEig | kDesc;
+    }
+    if (sd & kTips) {
+        t->codes = ctx->codes;
+        t->dirty |= kTips;
+    }
+    if (sd & kPi) t->pi = ctx->pi;
+    if (sd & kCat) {
+        t->rates = ctx->rates;
+        t->cw = ctx->cw;
+    }
+    if (sd & kPw) t->pw = ctx->pw;
+    t->dirty |= sd & (kPi | kCat | kPw);
+    // small per-evaluation inputs: copied every time
+    t->b = ctx->b;
+    t->heights = ctx->heights;
+    t->trates = ctx->trates;
+    t->set_ptr = ctx->set_ptr;
+    t->set_idx = ctx->set_idx;
+    t->n_sets = ctx->n_sets;
+    t->dirty |= kB | kTime | kSets;
+    t->have = ctx->have;
+    t->prof_on = ctx->prof_on;
+    ctx->sdirty = 0;
+    ctx->last_prec = PHG_FP64;
+    return t;
+}
+
+phg_status from_twin(phg_context* ctx, phg_context* t, phg_status s) {
+    if (s != PHG_OK && t != ctx) ctx->err = t->err;
+    return s;
 }
 
 }  // namespace phg
@@ -607,6 +707,7 @@ phg_status phg_create(int n_tips, int n_patterns, int n_states, int n_categories
 
 phg_status phg_destroy(phg_context* ctx) {
     if (!ctx) return PHG_OK;
+    phg_destroy(ctx->twin);
     if (ctx->dev_init) {
         (void)hipSetDevice(ctx->device);
         if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
@@ -656,6 +757,7 @@ phg_status phg_set_topology(phg_context* ctx, const int32_t* parent) {
     build_schedule(ctx);
     ctx->have |= kTopo;
     ctx->dirty |= kTopo;
+    ctx->sdirty |= kTopo;
     ctx->have &= ~kTime;     // heights must be set again for a new topology
     return PHG_OK;
 }
@@ -670,6 +772,7 @@ phg_status phg_set_branch_lengths(phg_context* ctx, const double* b) {
     ctx->b.assign(b, b + E);
     ctx->have |= kB;
     ctx->dirty |= kB;
+    ctx->sdirty |= kB;
     ctx->have &= ~kTime;     // lengths no longer come from a time tree
     return PHG_OK;
 }
@@ -688,6 +791,7 @@ phg_status set_eig(phg_context* ctx, const double* V, const double* Vinv, const 
     ctx->rd.eig_cat = ctx->eig_cat ? 1 : 0;
     ctx->have |= kEig;
     ctx->dirty |= kEig | kDesc;
+    ctx->sdirty |= kEig | kDesc;
     return PHG_OK;
 }
 }  // namespace
@@ -710,6 +814,7 @@ phg_status phg_set_root_frequencies(phg_context* ctx, const double* pi) {
     ctx->pi.assign(pi, pi + ctx->S);
     ctx->have |= kPi;
     ctx->dirty |= kPi;
+    ctx->sdirty |= kPi;
     return PHG_OK;
 }
 
@@ -726,6 +831,7 @@ phg_status phg_set_categories(phg_context* ctx, const double* rates, const doubl
     ctx->cw.assign(weights, weights + ctx->R);
     ctx->have |= kCat;
     ctx->dirty |= kCat;
+    ctx->sdirty |= kCat;
     return PHG_OK;
 }
 
@@ -743,6 +849,7 @@ phg_status phg_set_tip_states(phg_context* ctx, const int32_t* codes) {
     }
     ctx->have |= kTips;
     ctx->dirty |= kTips;
+    ctx->sdirty |= kTips;
     return PHG_OK;
 }
 
@@ -766,9 +873,11 @@ phg_status phg_set_tip_partials(phg_context* ctx, int tip, const double* partial
     if (had_any != !ctx->tip_vectors.empty() && (ctx->have & kTopo)) {
         build_schedule(ctx);
         ctx->dirty |= kTopo;
+        ctx->sdirty |= kTopo;
     }
     ctx->have |= kTipVec;
     ctx->dirty |= kTipVec;
+    ctx->sdirty |= kTipVec;
     return PHG_OK;
 }
 
@@ -781,6 +890,7 @@ phg_status phg_set_pattern_weights(phg_context* ctx, const double* w) {
     std::copy(w, w + ctx->C, ctx->pw.begin());
     ctx->have |= kPw;
     ctx->dirty |= kPw;
+    ctx->sdirty |= kPw;
     return PHG_OK;
 }
 
@@ -790,51 +900,69 @@ phg_status phg_set_schedule(phg_context* ctx, phg_schedule mode) {
         return ctx->fail(PHG_ERR_ARG, "unknown schedule %d", static_cast<int>(mode));
     if (mode == PHG_SCHEDULE_BLOCKS &&
         !phg::blocked_supported(ctx->S, ctx->R, ctx->prec == PHG_FP32_SCALED))
-        return ctx->fail(PHG_ERR_ARG, "the blocked schedule needs 4 states and R <= 8 (FP32) or R <= 4 (FP64)");
+        return ctx->fail(PHG_ERR_ARG, "the blocked schedule needs 4 states and R <= 8");
     if (mode == PHG_SCHEDULE_BLOCKS && !ctx->tip_vectors.empty())
         return ctx->fail(PHG_ERR_ARG, "the blocked schedule does not take general tip partials");
     ctx->sched_mode = mode;
     if (ctx->have & kTopo) {
         build_schedule(ctx);
         ctx->dirty |= kTopo;
+        ctx->sdirty |= kTopo;
     }
     return PHG_OK;
 }
 
 phg_status phg_prepare(phg_context* ctx) {
     if (!ctx) return PHG_ERR_ARG;
-    return ctx_ready(ctx);
+    phg_status s;
+    phg_context* t = eval_target(ctx, &s);
+    if (!t) return s;
+    return from_twin(ctx, t, ctx_ready(t));
 }
+
+namespace {
+// One synchronous evaluation on t (the context itself or its FP64 twin);
+// grad == nullptr asks for the log-likelihood only.
+phg_status eval_sync(phg_context* t, double* logl, double* grad) {
+    phg_status s = ctx_ready(t);
+    if (s != PHG_OK) return s;
+    PHG_TRY(ctx_host_out(t));
+    double* dout = ctx_out_dev(t);
+    s = ctx_enqueue_eval(t, dout, grad ? dout + 1 : nullptr);
+    if (s != PHG_OK) return s;
+    const size_t E = 2 * static_cast<size_t>(t->N) - 2;
+    PHG_HIP(t, hipMemcpyAsync(t->host_out, dout, (grad ? E + 1 : 1) * sizeof(double), hipMemcpyDeviceToHost,
+                              t->stream));
+    PHG_HIP(t, hipStreamSynchronize(t->stream));
+    const double ll = t->host_out[0];
+    if (!(ll > -std::numeric_limits<double>::infinity()) || !std::isfinite(ll)) {
+        if (logl) *logl = -std::numeric_limits<double>::infinity();
+        if (grad)
+            for (size_t x = 0; x < E; ++x) grad[x] = std::numeric_limits<double>::quiet_NaN();
+        return t->fail(PHG_ERR_NUMERIC, "a weighted site likelihood is zero or not finite");
+    }
+    if (logl) *logl = ll;
+    if (grad) std::memcpy(grad, t->host_out + 1, E * sizeof(double));
+    return PHG_OK;
+}
+}  // namespace
 
 phg_status phg_gradient(phg_context* ctx, double* logl, double* grad) {
     if (!ctx) return PHG_ERR_ARG;
     if (!grad) return ctx->fail(PHG_ERR_ARG, "grad is NULL");
-    phg_status s = ctx_ready(ctx);
-    if (s != PHG_OK) return s;
-    PHG_TRY(ctx_host_out(ctx));
-    double* dout = ctx_out_dev(ctx);
-    s = ctx_enqueue_eval(ctx, dout, dout + 1);
-    if (s != PHG_OK) return s;
-    const size_t E = 2 * static_cast<size_t>(ctx->N) - 2;
-    PHG_HIP(ctx, hipMemcpyAsync(ctx->host_out, dout, (E + 1) * sizeof(double), hipMemcpyDeviceToHost,
-                                ctx->stream));
-    PHG_HIP(ctx, hipStreamSynchronize(ctx->stream));
-    const double ll = ctx->host_out[0];
-    if (!(ll > -std::numeric_limits<double>::infinity()) || !std::isfinite(ll)) {
-        if (logl) *logl = -std::numeric_limits<double>::infinity();
-        for (size_t x = 0; x < E; ++x) grad[x] = std::numeric_limits<double>::quiet_NaN();
-        return ctx->fail(PHG_ERR_NUMERIC, "a weighted site likelihood is zero or not finite");
-    }
-    if (logl) *logl = ll;
-    std::memcpy(grad, ctx->host_out + 1, E * sizeof(double));
-    return PHG_OK;
+    phg_status s;
+    phg_context* t = eval_target(ctx, &s);
+    if (!t) return s;
+    return from_twin(ctx, t, eval_sync(t, logl, grad));
 }
 
 phg_status phg_log_likelihood(phg_context* ctx, double* logl) {
     if (!ctx) return PHG_ERR_ARG;
     if (!logl) return ctx->fail(PHG_ERR_ARG, "logl is NULL");
-    std::vector<double> g(2 * static_cast<size_t>(ctx->N) - 2);
-    return phg_gradient(ctx, logl, g.data());
+    phg_status s;
+    phg_context* t = eval_target(ctx, &s);
+    if (!t) return s;
+    return from_twin(ctx, t, eval_sync(t, logl, nullptr));
 }
 
 phg_status phg_workspace_size(int n_tips, int n_patterns, int n_states, int n_categories,
@@ -863,6 +991,7 @@ phg_status phg_bind_workspace(phg_context* ctx, void* device_ptr, size_t bytes) 
 
 phg_status phg_bind_stream(phg_context* ctx, void* hip_stream) {
     if (!ctx) return PHG_ERR_ARG;
+    if (ctx->twin) PHG_TRY(phg_bind_stream(ctx->twin, hip_stream));
     if (ctx->dev_init && ctx->own_stream && ctx->stream) {
         (void)hipSetDevice(ctx->device);
         (void)hipStreamSynchronize(ctx->stream);
@@ -881,9 +1010,34 @@ phg_status phg_bind_stream(phg_context* ctx, void* hip_stream) {
 phg_status phg_gradient_async(phg_context* ctx, double* d_logl, double* d_grad) {
     if (!ctx) return PHG_ERR_ARG;
     if (!d_logl || !d_grad) return ctx->fail(PHG_ERR_ARG, "NULL device output pointer");
-    phg_status s = ctx_ready(ctx);
-    if (s != PHG_OK) return s;
-    return ctx_enqueue_eval(ctx, d_logl, d_grad);
+    phg_status s;
+    phg_context* t = eval_target(ctx, &s);
+    if (!t) return s;
+    s = ctx_ready(t);
+    if (s == PHG_OK) s = ctx_enqueue_eval(t, d_logl, d_grad);
+    return from_twin(ctx, t, s);
+}
+
+phg_status phg_set_fp32_guard(phg_context* ctx, double threshold) {
+    if (!ctx) return PHG_ERR_ARG;
+    if (!(threshold >= 0.0)) return ctx->fail(PHG_ERR_ARG, "guard threshold %g must be >= 0", threshold);
+    ctx->fp32_guard = threshold;
+    return PHG_OK;
+}
+
+phg_status phg_fp32_saturation(phg_context* ctx, double* saturation) {
+    if (!ctx || !saturation) return PHG_ERR_ARG;
+    const unsigned need = kTopo | kB | kEig | kCat;
+    if ((ctx->have & need) != need)
+        return ctx->fail(PHG_ERR_STATE, "topology, branch lengths, eigensystem and categories must be set");
+    *saturation = fp32_saturation(ctx);
+    return PHG_OK;
+}
+
+phg_status phg_last_precision(phg_context* ctx, int* prec) {
+    if (!ctx || !prec) return PHG_ERR_ARG;
+    *prec = ctx->last_prec;
+    return PHG_OK;
 }
 
 phg_status phg_get_schedule(phg_context* ctx, int* schedule) {
@@ -926,9 +1080,16 @@ phg_status phg_profile_read(phg_context* ctx, double* ms, int* n_evals, int* lau
                 tot[k] += t;
             }
     }
+    // evaluations the precision guard routed to the FP64 twin
+    int n_twin = 0;
+    if (ctx->twin && ctx->twin->prof_used > 0) {
+        double tw[PHG_PROF_CLASSES];
+        PHG_TRY(from_twin(ctx, ctx->twin, phg_profile_read(ctx->twin, tw, &n_twin, nullptr)));
+        for (int k = 0; k < PHG_PROF_CLASSES; ++k) tot[k] += tw[k];
+    }
     if (ms)
         for (int k = 0; k < PHG_PROF_CLASSES; ++k) ms[k] = tot[k];
-    if (n_evals) *n_evals = static_cast<int>(n);
+    if (n_evals) *n_evals = static_cast<int>(n) + n_twin;
     if (launches) {
         launches[PHG_PROF_PMAT] = 1;
         launches[PHG_PROF_POST] = static_cast<int>(ctx->post_lv.size());

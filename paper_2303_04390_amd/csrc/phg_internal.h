@@ -135,6 +135,17 @@ constexpr int kBlockDepth = 3;
 // every in-block vector in registers.
 inline bool blocked_supported(int S, int R, bool /*fp32*/) { return S == 4 && R <= 8; }
 
+// Default threshold of the FP32 precision guard: an FP32 context evaluates in
+// FP64 when some internal node k has a child x' with min(L_k, L_x') above it,
+// where L_v = b_v * max_r(gamma_r * mu_r) is branch v's length in units of
+// the slowest decay of its fastest category (mu_r = smallest non-zero
+// |lambda| of category r's generator; the root branch counts as infinite).
+// There, nearly stationary pre-order vectors meet nearly flat sibling
+// vectors and a single float32 rounding of the stored partials already moves
+// some gradient components by ~1e-4 of themselves (measured in a float32
+// emulation of the recursion; 4-state trees first fail near 2.8).
+constexpr double kDefaultFp32Guard = 1.5;
+
 // Chain rules on a finished branch gradient (phg_chain.hip).  All pointers
 // are device pointers into the context's workspace.
 struct ChainArgs {

@@ -1413,8 +1413,10 @@ __global__ __launch_bounds__(256) void finalize_kernel(const ReqDesc* __restrict
     const int sidx = find_segment(segs, unit);
     const Segment& sg = segs.seg[sidx];
     const ReqDesc& d = descs[sg.desc];
-    const int blk = unit - segs.unit_begin[sidx];
     const int E = 2 * d.N - 2, tiles = d.tiles;
+    // flags 1: log-likelihood only (one unit; the gradient partials are not
+    // formed by a log-likelihood-only evaluation)
+    const int blk = (sg.flags & 1) ? E : unit - segs.unit_begin[sidx];
     const double* src = blk < E ? d.gpart + static_cast<size_t>(blk) * tiles : d.lpart;
     double acc = 0.0;
     for (int t = threadIdx.x; t < tiles; t += 256) acc += src[t];

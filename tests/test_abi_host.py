@@ -18,7 +18,7 @@ HEADER = os.path.join(os.path.dirname(os.path.dirname(__file__)), "include", "ph
 def declared_functions():
     txt = open(HEADER).read()
     txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
-    return sorted(set(re.findall(r"\b(phg_[a-z_]+)\s*\(", txt)))
+    return sorted(set(re.findall(r"\b(phg_[a-z0-9_]+)\s*\(", txt)))
 
 
 def test_library_exports_every_declared_symbol():

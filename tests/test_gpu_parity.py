@@ -127,17 +127,55 @@ def test_deep_caterpillar_needs_rescaling():
         compare("caterpillar1000-b0.1", prob, prec, ref)
 
 
-def test_saturated_branches_fp32_limit():
-    """Branches ~Exp(1) on a 1000-deep caterpillar: P(t) is close to
-    stationary, so the derivative of a long branch is a small difference of
-    FP32-rounded terms.  FP64 holds the full bar; the FP32 path keeps logL to
-    1e-6 but its gradient error grows to ~1e-3 of the component (measured),
-    so it is held to 1e-2 here."""
+@pytest.mark.fp32_routed
+def test_saturated_branches_fp32_guard():
+    """Branches ~Exp(1) on a 1000-deep caterpillar.  Nearly stationary
+    pre-order vectors meet nearly flat sibling vectors, and one float32
+    rounding of the stored partials already moves some derivatives by ~1e-4
+    of themselves, so no float32-partials arithmetic holds the bar here.  The
+    FP32 precision guard sees the saturation (statistic far above its 1.5
+    threshold) and evaluates in FP64: the FP32 request meets the FP32 bar."""
     prob = _caterpillar(1000, 96, 1.0, 11)
     ref = oracle.evaluate_problem(prob)
     compare("caterpillar1000-b1", prob, B.PHG_FP64, ref)
-    logl, grad = gpu_eval(prob, B.PHG_FP32_SCALED)
-    check("caterpillar1000-b1/fp32", logl, grad, ref, 1e-6, 1e-2)
+    print("[case] caterpillar1000-b1 fp32 guarded", flush=True)
+    with B.Context.for_problem(prob, B.PHG_FP32_SCALED) as ctx:
+        sat = B.phg_fp32_saturation(ctx.handle)
+        assert sat > 5.0, sat
+        logl, grad = ctx.gradient()
+        assert B.phg_last_precision(ctx.handle) == B.PHG_FP64
+        assert B.phg_log_likelihood(ctx.handle) == logl
+    check("caterpillar1000-b1/fp32-guarded", logl, grad, ref, *TOL[B.PHG_FP32_SCALED])
+
+
+def test_saturated_branches_fp32_unguarded_limit():
+    """The same tree with the guard off runs the float32 kernels.  This
+    characterises the conditioning limit the guard exists for (measured
+    ~1.4e-3 scaled error, beyond the 1e-4 bar): log P(Y) still meets 1e-6 and
+    the gradient stays within 1e-2."""
+    prob = _caterpillar(1000, 96, 1.0, 11)
+    ref = oracle.evaluate_problem(prob)
+    print("[case] caterpillar1000-b1 fp32 unguarded", flush=True)
+    with B.Context.for_problem(prob, B.PHG_FP32_SCALED) as ctx:
+        B.phg_set_fp32_guard(ctx.handle, 0.0)
+        logl, grad = ctx.gradient()
+        assert B.phg_last_precision(ctx.handle) == B.PHG_FP32_SCALED
+    check("caterpillar1000-b1/fp32-unguarded", logl, grad, ref, 1e-6, 1e-2)
+
+
+@pytest.mark.parametrize("schedule", [B.PHG_SCHEDULE_AUTO, B.PHG_SCHEDULE_LEVELS])
+@pytest.mark.parametrize("prec", [B.PHG_FP64, B.PHG_FP32_SCALED])
+def test_log_likelihood_only_path(hky1000, prec, schedule):
+    """phg_log_likelihood runs P(t), the post-order pass and the final sum
+    only; its value is bitwise the log-likelihood of the full evaluation."""
+    prob, ref = hky1000
+    print(f"[case] logL-only {PREC_NAME[prec]} {SCHED_NAME[schedule]}", flush=True)
+    with B.Context.for_problem(prob, prec, schedule=schedule) as ctx:
+        ll_only = ctx.log_likelihood()
+        logl, grad = ctx.gradient()
+        assert ll_only == logl
+        assert ctx.log_likelihood() == logl
+    assert abs(ll_only - ref["logl"]) / abs(ref["logl"]) <= TOL[prec][0]
 
 
 def test_zero_site_likelihood_is_numeric_error():
