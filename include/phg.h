@@ -262,6 +262,25 @@ phg_status phg_bind_stream(phg_context *ctx, void *hip_stream);
  * *d_logl: -inf or NaN signals a zero site likelihood). */
 phg_status phg_gradient_async(phg_context *ctx, double *d_logl, double *d_grad);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * evaluation as phg_gradient_async, with the context's whole workspace in a
+ * static device array of PHG_NOALLOC_SCRATCH_BYTES (64 MiB) that the library
+ * holds on each GPU it runs on until the process ends.  Calls no hipMalloc,
+ * hipFree or other allocating routine.  Requirements, else an error and no
+ * device work: a stream bound with phg_bind_stream (PHG_ERR_STATE);
+ * phg_workspace_size of the context <= PHG_NOALLOC_SCRATCH_BYTES
+ * (PHG_ERR_OOM); no general tip partials (PHG_ERR_ARG); the context has not
+ * evaluated in other device memory before (PHG_ERR_STATE).  Every context
+ * using this call on one GPU shares that GPU's array: a context whose data
+ * another context may have overwritten since its last call uploads all its
+ * inputs again (and waits for those copies), so alternating contexts is
+ * correct but slower; calls that overlap in time on one GPU (other threads,
+ * or work still queued on another stream) race and corrupt each other.  Not
+ * routed by the FP32 precision guard.  Profiling events are not recorded. */
+#define PHG_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+phg_status phg_gradient_async_noalloc(phg_context *ctx, double *d_logl, double *d_grad);
+
 /* Wall-clock-free introspection: number of kernel launches one gradient call
  * issues and the post-/pre-order level counts of the current topology. */
 phg_status phg_schedule_info(phg_context *ctx, int *n_post_levels,

@@ -68,6 +68,7 @@ _SIGS = {
     "phg_bind_workspace": [_vp, _vp, _c.c_size_t],
     "phg_bind_stream": [_vp, _vp],
     "phg_gradient_async": [_vp, _vp, _vp],
+    "phg_gradient_async_noalloc": [_vp, _vp, _vp],
     "phg_get_schedule": [_vp, _c.POINTER(_c.c_int)],
     "phg_set_category_eigen": [_vp, _dp, _dp, _dp],
     "phg_set_time_tree": [_vp, _dp, _dp],
@@ -256,6 +257,11 @@ def phg_bind_stream(ctx, hip_stream: int):
 
 def phg_gradient_async(ctx, d_logl: int, d_grad: int):
     _check(lib().phg_gradient_async(ctx, _vp(d_logl), _vp(d_grad)), ctx, "phg_gradient_async")
+
+
+def phg_gradient_async_noalloc(ctx, d_logl: int, d_grad: int):
+    _check(lib().phg_gradient_async_noalloc(ctx, _vp(d_logl), _vp(d_grad)), ctx,
+           "phg_gradient_async_noalloc")
 
 
 def phg_set_time_tree(ctx, heights, rates):

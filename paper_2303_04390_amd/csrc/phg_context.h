@@ -80,6 +80,8 @@ struct phg_context {
     // than fp32_guard (phg::fp32_saturation) evaluates on an FP64 twin
     // context holding copies of the same inputs; fp32_guard <= 0 disables.
     double fp32_guard = phg::kDefaultFp32Guard;
+    uint64_t uid = 0;            // unique per context of this process
+    bool static_ws = false;      // workspace is the static scratch array (phg_gradient_async_noalloc)
     phg_context* twin = nullptr;
     int last_prec = -1;          // precision of the last evaluation issued (-1: none)
 
@@ -154,6 +156,11 @@ double fp32_saturation(const phg_context* ctx);
 phg_context* eval_target(phg_context* ctx, phg_status* st);
 // Copy the twin's error message into ctx when a routed call failed.
 phg_status from_twin(phg_context* ctx, phg_context* t, phg_status s);
+// The static scratch array of phg_gradient_async_noalloc (phg_static.hip):
+// its device address on ctx's device, and whether another context used it
+// since ctx did (recording ctx as its user).
+phg_status scratch_address(phg_context* ctx, void** out);
+bool scratch_claim(const phg_context* ctx);
 // Forget the device binding (workspace, pinned output) so the context can be
 // bound to new memory later; every input is uploaded again on next use.  The
 // caller guarantees no device work of this context is pending.

@@ -563,6 +563,9 @@ phg_status ctx_ready(phg_context* ctx) {
     }
     phg_status s = ensure_device(ctx);
     if (s != PHG_OK) return s;
+    // a context in the shared static array uploads everything again when
+    // another context used the array since its last evaluation
+    if (ctx->static_ws && scratch_claim(ctx)) ctx->dirty |= ctx->have | kPw | kTopo | kDesc;
     return upload(ctx);
 }
 
@@ -696,6 +699,8 @@ phg_status phg_create(int n_tips, int n_patterns, int n_states, int n_categories
     ctx->Cpad = (n_patterns + phg::kLanes - 1) / phg::kLanes * phg::kLanes;
     ctx->tiles = ctx->Cpad / phg::tile_patterns(n_states, n_categories, prec == PHG_FP32_SCALED);
     ctx->S4 = (n_states + 3) / 4;
+    static std::atomic<uint64_t> next_uid{1};
+    ctx->uid = next_uid.fetch_add(1);
     ctx->pw.assign(ctx->Cpad, 0.0);
     std::fill(ctx->pw.begin(), ctx->pw.begin() + n_patterns, 1.0);
     ctx->codes.assign(static_cast<size_t>(n_tips) * ctx->Cpad, static_cast<uint8_t>(n_states));

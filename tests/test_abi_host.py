@@ -307,3 +307,20 @@ def test_tip_partials_validation_and_schedule():
         assert e.value.status == B.PHG_ERR_ARG
     finally:
         B.phg_destroy(ctx)
+
+
+def test_noalloc_entry_refuses_oversized_workspace():
+    """phg_gradient_async_noalloc checks the workspace against its static
+    array before any device work (the output pointers are never touched)."""
+    prob = synth.config_problem("hky1000", seed=0, n_patterns=64)
+    big = B.Context(1000, 10000, 4, 4, B.PHG_FP32_SCALED)
+    try:
+        small = synth.config_problem("hky1000", seed=0)
+        big.set_problem(small)
+        with pytest.raises(B.PhgError) as e:
+            B.phg_gradient_async_noalloc(big.handle, 256, 512)
+        assert e.value.status == B.PHG_ERR_OOM and "static scratch" in e.value.message
+    finally:
+        big.close()
+    assert B.phg_workspace_size(1000, 10000, 4, 4, B.PHG_FP32_SCALED) > (64 << 20)
+    assert prob.n_tips == 1000
