@@ -250,19 +250,46 @@ def serving_measurement(args, B, synth):
 MFMA_PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6}      # MI355X dense MFMA peaks
 
 
-def matvec_flops(parent, n_tips, C, R, S):
-    """Algorithmic flops of one evaluation on the MFMA kernels (one S x S
-    matrix-vector product per pattern and category = 2 S^2 flops):
-    post-order 2 per internal node (P_i p_i, P_j p_j); pre-order 4 per
-    internal node (m_i, m_j, dm_i, dm_j) and 1 per internal child (q_x =
-    P_x^T u_x)."""
+def accuracy(logl, grad, ref, n_sample):
+    """Error against the oracle: log-likelihood relative error; per gradient
+    component the scaled error |g-g*| / max(|g*|, 1e-2 A) (A = sum_c W_c |d_c|),
+    the pure relative error |g-g*| / |g*|, how many components relied on the
+    1e-2 A floor, and how many exceed 1e-4 in pure relative terms."""
+    g, gs, A = np.asarray(grad), ref["grad"], ref["absgrad"]
+    err = np.abs(g - gs)
+    denom = np.maximum(np.abs(gs), 1e-2 * A)
+    pure = err / np.maximum(np.abs(gs), 1e-300)
+    return {"sample_patterns": int(n_sample),
+            "logl_rel_err": float(abs(logl - ref["logl"]) / abs(ref["logl"])),
+            "grad_max_scaled_err": float(np.max(err / denom)),
+            "grad_max_pure_rel_err": float(np.max(pure)),
+            "grad_components": int(g.size),
+            "grad_floor_used": int(np.sum(1e-2 * A > np.abs(gs))),
+            "grad_pure_rel_err_above_1e-4": int(np.sum(pure > 1e-4))}
+
+
+def algorithmic_flops(n_tips, C, R, S):
+    """The method's own flops per evaluation at S states (2 S^2 per S x S
+    matrix-vector product, per pattern and category): the post-order forms
+    P_x p_x once per internal child (N-2 of them; a tip child's P e_y is a
+    column of P, no product); the pre-order forms P_x' p_x' for the sibling
+    vector, dP_x p_x and q_x = P_x^T u_x once per internal child (eq:preorder,
+    eq:gradient).  4 (N-2) products in all; the per-pattern dot products are
+    lower order and not counted."""
+    return 4.0 * (n_tips - 2) * 2.0 * S * S * C * R
+
+
+def executed_flops(parent, n_tips, C, R, S):
+    """Dense products the MFMA kernels issue per evaluation, at S padded to
+    the 16-state MFMA tile: post-order P_x p_x for both children of every
+    internal node (a tip child's one-hot operand included); pre-order P_x p_x
+    and dP_x p_x for both children of every internal node, and P_x^T u_x for
+    every internal child."""
     n = parent.shape[0]
     internal = n - n_tips
     internal_children = int(np.sum(np.arange(n - 1) >= n_tips))
-    post = 2 * internal
-    pre = 4 * internal + internal_children
-    per = 2.0 * S * S * C * R
-    return post * per, pre * per
+    Sp = -(-S // 16) * 16
+    return (2 * internal + 4 * internal + internal_children) * 2.0 * Sp * Sp * C * R
 
 
 def state_space_measurement(args, B, synth, stream, out):
@@ -272,25 +299,16 @@ def state_space_measurement(args, B, synth, stream, out):
     count of byte tip codes, near the paper's 256-state phylogeographic
     models), in FP32 and FP64."""
     import torch
+    import oracle
     res = {}
-    cases = [("aa500", synth.config_problem("aa500", seed=args.seed)),
-             ("codon128", synth.config_problem("codon128", seed=args.seed))]
-    rng = np.random.default_rng(args.seed + 5)
-    N122 = 128
-    parent = synth.yule_topology(N122, rng)
-    pi = rng.dirichlet([2.0] * 122)
-    Q = synth.gtr_model(rng.gamma(1.0, 1.0, 122 * 121 // 2), pi)
-    rates, w = synth.discrete_gamma(0.5, 4)
-    cases.append(("s122", synth.make_problem(parent, synth.exponential_branch_lengths(N122, 0.05, rng), Q, pi,
-                                             rates, w, 2000, rng)))
-    parent = synth.yule_topology(N122, rng)
-    pi = rng.dirichlet([2.0] * 240)
-    Q = synth.gtr_model(rng.gamma(1.0, 1.0, 240 * 239 // 2), pi)
-    cases.append(("s240", synth.make_problem(parent, synth.exponential_branch_lengths(N122, 0.05, rng), Q, pi,
-                                             rates, w, 1000, rng)))
+    cases = [(w, synth.config_problem(w, seed=args.seed)) for w in ("aa500", "codon128", "s122", "s240")]
     for name, prob in cases:
         N, C, S, R = prob.n_tips, prob.n_patterns, prob.n_states, prob.n_categories
-        post_f, pre_f = matvec_flops(prob.parent, N, C, R, S)
+        alg_f = algorithmic_flops(N, C, R, S)
+        exe_f = executed_flops(prob.parent, N, C, R, S)
+        # accuracy against the oracle on a pattern sample of the same workload
+        sample = prob.subset_patterns(np.arange(min(args.state_sample_patterns, C)))
+        ref = oracle.evaluate_problem(sample) if args.state_sample_patterns > 0 else None
         for prec, tag in ((B.PHG_FP32_SCALED, "f32"), (B.PHG_FP64, "f64")):
             h = B.phg_create(N, C, S, R, prec, 0)
             try:
@@ -312,14 +330,21 @@ def state_space_measurement(args, B, synth, stream, out):
                 B.phg_destroy(h)
             cls = dict(zip(B.PROF_NAMES, (ms_cls / max(n_prof, 1)).tolist()))
             t_mm = (cls["post"] + cls["pre_grad"]) * 1e-3
-            tflops = (post_f + pre_f) / t_mm / 1e12
-            res[f"{name}_{tag}"] = {
+            tflops = alg_f / t_mm / 1e12
+            entry = {
                 "n_tips": N, "n_patterns": C, "n_states": S, "n_categories": R,
                 "evals_per_s": round(1.0 / dt, 1), "ms_per_eval": round(dt * 1e3, 4),
                 "ms_per_class": {k2: round(v, 4) for k2, v in cls.items()},
-                "algorithmic_gflop_per_eval": round((post_f + pre_f) / 1e9, 2),
+                "algorithmic_gflop_per_eval": round(alg_f / 1e9, 2),
                 "mfma_tflops": round(tflops, 2), "mfma_peak_tflops": MFMA_PEAK_TFLOPS[tag],
-                "mfma_frac": round(tflops / MFMA_PEAK_TFLOPS[tag], 4)}
+                "mfma_frac": round(tflops / MFMA_PEAK_TFLOPS[tag], 4),
+                "executed_gflop_per_eval": round(exe_f / 1e9, 2),
+                "executed_tflops": round(exe_f / t_mm / 1e12, 2)}
+            if ref is not None:
+                with B.Context.for_problem(sample, prec) as ctx:
+                    logl, grad = ctx.gradient()
+                entry["accuracy_vs_oracle"] = accuracy(logl, grad, ref, sample.n_patterns)
+            res[f"{name}_{tag}"] = entry
             print(f"[bench] {name} {tag}: {1.0 / dt:.1f} evals/s, {tflops:.1f} TFLOP/s", file=sys.stderr,
                   flush=True)
     return res
@@ -372,6 +397,74 @@ def batched_vs_fp64(args, B, prob, fp64_evals_per_s):
             "server_steps": stats["steps"]}
 
 
+def _oracle_block(prob):
+    """One pattern block through the unchanged oracle, one BLAS thread."""
+    import oracle
+    from threadpoolctl import threadpool_limits
+    with threadpool_limits(limits=1):
+        r = oracle.evaluate_problem(prob)
+    return r["logl"], r["grad"]
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline(prob, args):
+    """The FP64 oracle as it stands, on the host: one thread on a pattern
+    sample, and every available core (at most --cpu-workers processes) on the
+    whole workload split into contiguous pattern blocks whose log-likelihoods
+    and gradients are summed in block order -- the paper's CPU scheme of
+    column blocks.  Each: one warm-up run, then the median of three."""
+    import multiprocessing as mp
+    import statistics
+    import oracle
+    from threadpoolctl import threadpool_limits
+    C = prob.n_patterns
+    Cs = min(args.cpu_sample_patterns, C)
+    s1 = prob.subset_patterns(np.arange(Cs))
+    print(f"[bench] oracle, 1 thread, {Cs} patterns: warm-up + 3 runs", file=sys.stderr, flush=True)
+    t1 = []
+    with threadpool_limits(limits=1):
+        for _ in range(4):
+            t0 = time.perf_counter()
+            oracle.evaluate_problem(s1)
+            t1.append(time.perf_counter() - t0)
+    t1 = statistics.median(t1[1:])
+    avail = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    workers = max(1, min(args.cpu_workers, avail))
+    blocks = [prob.subset_patterns(ix) for ix in np.array_split(np.arange(C), workers)]
+    print(f"[bench] oracle, {workers} processes, {C} patterns: warm-up + 3 runs", file=sys.stderr, flush=True)
+    tall = []
+    with mp.get_context("spawn").Pool(workers) as pool:
+        for _ in range(4):
+            t0 = time.perf_counter()
+            parts = pool.map(_oracle_block, blocks, chunksize=1)
+            logl = 0.0
+            grad = np.zeros_like(parts[0][1])
+            for ll, g in parts:          # fixed block order
+                logl += ll
+                grad += g
+            tall.append(time.perf_counter() - t0)
+    tall = statistics.median(tall[1:])
+    return {"value": round(1.0 / tall, 4), "unit": "evals/s", "cores": workers, "kind": "oracle",
+            "sample": f"the whole 1000-taxon workload ({C} patterns) in {workers} contiguous pattern blocks, "
+                      f"one process each, block results summed in order; median of 3 after 1 warm-up: "
+                      f"{tall:.2f} s per evaluation",
+            "one_thread": {"value": round((Cs / C) / t1, 5), "unit": "evals/s",
+                           "sample": f"first {Cs} of {C} patterns, median of 3 after 1 warm-up: {t1:.2f} s, "
+                                     f"scaled by {C}/{Cs} (cost is linear in patterns)"},
+            "host": {"cpu_model": _cpu_model(), "nproc": os.cpu_count(), "available_cpus": avail},
+            "logl_all_cores": logl}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -379,7 +472,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--latency-requests", type=int, default=50)
     ap.add_argument("--fp64-steps", type=int, default=10)
-    ap.add_argument("--cpu-sample-patterns", type=int, default=3000)
+    ap.add_argument("--cpu-sample-patterns", type=int, default=1000,
+                    help="patterns of the one-thread oracle timing")
+    ap.add_argument("--accuracy-sample-patterns", type=int, default=3000,
+                    help="patterns of the 1000-taxon workload checked against the oracle")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--schedule", choices=("auto", "levels", "blocks"), default="auto",
@@ -394,6 +490,10 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-states", action="store_true", help="skip the 20/61/122/240-state measurements")
     ap.add_argument("--state-steps", type=int, default=10)
+    ap.add_argument("--state-sample-patterns", type=int, default=200,
+                    help="patterns of each state-space workload checked against the oracle (0: none)")
+    ap.add_argument("--cpu-workers", type=int, default=16,
+                    help="most processes of the all-cores oracle timing (the box's CPU share per GPU)")
     ap.add_argument("--batched-chains", type=int, default=8)
     ap.add_argument("--batched-seconds", type=float, default=3.0)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -509,20 +609,33 @@ def main():
             and MEASURED_TRAFFIC["schedule"] == ("blocks" if blocked else "levels")
             and dominant in MEASURED_TRAFFIC["bytes_per_eval"]):
         traffic = int(MEASURED_TRAFFIC["bytes_per_eval"][dominant] / n_launch)
+    # the dominant kernel's share of the method minimum M0 (every internal
+    # partial written once and read once, tip codes twice, exponents once):
+    # the pre-order reads each non-root internal partial and each tip code
+    # once, the post-order does the rest
+    vec = R * S * 4
+    m0 = (2 * N - 3) * vec + 2 * N + (N - 1)
+    m0_pre = ((N - 2) * vec + N) * C
+    m0_share = m0_pre if dominant == "pre_grad" else m0 * C - m0_pre
+    m0_achieved = (m0_share / n_launch) / (dom_ms * 1e-3 / n_launch) / 1e9
     roofline = {
         "bound": "hbm",
         # the class: wide launches take <R, false>, narrow (latency-bound) ones <R, true>
         "kernel": (f"{'pre' if dominant == 'pre_grad' else 'post'}_bmf_kernel<{R}, *>" if blocked and R & (R - 1) == 0
                    else f"{'pre' if dominant == 'pre_grad' else 'post'}_{'blk' if blocked else 's4'}_kernel<float,{R}>"),
         "schedule": "blocks" if blocked else "levels",
-        "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+        "achieved": round(m0_achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "frac": round(m0_achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
         "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-        "algorithmic_bytes_per_launch": int(dom_bytes / n_launch),
+        "algorithmic_bytes_per_launch": int(m0_share / n_launch),
+        "algorithmic_bytes": "the kernel's share of the method minimum M0 per launch",
         "launches_per_eval": n_launch,
         "launch_avg_us": round(dom_ms * 1e3 / n_launch, 3),
+        "schedule_bytes_per_launch": int(dom_bytes / n_launch),
+        "schedule_achieved": round(achieved, 1),
+        "schedule_frac": round(achieved / HBM_PEAK_GBS, 4),
+        "schedule_bytes": "bytes the schedule itself must move per launch (block roots' vectors, codes)",
     }
-    m0 = (2 * N - 3) * R * S * 4 + 2 * N + (N - 1)
     path = {"ms_per_class": {k: round(v, 4) for k, v in cls.items()},
             "launches_per_class": dict(zip(B.PROF_NAMES, launches.tolist())),
             "m0_bytes_per_eval": int(m0 * C),
@@ -606,33 +719,25 @@ def main():
         "serving": serving,
     }
 
-    # ------------------------------------------------ oracle sample: accuracy + CPU baseline
+    # ------------------------------------------------ oracle: CPU baseline + accuracy
     if not args.no_cpu_baseline:
         import oracle
-        from threadpoolctl import threadpool_limits
-        Cs = min(args.cpu_sample_patterns, C)
+        rec["cpu_baseline"] = cpu_baseline(prob, args)
+        Cs = min(args.accuracy_sample_patterns, C)
         sample = prob.subset_patterns(np.arange(Cs))
-        print(f"[bench] oracle on {Cs} patterns (1 thread)", file=sys.stderr, flush=True)
-        with threadpool_limits(limits=1):
-            t0 = time.perf_counter()
-            ref = oracle.evaluate_problem(sample)
-            t_or = time.perf_counter() - t0
-        rec["cpu_baseline"] = {
-            "value": round((Cs / C) / t_or, 5), "unit": "evals/s", "cores": 1, "kind": "oracle",
-            "sample": f"hky1000 tree and model, first {Cs} of {C} patterns, one evaluation in "
-                      f"{t_or:.2f} s, scaled by {C}/{Cs} (cost is linear in patterns)",
-        }
+        print(f"[bench] accuracy against the oracle on {Cs} patterns", file=sys.stderr, flush=True)
+        ref = oracle.evaluate_problem(sample)
         acc = {}
         for prec, name in ((B.PHG_FP32_SCALED, "fp32"), (B.PHG_FP64, "fp64")):
             with B.Context.for_problem(sample, prec) as ctx:
                 logl, grad = ctx.gradient()
-            denom = np.maximum(np.abs(ref["grad"]), 1e-2 * ref["absgrad"])
-            acc[name] = {"logl_rel_err": float(abs(logl - ref["logl"]) / abs(ref["logl"])),
-                         "grad_max_scaled_err": float(np.max(np.abs(grad - ref["grad"]) / denom)),
-                         "grad_max_pure_rel_err": float(np.max(np.abs(grad - ref["grad"]) /
-                                                               np.abs(ref["grad"])))}
-        rec["accuracy_vs_oracle"] = {"sample_patterns": Cs, **acc,
-                                     "rule": "|g-g*| / max(|g*|, 1e-2 * sum_c W_c |d_c|)"}
+                ran = B.phg_last_precision(ctx.handle)
+                sat = B.phg_fp32_saturation(ctx.handle)
+            acc[name] = accuracy(logl, grad, ref, Cs)
+            acc[name]["ran_in"] = "fp64" if ran == B.PHG_FP64 else "fp32"
+        acc["fp32_guard_saturation"] = round(sat, 4)
+        acc["rule"] = "scaled: |g-g*| / max(|g*|, 1e-2 * sum_c W_c |d_c|); pure: |g-g*| / |g*|"
+        rec["accuracy_vs_oracle"] = acc
     print(json.dumps(rec), flush=True)
 
 

@@ -449,6 +449,11 @@ def config_problem(which: str, seed: int = 0, n_patterns: Optional[int] = None,
                 ~Gamma(1,1), pi~Dir(1^20), Gamma4 a=0.5, b~Exp(0.05), 5000 patterns.
     "codon128": 128 taxa, b~Exp(0.05), GY94 omega=0.3 kappa=2, F3x4 with
                 per-position Dir(10^4), Gamma4 a=0.5, 4000 patterns.
+    "s122":     128 taxa, b~Exp(0.05), 122-state GTR (exchangeabilities
+                ~Gamma(1,1), pi~Dir(2^122)), Gamma4 a=0.5, 2000 patterns (the
+                size of a Markov-modulated codon model).
+    "s240":     as "s122" with 240 states and 1000 patterns (near the
+                256-state models the paper's Discussion names).
     ``n_patterns``/``n_tips`` override the sizes (smaller parity cases).
     """
     rng = np.random.default_rng(seed)
@@ -489,6 +494,15 @@ def config_problem(which: str, seed: int = 0, n_patterns: Optional[int] = None,
         b = exponential_branch_lengths(N, 0.05, rng)
         pos = np.stack([rng.dirichlet([10.0] * 4) for _ in range(3)])
         Q, pi = gy94_model(0.3, 2.0, pos)
+        rates, w = discrete_gamma(0.5, 4)
+        return make_problem(parent, b, Q, pi, rates, w, C, rng, name=which)
+    if which in ("s122", "s240"):
+        S = 122 if which == "s122" else 240
+        N, C = n_tips or 128, n_patterns or (2000 if S == 122 else 1000)
+        parent = yule_topology(N, rng)
+        b = exponential_branch_lengths(N, 0.05, rng)
+        pi = rng.dirichlet([2.0] * S)
+        Q = gtr_model(rng.gamma(1.0, 1.0, S * (S - 1) // 2), pi)
         rates, w = discrete_gamma(0.5, 4)
         return make_problem(parent, b, Q, pi, rates, w, C, rng, name=which)
     raise ValueError(f"unknown config {which!r}")
