@@ -281,15 +281,14 @@ def algorithmic_flops(n_tips, C, R, S):
 
 def executed_flops(parent, n_tips, C, R, S):
     """Dense products the MFMA kernels issue per evaluation, at S padded to
-    the 16-state MFMA tile: post-order P_x p_x for both children of every
-    internal node (a tip child's one-hot operand included); pre-order P_x p_x
-    and dP_x p_x for both children of every internal node, and P_x^T u_x for
-    every internal child."""
+    the 16-state MFMA tile.  A tip child given by its code is a gather from
+    the P(t) tables, not a product, so the kernels issue P_x p_x in the
+    post-order and P_x p_x, dP_x p_x and P_x^T u_x in the pre-order for
+    internal children only: the method's 4 (N-2) products, padded."""
     n = parent.shape[0]
-    internal = n - n_tips
     internal_children = int(np.sum(np.arange(n - 1) >= n_tips))
     Sp = -(-S // 16) * 16
-    return (2 * internal + 4 * internal + internal_children) * 2.0 * Sp * Sp * C * R
+    return 4 * internal_children * 2.0 * Sp * Sp * C * R
 
 
 def state_space_measurement(args, B, synth, stream, out):

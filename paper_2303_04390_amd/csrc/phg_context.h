@@ -17,7 +17,7 @@ namespace phg {
 
 // Workspace plan: byte offsets of every device buffer inside one arena.
 struct Plan {
-    size_t codes, part, expo, eloc, P64, dP64, P32, dP32, PB32, PB64, TT64, dTT64, TT32, dTT32, b, V, Vinv, lam, rates, cw,
+    size_t codes, part, expo, eloc, P64, dP64, P32, dP32, PB32, PB64, dPB32, dPB64, vsum, TT64, dTT64, TT32, dTT32, b, V, Vinv, lam, rates, cw,
         pi, pw, sll, lpart, gpart, out, sched, desc, ch_parent, ch_kids, heights, trates, set_ptr, set_idx,
         total;
 };
@@ -59,6 +59,7 @@ struct phg_context {
     std::vector<int32_t> parent;
     std::vector<int32_t> kids;   // [N-1][2] children of internal node N + k
     std::vector<double> b, V, Vinv, lam, pi, rates, cw, pw;
+    std::vector<double> vsum;    // [models][S] row sums of Vinv (uploaded with the eigensystem)
     std::vector<uint8_t> codes;  // [N][Cpad], padding = S
     bool eig_cat = false;        // V, Vinv, lam hold one model per category
     // time tree (heights [2N-1], rate scalars [2N-2]) and branch sets (CSR)

@@ -53,14 +53,17 @@ Plan make_plan(int N, int C, int S, int R, phg_precision prec) {
         // MFMA operand order: one forward table per matrix and a backward
         // copy of P, in the path's own type only
         const size_t mat = E * R * gl_mat_rows(S) * gl_row(S);
+        const size_t back = E * R * gl_back_rows(S) * gl_row(S);
         p.part = take(I * tiles * R * tp * gl_row(S) * tsz);
         p.eloc = take(I * Cpad * sizeof(int32_t));
         p.P64 = take(fp32 ? 0 : mat * 8);
         p.dP64 = take(fp32 ? 0 : mat * 8);
-        p.PB64 = take(fp32 ? 0 : mat * 8);
+        p.PB64 = take(fp32 ? 0 : back * 8);
+        p.dPB64 = take(fp32 ? 0 : back * 8);
         p.P32 = take(fp32 ? mat * 4 : 0);
         p.dP32 = take(fp32 ? mat * 4 : 0);
-        p.PB32 = take(fp32 ? mat * 4 : 0);
+        p.PB32 = take(fp32 ? back * 4 : 0);
+        p.dPB32 = take(fp32 ? back * 4 : 0);
     } else {
         p.part = take(I * tiles * R * S * tp * tsz);
         p.eloc = take(0);
@@ -70,7 +73,10 @@ Plan make_plan(int N, int C, int S, int R, phg_precision prec) {
         p.dP32 = take(fp32 ? E * R * S * S * 4 : 0);
         p.PB64 = take(0);
         p.PB32 = take(0);
+        p.dPB64 = take(0);
+        p.dPB32 = take(0);
     }
+    p.vsum = take(static_cast<size_t>(R) * S * 8);
     const size_t tt = S == 4 ? E * R * 20 : 0;
     p.TT64 = take(tt * 8);
     p.dTT64 = take(tt * 8);
@@ -299,6 +305,9 @@ phg_status ensure_device(phg_context* ctx) {
     d.dP32 = reinterpret_cast<float*>(a + pl.dP32);
     d.PB32 = reinterpret_cast<float*>(a + pl.PB32);
     d.PB64 = reinterpret_cast<double*>(a + pl.PB64);
+    d.dPB32 = reinterpret_cast<float*>(a + pl.dPB32);
+    d.dPB64 = reinterpret_cast<double*>(a + pl.dPB64);
+    d.vsum = reinterpret_cast<const double*>(a + pl.vsum);
     d.TT64 = reinterpret_cast<double*>(a + pl.TT64);
     d.dTT64 = reinterpret_cast<double*>(a + pl.dTT64);
     d.TT32 = reinterpret_cast<float*>(a + pl.TT32);
@@ -443,6 +452,16 @@ phg_status upload(phg_context* ctx) {
     }
     if (dirty & kB) PHG_HIP(ctx, put(pl.b, ctx->b.data(), ctx->b.size() * 8));
     if (dirty & kEig) {
+        // row sums of Vinv, per model: P 1 = V diag(e) (Vinv 1)
+        const size_t S = ctx->S, models = ctx->Vinv.size() / (S * S);
+        ctx->vsum.assign(models * S, 0.0);
+        for (size_t m = 0; m < models; ++m)
+            for (size_t k = 0; k < S; ++k) {
+                double acc = 0.0;
+                for (size_t t = 0; t < S; ++t) acc += ctx->Vinv[(m * S + k) * S + t];
+                ctx->vsum[m * S + k] = acc;
+            }
+        PHG_HIP(ctx, put(pl.vsum, ctx->vsum.data(), ctx->vsum.size() * 8));
         PHG_HIP(ctx, put(pl.V, ctx->V.data(), ctx->V.size() * 8));
         PHG_HIP(ctx, put(pl.Vinv, ctx->Vinv.data(), ctx->Vinv.size() * 8));
         PHG_HIP(ctx, put(pl.lam, ctx->lam.data(), ctx->lam.size() * 8));

@@ -69,6 +69,13 @@ struct ReqDesc {
     float* dP32;
     float* PB32;
     double* PB64;
+    // 17..255 states: backward copy of dP (row t holds dP[s][t] at column
+    // gl_col(s)), and for P and dP one more row after the gl_mat_rows(S)
+    // rows of each backward table holding the row sums (a fully ambiguous
+    // tip's vector); vsum[m][k] = sum_t Vinv_m[k][t] (host-computed)
+    float* dPB32;
+    double* dPB64;
+    const double* vsum;
     // 4 states: tip tables [E][R][5][4]: entry y (0..3) is column y of P (or
     // dP), entry 4 its row sums (the ambiguous code), so P e_y is one load
     double* TT64;
@@ -183,6 +190,9 @@ __host__ __device__ constexpr inline int gl_col(int t, int kbp) { return (t & 3)
 __host__ __device__ constexpr inline int gl_mat_rows(int S) {
     return S <= 64 ? (S + 15) / 16 * 16 : (S + 63) / 64 * 64;
 }
+// Rows of one (branch, category) backward table: the gl_mat_rows(S) rows of
+// states, then the row sums (read for tip code S).
+__host__ __device__ constexpr inline int gl_back_rows(int S) { return gl_mat_rows(S) + 1; }
 // Row blocks of 16 patterns per tile: two (each matrix operand then feeds two
 // MFMAs) for FP32 above 32 states and FP64 at 65..128, one otherwise.
 // Measured: above 64 states two win even at one wave per SIMD; four at

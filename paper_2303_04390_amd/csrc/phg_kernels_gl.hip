@@ -125,6 +125,13 @@ __device__ __forceinline__ float* tabPB<float>(const ReqDesc& d) { return d.PB32
 template <>
 __device__ __forceinline__ double* tabPB<double>(const ReqDesc& d) { return d.PB64; }
 
+template <typename T>
+__device__ __forceinline__ T* tabdPB(const ReqDesc& d);
+template <>
+__device__ __forceinline__ float* tabdPB<float>(const ReqDesc& d) { return d.dPB32; }
+template <>
+__device__ __forceinline__ double* tabdPB<double>(const ReqDesc& d) { return d.dPB64; }
+
 template <typename T, int G>
 using VecG = T __attribute__((ext_vector_type(G)));
 
@@ -141,12 +148,12 @@ struct Cols {
     V4<T> v[RB][NBW];
 };
 
-// Where a child's input vector comes from.
+// Where a child's input vector comes from (a tip given by its codes does not
+// go through the products: see tip_lookup).
 template <typename T, int RB>
 struct Input {
     const T* lds;           // staged [TP][la] vector of (child, tile, r) in LDS, or null
-    const GLOBAL T* base;   // or the stored [TP][row] block in HBM, or null; both null: a tip
-    int code[RB];           // a tip's codes for patterns 16 rb + n of the tile
+    const GLOBAL T* base;   // or the stored [TP][row] block in HBM
 };
 
 // k-steps whose operands are loaded together before their MFMAs run (one
@@ -214,8 +221,8 @@ __device__ __forceinline__ void stage_vec(T* buf, const GLOBAL T* __restrict__ s
 
 // out1 = M1 v (and, with M2, out2 = M2 v) on this wave's columns:
 // out[c][s] = sum_t M[s][t] in[c][t], s = cb0 + 16 cb + n, from forward
-// tables; v from LDS (kLds) or HBM, or a tip's code.  One operand stream of v
-// feeds both products (P p and dP p of one child).
+// tables; v from LDS (kLds) or HBM.  One operand stream of v feeds both
+// products (P p and dP p of one child).
 template <typename T, int RB, int NBW, int G, bool kTwo, bool kLds = true>
 __device__ __forceinline__ void fwd(const GLOBAL T* __restrict__ M1, const GLOBAL T* __restrict__ M2,
                                     const Input<T, RB>& in, const Geo& ge, int cb0, int lane,
@@ -227,13 +234,12 @@ __device__ __forceinline__ void fwd(const GLOBAL T* __restrict__ M1, const GLOBA
 #pragma unroll
         for (int cb = 0; cb < NBW; ++cb) out1.v[rb][cb] = out2.v[rb][cb] = V4<T>{0, 0, 0, 0};
     const int off = gq * ge.kbp;
-    const bool tip = kLds ? in.lds == nullptr : in.base == nullptr;
     const T* ar[RB];
     const GLOBAL T* ag[RB];
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb) {
-        ar[rb] = kLds && !tip ? in.lds + (16 * rb + n) * ge.la + off : nullptr;
-        ag[rb] = !kLds && !tip ? in.base + (16 * rb + n) * ge.row + off : nullptr;
+        ar[rb] = kLds ? in.lds + (16 * rb + n) * ge.la + off : nullptr;
+        ag[rb] = !kLds ? in.base + (16 * rb + n) * ge.row + off : nullptr;
     }
     const GLOBAL T* br1[NBW];
     const GLOBAL T* br2[NBW];
@@ -263,22 +269,13 @@ __device__ __forceinline__ void fwd(const GLOBAL T* __restrict__ M1, const GLOBA
                 }
 #pragma unroll
                 for (int rb = 0; rb < RB; ++rb) {
-                    if (!tip) {
-                        T x[G];
-                        if (kLds)
-                            lds_run<T, G>(ar[rb] + k, x);
-                        else
-                            load_run<T, G>(ag[rb] + k, x);
+                    T x[G];
+                    if (kLds)
+                        lds_run<T, G>(ar[rb] + k, x);
+                    else
+                        load_run<T, G>(ag[rb] + k, x);
 #pragma unroll
-                        for (int j = 0; j < G; ++j) a[v * G + j][rb] = x[j];
-                    } else {
-#pragma unroll
-                        for (int j = 0; j < G; ++j) {
-                            const int t = 4 * (k + j) + gq;
-                            a[v * G + j][rb] =
-                                (t < ge.S && (in.code[rb] == t || in.code[rb] >= ge.S)) ? T(1) : T(0);
-                        }
-                    }
+                    for (int j = 0; j < G; ++j) a[v * G + j][rb] = x[j];
                 }
             }
         }
@@ -379,6 +376,41 @@ __device__ __forceinline__ void store_cols(GLOBAL T* __restrict__ base, const Ge
         }
     }
 }
+// A tip given by its codes: its vector is e_y (or all ones for code S), so
+// M e_y is column y of M, i.e. row y of M's backward table (row y holds
+// M[s][y] at column gl_col(s)), and M 1 is the row-sum row that follows the
+// table's gl_mat_rows(S) rows.  out1[c][s] = MB1[y_c][s] (and out2 from MB2)
+// on this wave's columns: a gather from the L2-resident table instead of
+// products on one-hot operands.  codes points at the tip's codes of this tile.
+template <typename T, int RB, int NBW, bool kTwo>
+__device__ __forceinline__ void tip_lookup(const GLOBAL T* __restrict__ MB1, const GLOBAL T* __restrict__ MB2,
+                                           const GLOBAL uint8_t* __restrict__ codes, const Geo& ge, int cb0,
+                                           int lane, Cols<T, RB, NBW>& out1, Cols<T, RB, NBW>& out2) {
+    const int gq = lane >> 4, n = lane & 15;
+    const int sum_row = gl_mat_rows(ge.S);
+    int yo[RB][4];      // row offset of each of this lane's patterns
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int y = codes[opat<T>(rb, gq, i)];
+            yo[rb][i] = (y < ge.S ? y : sum_row) * ge.row;
+        }
+#pragma unroll
+    for (int cb = 0; cb < NBW; ++cb) {
+        const int s = cb0 + 16 * cb + n;
+        const bool in_row = s < ge.row;
+        const int col = in_row ? gl_col(s, ge.kbp) : 0;
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                out1.v[rb][cb][i] = in_row ? MB1[yo[rb][i] + col] : T(0);
+                if (kTwo) out2.v[rb][cb][i] = in_row ? MB2[yo[rb][i] + col] : T(0);
+            }
+    }
+}
+
 // An LDS [TP][la] vector <-> this wave's columns.
 template <typename T, int RB, int NBW>
 __device__ __forceinline__ void vbuf_to_cols(const T* buf, const Geo& ge, int cb0, int lane, Cols<T, RB, NBW>& x) {
@@ -523,15 +555,6 @@ __device__ __forceinline__ bool gl_unit(const ReqDesc* __restrict__ descs, const
     return true;
 }
 
-template <typename T, int RB>
-__device__ __forceinline__ void tip_codes(Input<T, RB>& in, bool tip, int x, const ReqDesc& d, int tile, int n) {
-    constexpr int TP = 16 * RB;
-#pragma unroll
-    for (int rb = 0; rb < RB; ++rb)
-        in.code[rb] = tip ? static_cast<int>(g(d.codes)[static_cast<size_t>(x) * d.Cpad + tile * TP + 16 * rb + n])
-                          : 0;
-}
-
 // ---------------------------------------------------------------- post-order
 
 template <typename T, int RB, int NBW, int W>
@@ -560,24 +583,23 @@ __global__ __launch_bounds__(64 * W) void post_gl_kernel(const ReqDesc* __restri
     const size_t rstride = static_cast<size_t>(TP) * ge.row;
     const size_t tstride = rstride * R;
     const size_t mstride = static_cast<size_t>(gl_mat_rows(S)) * ge.row;   // one (branch, category) table
+    const size_t bstride = static_cast<size_t>(gl_back_rows(S)) * ge.row;   // one backward table
     GLOBAL T* part = g(static_cast<T*>(d.part));
     const GLOBAL T* P = g(tabP<T>(d));
+    const GLOBAL T* PB = g(tabPB<T>(d));
     const bool tip_i = nt.i < N, tip_j = nt.j < N;
-    Input<T, RB> si, sj;
-    tip_codes<T, RB>(si, tip_i, nt.i, d, tile, n);
-    tip_codes<T, RB>(sj, tip_j, nt.j, d, tile, n);
-    // inputs: stored partials, or a tip's general partial vector, or (null) its code
+    // inputs: stored partials, or a tip's general partial vector, or (null) its codes
     const GLOBAL T* pi_base = tip_src<T>(d, nt.i, tile, tiles, tstride, part);
     const GLOBAL T* pj_base = tip_src<T>(d, nt.j, tile, tiles, tstride, part);
+    const GLOBAL uint8_t* ci = g(d.codes) + static_cast<size_t>(nt.i) * Cpad + tile * TP;
+    const GLOBAL uint8_t* cj = g(d.codes) + static_cast<size_t>(nt.j) * Cpad + tile * TP;
     GLOBAL T* out_base = part + (static_cast<size_t>(nt.k - N) * tiles + tile) * tstride;
     const bool root = U.sg.flags & 1;
     {
         const int kids[2] = {nt.i, nt.j};
         stage_exps<TP, 2>(esh, kids, d, tile);      // read after the first barrier below
     }
-    si.lds = pi_base ? vb[0] : nullptr;
-    sj.lds = pj_base ? vb[1] : nullptr;
-    si.base = sj.base = nullptr;
+    const Input<T, RB> si{vb[0], nullptr}, sj{vb[1], nullptr};
     T mx[RB][4] = {};
     double site[RB][4] = {};
     for (int r = 0; r < R; ++r) {
@@ -585,12 +607,22 @@ __global__ __launch_bounds__(64 * W) void post_gl_kernel(const ReqDesc* __restri
         if (pj_base) stage_vec<T, TP, KIT>(vb[1], pj_base + r * rstride, ge);
         __syncthreads();
         Cols<T, RB, NBW> mi, mj, unused;
-        fwd<T, RB, NBW, G, false>(P + (static_cast<size_t>(nt.i) * R + r) * mstride, nullptr, si, ge, cb0, lane,
-                                  mi, unused);
-        if (!tip_i) scale_rows<T, RB, NBW>(mi, esh[0], lane);
-        fwd<T, RB, NBW, G, false>(P + (static_cast<size_t>(nt.j) * R + r) * mstride, nullptr, sj, ge, cb0, lane,
-                                  mj, unused);
-        if (!tip_j) scale_rows<T, RB, NBW>(mj, esh[1], lane);
+        if (pi_base) {
+            fwd<T, RB, NBW, G, false>(P + (static_cast<size_t>(nt.i) * R + r) * mstride, nullptr, si, ge, cb0,
+                                      lane, mi, unused);
+            if (!tip_i) scale_rows<T, RB, NBW>(mi, esh[0], lane);
+        } else {
+            tip_lookup<T, RB, NBW, false>(PB + (static_cast<size_t>(nt.i) * R + r) * bstride, nullptr, ci, ge, cb0,
+                                          lane, mi, unused);
+        }
+        if (pj_base) {
+            fwd<T, RB, NBW, G, false>(P + (static_cast<size_t>(nt.j) * R + r) * mstride, nullptr, sj, ge, cb0,
+                                      lane, mj, unused);
+            if (!tip_j) scale_rows<T, RB, NBW>(mj, esh[1], lane);
+        } else {
+            tip_lookup<T, RB, NBW, false>(PB + (static_cast<size_t>(nt.j) * R + r) * bstride, nullptr, cj, ge, cb0,
+                                          lane, mj, unused);
+        }
         mul_cols<T, RB, NBW>(mi, mj);
         if (!root) {
             max_cols<T, RB, NBW>(mi, mx);
@@ -714,11 +746,13 @@ __global__ __launch_bounds__(64 * W, (W == 2 && sizeof(T) == 4) ? 4 : 1) void pr
     const GLOBAL T* P = g(tabP<T>(d));
     const GLOBAL T* dP = g(tabdP<T>(d));
     const GLOBAL T* PB = g(tabPB<T>(d));
+    const GLOBAL T* dPB = g(tabdPB<T>(d));
+    const size_t bstride = static_cast<size_t>(gl_back_rows(S)) * ge.row;   // one backward table
     const bool is_root = nt.k == 2 * N - 2;
     const bool tip_i = nt.i < N, tip_j = nt.j < N;
-    Input<T, RB> si, sj;
-    tip_codes<T, RB>(si, tip_i, nt.i, d, tile, n);
-    tip_codes<T, RB>(sj, tip_j, nt.j, d, tile, n);
+    const GLOBAL uint8_t* ci = g(d.codes) + static_cast<size_t>(nt.i) * Cpad + tile * TP;
+    const GLOBAL uint8_t* cj = g(d.codes) + static_cast<size_t>(nt.j) * Cpad + tile * TP;
+    Input<T, RB> si{nullptr, nullptr}, sj{nullptr, nullptr};
     GLOBAL T* pi_base = tip_i ? nullptr : part + (static_cast<size_t>(nt.i - N) * tiles + tile) * tstride;
     GLOBAL T* pj_base = tip_j ? nullptr : part + (static_cast<size_t>(nt.j - N) * tiles + tile) * tstride;
     const GLOBAL T* qk_base = is_root ? nullptr : part + (static_cast<size_t>(nt.k - N) * tiles + tile) * tstride;
@@ -744,6 +778,8 @@ __global__ __launch_bounds__(64 * W, (W == 2 && sizeof(T) == 4) ? 4 : 1) void pr
         }
         const size_t mo_i = (static_cast<size_t>(nt.i) * R + r) * mstride;
         const size_t mo_j = (static_cast<size_t>(nt.j) * R + r) * mstride;
+        const size_t bo_i = (static_cast<size_t>(nt.i) * R + r) * bstride;
+        const size_t bo_j = (static_cast<size_t>(nt.j) * R + r) * bstride;
         const T wr = static_cast<T>(g(d.cweights)[r]);
         Cols<T, RB, NBW> qk, a, b, acc, dmj;
         if (is_root) {
@@ -761,16 +797,24 @@ __global__ __launch_bounds__(64 * W, (W == 2 && sizeof(T) == 4) ? 4 : 1) void pr
                 load_cols<T, RB, NBW>(qk_base + r * rstride, ge, cb0, lane, qk);
             scale_rows<T, RB, NBW>(qk, esh[2], lane);
         }
-        fwd<T, RB, NBW, G, true, kStage>(P + mo_j, dP + mo_j, sj, ge, cb0, lane, a, dmj);   // a = m_j, dm_j
-        if (!tip_j) {
-            scale_rows<T, RB, NBW>(a, esh[1], lane);
-            scale_rows<T, RB, NBW>(dmj, esh[1], lane);
+        if (pj_src) {
+            fwd<T, RB, NBW, G, true, kStage>(P + mo_j, dP + mo_j, sj, ge, cb0, lane, a, dmj);   // a = m_j, dm_j
+            if (!tip_j) {
+                scale_rows<T, RB, NBW>(a, esh[1], lane);
+                scale_rows<T, RB, NBW>(dmj, esh[1], lane);
+            }
+        } else {
+            tip_lookup<T, RB, NBW, true>(PB + bo_j, dPB + bo_j, cj, ge, cb0, lane, a, dmj);
         }
         mul_cols<T, RB, NBW>(a, qk);                                           // a = u_i
-        fwd<T, RB, NBW, G, true, kStage>(P + mo_i, dP + mo_i, si, ge, cb0, lane, b, acc);  // b = m_i, acc = dm_i
-        if (!tip_i) {
-            scale_rows<T, RB, NBW>(b, esh[0], lane);
-            scale_rows<T, RB, NBW>(acc, esh[0], lane);
+        if (pi_src) {
+            fwd<T, RB, NBW, G, true, kStage>(P + mo_i, dP + mo_i, si, ge, cb0, lane, b, acc);  // b = m_i, acc = dm_i
+            if (!tip_i) {
+                scale_rows<T, RB, NBW>(b, esh[0], lane);
+                scale_rows<T, RB, NBW>(acc, esh[0], lane);
+            }
+        } else {
+            tip_lookup<T, RB, NBW, true>(PB + bo_i, dPB + bo_i, ci, ge, cb0, lane, b, acc);
         }
         T dd[RB][4] = {}, ni[RB][4] = {}, nj[RB][4] = {};
         dot_cols<T, RB, NBW>(a, b, dd);                                        // u_i . m_i
@@ -790,12 +834,12 @@ __global__ __launch_bounds__(64 * W, (W == 2 && sizeof(T) == 4) ? 4 : 1) void pr
         if (!tip_j) cols_to_vbuf<T, RB, NBW>(vb[1], ge, cb0, lane, b);       // u_j over p_j
         __syncthreads();      // u complete in LDS
         if (!tip_i) {
-            bwd<T, RB, NBW, G>(PB + mo_i, vb[0], ge, cb0, lane, acc);    // q_i = P_i^T u_i, stored over p_i
+            bwd<T, RB, NBW, G>(PB + bo_i, vb[0], ge, cb0, lane, acc);    // q_i = P_i^T u_i, stored over p_i
             max_cols<T, RB, NBW>(acc, mxi);
             store_cols<T, RB, NBW>(pi_base + r * rstride, ge, cb0, lane, acc);
         }
         if (!tip_j) {
-            bwd<T, RB, NBW, G>(PB + mo_j, vb[1], ge, cb0, lane, acc);
+            bwd<T, RB, NBW, G>(PB + bo_j, vb[1], ge, cb0, lane, acc);
             max_cols<T, RB, NBW>(acc, mxj);
             store_cols<T, RB, NBW>(pj_base + r * rstride, ge, cb0, lane, acc);
         }
@@ -899,7 +943,9 @@ __global__ __launch_bounds__(64 * W, (W == 2 && sizeof(T) == 4) ? 4 : 1) void pr
 // P = V diag(exp(g lam b)) V^-1 and dP = V diag(g lam exp(g lam b)) V^-1 for
 // one (branch, category) pair (blockIdx.x) and one 64 x 64 tile of (s, t)
 // (blockIdx.y), FP64 sums stored in the path's type, written as the forward
-// tables of P and dP and the backward table of P, zeros included.  V's
+// tables of P and dP and their backward tables, zeros included; the first
+// column tile of each row tile also writes the row sums P 1, dP 1 (the
+// vector of a fully ambiguous tip) after the backward tables' rows.  V's
 // columns and V^-1's rows pass through LDS in chunks of 16 k, V^-1 already
 // scaled by exp and its derivative; a thread accumulates a 4 x 4 block.
 constexpr int kPmTile = 64, kPmK = 16;
@@ -908,7 +954,7 @@ __host__ __device__ inline int pmat_gl_tiles(int S) { return (gl_mat_rows(S) + k
 
 template <typename T>
 __global__ __launch_bounds__(256) void pmat_gl_kernel(const ReqDesc* __restrict__ descs, const SegTable segs) {
-    __shared__ double ex[256], dex[256];
+    __shared__ double ex[256], dex[256], wsum[256];
     __shared__ __align__(16) double As[kPmK][kPmTile], Be[kPmK][kPmTile], Bd[kPmK][kPmTile];
     const int unit = blockIdx.x;
     if (unit >= segs.unit_begin[segs.n]) return;
@@ -926,12 +972,17 @@ __global__ __launch_bounds__(256) void pmat_gl_kernel(const ReqDesc* __restrict_
     const double* lam = d.lam + (d.eig_cat ? r * S : 0);
     const double* V = d.V + (d.eig_cat ? static_cast<size_t>(r) * S * S : 0);
     const double* Vinv = d.Vinv + (d.eig_cat ? static_cast<size_t>(r) * S * S : 0);
+    const double* vs = d.vsum + (d.eig_cat ? r * S : 0);
     const int tid = threadIdx.x;
     for (int k = tid; k < S; k += blockDim.x) {
         const double e = exp(lam[k] * bt);
         ex[k] = e;
         dex[k] = gr * lam[k] * e;
+        wsum[k] = vs[k];
     }
+    // the first column tile also forms the row sums P 1 = V (e o Vinv 1) and
+    // dP 1 for its 64 rows (thread tid < 64 owns row s_base + tid)
+    double rsum = 0.0, drsum = 0.0;
     const int bs = tid / 16, bq = tid % 16;
     const int s_base = ts * kPmTile, t_base = tt * kPmTile;
     const int s0 = s_base + bs * 4, t0 = t_base + bq * 4;
@@ -956,6 +1007,13 @@ __global__ __launch_bounds__(256) void pmat_gl_kernel(const ReqDesc* __restrict_
             Bd[kb][ti] = vb * de;
         }
         __syncthreads();
+        if (tt == 0 && tid < kPmTile) {
+            for (int kk = 0; kk < kPmK && k0 + kk < S; ++kk) {
+                const double a = As[kk][tid] * wsum[k0 + kk];
+                rsum += a * ex[k0 + kk];
+                drsum += a * dex[k0 + kk];
+            }
+        }
 #pragma unroll 4
         for (int kk = 0; kk < kPmK; ++kk) {
             double vs[4], ve[4], vd[4];
@@ -975,11 +1033,17 @@ __global__ __launch_bounds__(256) void pmat_gl_kernel(const ReqDesc* __restrict_
         }
     }
     const int rows = gl_mat_rows(S), row = gl_row(S), kbp = gl_kbp(S);
-    if (s0 >= rows || t0 >= rows) return;  // after the last barrier
     const size_t base = static_cast<size_t>(pair) * rows * row;
+    const size_t bbase = static_cast<size_t>(pair) * gl_back_rows(S) * row;
     GLOBAL T* PF = g(tabP<T>(d)) + base;
     GLOBAL T* dPF = g(tabdP<T>(d)) + base;
-    GLOBAL T* PB = g(tabPB<T>(d)) + base;
+    GLOBAL T* PB = g(tabPB<T>(d)) + bbase;
+    GLOBAL T* dPB = g(tabdPB<T>(d)) + bbase;
+    if (tt == 0 && tid < kPmTile && s_base + tid < row) {   // the row-sum rows (zeros past S)
+        PB[static_cast<size_t>(rows) * row + gl_col(s_base + tid, kbp)] = static_cast<T>(rsum);
+        dPB[static_cast<size_t>(rows) * row + gl_col(s_base + tid, kbp)] = static_cast<T>(drsum);
+    }
+    if (s0 >= rows || t0 >= rows) return;  // after the last barrier
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -989,7 +1053,10 @@ __global__ __launch_bounds__(256) void pmat_gl_kernel(const ReqDesc* __restrict_
                 PF[static_cast<size_t>(sr) * row + gl_col(tc, kbp)] = static_cast<T>(acc[i][j]);
                 dPF[static_cast<size_t>(sr) * row + gl_col(tc, kbp)] = static_cast<T>(dacc[i][j]);
             }
-            if (sr < row) PB[static_cast<size_t>(tc) * row + gl_col(sr, kbp)] = static_cast<T>(acc[i][j]);
+            if (sr < row) {
+                PB[static_cast<size_t>(tc) * row + gl_col(sr, kbp)] = static_cast<T>(acc[i][j]);
+                dPB[static_cast<size_t>(tc) * row + gl_col(sr, kbp)] = static_cast<T>(dacc[i][j]);
+            }
         }
 }
 
