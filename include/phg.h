@@ -198,6 +198,33 @@ phg_status phg_fp32_saturation(phg_context *ctx, double *saturation);
  * before the first. */
 phg_status phg_last_precision(phg_context *ctx, int *prec);
 
+/* ---- tile-shape tuning ----
+ *
+ * A process-wide table of kernel shape parameters, per (state count,
+ * category count, precision).  Filled at the library's first use from a
+ * tuning file written by the project's autotuner (paper_2303_04390_amd/
+ * autotune.py): the file named by the environment variable PHG_TUNE_FILE, else
+ * tune_cache.txt beside libphg.so; PHG_TUNE=off skips it.  Each line reads
+ * "gfx950 S R prec param value" (prec 0 = FP64, 1 = FP32; R = 0 matches any
+ * category count); lines for other devices and '#' comments are ignored.
+ * phg_set_tuning changes an entry at run time.  Value 0 means the built-in
+ * rule.  Row blocks are read when a context is created (its tile is fixed for
+ * its lifetime); the narrow-launch threshold when a launch is issued. */
+typedef enum {
+    PHG_TUNE_ROW_BLOCKS = 0,    /* 17..255 states: 16-pattern row blocks per tile (1, 2 or 4,
+                                   as built for S and the precision) */
+    PHG_TUNE_NARROW_UNITS = 1,  /* 4 states, blocked FP32 kernels: largest launch (workgroups)
+                                   that takes the one-round-trip narrow variant */
+    PHG_TUNE_PARAMS = 2
+} phg_tune_param;
+
+/* n_categories = 0: any category count.  PHG_ERR_ARG for an unknown
+ * parameter or a value the kernels are not built for. */
+phg_status phg_set_tuning(int n_states, int n_categories, phg_precision prec, int param, int value);
+
+/* The value in effect (0: the built-in rule). */
+phg_status phg_get_tuning(int n_states, int n_categories, phg_precision prec, int param, int *value);
+
 /* ---- parameter chain rules: node heights, branch rates, branch sets ----
  *
  * The Methods section's problem statement allows a branch length to be the

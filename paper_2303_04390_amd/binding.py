@@ -92,6 +92,8 @@ _SIGS = {
     "phg_set_fp32_guard": [_vp, _c.c_double],
     "phg_fp32_saturation": [_vp, _dp],
     "phg_last_precision": [_vp, _c.POINTER(_c.c_int)],
+    "phg_set_tuning": [_c.c_int, _c.c_int, _c.c_int, _c.c_int, _c.c_int],
+    "phg_get_tuning": [_c.c_int, _c.c_int, _c.c_int, _c.c_int, _c.POINTER(_c.c_int)],
 }
 
 PHG_PROF_CLASSES = 4
@@ -340,6 +342,20 @@ def phg_fp32_saturation(ctx) -> float:
 def phg_last_precision(ctx) -> int:
     v = ctypes.c_int()
     _check(lib().phg_last_precision(ctx, ctypes.byref(v)), ctx, "phg_last_precision")
+    return v.value
+
+
+PHG_TUNE_ROW_BLOCKS = 0
+PHG_TUNE_NARROW_UNITS = 1
+
+
+def phg_set_tuning(n_states: int, n_categories: int, prec: int, param: int, value: int):
+    _check(lib().phg_set_tuning(n_states, n_categories, prec, param, value), None, "phg_set_tuning")
+
+
+def phg_get_tuning(n_states: int, n_categories: int, prec: int, param: int) -> int:
+    v = ctypes.c_int()
+    _check(lib().phg_get_tuning(n_states, n_categories, prec, param, ctypes.byref(v)), None, "phg_get_tuning")
     return v.value
 
 

@@ -7,10 +7,14 @@
 // the workspace (or uses a caller-bound one), uploads whatever changed and
 // enqueues: pmat -> post-order levels (height 1..H, the root last) ->
 // pre-order levels (depth 0..D) -> finalize.
+#include <dlfcn.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <atomic>
+#include <map>
+#include <mutex>
+#include <tuple>
 #include <cmath>
 #include <cstring>
 #include <limits>
@@ -113,6 +117,57 @@ using namespace phg;
 namespace {
 
 thread_local std::string g_create_error;
+
+// ---- tuning table (phg_set_tuning, tuning file)
+struct TuneKey {
+    int S, R, fp32, param;
+    bool operator<(const TuneKey& o) const {
+        return std::tie(S, R, fp32, param) < std::tie(o.S, o.R, o.fp32, o.param);
+    }
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, int> g_tune;
+std::once_flag g_tune_once;
+
+bool tune_value_ok(int S, int R, bool fp32, int param, int value) {
+    if (value < 0) return false;
+    if (value == 0) return true;
+    if (param == PHG_TUNE_ROW_BLOCKS)
+        return phg::uses_gl_kernels(S, R > 0 ? R : 1) && phg::gl_row_blocks_allowed(S, fp32, value);
+    if (param == PHG_TUNE_NARROW_UNITS) return S == 4 && fp32;
+    return false;
+}
+
+void tune_load_file() {
+    const char* off = std::getenv("PHG_TUNE");
+    if (off && std::strcmp(off, "off") == 0) return;
+    std::string path;
+    if (const char* f = std::getenv("PHG_TUNE_FILE")) {
+        path = f;
+    } else {
+        Dl_info info;
+        if (dladdr(reinterpret_cast<void*>(&tune_load_file), &info) && info.dli_fname) {
+            path = info.dli_fname;
+            const size_t slash = path.rfind('/');
+            path = (slash == std::string::npos ? std::string(".") : path.substr(0, slash)) + "/tune_cache.txt";
+        }
+    }
+    if (path.empty()) return;
+    FILE* fp = std::fopen(path.c_str(), "r");
+    if (!fp) return;
+    char line[256];
+    while (std::fgets(line, sizeof line, fp)) {
+        char arch[32];
+        int S, R, prec, param, value;
+        if (line[0] == '#') continue;
+        if (std::sscanf(line, "%31s %d %d %d %d %d", arch, &S, &R, &prec, &param, &value) != 6) continue;
+        if (std::strcmp(arch, "gfx950") != 0) continue;
+        if (param < 0 || param >= PHG_TUNE_PARAMS || (prec != 0 && prec != 1)) continue;
+        if (!tune_value_ok(S, R, prec == 1, param, value)) continue;
+        g_tune[TuneKey{S, R, prec, param}] = value;
+    }
+    std::fclose(fp);
+}
 
 bool finite_all(const double* x, size_t n) {
     for (size_t i = 0; i < n; ++i)
@@ -357,7 +412,7 @@ void pack_tip_vectors(const phg_context* ctx, std::vector<T>& out, std::vector<i
         }
     } else if (uses_gl_kernels(S, R)) {
         // [slot][tile][R][TP][row], state t at column gl_col(t)
-        const int TP = gl_tile_patterns(S, fp32), row = gl_row(S), kbp = gl_kbp(S);
+        const int TP = Cpad / tiles, row = gl_row(S), kbp = gl_kbp(S);
         const size_t per = static_cast<size_t>(tiles) * R * TP * row;
         out.assign(G * per, T(0));
         int gslot = 0;
@@ -513,6 +568,14 @@ SegTable one_segment(const ReqDesc& d, int units, int sched_off, int n_nodes, in
 }  // namespace
 
 namespace phg {
+
+int tuned_value(int S, int R, bool fp32, int param) {
+    std::call_once(g_tune_once, tune_load_file);
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find(TuneKey{S, R, fp32 ? 1 : 0, param});
+    if (it == g_tune.end()) it = g_tune.find(TuneKey{S, 0, fp32 ? 1 : 0, param});
+    return it == g_tune.end() ? 0 : it->second;
+}
 
 phg_status ctx_enqueue_eval(phg_context* ctx, double* d_logl, double* d_grad) {
     hipStream_t st = ctx->stream;
@@ -1040,6 +1103,33 @@ phg_status phg_gradient_async(phg_context* ctx, double* d_logl, double* d_grad) 
     s = ctx_ready(t);
     if (s == PHG_OK) s = ctx_enqueue_eval(t, d_logl, d_grad);
     return from_twin(ctx, t, s);
+}
+
+phg_status phg_set_tuning(int n_states, int n_categories, phg_precision prec, int param, int value) {
+    if (n_states < 2 || n_states > 255 || n_categories < 0 || n_categories > 64 ||
+        (prec != PHG_FP64 && prec != PHG_FP32_SCALED) || param < 0 || param >= PHG_TUNE_PARAMS) {
+        g_create_error = "phg_set_tuning: bad state count, category count, precision or parameter";
+        return PHG_ERR_ARG;
+    }
+    const bool fp32 = prec == PHG_FP32_SCALED;
+    if (!tune_value_ok(n_states, n_categories, fp32, param, value)) {
+        g_create_error = "phg_set_tuning: value " + std::to_string(value) + " is not built for these sizes";
+        return PHG_ERR_ARG;
+    }
+    std::call_once(g_tune_once, tune_load_file);
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    const TuneKey key{n_states, n_categories, fp32 ? 1 : 0, param};
+    if (value == 0)
+        g_tune.erase(key);
+    else
+        g_tune[key] = value;
+    return PHG_OK;
+}
+
+phg_status phg_get_tuning(int n_states, int n_categories, phg_precision prec, int param, int* value) {
+    if (!value || param < 0 || param >= PHG_TUNE_PARAMS) return PHG_ERR_ARG;
+    *value = tuned_value(n_states, n_categories, prec == PHG_FP32_SCALED, param);
+    return PHG_OK;
 }
 
 phg_status phg_set_fp32_guard(phg_context* ctx, double threshold) {

@@ -6,6 +6,8 @@
 #include <cstddef>
 #include <cstdint>
 
+#include "../../include/phg.h"
+
 namespace phg {
 
 constexpr int kLanes = 64;          // one wavefront = one tile of 64 site patterns
@@ -197,12 +199,24 @@ __host__ __device__ constexpr inline int gl_back_rows(int S) { return gl_mat_row
 // MFMAs) for FP32 above 32 states and FP64 at 65..128, one otherwise.
 // Measured: above 64 states two win even at one wave per SIMD; four at
 // 33..64 states (FP32), two at 33..64 (FP64) and two at 17..32 (FP32) lose.
-inline int gl_row_blocks(int S, bool fp32) {
+inline int gl_row_blocks_default(int S, bool fp32) {
     if (S <= 32) return 1;
     if (S > 128) return fp32 ? 2 : 1;
     return (fp32 || S > 64) ? 2 : 1;
 }
-inline int gl_tile_patterns(int S, bool fp32) { return 16 * gl_row_blocks(S, fp32); }
+// Row-block counts the MFMA kernels are built for at (S, precision).
+bool gl_row_blocks_allowed(int S, bool fp32, int rb);
+
+// Process-wide tuning table (phg_set_tuning; filled from a tuning file at
+// first use): per (state count, category count, precision, parameter) a value,
+// 0 meaning the built-in rule.  Read when a context is created (row blocks)
+// or a launch is issued (narrow-launch threshold).
+int tuned_value(int S, int R, bool fp32, int param);
+// Row blocks of 16 patterns per tile of a context created now.
+inline int gl_row_blocks(int S, int R, bool fp32) {
+    const int t = tuned_value(S, R, fp32, PHG_TUNE_ROW_BLOCKS);
+    return t > 0 ? t : gl_row_blocks_default(S, fp32);
+}
 hipError_t launch_level_gl(KernelClass k, const ReqDesc& shape, const ReqDesc* descs,
                            const SegTable& t, hipStream_t stream);
 // P(t) tables of those kernels (forward P, dP and backward P in operand order).

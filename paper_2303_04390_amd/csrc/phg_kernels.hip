@@ -1444,7 +1444,8 @@ hipError_t level_r(KernelClass k, bool blocked, const ReqDesc* descs, const SegT
             // with the frontier held in registers (5 waves per SIMD, 4 SIMDs,
             // 256 CUs) are latency-bound: take the variant with one load round
             // trip (the post-order kernel holds it at full occupancy always)
-            const bool narrow = n_units <= 256 * 4 * 5 / R;
+            const int tuned = tuned_value(4, R, true, PHG_TUNE_NARROW_UNITS);
+            const bool narrow = n_units <= (tuned > 0 ? tuned : 256 * 4 * 5 / R);
             if (k == kPost) {
                 hipLaunchKernelGGL((post_bmf_kernel<R>), dim3(n_units), dim3(kLanes * R), 0, st, descs, t);
             } else {
@@ -1493,7 +1494,7 @@ hipError_t level_t(KernelClass k, int R, bool blocked, const ReqDesc* descs, con
 bool kernels_support(int S, int R) { return S >= 2 && S <= 255 && R >= 1 && R <= 64; }
 
 int tile_patterns(int S, int R, bool fp32) {
-    if (uses_gl_kernels(S, R)) return gl_tile_patterns(S, fp32);
+    if (uses_gl_kernels(S, R)) return 16 * gl_row_blocks(S, R, fp32);
     return uses_s4_kernels(S, R) ? kLanes : gs_tile_patterns(fp32);
 }
 

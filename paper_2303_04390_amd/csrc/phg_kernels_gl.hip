@@ -712,9 +712,10 @@ __global__ __launch_bounds__(64 * W) void post_gl_kernel(const ReqDesc* __restri
 
 // ---------------------------------------------------------------- pre-order + gradient
 
-// Up to 32 states in FP32 the kernel fits in 128 registers: ask for 4 waves per SIMD.
+// Up to 32 states in FP32 with one row block the kernel fits in 128
+// registers: ask for 4 waves per SIMD.
 template <typename T, int RB, int NBW, int W>
-__global__ __launch_bounds__(64 * W, (W == 2 && sizeof(T) == 4) ? 4 : 1) void pre_gl_kernel(const ReqDesc* __restrict__ descs,
+__global__ __launch_bounds__(64 * W, (W == 2 && RB == 1 && sizeof(T) == 4) ? 4 : 1) void pre_gl_kernel(const ReqDesc* __restrict__ descs,
                                                         const SegTable segs) {
     constexpr int TP = 16 * RB;
     constexpr int G = (NBW == 1 && W <= 2) ? 2 : 4;   // gl_vec: 2 up to 32 states
@@ -1061,7 +1062,7 @@ __global__ __launch_bounds__(256) void pmat_gl_kernel(const ReqDesc* __restrict_
 }
 
 template <typename T>
-hipError_t launch_gl_t(KernelClass k, int S, const ReqDesc* descs, const SegTable& t, hipStream_t st) {
+hipError_t launch_gl_t(KernelClass k, int S, int rb, const ReqDesc* descs, const SegTable& t, hipStream_t st) {
     const int n_units = t.unit_begin[t.n];
     // up to 128 states: one 16-state block per wave, ceil(S / 16) waves (at
     // 65..128 eight waves of one block beat four of two: fewer registers and
@@ -1071,7 +1072,6 @@ hipError_t launch_gl_t(KernelClass k, int S, const ReqDesc* descs, const SegTabl
     const bool f32 = sizeof(T) == 4;
     const int nbw = S <= 128 ? 1 : (f32 ? (S + 63) / 64 : 2);
     const int w = S <= 128 ? (S + 15) / 16 : (f32 ? 4 : (S + 31) / 32);
-    const int rb = gl_row_blocks(S, sizeof(T) == 4);
 #define PHG_GL_CASE(RBV, NBV, WV)                                                                           \
     if (rb == RBV && nbw == NBV && w == WV) {                                                             \
         if (k == kPost)                                                                                     \
@@ -1087,6 +1087,9 @@ hipError_t launch_gl_t(KernelClass k, int S, const ReqDesc* descs, const SegTabl
         PHG_GL_CASE(2, 1, 4)
         PHG_GL_CASE(2, 3, 4)
         PHG_GL_CASE(2, 4, 4)
+        PHG_GL_CASE(4, 1, 2)
+        PHG_GL_CASE(4, 1, 3)
+        PHG_GL_CASE(4, 1, 4)
     } else {
         PHG_GL_CASE(1, 2, 5)
         PHG_GL_CASE(1, 2, 6)
@@ -1100,9 +1103,22 @@ hipError_t launch_gl_t(KernelClass k, int S, const ReqDesc* descs, const SegTabl
     PHG_GL_CASE(1, 1, 2)
     PHG_GL_CASE(1, 1, 3)
     PHG_GL_CASE(1, 1, 4)
+    PHG_GL_CASE(2, 1, 2)
 #undef PHG_GL_CASE
     return hipErrorInvalidValue;
 }
+
+}  // namespace
+
+bool gl_row_blocks_allowed(int S, bool fp32, int rb) {
+    // the instantiations of launch_gl_t
+    if (S <= 32) return rb == 1 || rb == 2 || (fp32 && rb == 4);
+    if (S <= 64) return rb == 1 || (fp32 && (rb == 2 || rb == 4));
+    if (S <= 128) return rb == 2;
+    return fp32 ? rb == 2 : rb == 1;
+}
+
+namespace {
 
 }  // namespace
 
@@ -1118,8 +1134,9 @@ hipError_t launch_pmat_gl(const ReqDesc& shape, const ReqDesc* descs, const SegT
 
 hipError_t launch_level_gl(KernelClass k, const ReqDesc& shape, const ReqDesc* descs, const SegTable& t,
                            hipStream_t st) {
-    if (shape.fp32) return launch_gl_t<float>(k, shape.S, descs, t, st);
-    return launch_gl_t<double>(k, shape.S, descs, t, st);
+    const int rb = shape.Cpad / shape.tiles / 16;   // the context's own tile
+    if (shape.fp32) return launch_gl_t<float>(k, shape.S, rb, descs, t, st);
+    return launch_gl_t<double>(k, shape.S, rb, descs, t, st);
 }
 
 }  // namespace phg

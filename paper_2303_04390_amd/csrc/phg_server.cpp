@@ -328,14 +328,14 @@ bool launch_step(phg_server* s) {
             it.seg.flags = (l == t->H - 1) ? 1 : 0;
             it.units = units_for(kPost, d, n);
             key = GroupKey{kPost, uses_s4_kernels(d.S, d.R) + 2 * d.blocked, d.fp32,
-                           uses_s4_kernels(d.S, d.R) ? d.R : (d.S + 15) / 16};
+                           uses_s4_kernels(d.S, d.R) ? d.R : (d.S + 15) / 16 + 256 * (d.Cpad / d.tiles)};
         } else if (st <= t->H + t->D) {
             const int l = st - t->H - 1, a = c->pre_lv[l].first, n = c->pre_lv[l].second;
             it.seg.sched_off = a;
             it.seg.n_nodes = n;
             it.units = units_for(kPre, d, n);
             key = GroupKey{kPre, uses_s4_kernels(d.S, d.R) + 2 * d.blocked, d.fp32,
-                           uses_s4_kernels(d.S, d.R) ? d.R : (d.S + 15) / 16};
+                           uses_s4_kernels(d.S, d.R) ? d.R : (d.S + 15) / 16 + 256 * (d.Cpad / d.tiles)};
         } else {
             double* out = ctx_out_dev(c);
             it.seg.out_logl = out;

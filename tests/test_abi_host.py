@@ -324,3 +324,60 @@ def test_noalloc_entry_refuses_oversized_workspace():
         big.close()
     assert B.phg_workspace_size(1000, 10000, 4, 4, B.PHG_FP32_SCALED) > (64 << 20)
     assert prob.n_tips == 1000
+
+
+def test_tuning_table_validation():
+    """phg_set_tuning accepts only values the kernels are built for; the
+    table is read back through phg_get_tuning; value 0 restores the rule."""
+    f32, f64 = B.PHG_FP32_SCALED, B.PHG_FP64
+    RB, NU = B.PHG_TUNE_ROW_BLOCKS, B.PHG_TUNE_NARROW_UNITS
+    try:
+        for S, prec, ok, bad in [(20, f32, (1, 2, 4), (3, 8)), (20, f64, (1, 2), (4,)),
+                                 (61, f32, (1, 2, 4), (3,)), (61, f64, (1,), (2, 4)),
+                                 (122, f32, (2,), (1, 4)), (240, f64, (1,), (2,))]:
+            for v in ok:
+                B.phg_set_tuning(S, 0, prec, RB, v)
+                assert B.phg_get_tuning(S, 4, prec, RB) == v
+            for v in bad:
+                with pytest.raises(B.PhgError) as e:
+                    B.phg_set_tuning(S, 0, prec, RB, v)
+                assert e.value.status == B.PHG_ERR_ARG
+            B.phg_set_tuning(S, 0, prec, RB, 0)
+            assert B.phg_get_tuning(S, 4, prec, RB) == 0
+        with pytest.raises(B.PhgError):
+            B.phg_set_tuning(4, 4, f32, RB, 2)          # 4 states do not take row blocks
+        B.phg_set_tuning(4, 4, f32, NU, 1000)
+        assert B.phg_get_tuning(4, 4, f32, NU) == 1000
+        assert B.phg_get_tuning(4, 2, f32, NU) == 0     # another category count
+        with pytest.raises(B.PhgError):
+            B.phg_set_tuning(4, 4, f64, NU, 1000)
+        # the context's tile follows the row blocks in effect at creation
+        B.phg_set_tuning(20, 0, f32, RB, 4)
+        big = B.phg_workspace_size(100, 1000, 20, 4, f32)
+        B.phg_set_tuning(20, 0, f32, RB, 1)
+        small = B.phg_workspace_size(100, 1000, 20, 4, f32)
+        assert big != small                             # per-tile sums: Cpad / tile of them
+    finally:
+        B.phg_set_tuning(4, 4, f32, NU, 0)
+        B.phg_set_tuning(20, 0, f32, RB, 0)
+
+
+def test_tuning_file_is_read_at_first_use(tmp_path):
+    """libphg.so fills its tuning table from PHG_TUNE_FILE (format: 'gfx950 S R
+    prec param value'); other devices, comments and values the kernels are not
+    built for are skipped; PHG_TUNE=off ignores the file."""
+    import subprocess
+    import sys
+    f = tmp_path / "tune.txt"
+    f.write_text("# comment\ngfx950 20 0 1 0 4\ngfx942 61 0 1 0 4\ngfx950 61 0 0 0 4\ngfx950 4 4 1 1 777\n")
+    code = ("from paper_2303_04390_amd import binding as B;"
+            "print(B.phg_get_tuning(20, 4, 1, 0), B.phg_get_tuning(61, 4, 1, 0), B.phg_get_tuning(61, 4, 0, 0),"
+            " B.phg_get_tuning(4, 4, 1, 1))")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    env = dict(os.environ, PHG_TUNE_FILE=str(f))
+    out = subprocess.run([sys.executable, "-c", code], cwd=root, env=env, capture_output=True, text=True)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.split() == ["4", "0", "0", "777"]
+    env["PHG_TUNE"] = "off"
+    out = subprocess.run([sys.executable, "-c", code], cwd=root, env=env, capture_output=True, text=True)
+    assert out.stdout.split() == ["0", "0", "0", "0"]
