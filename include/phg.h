@@ -225,6 +225,26 @@ phg_status phg_set_tuning(int n_states, int n_categories, phg_precision prec, in
 /* The value in effect (0: the built-in rule). */
 phg_status phg_get_tuning(int n_states, int n_categories, phg_precision prec, int param, int *value);
 
+/* ---- library-owned HIP graphs ----
+ *
+ * phg_gradient and phg_log_likelihood capture their evaluation's kernel
+ * launches (P(t), post-order levels, pre-order levels, final sums) as a HIP
+ * graph on first use and replay it on later calls while the launch sequence
+ * is unchanged: new branch lengths, model, categories, tip states and
+ * pattern weights are uploaded before the replay and leave the graph valid;
+ * a new topology, schedule, general tip partials, per-category eigensystems
+ * switched on or off, or a new device binding drop it (captured again on next
+ * use).  Tuning values read at launch (PHG_TUNE_NARROW_UNITS) are those of
+ * the capture.  Not used while profiling, nor by phg_gradient_async (whose
+ * callers can capture it themselves) or the chain-rule calls. */
+
+/* on = 0 turns graphs off for this context (every call issues its launches);
+ * default on. */
+phg_status phg_set_graphs(phg_context *ctx, int on);
+
+/* Graphs captured and replays issued by this context so far (each nullable). */
+phg_status phg_graph_stats(phg_context *ctx, uint64_t *captures, uint64_t *replays);
+
 /* ---- parameter chain rules: node heights, branch rates, branch sets ----
  *
  * The Methods section's problem statement allows a branch length to be the

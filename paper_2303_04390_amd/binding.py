@@ -92,6 +92,8 @@ _SIGS = {
     "phg_set_fp32_guard": [_vp, _c.c_double],
     "phg_fp32_saturation": [_vp, _dp],
     "phg_last_precision": [_vp, _c.POINTER(_c.c_int)],
+    "phg_set_graphs": [_vp, _c.c_int],
+    "phg_graph_stats": [_vp, _c.POINTER(_c.c_uint64), _c.POINTER(_c.c_uint64)],
     "phg_set_tuning": [_c.c_int, _c.c_int, _c.c_int, _c.c_int, _c.c_int],
     "phg_get_tuning": [_c.c_int, _c.c_int, _c.c_int, _c.c_int, _c.POINTER(_c.c_int)],
 }
@@ -343,6 +345,16 @@ def phg_last_precision(ctx) -> int:
     v = ctypes.c_int()
     _check(lib().phg_last_precision(ctx, ctypes.byref(v)), ctx, "phg_last_precision")
     return v.value
+
+
+def phg_set_graphs(ctx, on: bool):
+    _check(lib().phg_set_graphs(ctx, 1 if on else 0), ctx, "phg_set_graphs")
+
+
+def phg_graph_stats(ctx):
+    a, b = ctypes.c_uint64(), ctypes.c_uint64()
+    _check(lib().phg_graph_stats(ctx, ctypes.byref(a), ctypes.byref(b)), ctx, "phg_graph_stats")
+    return a.value, b.value
 
 
 PHG_TUNE_ROW_BLOCKS = 0

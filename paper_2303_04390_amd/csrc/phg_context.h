@@ -106,6 +106,15 @@ struct phg_context {
     phg::Plan plan{};
     phg::ReqDesc rd{};           // host copy of this request's descriptor
 
+    // library-owned HIP graphs of one whole evaluation (gradient, and
+    // log-likelihood only) for the synchronous calls: captured on first use,
+    // replayed while only device data changes (branch lengths, model, tips,
+    // weights are uploaded before the replay); dropped when the launch
+    // sequence changes (topology, schedule, descriptor, device binding)
+    bool graph_on = true;
+    hipGraphExec_t graph_exec[2] = {nullptr, nullptr};   // [0] gradient, [1] log-likelihood only
+    uint64_t graph_captures = 0, graph_replays = 0;
+
     // profiling: kProfEvents events per recorded evaluation
     bool prof_on = false;
     std::vector<hipEvent_t> prof_pool;
@@ -162,6 +171,9 @@ phg_status from_twin(phg_context* ctx, phg_context* t, phg_status s);
 // since ctx did (recording ctx as its user).
 phg_status scratch_address(phg_context* ctx, void** out);
 bool scratch_claim(const phg_context* ctx);
+// Destroy the context's captured evaluation graphs (they are captured again
+// on next use).
+void ctx_drop_graphs(phg_context* ctx);
 // Forget the device binding (workspace, pinned output) so the context can be
 // bound to new memory later; every input is uploaded again on next use.  The
 // caller guarantees no device work of this context is pending.

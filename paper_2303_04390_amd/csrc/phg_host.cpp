@@ -491,6 +491,8 @@ phg_status upload(phg_context* ctx) {
     char* a = ctx->arena;
     hipStream_t st = ctx->stream;
     const unsigned dirty = ctx->dirty;
+    // a new schedule or descriptor changes the launch sequence
+    if (dirty & (kTopo | kTipVec | kDesc)) ctx_drop_graphs(ctx);
     auto put = [&](size_t off, const void* src, size_t bytes) {
         return hipMemcpyAsync(a + off, src, bytes, hipMemcpyHostToDevice, st);
     };
@@ -607,8 +609,16 @@ phg_status ctx_enqueue_eval(phg_context* ctx, double* d_logl, double* d_grad) {
     return PHG_OK;
 }
 
+void ctx_drop_graphs(phg_context* ctx) {
+    for (hipGraphExec_t& g : ctx->graph_exec) {
+        if (g) (void)hipGraphExecDestroy(g);
+        g = nullptr;
+    }
+}
+
 void ctx_drop_device(phg_context* ctx) {
     if (!ctx->dev_init) return;
+    ctx_drop_graphs(ctx);
     free_tip_vectors(ctx);
     if (ctx->own_arena && ctx->arena) (void)hipFree(ctx->arena);
     if (ctx->host_out) (void)hipHostFree(ctx->host_out);
@@ -736,6 +746,7 @@ phg_context* eval_target(phg_context* ctx, phg_status* st) {
     t->dirty |= kB | kTime | kSets;
     t->have = ctx->have;
     t->prof_on = ctx->prof_on;
+    t->graph_on = ctx->graph_on;
     ctx->sdirty = 0;
     ctx->last_prec = PHG_FP64;
     return t;
@@ -798,6 +809,7 @@ phg_status phg_destroy(phg_context* ctx) {
     if (ctx->dev_init) {
         (void)hipSetDevice(ctx->device);
         if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+        ctx_drop_graphs(ctx);
         for (hipEvent_t ev : ctx->prof_pool) (void)hipEventDestroy(ev);
         free_tip_vectors(ctx);
         if (ctx->own_arena && ctx->arena) (void)hipFree(ctx->arena);
@@ -1010,12 +1022,42 @@ phg_status phg_prepare(phg_context* ctx) {
 namespace {
 // One synchronous evaluation on t (the context itself or its FP64 twin);
 // grad == nullptr asks for the log-likelihood only.
+// The evaluation's launches on t's stream: a replay of the captured graph
+// (captured here on first use) or, with graphs off or while profiling, the
+// launches themselves.  The graph holds kernel launches only.
+phg_status enqueue_graphed(phg_context* t, double* dout, bool with_grad) {
+    if (!t->graph_on || t->prof_on) return ctx_enqueue_eval(t, dout, with_grad ? dout + 1 : nullptr);
+    hipGraphExec_t& ge = t->graph_exec[with_grad ? 0 : 1];
+    if (!ge) {
+        PHG_HIP(t, hipStreamBeginCapture(t->stream, hipStreamCaptureModeThreadLocal));
+        const phg_status s = ctx_enqueue_eval(t, dout, with_grad ? dout + 1 : nullptr);
+        hipGraph_t graph = nullptr;
+        const hipError_t e = hipStreamEndCapture(t->stream, &graph);
+        if (s != PHG_OK) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return s;
+        }
+        if (e != hipSuccess) return t->fail(PHG_ERR_DEVICE, "graph capture failed: %s", hipGetErrorString(e));
+        const hipError_t ei = hipGraphInstantiate(&ge, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (ei != hipSuccess) {
+            ge = nullptr;
+            return t->fail(PHG_ERR_DEVICE, "graph instantiation failed: %s", hipGetErrorString(ei));
+        }
+        t->graph_captures++;
+    } else {
+        t->graph_replays++;
+    }
+    PHG_HIP(t, hipGraphLaunch(ge, t->stream));
+    return PHG_OK;
+}
+
 phg_status eval_sync(phg_context* t, double* logl, double* grad) {
     phg_status s = ctx_ready(t);
     if (s != PHG_OK) return s;
     PHG_TRY(ctx_host_out(t));
     double* dout = ctx_out_dev(t);
-    s = ctx_enqueue_eval(t, dout, grad ? dout + 1 : nullptr);
+    s = enqueue_graphed(t, dout, grad != nullptr);
     if (s != PHG_OK) return s;
     const size_t E = 2 * static_cast<size_t>(t->N) - 2;
     PHG_HIP(t, hipMemcpyAsync(t->host_out, dout, (grad ? E + 1 : 1) * sizeof(double), hipMemcpyDeviceToHost,
@@ -1129,6 +1171,21 @@ phg_status phg_set_tuning(int n_states, int n_categories, phg_precision prec, in
 phg_status phg_get_tuning(int n_states, int n_categories, phg_precision prec, int param, int* value) {
     if (!value || param < 0 || param >= PHG_TUNE_PARAMS) return PHG_ERR_ARG;
     *value = tuned_value(n_states, n_categories, prec == PHG_FP32_SCALED, param);
+    return PHG_OK;
+}
+
+phg_status phg_set_graphs(phg_context* ctx, int on) {
+    if (!ctx) return PHG_ERR_ARG;
+    ctx->graph_on = on != 0;
+    if (ctx->twin) ctx->twin->graph_on = ctx->graph_on;
+    return PHG_OK;
+}
+
+phg_status phg_graph_stats(phg_context* ctx, uint64_t* captures, uint64_t* replays) {
+    if (!ctx) return PHG_ERR_ARG;
+    const phg_context* t = ctx->twin;
+    if (captures) *captures = ctx->graph_captures + (t ? t->graph_captures : 0);
+    if (replays) *replays = ctx->graph_replays + (t ? t->graph_replays : 0);
     return PHG_OK;
 }
 

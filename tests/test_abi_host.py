@@ -381,3 +381,13 @@ def test_tuning_file_is_read_at_first_use(tmp_path):
     env["PHG_TUNE"] = "off"
     out = subprocess.run([sys.executable, "-c", code], cwd=root, env=env, capture_output=True, text=True)
     assert out.stdout.split() == ["0", "0", "0", "0"]
+
+
+def test_graph_calls_on_cpu():
+    ctx = _ctx()
+    try:
+        assert B.phg_graph_stats(ctx) == (0, 0)
+        B.phg_set_graphs(ctx, False)
+        B.phg_set_graphs(ctx, True)
+    finally:
+        B.phg_destroy(ctx)

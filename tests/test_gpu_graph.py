@@ -54,3 +54,45 @@ def test_graph_replay_matches_eager(prec):
             g.replay()
             torch.cuda.synchronize()
             assert np.array_equal(gout.cpu().numpy(), ref2), i
+
+
+@pytest.mark.parametrize("prec", [B.PHG_FP32_SCALED, B.PHG_FP64])
+@pytest.mark.parametrize("which", ["hky1000", "aa500"])
+def test_library_graph_replays_match_launches(prec, which):
+    """phg_gradient / phg_log_likelihood replay the context's own captured
+    graph while only device data changes; every replay equals a graph-free
+    context's launches bit for bit, new branch lengths and a new model flow
+    into the replay, and a new topology makes the context capture again."""
+    kw = dict(n_tips=200, n_patterns=1500) if which == "hky1000" else dict(n_tips=60, n_patterns=300)
+    prob = synth.config_problem(which, seed=4, **kw)
+    E = 2 * prob.n_tips - 2
+    rng = np.random.default_rng(2)
+    print(f"[case] library graph {which} prec={prec}", flush=True)
+    with B.Context.for_problem(prob, prec) as g, B.Context.for_problem(prob, prec) as e:
+        B.phg_set_graphs(e.handle, False)
+        for i in range(5):
+            b = prob.b * np.exp(rng.normal(0.0, 0.1, E))
+            for c in (g, e):
+                B.phg_set_branch_lengths(c.handle, b)
+            lg, gg = g.gradient()
+            le, ge = e.gradient()
+            assert lg == le and np.array_equal(gg, ge), i
+            assert g.log_likelihood() == e.log_likelihood() == lg
+        caps, reps = B.phg_graph_stats(g.handle)
+        assert caps == 2 and reps == 8, (caps, reps)      # one gradient graph, one logL graph
+        assert B.phg_graph_stats(e.handle) == (0, 0)
+        # a new model: device data only, the graph stays
+        pi2 = np.roll(prob.pi, 1)
+        for c in (g, e):
+            B.phg_set_root_frequencies(c.handle, pi2)
+        assert g.gradient()[0] == e.gradient()[0]
+        assert B.phg_graph_stats(g.handle)[0] == 2
+        # a new topology: a new launch sequence, captured again
+        parent2 = synth.yule_topology(prob.n_tips, np.random.default_rng(9))
+        for c in (g, e):
+            B.phg_set_topology(c.handle, parent2)
+            B.phg_set_branch_lengths(c.handle, prob.b)
+        lg, gg = g.gradient()
+        le, ge = e.gradient()
+        assert lg == le and np.array_equal(gg, ge)
+        assert B.phg_graph_stats(g.handle)[0] == 3
