@@ -300,7 +300,7 @@ def state_space_measurement(args, B, synth, stream, out):
     import torch
     import oracle
     res = {}
-    cases = [(w, synth.config_problem(w, seed=args.seed)) for w in ("aa500", "codon128", "s122", "s240")]
+    cases = [(w, synth.config_problem(w, seed=args.seed)) for w in args.states.split(",")]
     for name, prob in cases:
         N, C, S, R = prob.n_tips, prob.n_patterns, prob.n_states, prob.n_categories
         alg_f = algorithmic_flops(N, C, R, S)
@@ -309,6 +309,8 @@ def state_space_measurement(args, B, synth, stream, out):
         sample = prob.subset_patterns(np.arange(min(args.state_sample_patterns, C)))
         ref = oracle.evaluate_problem(sample) if args.state_sample_patterns > 0 else None
         for prec, tag in ((B.PHG_FP32_SCALED, "f32"), (B.PHG_FP64, "f64")):
+            if tag not in args.state_precisions.split(","):
+                continue
             h = B.phg_create(N, C, S, R, prec, 0)
             try:
                 B.phg_bind_stream(h, stream.cuda_stream)
@@ -489,6 +491,11 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-states", action="store_true", help="skip the 20/61/122/240-state measurements")
     ap.add_argument("--state-steps", type=int, default=10)
+    ap.add_argument("--states", default="aa500,codon128,s122,s240",
+                    help="state-space workloads to measure (comma-separated)")
+    ap.add_argument("--state-precisions", default="f32,f64")
+    ap.add_argument("--only-states", action="store_true",
+                    help="measure the state-space workloads only (for profiler runs)")
     ap.add_argument("--state-sample-patterns", type=int, default=200,
                     help="patterns of each state-space workload checked against the oracle (0: none)")
     ap.add_argument("--cpu-workers", type=int, default=16,
@@ -509,6 +516,13 @@ def main():
     from paper_2303_04390_amd import binding as B
     from paper_2303_04390_amd import synth
 
+    if args.only_states:
+        dev = torch.device("cuda:0")
+        torch.cuda.set_device(dev)
+        stream = torch.cuda.Stream(device=dev)
+        out = torch.empty(1 << 16, dtype=torch.float64, device=dev)
+        print(json.dumps({"state_spaces": state_space_measurement(args, B, synth, stream, out)}), flush=True)
+        return
     prob = synth.config_problem("hky1000", seed=args.seed)
     N, C, S, R = prob.n_tips, prob.n_patterns, prob.n_states, prob.n_categories
     E = 2 * N - 2

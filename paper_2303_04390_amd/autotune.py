@@ -70,7 +70,7 @@ def _time_evals(B, prob, prec, steps, warmup, stream, out):
     return ms, logl
 
 
-def tune(workloads, steps=10, warmup=2, log=print):
+def tune(workloads, steps=10, warmup=2, reps=3, log=print):
     """Returns a list of entries {S, R, prec, param, value, ms, candidates}."""
     import torch
     from paper_2303_04390_amd import binding as B
@@ -97,17 +97,22 @@ def tune(workloads, steps=10, warmup=2, log=print):
                 cands = [0] + row_block_candidates(S, fp32)
                 if len(cands) < 3:
                     continue
-            res = {}
+            # candidates timed in interleaved rounds; each keeps its median
+            times = {v: [] for v in cands}
             ref_logl = None
+            for _ in range(reps):
+                for v in cands:
+                    B.phg_set_tuning(S, 0, prec, param, v)
+                    ms, logl = _time_evals(B, prob, prec, steps, warmup, stream, out)
+                    if ref_logl is None:
+                        ref_logl = logl
+                    elif abs(logl - ref_logl) > 1e-6 * abs(ref_logl):
+                        raise RuntimeError(f"{name} prec={prec} value={v}: logL {logl} differs from {ref_logl}")
+                    times[v].append(ms)
+            res = {v: float(np.median(t)) for v, t in times.items()}
             for v in cands:
-                B.phg_set_tuning(S, 0, prec, param, v)
-                ms, logl = _time_evals(B, prob, prec, steps, warmup, stream, out)
-                if ref_logl is None:
-                    ref_logl = logl
-                elif abs(logl - ref_logl) > 1e-6 * abs(ref_logl):
-                    raise RuntimeError(f"{name} prec={prec} value={v}: logL {logl} differs from {ref_logl}")
-                res[v] = ms
-                log(f"[tune] {name} S={S} R={R} {'f32' if fp32 else 'f64'} param={param} value={v}: {ms:.4f} ms")
+                log(f"[tune] {name} S={S} R={R} {'f32' if fp32 else 'f64'} param={param} value={v}: "
+                    f"{res[v]:.4f} ms (median of {reps})")
             B.phg_set_tuning(S, 0, prec, param, 0)
             # keep the built-in rule (the first candidate) unless another
             # value is faster by more than the run-to-run noise
