@@ -14,7 +14,7 @@
  *   - Every non-root node x owns the branch to its parent; branch lengths and
  *     gradients are arrays of length 2N-2 indexed by child node x.
  *   - An unrooted tree is a rooted one with one root branch of length zero.
- *   - S states (2..255), R rate categories (1..64), C site patterns (>= 1).
+ *   - S states (2..256), R rate categories (1..64), C site patterns (>= 1).
  *
  * General rules for every call:
  *   - Every call returns a phg_status; PHG_OK (0) on success, a negative code
@@ -62,7 +62,7 @@ typedef enum {
 typedef struct phg_context phg_context;
 
 /* Create a context for one (tree, alignment) problem of fixed sizes.
- * n_tips >= 2, n_patterns >= 1, 2 <= n_states <= 255, 1 <= n_categories <= 64,
+ * n_tips >= 2, n_patterns >= 1, 2 <= n_states <= 256, 1 <= n_categories <= 64,
  * device = HIP device ordinal.  *out receives the context (NULL on error).
  * Host-only: no device work happens here. */
 phg_status phg_create(int n_tips, int n_patterns, int n_states, int n_categories,
@@ -288,6 +288,22 @@ phg_status phg_time_tree_gradient(phg_context *ctx, double *logl, double *d_heig
 phg_status phg_gradient_branch_sets(phg_context *ctx, double *logl, double *d_sets);
 
 /* ---- device-side variants (memory and streams owned by the caller) ---- */
+
+/* Device memory for the P(t) tables of 17..256 states.  A context keeps
+ * P, dP and their transposes for every (branch, category) when they fit in
+ * `bytes` (default 16 GiB); otherwise it holds a pool of as many branches'
+ * tables as fit (at least 2) and rebuilds them for each launch chunk of at
+ * most pool/2 nodes, just before the post-order or pre-order launch that
+ * reads them (P(t) is then computed twice per evaluation; results are
+ * bitwise those of full tables).  At 256 states, 20,000 branches and 4
+ * categories in FP32 the full tables take 84 GB, the default pool 16 GiB.
+ * Before first use (PHG_ERR_STATE after).  phg_workspace_size assumes the
+ * default; the serving engine keeps full tables. */
+phg_status phg_set_table_budget(phg_context *ctx, size_t bytes);
+
+/* Branch tables the context holds: 0 for every branch's, else the pool size
+ * (what first use will choose, before it). */
+phg_status phg_table_slots(phg_context *ctx, int *slots);
 
 /* Bytes of device workspace a context of these sizes needs. */
 phg_status phg_workspace_size(int n_tips, int n_patterns, int n_states,

@@ -93,6 +93,8 @@ _SIGS = {
     "phg_fp32_saturation": [_vp, _dp],
     "phg_last_precision": [_vp, _c.POINTER(_c.c_int)],
     "phg_set_graphs": [_vp, _c.c_int],
+    "phg_set_table_budget": [_vp, _c.c_size_t],
+    "phg_table_slots": [_vp, _c.POINTER(_c.c_int)],
     "phg_graph_stats": [_vp, _c.POINTER(_c.c_uint64), _c.POINTER(_c.c_uint64)],
     "phg_set_tuning": [_c.c_int, _c.c_int, _c.c_int, _c.c_int, _c.c_int],
     "phg_get_tuning": [_c.c_int, _c.c_int, _c.c_int, _c.c_int, _c.POINTER(_c.c_int)],
@@ -344,6 +346,16 @@ def phg_fp32_saturation(ctx) -> float:
 def phg_last_precision(ctx) -> int:
     v = ctypes.c_int()
     _check(lib().phg_last_precision(ctx, ctypes.byref(v)), ctx, "phg_last_precision")
+    return v.value
+
+
+def phg_set_table_budget(ctx, nbytes: int):
+    _check(lib().phg_set_table_budget(ctx, int(nbytes)), ctx, "phg_set_table_budget")
+
+
+def phg_table_slots(ctx) -> int:
+    v = ctypes.c_int()
+    _check(lib().phg_table_slots(ctx, ctypes.byref(v)), ctx, "phg_table_slots")
     return v.value
 
 

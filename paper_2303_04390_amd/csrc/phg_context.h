@@ -21,7 +21,13 @@ struct Plan {
         pi, pw, sll, lpart, gpart, out, sched, desc, ch_parent, ch_kids, heights, trates, set_ptr, set_idx,
         total;
 };
-Plan make_plan(int N, int C, int S, int R, phg_precision prec);
+// table_slots = 0: P(t) tables for every branch; else a pool of that many
+// (branch) tables, rebuilt per launch chunk (17..255-state kernels only).
+Plan make_plan(int N, int C, int S, int R, phg_precision prec, int table_slots);
+// Table slots a context of these sizes uses under a table-memory budget:
+// 0 (every branch's tables) when they fit, else the pool that fits (>= 2).
+int table_slots_for(int N, int S, int R, phg_precision prec, size_t budget);
+constexpr size_t kDefaultTableBudget = size_t{16} << 30;
 
 enum InputBit : unsigned {
     kTopo = 1u << 0,
@@ -82,6 +88,8 @@ struct phg_context {
     // context holding copies of the same inputs; fp32_guard <= 0 disables.
     double fp32_guard = phg::kDefaultFp32Guard;
     uint64_t uid = 0;            // unique per context of this process
+    size_t table_budget = phg::kDefaultTableBudget;   // bytes of P(t) tables before per-chunk tables
+    int table_slots = 0;         // 0: tables for every branch; else the per-chunk pool (set at device init)
     bool static_ws = false;      // workspace is the static scratch array (phg_gradient_async_noalloc)
     phg_context* twin = nullptr;
     int last_prec = -1;          // precision of the last evaluation issued (-1: none)

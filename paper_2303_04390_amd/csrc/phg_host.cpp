@@ -36,7 +36,22 @@ constexpr size_t kAlign = 256;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 }  // namespace
 
-Plan make_plan(int N, int C, int S, int R, phg_precision prec) {
+namespace {
+size_t gl_table_bytes_per_branch(int S, int R, bool fp32) {
+    return static_cast<size_t>(R) * (2 * gl_mat_rows(S) + 2 * gl_back_rows(S)) * gl_row(S) * (fp32 ? 4 : 8);
+}
+}  // namespace
+
+int table_slots_for(int N, int S, int R, phg_precision prec, size_t budget) {
+    if (!uses_gl_kernels(S, R)) return 0;
+    const size_t E = 2 * static_cast<size_t>(N) - 2;
+    const size_t per = gl_table_bytes_per_branch(S, R, prec == PHG_FP32_SCALED);
+    if (E * per <= budget) return 0;
+    const size_t fit = budget / per;
+    return static_cast<int>(std::max<size_t>(2, std::min(fit, E) & ~size_t{1}));
+}
+
+Plan make_plan(int N, int C, int S, int R, phg_precision prec, int table_slots) {
     const int Cpad = (C + kLanes - 1) / kLanes * kLanes;
     const int tp = tile_patterns(S, R, prec == PHG_FP32_SCALED);
     const int tiles = Cpad / tp;
@@ -51,13 +66,14 @@ Plan make_plan(int N, int C, int S, int R, phg_precision prec) {
         return o;
     };
     const bool fp32 = prec == PHG_FP32_SCALED;
-    p.codes = take(static_cast<size_t>(N) * Cpad);
+    p.codes = take(static_cast<size_t>(N) * Cpad * code_bytes(S));
     p.expo = take(I * Cpad * sizeof(int32_t));
     if (uses_gl_kernels(S, R)) {
         // MFMA operand order: one forward table per matrix and a backward
         // copy of P, in the path's own type only
-        const size_t mat = E * R * gl_mat_rows(S) * gl_row(S);
-        const size_t back = E * R * gl_back_rows(S) * gl_row(S);
+        const size_t T = table_slots > 0 ? static_cast<size_t>(table_slots) : E;   // tables held
+        const size_t mat = T * R * gl_mat_rows(S) * gl_row(S);
+        const size_t back = T * R * gl_back_rows(S) * gl_row(S);
         p.part = take(I * tiles * R * tp * gl_row(S) * tsz);
         p.eloc = take(I * Cpad * sizeof(int32_t));
         p.P64 = take(fp32 ? 0 : mat * 8);
@@ -117,6 +133,17 @@ using namespace phg;
 namespace {
 
 thread_local std::string g_create_error;
+
+// Tip code i (tip-major, Cpad per tip) in the host mirror: a byte, or a
+// little-endian 16-bit value above 255 states.
+void put_code(phg_context* ctx, size_t i, int v) {
+    if (code_bytes(ctx->S) == 1) {
+        ctx->codes[i] = static_cast<uint8_t>(v);
+    } else {
+        ctx->codes[2 * i] = static_cast<uint8_t>(v & 0xff);
+        ctx->codes[2 * i + 1] = static_cast<uint8_t>(v >> 8);
+    }
+}
 
 // ---- tuning table (phg_set_tuning, tuning file)
 struct TuneKey {
@@ -181,8 +208,8 @@ phg_status check_sizes(int n_tips, int n_patterns, int n_states, int n_categorie
     if (n_tips > (1 << 24)) return *why = "n_tips too large", PHG_ERR_ARG;
     if (n_patterns < 1) return *why = "n_patterns must be >= 1", PHG_ERR_ARG;
     if (n_patterns > (1 << 28)) return *why = "n_patterns too large", PHG_ERR_ARG;
-    // codes are bytes and S itself is the ambiguous code
-    if (n_states < 2 || n_states > 255) return *why = "n_states must be in [2, 255]", PHG_ERR_ARG;
+    // S itself is the ambiguous code: bytes up to 255 states, 16 bits above
+    if (n_states < 2 || n_states > 256) return *why = "n_states must be in [2, 256]", PHG_ERR_ARG;
     if (n_categories < 1 || n_categories > 64)
         return *why = "n_categories must be in [1, 64]", PHG_ERR_ARG;
     if (prec != PHG_FP64 && prec != PHG_FP32_SCALED) return *why = "unknown precision", PHG_ERR_ARG;
@@ -315,7 +342,8 @@ phg_status ensure_device(phg_context* ctx) {
     if (!kernels_support(ctx->S, ctx->R))
         return ctx->fail(PHG_ERR_ARG, "no kernel for S=%d, R=%d in this build", ctx->S, ctx->R);
 
-    ctx->plan = make_plan(ctx->N, ctx->C, ctx->S, ctx->R, ctx->prec);
+    ctx->table_slots = table_slots_for(ctx->N, ctx->S, ctx->R, ctx->prec, ctx->table_budget);
+    ctx->plan = make_plan(ctx->N, ctx->C, ctx->S, ctx->R, ctx->prec, ctx->table_slots);
     if (ctx->bound_ws) {
         if (ctx->bound_ws_bytes < ctx->plan.total)
             return ctx->fail(PHG_ERR_OOM, "bound workspace has %zu bytes, %zu needed",
@@ -349,6 +377,7 @@ phg_status ensure_device(phg_context* ctx) {
     d.fp32 = ctx->prec == PHG_FP32_SCALED ? 1 : 0;
     d.blocked = ctx->blocked ? 1 : 0;
     d.eig_cat = ctx->eig_cat ? 1 : 0;
+    d.level_tables = ctx->table_slots > 0 ? 1 : 0;
     d.sched = reinterpret_cast<const NodeTriple*>(a + pl.sched);
     d.codes = reinterpret_cast<const uint8_t*>(a + pl.codes);
     d.part = a + pl.part;
@@ -579,25 +608,40 @@ int tuned_value(int S, int R, bool fp32, int param) {
     return it == g_tune.end() ? 0 : it->second;
 }
 
+// One level's launches: the level kernel over its records [a, a + n), or,
+// with per-chunk P(t) tables, chunks of at most table_slots / 2 nodes, each
+// a P(t) launch building its children's tables and then the level kernel.
+phg_status enqueue_level(phg_context* ctx, KernelClass k, int a, int n, int flags) {
+    hipStream_t st = ctx->stream;
+    const ReqDesc& d = ctx->rd;
+    const ReqDesc* descs = ctx_desc_dev(ctx);
+    const int chunk = ctx->table_slots > 0 ? ctx->table_slots / 2 : n;
+    for (int c0 = 0; c0 < n; c0 += chunk) {
+        const int m = std::min(chunk, n - c0);
+        if (ctx->table_slots > 0)
+            PHG_HIP(ctx, launch_class(kPmat, d, descs, one_segment(d, 2 * m * d.R, a + c0, m, 2, nullptr, nullptr),
+                                      st));
+        PHG_HIP(ctx, launch_class(k, d, descs, one_segment(d, units_for(k, d, m), a + c0, m, flags, nullptr, nullptr),
+                                  st));
+    }
+    return PHG_OK;
+}
+
 phg_status ctx_enqueue_eval(phg_context* ctx, double* d_logl, double* d_grad) {
     hipStream_t st = ctx->stream;
     const ReqDesc& d = ctx->rd;
     const ReqDesc* descs = ctx_desc_dev(ctx);
     PHG_TRY(prof_mark(ctx));
-    PHG_HIP(ctx, launch_class(kPmat, d, descs, one_segment(d, units_for(kPmat, d, 0), 0, 0, 0, nullptr, nullptr), st));
+    if (ctx->table_slots == 0)
+        PHG_HIP(ctx, launch_class(kPmat, d, descs, one_segment(d, units_for(kPmat, d, 0), 0, 0, 0, nullptr, nullptr),
+                                  st));
     PHG_TRY(prof_mark(ctx));
     const int H = static_cast<int>(ctx->post_lv.size());
-    for (int h = 0; h < H; ++h) {
-        const int a = ctx->post_lv[h].first, n = ctx->post_lv[h].second;
-        PHG_HIP(ctx, launch_class(kPost, d, descs,
-                                  one_segment(d, units_for(kPost, d, n), a, n, h == H - 1 ? 1 : 0, nullptr, nullptr), st));
-    }
+    for (int h = 0; h < H; ++h)
+        PHG_TRY(enqueue_level(ctx, kPost, ctx->post_lv[h].first, ctx->post_lv[h].second, h == H - 1 ? 1 : 0));
     PHG_TRY(prof_mark(ctx));
     if (d_grad) {
-        for (const auto& lv : ctx->pre_lv) {
-            const int a = lv.first, n = lv.second;
-            PHG_HIP(ctx, launch_class(kPre, d, descs, one_segment(d, units_for(kPre, d, n), a, n, 0, nullptr, nullptr), st));
-        }
+        for (const auto& lv : ctx->pre_lv) PHG_TRY(enqueue_level(ctx, kPre, lv.first, lv.second, 0));
     }
     PHG_TRY(prof_mark(ctx));
     // without d_grad: log-likelihood only (no pre-order pass; one final unit)
@@ -706,6 +750,7 @@ phg_context* eval_target(phg_context* ctx, phg_status* st) {
             return nullptr;
         }
         ctx->twin = t;
+        t->table_budget = ctx->table_budget;
         ctx->sdirty = ~0u;
         if (ctx->stream && !ctx->own_stream) t->stream = ctx->stream;   // caller's stream
     }
@@ -757,6 +802,22 @@ phg_status from_twin(phg_context* ctx, phg_context* t, phg_status s) {
     return s;
 }
 
+// Kernel launches of one gradient evaluation per profiling class; with
+// per-chunk P(t) tables the P(t) launches run inside the level classes.
+void launches_per_class(phg_context* ctx, int* out) {
+    const int slots = ctx->dev_init ? ctx->table_slots
+                                    : table_slots_for(ctx->N, ctx->S, ctx->R, ctx->prec, ctx->table_budget);
+    auto count = [&](const std::vector<std::pair<int, int>>& lv) {
+        int c = 0;
+        for (const auto& l : lv) c += slots > 0 ? 2 * ((l.second + slots / 2 - 1) / (slots / 2)) : 1;
+        return c;
+    };
+    out[PHG_PROF_PMAT] = slots > 0 ? 0 : 1;
+    out[PHG_PROF_POST] = count(ctx->post_lv);
+    out[PHG_PROF_PRE] = count(ctx->pre_lv);
+    out[PHG_PROF_FINAL] = 1;
+}
+
 }  // namespace phg
 
 extern "C" {
@@ -796,7 +857,8 @@ phg_status phg_create(int n_tips, int n_patterns, int n_states, int n_categories
     ctx->uid = next_uid.fetch_add(1);
     ctx->pw.assign(ctx->Cpad, 0.0);
     std::fill(ctx->pw.begin(), ctx->pw.begin() + n_patterns, 1.0);
-    ctx->codes.assign(static_cast<size_t>(n_tips) * ctx->Cpad, static_cast<uint8_t>(n_states));
+    ctx->codes.assign(static_cast<size_t>(n_tips) * ctx->Cpad * code_bytes(n_states), 0);
+    for (size_t i = 0; i < static_cast<size_t>(n_tips) * ctx->Cpad; ++i) put_code(ctx, i, n_states);
     ctx->have = kPw;
     g_create_error.clear();
     *out = ctx;
@@ -942,10 +1004,9 @@ phg_status phg_set_tip_states(phg_context* ctx, const int32_t* codes) {
         if (codes[i] < 0 || codes[i] > S)
             return ctx->fail(PHG_ERR_ARG, "tip code %d at tip %zu pattern %zu outside [0, %d]", codes[i],
                              i / C, i % C, S);
-    for (int t = 0; t < N; ++t) {
-        uint8_t* row = ctx->codes.data() + static_cast<size_t>(t) * Cpad;
-        for (int c = 0; c < C; ++c) row[c] = static_cast<uint8_t>(codes[static_cast<size_t>(t) * C + c]);
-    }
+    for (int t = 0; t < N; ++t)
+        for (int c = 0; c < C; ++c)
+            put_code(ctx, static_cast<size_t>(t) * Cpad + c, codes[static_cast<size_t>(t) * C + c]);
     ctx->have |= kTips;
     ctx->dirty |= kTips;
     ctx->sdirty |= kTips;
@@ -1103,7 +1164,9 @@ phg_status phg_workspace_size(int n_tips, int n_patterns, int n_states, int n_ca
         g_create_error = why;
         return s;
     }
-    *bytes = make_plan(n_tips, n_patterns, n_states, n_categories, prec).total;
+    *bytes = make_plan(n_tips, n_patterns, n_states, n_categories, prec,
+                       table_slots_for(n_tips, n_states, n_categories, prec, kDefaultTableBudget))
+                 .total;
     return PHG_OK;
 }
 
@@ -1174,6 +1237,21 @@ phg_status phg_get_tuning(int n_states, int n_categories, phg_precision prec, in
     return PHG_OK;
 }
 
+phg_status phg_set_table_budget(phg_context* ctx, size_t bytes) {
+    if (!ctx) return PHG_ERR_ARG;
+    if (ctx->dev_init) return ctx->fail(PHG_ERR_STATE, "the table budget must be set before first use");
+    ctx->table_budget = bytes;
+    if (ctx->twin) ctx->twin->table_budget = bytes;
+    return PHG_OK;
+}
+
+phg_status phg_table_slots(phg_context* ctx, int* slots) {
+    if (!ctx || !slots) return PHG_ERR_ARG;
+    *slots = ctx->dev_init ? ctx->table_slots
+                           : table_slots_for(ctx->N, ctx->S, ctx->R, ctx->prec, ctx->table_budget);
+    return PHG_OK;
+}
+
 phg_status phg_set_graphs(phg_context* ctx, int on) {
     if (!ctx) return PHG_ERR_ARG;
     ctx->graph_on = on != 0;
@@ -1226,7 +1304,11 @@ phg_status phg_schedule_info(phg_context* ctx, int* n_post_levels, int* n_pre_le
     const int D = static_cast<int>(ctx->pre_lv.size());
     if (n_post_levels) *n_post_levels = H;
     if (n_pre_levels) *n_pre_levels = D;
-    if (n_launches) *n_launches = H + D + 2;
+    if (n_launches) {
+        int cls[PHG_PROF_CLASSES];
+        launches_per_class(ctx, cls);
+        *n_launches = cls[0] + cls[1] + cls[2] + cls[3];
+    }
     return PHG_OK;
 }
 
@@ -1261,12 +1343,7 @@ phg_status phg_profile_read(phg_context* ctx, double* ms, int* n_evals, int* lau
     if (ms)
         for (int k = 0; k < PHG_PROF_CLASSES; ++k) ms[k] = tot[k];
     if (n_evals) *n_evals = static_cast<int>(n) + n_twin;
-    if (launches) {
-        launches[PHG_PROF_PMAT] = 1;
-        launches[PHG_PROF_POST] = static_cast<int>(ctx->post_lv.size());
-        launches[PHG_PROF_PRE] = static_cast<int>(ctx->pre_lv.size());
-        launches[PHG_PROF_FINAL] = 1;
-    }
+    if (launches) launches_per_class(ctx, launches);
     ctx->prof_used = 0;
     return PHG_OK;
 }

@@ -59,6 +59,8 @@ struct BlockRec {
 struct ReqDesc {
     int32_t N, C, Cpad, S, S4, R, tiles, fp32;
     int32_t blocked;        // sched holds BlockRec records, else NodeTriple
+    int32_t level_tables;   // 17..255 states: P(t) tables per launch chunk (slot 2 n + c for child c of
+                            // the chunk's node n), built by a P(t) launch over the same records
     int32_t eig_cat;        // 1: V, Vinv [R][S][S] and lam [R][S], one model per category
     const NodeTriple* sched;
     const uint8_t* codes;
@@ -111,7 +113,8 @@ struct Segment {
     int32_t desc;        // index into the descriptor table
     int32_t sched_off;   // first NodeTriple of the level in `sched` (levels only)
     int32_t n_nodes;     // nodes in the level (levels only)
-    int32_t flags;       // bit 0: this post-order level is the root level
+    int32_t flags;       // bit 0: this post-order level is the root level; bit 1 (P(t) of the
+                         // MFMA kernels): tables of the children of records [sched_off, + n_nodes)
     const int32_t* sched;  // the request's schedule records (device), as in its descriptor
     double* out_logl;    // finalize only: where log P(Y) goes
     double* out_grad;    // finalize only: where the 2N-2 derivatives go
@@ -195,6 +198,9 @@ __host__ __device__ constexpr inline int gl_mat_rows(int S) {
 // Rows of one (branch, category) backward table: the gl_mat_rows(S) rows of
 // states, then the row sums (read for tip code S).
 __host__ __device__ constexpr inline int gl_back_rows(int S) { return gl_mat_rows(S) + 1; }
+// Bytes per stored tip code: code S marks a fully ambiguous entry, so 256
+// states need 16 bits (the MFMA kernels read both widths).
+__host__ __device__ constexpr inline int code_bytes(int S) { return S > 255 ? 2 : 1; }
 // Row blocks of 16 patterns per tile: two (each matrix operand then feeds two
 // MFMAs) for FP32 above 32 states and FP64 at 65..128, one otherwise.
 // Measured: above 64 states two win even at one wave per SIMD; four at

@@ -1491,7 +1491,7 @@ hipError_t level_t(KernelClass k, int R, bool blocked, const ReqDesc* descs, con
 // More than 8 categories (any S) run on the MFMA kernels, which take the
 // categories of a (node, tile) one at a time, so R is bounded only by this
 // check.
-bool kernels_support(int S, int R) { return S >= 2 && S <= 255 && R >= 1 && R <= 64; }
+bool kernels_support(int S, int R) { return S >= 2 && S <= 256 && R >= 1 && R <= 64; }
 
 int tile_patterns(int S, int R, bool fp32) {
     if (uses_gl_kernels(S, R)) return 16 * gl_row_blocks(S, R, fp32);

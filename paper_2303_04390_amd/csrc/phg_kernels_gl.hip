@@ -381,19 +381,22 @@ __device__ __forceinline__ void store_cols(GLOBAL T* __restrict__ base, const Ge
 // M[s][y] at column gl_col(s)), and M 1 is the row-sum row that follows the
 // table's gl_mat_rows(S) rows.  out1[c][s] = MB1[y_c][s] (and out2 from MB2)
 // on this wave's columns: a gather from the L2-resident table instead of
-// products on one-hot operands.  codes points at the tip's codes of this tile.
+// products on one-hot operands.  Code c0 + p is pattern p of the tile (bytes,
+// or 16-bit codes above 255 states).
 template <typename T, int RB, int NBW, bool kTwo>
 __device__ __forceinline__ void tip_lookup(const GLOBAL T* __restrict__ MB1, const GLOBAL T* __restrict__ MB2,
-                                           const GLOBAL uint8_t* __restrict__ codes, const Geo& ge, int cb0,
-                                           int lane, Cols<T, RB, NBW>& out1, Cols<T, RB, NBW>& out2) {
+                                           const GLOBAL uint8_t* __restrict__ codes, size_t c0, const Geo& ge,
+                                           int cb0, int lane, Cols<T, RB, NBW>& out1, Cols<T, RB, NBW>& out2) {
     const int gq = lane >> 4, n = lane & 15;
     const int sum_row = gl_mat_rows(ge.S);
+    const bool wide = code_bytes(ge.S) == 2;
     int yo[RB][4];      // row offset of each of this lane's patterns
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            const int y = codes[opat<T>(rb, gq, i)];
+            const size_t c = c0 + opat<T>(rb, gq, i);
+            const int y = wide ? reinterpret_cast<const GLOBAL uint16_t*>(codes)[c] : codes[c];
             yo[rb][i] = (y < ge.S ? y : sum_row) * ge.row;
         }
 #pragma unroll
@@ -539,6 +542,7 @@ struct GlUnit {
     Segment sg;
     NodeTriple nt;
     int tile, tiles;
+    int node_ix;    // the node's place in its segment
 };
 __device__ __forceinline__ bool gl_unit(const ReqDesc* __restrict__ descs, const SegTable& segs, GlUnit& U) {
     const int unit = blockIdx.x;
@@ -550,6 +554,7 @@ __device__ __forceinline__ bool gl_unit(const ReqDesc* __restrict__ descs, const
     const int local = unit - segs.unit_begin[sidx];
     const int node_ix = local / U.tiles;
     U.tile = local - node_ix * U.tiles;
+    U.node_ix = node_ix;
     const I4 t4 = reinterpret_cast<const GLOBAL I4*>(g(U.sg.sched))[U.sg.sched_off + node_ix];
     U.nt = NodeTriple{t4.x, t4.y, t4.z, 0};
     return true;
@@ -591,8 +596,10 @@ __global__ __launch_bounds__(64 * W) void post_gl_kernel(const ReqDesc* __restri
     // inputs: stored partials, or a tip's general partial vector, or (null) its codes
     const GLOBAL T* pi_base = tip_src<T>(d, nt.i, tile, tiles, tstride, part);
     const GLOBAL T* pj_base = tip_src<T>(d, nt.j, tile, tiles, tstride, part);
-    const GLOBAL uint8_t* ci = g(d.codes) + static_cast<size_t>(nt.i) * Cpad + tile * TP;
-    const GLOBAL uint8_t* cj = g(d.codes) + static_cast<size_t>(nt.j) * Cpad + tile * TP;
+    const size_t ci = static_cast<size_t>(nt.i) * Cpad + tile * TP;
+    const size_t cj = static_cast<size_t>(nt.j) * Cpad + tile * TP;
+    // P(t) tables of the children: by branch, or by slot in per-chunk tables
+    const int ti = d.level_tables ? 2 * U.node_ix : nt.i, tj = d.level_tables ? 2 * U.node_ix + 1 : nt.j;
     GLOBAL T* out_base = part + (static_cast<size_t>(nt.k - N) * tiles + tile) * tstride;
     const bool root = U.sg.flags & 1;
     {
@@ -608,20 +615,20 @@ __global__ __launch_bounds__(64 * W) void post_gl_kernel(const ReqDesc* __restri
         __syncthreads();
         Cols<T, RB, NBW> mi, mj, unused;
         if (pi_base) {
-            fwd<T, RB, NBW, G, false>(P + (static_cast<size_t>(nt.i) * R + r) * mstride, nullptr, si, ge, cb0,
+            fwd<T, RB, NBW, G, false>(P + (static_cast<size_t>(ti) * R + r) * mstride, nullptr, si, ge, cb0,
                                       lane, mi, unused);
             if (!tip_i) scale_rows<T, RB, NBW>(mi, esh[0], lane);
         } else {
-            tip_lookup<T, RB, NBW, false>(PB + (static_cast<size_t>(nt.i) * R + r) * bstride, nullptr, ci, ge, cb0,
-                                          lane, mi, unused);
+            tip_lookup<T, RB, NBW, false>(PB + (static_cast<size_t>(ti) * R + r) * bstride, nullptr, g(d.codes), ci,
+                                          ge, cb0, lane, mi, unused);
         }
         if (pj_base) {
-            fwd<T, RB, NBW, G, false>(P + (static_cast<size_t>(nt.j) * R + r) * mstride, nullptr, sj, ge, cb0,
+            fwd<T, RB, NBW, G, false>(P + (static_cast<size_t>(tj) * R + r) * mstride, nullptr, sj, ge, cb0,
                                       lane, mj, unused);
             if (!tip_j) scale_rows<T, RB, NBW>(mj, esh[1], lane);
         } else {
-            tip_lookup<T, RB, NBW, false>(PB + (static_cast<size_t>(nt.j) * R + r) * bstride, nullptr, cj, ge, cb0,
-                                          lane, mj, unused);
+            tip_lookup<T, RB, NBW, false>(PB + (static_cast<size_t>(tj) * R + r) * bstride, nullptr, g(d.codes), cj,
+                                          ge, cb0, lane, mj, unused);
         }
         mul_cols<T, RB, NBW>(mi, mj);
         if (!root) {
@@ -751,8 +758,10 @@ __global__ __launch_bounds__(64 * W, (W == 2 && RB == 1 && sizeof(T) == 4) ? 4 :
     const size_t bstride = static_cast<size_t>(gl_back_rows(S)) * ge.row;   // one backward table
     const bool is_root = nt.k == 2 * N - 2;
     const bool tip_i = nt.i < N, tip_j = nt.j < N;
-    const GLOBAL uint8_t* ci = g(d.codes) + static_cast<size_t>(nt.i) * Cpad + tile * TP;
-    const GLOBAL uint8_t* cj = g(d.codes) + static_cast<size_t>(nt.j) * Cpad + tile * TP;
+    const size_t ci = static_cast<size_t>(nt.i) * Cpad + tile * TP;
+    const size_t cj = static_cast<size_t>(nt.j) * Cpad + tile * TP;
+    // P(t) tables of the children: by branch, or by slot in per-chunk tables
+    const int ti = d.level_tables ? 2 * U.node_ix : nt.i, tj = d.level_tables ? 2 * U.node_ix + 1 : nt.j;
     Input<T, RB> si{nullptr, nullptr}, sj{nullptr, nullptr};
     GLOBAL T* pi_base = tip_i ? nullptr : part + (static_cast<size_t>(nt.i - N) * tiles + tile) * tstride;
     GLOBAL T* pj_base = tip_j ? nullptr : part + (static_cast<size_t>(nt.j - N) * tiles + tile) * tstride;
@@ -777,10 +786,10 @@ __global__ __launch_bounds__(64 * W, (W == 2 && RB == 1 && sizeof(T) == 4) ? 4 :
             if (!is_root) stage_vec<T, TP, KIT>(vb[kStage ? 2 : 0], qk_base + r * rstride, ge);
             __syncthreads();  // inputs of category r staged
         }
-        const size_t mo_i = (static_cast<size_t>(nt.i) * R + r) * mstride;
-        const size_t mo_j = (static_cast<size_t>(nt.j) * R + r) * mstride;
-        const size_t bo_i = (static_cast<size_t>(nt.i) * R + r) * bstride;
-        const size_t bo_j = (static_cast<size_t>(nt.j) * R + r) * bstride;
+        const size_t mo_i = (static_cast<size_t>(ti) * R + r) * mstride;
+        const size_t mo_j = (static_cast<size_t>(tj) * R + r) * mstride;
+        const size_t bo_i = (static_cast<size_t>(ti) * R + r) * bstride;
+        const size_t bo_j = (static_cast<size_t>(tj) * R + r) * bstride;
         const T wr = static_cast<T>(g(d.cweights)[r]);
         Cols<T, RB, NBW> qk, a, b, acc, dmj;
         if (is_root) {
@@ -805,7 +814,7 @@ __global__ __launch_bounds__(64 * W, (W == 2 && RB == 1 && sizeof(T) == 4) ? 4 :
                 scale_rows<T, RB, NBW>(dmj, esh[1], lane);
             }
         } else {
-            tip_lookup<T, RB, NBW, true>(PB + bo_j, dPB + bo_j, cj, ge, cb0, lane, a, dmj);
+            tip_lookup<T, RB, NBW, true>(PB + bo_j, dPB + bo_j, g(d.codes), cj, ge, cb0, lane, a, dmj);
         }
         mul_cols<T, RB, NBW>(a, qk);                                           // a = u_i
         if (pi_src) {
@@ -815,7 +824,7 @@ __global__ __launch_bounds__(64 * W, (W == 2 && RB == 1 && sizeof(T) == 4) ? 4 :
                 scale_rows<T, RB, NBW>(acc, esh[0], lane);
             }
         } else {
-            tip_lookup<T, RB, NBW, true>(PB + bo_i, dPB + bo_i, ci, ge, cb0, lane, b, acc);
+            tip_lookup<T, RB, NBW, true>(PB + bo_i, dPB + bo_i, g(d.codes), ci, ge, cb0, lane, b, acc);
         }
         T dd[RB][4] = {}, ni[RB][4] = {}, nj[RB][4] = {};
         dot_cols<T, RB, NBW>(a, b, dd);                                        // u_i . m_i
@@ -960,14 +969,20 @@ __global__ __launch_bounds__(256) void pmat_gl_kernel(const ReqDesc* __restrict_
     const int unit = blockIdx.x;
     if (unit >= segs.unit_begin[segs.n]) return;
     const int sidx = seg_of(segs, unit);
-    const ReqDesc& d = descs[segs.seg[sidx].desc];
-    const int pair = unit - segs.unit_begin[sidx];
+    const Segment& sg = segs.seg[sidx];
+    const ReqDesc& d = descs[sg.desc];
+    const int pair = unit - segs.unit_begin[sidx];   // table (branch or slot) * R + category
     const int R = d.R, S = d.S;
     const int nt = pmat_gl_tiles(S);
     if (static_cast<int>(blockIdx.y) >= nt * nt) return;  // whole workgroup: smaller S in a shared launch
     const int ts = blockIdx.y / nt, tt = blockIdx.y - ts * nt;
-    const int x = pair / R;
-    const int r = pair - x * R;
+    const int slot = pair / R;
+    const int r = pair - slot * R;
+    int x = slot;                                    // the branch: its own table
+    if (sg.flags & 2) {                              // per-chunk tables: child (slot & 1) of record slot / 2
+        const I4 t4 = reinterpret_cast<const GLOBAL I4*>(g(sg.sched))[sg.sched_off + slot / 2];
+        x = (slot & 1) ? t4.z : t4.y;
+    }
     const double gr = d.rates[r];
     const double bt = gr * d.b[x];
     const double* lam = d.lam + (d.eig_cat ? r * S : 0);

@@ -600,6 +600,7 @@ phg_status phg_server_register_tree(phg_server* s, const phg_tree_desc* d, uint6
     }
     const size_t E = 2 * static_cast<size_t>(d->n_tips) - 2;
     std::vector<double> b0(E, 0.0);
+    ctx->table_budget = static_cast<size_t>(-1);   // one P(t) stage per request: every branch's tables
     if (st == PHG_OK) st = phg_set_topology(ctx, d->parent);
     if (st == PHG_OK) st = phg_set_eigen(ctx, d->V, d->Vinv, d->lambda);
     if (st == PHG_OK) st = phg_set_root_frequencies(ctx, d->pi);
@@ -616,7 +617,8 @@ phg_status phg_server_register_tree(phg_server* s, const phg_tree_desc* d, uint6
     }
     auto t = std::make_unique<Tree>();
     t->ctx = ctx;
-    t->bytes = make_plan(d->n_tips, d->n_patterns, d->n_states, d->n_categories, d->prec).total;
+    // served trees keep every branch's P(t) tables (one P(t) stage per request)
+    t->bytes = make_plan(d->n_tips, d->n_patterns, d->n_states, d->n_categories, d->prec, 0).total;
     if (t->bytes > s->budget) {
         phg_destroy(ctx);
         return s->fail(PHG_ERR_OOM, "tree workspace exceeds the server memory budget");

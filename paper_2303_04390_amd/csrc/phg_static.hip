@@ -63,7 +63,10 @@ extern "C" phg_status phg_gradient_async_noalloc(phg_context* ctx, double* d_log
     if (!d_logl || !d_grad) return ctx->fail(PHG_ERR_ARG, "NULL device output pointer");
     if (!ctx->tip_vectors.empty())
         return ctx->fail(PHG_ERR_ARG, "general tip partials need memory of their own; not available here");
-    const size_t need = make_plan(ctx->N, ctx->C, ctx->S, ctx->R, ctx->prec).total;
+    const size_t need =
+        make_plan(ctx->N, ctx->C, ctx->S, ctx->R, ctx->prec,
+                  table_slots_for(ctx->N, ctx->S, ctx->R, ctx->prec, ctx->table_budget))
+            .total;
     if (need > PHG_NOALLOC_SCRATCH_BYTES)
         return ctx->fail(PHG_ERR_OOM, "workspace of %zu bytes exceeds the %zu-byte static scratch array", need,
                          static_cast<size_t>(PHG_NOALLOC_SCRATCH_BYTES));

@@ -454,6 +454,10 @@ def config_problem(which: str, seed: int = 0, n_patterns: Optional[int] = None,
                 size of a Markov-modulated codon model).
     "s240":     as "s122" with 240 states and 1000 patterns (near the
                 256-state models the paper's Discussion names).
+    "s256big":  10,000 taxa, b~Exp(0.05), 256-state GTR as "s122", Gamma4
+                a=0.5, 256 patterns of uniformly drawn tip states (not
+                simulated: a throughput shape for 20,000 branches at 256
+                states, where simulating down the tree would take minutes).
     ``n_patterns``/``n_tips`` override the sizes (smaller parity cases).
     """
     rng = np.random.default_rng(seed)
@@ -505,6 +509,18 @@ def config_problem(which: str, seed: int = 0, n_patterns: Optional[int] = None,
         Q = gtr_model(rng.gamma(1.0, 1.0, S * (S - 1) // 2), pi)
         rates, w = discrete_gamma(0.5, 4)
         return make_problem(parent, b, Q, pi, rates, w, C, rng, name=which)
+    if which == "s256big":
+        S = 256
+        N, C = n_tips or 10000, n_patterns or 256
+        parent = yule_topology(N, rng)
+        b = exponential_branch_lengths(N, 0.05, rng)
+        pi = rng.dirichlet([2.0] * S)
+        Q = gtr_model(rng.gamma(1.0, 1.0, S * (S - 1) // 2), pi)
+        rates, w = discrete_gamma(0.5, 4)
+        V, Vinv, lam = eigensystem(Q, pi)
+        return Problem(parent=parent, b=b, V=V, Vinv=Vinv, lam=lam, pi=pi, rates=rates, weights=w,
+                       codes=rng.integers(0, S, (N, C)).astype(np.int32), pattern_weights=np.ones(C),
+                       Q=Q, name=which)
     raise ValueError(f"unknown config {which!r}")
 
 

@@ -4,6 +4,9 @@ import sys
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+# tests run the built-in tile rules, not the tuning file beside the library
+# (tuned values change speed only; tests that read a tuning file set their own)
+os.environ.setdefault("PHG_TUNE", "off")
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 

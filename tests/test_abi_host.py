@@ -34,7 +34,7 @@ def test_create_validates_sizes():
     with pytest.raises(B.PhgError) as e:
         B.phg_create(1, 10, 4, 4, B.PHG_FP64)
     assert e.value.status == B.PHG_ERR_ARG
-    for args in [(10, 0, 4, 4, 0), (10, 10, 1, 4, 0), (10, 10, 256, 4, 0), (10, 10, 4, 0, 0),
+    for args in [(10, 0, 4, 4, 0), (10, 10, 1, 4, 0), (10, 10, 257, 4, 0), (10, 10, 4, 0, 0),
                  (10, 10, 4, 65, 0), (10, 10, 4, 4, 7)]:
         with pytest.raises(B.PhgError) as e:
             B.phg_create(*args)
@@ -375,6 +375,7 @@ def test_tuning_file_is_read_at_first_use(tmp_path):
             " B.phg_get_tuning(4, 4, 1, 1))")
     root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
     env = dict(os.environ, PHG_TUNE_FILE=str(f))
+    env.pop("PHG_TUNE", None)
     out = subprocess.run([sys.executable, "-c", code], cwd=root, env=env, capture_output=True, text=True)
     assert out.returncode == 0, out.stderr
     assert out.stdout.split() == ["4", "0", "0", "777"]

@@ -140,11 +140,64 @@ def test_generic_repeatable_and_async(codon128):
 
 
 @pytest.mark.parametrize("S,N,C,R", [(65, 10, 37, 2), (122, 12, 40, 4), (128, 8, 16, 1), (129, 8, 33, 3),
-                                     (200, 6, 20, 2), (255, 6, 17, 2)])
+                                     (200, 6, 20, 2), (255, 6, 17, 2), (256, 7, 23, 2), (256, 12, 40, 4)])
 def test_large_state_spaces(S, N, C, R):
-    """65..255 states (Markov-modulated and phylogeographic state spaces) on
-    the large-state MFMA kernels, ragged 16-pattern tiles."""
+    """65..256 states (Markov-modulated and phylogeographic state spaces) on
+    the large-state MFMA kernels, ragged 16-pattern tiles; 256 states take
+    16-bit tip codes (code 256 = fully ambiguous)."""
     prob = generic_problem(N, S, C, seed=S + C, R=R, mean_b=0.05)
     ref = oracle.evaluate_problem(prob)
     for prec in (B.PHG_FP64, B.PHG_FP32_SCALED):
         compare(f"S{S}-N{N}-C{C}-R{R}", prob, prec, ref)
+
+
+@pytest.mark.parametrize("which", ["s122", "s240"])
+def test_bench_shapes_large_states(which):
+    """The 128-taxon 122- and 240-state workloads of the benchmark, at their
+    full size (2000 and 1000 patterns), both precisions."""
+    prob = synth.config_problem(which, seed=0)
+    ref = oracle.evaluate_problem(prob)
+    for prec in (B.PHG_FP64, B.PHG_FP32_SCALED):
+        compare(which, prob, prec, ref)
+
+
+def _gl_table_bytes_per_branch(S, R, prec):
+    """P, dP (gl_mat_rows rows) and their backward copies (one more row) for
+    one branch: the unit the table budget is counted in."""
+    G = 2 if S <= 32 else 4
+    row = 4 * (((S + 3) // 4 + G - 1) // G * G)
+    rows = (S + 15) // 16 * 16 if S <= 64 else (S + 63) // 64 * 64
+    return R * (2 * rows + 2 * (rows + 1)) * row * (4 if prec == B.PHG_FP32_SCALED else 8)
+
+
+@pytest.mark.parametrize("S,N,C", [(20, 30, 70), (61, 12, 40), (256, 10, 20)])
+def test_per_chunk_tables_match_full_tables(S, N, C):
+    """Under a small table budget the context holds a pool of branch tables
+    and rebuilds them per launch chunk; its results are bitwise those of the
+    full tables, and both meet the oracle bar."""
+    prob = generic_problem(N, S, C, seed=S + 7, R=2, mean_b=0.05)
+    ref = oracle.evaluate_problem(prob)
+    for prec in (B.PHG_FP64, B.PHG_FP32_SCALED):
+        print(f"[case] per-chunk tables S={S} N={N} C={C} {NAME[prec]}", flush=True)
+        with B.Context.for_problem(prob, prec) as full:
+            assert B.phg_table_slots(full.handle) == 0
+            lf, gf = full.gradient()
+        check(f"S{S}-full/{NAME[prec]}", lf, gf, ref, *TOL[prec])
+        per = _gl_table_bytes_per_branch(S, prob.n_categories, prec)
+        for budget, slots in ((1, 2), (7 * per, 6)):
+            ctx = B.Context(prob.n_tips, prob.n_patterns, S, prob.n_categories, prec)
+            try:
+                B.phg_set_table_budget(ctx.handle, budget)
+                ctx.set_problem(prob)
+                assert B.phg_table_slots(ctx.handle) == slots
+                lc, gc = ctx.gradient()
+                assert B.phg_table_slots(ctx.handle) == slots
+                assert ctx.log_likelihood() == lc
+                n_post, n_pre, launches = B.phg_schedule_info(ctx.handle)
+            finally:
+                ctx.close()
+            assert lc == lf and np.array_equal(gc, gf), (budget, np.max(np.abs(gc - gf)))
+            # a P(t) launch before every chunk of every level
+            assert launches > n_post + n_pre + 2
+            if slots == 2:
+                assert launches == 4 * (N - 1) + 1
