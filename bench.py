@@ -135,115 +135,159 @@ def node_depths(parent):
     return depth
 
 
+def _yule_parents(args):
+    """Worker: fresh Yule topologies for (n_tips, seed) pairs."""
+    from paper_2303_04390_amd import synth
+    return [synth.yule_topology(int(n), np.random.default_rng(int(sd))) for n, sd in args]
+
+
 def serving_measurement(args, B, synth):
     """Poisson stream of likelihood+gradient requests through the server.
 
-    Trees: Yule, taxa ~ round(LogUniform[64, 4096]), patterns ~ round(LogUniform[
-    500, 20000]), HKY+Gamma4 drawn as in the 1000-taxon workload, FP32 with
-    rescaling.  A pool of distinct synthetic trees stands in for the stream's
-    new trees: a "new tree" request registers a pool tree under a fresh id (so
-    it is uploaded and made resident like an unseen tree); a "step" request
-    (probability 1/2) perturbs a registered tree's branch lengths by
-    exp(N(0, 0.05)), as an HMC step does.  The 32 most recently registered trees
-    stay registered.  Latency = results in host memory minus submission, on the
-    server's clock; submission happens at the scheduled arrival time.
+    Requests arrive at args.serving_rate per second for args.serving_seconds.
+    Half are branch-length perturbations b * exp(N(0, 0.05)) of a registered
+    tree (an HMC step); the other half bring a new tree: a freshly drawn Yule
+    topology with taxa ~ round(LogUniform[64, 4096]), branch lengths ~
+    Exp(0.01), HKY+Gamma4 drawn as in the 1000-taxon workload (kappa ~
+    U[1,5], alpha ~ U[0.2,2], pi ~ Dir(10^4)), and patterns ~
+    round(LogUniform[500, 20000]) whose tip states are a block of one
+    alignment simulated beforehand on a 4096-taxon tree (not re-simulated
+    per tree, which would take seconds each).  A new tree is registered when
+    its request arrives, by a pool of host threads, so registration (host
+    copy and validation) is inside that request's latency; its upload and
+    first evaluation follow on the GPU.  The 32 most recently registered
+    trees stay registered.  Latency = results in host memory minus arrival.
+    Also reported: the GPU-busy fraction (serving kernels' device time over
+    the stream's wall time).
     """
     import math
-    import threading
+    import multiprocessing as mp
+    from concurrent.futures import ThreadPoolExecutor
     rng = np.random.default_rng(args.seed + 1000)
-    pool = []
     t0 = time.perf_counter()
-    for k in range(args.serving_pool):
-        N = int(round(math.exp(rng.uniform(math.log(64), math.log(4096)))))
-        C = int(round(math.exp(rng.uniform(math.log(500), math.log(20000)))))
-        pool.append(synth.config_problem("hky1000", seed=int(rng.integers(1 << 30)), n_tips=N, n_patterns=C))
-    gen_s = time.perf_counter() - t0
     n_req = int(args.serving_rate * args.serving_seconds)
     arrivals = np.cumsum(rng.exponential(1.0 / args.serving_rate, n_req))
-    kinds = rng.random(n_req) < 0.5          # True: perturb a registered tree
-    picks = rng.integers(0, 1 << 30, n_req)
-    noise_seed = int(rng.integers(1 << 30))
+    is_step = rng.random(n_req) < 0.5
+    is_step[0] = False
+    new_idx = np.nonzero(~is_step)[0]
+    n_new = len(new_idx)
+    sizes_N = np.round(np.exp(rng.uniform(math.log(64), math.log(4096), n_new))).astype(int)
+    sizes_C = np.round(np.exp(rng.uniform(math.log(500), math.log(20000), n_new))).astype(int)
+    seeds = rng.integers(0, 1 << 30, n_new)
+    # fresh topologies, drawn in worker processes
+    jobs = [list(zip(sizes_N[k::args.cpu_workers], seeds[k::args.cpu_workers])) for k in range(args.cpu_workers)]
+    with mp.get_context("spawn").Pool(args.cpu_workers) as pool:
+        parts = pool.map(_yule_parents, jobs)
+    parents = [None] * n_new
+    for k in range(args.cpu_workers):
+        parents[k::args.cpu_workers] = parts[k]
+    base = synth.config_problem("hky1000", seed=args.seed + 77, n_tips=4096, n_patterns=20000)
+    gen_s = time.perf_counter() - t0
+
+    def new_problem(k):
+        r = np.random.default_rng(int(seeds[k]) + 1)
+        N, C = int(sizes_N[k]), int(sizes_C[k])
+        pi = r.dirichlet([10.0] * 4)
+        Q = synth.hky_model(r.uniform(1.0, 5.0), pi)
+        rates, w = synth.discrete_gamma(r.uniform(0.2, 2.0), 4)
+        V, Vinv, lam = synth.eigensystem(Q, pi)
+        r0 = int(r.integers(0, 4096 - N + 1))
+        c0 = int(r.integers(0, 20000 - C + 1))
+        return synth.Problem(parent=parents[k], b=r.exponential(0.01, 2 * N - 2), V=V, Vinv=Vinv, lam=lam,
+                             pi=pi, rates=rates, weights=w, codes=base.codes[r0:r0 + N, c0:c0 + C],
+                             pattern_weights=np.ones(C), Q=Q)
+
     budget = 96 << 30
     srv = B.phg_server_create(0, budget, 32)
-    window = []                              # (tree id, pool index), most recent last
-    submitted = []                           # (req id, n_branches)
-    lag = []
-    from concurrent.futures import ThreadPoolExecutor
-    regs = ThreadPoolExecutor(max_workers=4)
-    new_idx = [i for i in range(n_req) if not kinds[i]]
+    regs = ThreadPoolExecutor(max_workers=8)
+    window = []                 # (tree id, b, n_branches), most recent last
+    submitted = []              # (req id, n_branches, kind, host seconds from arrival to submit)
     futs = {}
-    ahead = 48
+    reg_s = []
 
-    def prefetch(upto):
-        # tree data is prepared (registered) before its request arrives
-        while prefetch.next < len(new_idx) and prefetch.next < upto:
-            i = new_idx[prefetch.next]
-            pk = int(picks[i] % len(pool))
-            futs[i] = regs.submit(B.phg_server_register_tree, srv, pool[pk], B.PHG_FP32_SCALED)
-            prefetch.next += 1
-    prefetch.next = 0
+    def register(k, i):
+        # on a host thread at the request's arrival: build, register, submit
+        prob = new_problem(k)
+        ta = time.perf_counter()
+        tid = B.phg_server_register_tree(srv, prob, B.PHG_FP32_SCALED)
+        rs = time.perf_counter() - ta
+        rid = B.phg_server_submit(srv, tid, prob.b)
+        return tid, prob.b, 2 * prob.n_tips - 2, rid, rs, time.perf_counter() - start - arrivals[i]
+
+    nrng = np.random.default_rng(args.seed + 5)
     try:
-        nrng = np.random.default_rng(noise_seed)
-        prefetch(ahead)
-        for f in list(futs.values())[:8]:
-            f.result()
+        busy0, wall0 = B.phg_server_busy(srv)
         start = time.perf_counter()
-        n_new = 0
+        knew = 0
         for i in range(n_req):
             while True:
                 dt = arrivals[i] - (time.perf_counter() - start)
                 if dt <= 0:
                     break
                 time.sleep(min(dt, 0.0005))
-            if kinds[i] and window:
-                tid, pk = window[int(picks[i] % len(window))]
-                b = pool[pk].b * np.exp(nrng.normal(0.0, 0.05, pool[pk].b.shape))
+            # new trees whose registration and submission finished join the window
+            for j in sorted(futs):
+                if futs[j].done():
+                    tid, b, E, rid, rs, pre_s = futs.pop(j).result()
+                    reg_s.append(rs)
+                    submitted.append((rid, E, "new", pre_s))
+                    window.append((tid, b, E))
+                    if len(window) > 32:
+                        B.phg_server_release_tree(srv, window.pop(0)[0])
+            if is_step[i] and not window:
+                # no tree registered yet: wait for the first one
+                j = min(futs)
+                tid, b, E, rid, rs, pre_s = futs.pop(j).result()
+                reg_s.append(rs)
+                submitted.append((rid, E, "new", pre_s))
+                window.append((tid, b, E))
+            if is_step[i]:
+                tid, b, E = window[int(nrng.integers(len(window)))]
+                b2 = b * np.exp(nrng.normal(0.0, 0.05, E))
+                rid = B.phg_server_submit(srv, tid, b2)
+                submitted.append((rid, E, "step", time.perf_counter() - start - arrivals[i]))
             else:
-                if i not in futs:                    # a "step" before any tree exists
-                    pk = int(picks[i] % len(pool))
-                    tid = B.phg_server_register_tree(srv, pool[pk], B.PHG_FP32_SCALED)
-                else:
-                    pk = int(picks[i] % len(pool))
-                    tid = futs.pop(i).result()
-                    n_new += 1
-                    prefetch(n_new + ahead)
-                window.append((tid, pk))
-                if len(window) > 32:
-                    B.phg_server_release_tree(srv, window.pop(0)[0])
-                b = pool[pk].b
-            rid = B.phg_server_submit(srv, tid, b)
-            lag.append(time.perf_counter() - start - arrivals[i])
-            submitted.append((rid, 2 * pool[pk].n_tips - 2))
-        lat = []
-        t_first, t_last = None, None
-        for rid, E in submitted:
+                futs[i] = regs.submit(register, knew, i)
+                knew += 1
+        for j in sorted(futs):
+            tid, b, E, rid, rs, pre_s = futs[j].result()
+            reg_s.append(rs)
+            submitted.append((rid, E, "new", pre_s))
+        lat = {"step": [], "new": []}
+        t_last = None
+        for rid, E, kind, pre_s in submitted:
             while True:
                 done, logl, grad, ts, td = B.phg_server_poll_timed(srv, rid, E)
                 if done:
                     break
                 time.sleep(0.0002)
-            lat.append((td - ts) * 1e-6)
-            t_first = ts if t_first is None else min(t_first, ts)
-            t_last = td if t_last is None else max(t_last, td)
+            lat[kind].append(pre_s * 1e3 + (td - ts) * 1e-6)
+        span = time.perf_counter() - start
+        busy1, wall1 = B.phg_server_busy(srv)
         stats = B.phg_server_stats(srv)
     finally:
         regs.shutdown(wait=True)
         B.phg_server_destroy(srv)
-    lat = np.array(lat)
-    span = (t_last - t_first) * 1e-9
+    allv = np.array(lat["step"] + lat["new"])
+
+    def pct(v):
+        v = np.asarray(v)
+        return {"p50": round(float(np.percentile(v, 50)), 3), "p99": round(float(np.percentile(v, 99)), 3),
+                "max": round(float(v.max()), 3), "requests": int(v.size)}
+
     return {
-        "workload": "Poisson arrivals; Yule trees, taxa LogUniform[64,4096], patterns LogUniform[500,20000], "
-                    "HKY+Gamma4, FP32 + rescaling; half new trees, half branch-length perturbations "
-                    "x exp(N(0,0.05)) of registered trees",
-        "rate_req_per_s": args.serving_rate, "requests": n_req, "pool_trees": len(pool),
-        "pool_mean_taxa_x_patterns": float(np.mean([p.n_tips * p.n_patterns for p in pool])),
-        "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3),
-                       "p99": round(float(np.percentile(lat, 99)), 3),
-                       "max": round(float(lat.max()), 3)},
+        "workload": "Poisson arrivals; half branch-length perturbations x exp(N(0,0.05)) of registered trees, "
+                    "half new trees (fresh Yule topology, taxa LogUniform[64,4096], b~Exp(0.01), HKY+Gamma4 "
+                    "as the 1000-taxon workload, patterns LogUniform[500,20000] from a pre-simulated "
+                    "alignment), FP32 + rescaling, registration inside the latency window",
+        "rate_req_per_s": args.serving_rate, "seconds": args.serving_seconds, "requests": n_req,
+        "new_trees": int(n_new), "mean_taxa_x_patterns_new": float(np.mean(sizes_N * sizes_C)),
+        "latency_ms": pct(allv), "latency_ms_steps": pct(lat["step"]), "latency_ms_new_trees": pct(lat["new"]),
+        "registration_ms": pct(np.array(reg_s) * 1e3),
         "throughput_req_per_s": round(n_req / span, 1),
-        "submit_lag_ms_p99": round(float(np.percentile(lag, 99)) * 1e3, 3),
+        "gpu_busy_fraction": round((busy1 - busy0) / max(wall1 - wall0, 1), 4),
         "server_stats": stats, "slots": 32, "budget_bytes": budget,
-        "pool_generation_s": round(gen_s, 1),
+        "generation_s": round(gen_s, 1),
     }
 
 
@@ -490,11 +534,9 @@ def main():
                     help="traversal schedule of the 4-state path (default: blocks where supported)")
     ap.add_argument("--quick", action="store_true",
                     help="throughput and kernel-class times only (for profiler runs)")
-    ap.add_argument("--serving-seconds", type=float, default=8.0,
+    ap.add_argument("--serving-seconds", type=float, default=60.0,
                     help="length of the Poisson request stream for the serving measurement")
     ap.add_argument("--serving-rate", type=float, default=500.0, help="mean arrivals per second")
-    ap.add_argument("--serving-pool", type=int, default=12,
-                    help="distinct synthetic trees the stream draws from")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-states", action="store_true", help="skip the 20/61/122/240-state measurements")
     ap.add_argument("--state-steps", type=int, default=10)

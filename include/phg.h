@@ -397,6 +397,16 @@ typedef struct {
     const double *rates, *weights;
     const int32_t *codes;
     const double *pattern_weights;
+    /* Optional, zero / NULL when unused (the gradient-kernel section's
+     * general form): per_category_eigen != 0 means V, Vinv hold R models
+     * (R*S*S each) and lambda R*S, as phg_set_category_eigen; n_tip_vectors
+     * tips (ids in tip_vector_tips) take general partial vectors, C*S each,
+     * concatenated in tip_vectors, as phg_set_tip_partials (their device copy
+     * lives outside the memory budget). */
+    int per_category_eigen;
+    int n_tip_vectors;
+    const int32_t *tip_vector_tips;
+    const double *tip_vectors;
 } phg_tree_desc;
 
 /* max_slots in [1, 48] concurrent evaluations; mem_budget_bytes of device
@@ -435,6 +445,13 @@ phg_status phg_server_wait(phg_server *srv, uint64_t req_id, double *logl, doubl
 /* Forget a tree: its device memory is released once no request for it is
  * queued or in flight.  Requests submitted afterwards fail with PHG_ERR_ARG. */
 phg_status phg_server_release_tree(phg_server *srv, uint64_t tree_id);
+
+/* Kernel time and wall time since the server's creation, in nanoseconds:
+ * *busy_ns sums, over scheduler steps, the device time from the step's first
+ * launch to its last (HIP events on the compute stream), so busy / wall is
+ * the fraction of time the GPU spent on serving kernels.  Either pointer may
+ * be NULL. */
+phg_status phg_server_busy(phg_server *srv, uint64_t *busy_ns, uint64_t *wall_ns);
 
 /* Counters since creation: stats[0] requests completed, [1] scheduler steps,
  * [2] kernel launches, [3] resident trees now, [4] evictions, [5] peak bytes of

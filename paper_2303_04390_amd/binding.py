@@ -87,6 +87,7 @@ _SIGS = {
     "phg_server_wait": [_vp, _c.c_uint64, _dp, _dp],
     "phg_server_release_tree": [_vp, _c.c_uint64],
     "phg_server_stats": [_vp, _c.POINTER(_c.c_uint64)],
+    "phg_server_busy": [_vp, _c.POINTER(_c.c_uint64), _c.POINTER(_c.c_uint64)],
     "phg_profile_enable": [_vp, _c.c_int],
     "phg_profile_read": [_vp, _dp, _c.POINTER(_c.c_int), _c.POINTER(_c.c_int)],
     "phg_set_fp32_guard": [_vp, _c.c_double],
@@ -389,7 +390,9 @@ class phg_tree_desc(ctypes.Structure):
     _fields_ = [("n_tips", _c.c_int), ("n_patterns", _c.c_int), ("n_states", _c.c_int),
                 ("n_categories", _c.c_int), ("prec", _c.c_int),
                 ("parent", _ip), ("V", _dp), ("Vinv", _dp), ("lambda_", _dp), ("pi", _dp),
-                ("rates", _dp), ("weights", _dp), ("codes", _ip), ("pattern_weights", _dp)]
+                ("rates", _dp), ("weights", _dp), ("codes", _ip), ("pattern_weights", _dp),
+                ("per_category_eigen", _c.c_int), ("n_tip_vectors", _c.c_int), ("tip_vector_tips", _ip),
+                ("tip_vectors", _dp)]
 
 
 def _scheck(status: int, srv, where: str):
@@ -414,10 +417,16 @@ def phg_server_register_tree(srv, prob, prec) -> int:
     keep = dict(parent=_i32(prob.parent), V=_f64(prob.V), Vinv=_f64(prob.Vinv), lam=_f64(prob.lam),
                 pi=_f64(prob.pi), rates=_f64(prob.rates), weights=_f64(prob.weights),
                 codes=_i32(prob.codes), pw=_f64(prob.pattern_weights))
+    tv = getattr(prob, "tip_vectors", None) or {}
+    tips = sorted(tv)
+    keep["tv_tips"] = _i32(np.array(tips, np.int32)) if tips else None
+    keep["tv"] = (_f64(np.concatenate([np.asarray(tv[t], np.float64).reshape(-1) for t in tips]))
+                  if tips else None)
     d = phg_tree_desc(prob.n_tips, prob.n_patterns, prob.n_states, prob.n_categories, prec,
                       _p(keep["parent"]), _p(keep["V"]), _p(keep["Vinv"]), _p(keep["lam"]),
                       _p(keep["pi"]), _p(keep["rates"]), _p(keep["weights"]), _p(keep["codes"]),
-                      _p(keep["pw"]))
+                      _p(keep["pw"]), 1 if np.ndim(prob.V) == 3 else 0, len(tips),
+                      _p(keep["tv_tips"]) if tips else None, _p(keep["tv"]) if tips else None)
     tid = ctypes.c_uint64()
     _scheck(lib().phg_server_register_tree(srv, ctypes.byref(d), ctypes.byref(tid)), srv,
             "phg_server_register_tree")
@@ -466,6 +475,13 @@ def phg_server_release_tree(srv, tree_id: int):
 
 SERVER_STATS = ("completed", "steps", "launches", "resident_trees", "evictions", "peak_bytes",
                 "queued", "in_flight")
+
+
+def phg_server_busy(srv):
+    """(kernel busy ns, wall ns) since the server's creation."""
+    a, b = ctypes.c_uint64(), ctypes.c_uint64()
+    _scheck(lib().phg_server_busy(srv, ctypes.byref(a), ctypes.byref(b)), srv, "phg_server_busy")
+    return a.value, b.value
 
 
 def phg_server_stats(srv) -> dict:

@@ -15,6 +15,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
@@ -152,6 +153,8 @@ struct phg_server {
     uint64_t next_tree = 1, next_req = 1, clock = 0;
     uint64_t n_done = 0, n_steps = 0, n_launches = 0, n_evictions = 0;
     int n_active = 0;
+    uint64_t t_created = 0;                  // steady clock, ns
+    std::atomic<uint64_t> busy_ns{0};        // device time of finished steps
 
     phg_status fail(phg_status s, const std::string& m) {
         err = m;
@@ -429,8 +432,17 @@ void scheduler(phg_server* s) {
         fail_all(s, "hipSetDevice failed on the scheduler thread");
         return;
     }
-    std::deque<hipEvent_t> ahead;
+    // each step in flight: events before its first launch and after its last
+    std::deque<std::pair<hipEvent_t, hipEvent_t>> ahead;
     std::vector<hipEvent_t> pool;
+    auto take_event = [&](hipEvent_t* ev) {
+        if (!pool.empty()) {
+            *ev = pool.back();
+            pool.pop_back();
+            return true;
+        }
+        return hipEventCreate(ev) == hipSuccess;
+    };
     for (;;) {
         std::unique_lock<std::mutex> lk(s->mu);
         if (s->failed) break;
@@ -454,39 +466,51 @@ void scheduler(phg_server* s) {
             }
             continue;
         }
+        hipEvent_t ev0 = nullptr, ev1 = nullptr;
+        if (!take_event(&ev0) || !take_event(&ev1)) {
+            fail_all(s, "hipEventCreate failed");
+            break;
+        }
+        if (hipEventRecord(ev0, s->stream) != hipSuccess) {
+            fail_all(s, "hipEventRecord failed");
+            break;
+        }
         if (!launch_step(s)) {
             fail_all(s, "kernel launch failed");
             break;
         }
-        hipEvent_t ev;
-        if (pool.empty()) {
-            if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
-                fail_all(s, "hipEventCreate failed");
-                break;
-            }
-        } else {
-            ev = pool.back();
-            pool.pop_back();
-        }
-        if (hipEventRecord(ev, s->stream) != hipSuccess) {
+        if (hipEventRecord(ev1, s->stream) != hipSuccess) {
             fail_all(s, "hipEventRecord failed");
             break;
         }
-        ahead.push_back(ev);
+        ahead.emplace_back(ev0, ev1);
         lk.unlock();
-        while (static_cast<int>(ahead.size()) > kMaxStepsAhead) {
-            const hipError_t e = hipEventSynchronize(ahead.front());
-            if (e != hipSuccess) {
+        // retire finished steps (and wait while too many are queued)
+        while (!ahead.empty()) {
+            const bool must = static_cast<int>(ahead.size()) > kMaxStepsAhead;
+            const hipError_t q = must ? hipEventSynchronize(ahead.front().second) : hipEventQuery(ahead.front().second);
+            if (q == hipErrorNotReady) break;
+            if (q != hipSuccess) {
                 std::lock_guard<std::mutex> lk2(s->mu);
-                fail_all(s, std::string("device error: ") + hipGetErrorString(e));
+                fail_all(s, std::string("device error: ") + hipGetErrorString(q));
                 break;
             }
-            pool.push_back(ahead.front());
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, ahead.front().first, ahead.front().second) == hipSuccess)
+                s->busy_ns += static_cast<uint64_t>(static_cast<double>(ms) * 1e6);
+            pool.push_back(ahead.front().first);
+            pool.push_back(ahead.front().second);
             ahead.pop_front();
         }
     }
     (void)hipStreamSynchronize(s->stream);
-    for (hipEvent_t e : ahead) (void)hipEventDestroy(e);
+    for (auto& e : ahead) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, e.first, e.second) == hipSuccess)
+            s->busy_ns += static_cast<uint64_t>(static_cast<double>(ms) * 1e6);
+        (void)hipEventDestroy(e.first);
+        (void)hipEventDestroy(e.second);
+    }
     for (hipEvent_t e : pool) (void)hipEventDestroy(e);
 }
 
@@ -521,6 +545,7 @@ phg_status phg_server_create(int device, size_t mem_budget_bytes, int max_slots,
     s->device = device;
     s->budget = mem_budget_bytes;
     s->max_slots = max_slots;
+    s->t_created = now_ns();
     void* p = nullptr;
     if (hipMalloc(&p, mem_budget_bytes) != hipSuccess) {
         g_server_error = "could not reserve the memory budget";
@@ -602,7 +627,14 @@ phg_status phg_server_register_tree(phg_server* s, const phg_tree_desc* d, uint6
     std::vector<double> b0(E, 0.0);
     ctx->table_budget = static_cast<size_t>(-1);   // one P(t) stage per request: every branch's tables
     if (st == PHG_OK) st = phg_set_topology(ctx, d->parent);
-    if (st == PHG_OK) st = phg_set_eigen(ctx, d->V, d->Vinv, d->lambda);
+    if (st == PHG_OK)
+        st = d->per_category_eigen ? phg_set_category_eigen(ctx, d->V, d->Vinv, d->lambda)
+                                   : phg_set_eigen(ctx, d->V, d->Vinv, d->lambda);
+    if (st == PHG_OK && d->n_tip_vectors < 0) st = PHG_ERR_ARG;
+    if (st == PHG_OK && d->n_tip_vectors > 0 && (!d->tip_vector_tips || !d->tip_vectors)) st = PHG_ERR_ARG;
+    for (int v = 0; st == PHG_OK && v < d->n_tip_vectors; ++v)
+        st = phg_set_tip_partials(ctx, d->tip_vector_tips[v],
+                                  d->tip_vectors + static_cast<size_t>(v) * d->n_patterns * d->n_states);
     if (st == PHG_OK) st = phg_set_root_frequencies(ctx, d->pi);
     if (st == PHG_OK) st = phg_set_categories(ctx, d->rates, d->weights);
     if (st == PHG_OK) st = phg_set_tip_states(ctx, d->codes);
@@ -720,6 +752,13 @@ phg_status phg_server_release_tree(phg_server* s, uint64_t tree_id) {
         phg_destroy(t->ctx);
         s->trees.erase(it);
     }
+    return PHG_OK;
+}
+
+phg_status phg_server_busy(phg_server* s, uint64_t* busy_ns, uint64_t* wall_ns) {
+    if (!s) return PHG_ERR_ARG;
+    if (busy_ns) *busy_ns = s->busy_ns.load();
+    if (wall_ns) *wall_ns = now_ns() - s->t_created;
     return PHG_OK;
 }
 

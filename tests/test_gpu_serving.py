@@ -212,3 +212,60 @@ def test_concurrent_submitters():
     finally:
         B.phg_server_destroy(srv)
     assert not errors, errors
+
+
+def general_trees(seed=30):
+    """Trees in the general form of the gradient-kernel section: one
+    substitution model per rate category (4 and 20 states), and general tip
+    partial vectors on some tips (4 and 61 states), beside plain trees."""
+    rng = np.random.default_rng(seed)
+    out = []
+    p = synth.config_problem("hky1000", seed=seed, n_tips=150, n_patterns=700)
+    p.Q, p.V, p.Vinv, p.lam = synth.category_models(4, 4, rng)
+    out.append((p, B.PHG_FP32_SCALED))
+    p = synth.config_problem("aa500", seed=seed + 1, n_tips=40, n_patterns=300)
+    p.Q, p.V, p.Vinv, p.lam = synth.category_models(20, 4, rng)
+    out.append((p, B.PHG_FP64))
+    p = synth.config_problem("hky16", seed=seed + 2, n_patterns=400)
+    p.tip_vectors = {t: rng.uniform(0.0, 1.0, (400, 4)) for t in (1, 5, 9)}
+    out.append((p, B.PHG_FP32_SCALED))
+    p = synth.config_problem("codon128", seed=seed + 3, n_tips=20, n_patterns=200)
+    p.tip_vectors = {t: rng.uniform(0.0, 1.0, (200, 61)) for t in (0, 7)}
+    out.append((p, B.PHG_FP32_SCALED))
+    out.append((synth.config_problem("hky1000", seed=seed + 4, n_tips=300, n_patterns=2000), B.PHG_FP32_SCALED))
+    return out
+
+
+def test_general_trees_alone_vs_mix_and_oracle():
+    """Per-category models and general tip vectors through the tree
+    descriptor: each request's result is bitwise the same alone, in a mix and
+    on a single context, and meets the oracle bar."""
+    mix = general_trees()
+    rng = np.random.default_rng(8)
+    bs = [p.b * np.exp(rng.normal(0, 0.05, p.b.shape)) for p, _ in mix]
+    alone = []
+    print("[case] general trees alone", flush=True)
+    srv = B.phg_server_create(0, 4 * GiB, 8)
+    try:
+        for (p, prec), b in zip(mix, bs):
+            tid = B.phg_server_register_tree(srv, p, prec)
+            alone.append(B.phg_server_wait(srv, B.phg_server_submit(srv, tid, b), 2 * p.n_tips - 2))
+    finally:
+        B.phg_server_destroy(srv)
+    print("[case] general trees in a mix", flush=True)
+    srv = B.phg_server_create(0, 4 * GiB, 8)
+    try:
+        tids = [B.phg_server_register_tree(srv, p, prec) for p, prec in mix]
+        rids = [B.phg_server_submit(srv, tid, b) for tid, b in zip(tids, bs)]
+        mixed = [B.phg_server_wait(srv, rid, 2 * p.n_tips - 2) for rid, (p, _) in zip(rids, mix)]
+        busy, wall = B.phg_server_busy(srv)
+    finally:
+        B.phg_server_destroy(srv)
+    assert 0 < busy < wall
+    for k, ((p, prec), b) in enumerate(zip(mix, bs)):
+        assert alone[k][0] == mixed[k][0] and np.array_equal(alone[k][1], mixed[k][1]), k
+        l0, g0 = single_context(p, prec, b)
+        assert alone[k][0] == l0 and np.array_equal(alone[k][1], g0), k
+        q = synth.Problem(**{**p.__dict__, "b": b})
+        tol = (1e-12, 1e-9) if prec == B.PHG_FP64 else (1e-6, 1e-4)
+        check(f"server-general-{k}", mixed[k][0], mixed[k][1], oracle.evaluate_problem(q), *tol)
