@@ -194,7 +194,8 @@ def serving_measurement(args, B, synth):
         r0 = int(r.integers(0, 4096 - N + 1))
         c0 = int(r.integers(0, 20000 - C + 1))
         return synth.Problem(parent=parents[k], b=r.exponential(0.01, 2 * N - 2), V=V, Vinv=Vinv, lam=lam,
-                             pi=pi, rates=rates, weights=w, codes=base.codes[r0:r0 + N, c0:c0 + C],
+                             pi=pi, rates=rates, weights=w,
+                             codes=np.ascontiguousarray(base.codes[r0:r0 + N, c0:c0 + C], np.int32),
                              pattern_weights=np.ones(C), Q=Q)
 
     budget = 96 << 30

@@ -20,6 +20,7 @@
 #include <limits>
 #include <new>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "phg_context.h"
@@ -1000,13 +1001,43 @@ phg_status phg_set_tip_states(phg_context* ctx, const int32_t* codes) {
     if (!ctx) return PHG_ERR_ARG;
     if (!codes) return ctx->fail(PHG_ERR_ARG, "codes is NULL");
     const int N = ctx->N, C = ctx->C, S = ctx->S, Cpad = ctx->Cpad;
-    for (size_t i = 0; i < static_cast<size_t>(N) * C; ++i)
-        if (codes[i] < 0 || codes[i] > S)
-            return ctx->fail(PHG_ERR_ARG, "tip code %d at tip %zu pattern %zu outside [0, %d]", codes[i],
-                             i / C, i % C, S);
-    for (int t = 0; t < N; ++t)
-        for (int c = 0; c < C; ++c)
-            put_code(ctx, static_cast<size_t>(t) * Cpad + c, codes[static_cast<size_t>(t) * C + c]);
+    // validate and convert tips [t0, t1): branch-free loops (vectorised),
+    // spread over threads for large alignments
+    auto rows = [&](int t0, int t1, bool* ok) {
+        uint32_t bad = 0;
+        for (int t = t0; t < t1; ++t) {
+            const int32_t* src = codes + static_cast<size_t>(t) * C;
+            for (int c = 0; c < C; ++c) bad |= static_cast<uint32_t>(src[c]) > static_cast<uint32_t>(S);
+        }
+        *ok = bad == 0;
+        if (bad) return;
+        for (int t = t0; t < t1; ++t) {
+            const int32_t* src = codes + static_cast<size_t>(t) * C;
+            if (code_bytes(S) == 1) {
+                uint8_t* dst = ctx->codes.data() + static_cast<size_t>(t) * Cpad;
+                for (int c = 0; c < C; ++c) dst[c] = static_cast<uint8_t>(src[c]);
+            } else {
+                for (int c = 0; c < C; ++c) put_code(ctx, static_cast<size_t>(t) * Cpad + c, src[c]);
+            }
+        }
+    };
+    const size_t total = static_cast<size_t>(N) * C;
+    const int nt = total >= (size_t{1} << 22) ? std::min(8, N) : 1;
+    std::vector<char> ok(nt, 0);
+    {
+        std::vector<std::thread> th;
+        for (int k = 1; k < nt; ++k)
+            th.emplace_back(rows, N * k / nt, N * (k + 1) / nt, reinterpret_cast<bool*>(&ok[k]));
+        rows(0, N / nt, reinterpret_cast<bool*>(&ok[0]));
+        for (auto& x : th) x.join();
+    }
+    for (int k = 0; k < nt; ++k) {
+        if (ok[k]) continue;
+        for (size_t i = 0; i < total; ++i)        // report the first bad entry
+            if (codes[i] < 0 || codes[i] > S)
+                return ctx->fail(PHG_ERR_ARG, "tip code %d at tip %zu pattern %zu outside [0, %d]", codes[i],
+                                 i / C, i % C, S);
+    }
     ctx->have |= kTips;
     ctx->dirty |= kTips;
     ctx->sdirty |= kTips;
