@@ -28,7 +28,8 @@ def check(name, logl, grad, ref, tol_ll, tol_g):
     worst = int(np.argmax(rel))
     print(f"[parity] {name}: logL rel err {rel_ll:.3e} (tol {tol_ll:.0e}); grad max scaled err "
           f"{rel.max():.3e} (tol {tol_g:.0e}) at branch {worst}; floor used by {floor_used}/"
-          f"{len(rel)}; max pure rel err {pure.max():.3e}", flush=True)
+          f"{len(rel)}; max pure rel err {pure.max():.3e}, {int(np.sum(pure > tol_g))} components "
+          f"above {tol_g:.0e} pure relative", flush=True)
     sys.stdout.flush()
     assert np.isfinite(logl)
     assert rel_ll <= tol_ll, (name, rel_ll)
