@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libphg.so")
 
 SOURCES = ["phg_host.cpp", "phg_server.cpp", "phg_chain.cpp", "phg_kernels.hip", "phg_kernels_gs.hip",
-           "phg_kernels_gl.hip", "phg_chain.hip", "phg_static.hip"]
+           "phg_kernels_gl.hip", "phg_kernels_vs.hip", "phg_chain.hip", "phg_static.hip"]
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     # no packed-FP32 instructions in device code

@@ -41,12 +41,19 @@ namespace {
 size_t gl_table_bytes_per_branch(int S, int R, bool fp32) {
     return static_cast<size_t>(R) * (2 * gl_mat_rows(S) + 2 * gl_back_rows(S)) * gl_row(S) * (fp32 ? 4 : 8);
 }
+// Vector-ALU kernels: forward P, dP [SP][SP] and backward P, dP [SP + 1][SP].
+size_t vs_table_bytes_per_branch(int S, int R, bool fp32) {
+    const size_t SP = vs_padded_states(S);
+    return static_cast<size_t>(R) * (2 * SP * SP + 2 * (SP + 1) * SP) * (fp32 ? 4 : 8);
+}
 }  // namespace
 
 int table_slots_for(int N, int S, int R, phg_precision prec, size_t budget) {
-    if (!uses_gl_kernels(S, R)) return 0;
+    const bool fp32 = prec == PHG_FP32_SCALED;
+    const bool vs = uses_vs_kernels(S, R, fp32);
+    if (!vs && !uses_gl_kernels(S, R, fp32)) return 0;
     const size_t E = 2 * static_cast<size_t>(N) - 2;
-    const size_t per = gl_table_bytes_per_branch(S, R, prec == PHG_FP32_SCALED);
+    const size_t per = vs ? vs_table_bytes_per_branch(S, R, fp32) : gl_table_bytes_per_branch(S, R, fp32);
     if (E * per <= budget) return 0;
     const size_t fit = budget / per;
     return static_cast<int>(std::max<size_t>(2, std::min(fit, E) & ~size_t{1}));
@@ -69,7 +76,23 @@ Plan make_plan(int N, int C, int S, int R, phg_precision prec, int table_slots) 
     const bool fp32 = prec == PHG_FP32_SCALED;
     p.codes = take(static_cast<size_t>(N) * Cpad * code_bytes(S));
     p.expo = take(I * Cpad * sizeof(int32_t));
-    if (uses_gl_kernels(S, R)) {
+    if (uses_vs_kernels(S, R, fp32)) {
+        // vector-ALU kernels: zero-padded tables of the path's own type
+        const size_t SP = vs_padded_states(S);
+        const size_t T = table_slots > 0 ? static_cast<size_t>(table_slots) : E;   // tables held
+        const size_t mat = T * R * SP * SP;
+        const size_t back = T * R * (SP + 1) * SP;
+        p.part = take(I * tiles * R * SP * tp * tsz);
+        p.eloc = take(0);
+        p.P64 = take(fp32 ? 0 : mat * 8);
+        p.dP64 = take(fp32 ? 0 : mat * 8);
+        p.PB64 = take(fp32 ? 0 : back * 8);
+        p.dPB64 = take(fp32 ? 0 : back * 8);
+        p.P32 = take(fp32 ? mat * 4 : 0);
+        p.dP32 = take(fp32 ? mat * 4 : 0);
+        p.PB32 = take(fp32 ? back * 4 : 0);
+        p.dPB32 = take(fp32 ? back * 4 : 0);
+    } else if (uses_gl_kernels(S, R, fp32)) {
         // MFMA operand order: one forward table per matrix and a backward
         // copy of P, in the path's own type only
         const size_t T = table_slots > 0 ? static_cast<size_t>(table_slots) : E;   // tables held
@@ -161,7 +184,7 @@ bool tune_value_ok(int S, int R, bool fp32, int param, int value) {
     if (value < 0) return false;
     if (value == 0) return true;
     if (param == PHG_TUNE_ROW_BLOCKS)
-        return phg::uses_gl_kernels(S, R > 0 ? R : 1) && phg::gl_row_blocks_allowed(S, fp32, value);
+        return S > 16 && phg::gl_row_blocks_allowed(S, fp32, value);   // read by the MFMA kernels only
     if (param == PHG_TUNE_NARROW_UNITS) return S == 4 && fp32;
     return false;
 }
@@ -440,7 +463,22 @@ void pack_tip_vectors(const phg_context* ctx, std::vector<T>& out, std::vector<i
                             (c % kLanes) * 4 + st] = static_cast<T>(value(kv.second, c, st));
             ++gslot;
         }
-    } else if (uses_gl_kernels(S, R)) {
+    } else if (uses_vs_kernels(S, R, fp32)) {
+        // [slot][tile][R][SP][64]
+        const int SP = vs_padded_states(S);
+        const size_t per = static_cast<size_t>(tiles) * R * SP * kLanes;
+        out.assign(G * per, T(0));
+        int gslot = 0;
+        for (const auto& kv : ctx->tip_vectors) {
+            tslot[kv.first] = gslot;
+            for (int c = 0; c < Cpad; ++c)
+                for (int r = 0; r < R; ++r)
+                    for (int st = 0; st < S; ++st)
+                        out[(((static_cast<size_t>(gslot) * tiles + c / kLanes) * R + r) * SP + st) * kLanes +
+                            c % kLanes] = static_cast<T>(value(kv.second, c, st));
+            ++gslot;
+        }
+    } else if (uses_gl_kernels(S, R, fp32)) {
         // [slot][tile][R][TP][row], state t at column gl_col(t)
         const int TP = Cpad / tiles, row = gl_row(S), kbp = gl_kbp(S);
         const size_t per = static_cast<size_t>(tiles) * R * TP * row;

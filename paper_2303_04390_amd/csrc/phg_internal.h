@@ -33,8 +33,10 @@ struct BlockRec {
 // alignment with its own workspace).  Layouts (T = float or double):
 //   codes  uint8  [N][Cpad]                  tip states, S = all-ones, pad = S
 //   part   T      4 states: [N-1][tiles][R][64][4] (lane-major quads)
-//                 17..255 states: [N-1][tiles][R][TP][gl_row(S)] (pattern
-//                   rows in the MFMA operand order gl_col, zero-padded)
+//                 vector-ALU kernels (17..32 states): [N-1][tiles][R][SP][64]
+//                   (state rows of the tile's 64 patterns, SP = vs_padded_states)
+//                 MFMA kernels (17..256 states): [N-1][tiles][R][TP][gl_row(S)]
+//                   (pattern rows in the MFMA operand order gl_col, zero-padded)
 //                 otherwise: [N-1][tiles][R][S][TP] (state rows of TP patterns)
 //                                             post-order partial of each
 //                                             internal node (slot = id - N);
@@ -42,7 +44,7 @@ struct BlockRec {
 //                                             pre-order partial
 //   expo   int32  [N-1][Cpad]                cumulative power-of-two exponent
 //                                             of the subtree below each node
-//   eloc   int32  [N-1][Cpad]                17..255 states: the node's own
+//   eloc   int32  [N-1][Cpad]                MFMA kernels: the node's own
 //                                             exponent e; its stored partial
 //                                             is 2^e times the normalised one
 //                                             (after the pre-order: that of q)
@@ -50,7 +52,10 @@ struct BlockRec {
 //                 17..255 states: only the table of the path's type T, as
 //                 [E][R][gl_mat_rows(S)][gl_row(S)] with row s holding P[s][t]
 //                 at column gl_col(t) (forward operand), and PB32 / PB64 the
-//                 same with row t holding P[s][t] at gl_col(s) (backward)
+//                 same with row t holding P[s][t] at gl_col(s) (backward);
+//                 vector-ALU kernels: forward [E][R][SP][SP] (row s = P[s][.])
+//                 and backward [E][R][SP + 1][SP] (row t = P[.][t], row SP the
+//                 row sums), zero-padded, for P and dP alike
 //   sll    double [Cpad]                     per-pattern log site likelihood
 //   lpart  double [tiles]                    per-tile weighted log-likelihood
 //   gpart  double [E][tiles]                 per-tile weighted gradient sums
@@ -177,9 +182,31 @@ struct ChainArgs {
 // d_rates (time_tree) or of grad.
 hipError_t launch_chain(const ChainArgs& a, bool time_tree, hipStream_t stream);
 
-// MFMA level kernels for 17..255 states (phg_kernels_gl.hip): one workgroup
-// per (node, pattern tile), the waves splitting the output states.
-inline bool uses_gl_kernels(int S, int R) { return S > 16 && !uses_s4_kernels(S, R); }
+// Vector-ALU level kernels for 17..32 states (FP32; 17..24 in FP64, whose
+// registers hold four padded vectors per lane) at 1, 2, 4 or 8 categories
+// (phg_kernels_vs.hip): one workgroup per (node, 64-pattern tile), one wave
+// per category, one lane per pattern, the matrices wave-uniform and staged
+// in LDS.  Their vectors and tables are padded to vs_padded_states(S) states.
+__host__ __device__ constexpr inline int vs_padded_states(int S) { return S <= 20 ? 20 : (S <= 24 ? 24 : 32); }
+// LDS of a pre-order workgroup: P and dP of both children for each category,
+// and the five per-pattern exchange values per category.  Shapes above
+// kVsLdsMax (two workgroups per CU) stay on the MFMA kernels.
+__host__ __device__ constexpr inline size_t vs_lds_bytes(int SP, int R, int tsz) {
+    return static_cast<size_t>(R) * (4 * SP * SP + 5 * 64) * tsz;
+}
+constexpr size_t kVsLdsMax = size_t{80} << 10;
+inline bool uses_vs_kernels(int S, int R, bool fp32) {
+    return S > 16 && S <= (fp32 ? 32 : 24) && R >= 1 && R <= 8 && (R & (R - 1)) == 0 &&
+           vs_lds_bytes(vs_padded_states(S), R, fp32 ? 4 : 8) <= kVsLdsMax;
+}
+hipError_t launch_vs(KernelClass k, const ReqDesc& shape, const ReqDesc* descs, const SegTable& t,
+                     hipStream_t stream);
+
+// MFMA level kernels for the other shapes above 16 states (phg_kernels_gl.hip):
+// one workgroup per (node, pattern tile), the waves splitting the output states.
+inline bool uses_gl_kernels(int S, int R, bool fp32) {
+    return S > 16 && !uses_s4_kernels(S, R) && !uses_vs_kernels(S, R, fp32);
+}
 // Their operand order: a stored vector (one pattern's partial) or matrix row
 // holds state t at column gl_col(t) = (t mod 4) KBP + t / 4, so the states
 // 4k + g that MFMA lane group g consumes on k-steps k, k+1, ... are adjacent

@@ -1494,8 +1494,8 @@ hipError_t level_t(KernelClass k, int R, bool blocked, const ReqDesc* descs, con
 bool kernels_support(int S, int R) { return S >= 2 && S <= 256 && R >= 1 && R <= 64; }
 
 int tile_patterns(int S, int R, bool fp32) {
-    if (uses_gl_kernels(S, R)) return 16 * gl_row_blocks(S, R, fp32);
-    return uses_s4_kernels(S, R) ? kLanes : gs_tile_patterns(fp32);
+    if (uses_gl_kernels(S, R, fp32)) return 16 * gl_row_blocks(S, R, fp32);
+    return (uses_s4_kernels(S, R) || uses_vs_kernels(S, R, fp32)) ? kLanes : gs_tile_patterns(fp32);
 }
 
 int units_for(KernelClass k, const ReqDesc& d, int n_nodes) {
@@ -1517,7 +1517,9 @@ hipError_t launch_class(KernelClass k, const ReqDesc& shape, const ReqDesc* desc
             if (shape.S == 4) {
                 hipLaunchKernelGGL(pmat4_kernel, dim3((4 * n_units + kPmatBlock - 1) / kPmatBlock),
                                    dim3(kPmatBlock), 0, st, descs, t);
-            } else if (uses_gl_kernels(shape.S, shape.R)) {
+            } else if (uses_vs_kernels(shape.S, shape.R, shape.fp32 != 0)) {
+                return launch_vs(kPmat, shape, descs, t, st);
+            } else if (uses_gl_kernels(shape.S, shape.R, shape.fp32 != 0)) {
                 return launch_pmat_gl(shape, descs, t, st);
             } else {
                 hipLaunchKernelGGL(pmat_block_kernel, dim3(n_units), dim3(256), 0, st, descs, t);
@@ -1525,7 +1527,8 @@ hipError_t launch_class(KernelClass k, const ReqDesc& shape, const ReqDesc* desc
             return hipGetLastError();
         case kPost:
         case kPre:
-            if (uses_gl_kernels(shape.S, shape.R)) return launch_level_gl(k, shape, descs, t, st);
+            if (uses_vs_kernels(shape.S, shape.R, shape.fp32 != 0)) return launch_vs(k, shape, descs, t, st);
+            if (uses_gl_kernels(shape.S, shape.R, shape.fp32 != 0)) return launch_level_gl(k, shape, descs, t, st);
             if (!uses_s4_kernels(shape.S, shape.R)) return launch_level_gs(k, shape, descs, t, st);
             if (shape.fp32) return level_t<float>(k, shape.R, shape.blocked != 0, descs, t, st);
             return level_t<double>(k, shape.R, shape.blocked != 0, descs, t, st);

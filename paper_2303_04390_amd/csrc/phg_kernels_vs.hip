@@ -1,0 +1,565 @@
+// gfx950 level kernels for 17..32 states (amino acids) on the vector ALUs.
+//
+// Same method as the other kernels (Methods: pruning equation, eq:preorder,
+// eq:gradient).  One workgroup takes one (node, 64-pattern tile); wave r of
+// the workgroup holds category r and lane l pattern l of the tile, with the
+// node's vectors for that (category, pattern) in registers (SP values, the
+// state count padded to a multiple of 4 with zeros).  Every lane of a wave
+// uses the same matrix, so an S x S product is SP^2 fused multiply-adds per
+// lane whose matrix operand is wave-uniform.  Each wave first copies the
+// P(t) tables of its category for the node's internal children into its own
+// LDS region -- all loads in flight at once, so the workgroup waits for
+// memory once -- and then reads matrix rows as LDS broadcasts (a row read
+// straight from memory before each row's multiply-adds would wait for
+// memory once per row).  Per-pattern quantities shared by the categories
+// (the rescaling maximum, the gradient's numerator and denominator sums) go
+// through LDS once per node.
+//
+// Layouts (all zero-padded, so no load is masked):
+//   partials  [slot][tile][r][SP states][64 patterns]   (state-major: a
+//             state of a wave is 64 contiguous values)
+//   forward   P, dP  [branch][r][SP rows s][SP cols t] = P[s][t]
+//   backward  P, dP  [branch][r][SP + 1 rows][SP]: row t < S holds column t
+//             (P[.][t]), rows S..SP-1 zeros, row SP the row sums P 1.
+// A tip given by code y takes row y of the backward tables as its P e_y and
+// dP e_y (row SP for the ambiguous code S); P^T u accumulates the rows of
+// the forward table, P^T u = sum_s u_s P[s][.].
+//
+// Scaling as in the 4-state kernels: one power-of-two exponent per (node,
+// pattern) shared by all categories; stored post-order partials are
+// normalised and the exponents cumulative per subtree; pre-order vectors are
+// normalised and their exponents dropped (the gradient ratio does not depend
+// on them).
+#include "phg_internal.h"
+
+#include <math.h>
+
+namespace phg {
+namespace {
+
+#define GLOBAL __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ GLOBAL T* g(T* p) {
+    return (GLOBAL T*)p;
+}
+
+constexpr int kVL = 64;   // patterns per tile (one per lane)
+
+template <typename T>
+__device__ __forceinline__ T* fwdP(const ReqDesc& d);
+template <>
+__device__ __forceinline__ float* fwdP<float>(const ReqDesc& d) { return d.P32; }
+template <>
+__device__ __forceinline__ double* fwdP<double>(const ReqDesc& d) { return d.P64; }
+template <typename T>
+__device__ __forceinline__ T* fwddP(const ReqDesc& d);
+template <>
+__device__ __forceinline__ float* fwddP<float>(const ReqDesc& d) { return d.dP32; }
+template <>
+__device__ __forceinline__ double* fwddP<double>(const ReqDesc& d) { return d.dP64; }
+template <typename T>
+__device__ __forceinline__ T* bwdP(const ReqDesc& d);
+template <>
+__device__ __forceinline__ float* bwdP<float>(const ReqDesc& d) { return d.PB32; }
+template <>
+__device__ __forceinline__ double* bwdP<double>(const ReqDesc& d) { return d.PB64; }
+template <typename T>
+__device__ __forceinline__ T* bwddP(const ReqDesc& d);
+template <>
+__device__ __forceinline__ float* bwddP<float>(const ReqDesc& d) { return d.dPB32; }
+template <>
+__device__ __forceinline__ double* bwddP<double>(const ReqDesc& d) { return d.dPB64; }
+
+__device__ __forceinline__ int exponent_of(float x) {
+    int e = 0;
+    if (x > 0.0f) (void)frexpf(x, &e);
+    return e;
+}
+__device__ __forceinline__ int exponent_of(double x) {
+    int e = 0;
+    if (x > 0.0) (void)frexp(x, &e);
+    return e;
+}
+__device__ __forceinline__ float exact_ldexp(float x, int e) { return ldexpf(x, e); }
+__device__ __forceinline__ double exact_ldexp(double x, int e) { return ldexp(x, e); }
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__device__ __forceinline__ int seg_index(const SegTable& t, int unit) {
+    int s = 0;
+    while (s + 1 < t.n && unit >= t.unit_begin[s + 1]) ++s;
+    return s;
+}
+
+// A stored vector of this lane's (category, pattern): SP values.
+template <typename T, int SP>
+__device__ __forceinline__ void vs_load(const GLOBAL T* __restrict__ base, int lane, T (&v)[SP]) {
+#pragma unroll
+    for (int s = 0; s < SP; ++s) v[s] = base[s * kVL + lane];
+}
+template <typename T, int SP>
+__device__ __forceinline__ void vs_store(GLOBAL T* __restrict__ base, int lane, const T (&v)[SP]) {
+#pragma unroll
+    for (int s = 0; s < SP; ++s) base[s * kVL + lane] = v[s];
+}
+
+// Row s of a wave-uniform SP x SP matrix (in LDS) times this lane's vector v.
+template <typename T, int SP>
+__device__ __forceinline__ T vs_row(const T* __restrict__ M, int s, const T (&v)[SP]) {
+    T a = T(0);
+#pragma unroll
+    for (int t = 0; t < SP; ++t) a = fma(M[s * SP + t], v[t], a);
+    return a;
+}
+// Keeps a matrix row's LDS reads beside its multiply-adds, so the registers
+// in use stay those of about one row.
+__device__ __forceinline__ void row_fence() { __builtin_amdgcn_sched_barrier(0); }
+
+// Copying a wave's SP x SP tables into LDS: 16-byte pieces, all loads of a
+// stage issued before the first store.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+template <typename T, int SP>
+struct Stage {
+    static constexpr int kPieces = SP * SP * static_cast<int>(sizeof(T)) / 16;
+    static constexpr int kIters = (kPieces + kVL - 1) / kVL;
+    u32x4 r[kIters];
+    __device__ __forceinline__ void load(const GLOBAL T* src, int lane) {
+        const GLOBAL u32x4* s4 = reinterpret_cast<const GLOBAL u32x4*>(src);
+#pragma unroll
+        for (int it = 0; it < kIters; ++it)
+            if (it * kVL + lane < kPieces) r[it] = s4[it * kVL + lane];
+    }
+    __device__ __forceinline__ void store(T* dst, int lane) const {
+        u32x4* d4 = reinterpret_cast<u32x4*>(dst);
+#pragma unroll
+        for (int it = 0; it < kIters; ++it)
+            if (it * kVL + lane < kPieces) d4[it * kVL + lane] = r[it];
+    }
+};
+
+// Child x's input for this (category, tile): its stored partial (internal),
+// a general tip vector, or null (a tip given by its code).
+template <typename T, int SP>
+__device__ __forceinline__ const GLOBAL T* vs_src(const ReqDesc& d, int x, int tile, int r) {
+    const size_t per = static_cast<size_t>(SP) * kVL;
+    if (x >= d.N)
+        return g(static_cast<const T*>(d.part)) + ((static_cast<size_t>(x - d.N) * d.tiles + tile) * d.R + r) * per;
+    const int gx = d.tslot ? g(d.tslot)[x] : -1;
+    return gx >= 0 ? g(static_cast<const T*>(d.tipvec)) + ((static_cast<size_t>(gx) * d.tiles + tile) * d.R + r) * per
+                   : nullptr;
+}
+
+// Row of a tip's backward table for code y: y itself for a state, row SP
+// (the row sums) for the ambiguous code S.
+template <int SP>
+__device__ __forceinline__ int tip_row(int y, int S) {
+    return (y < S ? y : SP) * SP;
+}
+
+struct VsUnit {
+    const ReqDesc* d;
+    Segment sg;
+    int i, j, k, tile;
+    int ti, tj;   // P(t) tables of the children: by branch, or by slot in per-chunk tables
+};
+__device__ __forceinline__ bool vs_unit(const ReqDesc* __restrict__ descs, const SegTable& segs, VsUnit& U) {
+    const int unit = blockIdx.x;
+    if (unit >= segs.unit_begin[segs.n]) return false;
+    const int sidx = seg_index(segs, unit);
+    U.sg = segs.seg[sidx];
+    U.d = &descs[U.sg.desc];
+    const int tiles = U.d->tiles;
+    const int local = unit - segs.unit_begin[sidx];
+    const int node_ix = local / tiles;
+    U.tile = local - node_ix * tiles;
+    const GLOBAL int32_t* rec = g(U.sg.sched) + static_cast<size_t>(U.sg.sched_off + node_ix) * 4;
+    U.k = rec[0];
+    U.i = rec[1];
+    U.j = rec[2];
+    U.ti = U.d->level_tables ? 2 * node_ix : U.i;
+    U.tj = U.d->level_tables ? 2 * node_ix + 1 : U.j;
+    return true;
+}
+
+// ---------------------------------------------------------------- post-order
+
+// p_k = (P_i p_i) o (P_j p_j) per category, rescaled by the largest entry
+// over the node's categories; at the root the site likelihood instead.
+template <typename T, int SP, int R>
+__global__ __launch_bounds__(kVL * R) void post_vs_kernel(const ReqDesc* __restrict__ descs, const SegTable segs) {
+    __shared__ __align__(16) T tab[R][2][SP * SP];   // P_i, P_j of each category
+    __shared__ T xmax[R][kVL];
+    __shared__ double xsite[R][kVL];
+    const int r = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & (kVL - 1);
+    VsUnit U;
+    if (!vs_unit(descs, segs, U)) return;
+    const ReqDesc& d = *U.d;
+    const int N = d.N, S = d.S, Cpad = d.Cpad, tile = U.tile;
+    const int c = tile * kVL + lane;
+    const size_t mat = static_cast<size_t>(SP) * SP, bmat = static_cast<size_t>(SP + 1) * SP;
+    const GLOBAL T* src_i = vs_src<T, SP>(d, U.i, tile, r);
+    const GLOBAL T* src_j = vs_src<T, SP>(d, U.j, tile, r);
+    {   // this category's tables of the children that take a product
+        Stage<T, SP> si, sj;
+        if (src_i) si.load(g(fwdP<T>(d)) + (static_cast<size_t>(U.ti) * R + r) * mat, lane);
+        if (src_j) sj.load(g(fwdP<T>(d)) + (static_cast<size_t>(U.tj) * R + r) * mat, lane);
+        if (src_i) si.store(tab[r][0], lane);
+        if (src_j) sj.store(tab[r][1], lane);
+    }
+    // the children's cumulative exponents
+    int ec = 0;
+    if (U.i >= N) ec += g(d.expo)[static_cast<size_t>(U.i - N) * Cpad + c];
+    if (U.j >= N) ec += g(d.expo)[static_cast<size_t>(U.j - N) * Cpad + c];
+    __syncthreads();
+    T p[SP];
+    if (src_i) {   // p = P_i p_i
+        T v[SP];
+        vs_load<T, SP>(src_i, lane, v);
+#pragma unroll
+        for (int s = 0; s < SP; ++s) {
+            p[s] = vs_row<T, SP>(tab[r][0], s, v);
+            row_fence();
+        }
+    } else {
+        const GLOBAL T* B = g(bwdP<T>(d)) + (static_cast<size_t>(U.ti) * R + r) * bmat +
+                            tip_row<SP>(g(d.codes)[static_cast<size_t>(U.i) * Cpad + c], S);
+#pragma unroll
+        for (int s = 0; s < SP; ++s) p[s] = B[s];
+    }
+    if (src_j) {   // p *= P_j p_j
+        T v[SP];
+        vs_load<T, SP>(src_j, lane, v);
+#pragma unroll
+        for (int s = 0; s < SP; ++s) {
+            p[s] *= vs_row<T, SP>(tab[r][1], s, v);
+            row_fence();
+        }
+    } else {
+        const GLOBAL T* B = g(bwdP<T>(d)) + (static_cast<size_t>(U.tj) * R + r) * bmat +
+                            tip_row<SP>(g(d.codes)[static_cast<size_t>(U.j) * Cpad + c], S);
+#pragma unroll
+        for (int s = 0; s < SP; ++s) p[s] *= B[s];
+    }
+    if (!(U.sg.flags & 1)) {
+        T lmx = T(0);
+#pragma unroll
+        for (int s = 0; s < SP; ++s) lmx = fmax(lmx, p[s]);
+        xmax[r][lane] = lmx;
+        __syncthreads();
+        T mx = xmax[0][lane];
+#pragma unroll
+        for (int rr = 1; rr < R; ++rr) mx = fmax(mx, xmax[rr][lane]);
+        const int e = exponent_of(mx);
+#pragma unroll
+        for (int s = 0; s < SP; ++s) p[s] = exact_ldexp(p[s], -e);
+        vs_store<T, SP>(g(static_cast<T*>(d.part)) +
+                            ((static_cast<size_t>(U.k - N) * d.tiles + tile) * R + r) * SP * kVL,
+                        lane, p);
+        if (r == 0) g(d.expo)[static_cast<size_t>(U.k - N) * Cpad + c] = e + ec;
+    } else {
+        // root: site likelihood sum_r w_r pi . p_r, categories summed in a fixed order
+        double acc = 0.0;
+#pragma unroll
+        for (int s = 0; s < SP; ++s)
+            if (s < S) acc += g(d.pi)[s] * static_cast<double>(p[s]);
+        xsite[r][lane] = g(d.cweights)[r] * acc;
+        __syncthreads();
+        if (r == 0) {
+            double site = 0.0;
+#pragma unroll
+            for (int rr = 0; rr < R; ++rr) site += xsite[rr][lane];
+            const double ll = (site > 0.0 ? log(site) : -INFINITY) + static_cast<double>(ec) * 0.69314718055994530942;
+            g(d.sll)[c] = ll;
+            const double W = g(d.pw)[c];
+            const double tsum = wave_sum(W != 0.0 ? W * ll : 0.0);
+            if (lane == 0) g(d.lpart)[tile] = tsum;
+        }
+    }
+}
+
+// ---------------------------------------------------------------- pre-order + gradient
+
+// With q the parent's pre-order vector (pi at the root), m_x = P_x p_x and
+// dm_x = dP_x p_x:  u_i = q o m_j, u_j = q o m_i; the children's pre-order
+// vectors P_i^T u_i, P_j^T u_j (rescaled as in the post-order pass) replace
+// their partials; the per-pattern gradient of branch i is
+// sum_r w_r u_i . dm_i over sum_r w_r u_i . m_i (likewise j).  Child i is
+// taken row by row, so at most four vectors per lane are live.
+template <typename T, int SP, int R>
+__global__ __launch_bounds__(kVL * R) void pre_vs_kernel(const ReqDesc* __restrict__ descs, const SegTable segs) {
+    __shared__ __align__(16) T tab[R][4][SP * SP];   // P_i, dP_i, P_j, dP_j of each category
+    __shared__ T xch[5][R][kVL];
+    const int r = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & (kVL - 1);
+    VsUnit U;
+    if (!vs_unit(descs, segs, U)) return;
+    const ReqDesc& d = *U.d;
+    const int N = d.N, S = d.S, Cpad = d.Cpad, tile = U.tile, tiles = d.tiles;
+    const int c = tile * kVL + lane;
+    const size_t mat = static_cast<size_t>(SP) * SP, bmat = static_cast<size_t>(SP + 1) * SP;
+    const size_t per = static_cast<size_t>(SP) * kVL;
+    GLOBAL T* part = g(static_cast<T*>(d.part));
+    const bool in_i = U.i >= N, in_j = U.j >= N;
+    const GLOBAL T* src_i = vs_src<T, SP>(d, U.i, tile, r);
+    const GLOBAL T* src_j = vs_src<T, SP>(d, U.j, tile, r);
+    {   // this category's tables of the children that take a product
+        const size_t oi = (static_cast<size_t>(U.ti) * R + r) * mat, oj = (static_cast<size_t>(U.tj) * R + r) * mat;
+        Stage<T, SP> a, da, b, db;
+        if (src_i) {
+            a.load(g(fwdP<T>(d)) + oi, lane);
+            da.load(g(fwddP<T>(d)) + oi, lane);
+        }
+        if (src_j) {
+            b.load(g(fwdP<T>(d)) + oj, lane);
+            db.load(g(fwddP<T>(d)) + oj, lane);
+        }
+        if (src_i) {
+            a.store(tab[r][0], lane);
+            da.store(tab[r][1], lane);
+        }
+        if (src_j) {
+            b.store(tab[r][2], lane);
+            db.store(tab[r][3], lane);
+        }
+    }
+    T q[SP];
+    if (U.k == 2 * N - 2) {
+#pragma unroll
+        for (int s = 0; s < SP; ++s) q[s] = s < S ? static_cast<T>(g(d.pi)[s]) : T(0);
+    } else {
+        vs_load<T, SP>(part + ((static_cast<size_t>(U.k - N) * tiles + tile) * R + r) * per, lane, q);
+    }
+    __syncthreads();
+    // child j: u_i = q o m_j and dm_j
+    T ui[SP], dmj[SP];
+    if (src_j) {
+        T v[SP];
+        vs_load<T, SP>(src_j, lane, v);
+#pragma unroll
+        for (int s = 0; s < SP; ++s) {
+            ui[s] = q[s] * vs_row<T, SP>(tab[r][2], s, v);
+            dmj[s] = vs_row<T, SP>(tab[r][3], s, v);
+            row_fence();
+        }
+    } else {
+        const size_t bo = (static_cast<size_t>(U.tj) * R + r) * bmat +
+                          tip_row<SP>(g(d.codes)[static_cast<size_t>(U.j) * Cpad + c], S);
+        const GLOBAL T* B = g(bwdP<T>(d)) + bo;
+        const GLOBAL T* B2 = g(bwddP<T>(d)) + bo;
+#pragma unroll
+        for (int s = 0; s < SP; ++s) {
+            ui[s] = q[s] * B[s];
+            dmj[s] = B2[s];
+        }
+    }
+    // child i, one state at a time: the sums, and q becomes u_j = q o m_i
+    T ni = T(0), nj = T(0), den = T(0);
+    if (src_i) {
+        T v[SP];
+        vs_load<T, SP>(src_i, lane, v);
+#pragma unroll
+        for (int s = 0; s < SP; ++s) {
+            const T m = vs_row<T, SP>(tab[r][0], s, v), dm = vs_row<T, SP>(tab[r][1], s, v);
+            ni = fma(ui[s], dm, ni);
+            den = fma(ui[s], m, den);
+            q[s] *= m;
+            nj = fma(q[s], dmj[s], nj);
+            row_fence();
+        }
+    } else {
+        const size_t bo = (static_cast<size_t>(U.ti) * R + r) * bmat +
+                          tip_row<SP>(g(d.codes)[static_cast<size_t>(U.i) * Cpad + c], S);
+        const GLOBAL T* B = g(bwdP<T>(d)) + bo;
+        const GLOBAL T* B2 = g(bwddP<T>(d)) + bo;
+#pragma unroll
+        for (int s = 0; s < SP; ++s) {
+            const T m = B[s], dm = B2[s];
+            ni = fma(ui[s], dm, ni);
+            den = fma(ui[s], m, den);
+            q[s] *= m;
+            nj = fma(q[s], dmj[s], nj);
+        }
+    }
+    // pre-order vectors of internal children: P^T u = sum_s u_s P[s][.]
+    T qi[SP], qj[SP];
+    T mxi = T(0), mxj = T(0);
+    if (in_i) {
+#pragma unroll
+        for (int t = 0; t < SP; ++t) qi[t] = T(0);
+#pragma unroll
+        for (int s = 0; s < SP; ++s) {
+            const T us = ui[s];
+#pragma unroll
+            for (int t = 0; t < SP; ++t) qi[t] = fma(tab[r][0][s * SP + t], us, qi[t]);
+            row_fence();
+        }
+#pragma unroll
+        for (int t = 0; t < SP; ++t) mxi = fmax(mxi, qi[t]);
+    }
+    if (in_j) {
+#pragma unroll
+        for (int t = 0; t < SP; ++t) qj[t] = T(0);
+#pragma unroll
+        for (int s = 0; s < SP; ++s) {
+            const T us = q[s];
+#pragma unroll
+            for (int t = 0; t < SP; ++t) qj[t] = fma(tab[r][2][s * SP + t], us, qj[t]);
+            row_fence();
+        }
+#pragma unroll
+        for (int t = 0; t < SP; ++t) mxj = fmax(mxj, qj[t]);
+    }
+    const T wr = static_cast<T>(g(d.cweights)[r]);
+    xch[0][r][lane] = wr * ni;
+    xch[1][r][lane] = wr * nj;
+    xch[2][r][lane] = wr * den;
+    xch[3][r][lane] = mxi;
+    xch[4][r][lane] = mxj;
+    __syncthreads();
+    T Ni = xch[0][0][lane], Nj = xch[1][0][lane], Dn = xch[2][0][lane];
+    T Mi = xch[3][0][lane], Mj = xch[4][0][lane];
+#pragma unroll
+    for (int rr = 1; rr < R; ++rr) {
+        Ni += xch[0][rr][lane];
+        Nj += xch[1][rr][lane];
+        Dn += xch[2][rr][lane];
+        Mi = fmax(Mi, xch[3][rr][lane]);
+        Mj = fmax(Mj, xch[4][rr][lane]);
+    }
+    if (in_i) {
+        const int e = exponent_of(Mi);
+#pragma unroll
+        for (int s = 0; s < SP; ++s) qi[s] = exact_ldexp(qi[s], -e);
+        vs_store<T, SP>(part + ((static_cast<size_t>(U.i - N) * tiles + tile) * R + r) * per, lane, qi);
+    }
+    if (in_j) {
+        const int e = exponent_of(Mj);
+#pragma unroll
+        for (int s = 0; s < SP; ++s) qj[s] = exact_ldexp(qj[s], -e);
+        vs_store<T, SP>(part + ((static_cast<size_t>(U.j - N) * tiles + tile) * R + r) * per, lane, qj);
+    }
+    if (r == 0) {
+        const double W = g(d.pw)[c];
+        const double di = (W != 0.0) ? W * (static_cast<double>(Ni) / static_cast<double>(Dn)) : 0.0;
+        const double dj = (W != 0.0) ? W * (static_cast<double>(Nj) / static_cast<double>(Dn)) : 0.0;
+        const double si = wave_sum(di), sj = wave_sum(dj);
+        if (lane == 0) {
+            g(d.gpart)[static_cast<size_t>(U.i) * tiles + tile] = si;
+            g(d.gpart)[static_cast<size_t>(U.j) * tiles + tile] = sj;
+        }
+    }
+}
+
+// ---------------------------------------------------------------- P(t) tables
+
+// One workgroup per (branch, category) pair: P and dP (FP64 sums stored in
+// the path's type) as zero-padded forward tables and as backward tables with
+// the row sums P 1 = V (e o Vinv 1), dP 1 in row SP.
+template <typename T, int SP>
+__global__ __launch_bounds__(256) void pmat_vs_kernel(const ReqDesc* __restrict__ descs, const SegTable segs) {
+    __shared__ double ex[SP], dex[SP];
+    const int unit = blockIdx.x;
+    if (unit >= segs.unit_begin[segs.n]) return;
+    const int sidx = seg_index(segs, unit);
+    const Segment& sg = segs.seg[sidx];
+    const ReqDesc& d = descs[sg.desc];
+    const int pair = unit - segs.unit_begin[sidx];   // table (branch or slot) * R + category
+    const int R = d.R, S = d.S;
+    const int slot = pair / R;
+    const int r = pair - slot * R;
+    int x = slot;                                    // the branch: its own table
+    if (sg.flags & 2) {                              // per-chunk tables: child (slot & 1) of record slot / 2
+        const GLOBAL int32_t* rec = g(sg.sched) + static_cast<size_t>(sg.sched_off + slot / 2) * 4;
+        x = (slot & 1) ? rec[2] : rec[1];
+    }
+    const double gr = d.rates[r];
+    const double bt = gr * d.b[x];
+    const double* lam = d.lam + (d.eig_cat ? r * S : 0);
+    const double* V = d.V + (d.eig_cat ? static_cast<size_t>(r) * S * S : 0);
+    const double* Vinv = d.Vinv + (d.eig_cat ? static_cast<size_t>(r) * S * S : 0);
+    const double* vs = d.vsum + (d.eig_cat ? r * S : 0);
+    for (int k = threadIdx.x; k < S; k += blockDim.x) {
+        const double e = exp(lam[k] * bt);
+        ex[k] = e;
+        dex[k] = gr * lam[k] * e;
+    }
+    __syncthreads();
+    GLOBAL T* F = g(fwdP<T>(d)) + static_cast<size_t>(pair) * SP * SP;
+    GLOBAL T* dF = g(fwddP<T>(d)) + static_cast<size_t>(pair) * SP * SP;
+    GLOBAL T* Bk = g(bwdP<T>(d)) + static_cast<size_t>(pair) * (SP + 1) * SP;
+    GLOBAL T* dB = g(bwddP<T>(d)) + static_cast<size_t>(pair) * (SP + 1) * SP;
+    for (int e = threadIdx.x; e < SP * SP; e += blockDim.x) {
+        const int s = e / SP, t = e - s * SP;
+        double acc = 0.0, dacc = 0.0;
+        if (s < S && t < S) {
+            for (int k = 0; k < S; ++k) {
+                const double v = V[s * S + k] * Vinv[k * S + t];
+                acc += v * ex[k];
+                dacc += v * dex[k];
+            }
+        }
+        F[e] = static_cast<T>(acc);
+        dF[e] = static_cast<T>(dacc);
+        Bk[t * SP + s] = static_cast<T>(acc);
+        dB[t * SP + s] = static_cast<T>(dacc);
+    }
+    for (int s = threadIdx.x; s < SP; s += blockDim.x) {
+        double rs = 0.0, drs = 0.0;
+        if (s < S)
+            for (int k = 0; k < S; ++k) {
+                const double a = V[s * S + k] * vs[k];
+                rs += a * ex[k];
+                drs += a * dex[k];
+            }
+        Bk[SP * SP + s] = static_cast<T>(rs);
+        dB[SP * SP + s] = static_cast<T>(drs);
+    }
+}
+
+template <typename T, int SP>
+hipError_t launch_vs_sp(KernelClass k, int R, const ReqDesc* descs, const SegTable& t, hipStream_t st) {
+    const int n_units = t.unit_begin[t.n];
+    if (k == kPmat) {
+        hipLaunchKernelGGL((pmat_vs_kernel<T, SP>), dim3(n_units), dim3(256), 0, st, descs, t);
+        return hipGetLastError();
+    }
+#define PHG_VS_CASE(RV)                                                                                    \
+    if constexpr (vs_lds_bytes(SP, RV, sizeof(T)) <= kVsLdsMax)                                            \
+    if (R == RV) {                                                                                         \
+        if (k == kPost)                                                                                    \
+            hipLaunchKernelGGL((post_vs_kernel<T, SP, RV>), dim3(n_units), dim3(kVL * RV), 0, st, descs, t); \
+        else                                                                                               \
+            hipLaunchKernelGGL((pre_vs_kernel<T, SP, RV>), dim3(n_units), dim3(kVL * RV), 0, st, descs, t);  \
+        return hipGetLastError();                                                                          \
+    }
+    PHG_VS_CASE(1)
+    PHG_VS_CASE(2)
+    PHG_VS_CASE(4)
+    PHG_VS_CASE(8)
+#undef PHG_VS_CASE
+    return hipErrorInvalidValue;
+}
+
+template <typename T>
+hipError_t launch_vs_t(KernelClass k, int S, int R, const ReqDesc* descs, const SegTable& t, hipStream_t st) {
+    if (vs_padded_states(S) == 20) return launch_vs_sp<T, 20>(k, R, descs, t, st);
+    if (vs_padded_states(S) == 24) return launch_vs_sp<T, 24>(k, R, descs, t, st);
+    if constexpr (sizeof(T) == 4) return launch_vs_sp<T, 32>(k, R, descs, t, st);
+    return hipErrorInvalidValue;   // FP64 takes these kernels up to 24 states
+}
+
+}  // namespace
+
+hipError_t launch_vs(KernelClass k, const ReqDesc& shape, const ReqDesc* descs, const SegTable& t,
+                     hipStream_t st) {
+    if (t.n <= 0 || t.unit_begin[t.n] <= 0) return hipSuccess;
+    if (shape.fp32) return launch_vs_t<float>(k, shape.S, shape.R, descs, t, st);
+    return launch_vs_t<double>(k, shape.S, shape.R, descs, t, st);
+}
+
+}  // namespace phg

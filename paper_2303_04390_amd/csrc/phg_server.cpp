@@ -304,6 +304,16 @@ struct Item {
     const ReqDesc* shape;
 };
 
+// Requests whose level launches can share one kernel: the 4-state kernels
+// per category count (and schedule), the vector-ALU kernels per category
+// count and padded state count, the MFMA kernels per 16-state block count
+// and tile size; always per precision.
+GroupKey level_key(KernelClass k, const ReqDesc& d) {
+    if (uses_s4_kernels(d.S, d.R)) return GroupKey{k, 1 + 2 * d.blocked, d.fp32, d.R};
+    if (uses_vs_kernels(d.S, d.R, d.fp32 != 0)) return GroupKey{k, 4, d.fp32, vs_padded_states(d.S) + 256 * d.R};
+    return GroupKey{k, 0, d.fp32, (d.S + 15) / 16 + 256 * (d.Cpad / d.tiles)};
+}
+
 // Build and issue one step for every active request; returns false on error.
 bool launch_step(phg_server* s) {
     std::map<GroupKey, std::vector<Item>> groups;
@@ -319,10 +329,13 @@ bool launch_step(phg_server* s) {
         GroupKey key{};
         if (st == 0) {
             // one P(t) kernel per launch: the 4-state one, the generic one
-            // (S <= 16) or the operand-order one of the MFMA kernels, which is
-            // typed by precision and launched over a grid of output tiles
-            const int kind = d.S == 4 ? 0 : (uses_gl_kernels(d.S, d.R) ? 1 : 2);
-            key = GroupKey{kPmat, kind, kind == 1 ? d.fp32 : 0, kind == 1 ? (gl_mat_rows(d.S) + 63) / 64 : 0};
+            // (S <= 16), the operand-order one of the MFMA kernels (typed by
+            // precision, launched over a grid of output tiles) or the padded
+            // one of the vector-ALU kernels (typed by precision and padding)
+            const bool f32 = d.fp32 != 0;
+            const int kind = d.S == 4 ? 0 : uses_gl_kernels(d.S, d.R, f32) ? 1 : uses_vs_kernels(d.S, d.R, f32) ? 3 : 2;
+            key = GroupKey{kPmat, kind, kind == 1 || kind == 3 ? d.fp32 : 0,
+                           kind == 1 ? (gl_mat_rows(d.S) + 63) / 64 : (kind == 3 ? vs_padded_states(d.S) : 0)};
             it.units = units_for(kPmat, d, 0);
         } else if (st <= t->H) {
             const int l = st - 1, a = c->post_lv[l].first, n = c->post_lv[l].second;
@@ -330,15 +343,13 @@ bool launch_step(phg_server* s) {
             it.seg.n_nodes = n;
             it.seg.flags = (l == t->H - 1) ? 1 : 0;
             it.units = units_for(kPost, d, n);
-            key = GroupKey{kPost, uses_s4_kernels(d.S, d.R) + 2 * d.blocked, d.fp32,
-                           uses_s4_kernels(d.S, d.R) ? d.R : (d.S + 15) / 16 + 256 * (d.Cpad / d.tiles)};
+            key = level_key(kPost, d);
         } else if (st <= t->H + t->D) {
             const int l = st - t->H - 1, a = c->pre_lv[l].first, n = c->pre_lv[l].second;
             it.seg.sched_off = a;
             it.seg.n_nodes = n;
             it.units = units_for(kPre, d, n);
-            key = GroupKey{kPre, uses_s4_kernels(d.S, d.R) + 2 * d.blocked, d.fp32,
-                           uses_s4_kernels(d.S, d.R) ? d.R : (d.S + 15) / 16 + 256 * (d.Cpad / d.tiles)};
+            key = level_key(kPre, d);
         } else {
             double* out = ctx_out_dev(c);
             it.seg.out_logl = out;

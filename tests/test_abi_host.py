@@ -351,12 +351,17 @@ def test_tuning_table_validation():
         assert B.phg_get_tuning(4, 2, f32, NU) == 0     # another category count
         with pytest.raises(B.PhgError):
             B.phg_set_tuning(4, 4, f64, NU, 1000)
-        # the context's tile follows the row blocks in effect at creation
+        # the context's tile follows the row blocks in effect at creation on
+        # the MFMA kernels (20 states at 3 categories); the vector-ALU kernels
+        # (20 states at 4 categories) have a fixed 64-pattern tile
         B.phg_set_tuning(20, 0, f32, RB, 4)
-        big = B.phg_workspace_size(100, 1000, 20, 4, f32)
+        big = B.phg_workspace_size(100, 1000, 20, 3, f32)
+        vs_a = B.phg_workspace_size(100, 1000, 20, 4, f32)
         B.phg_set_tuning(20, 0, f32, RB, 1)
-        small = B.phg_workspace_size(100, 1000, 20, 4, f32)
+        small = B.phg_workspace_size(100, 1000, 20, 3, f32)
+        vs_b = B.phg_workspace_size(100, 1000, 20, 4, f32)
         assert big != small                             # per-tile sums: Cpad / tile of them
+        assert vs_a == vs_b
     finally:
         B.phg_set_tuning(4, 4, f32, NU, 0)
         B.phg_set_tuning(20, 0, f32, RB, 0)

@@ -1,6 +1,6 @@
 """One substitution model per rate category on the GPU (phg_set_category_eigen)
 against the oracle, at the standard bars, for 4 states (both schedules, both
-precisions) and for 20 states (MFMA kernels)."""
+precisions) and for 20 states (MFMA and vector-ALU kernels)."""
 import numpy as np
 import pytest
 
@@ -39,14 +39,15 @@ def test_four_states_per_category_models(prec, schedule):
     check(f"cat-models-S4/{prec}/{schedule}", logl, grad, ref, *TOL[prec])
 
 
+@pytest.mark.parametrize("R", [3, 4])     # MFMA kernels, vector-ALU kernels
 @pytest.mark.parametrize("prec", [B.PHG_FP32_SCALED, B.PHG_FP64])
-def test_twenty_states_per_category_models(prec):
-    prob = cat_problem(40, 230, 20, 3, seed=2)
+def test_twenty_states_per_category_models(prec, R):
+    prob = cat_problem(40, 230, 20, R, seed=2)
     ref = oracle.evaluate_problem(prob)
-    print(f"[case] per-category S=20 prec={prec}", flush=True)
+    print(f"[case] per-category S=20 R={R} prec={prec}", flush=True)
     with B.Context.for_problem(prob, prec) as ctx:
         logl, grad = ctx.gradient()
-    check(f"cat-models-S20/{prec}", logl, grad, ref, *TOL[prec])
+    check(f"cat-models-S20-R{R}/{prec}", logl, grad, ref, *TOL[prec])
 
 
 def test_identical_category_models_match_the_shared_model_bitwise():

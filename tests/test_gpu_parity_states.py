@@ -67,6 +67,7 @@ def test_codon128_full(codon128, prec):
 
 @pytest.mark.parametrize("S,N,C", [(20, 9, 1), (20, 9, 37), (20, 9, 100), (61, 6, 33), (61, 6, 70),
                                    (2, 12, 50), (3, 12, 50), (5, 12, 50), (16, 12, 50), (17, 12, 50),
+                                   (21, 10, 70), (24, 9, 130), (25, 8, 65), (32, 7, 129),
                                    (33, 8, 50), (40, 7, 31), (48, 9, 97), (49, 7, 65), (64, 6, 40)])
 def test_state_counts_and_ragged_tiles(S, N, C):
     prob = generic_problem(N, S, C, seed=S * 100 + C)
@@ -75,7 +76,7 @@ def test_state_counts_and_ragged_tiles(S, N, C):
         compare(f"S{S}-N{N}-C{C}", prob, prec, ref)
 
 
-@pytest.mark.parametrize("R", [1, 3, 16])
+@pytest.mark.parametrize("R", [1, 2, 3, 8, 16])
 def test_categories_generic(R):
     prob = generic_problem(10, 20, 80, seed=R, R=R)
     ref = oracle.evaluate_problem(prob)
@@ -161,29 +162,37 @@ def test_bench_shapes_large_states(which):
         compare(which, prob, prec, ref)
 
 
-def _gl_table_bytes_per_branch(S, R, prec):
-    """P, dP (gl_mat_rows rows) and their backward copies (one more row) for
-    one branch: the unit the table budget is counted in."""
+def _table_bytes_per_branch(S, R, prec):
+    """The unit the table budget is counted in: P, dP and their backward
+    copies for one branch.  Vector-ALU kernels (17..32 states, FP64 up to 24,
+    R in 1, 2, 4, 8): [SP][SP] forward and [SP + 1][SP] backward tables, SP
+    the state count padded to 20, 24 or 32.  MFMA kernels: gl_mat_rows rows
+    of the operand-order row length, backward copies one row more."""
+    fp32 = prec == B.PHG_FP32_SCALED
+    tsz = 4 if fp32 else 8
+    if 16 < S <= (32 if fp32 else 24) and R in (1, 2, 4, 8):
+        SP = 20 if S <= 20 else (24 if S <= 24 else 32)
+        return R * (2 * SP * SP + 2 * (SP + 1) * SP) * tsz
     G = 2 if S <= 32 else 4
     row = 4 * (((S + 3) // 4 + G - 1) // G * G)
     rows = (S + 15) // 16 * 16 if S <= 64 else (S + 63) // 64 * 64
-    return R * (2 * rows + 2 * (rows + 1)) * row * (4 if prec == B.PHG_FP32_SCALED else 8)
+    return R * (2 * rows + 2 * (rows + 1)) * row * tsz
 
 
-@pytest.mark.parametrize("S,N,C", [(20, 30, 70), (61, 12, 40), (256, 10, 20)])
-def test_per_chunk_tables_match_full_tables(S, N, C):
+@pytest.mark.parametrize("S,N,C,R", [(20, 30, 70, 2), (20, 30, 70, 3), (61, 12, 40, 2), (256, 10, 20, 2)])
+def test_per_chunk_tables_match_full_tables(S, N, C, R):
     """Under a small table budget the context holds a pool of branch tables
     and rebuilds them per launch chunk; its results are bitwise those of the
     full tables, and both meet the oracle bar."""
-    prob = generic_problem(N, S, C, seed=S + 7, R=2, mean_b=0.05)
+    prob = generic_problem(N, S, C, seed=S + 7, R=R, mean_b=0.05)
     ref = oracle.evaluate_problem(prob)
     for prec in (B.PHG_FP64, B.PHG_FP32_SCALED):
-        print(f"[case] per-chunk tables S={S} N={N} C={C} {NAME[prec]}", flush=True)
+        print(f"[case] per-chunk tables S={S} N={N} C={C} R={R} {NAME[prec]}", flush=True)
         with B.Context.for_problem(prob, prec) as full:
             assert B.phg_table_slots(full.handle) == 0
             lf, gf = full.gradient()
         check(f"S{S}-full/{NAME[prec]}", lf, gf, ref, *TOL[prec])
-        per = _gl_table_bytes_per_branch(S, prob.n_categories, prec)
+        per = _table_bytes_per_branch(S, prob.n_categories, prec)
         for budget, slots in ((1, 2), (7 * per, 6)):
             ctx = B.Context(prob.n_tips, prob.n_patterns, S, prob.n_categories, prec)
             try:

@@ -1,6 +1,7 @@
 """General tip partial vectors (phg_set_tip_partials) on the GPU, against the
 oracle: every level-kernel family they run on (4 states; up to 16 states or
-R > 8; 17..255 states with and without LDS-staged inputs), both precisions,
+R > 8; 17..32 states on the vector ALUs; above 16 states on the MFMA kernels
+with and without LDS-staged inputs), both precisions,
 ragged tiles, cherries of two such tips."""
 import numpy as np
 import pytest
@@ -29,7 +30,7 @@ def with_vectors(prob, frac, seed):
 
 
 @pytest.mark.parametrize("S,N,C,R", [(4, 40, 150, 4), (4, 30, 70, 16), (8, 25, 90, 3), (20, 20, 80, 4),
-                                     (61, 10, 45, 2), (122, 8, 33, 2)])
+                                     (20, 12, 50, 3), (28, 15, 70, 2), (61, 10, 45, 2), (122, 8, 33, 2)])
 @pytest.mark.parametrize("prec", [B.PHG_FP32_SCALED, B.PHG_FP64])
 def test_tip_vectors_match_oracle(S, N, C, R, prec):
     prob = with_vectors(generic_problem(N, S, C, seed=S * 7 + C, R=R, mean_b=0.1), 0.35, seed=S + N)
