@@ -318,10 +318,21 @@ void build_schedule(phg_context* ctx) {
         for (int m = 0; m <= M; ++m) ctx->pre_lv.emplace_back(start[m], start[m + 1] - start[m]);
         return;
     }
+    // vector-ALU kernels with tables for every branch: fold the internal nodes
+    // (but the root) whose two children are tips given by codes -- their
+    // launch stores the exponent only; the parent forms the partial from the
+    // tips
+    std::vector<char> folded(n, 0);
+    if (phg::uses_vs_kernels(ctx->S, ctx->R, fp32) &&
+        table_slots_for(N, ctx->S, ctx->R, ctx->prec, ctx->table_budget) == 0) {
+        for (int v = N; v < root; ++v)
+            folded[v] = c0[v] < N && c1[v] < N && !ctx->tip_vectors.count(c0[v]) && !ctx->tip_vectors.count(c1[v]);
+    }
     std::vector<std::vector<int>> by(H + 1);
     for (int v = N; v < n; ++v) by[height[v]].push_back(v);
     auto put = [&](int v) {
-        const int32_t rec[4] = {v, c0[v], c1[v], 0};
+        const int32_t rec[4] = {v, c0[v], c1[v],
+                                (folded[c0[v]] ? 1 : 0) | (folded[c1[v]] ? 2 : 0) | (folded[v] ? 4 : 0)};
         ctx->sched.insert(ctx->sched.end(), rec, rec + 4);
     };
     for (int h = 1; h <= H; ++h) {
@@ -403,6 +414,7 @@ phg_status ensure_device(phg_context* ctx) {
     d.eig_cat = ctx->eig_cat ? 1 : 0;
     d.level_tables = ctx->table_slots > 0 ? 1 : 0;
     d.sched = reinterpret_cast<const NodeTriple*>(a + pl.sched);
+    d.kids = reinterpret_cast<const int32_t*>(a + pl.ch_kids);
     d.codes = reinterpret_cast<const uint8_t*>(a + pl.codes);
     d.part = a + pl.part;
     d.expo = reinterpret_cast<int32_t*>(a + pl.expo);
@@ -1088,7 +1100,6 @@ phg_status phg_set_tip_partials(phg_context* ctx, int tip, const double* partial
     if (partials && ctx->sched_mode == PHG_SCHEDULE_BLOCKS)
         return ctx->fail(PHG_ERR_ARG, "general tip partials need the level schedule (schedule is BLOCKS)");
     const size_t n = static_cast<size_t>(ctx->C) * ctx->S;
-    const bool had_any = !ctx->tip_vectors.empty();
     if (partials) {
         for (size_t i = 0; i < n; ++i)
             if (!std::isfinite(partials[i]) || partials[i] < 0.0)
@@ -1098,8 +1109,9 @@ phg_status phg_set_tip_partials(phg_context* ctx, int tip, const double* partial
     } else {
         ctx->tip_vectors.erase(tip);
     }
-    // the schedule depends on whether any tip has a general vector
-    if (had_any != !ctx->tip_vectors.empty() && (ctx->have & kTopo)) {
+    // the schedule depends on whether any tip has a general vector (blocked
+    // schedule) and on which tips have one (folded nodes)
+    if (ctx->have & kTopo) {
         build_schedule(ctx);
         ctx->dirty |= kTopo;
         ctx->sdirty |= kTopo;
@@ -1311,6 +1323,11 @@ phg_status phg_set_table_budget(phg_context* ctx, size_t bytes) {
     if (ctx->dev_init) return ctx->fail(PHG_ERR_STATE, "the table budget must be set before first use");
     ctx->table_budget = bytes;
     if (ctx->twin) ctx->twin->table_budget = bytes;
+    if (ctx->have & kTopo) {   // folded nodes need tables for every branch
+        build_schedule(ctx);
+        ctx->dirty |= kTopo;
+        ctx->sdirty |= kTopo;
+    }
     return PHG_OK;
 }
 

@@ -14,9 +14,14 @@ constexpr int kLanes = 64;          // one wavefront = one tile of 64 site patte
 
 // One parent with its two children, by node id.  Post-order levels list the
 // internal nodes of equal height; pre-order levels the internal nodes of
-// equal depth.  Children are stored in ascending id order.
+// equal depth.  Children are stored in ascending id order.  fold (vector-ALU
+// kernels only): bit 0 / bit 1 set when child i / j is a folded node -- an
+// internal node (not the root) whose two children are tips given by codes --
+// and bit 2 when node k is one.  A folded node's post-order launch stores
+// its exponent but not its partial; its parent forms that partial from the
+// two tips' rows of the P(t) tables, scaled by the exponent.
 struct NodeTriple {
-    int32_t k, i, j, pad;
+    int32_t k, i, j, fold;
 };
 
 // A block of the tree for the blocked 4-state schedule: a block root at a
@@ -68,6 +73,7 @@ struct ReqDesc {
                             // the chunk's node n), built by a P(t) launch over the same records
     int32_t eig_cat;        // 1: V, Vinv [R][S][S] and lam [R][S], one model per category
     const NodeTriple* sched;
+    const int32_t* kids;    // [N-1][2] children of internal node N + k
     const uint8_t* codes;
     void* part;
     int32_t* expo;
@@ -189,7 +195,7 @@ hipError_t launch_chain(const ChainArgs& a, bool time_tree, hipStream_t stream);
 // in LDS.  Their vectors and tables are padded to vs_padded_states(S) states.
 __host__ __device__ constexpr inline int vs_padded_states(int S) { return S <= 20 ? 20 : (S <= 24 ? 24 : 32); }
 // LDS of a pre-order workgroup: P and dP of both children for each category,
-// and the five per-pattern exchange values per category.  Shapes above
+// and five per-pattern exchange values per category.  Shapes above
 // kVsLdsMax (two workgroups per CU) stay on the MFMA kernels.
 __host__ __device__ constexpr inline size_t vs_lds_bytes(int SP, int R, int tsz) {
     return static_cast<size_t>(R) * (4 * SP * SP + 5 * 64) * tsz;

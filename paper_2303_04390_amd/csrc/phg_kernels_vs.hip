@@ -25,6 +25,12 @@
 // dP e_y (row SP for the ambiguous code S); P^T u accumulates the rows of
 // the forward table, P^T u = sum_s u_s P[s][.].
 //
+// An internal node whose two children are tips given by codes is folded
+// (when every branch has its tables): its post-order launch stores only its
+// exponent, and its parent forms (P_a e_ya) o (P_b e_yb) from two table rows,
+// scaled by it -- bit for bit the vector that would have been stored, at
+// less cost than writing and reading it.
+//
 // Scaling as in the 4-state kernels: one power-of-two exponent per (node,
 // pattern) shared by all categories; stored post-order partials are
 // normalised and the exponents cumulative per subtree; pre-order vectors are
@@ -165,6 +171,8 @@ struct VsUnit {
     Segment sg;
     int i, j, k, tile;
     int ti, tj;   // P(t) tables of the children: by branch, or by slot in per-chunk tables
+    bool fi, fj;  // child i / j is a folded node
+    bool fk;      // this node is folded (store its exponent only)
 };
 __device__ __forceinline__ bool vs_unit(const ReqDesc* __restrict__ descs, const SegTable& segs, VsUnit& U) {
     const int unit = blockIdx.x;
@@ -182,7 +190,37 @@ __device__ __forceinline__ bool vs_unit(const ReqDesc* __restrict__ descs, const
     U.j = rec[2];
     U.ti = U.d->level_tables ? 2 * node_ix : U.i;
     U.tj = U.d->level_tables ? 2 * node_ix + 1 : U.j;
+    U.fi = (rec[3] & 1) != 0;
+    U.fj = (rec[3] & 2) != 0;
+    U.fk = (rec[3] & 4) != 0;
     return true;
+}
+
+// A folded child x (internal, both children a, b tips given by codes): its
+// partial (P_a e_ya) o (P_b e_yb) is not stored; its post-order launch
+// stores only its exponent e, and consumers form the partial from two rows
+// of the backward tables (folding needs tables for every branch), scaled by
+// 2^-e: bit for bit the vector that launch would have stored.
+template <typename T, int SP>
+__device__ __forceinline__ void vs_folded(const ReqDesc& d, int x, int r, int c, int e, T (&v)[SP]) {
+    const GLOBAL int32_t* kk = g(d.kids) + 2 * static_cast<size_t>(x - d.N);
+    const int a = kk[0], b = kk[1];
+    const size_t bmat = static_cast<size_t>(SP + 1) * SP;
+    const GLOBAL T* Ba = g(bwdP<T>(d)) + (static_cast<size_t>(a) * d.R + r) * bmat +
+                         tip_row<SP>(g(d.codes)[static_cast<size_t>(a) * d.Cpad + c], d.S);
+    const GLOBAL T* Bb = g(bwdP<T>(d)) + (static_cast<size_t>(b) * d.R + r) * bmat +
+                         tip_row<SP>(g(d.codes)[static_cast<size_t>(b) * d.Cpad + c], d.S);
+#pragma unroll
+    for (int s = 0; s < SP; ++s) v[s] = exact_ldexp(Ba[s] * Bb[s], -e);
+}
+// Child x's input vector: folded (formed from its tips, exponent e) or loaded.
+template <typename T, int SP>
+__device__ __forceinline__ void vs_input(const ReqDesc& d, bool folded, int e, const GLOBAL T* src, int x, int r,
+                                         int c, int lane, T (&v)[SP]) {
+    if (folded)
+        vs_folded<T, SP>(d, x, r, c, e, v);
+    else
+        vs_load<T, SP>(src, lane, v);
 }
 
 // ---------------------------------------------------------------- post-order
@@ -202,24 +240,25 @@ __global__ __launch_bounds__(kVL * R) void post_vs_kernel(const ReqDesc* __restr
     const int N = d.N, S = d.S, Cpad = d.Cpad, tile = U.tile;
     const int c = tile * kVL + lane;
     const size_t mat = static_cast<size_t>(SP) * SP, bmat = static_cast<size_t>(SP + 1) * SP;
+    // children that take a product: internal (stored or folded) or general tip vectors
     const GLOBAL T* src_i = vs_src<T, SP>(d, U.i, tile, r);
     const GLOBAL T* src_j = vs_src<T, SP>(d, U.j, tile, r);
-    {   // this category's tables of the children that take a product
+    {   // this category's tables of those children
         Stage<T, SP> si, sj;
         if (src_i) si.load(g(fwdP<T>(d)) + (static_cast<size_t>(U.ti) * R + r) * mat, lane);
         if (src_j) sj.load(g(fwdP<T>(d)) + (static_cast<size_t>(U.tj) * R + r) * mat, lane);
         if (src_i) si.store(tab[r][0], lane);
         if (src_j) sj.store(tab[r][1], lane);
     }
-    // the children's cumulative exponents
-    int ec = 0;
-    if (U.i >= N) ec += g(d.expo)[static_cast<size_t>(U.i - N) * Cpad + c];
-    if (U.j >= N) ec += g(d.expo)[static_cast<size_t>(U.j - N) * Cpad + c];
+    // the children's cumulative exponents (a folded child's is its own)
+    const int ei = U.i >= N ? g(d.expo)[static_cast<size_t>(U.i - N) * Cpad + c] : 0;
+    const int ej = U.j >= N ? g(d.expo)[static_cast<size_t>(U.j - N) * Cpad + c] : 0;
+    const int ec = ei + ej;
     __syncthreads();
     T p[SP];
     if (src_i) {   // p = P_i p_i
         T v[SP];
-        vs_load<T, SP>(src_i, lane, v);
+        vs_input<T, SP>(d, U.fi, ei, src_i, U.i, r, c, lane, v);
 #pragma unroll
         for (int s = 0; s < SP; ++s) {
             p[s] = vs_row<T, SP>(tab[r][0], s, v);
@@ -233,7 +272,7 @@ __global__ __launch_bounds__(kVL * R) void post_vs_kernel(const ReqDesc* __restr
     }
     if (src_j) {   // p *= P_j p_j
         T v[SP];
-        vs_load<T, SP>(src_j, lane, v);
+        vs_input<T, SP>(d, U.fj, ej, src_j, U.j, r, c, lane, v);
 #pragma unroll
         for (int s = 0; s < SP; ++s) {
             p[s] *= vs_row<T, SP>(tab[r][1], s, v);
@@ -255,11 +294,13 @@ __global__ __launch_bounds__(kVL * R) void post_vs_kernel(const ReqDesc* __restr
 #pragma unroll
         for (int rr = 1; rr < R; ++rr) mx = fmax(mx, xmax[rr][lane]);
         const int e = exponent_of(mx);
+        if (!U.fk) {   // a folded node's partial is formed again by its parent
 #pragma unroll
-        for (int s = 0; s < SP; ++s) p[s] = exact_ldexp(p[s], -e);
-        vs_store<T, SP>(g(static_cast<T*>(d.part)) +
-                            ((static_cast<size_t>(U.k - N) * d.tiles + tile) * R + r) * SP * kVL,
-                        lane, p);
+            for (int s = 0; s < SP; ++s) p[s] = exact_ldexp(p[s], -e);
+            vs_store<T, SP>(g(static_cast<T*>(d.part)) +
+                                ((static_cast<size_t>(U.k - N) * d.tiles + tile) * R + r) * SP * kVL,
+                            lane, p);
+        }
         if (r == 0) g(d.expo)[static_cast<size_t>(U.k - N) * Cpad + c] = e + ec;
     } else {
         // root: site likelihood sum_r w_r pi . p_r, categories summed in a fixed order
@@ -334,12 +375,14 @@ __global__ __launch_bounds__(kVL * R) void pre_vs_kernel(const ReqDesc* __restri
     } else {
         vs_load<T, SP>(part + ((static_cast<size_t>(U.k - N) * tiles + tile) * R + r) * per, lane, q);
     }
+    const int efi = U.fi ? g(d.expo)[static_cast<size_t>(U.i - N) * Cpad + c] : 0;
+    const int efj = U.fj ? g(d.expo)[static_cast<size_t>(U.j - N) * Cpad + c] : 0;
     __syncthreads();
     // child j: u_i = q o m_j and dm_j
     T ui[SP], dmj[SP];
     if (src_j) {
         T v[SP];
-        vs_load<T, SP>(src_j, lane, v);
+        vs_input<T, SP>(d, U.fj, efj, src_j, U.j, r, c, lane, v);
 #pragma unroll
         for (int s = 0; s < SP; ++s) {
             ui[s] = q[s] * vs_row<T, SP>(tab[r][2], s, v);
@@ -361,7 +404,7 @@ __global__ __launch_bounds__(kVL * R) void pre_vs_kernel(const ReqDesc* __restri
     T ni = T(0), nj = T(0), den = T(0);
     if (src_i) {
         T v[SP];
-        vs_load<T, SP>(src_i, lane, v);
+        vs_input<T, SP>(d, U.fi, efi, src_i, U.i, r, c, lane, v);
 #pragma unroll
         for (int s = 0; s < SP; ++s) {
             const T m = vs_row<T, SP>(tab[r][0], s, v), dm = vs_row<T, SP>(tab[r][1], s, v);
