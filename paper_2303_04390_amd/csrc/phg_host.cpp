@@ -320,8 +320,9 @@ void build_schedule(phg_context* ctx) {
     }
     // vector-ALU kernels with tables for every branch: fold the internal nodes
     // (but the root) whose two children are tips given by codes -- their
-    // launch stores the exponent only; the parent forms the partial from the
-    // tips
+    // post-order launch stores the exponent only and they have no pre-order
+    // launch; the parent forms the partial from the tips and the tips'
+    // gradient sums from the node's pre-order vector
     std::vector<char> folded(n, 0);
     if (phg::uses_vs_kernels(ctx->S, ctx->R, fp32) &&
         table_slots_for(N, ctx->S, ctx->R, ctx->prec, ctx->table_budget) == 0) {
@@ -341,8 +342,10 @@ void build_schedule(phg_context* ctx) {
         ctx->post_lv.emplace_back(a, static_cast<int>(ctx->sched.size() / 4) - a);
     }
     std::vector<std::vector<int>> bd(D + 1);
-    for (int v = N; v < n; ++v) bd[depth[v]].push_back(v);
+    for (int v = N; v < n; ++v)
+        if (!folded[v]) bd[depth[v]].push_back(v);   // a folded node's parent forms its tip gradients
     for (int d = 0; d <= D; ++d) {
+        if (bd[d].empty()) continue;
         const int a = static_cast<int>(ctx->sched.size() / 4);
         for (int v : bd[d]) put(v);
         ctx->pre_lv.emplace_back(a, static_cast<int>(ctx->sched.size() / 4) - a);

@@ -19,7 +19,9 @@ constexpr int kLanes = 64;          // one wavefront = one tile of 64 site patte
 // internal node (not the root) whose two children are tips given by codes --
 // and bit 2 when node k is one.  A folded node's post-order launch stores
 // its exponent but not its partial; its parent forms that partial from the
-// two tips' rows of the P(t) tables, scaled by the exponent.
+// two tips' rows of the P(t) tables, scaled by the exponent.  Folded nodes
+// have no pre-order record: the parent's pre-order launch forms the gradient
+// sums of their tip branches.
 struct NodeTriple {
     int32_t k, i, j, fold;
 };
@@ -195,10 +197,10 @@ hipError_t launch_chain(const ChainArgs& a, bool time_tree, hipStream_t stream);
 // in LDS.  Their vectors and tables are padded to vs_padded_states(S) states.
 __host__ __device__ constexpr inline int vs_padded_states(int S) { return S <= 20 ? 20 : (S <= 24 ? 24 : 32); }
 // LDS of a pre-order workgroup: P and dP of both children for each category,
-// and five per-pattern exchange values per category.  Shapes above
+// and eleven per-pattern exchange values per category.  Shapes above
 // kVsLdsMax (two workgroups per CU) stay on the MFMA kernels.
 __host__ __device__ constexpr inline size_t vs_lds_bytes(int SP, int R, int tsz) {
-    return static_cast<size_t>(R) * (4 * SP * SP + 5 * 64) * tsz;
+    return static_cast<size_t>(R) * (4 * SP * SP + 11 * 64) * tsz;
 }
 constexpr size_t kVsLdsMax = size_t{80} << 10;
 inline bool uses_vs_kernels(int S, int R, bool fp32) {

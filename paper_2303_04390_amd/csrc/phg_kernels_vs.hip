@@ -29,7 +29,9 @@
 // (when every branch has its tables): its post-order launch stores only its
 // exponent, and its parent forms (P_a e_ya) o (P_b e_yb) from two table rows,
 // scaled by it -- bit for bit the vector that would have been stored, at
-// less cost than writing and reading it.
+// less cost than writing and reading it.  It has no pre-order launch: its
+// parent turns the folded node's pre-order vector into the gradient sums of
+// the two tip branches at once, by the operations that launch would use.
 //
 // Scaling as in the 4-state kernels: one power-of-two exponent per (node,
 // pattern) shared by all categories; stored post-order partials are
@@ -223,6 +225,64 @@ __device__ __forceinline__ void vs_input(const ReqDesc& d, bool folded, int e, c
         vs_load<T, SP>(src, lane, v);
 }
 
+// The gradient sums of a folded node x's two tip branches a < b, formed from
+// x's rescaled pre-order vector q by the same operations as a pre-order
+// launch of x would use: with m, dm the tips' table rows, u_a = q o m_b and
+// u_b = q o m_a, na = u_a . dm_a, nb = u_b . dm_b, den = u_a . m_a.
+// Consumes q.
+template <typename T, int SP>
+__device__ __forceinline__ void folded_grad_sums(const ReqDesc& d, int x, int r, int c, T (&q)[SP], T& na, T& nb,
+                                                 T& den) {
+    const GLOBAL int32_t* kk = g(d.kids) + 2 * static_cast<size_t>(x - d.N);
+    const int a = kk[0], b = kk[1];
+    const size_t bmat = static_cast<size_t>(SP + 1) * SP;
+    const size_t oa = (static_cast<size_t>(a) * d.R + r) * bmat +
+                      tip_row<SP>(g(d.codes)[static_cast<size_t>(a) * d.Cpad + c], d.S);
+    const size_t ob = (static_cast<size_t>(b) * d.R + r) * bmat +
+                      tip_row<SP>(g(d.codes)[static_cast<size_t>(b) * d.Cpad + c], d.S);
+    const GLOBAL T* P = g(bwdP<T>(d));
+    const GLOBAL T* dP = g(bwddP<T>(d));
+    T ua[SP], dmb[SP];
+#pragma unroll
+    for (int s = 0; s < SP; ++s) {
+        ua[s] = q[s] * P[ob + s];
+        dmb[s] = dP[ob + s];
+    }
+    na = T(0);
+    nb = T(0);
+    den = T(0);
+#pragma unroll
+    for (int s = 0; s < SP; ++s) {
+        const T m = P[oa + s], dm = dP[oa + s];
+        na = fma(ua[s], dm, na);
+        den = fma(ua[s], m, den);
+        q[s] *= m;
+        nb = fma(q[s], dmb[s], nb);
+    }
+}
+
+// Per-tile gradient sums of branches bi, bj from the categories' weighted
+// numerators and denominator in LDS (wave 0).
+template <typename T, int R>
+__device__ __forceinline__ void write_grad(const ReqDesc& d, const T (&xn_i)[R][kVL], const T (&xn_j)[R][kVL],
+                                           const T (&xden)[R][kVL], int lane, int c, int tile, int bi, int bj) {
+    T Ni = xn_i[0][lane], Nj = xn_j[0][lane], Dn = xden[0][lane];
+#pragma unroll
+    for (int rr = 1; rr < R; ++rr) {
+        Ni += xn_i[rr][lane];
+        Nj += xn_j[rr][lane];
+        Dn += xden[rr][lane];
+    }
+    const double W = g(d.pw)[c];
+    const double di = (W != 0.0) ? W * (static_cast<double>(Ni) / static_cast<double>(Dn)) : 0.0;
+    const double dj = (W != 0.0) ? W * (static_cast<double>(Nj) / static_cast<double>(Dn)) : 0.0;
+    const double si = wave_sum(di), sj = wave_sum(dj);
+    if (lane == 0) {
+        g(d.gpart)[static_cast<size_t>(bi) * d.tiles + tile] = si;
+        g(d.gpart)[static_cast<size_t>(bj) * d.tiles + tile] = sj;
+    }
+}
+
 // ---------------------------------------------------------------- post-order
 
 // p_k = (P_i p_i) o (P_j p_j) per category, rescaled by the largest entry
@@ -335,6 +395,7 @@ template <typename T, int SP, int R>
 __global__ __launch_bounds__(kVL * R) void pre_vs_kernel(const ReqDesc* __restrict__ descs, const SegTable segs) {
     __shared__ __align__(16) T tab[R][4][SP * SP];   // P_i, dP_i, P_j, dP_j of each category
     __shared__ T xch[5][R][kVL];
+    __shared__ T xg[6][R][kVL];                      // folded children's gradient sums
     const int r = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & (kVL - 1);
     VsUnit U;
@@ -464,37 +525,48 @@ __global__ __launch_bounds__(kVL * R) void pre_vs_kernel(const ReqDesc* __restri
     xch[3][r][lane] = mxi;
     xch[4][r][lane] = mxj;
     __syncthreads();
-    T Ni = xch[0][0][lane], Nj = xch[1][0][lane], Dn = xch[2][0][lane];
     T Mi = xch[3][0][lane], Mj = xch[4][0][lane];
 #pragma unroll
     for (int rr = 1; rr < R; ++rr) {
-        Ni += xch[0][rr][lane];
-        Nj += xch[1][rr][lane];
-        Dn += xch[2][rr][lane];
         Mi = fmax(Mi, xch[3][rr][lane]);
         Mj = fmax(Mj, xch[4][rr][lane]);
     }
+    // a child's rescaled pre-order vector is stored, or, for a folded child,
+    // turned into its tip branches' gradient sums at once
     if (in_i) {
         const int e = exponent_of(Mi);
 #pragma unroll
         for (int s = 0; s < SP; ++s) qi[s] = exact_ldexp(qi[s], -e);
-        vs_store<T, SP>(part + ((static_cast<size_t>(U.i - N) * tiles + tile) * R + r) * per, lane, qi);
+        if (U.fi) {
+            T na, nb, dn;
+            folded_grad_sums<T, SP>(d, U.i, r, c, qi, na, nb, dn);
+            xg[0][r][lane] = wr * na;
+            xg[1][r][lane] = wr * nb;
+            xg[2][r][lane] = wr * dn;
+        } else {
+            vs_store<T, SP>(part + ((static_cast<size_t>(U.i - N) * tiles + tile) * R + r) * per, lane, qi);
+        }
     }
     if (in_j) {
         const int e = exponent_of(Mj);
 #pragma unroll
         for (int s = 0; s < SP; ++s) qj[s] = exact_ldexp(qj[s], -e);
-        vs_store<T, SP>(part + ((static_cast<size_t>(U.j - N) * tiles + tile) * R + r) * per, lane, qj);
-    }
-    if (r == 0) {
-        const double W = g(d.pw)[c];
-        const double di = (W != 0.0) ? W * (static_cast<double>(Ni) / static_cast<double>(Dn)) : 0.0;
-        const double dj = (W != 0.0) ? W * (static_cast<double>(Nj) / static_cast<double>(Dn)) : 0.0;
-        const double si = wave_sum(di), sj = wave_sum(dj);
-        if (lane == 0) {
-            g(d.gpart)[static_cast<size_t>(U.i) * tiles + tile] = si;
-            g(d.gpart)[static_cast<size_t>(U.j) * tiles + tile] = sj;
+        if (U.fj) {
+            T na, nb, dn;
+            folded_grad_sums<T, SP>(d, U.j, r, c, qj, na, nb, dn);
+            xg[3][r][lane] = wr * na;
+            xg[4][r][lane] = wr * nb;
+            xg[5][r][lane] = wr * dn;
+        } else {
+            vs_store<T, SP>(part + ((static_cast<size_t>(U.j - N) * tiles + tile) * R + r) * per, lane, qj);
         }
+    }
+    if (U.fi || U.fj) __syncthreads();
+    if (r == 0) {
+        write_grad<T, R>(d, xch[0], xch[1], xch[2], lane, c, tile, U.i, U.j);
+        const GLOBAL int32_t* kk = g(d.kids);
+        if (U.fi) write_grad<T, R>(d, xg[0], xg[1], xg[2], lane, c, tile, kk[2 * (U.i - N)], kk[2 * (U.i - N) + 1]);
+        if (U.fj) write_grad<T, R>(d, xg[3], xg[4], xg[5], lane, c, tile, kk[2 * (U.j - N)], kk[2 * (U.j - N) + 1]);
     }
 }
 
