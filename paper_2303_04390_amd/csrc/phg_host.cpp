@@ -319,10 +319,9 @@ void build_schedule(phg_context* ctx) {
         return;
     }
     // vector-ALU kernels with tables for every branch: fold the internal nodes
-    // (but the root) whose two children are tips given by codes -- their
-    // post-order launch stores the exponent only and they have no pre-order
-    // launch; the parent forms the partial from the tips and the tips'
-    // gradient sums from the node's pre-order vector
+    // (but the root) whose two children are tips given by codes -- no
+    // launches of their own; the parent forms the partial from the tips and
+    // the tips' gradient sums from the node's pre-order vector
     std::vector<char> folded(n, 0);
     if (phg::uses_vs_kernels(ctx->S, ctx->R, fp32) &&
         table_slots_for(N, ctx->S, ctx->R, ctx->prec, ctx->table_budget) == 0) {
@@ -330,13 +329,14 @@ void build_schedule(phg_context* ctx) {
             folded[v] = c0[v] < N && c1[v] < N && !ctx->tip_vectors.count(c0[v]) && !ctx->tip_vectors.count(c1[v]);
     }
     std::vector<std::vector<int>> by(H + 1);
-    for (int v = N; v < n; ++v) by[height[v]].push_back(v);
+    for (int v = N; v < n; ++v)
+        if (!folded[v]) by[height[v]].push_back(v);
     auto put = [&](int v) {
-        const int32_t rec[4] = {v, c0[v], c1[v],
-                                (folded[c0[v]] ? 1 : 0) | (folded[c1[v]] ? 2 : 0) | (folded[v] ? 4 : 0)};
+        const int32_t rec[4] = {v, c0[v], c1[v], (folded[c0[v]] ? 1 : 0) | (folded[c1[v]] ? 2 : 0)};
         ctx->sched.insert(ctx->sched.end(), rec, rec + 4);
     };
     for (int h = 1; h <= H; ++h) {
+        if (by[h].empty()) continue;   // height 1 when every node there is folded
         const int a = static_cast<int>(ctx->sched.size() / 4);
         for (int v : by[h]) put(v);
         ctx->post_lv.emplace_back(a, static_cast<int>(ctx->sched.size() / 4) - a);

@@ -16,12 +16,10 @@ constexpr int kLanes = 64;          // one wavefront = one tile of 64 site patte
 // internal nodes of equal height; pre-order levels the internal nodes of
 // equal depth.  Children are stored in ascending id order.  fold (vector-ALU
 // kernels only): bit 0 / bit 1 set when child i / j is a folded node -- an
-// internal node (not the root) whose two children are tips given by codes --
-// and bit 2 when node k is one.  A folded node's post-order launch stores
-// its exponent but not its partial; its parent forms that partial from the
-// two tips' rows of the P(t) tables, scaled by the exponent.  Folded nodes
-// have no pre-order record: the parent's pre-order launch forms the gradient
-// sums of their tip branches.
+// internal node (not the root) whose two children are tips given by codes.
+// Folded nodes have no records: their parent's post-order launch forms
+// their partial from the two tips' rows of the P(t) tables, and its
+// pre-order launch the gradient sums of their tip branches.
 struct NodeTriple {
     int32_t k, i, j, fold;
 };

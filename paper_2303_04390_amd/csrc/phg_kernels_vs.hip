@@ -26,12 +26,12 @@
 // the forward table, P^T u = sum_s u_s P[s][.].
 //
 // An internal node whose two children are tips given by codes is folded
-// (when every branch has its tables): its post-order launch stores only its
-// exponent, and its parent forms (P_a e_ya) o (P_b e_yb) from two table rows,
-// scaled by it -- bit for bit the vector that would have been stored, at
-// less cost than writing and reading it.  It has no pre-order launch: its
-// parent turns the folded node's pre-order vector into the gradient sums of
-// the two tip branches at once, by the operations that launch would use.
+// (when every branch has its tables): it has no launch of its own.  Its
+// parent forms its partial (P_a e_ya) o (P_b e_yb) from two table rows --
+// such nodes are never rescaled, so this is bit for bit the vector that
+// would have been stored, at less cost than writing and reading it -- and
+// turns its pre-order vector into the gradient sums of the two tip branches
+// by the operations its own pre-order launch would use.
 //
 // Scaling as in the 4-state kernels: one power-of-two exponent per (node,
 // pattern) shared by all categories; stored post-order partials are
@@ -174,7 +174,6 @@ struct VsUnit {
     int i, j, k, tile;
     int ti, tj;   // P(t) tables of the children: by branch, or by slot in per-chunk tables
     bool fi, fj;  // child i / j is a folded node
-    bool fk;      // this node is folded (store its exponent only)
 };
 __device__ __forceinline__ bool vs_unit(const ReqDesc* __restrict__ descs, const SegTable& segs, VsUnit& U) {
     const int unit = blockIdx.x;
@@ -194,17 +193,17 @@ __device__ __forceinline__ bool vs_unit(const ReqDesc* __restrict__ descs, const
     U.tj = U.d->level_tables ? 2 * node_ix + 1 : U.j;
     U.fi = (rec[3] & 1) != 0;
     U.fj = (rec[3] & 2) != 0;
-    U.fk = (rec[3] & 4) != 0;
     return true;
 }
 
 // A folded child x (internal, both children a, b tips given by codes): its
-// partial (P_a e_ya) o (P_b e_yb) is not stored; its post-order launch
-// stores only its exponent e, and consumers form the partial from two rows
-// of the backward tables (folding needs tables for every branch), scaled by
-// 2^-e: bit for bit the vector that launch would have stored.
+// partial (P_a e_ya) o (P_b e_yb) is not stored; consumers form it from two
+// rows of the backward tables (folding needs tables for every branch).  A
+// node whose children are both tips given by codes is never rescaled
+// (exponent 0), so this is bit for bit the vector a post-order launch of x
+// would have stored.
 template <typename T, int SP>
-__device__ __forceinline__ void vs_folded(const ReqDesc& d, int x, int r, int c, int e, T (&v)[SP]) {
+__device__ __forceinline__ void vs_folded(const ReqDesc& d, int x, int r, int c, T (&v)[SP]) {
     const GLOBAL int32_t* kk = g(d.kids) + 2 * static_cast<size_t>(x - d.N);
     const int a = kk[0], b = kk[1];
     const size_t bmat = static_cast<size_t>(SP + 1) * SP;
@@ -213,14 +212,14 @@ __device__ __forceinline__ void vs_folded(const ReqDesc& d, int x, int r, int c,
     const GLOBAL T* Bb = g(bwdP<T>(d)) + (static_cast<size_t>(b) * d.R + r) * bmat +
                          tip_row<SP>(g(d.codes)[static_cast<size_t>(b) * d.Cpad + c], d.S);
 #pragma unroll
-    for (int s = 0; s < SP; ++s) v[s] = exact_ldexp(Ba[s] * Bb[s], -e);
+    for (int s = 0; s < SP; ++s) v[s] = Ba[s] * Bb[s];
 }
-// Child x's input vector: folded (formed from its tips, exponent e) or loaded.
+// Child x's input vector: folded (formed from its tips) or loaded.
 template <typename T, int SP>
-__device__ __forceinline__ void vs_input(const ReqDesc& d, bool folded, int e, const GLOBAL T* src, int x, int r,
-                                         int c, int lane, T (&v)[SP]) {
+__device__ __forceinline__ void vs_input(const ReqDesc& d, bool folded, const GLOBAL T* src, int x, int r, int c,
+                                         int lane, T (&v)[SP]) {
     if (folded)
-        vs_folded<T, SP>(d, x, r, c, e, v);
+        vs_folded<T, SP>(d, x, r, c, v);
     else
         vs_load<T, SP>(src, lane, v);
 }
@@ -310,15 +309,15 @@ __global__ __launch_bounds__(kVL * R) void post_vs_kernel(const ReqDesc* __restr
         if (src_i) si.store(tab[r][0], lane);
         if (src_j) sj.store(tab[r][1], lane);
     }
-    // the children's cumulative exponents (a folded child's is its own)
-    const int ei = U.i >= N ? g(d.expo)[static_cast<size_t>(U.i - N) * Cpad + c] : 0;
-    const int ej = U.j >= N ? g(d.expo)[static_cast<size_t>(U.j - N) * Cpad + c] : 0;
-    const int ec = ei + ej;
+    // the children's cumulative exponents (a folded child's is 0)
+    int ec = 0;
+    if (U.i >= N && !U.fi) ec += g(d.expo)[static_cast<size_t>(U.i - N) * Cpad + c];
+    if (U.j >= N && !U.fj) ec += g(d.expo)[static_cast<size_t>(U.j - N) * Cpad + c];
     __syncthreads();
     T p[SP];
     if (src_i) {   // p = P_i p_i
         T v[SP];
-        vs_input<T, SP>(d, U.fi, ei, src_i, U.i, r, c, lane, v);
+        vs_input<T, SP>(d, U.fi, src_i, U.i, r, c, lane, v);
 #pragma unroll
         for (int s = 0; s < SP; ++s) {
             p[s] = vs_row<T, SP>(tab[r][0], s, v);
@@ -332,7 +331,7 @@ __global__ __launch_bounds__(kVL * R) void post_vs_kernel(const ReqDesc* __restr
     }
     if (src_j) {   // p *= P_j p_j
         T v[SP];
-        vs_input<T, SP>(d, U.fj, ej, src_j, U.j, r, c, lane, v);
+        vs_input<T, SP>(d, U.fj, src_j, U.j, r, c, lane, v);
 #pragma unroll
         for (int s = 0; s < SP; ++s) {
             p[s] *= vs_row<T, SP>(tab[r][1], s, v);
@@ -345,22 +344,25 @@ __global__ __launch_bounds__(kVL * R) void post_vs_kernel(const ReqDesc* __restr
         for (int s = 0; s < SP; ++s) p[s] *= B[s];
     }
     if (!(U.sg.flags & 1)) {
-        T lmx = T(0);
+        // rescale, unless both children are tips given by codes (a product of
+        // two table entries needs none, and folded nodes rely on exponent 0)
+        int e = 0;
+        if (src_i || src_j) {
+            T lmx = T(0);
 #pragma unroll
-        for (int s = 0; s < SP; ++s) lmx = fmax(lmx, p[s]);
-        xmax[r][lane] = lmx;
-        __syncthreads();
-        T mx = xmax[0][lane];
+            for (int s = 0; s < SP; ++s) lmx = fmax(lmx, p[s]);
+            xmax[r][lane] = lmx;
+            __syncthreads();
+            T mx = xmax[0][lane];
 #pragma unroll
-        for (int rr = 1; rr < R; ++rr) mx = fmax(mx, xmax[rr][lane]);
-        const int e = exponent_of(mx);
-        if (!U.fk) {   // a folded node's partial is formed again by its parent
+            for (int rr = 1; rr < R; ++rr) mx = fmax(mx, xmax[rr][lane]);
+            e = exponent_of(mx);
 #pragma unroll
             for (int s = 0; s < SP; ++s) p[s] = exact_ldexp(p[s], -e);
-            vs_store<T, SP>(g(static_cast<T*>(d.part)) +
-                                ((static_cast<size_t>(U.k - N) * d.tiles + tile) * R + r) * SP * kVL,
-                            lane, p);
         }
+        vs_store<T, SP>(g(static_cast<T*>(d.part)) +
+                            ((static_cast<size_t>(U.k - N) * d.tiles + tile) * R + r) * SP * kVL,
+                        lane, p);
         if (r == 0) g(d.expo)[static_cast<size_t>(U.k - N) * Cpad + c] = e + ec;
     } else {
         // root: site likelihood sum_r w_r pi . p_r, categories summed in a fixed order
@@ -436,14 +438,12 @@ __global__ __launch_bounds__(kVL * R) void pre_vs_kernel(const ReqDesc* __restri
     } else {
         vs_load<T, SP>(part + ((static_cast<size_t>(U.k - N) * tiles + tile) * R + r) * per, lane, q);
     }
-    const int efi = U.fi ? g(d.expo)[static_cast<size_t>(U.i - N) * Cpad + c] : 0;
-    const int efj = U.fj ? g(d.expo)[static_cast<size_t>(U.j - N) * Cpad + c] : 0;
     __syncthreads();
     // child j: u_i = q o m_j and dm_j
     T ui[SP], dmj[SP];
     if (src_j) {
         T v[SP];
-        vs_input<T, SP>(d, U.fj, efj, src_j, U.j, r, c, lane, v);
+        vs_input<T, SP>(d, U.fj, src_j, U.j, r, c, lane, v);
 #pragma unroll
         for (int s = 0; s < SP; ++s) {
             ui[s] = q[s] * vs_row<T, SP>(tab[r][2], s, v);
@@ -465,7 +465,7 @@ __global__ __launch_bounds__(kVL * R) void pre_vs_kernel(const ReqDesc* __restri
     T ni = T(0), nj = T(0), den = T(0);
     if (src_i) {
         T v[SP];
-        vs_input<T, SP>(d, U.fi, efi, src_i, U.i, r, c, lane, v);
+        vs_input<T, SP>(d, U.fi, src_i, U.i, r, c, lane, v);
 #pragma unroll
         for (int s = 0; s < SP; ++s) {
             const T m = vs_row<T, SP>(tab[r][0], s, v), dm = vs_row<T, SP>(tab[r][1], s, v);
