@@ -293,6 +293,22 @@ def serving_measurement(args, B, synth):
 
 
 MFMA_PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6}      # MI355X dense MFMA peaks
+# MI355X vector-ALU peaks (256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz x 2 flops
+# per FMA, FP64 at full rate; the FP32 figure counts packed FMAs, which
+# this build does not emit, so its issue-limited FP32 rate is the FP64 one)
+VALU_PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6}
+VALU_UNPACKED_TFLOPS = 78.6
+
+
+def kernel_family(S, R, fp32):
+    """Which level kernels a context of these sizes runs: 'valu' (17..32
+    states, FP64 up to 24, R in 1, 2, 4, 8, LDS within 80 KiB per
+    workgroup), else 'mfma' above 16 states (the library's own rule)."""
+    if 16 < S <= (32 if fp32 else 24) and R in (1, 2, 4, 8):
+        SP = 20 if S <= 20 else (24 if S <= 24 else 32)
+        if R * (4 * SP * SP + 11 * 64) * (4 if fp32 else 8) <= 80 * 1024:
+            return "valu"
+    return "mfma" if S > 16 else "other"
 
 
 def accuracy(logl, grad, ref, n_sample):
@@ -324,20 +340,24 @@ def algorithmic_flops(n_tips, C, R, S):
     return 4.0 * (n_tips - 2) * 2.0 * S * S * C * R
 
 
-def executed_flops(parent, n_tips, C, R, S):
-    """Dense products the MFMA kernels issue per evaluation, at S padded to
-    the 16-state MFMA tile.  A tip child given by its code is a gather from
-    the P(t) tables, not a product, so the kernels issue P_x p_x in the
-    post-order and P_x p_x, dP_x p_x and P_x^T u_x in the pre-order for
-    internal children only: the method's 4 (N-2) products, padded."""
+def executed_flops(parent, n_tips, C, R, S, family):
+    """Products the kernels issue per evaluation, at S padded to the 16-state
+    MFMA tile (MFMA kernels) or to 20, 24 or 32 states (vector-ALU kernels).
+    A tip child given by its code is a gather from the P(t) tables, not a
+    product, so the kernels issue P_x p_x in the post-order and P_x p_x,
+    dP_x p_x and P_x^T u_x in the pre-order for internal children only: the
+    method's 4 (N-2) products, padded."""
     n = parent.shape[0]
     internal_children = int(np.sum(np.arange(n - 1) >= n_tips))
-    Sp = -(-S // 16) * 16
+    if family == "valu":
+        Sp = 20 if S <= 20 else (24 if S <= 24 else 32)
+    else:
+        Sp = -(-S // 16) * 16
     return 4 * internal_children * 2.0 * Sp * Sp * C * R
 
 
 def state_space_measurement(args, B, synth, stream, out):
-    """Throughput and MFMA utilisation of the larger state spaces: the
+    """Throughput and arithmetic-unit utilisation of the larger state spaces: the
     500-taxon amino-acid and 128-taxon codon workloads, a 122-state
     (Markov-modulated size) case and a 240-state case (the largest state
     count of byte tip codes, near the paper's 256-state phylogeographic
@@ -349,7 +369,6 @@ def state_space_measurement(args, B, synth, stream, out):
     for name, prob in cases:
         N, C, S, R = prob.n_tips, prob.n_patterns, prob.n_states, prob.n_categories
         alg_f = algorithmic_flops(N, C, R, S)
-        exe_f = executed_flops(prob.parent, N, C, R, S)
         # accuracy against the oracle on a pattern sample of the same workload
         # (not for the 10,000-taxon 256-state shape: the oracle's P(t) alone
         # would take minutes there; its per-chunk tables are checked against
@@ -360,6 +379,8 @@ def state_space_measurement(args, B, synth, stream, out):
         for prec, tag in ((B.PHG_FP32_SCALED, "f32"), (B.PHG_FP64, "f64")):
             if tag not in args.state_precisions.split(","):
                 continue
+            family = kernel_family(S, R, tag == "f32")
+            exe_f = executed_flops(prob.parent, N, C, R, S, family)
             h = B.phg_create(N, C, S, R, prec, 0)
             try:
                 B.phg_bind_stream(h, stream.cuda_stream)
@@ -383,16 +404,22 @@ def state_space_measurement(args, B, synth, stream, out):
             cls = dict(zip(B.PROF_NAMES, (ms_cls / max(n_prof, 1)).tolist()))
             t_mm = (cls["post"] + cls["pre_grad"]) * 1e-3
             tflops = alg_f / t_mm / 1e12
+            peak = (VALU_PEAK_TFLOPS if family == "valu" else MFMA_PEAK_TFLOPS)[tag]
             entry = {
                 "n_tips": N, "n_patterns": C, "n_states": S, "n_categories": R,
+                "kernels": family,
                 "evals_per_s": round(1.0 / dt, 1), "ms_per_eval": round(dt * 1e3, 4),
                 "ms_per_class": {k2: round(v, 4) for k2, v in cls.items()},
                 "algorithmic_gflop_per_eval": round(alg_f / 1e9, 2),
-                "mfma_tflops": round(tflops, 2), "mfma_peak_tflops": MFMA_PEAK_TFLOPS[tag],
-                "mfma_frac": round(tflops / MFMA_PEAK_TFLOPS[tag], 4),
+                "tflops": round(tflops, 2), "peak_tflops": peak, "frac": round(tflops / peak, 4),
+                # the same method flops against the dense MFMA peak, whichever
+                # unit ran them (comparable across kernel families)
+                "mfma_peak_frac": round(tflops / MFMA_PEAK_TFLOPS[tag], 4),
                 "executed_gflop_per_eval": round(exe_f / 1e9, 2),
                 "executed_tflops": round(exe_f / t_mm / 1e12, 2),
                 "table_slots": slots, "workspace_bytes": ws}
+            if family == "valu" and tag == "f32":
+                entry["frac_unpacked_valu"] = round(tflops / VALU_UNPACKED_TFLOPS, 4)
             if ref is not None:
                 with B.Context.for_problem(sample, prec) as ctx:
                     logl, grad = ctx.gradient()
