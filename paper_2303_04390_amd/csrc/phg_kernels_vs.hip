@@ -42,6 +42,8 @@
 
 #include <math.h>
 
+#include <utility>
+
 namespace phg {
 namespace {
 
@@ -570,6 +572,403 @@ __global__ __launch_bounds__(kVL * R) void pre_vs_kernel(const ReqDesc* __restri
     }
 }
 
+// ---------------------------------------------------------------- FP32, 20 states: matrices in registers
+
+// The FP32 kernels at 17..20 states stage the tables in LDS as the others
+// do, then copy the one matrix a pass needs into VGPRs and feed every
+// multiply-add its matrix entry as a DPP row_newbcast operand (the value in
+// lane n of each 16-lane row, broadcast to the row), so the products read
+// no LDS: a 20 x 20 matrix is 25 registers, replicated in the
+// four 16-lane rows -- register s (s < 20) holds M[s][0..15] in lanes 0..15,
+// register 20 + j holds M[s][16..19] for rows s = 4j..4j+3 in lanes
+// 4 (s mod 4) .. 4 (s mod 4) + 3.  The multiply-adds are written as
+// v_fmac_f32_dpp in inline assembly (the compiler does not fold a DPP move
+// into an accumulating FMA); each block opens with five wait states, which
+// covers the DPP read-after-VALU-write and EXEC-write hazards for whatever
+// the compiler placed before it.  Products accumulate in the same order as
+// the other kernels' (t ascending, first term a plain product), so results
+// are bit for bit theirs.
+struct MatReg20 {
+    float r[25];
+    // from a row-major 20 x 20 table staged in LDS (25 reads of 4 bytes per lane)
+    __device__ __forceinline__ void load(const float* __restrict__ M, int lane) {
+        const int n = lane & 15;
+#pragma unroll
+        for (int s = 0; s < 20; ++s) r[s] = M[s * 20 + n];
+#pragma unroll
+        for (int j = 0; j < 5; ++j) r[20 + j] = M[(4 * j + n / 4) * 20 + 16 + (n & 3)];
+    }
+};
+
+// a = M[s][0..15] . v[0..15]  (mr = register s)
+__device__ __forceinline__ float dpp_dot16(float mr, const float (&v)[20]) {
+    float a;
+    asm(
+        "s_nop 4\n\t"
+        "v_mul_f32_dpp %0, %1, %2 row_newbcast:0 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %0, %1, %3 row_newbcast:1 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %0, %1, %4 row_newbcast:2 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %0, %1, %5 row_newbcast:3 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %0, %1, %6 row_newbcast:4 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %0, %1, %7 row_newbcast:5 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %0, %1, %8 row_newbcast:6 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %0, %1, %9 row_newbcast:7 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %0, %1, %10 row_newbcast:8 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %0, %1, %11 row_newbcast:9 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %0, %1, %12 row_newbcast:10 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %0, %1, %13 row_newbcast:11 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %0, %1, %14 row_newbcast:12 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %0, %1, %15 row_newbcast:13 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %0, %1, %16 row_newbcast:14 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %0, %1, %17 row_newbcast:15 row_mask:0xf bank_mask:0xf"
+        : "=&v"(a)
+        : "v"(mr), "v"(v[0]), "v"(v[1]), "v"(v[2]), "v"(v[3]), "v"(v[4]), "v"(v[5]), "v"(v[6]), "v"(v[7]),
+          "v"(v[8]), "v"(v[9]), "v"(v[10]), "v"(v[11]), "v"(v[12]), "v"(v[13]), "v"(v[14]), "v"(v[15]));
+    return a;
+}
+// a += M[s][16..19] . v[16..19]  (tr = the tail register, lanes B..B+3)
+template <int B>
+__device__ __forceinline__ void dpp_dot4(float& a, float tr, const float (&v)[20]) {
+    asm(
+        "s_nop 4\n\t"
+        "v_fmac_f32_dpp %0, %1, %2 row_newbcast:%6 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %0, %1, %3 row_newbcast:%7 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %0, %1, %4 row_newbcast:%8 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %0, %1, %5 row_newbcast:%9 row_mask:0xf bank_mask:0xf"
+        : "+v"(a)
+        : "v"(tr), "v"(v[16]), "v"(v[17]), "v"(v[18]), "v"(v[19]), "i"(B), "i"(B + 1), "i"(B + 2), "i"(B + 3));
+}
+// (M v)_s
+template <int S>
+__device__ __forceinline__ float dpp_row(const MatReg20& M, const float (&v)[20]) {
+    float a = dpp_dot16(M.r[S], v);
+    dpp_dot4<4 * (S % 4)>(a, M.r[20 + S / 4], v);
+    return a;
+}
+// q[t] += M[s][t] u_s for every t (row s of P^T u)
+template <int S>
+__device__ __forceinline__ void dpp_acc_row(const MatReg20& M, float us, float (&q)[20]) {
+    asm(
+        "s_nop 4\n\t"
+        "v_fmac_f32_dpp %0, %16, %17 row_newbcast:0 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %1, %16, %17 row_newbcast:1 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %2, %16, %17 row_newbcast:2 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %3, %16, %17 row_newbcast:3 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %4, %16, %17 row_newbcast:4 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %5, %16, %17 row_newbcast:5 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %6, %16, %17 row_newbcast:6 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %7, %16, %17 row_newbcast:7 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %8, %16, %17 row_newbcast:8 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %9, %16, %17 row_newbcast:9 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %10, %16, %17 row_newbcast:10 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %11, %16, %17 row_newbcast:11 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %12, %16, %17 row_newbcast:12 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %13, %16, %17 row_newbcast:13 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %14, %16, %17 row_newbcast:14 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %15, %16, %17 row_newbcast:15 row_mask:0xf bank_mask:0xf"
+        : "+v"(q[0]), "+v"(q[1]), "+v"(q[2]), "+v"(q[3]), "+v"(q[4]), "+v"(q[5]), "+v"(q[6]), "+v"(q[7]),
+          "+v"(q[8]), "+v"(q[9]), "+v"(q[10]), "+v"(q[11]), "+v"(q[12]), "+v"(q[13]), "+v"(q[14]), "+v"(q[15])
+        : "v"(M.r[S]), "v"(us));
+    asm(
+        "s_nop 4\n\t"
+        "v_fmac_f32_dpp %0, %4, %5 row_newbcast:%6 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %1, %4, %5 row_newbcast:%7 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %2, %4, %5 row_newbcast:%8 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %3, %4, %5 row_newbcast:%9 row_mask:0xf bank_mask:0xf"
+        : "+v"(q[16]), "+v"(q[17]), "+v"(q[18]), "+v"(q[19])
+        : "v"(M.r[20 + S / 4]), "v"(us), "i"(4 * (S % 4)), "i"(4 * (S % 4) + 1), "i"(4 * (S % 4) + 2),
+          "i"(4 * (S % 4) + 3));
+}
+
+template <typename F, int... I>
+__device__ __forceinline__ void static_for_impl(F&& f, std::integer_sequence<int, I...>) {
+    (f(std::integral_constant<int, I>{}), ...);
+}
+// f(std::integral_constant<int, i>) for i = 0 .. n-1, in order.
+template <int N, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+    static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
+
+// Post-order, FP32, 17..20 states (as post_vs_kernel, products on registers).
+template <int R>
+__global__ __launch_bounds__(kVL * R) void post_vd_kernel(const ReqDesc* __restrict__ descs, const SegTable segs) {
+    constexpr int SP = 20;
+    using T = float;
+    __shared__ __align__(16) T tab[R][2][SP * SP];   // P_i, P_j of each category
+    __shared__ T xmax[R][kVL];
+    __shared__ double xsite[R][kVL];
+    const int r = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & (kVL - 1);
+    VsUnit U;
+    if (!vs_unit(descs, segs, U)) return;
+    const ReqDesc& d = *U.d;
+    const int N = d.N, S = d.S, Cpad = d.Cpad, tile = U.tile;
+    const int c = tile * kVL + lane;
+    const size_t mat = static_cast<size_t>(SP) * SP, bmat = static_cast<size_t>(SP + 1) * SP;
+    const GLOBAL T* src_i = vs_src<T, SP>(d, U.i, tile, r);
+    const GLOBAL T* src_j = vs_src<T, SP>(d, U.j, tile, r);
+    {
+        Stage<T, SP> si, sj;
+        if (src_i) si.load(g(fwdP<T>(d)) + (static_cast<size_t>(U.ti) * R + r) * mat, lane);
+        if (src_j) sj.load(g(fwdP<T>(d)) + (static_cast<size_t>(U.tj) * R + r) * mat, lane);
+        if (src_i) si.store(tab[r][0], lane);
+        if (src_j) sj.store(tab[r][1], lane);
+    }
+    int ec = 0;
+    if (U.i >= N && !U.fi) ec += g(d.expo)[static_cast<size_t>(U.i - N) * Cpad + c];
+    if (U.j >= N && !U.fj) ec += g(d.expo)[static_cast<size_t>(U.j - N) * Cpad + c];
+    __syncthreads();
+    T p[SP];
+    if (src_i) {   // p = P_i p_i
+        T v[SP];
+        vs_input<T, SP>(d, U.fi, src_i, U.i, r, c, lane, v);
+        MatReg20 M;
+        M.load(tab[r][0], lane);
+        static_for<SP>([&](auto s) { p[s] = dpp_row<s>(M, v); });
+    } else {
+        const GLOBAL T* B = g(bwdP<T>(d)) + (static_cast<size_t>(U.ti) * R + r) * bmat +
+                            tip_row<SP>(g(d.codes)[static_cast<size_t>(U.i) * Cpad + c], S);
+#pragma unroll
+        for (int s = 0; s < SP; ++s) p[s] = B[s];
+    }
+    if (src_j) {   // p *= P_j p_j
+        T v[SP];
+        vs_input<T, SP>(d, U.fj, src_j, U.j, r, c, lane, v);
+        MatReg20 M;
+        M.load(tab[r][1], lane);
+        static_for<SP>([&](auto s) { p[s] *= dpp_row<s>(M, v); });
+    } else {
+        const GLOBAL T* B = g(bwdP<T>(d)) + (static_cast<size_t>(U.tj) * R + r) * bmat +
+                            tip_row<SP>(g(d.codes)[static_cast<size_t>(U.j) * Cpad + c], S);
+#pragma unroll
+        for (int s = 0; s < SP; ++s) p[s] *= B[s];
+    }
+    if (!(U.sg.flags & 1)) {
+        int e = 0;
+        if (src_i || src_j) {
+            T lmx = T(0);
+#pragma unroll
+            for (int s = 0; s < SP; ++s) lmx = fmax(lmx, p[s]);
+            xmax[r][lane] = lmx;
+            __syncthreads();
+            T mx = xmax[0][lane];
+#pragma unroll
+            for (int rr = 1; rr < R; ++rr) mx = fmax(mx, xmax[rr][lane]);
+            e = exponent_of(mx);
+#pragma unroll
+            for (int s = 0; s < SP; ++s) p[s] = exact_ldexp(p[s], -e);
+        }
+        vs_store<T, SP>(g(static_cast<T*>(d.part)) +
+                            ((static_cast<size_t>(U.k - N) * d.tiles + tile) * R + r) * SP * kVL,
+                        lane, p);
+        if (r == 0) g(d.expo)[static_cast<size_t>(U.k - N) * Cpad + c] = e + ec;
+    } else {
+        double acc = 0.0;
+#pragma unroll
+        for (int s = 0; s < SP; ++s)
+            if (s < S) acc += g(d.pi)[s] * static_cast<double>(p[s]);
+        xsite[r][lane] = g(d.cweights)[r] * acc;
+        __syncthreads();
+        if (r == 0) {
+            double site = 0.0;
+#pragma unroll
+            for (int rr = 0; rr < R; ++rr) site += xsite[rr][lane];
+            const double ll = (site > 0.0 ? log(site) : -INFINITY) + static_cast<double>(ec) * 0.69314718055994530942;
+            g(d.sll)[c] = ll;
+            const double W = g(d.pw)[c];
+            const double tsum = wave_sum(W != 0.0 ? W * ll : 0.0);
+            if (lane == 0) g(d.lpart)[tile] = tsum;
+        }
+    }
+}
+
+// Pre-order and gradient, FP32, 17..20 states (as pre_vs_kernel, products on
+// registers, one matrix at a time: each child's P and dP products run as
+// two passes, and P^T u accumulates the rows of the forward table).  Every
+// sum keeps its order, so results are those of pre_vs_kernel bit for bit.
+template <int R>
+__global__ __launch_bounds__(kVL * R) __attribute__((amdgpu_waves_per_eu(4)))
+void pre_vd_kernel(const ReqDesc* __restrict__ descs, const SegTable segs) {
+    constexpr int SP = 20;
+    using T = float;
+    __shared__ __align__(16) T tab[R][4][SP * SP];   // P_i, dP_i, P_j, dP_j of each category
+    __shared__ T xch[5][R][kVL];
+    __shared__ T xg[6][R][kVL];
+    const int r = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & (kVL - 1);
+    VsUnit U;
+    if (!vs_unit(descs, segs, U)) return;
+    const ReqDesc& d = *U.d;
+    const int N = d.N, S = d.S, Cpad = d.Cpad, tile = U.tile, tiles = d.tiles;
+    const int c = tile * kVL + lane;
+    const size_t mat = static_cast<size_t>(SP) * SP, bmat = static_cast<size_t>(SP + 1) * SP;
+    const size_t per = static_cast<size_t>(SP) * kVL;
+    GLOBAL T* part = g(static_cast<T*>(d.part));
+    const bool in_i = U.i >= N, in_j = U.j >= N;
+    const GLOBAL T* src_i = vs_src<T, SP>(d, U.i, tile, r);
+    const GLOBAL T* src_j = vs_src<T, SP>(d, U.j, tile, r);
+    {
+        const size_t oi = (static_cast<size_t>(U.ti) * R + r) * mat, oj = (static_cast<size_t>(U.tj) * R + r) * mat;
+        Stage<T, SP> a, da, b, db;
+        if (src_i) {
+            a.load(g(fwdP<T>(d)) + oi, lane);
+            da.load(g(fwddP<T>(d)) + oi, lane);
+        }
+        if (src_j) {
+            b.load(g(fwdP<T>(d)) + oj, lane);
+            db.load(g(fwddP<T>(d)) + oj, lane);
+        }
+        if (src_i) {
+            a.store(tab[r][0], lane);
+            da.store(tab[r][1], lane);
+        }
+        if (src_j) {
+            b.store(tab[r][2], lane);
+            db.store(tab[r][3], lane);
+        }
+    }
+    T q[SP];
+    if (U.k == 2 * N - 2) {
+#pragma unroll
+        for (int s = 0; s < SP; ++s) q[s] = s < S ? static_cast<T>(g(d.pi)[s]) : T(0);
+    } else {
+        vs_load<T, SP>(part + ((static_cast<size_t>(U.k - N) * tiles + tile) * R + r) * per, lane, q);
+    }
+    __syncthreads();
+    // child j: u_i = q o m_j, then dm_j
+    T ui[SP], dmj[SP];
+    if (src_j) {
+        T v[SP];
+        vs_input<T, SP>(d, U.fj, src_j, U.j, r, c, lane, v);
+        {
+            MatReg20 M;
+            M.load(tab[r][2], lane);
+            static_for<SP>([&](auto s) { ui[s] = q[s] * dpp_row<s>(M, v); });
+        }
+        {
+            MatReg20 M;
+            M.load(tab[r][3], lane);
+            static_for<SP>([&](auto s) { dmj[s] = dpp_row<s>(M, v); });
+        }
+    } else {
+        const size_t bo = (static_cast<size_t>(U.tj) * R + r) * bmat +
+                          tip_row<SP>(g(d.codes)[static_cast<size_t>(U.j) * Cpad + c], S);
+        const GLOBAL T* B = g(bwdP<T>(d)) + bo;
+        const GLOBAL T* B2 = g(bwddP<T>(d)) + bo;
+#pragma unroll
+        for (int s = 0; s < SP; ++s) {
+            ui[s] = q[s] * B[s];
+            dmj[s] = B2[s];
+        }
+    }
+    // child i: with m_i the sums den, nj and q becomes u_j = q o m_i; with dm_i, ni
+    T ni = T(0), nj = T(0), den = T(0);
+    if (src_i) {
+        T v[SP];
+        vs_input<T, SP>(d, U.fi, src_i, U.i, r, c, lane, v);
+        {
+            MatReg20 M;
+            M.load(tab[r][0], lane);
+            static_for<SP>([&](auto s) {
+                const T m = dpp_row<s>(M, v);
+                den = fma(ui[s], m, den);
+                q[s] *= m;
+                nj = fma(q[s], dmj[s], nj);
+            });
+        }
+        {
+            MatReg20 M;
+            M.load(tab[r][1], lane);
+            static_for<SP>([&](auto s) { ni = fma(ui[s], dpp_row<s>(M, v), ni); });
+        }
+    } else {
+        const size_t bo = (static_cast<size_t>(U.ti) * R + r) * bmat +
+                          tip_row<SP>(g(d.codes)[static_cast<size_t>(U.i) * Cpad + c], S);
+        const GLOBAL T* B = g(bwdP<T>(d)) + bo;
+        const GLOBAL T* B2 = g(bwddP<T>(d)) + bo;
+#pragma unroll
+        for (int s = 0; s < SP; ++s) {
+            const T m = B[s], dm = B2[s];
+            ni = fma(ui[s], dm, ni);
+            den = fma(ui[s], m, den);
+            q[s] *= m;
+            nj = fma(q[s], dmj[s], nj);
+        }
+    }
+    // pre-order vectors of internal children: P^T u = sum_s u_s P[s][.]
+    T qi[SP], qj[SP];
+    T mxi = T(0), mxj = T(0);
+    if (in_i) {
+        MatReg20 M;
+        M.load(tab[r][0], lane);
+#pragma unroll
+        for (int t = 0; t < SP; ++t) qi[t] = T(0);
+        static_for<SP>([&](auto s) { dpp_acc_row<s>(M, ui[s], qi); });
+#pragma unroll
+        for (int t = 0; t < SP; ++t) mxi = fmax(mxi, qi[t]);
+    }
+    if (in_j) {
+        MatReg20 M;
+        M.load(tab[r][2], lane);
+#pragma unroll
+        for (int t = 0; t < SP; ++t) qj[t] = T(0);
+        static_for<SP>([&](auto s) { dpp_acc_row<s>(M, q[s], qj); });
+#pragma unroll
+        for (int t = 0; t < SP; ++t) mxj = fmax(mxj, qj[t]);
+    }
+    const T wr = static_cast<T>(g(d.cweights)[r]);
+    xch[0][r][lane] = wr * ni;
+    xch[1][r][lane] = wr * nj;
+    xch[2][r][lane] = wr * den;
+    xch[3][r][lane] = mxi;
+    xch[4][r][lane] = mxj;
+    __syncthreads();
+    T Mi = xch[3][0][lane], Mj = xch[4][0][lane];
+#pragma unroll
+    for (int rr = 1; rr < R; ++rr) {
+        Mi = fmax(Mi, xch[3][rr][lane]);
+        Mj = fmax(Mj, xch[4][rr][lane]);
+    }
+    // a child's rescaled pre-order vector is stored, or, for a folded child,
+    // turned into its tip branches' gradient sums at once
+    if (in_i) {
+        const int e = exponent_of(Mi);
+#pragma unroll
+        for (int s = 0; s < SP; ++s) qi[s] = exact_ldexp(qi[s], -e);
+        if (U.fi) {
+            T na, nb, dn;
+            folded_grad_sums<T, SP>(d, U.i, r, c, qi, na, nb, dn);
+            xg[0][r][lane] = wr * na;
+            xg[1][r][lane] = wr * nb;
+            xg[2][r][lane] = wr * dn;
+        } else {
+            vs_store<T, SP>(part + ((static_cast<size_t>(U.i - N) * tiles + tile) * R + r) * per, lane, qi);
+        }
+    }
+    if (in_j) {
+        const int e = exponent_of(Mj);
+#pragma unroll
+        for (int s = 0; s < SP; ++s) qj[s] = exact_ldexp(qj[s], -e);
+        if (U.fj) {
+            T na, nb, dn;
+            folded_grad_sums<T, SP>(d, U.j, r, c, qj, na, nb, dn);
+            xg[3][r][lane] = wr * na;
+            xg[4][r][lane] = wr * nb;
+            xg[5][r][lane] = wr * dn;
+        } else {
+            vs_store<T, SP>(part + ((static_cast<size_t>(U.j - N) * tiles + tile) * R + r) * per, lane, qj);
+        }
+    }
+    if (U.fi || U.fj) __syncthreads();
+    if (r == 0) {
+        write_grad<T, R>(d, xch[0], xch[1], xch[2], lane, c, tile, U.i, U.j);
+        const GLOBAL int32_t* kk = g(d.kids);
+        if (U.fi) write_grad<T, R>(d, xg[0], xg[1], xg[2], lane, c, tile, kk[2 * (U.i - N)], kk[2 * (U.i - N) + 1]);
+        if (U.fj) write_grad<T, R>(d, xg[3], xg[4], xg[5], lane, c, tile, kk[2 * (U.j - N)], kk[2 * (U.j - N) + 1]);
+    }
+}
+
 // ---------------------------------------------------------------- P(t) tables
 
 // One workgroup per (branch, category) pair: P and dP (FP64 sums stored in
@@ -646,10 +1045,17 @@ hipError_t launch_vs_sp(KernelClass k, int R, const ReqDesc* descs, const SegTab
 #define PHG_VS_CASE(RV)                                                                                    \
     if constexpr (vs_lds_bytes(SP, RV, sizeof(T)) <= kVsLdsMax)                                            \
     if (R == RV) {                                                                                         \
-        if (k == kPost)                                                                                    \
-            hipLaunchKernelGGL((post_vs_kernel<T, SP, RV>), dim3(n_units), dim3(kVL * RV), 0, st, descs, t); \
-        else                                                                                               \
-            hipLaunchKernelGGL((pre_vs_kernel<T, SP, RV>), dim3(n_units), dim3(kVL * RV), 0, st, descs, t);  \
+        if constexpr (sizeof(T) == 4 && SP == 20) {                                                        \
+            if (k == kPost)                                                                                \
+                hipLaunchKernelGGL((post_vd_kernel<RV>), dim3(n_units), dim3(kVL * RV), 0, st, descs, t);  \
+            else                                                                                           \
+                hipLaunchKernelGGL((pre_vd_kernel<RV>), dim3(n_units), dim3(kVL * RV), 0, st, descs, t);   \
+        } else {                                                                                           \
+            if (k == kPost)                                                                                \
+                hipLaunchKernelGGL((post_vs_kernel<T, SP, RV>), dim3(n_units), dim3(kVL * RV), 0, st, descs, t); \
+            else                                                                                           \
+                hipLaunchKernelGGL((pre_vs_kernel<T, SP, RV>), dim3(n_units), dim3(kVL * RV), 0, st, descs, t);  \
+        }                                                                                                  \
         return hipGetLastError();                                                                          \
     }
     PHG_VS_CASE(1)
