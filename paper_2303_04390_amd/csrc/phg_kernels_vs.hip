@@ -977,6 +977,7 @@ void pre_vd_kernel(const ReqDesc* __restrict__ descs, const SegTable segs) {
 template <typename T, int SP>
 __global__ __launch_bounds__(256) void pmat_vs_kernel(const ReqDesc* __restrict__ descs, const SegTable segs) {
     __shared__ double ex[SP], dex[SP];
+    __shared__ double sV[SP * SP], sVi[SP * SP];     // V and V^-1 (S x S used), read once from memory
     const int unit = blockIdx.x;
     if (unit >= segs.unit_begin[segs.n]) return;
     const int sidx = seg_index(segs, unit);
@@ -1002,6 +1003,10 @@ __global__ __launch_bounds__(256) void pmat_vs_kernel(const ReqDesc* __restrict_
         ex[k] = e;
         dex[k] = gr * lam[k] * e;
     }
+    for (int i = threadIdx.x; i < S * S; i += blockDim.x) {
+        sV[i] = V[i];
+        sVi[i] = Vinv[i];
+    }
     __syncthreads();
     GLOBAL T* F = g(fwdP<T>(d)) + static_cast<size_t>(pair) * SP * SP;
     GLOBAL T* dF = g(fwddP<T>(d)) + static_cast<size_t>(pair) * SP * SP;
@@ -1012,7 +1017,7 @@ __global__ __launch_bounds__(256) void pmat_vs_kernel(const ReqDesc* __restrict_
         double acc = 0.0, dacc = 0.0;
         if (s < S && t < S) {
             for (int k = 0; k < S; ++k) {
-                const double v = V[s * S + k] * Vinv[k * S + t];
+                const double v = sV[s * S + k] * sVi[k * S + t];
                 acc += v * ex[k];
                 dacc += v * dex[k];
             }
@@ -1026,7 +1031,7 @@ __global__ __launch_bounds__(256) void pmat_vs_kernel(const ReqDesc* __restrict_
         double rs = 0.0, drs = 0.0;
         if (s < S)
             for (int k = 0; k < S; ++k) {
-                const double a = V[s * S + k] * vs[k];
+                const double a = sV[s * S + k] * vs[k];
                 rs += a * ex[k];
                 drs += a * dex[k];
             }
