@@ -300,15 +300,10 @@ VALU_PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6}
 VALU_UNPACKED_TFLOPS = 78.6
 
 
-def kernel_family(S, R, fp32):
-    """Which level kernels a context of these sizes runs: 'valu' (17..32
-    states, FP64 up to 24, R in 1, 2, 4, 8, LDS within 80 KiB per
-    workgroup), else 'mfma' above 16 states (the library's own rule)."""
-    if 16 < S <= (32 if fp32 else 24) and R in (1, 2, 4, 8):
-        SP = 20 if S <= 20 else (24 if S <= 24 else 32)
-        if R * (4 * SP * SP + 11 * 64) * (4 if fp32 else 8) <= 80 * 1024:
-            return "valu"
-    return "mfma" if S > 16 else "other"
+def kernel_family(B, S, R, fp32):
+    """The library's level-kernel family for these sizes ('valu', 'mfma', ...)."""
+    prec = B.PHG_FP32_SCALED if fp32 else B.PHG_FP64
+    return B.KERNEL_FAMILY_NAMES[B.phg_kernel_family_of(S, R, prec)]
 
 
 def accuracy(logl, grad, ref, n_sample):
@@ -379,7 +374,7 @@ def state_space_measurement(args, B, synth, stream, out):
         for prec, tag in ((B.PHG_FP32_SCALED, "f32"), (B.PHG_FP64, "f64")):
             if tag not in args.state_precisions.split(","):
                 continue
-            family = kernel_family(S, R, tag == "f32")
+            family = kernel_family(B, S, R, tag == "f32")
             exe_f = executed_flops(prob.parent, N, C, R, S, family)
             h = B.phg_create(N, C, S, R, prec, 0)
             try:

@@ -309,6 +309,21 @@ phg_status phg_table_slots(phg_context *ctx, int *slots);
 phg_status phg_workspace_size(int n_tips, int n_patterns, int n_states,
                               int n_categories, phg_precision prec, size_t *bytes);
 
+/* The level kernels a context of these sizes runs (host only; no device
+ * work).  All families compute the same quantities (Methods: pruning
+ * equation, eq:preorder, eq:gradient); they differ in how the products are
+ * laid out on the hardware. */
+typedef enum {
+    PHG_KERNELS_FOUR_STATE = 0,  /* 4 states, R <= 8: blocked or level 4-state kernels */
+    PHG_KERNELS_SMALL_MFMA = 1,  /* other shapes up to 16 states (and 4 states with R > 8) */
+    PHG_KERNELS_VECTOR_ALU = 2,  /* 17..32 states (FP64: 17..24), R in 1, 2, 4, 8: one wave per
+                                    category, per-lane products on the vector ALUs */
+    PHG_KERNELS_MFMA = 3         /* other shapes above 16 states: MFMA tiles */
+} phg_kernel_family;
+
+/* PHG_ERR_ARG for sizes phg_create would refuse. */
+phg_status phg_kernel_family_of(int n_states, int n_categories, phg_precision prec, int *family);
+
 /* Use caller-owned device memory (>= phg_workspace_size bytes, 256-byte
  * aligned) instead of allocating.  It must outlive every later compute call.
  * Must be called before the first compute call / phg_prepare. */

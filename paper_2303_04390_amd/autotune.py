@@ -93,6 +93,9 @@ def tune(workloads, steps=10, warmup=2, reps=3, log=print):
                 base = 256 * 4 * 5 // R
                 cands = [0, 1, base // 2, base * 2, base * 4]
             else:
+                # row blocks exist only on the MFMA kernels
+                if B.phg_kernel_family_of(S, R, prec) != B.PHG_KERNELS_MFMA:
+                    continue
                 param = B.PHG_TUNE_ROW_BLOCKS
                 cands = [0] + row_block_candidates(S, fp32)
                 if len(cands) < 3:

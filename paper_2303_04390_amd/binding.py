@@ -65,6 +65,7 @@ _SIGS = {
     "phg_log_likelihood": [_vp, _dp],
     "phg_gradient": [_vp, _dp, _dp],
     "phg_workspace_size": [_c.c_int, _c.c_int, _c.c_int, _c.c_int, _c.c_int, _c.POINTER(_c.c_size_t)],
+    "phg_kernel_family_of": [_c.c_int, _c.c_int, _c.c_int, _c.POINTER(_c.c_int)],
     "phg_bind_workspace": [_vp, _vp, _c.c_size_t],
     "phg_bind_stream": [_vp, _vp],
     "phg_gradient_async": [_vp, _vp, _vp],
@@ -251,6 +252,17 @@ def phg_workspace_size(n_tips, n_patterns, n_states, n_categories, prec) -> int:
     v = ctypes.c_size_t()
     st = lib().phg_workspace_size(n_tips, n_patterns, n_states, n_categories, prec, ctypes.byref(v))
     _check(st, None, "phg_workspace_size")
+    return v.value
+
+
+PHG_KERNELS_FOUR_STATE, PHG_KERNELS_SMALL_MFMA, PHG_KERNELS_VECTOR_ALU, PHG_KERNELS_MFMA = 0, 1, 2, 3
+KERNEL_FAMILY_NAMES = ("four_state", "small_mfma", "valu", "mfma")
+
+
+def phg_kernel_family_of(n_states, n_categories, prec) -> int:
+    v = ctypes.c_int()
+    st = lib().phg_kernel_family_of(n_states, n_categories, prec, ctypes.byref(v))
+    _check(st, None, "phg_kernel_family_of")
     return v.value
 
 

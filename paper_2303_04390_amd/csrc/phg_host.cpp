@@ -1254,6 +1254,21 @@ phg_status phg_workspace_size(int n_tips, int n_patterns, int n_states, int n_ca
     return PHG_OK;
 }
 
+phg_status phg_kernel_family_of(int n_states, int n_categories, phg_precision prec, int* family) {
+    if (!family || (prec != PHG_FP64 && prec != PHG_FP32_SCALED) || !phg::kernels_support(n_states, n_categories))
+        return PHG_ERR_ARG;
+    const bool fp32 = prec == PHG_FP32_SCALED;
+    if (phg::uses_s4_kernels(n_states, n_categories))
+        *family = PHG_KERNELS_FOUR_STATE;
+    else if (phg::uses_vs_kernels(n_states, n_categories, fp32))
+        *family = PHG_KERNELS_VECTOR_ALU;
+    else if (phg::uses_gl_kernels(n_states, n_categories, fp32))
+        *family = PHG_KERNELS_MFMA;
+    else
+        *family = PHG_KERNELS_SMALL_MFMA;
+    return PHG_OK;
+}
+
 phg_status phg_bind_workspace(phg_context* ctx, void* device_ptr, size_t bytes) {
     if (!ctx) return PHG_ERR_ARG;
     if (ctx->dev_init) return ctx->fail(PHG_ERR_STATE, "workspace must be bound before first use");

@@ -397,3 +397,29 @@ def test_graph_calls_on_cpu():
         B.phg_set_graphs(ctx, True)
     finally:
         B.phg_destroy(ctx)
+
+
+def test_kernel_family_matches_the_routing_rule():
+    """phg_kernel_family_of: 4 states at R <= 8 on the 4-state kernels; other
+    shapes up to 16 states on the small MFMA kernels; 17..32 states (FP64
+    17..24) at R in 1, 2, 4, 8 on the vector-ALU kernels while the pre-order
+    workgroup's LDS fits 80 KiB; everything else above 16 states on the MFMA
+    kernels; sizes phg_create refuses are PHG_ERR_ARG."""
+    f32, f64 = B.PHG_FP32_SCALED, B.PHG_FP64
+    fam = B.phg_kernel_family_of
+    assert fam(4, 4, f32) == fam(4, 8, f64) == B.PHG_KERNELS_FOUR_STATE
+    assert fam(4, 16, f32) == fam(8, 3, f64) == fam(16, 4, f32) == B.PHG_KERNELS_SMALL_MFMA
+    for S in (17, 20, 24, 25, 32):
+        for R in (1, 2, 4):
+            assert fam(S, R, f32) == B.PHG_KERNELS_VECTOR_ALU, (S, R)
+    assert fam(20, 8, f32) == B.PHG_KERNELS_VECTOR_ALU         # 72 KiB of LDS
+    assert fam(24, 8, f32) == B.PHG_KERNELS_MFMA                # 94 KiB
+    assert fam(20, 4, f64) == B.PHG_KERNELS_VECTOR_ALU
+    assert fam(24, 4, f64) == B.PHG_KERNELS_MFMA                # 94 KiB
+    assert fam(25, 1, f64) == B.PHG_KERNELS_MFMA                # FP64 stops at 24 states
+    for S, R in ((20, 3), (20, 16), (33, 4), (61, 4), (256, 2)):
+        assert fam(S, R, f32) == B.PHG_KERNELS_MFMA, (S, R)
+    for S, R in ((1, 4), (257, 4), (20, 0), (20, 65)):
+        with pytest.raises(B.PhgError) as e:
+            fam(S, R, f32)
+        assert e.value.status == B.PHG_ERR_ARG

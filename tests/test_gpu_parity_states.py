@@ -164,13 +164,13 @@ def test_bench_shapes_large_states(which):
 
 def _table_bytes_per_branch(S, R, prec):
     """The unit the table budget is counted in: P, dP and their backward
-    copies for one branch.  Vector-ALU kernels (17..32 states, FP64 up to 24,
-    R in 1, 2, 4, 8): [SP][SP] forward and [SP + 1][SP] backward tables, SP
+    copies for one branch.  Vector-ALU kernels (phg_kernel_family_of):
+    [SP][SP] forward and [SP + 1][SP] backward tables, SP
     the state count padded to 20, 24 or 32.  MFMA kernels: gl_mat_rows rows
     of the operand-order row length, backward copies one row more."""
     fp32 = prec == B.PHG_FP32_SCALED
     tsz = 4 if fp32 else 8
-    if 16 < S <= (32 if fp32 else 24) and R in (1, 2, 4, 8):
+    if B.phg_kernel_family_of(S, R, prec) == B.PHG_KERNELS_VECTOR_ALU:
         SP = 20 if S <= 20 else (24 if S <= 24 else 32)
         return R * (2 * SP * SP + 2 * (SP + 1) * SP) * tsz
     G = 2 if S <= 32 else 4
