@@ -318,12 +318,13 @@ void build_schedule(phg_context* ctx) {
         for (int m = 0; m <= M; ++m) ctx->pre_lv.emplace_back(start[m], start[m + 1] - start[m]);
         return;
     }
-    // vector-ALU kernels with tables for every branch: fold the internal nodes
-    // (but the root) whose two children are tips given by codes -- no
-    // launches of their own; the parent forms the partial from the tips and
-    // the tips' gradient sums from the node's pre-order vector
+    // kernel families that fold, with tables for every branch: fold the
+    // internal nodes (but the root) whose two children are tips given by
+    // codes -- no post-order launch; the parent forms the partial from the
+    // tips (and, with folds_pre_order, the tips' gradient sums from the
+    // node's pre-order vector, so no pre-order launch either)
     std::vector<char> folded(n, 0);
-    if (phg::uses_vs_kernels(ctx->S, ctx->R, fp32) &&
+    if (phg::folds_tip_pairs(ctx->S, ctx->R, fp32) &&
         table_slots_for(N, ctx->S, ctx->R, ctx->prec, ctx->table_budget) == 0) {
         for (int v = N; v < root; ++v)
             folded[v] = c0[v] < N && c1[v] < N && !ctx->tip_vectors.count(c0[v]) && !ctx->tip_vectors.count(c1[v]);
@@ -342,8 +343,9 @@ void build_schedule(phg_context* ctx) {
         ctx->post_lv.emplace_back(a, static_cast<int>(ctx->sched.size() / 4) - a);
     }
     std::vector<std::vector<int>> bd(D + 1);
+    const bool fold_pre = phg::folds_pre_order(ctx->S, ctx->R, fp32);
     for (int v = N; v < n; ++v)
-        if (!folded[v]) bd[depth[v]].push_back(v);   // a folded node's parent forms its tip gradients
+        if (!(fold_pre && folded[v])) bd[depth[v]].push_back(v);   // else the parent forms its tip gradients
     for (int d = 0; d <= D; ++d) {
         if (bd[d].empty()) continue;
         const int a = static_cast<int>(ctx->sched.size() / 4);

@@ -14,12 +14,15 @@ constexpr int kLanes = 64;          // one wavefront = one tile of 64 site patte
 
 // One parent with its two children, by node id.  Post-order levels list the
 // internal nodes of equal height; pre-order levels the internal nodes of
-// equal depth.  Children are stored in ascending id order.  fold (vector-ALU
-// kernels only): bit 0 / bit 1 set when child i / j is a folded node -- an
-// internal node (not the root) whose two children are tips given by codes.
-// Folded nodes have no records: their parent's post-order launch forms
-// their partial from the two tips' rows of the P(t) tables, and its
-// pre-order launch the gradient sums of their tip branches.
+// equal depth.  Children are stored in ascending id order.  fold (kernel
+// families with folds_tip_pairs): bit 0 / bit 1 set when child i / j is a
+// folded node -- an internal node (not the root) whose two children are tips
+// given by codes.  Folded nodes have no post-order records: their parent's
+// launches form their partial from the two tips' rows of the P(t) tables
+// (such nodes are never rescaled, so that is the vector a launch of theirs
+// would have stored).  With folds_pre_order they have no pre-order records
+// either: the parent's pre-order launch forms the gradient sums of their tip
+// branches.
 struct NodeTriple {
     int32_t k, i, j, fold;
 };
@@ -213,6 +216,15 @@ hipError_t launch_vs(KernelClass k, const ReqDesc& shape, const ReqDesc* descs, 
 inline bool uses_gl_kernels(int S, int R, bool fp32) {
     return S > 16 && !uses_s4_kernels(S, R) && !uses_vs_kernels(S, R, fp32);
 }
+// Kernel families that fold tip-tip nodes (the node triple's fold bits): the
+// vector-ALU kernels, and the MFMA kernels where their pre-order stages its
+// inputs in LDS (above 32 states).  The vector-ALU kernels also take a
+// folded node's pre-order into its parent's launch; the MFMA kernels keep
+// its own pre-order launch.
+inline bool folds_tip_pairs(int S, int R, bool fp32) {
+    return uses_vs_kernels(S, R, fp32) || (uses_gl_kernels(S, R, fp32) && S > 32);
+}
+inline bool folds_pre_order(int S, int R, bool fp32) { return uses_vs_kernels(S, R, fp32); }
 // Their operand order: a stored vector (one pattern's partial) or matrix row
 // holds state t at column gl_col(t) = (t mod 4) KBP + t / 4, so the states
 // 4k + g that MFMA lane group g consumes on k-steps k, k+1, ... are adjacent

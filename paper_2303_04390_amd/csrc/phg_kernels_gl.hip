@@ -219,6 +219,50 @@ __device__ __forceinline__ void stage_vec(T* buf, const GLOBAL T* __restrict__ s
     }
 }
 
+// A folded child x's partial -- (P_a e_ya) o (P_b e_yb) for its tip children
+// a < b, the product of two rows of the backward P tables (which hold each
+// tip's P e_y in the stored operand order; the row-sum row for the
+// ambiguous code) -- into an LDS [TP][la] buffer, as stage_vec would copy
+// the stored block.  Folding needs tables for every branch.  The caller
+// synchronises.
+template <typename T, int TP, int KIT>
+__device__ __forceinline__ void stage_folded(T* buf, const ReqDesc& d, int x, int r, int tile, size_t bstride,
+                                             const Geo& ge) {
+    constexpr int E = 16 / static_cast<int>(sizeof(T));
+    const int per_row = ge.row / E;
+    const int n = TP * per_row;
+    const GLOBAL int32_t* kk = g(d.kids) + 2 * static_cast<size_t>(x - d.N);
+    const int a = kk[0], b = kk[1];
+    const GLOBAL T* PB = g(tabPB<T>(d));
+    const GLOBAL T* Ba = PB + (static_cast<size_t>(a) * d.R + r) * bstride;
+    const GLOBAL T* Bb = PB + (static_cast<size_t>(b) * d.R + r) * bstride;
+    const size_t ca = static_cast<size_t>(a) * d.Cpad + static_cast<size_t>(tile) * TP;
+    const size_t cb = static_cast<size_t>(b) * d.Cpad + static_cast<size_t>(tile) * TP;
+    const int sum_row = gl_mat_rows(ge.S);
+    const bool wide = code_bytes(ge.S) == 2;
+    const GLOBAL uint8_t* codes = g(d.codes);
+    VecG<T, E> va[KIT], vb[KIT];
+#pragma unroll
+    for (int it = 0; it < KIT; ++it) {
+        const int t = static_cast<int>(threadIdx.x) + it * static_cast<int>(blockDim.x);
+        if (t < n) {
+            const int p = t / per_row, c = (t - p * per_row) * E;
+            const int ya = wide ? reinterpret_cast<const GLOBAL uint16_t*>(codes)[ca + p] : codes[ca + p];
+            const int yb = wide ? reinterpret_cast<const GLOBAL uint16_t*>(codes)[cb + p] : codes[cb + p];
+            va[it] = *reinterpret_cast<const GLOBAL VecG<T, E>*>(Ba + (ya < ge.S ? ya : sum_row) * ge.row + c);
+            vb[it] = *reinterpret_cast<const GLOBAL VecG<T, E>*>(Bb + (yb < ge.S ? yb : sum_row) * ge.row + c);
+        }
+    }
+#pragma unroll
+    for (int it = 0; it < KIT; ++it) {
+        const int t = static_cast<int>(threadIdx.x) + it * static_cast<int>(blockDim.x);
+        if (t < n) {
+            const int p = t / per_row, c = (t - p * per_row) * E;
+            *reinterpret_cast<VecG<T, E>*>(buf + p * ge.la + c) = va[it] * vb[it];
+        }
+    }
+}
+
 // out1 = M1 v (and, with M2, out2 = M2 v) on this wave's columns:
 // out[c][s] = sum_t M[s][t] in[c][t], s = cb0 + 16 cb + n, from forward
 // tables; v from LDS (kLds) or HBM.  One operand stream of v feeds both
@@ -543,6 +587,7 @@ struct GlUnit {
     NodeTriple nt;
     int tile, tiles;
     int node_ix;    // the node's place in its segment
+    bool fi, fj;    // child i / j is a folded node (NodeTriple::fold)
 };
 __device__ __forceinline__ bool gl_unit(const ReqDesc* __restrict__ descs, const SegTable& segs, GlUnit& U) {
     const int unit = blockIdx.x;
@@ -557,6 +602,8 @@ __device__ __forceinline__ bool gl_unit(const ReqDesc* __restrict__ descs, const
     U.node_ix = node_ix;
     const I4 t4 = reinterpret_cast<const GLOBAL I4*>(g(U.sg.sched))[U.sg.sched_off + node_ix];
     U.nt = NodeTriple{t4.x, t4.y, t4.z, 0};
+    U.fi = (t4.w & 1) != 0;
+    U.fj = (t4.w & 2) != 0;
     return true;
 }
 
@@ -603,15 +650,21 @@ __global__ __launch_bounds__(64 * W) void post_gl_kernel(const ReqDesc* __restri
     GLOBAL T* out_base = part + (static_cast<size_t>(nt.k - N) * tiles + tile) * tstride;
     const bool root = U.sg.flags & 1;
     {
-        const int kids[2] = {nt.i, nt.j};
+        const int kids[2] = {U.fi ? -1 : nt.i, U.fj ? -1 : nt.j};   // a folded child's exponent is 0
         stage_exps<TP, 2>(esh, kids, d, tile);      // read after the first barrier below
     }
     const Input<T, RB> si{vb[0], nullptr}, sj{vb[1], nullptr};
     T mx[RB][4] = {};
     double site[RB][4] = {};
     for (int r = 0; r < R; ++r) {
-        if (pi_base) stage_vec<T, TP, KIT>(vb[0], pi_base + r * rstride, ge);
-        if (pj_base) stage_vec<T, TP, KIT>(vb[1], pj_base + r * rstride, ge);
+        if (U.fi)
+            stage_folded<T, TP, KIT>(vb[0], d, nt.i, r, tile, bstride, ge);
+        else if (pi_base)
+            stage_vec<T, TP, KIT>(vb[0], pi_base + r * rstride, ge);
+        if (U.fj)
+            stage_folded<T, TP, KIT>(vb[1], d, nt.j, r, tile, bstride, ge);
+        else if (pj_base)
+            stage_vec<T, TP, KIT>(vb[1], pj_base + r * rstride, ge);
         __syncthreads();
         Cols<T, RB, NBW> mi, mj, unused;
         if (pi_base) {
@@ -654,20 +707,26 @@ __global__ __launch_bounds__(64 * W) void post_gl_kernel(const ReqDesc* __restri
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int c = tile * TP + opat<T>(rb, gq, i);
-            ec[rb][i] = (tip_i ? 0 : g(d.expo)[static_cast<size_t>(nt.i - N) * Cpad + c]) +
-                        (tip_j ? 0 : g(d.expo)[static_cast<size_t>(nt.j - N) * Cpad + c]);
+            ec[rb][i] = (tip_i || U.fi ? 0 : g(d.expo)[static_cast<size_t>(nt.i - N) * Cpad + c]) +
+                        (tip_j || U.fj ? 0 : g(d.expo)[static_cast<size_t>(nt.j - N) * Cpad + c]);
         }
     if (!root) {
+        // a node whose children are both tips given by codes is never
+        // rescaled (folded nodes rely on exponent 0; its entries are products
+        // of two table entries)
+        const bool tiptip = !pi_base && !pj_base;
+        int e[RB][4] = {};
+        if (!tiptip) {
 #pragma unroll
-        for (int rb = 0; rb < RB; ++rb)
+            for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
-            for (int i = 0; i < 4; ++i) mx[rb][i] = max16(mx[rb][i]);
-        wg_max<T, RB, W>(mx, red, w, lane);
-        int e[RB][4];
+                for (int i = 0; i < 4; ++i) mx[rb][i] = max16(mx[rb][i]);
+            wg_max<T, RB, W>(mx, red, w, lane);
 #pragma unroll
-        for (int rb = 0; rb < RB; ++rb)
+            for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
-            for (int i = 0; i < 4; ++i) e[rb][i] = exp_of(mx[rb][i]);
+                for (int i = 0; i < 4; ++i) e[rb][i] = exp_of(mx[rb][i]);
+        }
         if (w == 0 && n == 0) {
 #pragma unroll
             for (int rb = 0; rb < RB; ++rb)
@@ -770,7 +829,8 @@ __global__ __launch_bounds__(64 * W, (W == 2 && RB == 1 && sizeof(T) == 4) ? 4 :
     const GLOBAL T* pi_src = tip_src<T>(d, nt.i, tile, tiles, tstride, part);
     const GLOBAL T* pj_src = tip_src<T>(d, nt.j, tile, tiles, tstride, part);
     {
-        const int nodes[3] = {nt.i, nt.j, is_root ? -1 : nt.k};
+        // a folded child's exponent is 0 (folding happens only where kStage)
+        const int nodes[3] = {U.fi ? -1 : nt.i, U.fj ? -1 : nt.j, is_root ? -1 : nt.k};
         stage_exps<TP, 3>(esh, nodes, d, tile);
     }
     if constexpr (!kStage) __syncthreads();    // exponents in LDS (staging has its own barrier)
@@ -781,8 +841,14 @@ __global__ __launch_bounds__(64 * W, (W == 2 && RB == 1 && sizeof(T) == 4) ? 4 :
         si.base = !kStage && pi_src ? pi_src + r * rstride : nullptr;
         sj.base = !kStage && pj_src ? pj_src + r * rstride : nullptr;
         if constexpr (kStage) {
-            if (pi_src) stage_vec<T, TP, KIT>(vb[0], pi_src + r * rstride, ge);
-            if (pj_src) stage_vec<T, TP, KIT>(vb[1], pj_src + r * rstride, ge);
+            if (U.fi)
+                stage_folded<T, TP, KIT>(vb[0], d, nt.i, r, tile, bstride, ge);
+            else if (pi_src)
+                stage_vec<T, TP, KIT>(vb[0], pi_src + r * rstride, ge);
+            if (U.fj)
+                stage_folded<T, TP, KIT>(vb[1], d, nt.j, r, tile, bstride, ge);
+            else if (pj_src)
+                stage_vec<T, TP, KIT>(vb[1], pj_src + r * rstride, ge);
             if (!is_root) stage_vec<T, TP, KIT>(vb[kStage ? 2 : 0], qk_base + r * rstride, ge);
             __syncthreads();  // inputs of category r staged
         }
