@@ -553,8 +553,9 @@ def main():
                     help="patterns of the 1000-taxon workload checked against the oracle")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--schedule", choices=("auto", "levels", "blocks"), default="auto",
-                    help="traversal schedule of the 4-state path (default: blocks where supported)")
+    ap.add_argument("--schedule", choices=("auto", "levels", "blocks", "queue"), default="queue",
+                    help="traversal schedule of the FP32 4-state path (default: the work-queue traversal; "
+                         "FP64 contexts take auto, i.e. blocks)")
     ap.add_argument("--quick", action="store_true",
                     help="throughput and kernel-class times only (for profiler runs)")
     ap.add_argument("--serving-seconds", type=float, default=60.0,
@@ -615,12 +616,16 @@ def main():
         del src, dst
 
     sched = {"auto": B.PHG_SCHEDULE_AUTO, "levels": B.PHG_SCHEDULE_LEVELS,
-             "blocks": B.PHG_SCHEDULE_BLOCKS}[args.schedule]
+             "blocks": B.PHG_SCHEDULE_BLOCKS, "queue": B.PHG_SCHEDULE_QUEUE}[args.schedule]
+    SCHED_NAMES = {B.PHG_SCHEDULE_LEVELS: "levels", B.PHG_SCHEDULE_BLOCKS: "blocks",
+                   B.PHG_SCHEDULE_QUEUE: "queue"}
 
-    def open_ctx(prec):
+    def open_ctx(prec, schedule=None):
+        schedule = sched if schedule is None else schedule
         h = B.phg_create(N, C, S, R, prec, 0)
-        if sched != B.PHG_SCHEDULE_AUTO:
-            B.phg_set_schedule(h, sched)
+        # the work-queue traversal is FP32-only: FP64 contexts keep AUTO
+        if schedule != B.PHG_SCHEDULE_AUTO and not (schedule == B.PHG_SCHEDULE_QUEUE and prec != B.PHG_FP32_SCALED):
+            B.phg_set_schedule(h, schedule)
         B.phg_bind_stream(h, stream.cuda_stream)
         B.set_problem(h, prob)
         B.phg_prepare(h)
@@ -679,7 +684,8 @@ def main():
 
     # ------------------------------------------------ live kernel-class times
     per_eval_ms = ms_cls / max(n_prof, 1)
-    blocked = B.phg_get_schedule(h) == B.PHG_SCHEDULE_BLOCKS
+    sched_name = SCHED_NAMES[B.phg_get_schedule(h)]
+    blocked = sched_name in ("blocks", "queue")
     post_bytes, pre_bytes = (algorithmic_bytes_blocked if blocked else algorithmic_bytes)(
         prob.parent, N, C, R, S, 4)
     cls = dict(zip(B.PROF_NAMES, per_eval_ms.tolist()))
@@ -691,7 +697,7 @@ def main():
     achieved = (dom_bytes / n_launch) / (dom_ms * 1e-3 / n_launch) / 1e9
     traffic = None
     if (MEASURED_TRAFFIC["kernel_source_sha256"] == kernel_source_sha256()
-            and MEASURED_TRAFFIC["schedule"] == ("blocks" if blocked else "levels")
+            and MEASURED_TRAFFIC["schedule"] == sched_name
             and dominant in MEASURED_TRAFFIC["bytes_per_eval"]):
         traffic = int(MEASURED_TRAFFIC["bytes_per_eval"][dominant] / n_launch)
     # the dominant kernel's share of the method minimum M0 (every internal
@@ -705,10 +711,14 @@ def main():
     m0_achieved = (m0_share / n_launch) / (dom_ms * 1e-3 / n_launch) / 1e9
     roofline = {
         "bound": "hbm",
-        # the class: wide launches take <R, false>, narrow (latency-bound) ones <R, true>
-        "kernel": (f"{'pre' if dominant == 'pre_grad' else 'post'}_bmf_kernel<{R}, *>" if blocked and R & (R - 1) == 0
+        # the class: the work-queue kernel's pass (<R, 1> post-order, <R, 2>
+        # pre-order), or the level kernels (wide launches take <R, false>,
+        # narrow, latency-bound ones <R, true>)
+        "kernel": (f"queue_bmf_kernel<{R}, {2 if dominant == 'pre_grad' else 1}>" if sched_name == "queue"
+                   else f"{'pre' if dominant == 'pre_grad' else 'post'}_bmf_kernel<{R}, *>"
+                   if blocked and R & (R - 1) == 0
                    else f"{'pre' if dominant == 'pre_grad' else 'post'}_{'blk' if blocked else 's4'}_kernel<float,{R}>"),
-        "schedule": "blocks" if blocked else "levels",
+        "schedule": sched_name,
         "achieved": round(m0_achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
         "frac": round(m0_achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
         "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
@@ -751,6 +761,22 @@ def main():
     lat = np.array(lat)
     B.phg_destroy(h)
 
+    # ------------------------------------------------ the other FP32 schedules
+    sched_ms = {sched_name: round(stream_ms, 4)}
+    for other, code in (("blocks", B.PHG_SCHEDULE_BLOCKS), ("levels", B.PHG_SCHEDULE_LEVELS),
+                        ("queue", B.PHG_SCHEDULE_QUEUE)):
+        if other in sched_ms:
+            continue
+        ho = open_ctx(B.PHG_FP32_SCALED, code)
+        run_async(ho, args.warmup)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        run_async(ho, args.steps)
+        torch.cuda.synchronize()
+        sched_ms[other] = round((time.perf_counter() - t0) * 1e3 / args.steps, 4)
+        B.phg_destroy(ho)
+    print(f"[bench] fp32 schedules, stream launches, ms/eval: {sched_ms}", file=sys.stderr, flush=True)
+
     # ------------------------------------------------ plain FP64 path
     h64 = open_ctx(B.PHG_FP64)
     run_async(h64, 2)
@@ -783,7 +809,8 @@ def main():
         "config": {"workload": "hky1000: 1000-taxon Yule tree (b~Exp(0.01)), HKY+Gamma4, 10,000 "
                                "simulated patterns (weights 1+Poisson(3), 5% ambiguous tip entries); "
                                "FP32 partials with power-of-two rescaling, FP64 P(t) and reductions",
-                   "n_tips": N, "n_patterns": C, "n_states": S, "n_categories": R, "seed": args.seed},
+                   "n_tips": N, "n_patterns": C, "n_states": S, "n_categories": R, "seed": args.seed,
+                   "schedule": sched_name},
         "branch_derivatives_per_s": round(value * E, 1),
         "timing": {"method": timing, "stream_launches_ms_per_step": round(stream_ms, 4),
                    "graph_replay_ms_per_step": None if graph_ms is None else round(graph_ms, 4),
@@ -799,6 +826,8 @@ def main():
         "roofline": roofline,
         "path": path,
         "fp64_path": {"ms_per_step": round(fp64_ms, 4), "evals_per_s": round(1e3 / fp64_ms, 2)},
+        "fp32_schedules_ms_per_step": dict(sched_ms, what="the same FP32 evaluation under each 4-state "
+                                           "schedule, stream launches (the value's schedule is in config)"),
         "batched_fp32_vs_fp64": batched,
         "state_spaces": states,
         "serving": serving,

@@ -143,13 +143,31 @@ phg_status phg_set_pattern_weights(phg_context *ctx, const double *w);
  * every depth that is a multiple of 3, with its internal children and
  * grandchildren); only block roots' partials go to device memory and the
  * pre-order pass recomputes in-block post-order partials in registers, which
- * moves about 2.5x fewer bytes on a Yule tree.  AUTO (default) picks BLOCKS
- * where supported.  Same results up to rounding order. */
-typedef enum { PHG_SCHEDULE_AUTO = 0, PHG_SCHEDULE_LEVELS = 1, PHG_SCHEDULE_BLOCKS = 2 } phg_schedule;
+ * moves about 2.5x fewer bytes on a Yule tree; one launch per block level and
+ * pass.  QUEUE (4 states, FP32, R in {1, 2, 4, 8}; opt-in): the same blocks
+ * and arithmetic, one launch per pass (PHG_TUNE_QUEUE_LAUNCHES) over
+ * (block, 64-pattern tile) work items in dependency order, each waiting only
+ * on the items it reads (Methods: the post-order and pre-order recursions
+ * order nodes, not whole tree levels), so there is no level-wide barrier.
+ * It relies on the GPU starting a launch's workgroups in increasing order on
+ * each XCD, and is meant for one such evaluation on the device at a time:
+ * two QUEUE evaluations running concurrently on different streams can stall
+ * each other until a wait gives up after 2 s, when the evaluation returns
+ * NaN (PHG_ERR_NUMERIC from the synchronous calls).  A tree too large for
+ * one launch per pass runs BLOCKS.  AUTO (default) picks BLOCKS where
+ * supported.  Same results up to rounding order; BLOCKS and QUEUE give
+ * bitwise-identical results. */
+typedef enum {
+    PHG_SCHEDULE_AUTO = 0,
+    PHG_SCHEDULE_LEVELS = 1,
+    PHG_SCHEDULE_BLOCKS = 2,
+    PHG_SCHEDULE_QUEUE = 3
+} phg_schedule;
 phg_status phg_set_schedule(phg_context *ctx, phg_schedule mode);
 
 /* The schedule in effect for the current topology: *schedule is
- * PHG_SCHEDULE_LEVELS or PHG_SCHEDULE_BLOCKS (AUTO resolved).  PHG_ERR_STATE
+ * PHG_SCHEDULE_LEVELS, PHG_SCHEDULE_BLOCKS or PHG_SCHEDULE_QUEUE (AUTO
+ * resolved).  PHG_ERR_STATE
  * before the topology is set. */
 phg_status phg_get_schedule(phg_context *ctx, int *schedule);
 
@@ -215,7 +233,9 @@ typedef enum {
                                    as built for S and the precision) */
     PHG_TUNE_NARROW_UNITS = 1,  /* 4 states, blocked FP32 kernels: largest launch (workgroups)
                                    that takes the one-round-trip narrow variant */
-    PHG_TUNE_PARAMS = 2
+    PHG_TUNE_QUEUE_LAUNCHES = 2,  /* 4 states, QUEUE schedule: launches per evaluation with the
+                                     gradient (1: both passes in one; 2, the default: one per pass) */
+    PHG_TUNE_PARAMS = 3
 } phg_tune_param;
 
 /* n_categories = 0: any category count.  PHG_ERR_ARG for an unknown
@@ -373,7 +393,9 @@ enum { PHG_PROF_PMAT = 0, PHG_PROF_POST = 1, PHG_PROF_PRE = 2, PHG_PROF_FINAL = 
 /* on != 0: every later evaluation records HIP events on the context's stream
  * around each kernel class (P(t); post-order levels incl. the root; pre-order
  * + gradient levels; final sums).  on == 0 stops recording.  Recording adds
- * event records between launches and nothing else. */
+ * event records between launches and nothing else, except that a QUEUE
+ * schedule records one launch per pass even where it is tuned to one launch
+ * for both. */
 phg_status phg_profile_enable(phg_context *ctx, int on);
 
 /* Wait for the recorded evaluations, then write the summed device time in

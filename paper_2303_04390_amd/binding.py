@@ -30,6 +30,7 @@ PHG_FP32_SCALED = 1
 PHG_SCHEDULE_AUTO = 0
 PHG_SCHEDULE_LEVELS = 1
 PHG_SCHEDULE_BLOCKS = 2
+PHG_SCHEDULE_QUEUE = 3
 
 STATUS_NAMES = {0: "PHG_OK", -1: "PHG_ERR_ARG", -2: "PHG_ERR_STATE", -3: "PHG_ERR_OOM",
                 -4: "PHG_ERR_DEVICE", -5: "PHG_ERR_NUMERIC", -6: "PHG_ERR_BUSY"}
@@ -384,6 +385,7 @@ def phg_graph_stats(ctx):
 
 PHG_TUNE_ROW_BLOCKS = 0
 PHG_TUNE_NARROW_UNITS = 1
+PHG_TUNE_QUEUE_LAUNCHES = 2
 
 
 def phg_set_tuning(n_states: int, n_categories: int, prec: int, param: int, value: int):

@@ -19,7 +19,7 @@ namespace phg {
 struct Plan {
     size_t codes, part, expo, eloc, P64, dP64, P32, dP32, PB32, PB64, dPB32, dPB64, vsum, TT64, dTT64, TT32, dTT32, b, V, Vinv, lam, rates, cw,
         pi, pw, sll, lpart, gpart, out, sched, desc, ch_parent, ch_kids, heights, trates, set_ptr, set_idx,
-        total;
+        qitems, qdep, qdone, qctr, total;
 };
 // table_slots = 0: P(t) tables for every branch; else a pool of that many
 // (branch) tables, rebuilt per launch chunk (17..255-state kernels only).
@@ -101,6 +101,11 @@ struct phg_context {
     std::vector<int32_t> sched;
     // levels in execution order: (first record, record count)
     std::vector<std::pair<int, int>> post_lv, pre_lv;
+    // work-queue traversal of the blocked schedule (phg::QueueArgs): items
+    // [n][2] (post-order items first), dependencies [B][16]
+    bool queue = false;
+    std::vector<int32_t> qitems, qdep;
+    int q_post = 0, q_blocks = 0;
 
     // device state
     bool dev_init = false;

@@ -146,6 +146,12 @@ Plan make_plan(int N, int C, int S, int R, phg_precision prec, int table_slots) 
     p.trates = take(E * 8);
     p.set_ptr = take((E + 1) * 4);
     p.set_idx = take(E * 4);
+    // work-queue traversal (blocks <= internal nodes)
+    const bool queue = queue_supported(S, R, fp32);
+    p.qitems = take(queue ? 2 * I * tiles * 2 * sizeof(int32_t) : 0);
+    p.qdep = take(queue ? I * 16 * sizeof(int32_t) : 0);
+    p.qdone = take(queue ? 2 * I * tiles * sizeof(uint32_t) : 0);
+    p.qctr = take(queue ? kQueueWords * sizeof(uint32_t) : 0);
     p.total = off;
     return p;
 }
@@ -186,6 +192,7 @@ bool tune_value_ok(int S, int R, bool fp32, int param, int value) {
     if (param == PHG_TUNE_ROW_BLOCKS)
         return S > 16 && phg::gl_row_blocks_allowed(S, fp32, value);   // read by the MFMA kernels only
     if (param == PHG_TUNE_NARROW_UNITS) return S == 4 && fp32;
+    if (param == PHG_TUNE_QUEUE_LAUNCHES) return S == 4 && fp32 && value <= 2;
     return false;
 }
 
@@ -283,9 +290,12 @@ void build_schedule(phg_context* ctx) {
     ctx->sched.clear();
     ctx->post_lv.clear();
     ctx->pre_lv.clear();
+    ctx->queue = false;
+    ctx->qitems.clear();
+    ctx->qdep.clear();
     const bool fp32 = ctx->prec == PHG_FP32_SCALED;
     // the blocked kernels take tips by their codes only
-    ctx->blocked = ctx->sched_mode == PHG_SCHEDULE_BLOCKS ||
+    ctx->blocked = ctx->sched_mode == PHG_SCHEDULE_BLOCKS || ctx->sched_mode == PHG_SCHEDULE_QUEUE ||
                    (ctx->sched_mode == PHG_SCHEDULE_AUTO && phg::blocked_supported(ctx->S, ctx->R, fp32) &&
                     ctx->tip_vectors.empty());
     if (ctx->blocked) {
@@ -316,6 +326,39 @@ void build_schedule(phg_context* ctx) {
         start[M + 1] = static_cast<int>(ctx->sched.size() / 16);
         for (int m = M; m >= 0; --m) ctx->post_lv.emplace_back(start[m], start[m + 1] - start[m]);
         for (int m = 0; m <= M; ++m) ctx->pre_lv.emplace_back(start[m], start[m + 1] - start[m]);
+        const int B = start[M + 1];
+        ctx->queue = ctx->sched_mode == PHG_SCHEDULE_QUEUE && phg::queue_supported(ctx->S, ctx->R, fp32) &&
+                     static_cast<int64_t>(2) * B * ctx->tiles * phg::kLanes * ctx->R < (int64_t{1} << 31);
+        if (ctx->queue) {
+            // dependencies: the records of the blocks rooted at each frontier
+            // position, and each block's parent record
+            std::vector<int> rec_of(n, -1);
+            for (int r = 0; r < B; ++r) rec_of[ctx->sched[16 * r + 1]] = r;
+            ctx->qdep.assign(static_cast<size_t>(B) * 16, -1);
+            for (int r = 0; r < B; ++r)
+                for (int j = 0; j < 8; ++j) {
+                    const int c = ctx->sched[16 * r + 8 + j];
+                    if (c < N) continue;                     // tip or absent
+                    ctx->qdep[16 * r + j] = rec_of[c];
+                    ctx->qdep[16 * rec_of[c] + 8] = r;
+                }
+            // items: post-order levels deepest first, then pre-order levels
+            // from the root's; block-major within a level (a block's tiles
+            // together: its matrices and tip-code rows are read by
+            // neighbouring workgroups)
+            ctx->qitems.clear();
+            ctx->qitems.reserve(static_cast<size_t>(4) * B * ctx->tiles);
+            for (int pass = 0; pass < 2; ++pass) {
+                for (const auto& lv : pass == 0 ? ctx->post_lv : ctx->pre_lv)
+                    for (int r = lv.first; r < lv.first + lv.second; ++r)
+                        for (int t = 0; t < ctx->tiles; ++t) {
+                            ctx->qitems.push_back(r | (pass << 30));
+                            ctx->qitems.push_back(t);
+                        }
+                if (pass == 0) ctx->q_post = static_cast<int>(ctx->qitems.size() / 2);
+            }
+            ctx->q_blocks = B;
+        }
         return;
     }
     // kernel families that fold, with tables for every branch: fold the
@@ -582,6 +625,17 @@ phg_status upload(phg_context* ctx) {
         return hipMemcpyAsync(a + off, src, bytes, hipMemcpyHostToDevice, st);
     };
     if (dirty & kTipVec) PHG_TRY(upload_tip_vectors(ctx));
+    std::vector<uint32_t> zeros;
+    if ((dirty & kTopo) && ctx->queue) {
+        // completion marks and counters start at zero (epoch 0: the first
+        // evaluation's marks are 1); the marks of another topology would not
+        // match its records
+        zeros.assign(ctx->qitems.size() + kQueueWords, 0u);
+        PHG_HIP(ctx, put(pl.qitems, ctx->qitems.data(), ctx->qitems.size() * sizeof(int32_t)));
+        PHG_HIP(ctx, put(pl.qdep, ctx->qdep.data(), ctx->qdep.size() * sizeof(int32_t)));
+        PHG_HIP(ctx, put(pl.qdone, zeros.data(), ctx->qitems.size() / 2 * sizeof(uint32_t)));
+        PHG_HIP(ctx, put(pl.qctr, zeros.data(), kQueueWords * sizeof(uint32_t)));
+    }
     if (dirty & kTopo) {
         PHG_HIP(ctx, put(pl.sched, ctx->sched.data(), ctx->sched.size() * sizeof(int32_t)));
         PHG_HIP(ctx, put(pl.ch_parent, ctx->parent.data(), ctx->parent.size() * sizeof(int32_t)));
@@ -589,6 +643,7 @@ phg_status upload(phg_context* ctx) {
     }
     if (dirty & (kTopo | kDesc | kTipVec)) {
         ctx->rd.blocked = ctx->blocked ? 1 : 0;
+        ctx->rd.qctr = ctx->queue ? reinterpret_cast<uint32_t*>(a + pl.qctr) : nullptr;
         ctx->rd.eig_cat = ctx->eig_cat ? 1 : 0;
         PHG_HIP(ctx, put(pl.desc, &ctx->rd, sizeof(ReqDesc)));
     }
@@ -664,6 +719,24 @@ int tuned_value(int S, int R, bool fp32, int param) {
     return it == g_tune.end() ? 0 : it->second;
 }
 
+// kQueueWaitMs of the device's constant clock, in its ticks.
+uint64_t queue_wait_ticks(int device) {
+    static std::atomic<int> khz[64];
+    const int dev = device >= 0 && device < 64 ? device : 0;
+    int rate = khz[dev].load();
+    if (rate <= 0) {
+        if (hipDeviceGetAttribute(&rate, hipDeviceAttributeWallClockRate, device) != hipSuccess || rate <= 0)
+            rate = 100000;                                   // 100 MHz
+        khz[dev].store(rate);
+    }
+    return static_cast<uint64_t>(rate) * kQueueWaitMs;
+}
+
+int queue_launches(int S, int R, bool fp32) {
+    const int v = tuned_value(S, R, fp32, PHG_TUNE_QUEUE_LAUNCHES);
+    return v > 0 ? v : kQueueLaunchesDefault;
+}
+
 // One level's launches: the level kernel over its records [a, a + n), or,
 // with per-chunk P(t) tables, chunks of at most table_slots / 2 nodes, each
 // a P(t) launch building its children's tables and then the level kernel.
@@ -692,12 +765,38 @@ phg_status ctx_enqueue_eval(phg_context* ctx, double* d_logl, double* d_grad) {
         PHG_HIP(ctx, launch_class(kPmat, d, descs, one_segment(d, units_for(kPmat, d, 0), 0, 0, 0, nullptr, nullptr),
                                   st));
     PHG_TRY(prof_mark(ctx));
-    const int H = static_cast<int>(ctx->post_lv.size());
-    for (int h = 0; h < H; ++h)
-        PHG_TRY(enqueue_level(ctx, kPost, ctx->post_lv[h].first, ctx->post_lv[h].second, h == H - 1 ? 1 : 0));
-    PHG_TRY(prof_mark(ctx));
-    if (d_grad) {
-        for (const auto& lv : ctx->pre_lv) PHG_TRY(enqueue_level(ctx, kPre, lv.first, lv.second, 0));
+    if (ctx->queue) {
+        // work-queue traversal: both passes in one launch, or one launch per
+        // pass (always while profiling, so the classes keep their times)
+        char* a = ctx->arena;
+        const Plan& pl = ctx->plan;
+        QueueArgs q{};
+        q.items = reinterpret_cast<const int32_t*>(a + pl.qitems);
+        q.dep = reinterpret_cast<const int32_t*>(a + pl.qdep);
+        q.done = reinterpret_cast<uint32_t*>(a + pl.qdone);
+        q.ctr = reinterpret_cast<uint32_t*>(a + pl.qctr);
+        q.n_blocks = ctx->q_blocks;
+        q.root_rec = ctx->pre_lv.front().first;
+        q.wait_ticks = queue_wait_ticks(ctx->device);
+        const int n_items = static_cast<int>(ctx->qitems.size() / 2);
+        const bool one_launch = d_grad && !ctx->prof_on && queue_launches(d.S, d.R, d.fp32 != 0) == 1;
+        q.t0 = 0;
+        q.t1 = one_launch ? n_items : ctx->q_post;
+        PHG_HIP(ctx, launch_queue(d, descs, q, one_launch ? 3 : 1, st));
+        PHG_TRY(prof_mark(ctx));
+        if (d_grad && !one_launch) {
+            q.t0 = ctx->q_post;
+            q.t1 = n_items;
+            PHG_HIP(ctx, launch_queue(d, descs, q, 2, st));
+        }
+    } else {
+        const int H = static_cast<int>(ctx->post_lv.size());
+        for (int h = 0; h < H; ++h)
+            PHG_TRY(enqueue_level(ctx, kPost, ctx->post_lv[h].first, ctx->post_lv[h].second, h == H - 1 ? 1 : 0));
+        PHG_TRY(prof_mark(ctx));
+        if (d_grad) {
+            for (const auto& lv : ctx->pre_lv) PHG_TRY(enqueue_level(ctx, kPre, lv.first, lv.second, 0));
+        }
     }
     PHG_TRY(prof_mark(ctx));
     // without d_grad: log-likelihood only (no pre-order pass; one final unit)
@@ -869,8 +968,9 @@ void launches_per_class(phg_context* ctx, int* out) {
         return c;
     };
     out[PHG_PROF_PMAT] = slots > 0 ? 0 : 1;
-    out[PHG_PROF_POST] = count(ctx->post_lv);
-    out[PHG_PROF_PRE] = count(ctx->pre_lv);
+    // the work-queue traversal: one launch per pass (profiled evaluations)
+    out[PHG_PROF_POST] = ctx->queue ? 1 : count(ctx->post_lv);
+    out[PHG_PROF_PRE] = ctx->queue ? 1 : count(ctx->pre_lv);
     out[PHG_PROF_FINAL] = 1;
 }
 
@@ -1102,7 +1202,7 @@ phg_status phg_set_tip_states(phg_context* ctx, const int32_t* codes) {
 phg_status phg_set_tip_partials(phg_context* ctx, int tip, const double* partials) {
     if (!ctx) return PHG_ERR_ARG;
     if (tip < 0 || tip >= ctx->N) return ctx->fail(PHG_ERR_ARG, "tip %d outside [0, %d)", tip, ctx->N);
-    if (partials && ctx->sched_mode == PHG_SCHEDULE_BLOCKS)
+    if (partials && (ctx->sched_mode == PHG_SCHEDULE_BLOCKS || ctx->sched_mode == PHG_SCHEDULE_QUEUE))
         return ctx->fail(PHG_ERR_ARG, "general tip partials need the level schedule (schedule is BLOCKS)");
     const size_t n = static_cast<size_t>(ctx->C) * ctx->S;
     if (partials) {
@@ -1142,12 +1242,15 @@ phg_status phg_set_pattern_weights(phg_context* ctx, const double* w) {
 
 phg_status phg_set_schedule(phg_context* ctx, phg_schedule mode) {
     if (!ctx) return PHG_ERR_ARG;
-    if (mode != PHG_SCHEDULE_AUTO && mode != PHG_SCHEDULE_LEVELS && mode != PHG_SCHEDULE_BLOCKS)
+    if (mode != PHG_SCHEDULE_AUTO && mode != PHG_SCHEDULE_LEVELS && mode != PHG_SCHEDULE_BLOCKS &&
+        mode != PHG_SCHEDULE_QUEUE)
         return ctx->fail(PHG_ERR_ARG, "unknown schedule %d", static_cast<int>(mode));
     if (mode == PHG_SCHEDULE_BLOCKS &&
         !phg::blocked_supported(ctx->S, ctx->R, ctx->prec == PHG_FP32_SCALED))
         return ctx->fail(PHG_ERR_ARG, "the blocked schedule needs 4 states and R <= 8");
-    if (mode == PHG_SCHEDULE_BLOCKS && !ctx->tip_vectors.empty())
+    if (mode == PHG_SCHEDULE_QUEUE && !phg::queue_supported(ctx->S, ctx->R, ctx->prec == PHG_FP32_SCALED))
+        return ctx->fail(PHG_ERR_ARG, "the work-queue traversal needs 4 states, FP32 and R in {1, 2, 4, 8}");
+    if ((mode == PHG_SCHEDULE_BLOCKS || mode == PHG_SCHEDULE_QUEUE) && !ctx->tip_vectors.empty())
         return ctx->fail(PHG_ERR_ARG, "the blocked schedule does not take general tip partials");
     ctx->sched_mode = mode;
     if (ctx->have & kTopo) {
@@ -1398,7 +1501,7 @@ phg_status phg_last_precision(phg_context* ctx, int* prec) {
 phg_status phg_get_schedule(phg_context* ctx, int* schedule) {
     if (!ctx || !schedule) return PHG_ERR_ARG;
     if (!(ctx->have & kTopo)) return ctx->fail(PHG_ERR_STATE, "topology not set");
-    *schedule = ctx->blocked ? PHG_SCHEDULE_BLOCKS : PHG_SCHEDULE_LEVELS;
+    *schedule = ctx->queue ? PHG_SCHEDULE_QUEUE : ctx->blocked ? PHG_SCHEDULE_BLOCKS : PHG_SCHEDULE_LEVELS;
     return PHG_OK;
 }
 
@@ -1413,7 +1516,9 @@ phg_status phg_schedule_info(phg_context* ctx, int* n_post_levels, int* n_pre_le
     if (n_launches) {
         int cls[PHG_PROF_CLASSES];
         launches_per_class(ctx, cls);
-        *n_launches = cls[0] + cls[1] + cls[2] + cls[3];
+        // the work-queue traversal may run both passes in one launch
+        const bool one = ctx->queue && queue_launches(ctx->S, ctx->R, ctx->prec == PHG_FP32_SCALED) == 1;
+        *n_launches = cls[0] + cls[1] + (one ? 0 : cls[2]) + cls[3];
     }
     return PHG_OK;
 }

@@ -117,6 +117,10 @@ struct ReqDesc {
     // Null when no tip has one.
     const int32_t* tslot;
     const void* tipvec;
+    // Work-queue traversal: its counter words (phg::kQueueWords), else
+    // null.  The P(t) launch of an evaluation advances the epoch and clears
+    // the fault word; the final sums turn to NaN if it is set.
+    uint32_t* qctr;
 };
 
 // A launch processes the work units of up to kMaxSegs segments; a segment is
@@ -160,6 +164,40 @@ constexpr int kBlockDepth = 3;
 // Whether the blocked schedule has kernels for (S, R, precision) that keep
 // every in-block vector in registers.
 inline bool blocked_supported(int S, int R, bool /*fp32*/) { return S == 4 && R <= 8; }
+
+// Work-queue traversal of the blocked schedule (FP32, 4 states, R in
+// {1, 2, 4, 8}): one launch for both passes instead of one per block level.
+inline bool queue_supported(int S, int R, bool fp32) {
+    return S == 4 && fp32 && R <= 8 && (R & (R - 1)) == 0;
+}
+// Counter words of a context's queue (each on a 64-byte line of its own):
+// the epoch and the fault word.
+constexpr int kQueueEpoch = 0, kQueueFault = 16, kQueueWords = 32;
+// Milliseconds before a dependency wait gives up: far above any legitimate
+// wait (an item waits only on items already running).
+constexpr int kQueueWaitMs = 2000;
+uint64_t queue_wait_ticks(int device);
+// Launches per evaluation with the gradient (1: both passes in one, 2: one per
+// pass) unless tuned (PHG_TUNE_QUEUE_LAUNCHES).
+constexpr int kQueueLaunchesDefault = 2;
+int queue_launches(int S, int R, bool fp32);
+struct QueueArgs {
+    const int32_t* items;   // [n][2]: (block record | pass << 30, tile); pass 0 post-order, 1 pre-order;
+                            // numbered so that every item's inputs come from smaller numbers
+    const int32_t* dep;     // [B][16]: j < 8 the record of the block rooted at heap position 8 + j
+                            // (-1: none); 8 the parent block's record (-1: the root block)
+    uint32_t* done;         // [2][B][tiles] completion marks (post-order, pre-order)
+    uint32_t* ctr;          // [kQueueWords] counter words: epoch, fault
+    int32_t t0, t1;         // this launch's items (workgroup i takes item t0 + i)
+    int32_t n_blocks;       // B
+    int32_t root_rec;       // record of the block holding the tree root
+    uint64_t wait_ticks;    // constant-clock ticks before a wait gives up
+};
+// Items [q.t0, q.t1) of the context whose descriptor is descs[0], one
+// workgroup each; passes: 1 the range holds post-order items only, 2
+// pre-order items only, 3 both.
+hipError_t launch_queue(const ReqDesc& shape, const ReqDesc* descs, const QueueArgs& q, int passes,
+                        hipStream_t stream);
 
 // Default threshold of the FP32 precision guard: an FP32 context evaluates in
 // FP64 when some internal node k has a child x' with min(L_k, L_x') above it,

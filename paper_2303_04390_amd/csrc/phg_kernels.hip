@@ -34,6 +34,7 @@
 
 #include <math.h>
 
+#include <algorithm>
 #include <type_traits>
 
 namespace phg {
@@ -797,6 +798,70 @@ __device__ __forceinline__ GLOBAL char* chunk(GLOBAL F4* part, unsigned slot, un
            (static_cast<size_t>(slot) * tiles + tile) * (static_cast<size_t>(R) * kLanes * 16);
 }
 
+// Loads and stores of the partials and exponents that one work item writes
+// and another reads.  kCoh = false: ordinary accesses (level launches, where
+// the launch boundary orders producer and consumer).  kCoh = true (the
+// work-queue kernel, where both run inside one launch): buffer accesses with
+// the device-scope coherence bit, which skip stale copies in the per-CU cache
+// and in the L2 of another XCD; `base` is wave-uniform (a chunk or row base).
+constexpr int kScDevice = 16;                // cache policy: sc1 (device scope)
+constexpr int kRsrcFlags = 0x00020000;       // buffer descriptor word 3 (raw 32-bit data)
+template <bool kCoh>
+__device__ __forceinline__ F4 ld_f4(const GLOBAL char* base, uint32_t off, int bytes) {
+    if constexpr (kCoh) {
+        const auto rs = __builtin_amdgcn_make_buffer_rsrc(const_cast<GLOBAL char*>(base), 0, bytes, kRsrcFlags);
+        return __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, kScDevice);
+    } else {
+        return *reinterpret_cast<const GLOBAL F4*>(base + off);
+    }
+}
+template <bool kCoh>
+__device__ __forceinline__ void st_f4(GLOBAL char* base, uint32_t off, int bytes, F4 v) {
+    if constexpr (kCoh) {
+        const auto rs = __builtin_amdgcn_make_buffer_rsrc(base, 0, bytes, kRsrcFlags);
+        __builtin_amdgcn_raw_buffer_store_b128(v, rs, off, 0, kScDevice);
+    } else {
+        *reinterpret_cast<GLOBAL F4*>(base + off) = v;
+    }
+}
+template <bool kCoh>
+__device__ __forceinline__ int ld_i32(const GLOBAL int32_t* base, uint32_t idx, int count) {
+    if constexpr (kCoh) {
+        const auto rs = __builtin_amdgcn_make_buffer_rsrc(const_cast<GLOBAL int32_t*>(base), 0, 4 * count, kRsrcFlags);
+        return __builtin_amdgcn_raw_buffer_load_b32(rs, 4 * idx, 0, kScDevice);
+    } else {
+        return base[idx];
+    }
+}
+template <bool kCoh>
+__device__ __forceinline__ void st_i32(GLOBAL int32_t* base, uint32_t idx, int count, int v) {
+    if constexpr (kCoh) {
+        const auto rs = __builtin_amdgcn_make_buffer_rsrc(base, 0, 4 * count, kRsrcFlags);
+        __builtin_amdgcn_raw_buffer_store_b32(v, rs, 4 * idx, 0, kScDevice);
+    } else {
+        base[idx] = v;
+    }
+}
+// The partial of (slot, tile) for the lane (r, pattern), and the exponent of
+// (slot, pattern c = tile * 64 + pat).
+template <int R, bool kCoh>
+__device__ __forceinline__ F4 ld_part(GLOBAL F4* part, unsigned slot, unsigned tile, unsigned tiles, uint32_t off) {
+    return ld_f4<kCoh>(chunk<R>(part, slot, tile, tiles), off, R * kLanes * 16);
+}
+template <int R, bool kCoh>
+__device__ __forceinline__ void st_part(GLOBAL F4* part, unsigned slot, unsigned tile, unsigned tiles, uint32_t off,
+                                        F4 v) {
+    st_f4<kCoh>(chunk<R>(part, slot, tile, tiles), off, R * kLanes * 16, v);
+}
+template <bool kCoh>
+__device__ __forceinline__ int ld_expo(const GLOBAL int32_t* expo, unsigned slot, int Cpad, unsigned tile, int pat) {
+    return ld_i32<kCoh>(expo + static_cast<size_t>(slot) * Cpad + static_cast<size_t>(tile) * kLanes, pat, kLanes);
+}
+template <bool kCoh>
+__device__ __forceinline__ void st_expo(GLOBAL int32_t* expo, unsigned slot, int Cpad, unsigned tile, int pat, int v) {
+    st_i32<kCoh>(expo + static_cast<size_t>(slot) * Cpad + static_cast<size_t>(tile) * kLanes, pat, kLanes, v);
+}
+
 __device__ __forceinline__ void f4_to(const F4 q, float out[4]) {
     out[0] = q.x;
     out[1] = q.y;
@@ -978,20 +1043,19 @@ __device__ __forceinline__ int rescale_shared(float x[4]) {
 // registers stay live through the pre-order phase and cost occupancy, so it
 // pays only in launches too narrow to fill the chip (near the root), where
 // latency, not occupancy, bounds them.
-template <int R, bool kExpo>
+template <int R, bool kExpo, bool kCoh>
 __device__ __forceinline__ void load_frontier(const int (&nd)[16], const BmfLane& L, const int tile,
                                               const int tiles, const int N, const int Cpad,
                                               GLOBAL F4* __restrict__ part, const GLOBAL int32_t* __restrict__ expo,
                                               float (&fr)[8][4], int (&fe)[8]) {
-    const int c = tile * kLanes + L.pat;
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
         const int cn = nd[8 + j];
         F4 v = {0.0f, 0.0f, 0.0f, 0.0f};
         int e = 0;
         if (cn >= N) {
-            v = *reinterpret_cast<const GLOBAL F4*>(chunk<R>(part, cn - N, tile, tiles) + L.part);
-            if (kExpo) e = expo[static_cast<size_t>(cn - N) * Cpad + c];
+            v = ld_part<R, kCoh>(part, cn - N, tile, tiles, L.part);
+            if (kExpo) e = ld_expo<kCoh>(expo, cn - N, Cpad, tile, L.pat);
         }
         f4_to(v, fr[j]);
         fe[j] = e;
@@ -1002,13 +1066,12 @@ __device__ __forceinline__ void load_frontier(const int (&nd)[16], const BmfLane
 // pattern).  With kExpo, returns the sum of exponents taken (in-block nodes and
 // frontier block roots); otherwise exponents are not read.  Frontier inputs
 // come from load_frontier (kPre) or are loaded per position.
-template <int R, int NM, int LO, bool kExpo, bool kPre>
+template <int R, int NM, int LO, bool kExpo, bool kPre, bool kCoh>
 __device__ __forceinline__ int bmf_postorder(const int (&nd)[16], const BmfLane& L, const BmfMats<R, NM>& S,
                                              const uint32_t (&CL)[14][16], const int tile, const int tiles,
                                              const int N, const int Cpad, GLOBAL F4* __restrict__ part,
                                              const GLOBAL int32_t* __restrict__ expo, const float (&fr)[8][4],
                                              const int (&fe)[8], float (&p)[8][4]) {
-    const int c = tile * kLanes + L.pat;
     int esum = 0;
     static_for<0, 8 - LO>([&](auto I_) {
         constexpr int pos = 7 - decltype(I_)::value;
@@ -1030,8 +1093,8 @@ __device__ __forceinline__ int bmf_postorder(const int (&nd)[16], const BmfLane&
             for (int s = 0; s < 2; ++s) {
                 const int cn = nd[2 * pos + s];
                 const int slot = cn >= N ? cn - N : 0;
-                f4_to(*reinterpret_cast<const GLOBAL F4*>(chunk<R>(part, slot, tile, tiles) + L.part), v[s]);
-                ex[s] = kExpo ? expo[static_cast<size_t>(slot) * Cpad + c] : 0;
+                f4_to(ld_part<R, kCoh>(part, slot, tile, tiles, L.part), v[s]);
+                ex[s] = kExpo ? ld_expo<kCoh>(expo, slot, Cpad, tile, L.pat) : 0;
             }
 #pragma unroll
             for (int s = 0; s < 2; ++s)
@@ -1105,12 +1168,13 @@ __global__ __launch_bounds__(kLanes * R) __attribute__((amdgpu_waves_per_eu(4)))
     GLOBAL int32_t* expo = g(d.expo);
     float fr[8][4];
     int fe[8];
-    load_frontier<R, true>(nd, L, tile, U.tiles, N, U.Cpad, part, expo, fr, fe);
+    load_frontier<R, true, false>(nd, L, tile, U.tiles, N, U.Cpad, part, expo, fr, fe);
     stage_codes<R>(CL, nd, N, U.Cpad, tile * kLanes, g(d.codes));
     stage_mats<R, 1>(S, nd, g(d.P32), nullptr);
     __syncthreads();
     float p[8][4];
-    const int ek = bmf_postorder<R, 1, 1, true, true>(nd, L, S, CL, tile, U.tiles, N, U.Cpad, part, expo, fr, fe, p);
+    const int ek =
+        bmf_postorder<R, 1, 1, true, true, false>(nd, L, S, CL, tile, U.tiles, N, U.Cpad, part, expo, fr, fe, p);
     if (!(U.sg.flags & 1)) {
         *reinterpret_cast<GLOBAL F4*>(chunk<R>(part, nd[1] - N, tile, U.tiles) + L.part) = to_f4(p[1]);
         if (L.r == 0) expo[static_cast<size_t>(nd[1] - N) * U.Cpad + c] = ek;
@@ -1166,7 +1230,7 @@ __global__ __launch_bounds__(kLanes * R) __attribute__((amdgpu_waves_per_eu(4)))
     GLOBAL F4* part = reinterpret_cast<GLOBAL F4*>(g(part_of<float>(d)));
     float fr[8][4];
     int fe[8];
-    if constexpr (kPre) load_frontier<R, false>(nd, L, tile, tiles, N, U.Cpad, part, nullptr, fr, fe);
+    if constexpr (kPre) load_frontier<R, false, false>(nd, L, tile, tiles, N, U.Cpad, part, nullptr, fr, fe);
     stage_codes<R>(CL, nd, N, U.Cpad, tile * kLanes, g(d.codes));
     float q[8][4];
     if (nd[1] == 2 * N - 2) {
@@ -1180,7 +1244,7 @@ __global__ __launch_bounds__(kLanes * R) __attribute__((amdgpu_waves_per_eu(4)))
     stage_mats<R, 2>(S, nd, g(d.P32), g(d.dP32));
     __syncthreads();
     float p[8][4];
-    (void)bmf_postorder<R, 2, 2, false, kPre>(nd, L, S, CL, tile, tiles, N, U.Cpad, part, nullptr, fr, fe, p);
+    (void)bmf_postorder<R, 2, 2, false, kPre, false>(nd, L, S, CL, tile, tiles, N, U.Cpad, part, nullptr, fr, fe, p);
     const float wr = static_cast<float>(g(d.cweights)[L.r]);
     static_for<1, 8>([&](auto P_) {
         constexpr int pos = decltype(P_)::value;
@@ -1284,6 +1348,324 @@ __global__ __launch_bounds__(kLanes * R) __attribute__((amdgpu_waves_per_eu(4)))
     }
 }
 
+// Item bodies of the work-queue traversal (below): the post_bmf_kernel and
+// pre_bmf_kernel arithmetic for one (block, tile), with device-coherent
+// accesses to the partials and exponents that cross items, and the matrices
+// and codes staged before the dependency wait.  LDS of the two bodies:
+template <int R>
+struct PostBmfLds {
+    BmfMats<R, 1> S;
+    uint32_t CL[14][16];                     // tip codes of the block, [position - 2][pattern]
+    double sw[R];
+};
+template <int R>
+struct PreBmfLds {
+    BmfMats<R, 2> S;
+    uint32_t CL[14][16];                     // tip codes of the block, [position - 2][pattern]
+    // per child slot j = 2 (pos - 1) + side: sum_r w_r u . dm; per position:
+    // sum_r w_r u . m (the same for both children); lane = pattern of the tile
+    float gnum[14][kLanes];
+    float gden[7][kLanes];
+    double wl[kLanes];                       // pattern weights of the tile
+};
+
+// Post-order of one (block, tile) with the block's heap record at `heap`;
+// root: the block holds the tree root.  `wait` returns (after a barrier) once
+// the frontier block roots' partials of this tile are complete.
+template <int R, class Wait>
+__device__ __forceinline__ void post_bmf_body(const ReqDesc& d, const GLOBAL int32_t* __restrict__ heap,
+                                              const int tile, const int tiles, const bool root,
+                                              PostBmfLds<R>& sm, const int w, const int lane, Wait&& wait) {
+    constexpr int PW = kLanes / R;
+    const BmfLane L = bmf_lane<R>(w, lane);
+    const int N = d.N, Cpad = d.Cpad;
+    int nd[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) nd[i] = heap[i];
+    const int c = tile * kLanes + L.pat;
+    GLOBAL F4* part = reinterpret_cast<GLOBAL F4*>(g(part_of<float>(d)));
+    GLOBAL int32_t* expo = g(d.expo);
+    stage_codes<R>(sm.CL, nd, N, Cpad, tile * kLanes, g(d.codes));
+    stage_mats<R, 1>(sm.S, nd, g(d.P32), nullptr);
+    wait();
+    float fr[8][4];
+    int fe[8];
+    load_frontier<R, true, true>(nd, L, tile, tiles, N, Cpad, part, expo, fr, fe);
+    float p[8][4];
+    const int ek =
+        bmf_postorder<R, 1, 1, true, true, true>(nd, L, sm.S, sm.CL, tile, tiles, N, Cpad, part, expo, fr, fe, p);
+    if (!root) {
+        st_part<R, true>(part, nd[1] - N, tile, tiles, L.part, to_f4(p[1]));
+        if (L.r == 0) st_expo<true>(expo, nd[1] - N, Cpad, tile, L.pat, ek);
+        return;
+    }
+    // the tree root: log site likelihood and this tile's weighted sum
+    const GLOBAL double* pi = g(d.pi);
+    double acc = 0.0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc += pi[u] * static_cast<double>(p[1][u]);
+    double site = g(d.cweights)[L.r] * acc;
+#pragma unroll
+    for (int off = kLanes / 2; off >= PW; off >>= 1) site += __shfl_xor(site, off, kLanes);
+    double contrib = 0.0;
+    if (L.r == 0) {
+        const double ll = (site > 0.0 ? log(site) : -INFINITY) + static_cast<double>(ek) * 0.69314718055994530942;
+        g(d.sll)[c] = ll;
+        const double W = g(d.pw)[c];
+        contrib = W != 0.0 ? W * ll : 0.0;
+    }
+    const double ws = wave_sum(contrib);
+    if (lane == 0) sm.sw[w] = ws;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+#pragma unroll
+        for (int i = 0; i < R; ++i) t += sm.sw[i];
+        g(d.lpart)[tile] = t;
+    }
+}
+
+// Pre-order and gradient sums of one (block, tile).  `wait` returns (after a
+// barrier) once the pre-order vector of the block root (written by the
+// parent block's item) is complete.
+template <int R, class Wait>
+__device__ __forceinline__ void pre_bmf_body(const ReqDesc& d, const GLOBAL int32_t* __restrict__ heap,
+                                             const int tile, const int tiles, PreBmfLds<R>& sm, const int w,
+                                             const int lane, Wait&& wait) {
+    const BmfLane L = bmf_lane<R>(w, lane);
+    const int N = d.N, Cpad = d.Cpad;
+    int nd[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) nd[i] = heap[i];
+    const int c = tile * kLanes + L.pat;
+    GLOBAL F4* part = reinterpret_cast<GLOBAL F4*>(g(part_of<float>(d)));
+    float fr[8][4];                                     // unused: frontier partials are loaded per position
+    int fe[8];
+    stage_codes<R>(sm.CL, nd, N, Cpad, tile * kLanes, g(d.codes));
+    if (L.r == 0) sm.wl[L.pat] = g(d.pw)[c];
+    stage_mats<R, 2>(sm.S, nd, g(d.P32), g(d.dP32));
+    wait();
+    float q[8][4];
+    if (nd[1] == 2 * N - 2) {
+        const GLOBAL double* pi = g(d.pi);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) q[1][u] = static_cast<float>(pi[u]);
+    } else {
+        f4_to(ld_part<R, true>(part, nd[1] - N, tile, tiles, L.part), q[1]);
+    }
+    float p[8][4];
+    (void)bmf_postorder<R, 2, 2, false, false, true>(nd, L, sm.S, sm.CL, tile, tiles, N, Cpad, part, nullptr, fr,
+                                                     fe, p);
+    const float wr = static_cast<float>(g(d.cweights)[L.r]);
+    static_for<1, 8>([&](auto P_) {
+        constexpr int pos = decltype(P_)::value;
+        const int k = nd[pos];
+        if (k < N) return;
+        float m[2][4], dm[2][4], v[2][4];
+        bool in[2];
+        if constexpr (pos >= 4) {
+#pragma unroll
+            for (int s = 0; s < 2; ++s) {
+                const int cn = nd[2 * pos + s];
+                f4_to(ld_part<R, true>(part, cn >= N ? cn - N : 0, tile, tiles, L.part), v[s]);
+            }
+        } else {
+#pragma unroll
+            for (int s = 0; s < 2; ++s)
+#pragma unroll
+                for (int u = 0; u < 4; ++u) v[s][u] = p[pos < 4 ? 2 * pos + s : 0][u];
+        }
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            const int cp = 2 * pos + s;
+            const float* M = sm.S.m[cp - 2][L.r][0];
+            const float* dM = sm.S.m[cp - 2][L.r][1];
+            in[s] = nd[cp] >= N;
+            if (!in[s]) {
+                const int code = code_at(sm.CL, cp, L.pat);
+                lds_column(M, code, m[s]);
+                lds_column(dM, code, dm[s]);
+            } else {
+                mfma_mv<false>(M, L, v[s], m[s]);
+                mfma_mv<false>(dM, L, v[s], dm[s]);
+            }
+        }
+        float uu[2][4], a0 = 0.0f, a1 = 0.0f, dd = 0.0f;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            uu[0][u] = q[pos][u] * m[1][u];
+            uu[1][u] = q[pos][u] * m[0][u];
+            a0 += uu[0][u] * dm[0][u];
+            a1 += uu[1][u] * dm[1][u];
+            dd += uu[0][u] * m[0][u];
+        }
+        const float num0 = sum_over_categories<R>(wr * a0);
+        const float num1 = sum_over_categories<R>(wr * a1);
+        const float den = sum_over_categories<R>(wr * dd);
+        if (L.r == 0) {
+            sm.gnum[2 * pos - 2][L.pat] = num0;
+            sm.gnum[2 * pos - 1][L.pat] = num1;
+            sm.gden[pos - 1][L.pat] = den;
+        }
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            if (!in[s]) continue;
+            const int cp = 2 * pos + s;
+            const int cn = nd[cp];
+            float qn[4];
+            mfma_mv<true>(sm.S.m[cp - 2][L.r][0], L, uu[s], qn);
+            (void)rescale_shared<R>(qn);
+            if (cp < 8) {
+#pragma unroll
+                for (int u = 0; u < 4; ++u) q[cp < 8 ? cp : 0][u] = qn[u];
+            } else {
+                st_part<R, true>(part, cn - N, tile, tiles, L.part, to_f4(qn));
+            }
+        }
+    });
+    __syncthreads();
+    // per-tile sums of W_c num / den for the (up to) 14 child branches: sixteen
+    // threads per branch, four patterns each, then a sixteen-lane reduction;
+    // fixed order, so results are deterministic
+    constexpr int kThreads = kLanes * R;
+    GLOBAL double* gpart = g(d.gpart);
+    int ndv = 0;                                        // lanes 0..15: the heap record
+#pragma unroll
+    for (int j = 0; j < 16; ++j) ndv = write_lane(ndv, nd[j], j);
+#pragma unroll
+    for (int t0 = 0; t0 < 14 * 16; t0 += kThreads) {
+        const int t = t0 + static_cast<int>(threadIdx.x);
+        const int j = min(t >> 4, 13);
+        const int sub = t & 15;
+        double acc = 0.0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int pp = sub * 4 + i;
+            const double W = sm.wl[pp];
+            if (W != 0.0)
+                acc += W * (static_cast<double>(sm.gnum[j][pp]) / static_cast<double>(sm.gden[j >> 1][pp]));
+        }
+#pragma unroll
+        for (int off = 8; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 16);
+        const int parent_node = __builtin_amdgcn_ds_bpermute(((j >> 1) + 1) << 2, ndv);
+        const int child = __builtin_amdgcn_ds_bpermute((j + 2) << 2, ndv);
+        if (sub == 0 && t < 14 * 16 && parent_node >= N) gpart[static_cast<size_t>(child) * tiles + tile] = acc;
+    }
+}
+
+// ------------------------------------------- work-queue traversal (blocked, FP32)
+//
+// One launch per pass (or one for both) in place of one launch per block
+// level.  Work items are (block, tile) pairs, numbered so that every item's
+// inputs come from items with smaller numbers: post-order levels deepest
+// first, then pre-order levels from the root's down; within a level
+// tile-major, so one tile's items finish close together and the next level's
+// items of that tile are ready when they are reached.  Tiles are independent,
+// so one tile's items near the root run while other tiles are still in wide
+// levels: no launch boundary and no level-wide barrier.
+//
+// Workgroup i takes item t0 + i and waits only on items with smaller numbers.
+// Forward progress rests on the dispatcher starting a launch's workgroups in
+// increasing order on each XCD: then the unfinished item with the smallest
+// number is running or next to start on its XCD (every earlier workgroup of
+// that XCD has finished), and its inputs are complete.  (A device-wide ticket
+// counter would not need that order, but one atomic per workgroup on one
+// address serialises: it made the traversal ~2.8x slower than the level
+// launches.)  An item is complete when its completion mark, per (pass, block,
+// tile), equals the evaluation's epoch, which the evaluation's P(t) launch
+// advances; marks of earlier evaluations hold other values, so nothing is
+// cleared between evaluations and the launches replay in a graph.  Every wait
+// is bounded: past `wait_ticks` of the device's constant clock the item sets
+// the fault word and goes on, its results invalid (the final sums then turn
+// to NaN), and once the word is set every other wait ends at its next poll,
+// so every workgroup exits.
+//
+// Partials and exponents that cross items use device-coherent accesses
+// (kCoh); an item's mark is stored after its stores have completed at device
+// scope (vmcnt(0) in every wave, then a barrier).
+
+__device__ __forceinline__ uint32_t ld_mark(const GLOBAL uint32_t* base, uint32_t idx, int count) {
+    return static_cast<uint32_t>(ld_i32<true>(reinterpret_cast<const GLOBAL int32_t*>(base), idx, count));
+}
+
+// kPasses: 1 post-order items only, 2 pre-order items only, 3 both.
+template <int R, int kPasses>
+__global__ __launch_bounds__(kLanes * R) __attribute__((amdgpu_waves_per_eu(4))) void queue_bmf_kernel(
+    const ReqDesc* __restrict__ descs, const QueueArgs q) {
+    union Lds {
+        PostBmfLds<R> post;
+        PreBmfLds<R> pre;
+    };
+    __shared__ Lds sm;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & (kLanes - 1);
+    const ReqDesc& d = descs[0];
+    const int tiles = d.tiles;
+    const int B = q.n_blocks;
+    const int n_marks = 2 * B * tiles;
+    GLOBAL uint32_t* done = g(q.done);
+    // the epoch (advanced by this evaluation's P(t) launch) is constant
+    // during the launch: a plain scalar load
+    const uint32_t target = g(q.ctr)[kQueueEpoch];
+    const int t = q.t0 + static_cast<int>(blockIdx.x);
+    if (t >= q.t1) return;
+    const int code = g(q.items)[2 * static_cast<size_t>(t)];
+    const int tile = g(q.items)[2 * static_cast<size_t>(t) + 1];
+    const int pass = kPasses == 3 ? code >> 30 : kPasses - 1;
+    const int rec = code & 0x3FFFFFFF;
+    const GLOBAL int32_t* heap = reinterpret_cast<const GLOBAL int32_t*>(g(d.sched)) + static_cast<size_t>(rec) * 16;
+    // wave 0 polls the marks this item needs: post-order, lane j < 8 the
+    // block rooted at frontier position 8 + j; pre-order, lane 0 the parent
+    // block's pre-order mark (the root block: its own post-order mark, which
+    // implies every post-order item of the tile)
+    auto wait = [&]() {
+        if (w == 0) {
+            int m = -1;
+            const GLOBAL int32_t* dep = g(q.dep) + static_cast<size_t>(rec) * 16;
+            if (pass == 0) {
+                if (lane < 8) {
+                    const int cb = dep[lane];
+                    if (cb >= 0) m = cb * tiles + tile;
+                }
+            } else if (lane == 0) {
+                const int pb = dep[8];
+                m = pb >= 0 ? (B + pb) * tiles + tile : rec * tiles + tile;
+            }
+            // lane 63 watches the fault word
+            const GLOBAL int32_t* cw = reinterpret_cast<const GLOBAL int32_t*>(g(q.ctr));
+            const uint64_t t_start = wall_clock64();
+            for (;;) {
+                const bool ok = m < 0 || ld_mark(done, static_cast<uint32_t>(max(m, 0)), n_marks) == target;
+                const bool quit = lane == kLanes - 1 && ld_i32<true>(cw, kQueueFault, kQueueWords) != 0;
+                if (__builtin_amdgcn_ballot_w64(!ok) == 0 || __builtin_amdgcn_ballot_w64(quit) != 0) break;
+                if (wall_clock64() - t_start > q.wait_ticks) {
+                    if (lane == 0)
+                        st_i32<true>(reinterpret_cast<GLOBAL int32_t*>(g(q.ctr)), kQueueFault, kQueueWords, 1);
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(2);
+            }
+        }
+        __syncthreads();
+    };
+    if constexpr (kPasses == 1) {
+        post_bmf_body<R>(d, heap, tile, tiles, rec == q.root_rec, sm.post, w, lane, wait);
+    } else if constexpr (kPasses == 2) {
+        pre_bmf_body<R>(d, heap, tile, tiles, sm.pre, w, lane, wait);
+    } else {
+        if (pass == 0)
+            post_bmf_body<R>(d, heap, tile, tiles, rec == q.root_rec, sm.post, w, lane, wait);
+        else
+            pre_bmf_body<R>(d, heap, tile, tiles, sm.pre, w, lane, wait);
+    }
+    __builtin_amdgcn_s_waitcnt(0x0F70);                 // vmcnt(0): this wave's stores are complete
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        st_i32<true>(reinterpret_cast<GLOBAL int32_t*>(done), (pass * B + rec) * tiles + tile, n_marks,
+                     static_cast<int>(target));
+    }
+}
+
 // S = 4: one thread per row s of one (branch, category) pair, so a pair's
 // four rows come from four neighbouring lanes (contiguous stores) and even a
 // small tree spreads over many workgroups.  Row s of P and dP:
@@ -1298,6 +1680,13 @@ __global__ __launch_bounds__(kPmatBlock) void pmat4_kernel(const ReqDesc* __rest
     const int gid = blockIdx.x * kPmatBlock + threadIdx.x;
     const int unit = gid >> 2;
     const int s = gid & 3;
+    if (gid == 0 && descs[segs.seg[0].desc].qctr) {
+        // a new evaluation of a work-queue context: a new epoch for its
+        // marks, no fault yet
+        uint32_t* c = descs[segs.seg[0].desc].qctr;
+        __hip_atomic_fetch_add(&c[kQueueEpoch], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_exchange(&c[kQueueFault], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
     if (unit >= segs.unit_begin[segs.n]) return;
     int sidx = 0;
     while (sidx + 1 < segs.n && unit >= segs.unit_begin[sidx + 1]) ++sidx;
@@ -1427,10 +1816,14 @@ __global__ __launch_bounds__(256) void finalize_kernel(const ReqDesc* __restrict
         __syncthreads();
     }
     if (threadIdx.x == 0) {
+        // a work-queue traversal whose dependency wait gave up: invalid sums
+        const bool fault =
+            d.qctr && __hip_atomic_load(&d.qctr[kQueueFault], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+        const double v = fault ? __builtin_nan("") : red[0];
         if (blk < E)
-            sg.out_grad[blk] = red[0];
+            sg.out_grad[blk] = v;
         else
-            *sg.out_logl = red[0];
+            *sg.out_logl = v;
     }
 }
 
@@ -1535,6 +1928,33 @@ hipError_t launch_class(KernelClass k, const ReqDesc& shape, const ReqDesc* desc
         case kFinal:
             hipLaunchKernelGGL(finalize_kernel, dim3(n_units), dim3(256), 0, st, descs, t);
             return hipGetLastError();
+    }
+    return hipErrorInvalidValue;
+}
+
+namespace {
+template <int R>
+hipError_t queue_r(const ReqDesc* descs, const QueueArgs& q, int passes, hipStream_t st) {
+    const dim3 grid(q.t1 - q.t0), block(kLanes * R);
+    if (passes == 1)
+        hipLaunchKernelGGL((queue_bmf_kernel<R, 1>), grid, block, 0, st, descs, q);
+    else if (passes == 2)
+        hipLaunchKernelGGL((queue_bmf_kernel<R, 2>), grid, block, 0, st, descs, q);
+    else
+        hipLaunchKernelGGL((queue_bmf_kernel<R, 3>), grid, block, 0, st, descs, q);
+    return hipGetLastError();
+}
+}  // namespace
+
+hipError_t launch_queue(const ReqDesc& shape, const ReqDesc* descs, const QueueArgs& q, int passes,
+                        hipStream_t st) {
+    if (q.t1 <= q.t0) return hipSuccess;
+    if (!queue_supported(shape.S, shape.R, shape.fp32 != 0) || passes < 1 || passes > 3) return hipErrorInvalidValue;
+    switch (shape.R) {
+        case 1: return queue_r<1>(descs, q, passes, st);
+        case 2: return queue_r<2>(descs, q, passes, st);
+        case 4: return queue_r<4>(descs, q, passes, st);
+        case 8: return queue_r<8>(descs, q, passes, st);
     }
     return hipErrorInvalidValue;
 }

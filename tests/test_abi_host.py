@@ -209,6 +209,41 @@ def test_block_schedule_shape():
         B.phg_destroy(ctx)
 
 
+def test_queue_schedule_is_opt_in_and_checked():
+    N = 300
+    parent = synth.yule_topology(N, np.random.default_rng(4))
+    ctx = B.phg_create(N, 100, 4, 4, B.PHG_FP32_SCALED, 0)
+    try:
+        B.phg_set_topology(ctx, parent)
+        assert B.phg_get_schedule(ctx) == B.PHG_SCHEDULE_BLOCKS       # AUTO: not the queue
+        B.phg_set_schedule(ctx, B.PHG_SCHEDULE_QUEUE)
+        assert B.phg_get_schedule(ctx) == B.PHG_SCHEDULE_QUEUE
+        post_q, pre_q, _ = B.phg_schedule_info(ctx)
+        B.phg_set_schedule(ctx, B.PHG_SCHEDULE_BLOCKS)
+        assert B.phg_schedule_info(ctx)[:2] == (post_q, pre_q)         # the same block levels
+        with pytest.raises(B.PhgError) as e:
+            B.phg_set_schedule(ctx, 4)
+        assert e.value.status == B.PHG_ERR_ARG
+    finally:
+        B.phg_destroy(ctx)
+    # FP32, 4 states and R in {1, 2, 4, 8} only
+    for S, R, prec in ((4, 4, B.PHG_FP64), (4, 3, B.PHG_FP32_SCALED), (20, 4, B.PHG_FP32_SCALED)):
+        ctx = B.phg_create(30, 10, S, R, prec, 0)
+        try:
+            with pytest.raises(B.PhgError) as e:
+                B.phg_set_schedule(ctx, B.PHG_SCHEDULE_QUEUE)
+            assert e.value.status == B.PHG_ERR_ARG
+        finally:
+            B.phg_destroy(ctx)
+    # launches per evaluation: 1 or 2, 4-state FP32 only
+    B.phg_set_tuning(4, 0, B.PHG_FP32_SCALED, B.PHG_TUNE_QUEUE_LAUNCHES, 1)
+    assert B.phg_get_tuning(4, 0, B.PHG_FP32_SCALED, B.PHG_TUNE_QUEUE_LAUNCHES) == 1
+    B.phg_set_tuning(4, 0, B.PHG_FP32_SCALED, B.PHG_TUNE_QUEUE_LAUNCHES, 0)
+    for S, prec, v in ((4, B.PHG_FP32_SCALED, 3), (4, B.PHG_FP64, 1), (20, B.PHG_FP32_SCALED, 1)):
+        with pytest.raises(B.PhgError):
+            B.phg_set_tuning(S, 0, prec, B.PHG_TUNE_QUEUE_LAUNCHES, v)
+
+
 def test_time_tree_and_branch_set_validation():
     N = 6
     parent = synth.yule_topology(N, np.random.default_rng(2))
