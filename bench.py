@@ -37,14 +37,14 @@ HBM_PEAK_GBS = 8000.0
 KERNEL_SRC = os.path.join(ROOT, "paper_2303_04390_amd", "csrc", "phg_kernels.hip")
 
 # HBM bytes per evaluation by kernel class on the hky1000 FP32 workload under the
-# blocked schedule, from two rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE;
-# scaled by a plain 1 GiB copy: x2.0 and x1.0; profiles/blocked_kernels_hky1000_fp32.md),
+# work-queue schedule, from two rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE;
+# scaled by a plain 1 GiB copy: x2.0 and x1.0; profiles/queue_kernels_hky1000_fp32.md),
 # recorded with the kernel source whose SHA-256 is given.  When the kernel
 # source or the schedule differs the figure no longer applies and traffic is null.
 MEASURED_TRAFFIC = {
-    "kernel_source_sha256": "4ff02b16603618c4143e86f72cb817ad6c6ac1a9ddb74d7dd73fc01cb0eaaf1f",
-    "schedule": "blocks",
-    "bytes_per_eval": {"pre_grad": 738460451, "post": 484050494},
+    "kernel_source_sha256": "c94ebd4b0cc6def9b5474f04d694fede0fde9e49cdd2d684894fe7b15f2e73c7",
+    "schedule": "queue",
+    "bytes_per_eval": {"pre_grad": 718464614, "post": 493573837},
 }
 
 
