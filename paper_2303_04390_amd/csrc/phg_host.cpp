@@ -295,7 +295,8 @@ void build_schedule(phg_context* ctx) {
     ctx->qdep.clear();
     const bool fp32 = ctx->prec == PHG_FP32_SCALED;
     // the blocked kernels take tips by their codes only
-    ctx->blocked = ctx->sched_mode == PHG_SCHEDULE_BLOCKS || ctx->sched_mode == PHG_SCHEDULE_QUEUE ||
+    ctx->blocked = ctx->sched_mode == PHG_SCHEDULE_BLOCKS ||
+                   (ctx->sched_mode == PHG_SCHEDULE_QUEUE && phg::blocked_supported(ctx->S, ctx->R, fp32)) ||
                    (ctx->sched_mode == PHG_SCHEDULE_AUTO && phg::blocked_supported(ctx->S, ctx->R, fp32) &&
                     ctx->tip_vectors.empty());
     if (ctx->blocked) {
@@ -327,7 +328,7 @@ void build_schedule(phg_context* ctx) {
         for (int m = M; m >= 0; --m) ctx->post_lv.emplace_back(start[m], start[m + 1] - start[m]);
         for (int m = 0; m <= M; ++m) ctx->pre_lv.emplace_back(start[m], start[m + 1] - start[m]);
         const int B = start[M + 1];
-        ctx->queue = ctx->sched_mode == PHG_SCHEDULE_QUEUE && phg::queue_supported(ctx->S, ctx->R, fp32) &&
+        ctx->queue = ctx->sched_mode == PHG_SCHEDULE_QUEUE && ctx->S == 4 && phg::queue_supported(ctx->S, ctx->R, fp32) &&
                      static_cast<int64_t>(2) * B * ctx->tiles * phg::kLanes * ctx->R < (int64_t{1} << 31);
         if (ctx->queue) {
             // dependencies: the records of the blocks rooted at each frontier
@@ -395,6 +396,33 @@ void build_schedule(phg_context* ctx) {
         for (int v : bd[d]) put(v);
         ctx->pre_lv.emplace_back(a, static_cast<int>(ctx->sched.size() / 4) - a);
     }
+    // work-queue traversal of the vector-ALU kernels (tables for every branch)
+    const int n_rec = static_cast<int>(ctx->sched.size() / 4);
+    ctx->queue = ctx->sched_mode == PHG_SCHEDULE_QUEUE && phg::uses_vs_kernels(ctx->S, ctx->R, fp32) &&
+                 table_slots_for(N, ctx->S, ctx->R, ctx->prec, ctx->table_budget) == 0 &&
+                 static_cast<int64_t>(n_rec) * ctx->tiles * phg::kLanes * ctx->R < (int64_t{1} << 31);
+    if (!ctx->queue) return;
+    // a pre-order record waits on its parent's (which wrote its vector)
+    ctx->qdep.assign(static_cast<size_t>(2) * n_rec, -1);
+    for (const auto& lv : ctx->pre_lv)
+        for (int r = lv.first; r < lv.first + lv.second; ++r) {
+            const int k = ctx->sched[4 * r];
+            if (k != root) ctx->qdep[2 * r] = ctx->parent[k] - N;
+        }
+    // items: post-order levels deepest first, then pre-order levels from the
+    // root's; tile-major within a level
+    ctx->qitems.clear();
+    ctx->qitems.reserve(static_cast<size_t>(2) * n_rec * ctx->tiles);
+    for (int pass = 0; pass < 2; ++pass) {
+        for (const auto& lv : pass == 0 ? ctx->post_lv : ctx->pre_lv)
+            for (int t = 0; t < ctx->tiles; ++t)
+                for (int r = lv.first; r < lv.first + lv.second; ++r) {
+                    ctx->qitems.push_back(r);
+                    ctx->qitems.push_back(t);
+                }
+        if (pass == 0) ctx->q_post = static_cast<int>(ctx->qitems.size() / 2);
+    }
+    ctx->q_blocks = N - 1;
 }
 
 // Devices already checked to be gfx950 (bit per ordinal < 64).
@@ -630,10 +658,11 @@ phg_status upload(phg_context* ctx) {
         // completion marks and counters start at zero (epoch 0: the first
         // evaluation's marks are 1); the marks of another topology would not
         // match its records
-        zeros.assign(ctx->qitems.size() + kQueueWords, 0u);
+        const size_t marks = static_cast<size_t>(2) * ctx->q_blocks * ctx->tiles;
+        zeros.assign(std::max<size_t>(marks, kQueueWords), 0u);
         PHG_HIP(ctx, put(pl.qitems, ctx->qitems.data(), ctx->qitems.size() * sizeof(int32_t)));
         PHG_HIP(ctx, put(pl.qdep, ctx->qdep.data(), ctx->qdep.size() * sizeof(int32_t)));
-        PHG_HIP(ctx, put(pl.qdone, zeros.data(), ctx->qitems.size() / 2 * sizeof(uint32_t)));
+        PHG_HIP(ctx, put(pl.qdone, zeros.data(), marks * sizeof(uint32_t)));
         PHG_HIP(ctx, put(pl.qctr, zeros.data(), kQueueWords * sizeof(uint32_t)));
     }
     if (dirty & kTopo) {
@@ -779,7 +808,8 @@ phg_status ctx_enqueue_eval(phg_context* ctx, double* d_logl, double* d_grad) {
         q.root_rec = ctx->pre_lv.front().first;
         q.wait_ticks = queue_wait_ticks(ctx->device);
         const int n_items = static_cast<int>(ctx->qitems.size() / 2);
-        const bool one_launch = d_grad && !ctx->prof_on && queue_launches(d.S, d.R, d.fp32 != 0) == 1;
+        const bool one_launch =
+            d_grad && !ctx->prof_on && d.S == 4 && queue_launches(d.S, d.R, d.fp32 != 0) == 1;
         q.t0 = 0;
         q.t1 = one_launch ? n_items : ctx->q_post;
         PHG_HIP(ctx, launch_queue(d, descs, q, one_launch ? 3 : 1, st));
@@ -1202,7 +1232,7 @@ phg_status phg_set_tip_states(phg_context* ctx, const int32_t* codes) {
 phg_status phg_set_tip_partials(phg_context* ctx, int tip, const double* partials) {
     if (!ctx) return PHG_ERR_ARG;
     if (tip < 0 || tip >= ctx->N) return ctx->fail(PHG_ERR_ARG, "tip %d outside [0, %d)", tip, ctx->N);
-    if (partials && (ctx->sched_mode == PHG_SCHEDULE_BLOCKS || ctx->sched_mode == PHG_SCHEDULE_QUEUE))
+    if (partials && (ctx->sched_mode == PHG_SCHEDULE_BLOCKS || (ctx->sched_mode == PHG_SCHEDULE_QUEUE && ctx->S == 4)))
         return ctx->fail(PHG_ERR_ARG, "general tip partials need the level schedule (schedule is BLOCKS)");
     const size_t n = static_cast<size_t>(ctx->C) * ctx->S;
     if (partials) {
@@ -1249,8 +1279,9 @@ phg_status phg_set_schedule(phg_context* ctx, phg_schedule mode) {
         !phg::blocked_supported(ctx->S, ctx->R, ctx->prec == PHG_FP32_SCALED))
         return ctx->fail(PHG_ERR_ARG, "the blocked schedule needs 4 states and R <= 8");
     if (mode == PHG_SCHEDULE_QUEUE && !phg::queue_supported(ctx->S, ctx->R, ctx->prec == PHG_FP32_SCALED))
-        return ctx->fail(PHG_ERR_ARG, "the work-queue traversal needs 4 states, FP32 and R in {1, 2, 4, 8}");
-    if ((mode == PHG_SCHEDULE_BLOCKS || mode == PHG_SCHEDULE_QUEUE) && !ctx->tip_vectors.empty())
+        return ctx->fail(PHG_ERR_ARG, "the work-queue traversal needs 4 states with FP32 and R in {1, 2, 4, 8}, "
+                                      "or the vector-ALU kernels' shapes");
+    if ((mode == PHG_SCHEDULE_BLOCKS || (mode == PHG_SCHEDULE_QUEUE && ctx->S == 4)) && !ctx->tip_vectors.empty())
         return ctx->fail(PHG_ERR_ARG, "the blocked schedule does not take general tip partials");
     ctx->sched_mode = mode;
     if (ctx->have & kTopo) {
@@ -1517,7 +1548,8 @@ phg_status phg_schedule_info(phg_context* ctx, int* n_post_levels, int* n_pre_le
         int cls[PHG_PROF_CLASSES];
         launches_per_class(ctx, cls);
         // the work-queue traversal may run both passes in one launch
-        const bool one = ctx->queue && queue_launches(ctx->S, ctx->R, ctx->prec == PHG_FP32_SCALED) == 1;
+        const bool one =
+            ctx->queue && ctx->S == 4 && queue_launches(ctx->S, ctx->R, ctx->prec == PHG_FP32_SCALED) == 1;
         *n_launches = cls[0] + cls[1] + (one ? 0 : cls[2]) + cls[3];
     }
     return PHG_OK;

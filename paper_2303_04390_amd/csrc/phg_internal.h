@@ -165,11 +165,11 @@ constexpr int kBlockDepth = 3;
 // every in-block vector in registers.
 inline bool blocked_supported(int S, int R, bool /*fp32*/) { return S == 4 && R <= 8; }
 
-// Work-queue traversal of the blocked schedule (FP32, 4 states, R in
-// {1, 2, 4, 8}): one launch for both passes instead of one per block level.
-inline bool queue_supported(int S, int R, bool fp32) {
-    return S == 4 && fp32 && R <= 8 && (R & (R - 1)) == 0;
-}
+// Work-queue traversals: one launch per pass (or, 4 states, one for both)
+// instead of one per level, over the blocked schedule (FP32, 4 states, R in
+// {1, 2, 4, 8}) or the level schedule of the vector-ALU kernels (with P(t)
+// tables for every branch).
+inline bool queue_supported(int S, int R, bool fp32);
 // Counter words of a context's queue (each on a 64-byte line of its own):
 // the epoch and the fault word.
 constexpr int kQueueEpoch = 0, kQueueFault = 16, kQueueWords = 32;
@@ -195,7 +195,10 @@ struct QueueArgs {
 };
 // Items [q.t0, q.t1) of the context whose descriptor is descs[0], one
 // workgroup each; passes: 1 the range holds post-order items only, 2
-// pre-order items only, 3 both.
+// pre-order items only, 3 both (4 states only).  Records: block records
+// (4 states; dep [B][16]: frontier children's blocks, parent block) or level
+// records (vector-ALU kernels; dep [records][2]: the parent's node slot of a
+// pre-order record, marks per node slot).
 hipError_t launch_queue(const ReqDesc& shape, const ReqDesc* descs, const QueueArgs& q, int passes,
                         hipStream_t stream);
 
@@ -263,6 +266,11 @@ inline bool folds_tip_pairs(int S, int R, bool fp32) {
     return uses_vs_kernels(S, R, fp32) || (uses_gl_kernels(S, R, fp32) && S > 32);
 }
 inline bool folds_pre_order(int S, int R, bool fp32) { return uses_vs_kernels(S, R, fp32); }
+inline bool queue_supported(int S, int R, bool fp32) {
+    return (S == 4 && fp32 && R <= 8 && (R & (R - 1)) == 0) || uses_vs_kernels(S, R, fp32);
+}
+hipError_t launch_vs_queue(const ReqDesc& shape, const ReqDesc* descs, const QueueArgs& q, int pass,
+                           hipStream_t stream);
 // Their operand order: a stored vector (one pattern's partial) or matrix row
 // holds state t at column gl_col(t) = (t mod 4) KBP + t / 4, so the states
 // 4k + g that MFMA lane group g consumes on k-steps k, k+1, ... are adjacent

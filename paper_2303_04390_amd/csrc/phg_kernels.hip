@@ -31,6 +31,7 @@
 // Partials are stored [slot][tile][r][lane][4], so each category of a unit is
 // one contiguous 1 KiB (float) wave access.
 #include "phg_internal.h"
+#include "phg_queue_device.h"
 
 #include <math.h>
 
@@ -801,65 +802,38 @@ __device__ __forceinline__ GLOBAL char* chunk(GLOBAL F4* part, unsigned slot, un
 // Loads and stores of the partials and exponents that one work item writes
 // and another reads.  kCoh = false: ordinary accesses (level launches, where
 // the launch boundary orders producer and consumer).  kCoh = true (the
-// work-queue kernel, where both run inside one launch): buffer accesses with
-// the device-scope coherence bit, which skip stale copies in the per-CU cache
-// and in the L2 of another XCD; `base` is wave-uniform (a chunk or row base).
-constexpr int kScDevice = 16;                // cache policy: sc1 (device scope)
-constexpr int kRsrcFlags = 0x00020000;       // buffer descriptor word 3 (raw 32-bit data)
-template <bool kCoh>
-__device__ __forceinline__ F4 ld_f4(const GLOBAL char* base, uint32_t off, int bytes) {
-    if constexpr (kCoh) {
-        const auto rs = __builtin_amdgcn_make_buffer_rsrc(const_cast<GLOBAL char*>(base), 0, bytes, kRsrcFlags);
-        return __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, kScDevice);
-    } else {
-        return *reinterpret_cast<const GLOBAL F4*>(base + off);
-    }
-}
-template <bool kCoh>
-__device__ __forceinline__ void st_f4(GLOBAL char* base, uint32_t off, int bytes, F4 v) {
-    if constexpr (kCoh) {
-        const auto rs = __builtin_amdgcn_make_buffer_rsrc(base, 0, bytes, kRsrcFlags);
-        __builtin_amdgcn_raw_buffer_store_b128(v, rs, off, 0, kScDevice);
-    } else {
-        *reinterpret_cast<GLOBAL F4*>(base + off) = v;
-    }
-}
-template <bool kCoh>
-__device__ __forceinline__ int ld_i32(const GLOBAL int32_t* base, uint32_t idx, int count) {
-    if constexpr (kCoh) {
-        const auto rs = __builtin_amdgcn_make_buffer_rsrc(const_cast<GLOBAL int32_t*>(base), 0, 4 * count, kRsrcFlags);
-        return __builtin_amdgcn_raw_buffer_load_b32(rs, 4 * idx, 0, kScDevice);
-    } else {
-        return base[idx];
-    }
-}
-template <bool kCoh>
-__device__ __forceinline__ void st_i32(GLOBAL int32_t* base, uint32_t idx, int count, int v) {
-    if constexpr (kCoh) {
-        const auto rs = __builtin_amdgcn_make_buffer_rsrc(base, 0, 4 * count, kRsrcFlags);
-        __builtin_amdgcn_raw_buffer_store_b32(v, rs, 4 * idx, 0, kScDevice);
-    } else {
-        base[idx] = v;
-    }
-}
-// The partial of (slot, tile) for the lane (r, pattern), and the exponent of
+// work-queue kernel, where both run inside one launch): device-coherent
+// (queue::ld / queue::st).  The partial of (slot, tile) for the lane
+// (r, pattern), at byte offset `off` of the chunk, and the exponent of
 // (slot, pattern c = tile * 64 + pat).
 template <int R, bool kCoh>
 __device__ __forceinline__ F4 ld_part(GLOBAL F4* part, unsigned slot, unsigned tile, unsigned tiles, uint32_t off) {
-    return ld_f4<kCoh>(chunk<R>(part, slot, tile, tiles), off, R * kLanes * 16);
+    const GLOBAL F4* base = reinterpret_cast<const GLOBAL F4*>(chunk<R>(part, slot, tile, tiles));
+    if constexpr (kCoh) return queue::ld(base, off / 16, R * kLanes);
+    return base[off / 16];
 }
 template <int R, bool kCoh>
 __device__ __forceinline__ void st_part(GLOBAL F4* part, unsigned slot, unsigned tile, unsigned tiles, uint32_t off,
                                         F4 v) {
-    st_f4<kCoh>(chunk<R>(part, slot, tile, tiles), off, R * kLanes * 16, v);
+    GLOBAL F4* base = reinterpret_cast<GLOBAL F4*>(chunk<R>(part, slot, tile, tiles));
+    if constexpr (kCoh)
+        queue::st(base, off / 16, R * kLanes, v);
+    else
+        base[off / 16] = v;
 }
 template <bool kCoh>
 __device__ __forceinline__ int ld_expo(const GLOBAL int32_t* expo, unsigned slot, int Cpad, unsigned tile, int pat) {
-    return ld_i32<kCoh>(expo + static_cast<size_t>(slot) * Cpad + static_cast<size_t>(tile) * kLanes, pat, kLanes);
+    const GLOBAL int32_t* base = expo + static_cast<size_t>(slot) * Cpad + static_cast<size_t>(tile) * kLanes;
+    if constexpr (kCoh) return queue::ld(base, pat, kLanes);
+    return base[pat];
 }
 template <bool kCoh>
 __device__ __forceinline__ void st_expo(GLOBAL int32_t* expo, unsigned slot, int Cpad, unsigned tile, int pat, int v) {
-    st_i32<kCoh>(expo + static_cast<size_t>(slot) * Cpad + static_cast<size_t>(tile) * kLanes, pat, kLanes, v);
+    GLOBAL int32_t* base = expo + static_cast<size_t>(slot) * Cpad + static_cast<size_t>(tile) * kLanes;
+    if constexpr (kCoh)
+        queue::st(base, pat, kLanes, v);
+    else
+        base[pat] = v;
 }
 
 __device__ __forceinline__ void f4_to(const F4 q, float out[4]) {
@@ -1584,10 +1558,6 @@ __device__ __forceinline__ void pre_bmf_body(const ReqDesc& d, const GLOBAL int3
 // (kCoh); an item's mark is stored after its stores have completed at device
 // scope (vmcnt(0) in every wave, then a barrier).
 
-__device__ __forceinline__ uint32_t ld_mark(const GLOBAL uint32_t* base, uint32_t idx, int count) {
-    return static_cast<uint32_t>(ld_i32<true>(reinterpret_cast<const GLOBAL int32_t*>(base), idx, count));
-}
-
 // kPasses: 1 post-order items only, 2 pre-order items only, 3 both.
 template <int R, int kPasses>
 __global__ __launch_bounds__(kLanes * R) __attribute__((amdgpu_waves_per_eu(4))) void queue_bmf_kernel(
@@ -1603,10 +1573,7 @@ __global__ __launch_bounds__(kLanes * R) __attribute__((amdgpu_waves_per_eu(4)))
     const int tiles = d.tiles;
     const int B = q.n_blocks;
     const int n_marks = 2 * B * tiles;
-    GLOBAL uint32_t* done = g(q.done);
-    // the epoch (advanced by this evaluation's P(t) launch) is constant
-    // during the launch: a plain scalar load
-    const uint32_t target = g(q.ctr)[kQueueEpoch];
+    const uint32_t target = queue::epoch(q);
     const int t = q.t0 + static_cast<int>(blockIdx.x);
     if (t >= q.t1) return;
     const int code = g(q.items)[2 * static_cast<size_t>(t)];
@@ -1631,20 +1598,7 @@ __global__ __launch_bounds__(kLanes * R) __attribute__((amdgpu_waves_per_eu(4)))
                 const int pb = dep[8];
                 m = pb >= 0 ? (B + pb) * tiles + tile : rec * tiles + tile;
             }
-            // lane 63 watches the fault word
-            const GLOBAL int32_t* cw = reinterpret_cast<const GLOBAL int32_t*>(g(q.ctr));
-            const uint64_t t_start = wall_clock64();
-            for (;;) {
-                const bool ok = m < 0 || ld_mark(done, static_cast<uint32_t>(max(m, 0)), n_marks) == target;
-                const bool quit = lane == kLanes - 1 && ld_i32<true>(cw, kQueueFault, kQueueWords) != 0;
-                if (__builtin_amdgcn_ballot_w64(!ok) == 0 || __builtin_amdgcn_ballot_w64(quit) != 0) break;
-                if (wall_clock64() - t_start > q.wait_ticks) {
-                    if (lane == 0)
-                        st_i32<true>(reinterpret_cast<GLOBAL int32_t*>(g(q.ctr)), kQueueFault, kQueueWords, 1);
-                    break;
-                }
-                __builtin_amdgcn_s_sleep(2);
-            }
+            queue::wait_marks(q, m, target, n_marks, lane);
         }
         __syncthreads();
     };
@@ -1658,12 +1612,9 @@ __global__ __launch_bounds__(kLanes * R) __attribute__((amdgpu_waves_per_eu(4)))
         else
             pre_bmf_body<R>(d, heap, tile, tiles, sm.pre, w, lane, wait);
     }
-    __builtin_amdgcn_s_waitcnt(0x0F70);                 // vmcnt(0): this wave's stores are complete
+    queue::stores_complete();
     __syncthreads();
-    if (threadIdx.x == 0) {
-        st_i32<true>(reinterpret_cast<GLOBAL int32_t*>(done), (pass * B + rec) * tiles + tile, n_marks,
-                     static_cast<int>(target));
-    }
+    if (threadIdx.x == 0) queue::set_mark(q, (pass * B + rec) * tiles + tile, target, n_marks);
 }
 
 // S = 4: one thread per row s of one (branch, category) pair, so a pair's
@@ -1680,13 +1631,8 @@ __global__ __launch_bounds__(kPmatBlock) void pmat4_kernel(const ReqDesc* __rest
     const int gid = blockIdx.x * kPmatBlock + threadIdx.x;
     const int unit = gid >> 2;
     const int s = gid & 3;
-    if (gid == 0 && descs[segs.seg[0].desc].qctr) {
-        // a new evaluation of a work-queue context: a new epoch for its
-        // marks, no fault yet
-        uint32_t* c = descs[segs.seg[0].desc].qctr;
-        __hip_atomic_fetch_add(&c[kQueueEpoch], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_exchange(&c[kQueueFault], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
+    // a new evaluation of a work-queue context
+    if (gid == 0 && descs[segs.seg[0].desc].qctr) queue::new_evaluation(descs[segs.seg[0].desc].qctr);
     if (unit >= segs.unit_begin[segs.n]) return;
     int sidx = 0;
     while (sidx + 1 < segs.n && unit >= segs.unit_begin[sidx + 1]) ++sidx;
@@ -1950,6 +1896,7 @@ hipError_t launch_queue(const ReqDesc& shape, const ReqDesc* descs, const QueueA
                         hipStream_t st) {
     if (q.t1 <= q.t0) return hipSuccess;
     if (!queue_supported(shape.S, shape.R, shape.fp32 != 0) || passes < 1 || passes > 3) return hipErrorInvalidValue;
+    if (shape.S != 4) return passes == 3 ? hipErrorInvalidValue : launch_vs_queue(shape, descs, q, passes, st);
     switch (shape.R) {
         case 1: return queue_r<1>(descs, q, passes, st);
         case 2: return queue_r<2>(descs, q, passes, st);

@@ -39,9 +39,11 @@
 // normalised and their exponents dropped (the gradient ratio does not depend
 // on them).
 #include "phg_internal.h"
+#include "phg_queue_device.h"
 
 #include <math.h>
 
+#include <type_traits>
 #include <utility>
 
 namespace phg {
@@ -117,6 +119,43 @@ __device__ __forceinline__ void vs_store(GLOBAL T* __restrict__ base, int lane, 
     for (int s = 0; s < SP; ++s) base[s * kVL + lane] = v[s];
 }
 
+// The same with device-coherent accesses (kCoh: vectors that another item of
+// a work-queue launch writes or reads).
+template <typename T, int SP, bool kCoh>
+__device__ __forceinline__ void vs_load_k(const GLOBAL T* __restrict__ base, int lane, T (&v)[SP]) {
+    if constexpr (kCoh) {
+#pragma unroll
+        for (int s = 0; s < SP; ++s) v[s] = queue::ld(base, s * kVL + lane, SP * kVL);
+    } else {
+        vs_load<T, SP>(base, lane, v);
+    }
+}
+template <typename T, int SP, bool kCoh>
+__device__ __forceinline__ void vs_store_k(GLOBAL T* __restrict__ base, int lane, const T (&v)[SP]) {
+    if constexpr (kCoh) {
+#pragma unroll
+        for (int s = 0; s < SP; ++s) queue::st(base, s * kVL + lane, SP * kVL, v[s]);
+    } else {
+        vs_store<T, SP>(base, lane, v);
+    }
+}
+// Cumulative exponent of internal node x at this lane's pattern c.
+template <bool kCoh>
+__device__ __forceinline__ int vs_expo(const ReqDesc& d, int x, int tile, int lane) {
+    const GLOBAL int32_t* base =
+        g(d.expo) + static_cast<size_t>(x - d.N) * d.Cpad + static_cast<size_t>(tile) * kVL;
+    if constexpr (kCoh) return queue::ld(base, lane, kVL);
+    return base[lane];
+}
+template <bool kCoh>
+__device__ __forceinline__ void vs_set_expo(const ReqDesc& d, int x, int tile, int lane, int e) {
+    GLOBAL int32_t* base = g(d.expo) + static_cast<size_t>(x - d.N) * d.Cpad + static_cast<size_t>(tile) * kVL;
+    if constexpr (kCoh)
+        queue::st(base, lane, kVL, e);
+    else
+        base[lane] = e;
+}
+
 // Row s of a wave-uniform SP x SP matrix (in LDS) times this lane's vector v.
 template <typename T, int SP>
 __device__ __forceinline__ T vs_row(const T* __restrict__ M, int s, const T (&v)[SP]) {
@@ -176,6 +215,8 @@ struct VsUnit {
     int i, j, k, tile;
     int ti, tj;   // P(t) tables of the children: by branch, or by slot in per-chunk tables
     bool fi, fj;  // child i / j is a folded node
+    bool root;    // k is the tree root
+    int rec;      // work-queue launches: the record's index in the schedule
 };
 __device__ __forceinline__ bool vs_unit(const ReqDesc* __restrict__ descs, const SegTable& segs, VsUnit& U) {
     const int unit = blockIdx.x;
@@ -195,7 +236,62 @@ __device__ __forceinline__ bool vs_unit(const ReqDesc* __restrict__ descs, const
     U.tj = U.d->level_tables ? 2 * node_ix + 1 : U.j;
     U.fi = (rec[3] & 1) != 0;
     U.fj = (rec[3] & 2) != 0;
+    U.root = (U.sg.flags & 1) != 0;
     return true;
+}
+// Work-queue launches (the context's descriptor is descs[0]): workgroup i
+// takes item t0 + i, a (record, tile) pair of this launch's pass.
+__device__ __forceinline__ bool vs_unit(const ReqDesc* __restrict__ descs, const QueueArgs& q, VsUnit& U) {
+    const int t = q.t0 + static_cast<int>(blockIdx.x);
+    if (t >= q.t1) return false;
+    U.d = &descs[0];
+    U.sg = Segment{};
+    U.rec = g(q.items)[2 * static_cast<size_t>(t)];
+    U.tile = g(q.items)[2 * static_cast<size_t>(t) + 1];
+    const GLOBAL int32_t* rec = reinterpret_cast<const GLOBAL int32_t*>(g(U.d->sched)) + static_cast<size_t>(U.rec) * 4;
+    U.k = rec[0];
+    U.i = rec[1];
+    U.j = rec[2];
+    U.ti = U.i;
+    U.tj = U.j;
+    U.fi = (rec[3] & 1) != 0;
+    U.fj = (rec[3] & 2) != 0;
+    U.root = U.k == 2 * U.d->N - 2;
+    return true;
+}
+
+// Completion marks of the work-queue launches, per node slot and tile:
+// post-order [0, I tiles), pre-order [I tiles, 2 I tiles), I = q.n_blocks.
+// A post-order item waits on its stored children's marks, a pre-order item
+// on its parent's (which wrote its pre-order vector); wave 0 polls, then the
+// workgroup synchronises.
+__device__ __forceinline__ void vs_wait_post(const QueueArgs& q, const VsUnit& U, int r, int lane, uint32_t target) {
+    if (r == 0) {
+        const ReqDesc& d = *U.d;
+        int m = -1;
+        if (lane == 0 && U.i >= d.N && !U.fi) m = (U.i - d.N) * d.tiles + U.tile;
+        if (lane == 1 && U.j >= d.N && !U.fj) m = (U.j - d.N) * d.tiles + U.tile;
+        queue::wait_marks(q, m, target, 2u * q.n_blocks * d.tiles, lane);
+    }
+    __syncthreads();
+}
+__device__ __forceinline__ void vs_wait_pre(const QueueArgs& q, const VsUnit& U, int r, int lane, uint32_t target) {
+    if (r == 0) {
+        const ReqDesc& d = *U.d;
+        const int p = g(q.dep)[2 * static_cast<size_t>(U.rec)];     // the parent's slot, -1 at the root
+        const int m = lane == 0 && p >= 0 ? (q.n_blocks + p) * d.tiles + U.tile : -1;
+        queue::wait_marks(q, m, target, 2u * q.n_blocks * d.tiles, lane);
+    }
+    __syncthreads();
+}
+// End of an item: every wave's stores complete, then its mark.
+__device__ __forceinline__ void vs_done(const QueueArgs& q, const VsUnit& U, bool pre, uint32_t target) {
+    const ReqDesc& d = *U.d;
+    queue::stores_complete();
+    __syncthreads();
+    if (threadIdx.x == 0)
+        queue::set_mark(q, ((pre ? q.n_blocks : 0) + U.k - d.N) * d.tiles + U.tile, target,
+                        2u * q.n_blocks * d.tiles);
 }
 
 // A folded child x (internal, both children a, b tips given by codes): its
@@ -217,13 +313,13 @@ __device__ __forceinline__ void vs_folded(const ReqDesc& d, int x, int r, int c,
     for (int s = 0; s < SP; ++s) v[s] = Ba[s] * Bb[s];
 }
 // Child x's input vector: folded (formed from its tips) or loaded.
-template <typename T, int SP>
+template <typename T, int SP, bool kCoh = false>
 __device__ __forceinline__ void vs_input(const ReqDesc& d, bool folded, const GLOBAL T* src, int x, int r, int c,
                                          int lane, T (&v)[SP]) {
     if (folded)
         vs_folded<T, SP>(d, x, r, c, v);
     else
-        vs_load<T, SP>(src, lane, v);
+        vs_load_k<T, SP, kCoh>(src, lane, v);
 }
 
 // The gradient sums of a folded node x's two tip branches a < b, formed from
@@ -288,15 +384,15 @@ __device__ __forceinline__ void write_grad(const ReqDesc& d, const T (&xn_i)[R][
 
 // p_k = (P_i p_i) o (P_j p_j) per category, rescaled by the largest entry
 // over the node's categories; at the root the site likelihood instead.
-template <typename T, int SP, int R>
-__global__ __launch_bounds__(kVL * R) void post_vs_kernel(const ReqDesc* __restrict__ descs, const SegTable segs) {
+template <typename T, int SP, int R, bool kQ, typename Arg>
+__device__ __forceinline__ void post_vs_body(const ReqDesc* __restrict__ descs, const Arg& arg) {
     __shared__ __align__(16) T tab[R][2][SP * SP];   // P_i, P_j of each category
     __shared__ T xmax[R][kVL];
     __shared__ double xsite[R][kVL];
     const int r = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & (kVL - 1);
     VsUnit U;
-    if (!vs_unit(descs, segs, U)) return;
+    if (!vs_unit(descs, arg, U)) return;
     const ReqDesc& d = *U.d;
     const int N = d.N, S = d.S, Cpad = d.Cpad, tile = U.tile;
     const int c = tile * kVL + lane;
@@ -312,14 +408,24 @@ __global__ __launch_bounds__(kVL * R) void post_vs_kernel(const ReqDesc* __restr
         if (src_j) sj.store(tab[r][1], lane);
     }
     // the children's cumulative exponents (a folded child's is 0)
+    uint32_t target = 0;
+    if constexpr (kQ) {
+        target = queue::epoch(arg);
+        vs_wait_post(arg, U, r, lane, target);
+    }
     int ec = 0;
-    if (U.i >= N && !U.fi) ec += g(d.expo)[static_cast<size_t>(U.i - N) * Cpad + c];
-    if (U.j >= N && !U.fj) ec += g(d.expo)[static_cast<size_t>(U.j - N) * Cpad + c];
+    if constexpr (kQ) {
+        if (U.i >= N && !U.fi) ec += vs_expo<true>(d, U.i, tile, lane);
+        if (U.j >= N && !U.fj) ec += vs_expo<true>(d, U.j, tile, lane);
+    } else {
+        if (U.i >= N && !U.fi) ec += g(d.expo)[static_cast<size_t>(U.i - N) * Cpad + c];
+        if (U.j >= N && !U.fj) ec += g(d.expo)[static_cast<size_t>(U.j - N) * Cpad + c];
+    }
     __syncthreads();
     T p[SP];
     if (src_i) {   // p = P_i p_i
         T v[SP];
-        vs_input<T, SP>(d, U.fi, src_i, U.i, r, c, lane, v);
+        vs_input<T, SP, kQ>(d, U.fi, src_i, U.i, r, c, lane, v);
 #pragma unroll
         for (int s = 0; s < SP; ++s) {
             p[s] = vs_row<T, SP>(tab[r][0], s, v);
@@ -333,7 +439,7 @@ __global__ __launch_bounds__(kVL * R) void post_vs_kernel(const ReqDesc* __restr
     }
     if (src_j) {   // p *= P_j p_j
         T v[SP];
-        vs_input<T, SP>(d, U.fj, src_j, U.j, r, c, lane, v);
+        vs_input<T, SP, kQ>(d, U.fj, src_j, U.j, r, c, lane, v);
 #pragma unroll
         for (int s = 0; s < SP; ++s) {
             p[s] *= vs_row<T, SP>(tab[r][1], s, v);
@@ -345,7 +451,7 @@ __global__ __launch_bounds__(kVL * R) void post_vs_kernel(const ReqDesc* __restr
 #pragma unroll
         for (int s = 0; s < SP; ++s) p[s] *= B[s];
     }
-    if (!(U.sg.flags & 1)) {
+    if (!U.root) {
         // rescale, unless both children are tips given by codes (a product of
         // two table entries needs none, and folded nodes rely on exponent 0)
         int e = 0;
@@ -362,10 +468,14 @@ __global__ __launch_bounds__(kVL * R) void post_vs_kernel(const ReqDesc* __restr
 #pragma unroll
             for (int s = 0; s < SP; ++s) p[s] = exact_ldexp(p[s], -e);
         }
-        vs_store<T, SP>(g(static_cast<T*>(d.part)) +
+        vs_store_k<T, SP, kQ>(g(static_cast<T*>(d.part)) +
                             ((static_cast<size_t>(U.k - N) * d.tiles + tile) * R + r) * SP * kVL,
                         lane, p);
-        if (r == 0) g(d.expo)[static_cast<size_t>(U.k - N) * Cpad + c] = e + ec;
+        if constexpr (kQ) {
+            if (r == 0) vs_set_expo<true>(d, U.k, tile, lane, e + ec);
+        } else {
+            if (r == 0) g(d.expo)[static_cast<size_t>(U.k - N) * Cpad + c] = e + ec;
+        }
     } else {
         // root: site likelihood sum_r w_r pi . p_r, categories summed in a fixed order
         double acc = 0.0;
@@ -385,6 +495,17 @@ __global__ __launch_bounds__(kVL * R) void post_vs_kernel(const ReqDesc* __restr
             if (lane == 0) g(d.lpart)[tile] = tsum;
         }
     }
+    if constexpr (kQ) vs_done(arg, U, false, target);
+}
+
+template <typename T, int SP, int R>
+__global__ __launch_bounds__(kVL * R) void post_vs_kernel(const ReqDesc* __restrict__ descs, const SegTable segs) {
+    post_vs_body<T, SP, R, false>(descs, segs);
+}
+// The same over a work-queue launch's items.
+template <typename T, int SP, int R>
+__global__ __launch_bounds__(kVL * R) void post_vs_queue_kernel(const ReqDesc* __restrict__ descs, const QueueArgs q) {
+    post_vs_body<T, SP, R, true>(descs, q);
 }
 
 // ---------------------------------------------------------------- pre-order + gradient
@@ -395,15 +516,15 @@ __global__ __launch_bounds__(kVL * R) void post_vs_kernel(const ReqDesc* __restr
 // their partials; the per-pattern gradient of branch i is
 // sum_r w_r u_i . dm_i over sum_r w_r u_i . m_i (likewise j).  Child i is
 // taken row by row, so at most four vectors per lane are live.
-template <typename T, int SP, int R>
-__global__ __launch_bounds__(kVL * R) void pre_vs_kernel(const ReqDesc* __restrict__ descs, const SegTable segs) {
+template <typename T, int SP, int R, bool kQ, typename Arg>
+__device__ __forceinline__ void pre_vs_body(const ReqDesc* __restrict__ descs, const Arg& arg) {
     __shared__ __align__(16) T tab[R][4][SP * SP];   // P_i, dP_i, P_j, dP_j of each category
     __shared__ T xch[5][R][kVL];
     __shared__ T xg[6][R][kVL];                      // folded children's gradient sums
     const int r = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & (kVL - 1);
     VsUnit U;
-    if (!vs_unit(descs, segs, U)) return;
+    if (!vs_unit(descs, arg, U)) return;
     const ReqDesc& d = *U.d;
     const int N = d.N, S = d.S, Cpad = d.Cpad, tile = U.tile, tiles = d.tiles;
     const int c = tile * kVL + lane;
@@ -433,12 +554,17 @@ __global__ __launch_bounds__(kVL * R) void pre_vs_kernel(const ReqDesc* __restri
             db.store(tab[r][3], lane);
         }
     }
+    uint32_t target = 0;
+    if constexpr (kQ) {
+        target = queue::epoch(arg);
+        vs_wait_pre(arg, U, r, lane, target);
+    }
     T q[SP];
     if (U.k == 2 * N - 2) {
 #pragma unroll
         for (int s = 0; s < SP; ++s) q[s] = s < S ? static_cast<T>(g(d.pi)[s]) : T(0);
     } else {
-        vs_load<T, SP>(part + ((static_cast<size_t>(U.k - N) * tiles + tile) * R + r) * per, lane, q);
+        vs_load_k<T, SP, kQ>(part + ((static_cast<size_t>(U.k - N) * tiles + tile) * R + r) * per, lane, q);
     }
     __syncthreads();
     // child j: u_i = q o m_j and dm_j
@@ -546,7 +672,7 @@ __global__ __launch_bounds__(kVL * R) void pre_vs_kernel(const ReqDesc* __restri
             xg[1][r][lane] = wr * nb;
             xg[2][r][lane] = wr * dn;
         } else {
-            vs_store<T, SP>(part + ((static_cast<size_t>(U.i - N) * tiles + tile) * R + r) * per, lane, qi);
+            vs_store_k<T, SP, kQ>(part + ((static_cast<size_t>(U.i - N) * tiles + tile) * R + r) * per, lane, qi);
         }
     }
     if (in_j) {
@@ -560,7 +686,7 @@ __global__ __launch_bounds__(kVL * R) void pre_vs_kernel(const ReqDesc* __restri
             xg[4][r][lane] = wr * nb;
             xg[5][r][lane] = wr * dn;
         } else {
-            vs_store<T, SP>(part + ((static_cast<size_t>(U.j - N) * tiles + tile) * R + r) * per, lane, qj);
+            vs_store_k<T, SP, kQ>(part + ((static_cast<size_t>(U.j - N) * tiles + tile) * R + r) * per, lane, qj);
         }
     }
     if (U.fi || U.fj) __syncthreads();
@@ -570,6 +696,17 @@ __global__ __launch_bounds__(kVL * R) void pre_vs_kernel(const ReqDesc* __restri
         if (U.fi) write_grad<T, R>(d, xg[0], xg[1], xg[2], lane, c, tile, kk[2 * (U.i - N)], kk[2 * (U.i - N) + 1]);
         if (U.fj) write_grad<T, R>(d, xg[3], xg[4], xg[5], lane, c, tile, kk[2 * (U.j - N)], kk[2 * (U.j - N) + 1]);
     }
+    if constexpr (kQ) vs_done(arg, U, true, target);
+}
+
+template <typename T, int SP, int R>
+__global__ __launch_bounds__(kVL * R) void pre_vs_kernel(const ReqDesc* __restrict__ descs, const SegTable segs) {
+    pre_vs_body<T, SP, R, false>(descs, segs);
+}
+// The same over a work-queue launch's items.
+template <typename T, int SP, int R>
+__global__ __launch_bounds__(kVL * R) void pre_vs_queue_kernel(const ReqDesc* __restrict__ descs, const QueueArgs q) {
+    pre_vs_body<T, SP, R, true>(descs, q);
 }
 
 // ---------------------------------------------------------------- FP32, 20 states: matrices in registers
@@ -691,8 +828,8 @@ __device__ __forceinline__ void static_for(F&& f) {
 }
 
 // Post-order, FP32, 17..20 states (as post_vs_kernel, products on registers).
-template <int R>
-__global__ __launch_bounds__(kVL * R) void post_vd_kernel(const ReqDesc* __restrict__ descs, const SegTable segs) {
+template <int R, bool kQ, typename Arg>
+__device__ __forceinline__ void post_vd_body(const ReqDesc* __restrict__ descs, const Arg& arg) {
     constexpr int SP = 20;
     using T = float;
     __shared__ __align__(16) T tab[R][2][SP * SP];   // P_i, P_j of each category
@@ -701,7 +838,7 @@ __global__ __launch_bounds__(kVL * R) void post_vd_kernel(const ReqDesc* __restr
     const int r = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & (kVL - 1);
     VsUnit U;
-    if (!vs_unit(descs, segs, U)) return;
+    if (!vs_unit(descs, arg, U)) return;
     const ReqDesc& d = *U.d;
     const int N = d.N, S = d.S, Cpad = d.Cpad, tile = U.tile;
     const int c = tile * kVL + lane;
@@ -715,14 +852,24 @@ __global__ __launch_bounds__(kVL * R) void post_vd_kernel(const ReqDesc* __restr
         if (src_i) si.store(tab[r][0], lane);
         if (src_j) sj.store(tab[r][1], lane);
     }
+    uint32_t target = 0;
+    if constexpr (kQ) {
+        target = queue::epoch(arg);
+        vs_wait_post(arg, U, r, lane, target);
+    }
     int ec = 0;
-    if (U.i >= N && !U.fi) ec += g(d.expo)[static_cast<size_t>(U.i - N) * Cpad + c];
-    if (U.j >= N && !U.fj) ec += g(d.expo)[static_cast<size_t>(U.j - N) * Cpad + c];
+    if constexpr (kQ) {
+        if (U.i >= N && !U.fi) ec += vs_expo<true>(d, U.i, tile, lane);
+        if (U.j >= N && !U.fj) ec += vs_expo<true>(d, U.j, tile, lane);
+    } else {
+        if (U.i >= N && !U.fi) ec += g(d.expo)[static_cast<size_t>(U.i - N) * Cpad + c];
+        if (U.j >= N && !U.fj) ec += g(d.expo)[static_cast<size_t>(U.j - N) * Cpad + c];
+    }
     __syncthreads();
     T p[SP];
     if (src_i) {   // p = P_i p_i
         T v[SP];
-        vs_input<T, SP>(d, U.fi, src_i, U.i, r, c, lane, v);
+        vs_input<T, SP, kQ>(d, U.fi, src_i, U.i, r, c, lane, v);
         MatReg20 M;
         M.load(tab[r][0], lane);
         static_for<SP>([&](auto s) { p[s] = dpp_row<s>(M, v); });
@@ -734,7 +881,7 @@ __global__ __launch_bounds__(kVL * R) void post_vd_kernel(const ReqDesc* __restr
     }
     if (src_j) {   // p *= P_j p_j
         T v[SP];
-        vs_input<T, SP>(d, U.fj, src_j, U.j, r, c, lane, v);
+        vs_input<T, SP, kQ>(d, U.fj, src_j, U.j, r, c, lane, v);
         MatReg20 M;
         M.load(tab[r][1], lane);
         static_for<SP>([&](auto s) { p[s] *= dpp_row<s>(M, v); });
@@ -744,7 +891,7 @@ __global__ __launch_bounds__(kVL * R) void post_vd_kernel(const ReqDesc* __restr
 #pragma unroll
         for (int s = 0; s < SP; ++s) p[s] *= B[s];
     }
-    if (!(U.sg.flags & 1)) {
+    if (!U.root) {
         int e = 0;
         if (src_i || src_j) {
             T lmx = T(0);
@@ -759,10 +906,14 @@ __global__ __launch_bounds__(kVL * R) void post_vd_kernel(const ReqDesc* __restr
 #pragma unroll
             for (int s = 0; s < SP; ++s) p[s] = exact_ldexp(p[s], -e);
         }
-        vs_store<T, SP>(g(static_cast<T*>(d.part)) +
+        vs_store_k<T, SP, kQ>(g(static_cast<T*>(d.part)) +
                             ((static_cast<size_t>(U.k - N) * d.tiles + tile) * R + r) * SP * kVL,
                         lane, p);
-        if (r == 0) g(d.expo)[static_cast<size_t>(U.k - N) * Cpad + c] = e + ec;
+        if constexpr (kQ) {
+            if (r == 0) vs_set_expo<true>(d, U.k, tile, lane, e + ec);
+        } else {
+            if (r == 0) g(d.expo)[static_cast<size_t>(U.k - N) * Cpad + c] = e + ec;
+        }
     } else {
         double acc = 0.0;
 #pragma unroll
@@ -781,15 +932,25 @@ __global__ __launch_bounds__(kVL * R) void post_vd_kernel(const ReqDesc* __restr
             if (lane == 0) g(d.lpart)[tile] = tsum;
         }
     }
+    if constexpr (kQ) vs_done(arg, U, false, target);
+}
+
+template <int R>
+__global__ __launch_bounds__(kVL * R) void post_vd_kernel(const ReqDesc* __restrict__ descs, const SegTable segs) {
+    post_vd_body<R, false>(descs, segs);
+}
+// The same over a work-queue launch's items.
+template <int R>
+__global__ __launch_bounds__(kVL * R) void post_vd_queue_kernel(const ReqDesc* __restrict__ descs, const QueueArgs q) {
+    post_vd_body<R, true>(descs, q);
 }
 
 // Pre-order and gradient, FP32, 17..20 states (as pre_vs_kernel, products on
 // registers, one matrix at a time: each child's P and dP products run as
 // two passes, and P^T u accumulates the rows of the forward table).  Every
 // sum keeps its order, so results are those of pre_vs_kernel bit for bit.
-template <int R>
-__global__ __launch_bounds__(kVL * R) __attribute__((amdgpu_waves_per_eu(4)))
-void pre_vd_kernel(const ReqDesc* __restrict__ descs, const SegTable segs) {
+template <int R, bool kQ, typename Arg>
+__device__ __forceinline__ void pre_vd_body(const ReqDesc* __restrict__ descs, const Arg& arg) {
     constexpr int SP = 20;
     using T = float;
     __shared__ __align__(16) T tab[R][4][SP * SP];   // P_i, dP_i, P_j, dP_j of each category
@@ -798,7 +959,7 @@ void pre_vd_kernel(const ReqDesc* __restrict__ descs, const SegTable segs) {
     const int r = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & (kVL - 1);
     VsUnit U;
-    if (!vs_unit(descs, segs, U)) return;
+    if (!vs_unit(descs, arg, U)) return;
     const ReqDesc& d = *U.d;
     const int N = d.N, S = d.S, Cpad = d.Cpad, tile = U.tile, tiles = d.tiles;
     const int c = tile * kVL + lane;
@@ -828,12 +989,17 @@ void pre_vd_kernel(const ReqDesc* __restrict__ descs, const SegTable segs) {
             db.store(tab[r][3], lane);
         }
     }
+    uint32_t target = 0;
+    if constexpr (kQ) {
+        target = queue::epoch(arg);
+        vs_wait_pre(arg, U, r, lane, target);
+    }
     T q[SP];
     if (U.k == 2 * N - 2) {
 #pragma unroll
         for (int s = 0; s < SP; ++s) q[s] = s < S ? static_cast<T>(g(d.pi)[s]) : T(0);
     } else {
-        vs_load<T, SP>(part + ((static_cast<size_t>(U.k - N) * tiles + tile) * R + r) * per, lane, q);
+        vs_load_k<T, SP, kQ>(part + ((static_cast<size_t>(U.k - N) * tiles + tile) * R + r) * per, lane, q);
     }
     __syncthreads();
     // child j: u_i = q o m_j, then dm_j
@@ -943,7 +1109,7 @@ void pre_vd_kernel(const ReqDesc* __restrict__ descs, const SegTable segs) {
             xg[1][r][lane] = wr * nb;
             xg[2][r][lane] = wr * dn;
         } else {
-            vs_store<T, SP>(part + ((static_cast<size_t>(U.i - N) * tiles + tile) * R + r) * per, lane, qi);
+            vs_store_k<T, SP, kQ>(part + ((static_cast<size_t>(U.i - N) * tiles + tile) * R + r) * per, lane, qi);
         }
     }
     if (in_j) {
@@ -957,7 +1123,7 @@ void pre_vd_kernel(const ReqDesc* __restrict__ descs, const SegTable segs) {
             xg[4][r][lane] = wr * nb;
             xg[5][r][lane] = wr * dn;
         } else {
-            vs_store<T, SP>(part + ((static_cast<size_t>(U.j - N) * tiles + tile) * R + r) * per, lane, qj);
+            vs_store_k<T, SP, kQ>(part + ((static_cast<size_t>(U.j - N) * tiles + tile) * R + r) * per, lane, qj);
         }
     }
     if (U.fi || U.fj) __syncthreads();
@@ -967,6 +1133,19 @@ void pre_vd_kernel(const ReqDesc* __restrict__ descs, const SegTable segs) {
         if (U.fi) write_grad<T, R>(d, xg[0], xg[1], xg[2], lane, c, tile, kk[2 * (U.i - N)], kk[2 * (U.i - N) + 1]);
         if (U.fj) write_grad<T, R>(d, xg[3], xg[4], xg[5], lane, c, tile, kk[2 * (U.j - N)], kk[2 * (U.j - N) + 1]);
     }
+    if constexpr (kQ) vs_done(arg, U, true, target);
+}
+
+template <int R>
+__global__ __launch_bounds__(kVL * R) __attribute__((amdgpu_waves_per_eu(4)))
+void pre_vd_kernel(const ReqDesc* __restrict__ descs, const SegTable segs) {
+    pre_vd_body<R, false>(descs, segs);
+}
+// The same over a work-queue launch's items.
+template <int R>
+__global__ __launch_bounds__(kVL * R) __attribute__((amdgpu_waves_per_eu(4)))
+void pre_vd_queue_kernel(const ReqDesc* __restrict__ descs, const QueueArgs q) {
+    pre_vd_body<R, true>(descs, q);
 }
 
 // ---------------------------------------------------------------- P(t) tables
@@ -979,6 +1158,9 @@ __global__ __launch_bounds__(256) void pmat_vs_kernel(const ReqDesc* __restrict_
     __shared__ double ex[SP], dex[SP];
     __shared__ double sV[SP * SP], sVi[SP * SP];     // V and V^-1 (S x S used), read once from memory
     const int unit = blockIdx.x;
+    // a new evaluation of a work-queue context
+    if (unit == 0 && threadIdx.x == 0 && descs[segs.seg[0].desc].qctr)
+        queue::new_evaluation(descs[segs.seg[0].desc].qctr);
     if (unit >= segs.unit_begin[segs.n]) return;
     const int sidx = seg_index(segs, unit);
     const Segment& sg = segs.seg[sidx];
@@ -1071,6 +1253,43 @@ hipError_t launch_vs_sp(KernelClass k, int R, const ReqDesc* descs, const SegTab
     return hipErrorInvalidValue;
 }
 
+// Work-queue launches: post-order (pass 1) or pre-order (pass 2) items
+// [q.t0, q.t1), one workgroup each.
+template <typename T, int SP>
+hipError_t launch_vs_queue_sp(int pass, int R, const ReqDesc* descs, const QueueArgs& q, hipStream_t st) {
+    const dim3 grid(q.t1 - q.t0);
+#define PHG_VSQ_CASE(RV)                                                                                   \
+    if constexpr (vs_lds_bytes(SP, RV, sizeof(T)) <= kVsLdsMax)                                            \
+    if (R == RV) {                                                                                         \
+        if constexpr (sizeof(T) == 4 && SP == 20) {                                                        \
+            if (pass == 1)                                                                                 \
+                hipLaunchKernelGGL((post_vd_queue_kernel<RV>), grid, dim3(kVL * RV), 0, st, descs, q);    \
+            else                                                                                           \
+                hipLaunchKernelGGL((pre_vd_queue_kernel<RV>), grid, dim3(kVL * RV), 0, st, descs, q);     \
+        } else {                                                                                           \
+            if (pass == 1)                                                                                 \
+                hipLaunchKernelGGL((post_vs_queue_kernel<T, SP, RV>), grid, dim3(kVL * RV), 0, st, descs, q); \
+            else                                                                                           \
+                hipLaunchKernelGGL((pre_vs_queue_kernel<T, SP, RV>), grid, dim3(kVL * RV), 0, st, descs, q);  \
+        }                                                                                                  \
+        return hipGetLastError();                                                                          \
+    }
+    PHG_VSQ_CASE(1)
+    PHG_VSQ_CASE(2)
+    PHG_VSQ_CASE(4)
+    PHG_VSQ_CASE(8)
+#undef PHG_VSQ_CASE
+    return hipErrorInvalidValue;
+}
+
+template <typename T>
+hipError_t launch_vs_queue_t(int pass, int S, int R, const ReqDesc* descs, const QueueArgs& q, hipStream_t st) {
+    if (vs_padded_states(S) == 20) return launch_vs_queue_sp<T, 20>(pass, R, descs, q, st);
+    if (vs_padded_states(S) == 24) return launch_vs_queue_sp<T, 24>(pass, R, descs, q, st);
+    if constexpr (sizeof(T) == 4) return launch_vs_queue_sp<T, 32>(pass, R, descs, q, st);
+    return hipErrorInvalidValue;
+}
+
 template <typename T>
 hipError_t launch_vs_t(KernelClass k, int S, int R, const ReqDesc* descs, const SegTable& t, hipStream_t st) {
     if (vs_padded_states(S) == 20) return launch_vs_sp<T, 20>(k, R, descs, t, st);
@@ -1086,6 +1305,14 @@ hipError_t launch_vs(KernelClass k, const ReqDesc& shape, const ReqDesc* descs, 
     if (t.n <= 0 || t.unit_begin[t.n] <= 0) return hipSuccess;
     if (shape.fp32) return launch_vs_t<float>(k, shape.S, shape.R, descs, t, st);
     return launch_vs_t<double>(k, shape.S, shape.R, descs, t, st);
+}
+
+hipError_t launch_vs_queue(const ReqDesc& shape, const ReqDesc* descs, const QueueArgs& q, int pass,
+                           hipStream_t st) {
+    if (q.t1 <= q.t0) return hipSuccess;
+    if (pass != 1 && pass != 2) return hipErrorInvalidValue;
+    if (shape.fp32) return launch_vs_queue_t<float>(pass, shape.S, shape.R, descs, q, st);
+    return launch_vs_queue_t<double>(pass, shape.S, shape.R, descs, q, st);
 }
 
 }  // namespace phg

@@ -226,13 +226,25 @@ def test_queue_schedule_is_opt_in_and_checked():
         assert e.value.status == B.PHG_ERR_ARG
     finally:
         B.phg_destroy(ctx)
-    # FP32, 4 states and R in {1, 2, 4, 8} only
-    for S, R, prec in ((4, 4, B.PHG_FP64), (4, 3, B.PHG_FP32_SCALED), (20, 4, B.PHG_FP32_SCALED)):
+    # 4 states: FP32 and R in {1, 2, 4, 8}; else the vector-ALU kernels' shapes
+    for S, R, prec in ((4, 4, B.PHG_FP64), (4, 3, B.PHG_FP32_SCALED), (20, 3, B.PHG_FP32_SCALED),
+                       (61, 4, B.PHG_FP32_SCALED), (32, 4, B.PHG_FP64)):
         ctx = B.phg_create(30, 10, S, R, prec, 0)
         try:
             with pytest.raises(B.PhgError) as e:
                 B.phg_set_schedule(ctx, B.PHG_SCHEDULE_QUEUE)
             assert e.value.status == B.PHG_ERR_ARG
+        finally:
+            B.phg_destroy(ctx)
+    for S, prec in ((20, B.PHG_FP32_SCALED), (32, B.PHG_FP32_SCALED), (20, B.PHG_FP64)):
+        ctx = B.phg_create(30, 10, S, 4, prec, 0)
+        try:
+            B.phg_set_topology(ctx, synth.yule_topology(30, np.random.default_rng(5)))
+            B.phg_set_schedule(ctx, B.PHG_SCHEDULE_QUEUE)
+            assert B.phg_get_schedule(ctx) == B.PHG_SCHEDULE_QUEUE
+            # per-chunk P(t) tables (a table budget below one table per branch): levels
+            B.phg_set_table_budget(ctx, 1 << 16)
+            assert B.phg_get_schedule(ctx) == B.PHG_SCHEDULE_LEVELS
         finally:
             B.phg_destroy(ctx)
     # launches per evaluation: 1 or 2, 4-state FP32 only

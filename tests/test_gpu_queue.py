@@ -1,12 +1,14 @@
-"""The work-queue traversal (PHG_SCHEDULE_QUEUE) through the C ABI.
+"""The work-queue traversals (PHG_SCHEDULE_QUEUE) through the C ABI.
 
-It runs the blocked schedule's arithmetic in one launch per pass (or one for
-both), items waiting on per-(block, tile) completion marks instead of level
-launches, so its results must equal the level-launched blocked schedule's
-bit for bit -- which the oracle parity tests hold to the FP32 bar -- on every
-tree shape, category count, both launch modes, repeated evaluations (the
-marks' epochs), library-owned graph replays and the log-likelihood-only
-path.  One case is also checked against the oracle directly.
+4 states (FP32): the blocked schedule's arithmetic in one launch per pass
+(or one for both), items waiting on per-(block, tile) completion marks
+instead of level launches.  17..32 states on the vector-ALU kernels (FP32,
+and FP64 to 24 states): the level schedule's records as items, one launch
+per pass.  Results must equal the level-launched schedule's bit for bit --
+which the oracle parity tests hold to their bars -- on every tree shape,
+category count, launch mode, repeated evaluations (the marks' epochs),
+library-owned graph replays and the log-likelihood-only path.  Some cases
+are also checked against the oracle directly.
 """
 import numpy as np
 import pytest
@@ -21,12 +23,12 @@ pytestmark = pytest.mark.gpu
 F32 = B.PHG_FP32_SCALED
 
 
-def _run(prob, schedule, launches=0, graphs=True, repeats=2):
+def _run(prob, schedule, launches=0, graphs=True, repeats=2, prec=F32):
     """(logL, gradient) of `repeats` synchronous evaluations and a
     log-likelihood-only one."""
     B.phg_set_tuning(4, 0, F32, B.PHG_TUNE_QUEUE_LAUNCHES, launches)
     try:
-        with B.Context.for_problem(prob, F32, schedule=schedule) as ctx:
+        with B.Context.for_problem(prob, prec, schedule=schedule) as ctx:
             B.phg_set_fp32_guard(ctx.handle, 0.0)
             B.phg_set_graphs(ctx.handle, graphs)
             got = B.phg_get_schedule(ctx.handle)
@@ -38,12 +40,15 @@ def _run(prob, schedule, launches=0, graphs=True, repeats=2):
     return outs, ll_only
 
 
-def _same(name, prob):
-    print(f"[case] queue {name} N={prob.n_tips} C={prob.n_patterns} R={prob.n_categories}", flush=True)
-    (ref, *_), ref_ll = _run(prob, B.PHG_SCHEDULE_BLOCKS, repeats=1)
-    for launches in (1, 2):
+def _same(name, prob, prec=F32):
+    print(f"[case] queue {name} N={prob.n_tips} C={prob.n_patterns} S={prob.n_states} R={prob.n_categories} "
+          f"{'fp32' if prec == F32 else 'fp64'}", flush=True)
+    four = prob.n_states == 4
+    ref_sched = B.PHG_SCHEDULE_BLOCKS if four else B.PHG_SCHEDULE_LEVELS
+    (ref, *_), ref_ll = _run(prob, ref_sched, repeats=1, prec=prec)
+    for launches in ((1, 2) if four else (0,)):
         for graphs in (True, False):
-            outs, ll_only = _run(prob, B.PHG_SCHEDULE_QUEUE, launches, graphs)
+            outs, ll_only = _run(prob, B.PHG_SCHEDULE_QUEUE, launches, graphs, prec=prec)
             for logl, grad in outs:
                 assert logl == ref[0], (name, launches, graphs, logl, ref[0])
                 assert np.array_equal(grad, ref[1]), (name, launches, graphs)
@@ -51,15 +56,20 @@ def _same(name, prob):
     return ref
 
 
-def _problem(N, C, R, seed, caterpillar=False, mean_b=0.05):
+def _problem(N, C, R, seed, caterpillar=False, mean_b=0.05, S=4):
     rng = np.random.default_rng(seed)
     parent = synth.caterpillar_topology(N) if caterpillar else synth.yule_topology(N, rng)
     b = rng.exponential(mean_b, 2 * N - 2)
-    pi = rng.dirichlet([5.0] * 4)
+    pi = rng.dirichlet([5.0] * S)
+    if S == 4:
+        Q = synth.hky_model(3.0, pi)
+    else:
+        ex = np.triu(rng.gamma(1.0, 1.0, (S, S)), 1)
+        Q = synth.reversible_q(ex + ex.T, pi)
     rates, w = synth.discrete_gamma(0.6, R)
     if R > 1:
         w = rng.dirichlet([3.0] * R)
-    return synth.make_problem(parent, b, synth.hky_model(3.0, pi), pi, rates, w, C, rng,
+    return synth.make_problem(parent, b, Q, pi, rates, w, C, rng,
                               pattern_weights=1.0 + rng.poisson(2.0, C), ambiguous_fraction=0.05)
 
 
@@ -96,3 +106,40 @@ def test_queue_branch_updates_between_evaluations():
             lq, gq = q.gradient()
             lb, gb = b.gradient()
             assert lq == lb and np.array_equal(gq, gb)
+
+
+# vector-ALU kernels: 17..20 states FP32 (DPP kernels), 24 and 32 states
+# FP32, 20 and 24 states FP64; tip-tip nodes are folded on these shapes
+@pytest.mark.parametrize("N,C,S,R,prec,seed", [(2, 70, 20, 4, F32, 21), (9, 64, 20, 4, F32, 22),
+                                               (60, 130, 20, 1, F32, 23), (60, 130, 20, 8, F32, 24),
+                                               (120, 65, 17, 4, F32, 25), (80, 100, 24, 2, F32, 26),
+                                               (50, 70, 32, 4, F32, 27), (60, 130, 20, 4, B.PHG_FP64, 28),
+                                               (40, 70, 24, 2, B.PHG_FP64, 29)])
+def test_queue_vector_alu_equals_levels(N, C, S, R, prec, seed):
+    _same(f"valu-N{N}-C{C}", _problem(N, C, R, seed, S=S, mean_b=0.1), prec)
+
+
+def test_queue_vector_alu_caterpillar():
+    # 149 post-order and pre-order levels of one node each
+    _same("valu-caterpillar150", _problem(150, 70, 4, 30, caterpillar=True, mean_b=0.05, S=20))
+
+
+def test_queue_vector_alu_against_oracle():
+    prob = _problem(90, 200, 4, 32, S=20, mean_b=0.1)
+    ref = _same("valu-N90-C200", prob)
+    check("queue/valu-N90-C200", ref[0], ref[1], oracle.evaluate_problem(prob), 1e-6, 1e-4)
+
+
+def test_queue_vector_alu_tip_vectors():
+    # general tip vectors are inputs the items read as they are (no marks)
+    prob = _problem(40, 70, 4, 31, S=20, mean_b=0.1)
+    rng = np.random.default_rng(31)
+    vec = rng.uniform(0.0, 1.0, (prob.n_patterns, 20))
+    outs = []
+    for schedule in (B.PHG_SCHEDULE_LEVELS, B.PHG_SCHEDULE_QUEUE):
+        with B.Context.for_problem(prob, F32, schedule=schedule) as ctx:
+            B.phg_set_fp32_guard(ctx.handle, 0.0)
+            B.phg_set_tip_partials(ctx.handle, 3, vec)
+            assert B.phg_get_schedule(ctx.handle) == schedule
+            outs.append(ctx.gradient())
+    assert outs[0][0] == outs[1][0] and np.array_equal(outs[0][1], outs[1][1])
