@@ -376,8 +376,14 @@ def state_space_measurement(args, B, synth, stream, out):
                 continue
             family = kernel_family(B, S, R, tag == "f32")
             exe_f = executed_flops(prob.parent, N, C, R, S, family)
+            # the vector-ALU kernels run their work-queue traversal (one launch
+            # per pass) unless --state-schedule levels
+            sched = (B.PHG_SCHEDULE_QUEUE if family == "valu" and args.state_schedule == "queue"
+                     else B.PHG_SCHEDULE_AUTO)
             h = B.phg_create(N, C, S, R, prec, 0)
             try:
+                if sched != B.PHG_SCHEDULE_AUTO:
+                    B.phg_set_schedule(h, sched)
                 B.phg_bind_stream(h, stream.cuda_stream)
                 B.set_problem(h, prob)
                 B.phg_prepare(h)
@@ -393,6 +399,8 @@ def state_space_measurement(args, B, synth, stream, out):
                 dt = (time.perf_counter() - t0) / k
                 ms_cls, n_prof, _ = B.phg_profile_read(h)
                 slots = B.phg_table_slots(h)
+                sched_name = {B.PHG_SCHEDULE_LEVELS: "levels", B.PHG_SCHEDULE_BLOCKS: "blocks",
+                              B.PHG_SCHEDULE_QUEUE: "queue"}[B.phg_get_schedule(h)]
                 ws = B.phg_workspace_size(N, C, S, R, prec)
             finally:
                 B.phg_destroy(h)
@@ -402,7 +410,7 @@ def state_space_measurement(args, B, synth, stream, out):
             peak = (VALU_PEAK_TFLOPS if family == "valu" else MFMA_PEAK_TFLOPS)[tag]
             entry = {
                 "n_tips": N, "n_patterns": C, "n_states": S, "n_categories": R,
-                "kernels": family,
+                "kernels": family, "schedule": sched_name,
                 "evals_per_s": round(1.0 / dt, 1), "ms_per_eval": round(dt * 1e3, 4),
                 "ms_per_class": {k2: round(v, 4) for k2, v in cls.items()},
                 "algorithmic_gflop_per_eval": round(alg_f / 1e9, 2),
@@ -416,7 +424,7 @@ def state_space_measurement(args, B, synth, stream, out):
             if family == "valu" and tag == "f32":
                 entry["frac_unpacked_valu"] = round(tflops / VALU_UNPACKED_TFLOPS, 4)
             if ref is not None:
-                with B.Context.for_problem(sample, prec) as ctx:
+                with B.Context.for_problem(sample, prec, schedule=sched) as ctx:
                     logl, grad = ctx.gradient()
                 entry["accuracy_vs_oracle"] = accuracy(logl, grad, ref, sample.n_patterns)
             res[f"{name}_{tag}"] = entry
@@ -567,6 +575,8 @@ def main():
     ap.add_argument("--states", default="aa500,codon128,s122,s240,s256big",
                     help="state-space workloads to measure (comma-separated)")
     ap.add_argument("--state-precisions", default="f32,f64")
+    ap.add_argument("--state-schedule", choices=("queue", "levels"), default="queue",
+                    help="schedule of the vector-ALU (17..32-state) entries")
     ap.add_argument("--only-states", action="store_true",
                     help="measure the state-space workloads only (for profiler runs)")
     ap.add_argument("--state-sample-patterns", type=int, default=200,
