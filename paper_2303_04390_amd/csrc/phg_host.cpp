@@ -396,9 +396,11 @@ void build_schedule(phg_context* ctx) {
         for (int v : bd[d]) put(v);
         ctx->pre_lv.emplace_back(a, static_cast<int>(ctx->sched.size() / 4) - a);
     }
-    // work-queue traversal of the vector-ALU kernels (tables for every branch)
+    // work-queue traversal of the vector-ALU and MFMA kernels (tables for
+    // every branch)
     const int n_rec = static_cast<int>(ctx->sched.size() / 4);
-    ctx->queue = ctx->sched_mode == PHG_SCHEDULE_QUEUE && phg::uses_vs_kernels(ctx->S, ctx->R, fp32) &&
+    ctx->queue = ctx->sched_mode == PHG_SCHEDULE_QUEUE && ctx->S != 4 &&
+                 phg::queue_supported(ctx->S, ctx->R, fp32) &&
                  table_slots_for(N, ctx->S, ctx->R, ctx->prec, ctx->table_budget) == 0 &&
                  static_cast<int64_t>(n_rec) * ctx->tiles * phg::kLanes * ctx->R < (int64_t{1} << 31);
     if (!ctx->queue) return;
@@ -410,16 +412,22 @@ void build_schedule(phg_context* ctx) {
             if (k != root) ctx->qdep[2 * r] = ctx->parent[k] - N;
         }
     // items: post-order levels deepest first, then pre-order levels from the
-    // root's; tile-major within a level
+    // root's; within a level tile-major for the vector-ALU kernels (small
+    // tables), record-major for the MFMA kernels (a record's large P(t)
+    // tables then stay in L2 for its tiles, as in the level launches)
+    const bool by_record = phg::uses_gl_kernels(ctx->S, ctx->R, fp32);
     ctx->qitems.clear();
     ctx->qitems.reserve(static_cast<size_t>(2) * n_rec * ctx->tiles);
     for (int pass = 0; pass < 2; ++pass) {
-        for (const auto& lv : pass == 0 ? ctx->post_lv : ctx->pre_lv)
-            for (int t = 0; t < ctx->tiles; ++t)
-                for (int r = lv.first; r < lv.first + lv.second; ++r) {
-                    ctx->qitems.push_back(r);
-                    ctx->qitems.push_back(t);
-                }
+        for (const auto& lv : pass == 0 ? ctx->post_lv : ctx->pre_lv) {
+            const int n_in = lv.second * ctx->tiles;
+            for (int x = 0; x < n_in; ++x) {
+                const int r = lv.first + (by_record ? x / ctx->tiles : x % lv.second);
+                const int t = by_record ? x % ctx->tiles : x / lv.second;
+                ctx->qitems.push_back(r);
+                ctx->qitems.push_back(t);
+            }
+        }
         if (pass == 0) ctx->q_post = static_cast<int>(ctx->qitems.size() / 2);
     }
     ctx->q_blocks = N - 1;

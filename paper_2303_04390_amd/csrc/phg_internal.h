@@ -267,9 +267,12 @@ inline bool folds_tip_pairs(int S, int R, bool fp32) {
 }
 inline bool folds_pre_order(int S, int R, bool fp32) { return uses_vs_kernels(S, R, fp32); }
 inline bool queue_supported(int S, int R, bool fp32) {
-    return (S == 4 && fp32 && R <= 8 && (R & (R - 1)) == 0) || uses_vs_kernels(S, R, fp32);
+    return (S == 4 && fp32 && R <= 8 && (R & (R - 1)) == 0) || uses_vs_kernels(S, R, fp32) ||
+           uses_gl_kernels(S, R, fp32);
 }
 hipError_t launch_vs_queue(const ReqDesc& shape, const ReqDesc* descs, const QueueArgs& q, int pass,
+                           hipStream_t stream);
+hipError_t launch_gl_queue(const ReqDesc& shape, const ReqDesc* descs, const QueueArgs& q, int pass,
                            hipStream_t stream);
 // Their operand order: a stored vector (one pattern's partial) or matrix row
 // holds state t at column gl_col(t) = (t mod 4) KBP + t / 4, so the states

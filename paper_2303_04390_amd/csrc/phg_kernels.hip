@@ -1896,7 +1896,11 @@ hipError_t launch_queue(const ReqDesc& shape, const ReqDesc* descs, const QueueA
                         hipStream_t st) {
     if (q.t1 <= q.t0) return hipSuccess;
     if (!queue_supported(shape.S, shape.R, shape.fp32 != 0) || passes < 1 || passes > 3) return hipErrorInvalidValue;
-    if (shape.S != 4) return passes == 3 ? hipErrorInvalidValue : launch_vs_queue(shape, descs, q, passes, st);
+    if (shape.S != 4) {
+        if (passes == 3) return hipErrorInvalidValue;
+        if (uses_vs_kernels(shape.S, shape.R, shape.fp32 != 0)) return launch_vs_queue(shape, descs, q, passes, st);
+        return launch_gl_queue(shape, descs, q, passes, st);
+    }
     switch (shape.R) {
         case 1: return queue_r<1>(descs, q, passes, st);
         case 2: return queue_r<2>(descs, q, passes, st);

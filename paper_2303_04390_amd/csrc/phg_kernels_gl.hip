@@ -36,6 +36,7 @@
 // products, so this equals storing normalised partials, without a second
 // pass over the outputs.
 #include "phg_internal.h"
+#include "phg_queue_device.h"
 
 #include <math.h>
 
@@ -195,7 +196,7 @@ __device__ __forceinline__ void lds_run(const T* p, T (&out)[G]) {
 // Copy a stored [TP][row] block (contiguous in HBM) into an LDS [TP][la]
 // buffer in 16-byte pieces.  All threads take part; each issues all of its
 // (at most KIT) loads before its first LDS write.  The caller synchronises.
-template <typename T, int TP, int KIT>
+template <typename T, int TP, int KIT, bool kCoh = false>
 __device__ __forceinline__ void stage_vec(T* buf, const GLOBAL T* __restrict__ src, const Geo& ge) {
     constexpr int E = 16 / static_cast<int>(sizeof(T));
     const int per_row = ge.row / E;
@@ -206,7 +207,11 @@ __device__ __forceinline__ void stage_vec(T* buf, const GLOBAL T* __restrict__ s
         const int t = static_cast<int>(threadIdx.x) + it * static_cast<int>(blockDim.x);
         if (t < n) {
             const int p = t / per_row, c = (t - p * per_row) * E;
-            v[it] = *reinterpret_cast<const GLOBAL VecG<T, E>*>(src + p * ge.row + c);
+            if constexpr (kCoh)   // device-coherent (work-queue launches): piece t of the [TP][row] block
+                v[it] = queue::ld(reinterpret_cast<const GLOBAL VecG<T, E>*>(src), static_cast<uint32_t>(t),
+                                  static_cast<uint32_t>(n));
+            else
+                v[it] = *reinterpret_cast<const GLOBAL VecG<T, E>*>(src + p * ge.row + c);
         }
     }
 #pragma unroll
@@ -390,7 +395,7 @@ __device__ __forceinline__ void bwd(const GLOBAL T* __restrict__ MB, const T* U,
 
 // A stored [TP][row] block in HBM -> this wave's columns, and back (states
 // past S are zeros; states past the row do not exist).
-template <typename T, int RB, int NBW>
+template <typename T, int RB, int NBW, bool kCoh = false>
 __device__ __forceinline__ void load_cols(const GLOBAL T* __restrict__ base, const Geo& ge, int cb0, int lane,
                                           Cols<T, RB, NBW>& x) {
     const int gq = lane >> 4, n = lane & 15;
@@ -401,10 +406,16 @@ __device__ __forceinline__ void load_cols(const GLOBAL T* __restrict__ base, con
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
-            for (int i = 0; i < 4; ++i) x.v[rb][cb][i] = s < ge.row ? base[opat<T>(rb, gq, i) * ge.row + col] : T(0);
+            for (int i = 0; i < 4; ++i) {
+                const int ix = opat<T>(rb, gq, i) * ge.row + col;
+                if constexpr (kCoh)   // device-coherent (work-queue launches)
+                    x.v[rb][cb][i] = s < ge.row ? queue::ld(base, ix, 16 * RB * ge.row) : T(0);
+                else
+                    x.v[rb][cb][i] = s < ge.row ? base[ix] : T(0);
+            }
     }
 }
-template <typename T, int RB, int NBW>
+template <typename T, int RB, int NBW, bool kCoh = false>
 __device__ __forceinline__ void store_cols(GLOBAL T* __restrict__ base, const Geo& ge, int cb0, int lane,
                                            const Cols<T, RB, NBW>& x) {
     const int gq = lane >> 4, n = lane & 15;
@@ -416,7 +427,13 @@ __device__ __forceinline__ void store_cols(GLOBAL T* __restrict__ base, const Ge
 #pragma unroll
             for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
-                for (int i = 0; i < 4; ++i) base[opat<T>(rb, gq, i) * ge.row + col] = x.v[rb][cb][i];
+                for (int i = 0; i < 4; ++i) {
+                    const int ix = opat<T>(rb, gq, i) * ge.row + col;
+                    if constexpr (kCoh)   // device-coherent (work-queue launches)
+                        queue::st(base, ix, 16 * RB * ge.row, x.v[rb][cb][i]);
+                    else
+                        base[ix] = x.v[rb][cb][i];
+                }
         }
     }
 }
@@ -555,16 +572,31 @@ __device__ __forceinline__ void scale_rows(Cols<T, RB, NBW>& x, const int* e, in
         }
 }
 
+// An exponent word another item of a work-queue launch writes or reads
+// (kCoh: device-coherent), at a per-lane address.
+template <bool kCoh>
+__device__ __forceinline__ int ld_int(const GLOBAL int32_t* p) {
+    if constexpr (kCoh) return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return *p;
+}
+template <bool kCoh>
+__device__ __forceinline__ void st_int(GLOBAL int32_t* p, int v) {
+    if constexpr (kCoh)
+        __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else
+        *p = v;
+}
+
 // Stage the own exponents (eloc) of up to three nodes for the tile's
 // patterns in LDS: row c holds node[c]'s, zeros for a tip or a negative id.
 // The caller synchronises.
-template <int TP, int NC>
+template <int TP, int NC, bool kCoh = false>
 __device__ __forceinline__ void stage_exps(int (&esh)[NC][TP], const int (&node)[NC], const ReqDesc& d, int tile) {
     const int N = d.N;
     for (int t = threadIdx.x; t < NC * TP; t += blockDim.x) {
         const int c = t / TP, p = t - c * TP;
         const int x = node[c];
-        esh[c][p] = x >= N ? g(d.eloc)[static_cast<size_t>(x - N) * d.Cpad + tile * TP + p] : 0;
+        esh[c][p] = x >= N ? ld_int<kCoh>(g(d.eloc) + static_cast<size_t>(x - N) * d.Cpad + tile * TP + p) : 0;
     }
 }
 
@@ -588,6 +620,8 @@ struct GlUnit {
     int tile, tiles;
     int node_ix;    // the node's place in its segment
     bool fi, fj;    // child i / j is a folded node (NodeTriple::fold)
+    bool root;      // post-order: the record of the tree root
+    int rec;        // work-queue launches: the record's index in the schedule
 };
 __device__ __forceinline__ bool gl_unit(const ReqDesc* __restrict__ descs, const SegTable& segs, GlUnit& U) {
     const int unit = blockIdx.x;
@@ -604,14 +638,60 @@ __device__ __forceinline__ bool gl_unit(const ReqDesc* __restrict__ descs, const
     U.nt = NodeTriple{t4.x, t4.y, t4.z, 0};
     U.fi = (t4.w & 1) != 0;
     U.fj = (t4.w & 2) != 0;
+    U.root = (U.sg.flags & 1) != 0;
     return true;
+}
+// Work-queue launches (the context's descriptor is descs[0]; tables for
+// every branch): workgroup i takes item t0 + i, a (record, tile) pair.
+__device__ __forceinline__ bool gl_unit(const ReqDesc* __restrict__ descs, const QueueArgs& q, GlUnit& U) {
+    const int t = q.t0 + static_cast<int>(blockIdx.x);
+    if (t >= q.t1) return false;
+    U.d = &descs[0];
+    U.sg = Segment{};
+    U.tiles = U.d->tiles;
+    U.rec = g(q.items)[2 * static_cast<size_t>(t)];
+    U.tile = g(q.items)[2 * static_cast<size_t>(t) + 1];
+    U.node_ix = 0;
+    const I4 t4 = reinterpret_cast<const GLOBAL I4*>(g(U.d->sched))[U.rec];
+    U.nt = NodeTriple{t4.x, t4.y, t4.z, 0};
+    U.fi = (t4.w & 1) != 0;
+    U.fj = (t4.w & 2) != 0;
+    U.root = t4.x == 2 * U.d->N - 2;
+    return true;
+}
+// Marks per (pass, node slot, tile), I = q.n_blocks node slots: a post-order
+// item waits on its stored children, a pre-order item on its parent (which
+// wrote its pre-order vector and exponent); wave 0 polls, then the workgroup
+// synchronises.  At the end every wave's stores complete, then the mark.
+__device__ __forceinline__ void gl_wait(const QueueArgs& q, const GlUnit& U, bool pre, int w, int lane,
+                                        uint32_t target) {
+    if (w == 0) {
+        const ReqDesc& d = *U.d;
+        const int N = d.N;
+        int m = -1;
+        if (!pre) {
+            if (lane == 0 && U.nt.i >= N && !U.fi) m = (U.nt.i - N) * U.tiles + U.tile;
+            if (lane == 1 && U.nt.j >= N && !U.fj) m = (U.nt.j - N) * U.tiles + U.tile;
+        } else if (lane == 0) {
+            const int par = g(q.dep)[2 * static_cast<size_t>(U.rec)];   // the parent's slot, -1 at the root
+            if (par >= 0) m = (q.n_blocks + par) * U.tiles + U.tile;
+        }
+        queue::wait_marks(q, m, target, 2u * q.n_blocks * U.tiles, lane);
+    }
+    __syncthreads();
+}
+__device__ __forceinline__ void gl_done(const QueueArgs& q, const GlUnit& U, bool pre, uint32_t target) {
+    queue::stores_complete();
+    __syncthreads();
+    if (threadIdx.x == 0)
+        queue::set_mark(q, ((pre ? q.n_blocks : 0) + U.nt.k - U.d->N) * U.tiles + U.tile, target,
+                        2u * q.n_blocks * U.tiles);
 }
 
 // ---------------------------------------------------------------- post-order
 
-template <typename T, int RB, int NBW, int W>
-__global__ __launch_bounds__(64 * W) void post_gl_kernel(const ReqDesc* __restrict__ descs,
-                                                         const SegTable segs) {
+template <typename T, int RB, int NBW, int W, bool kQ, typename Arg>
+__device__ __forceinline__ void post_gl_body(const ReqDesc* __restrict__ descs, const Arg& arg) {
     constexpr int TP = 16 * RB;
     constexpr int G = (NBW == 1 && W <= 2) ? 2 : 4;   // gl_vec: 2 up to 32 states
     constexpr int SP = 16 * NBW * W;                // padded states (>= the row length)
@@ -626,7 +706,7 @@ __global__ __launch_bounds__(64 * W) void post_gl_kernel(const ReqDesc* __restri
     const int lane = threadIdx.x & 63;
     const int gq = lane >> 4, n = lane & 15;
     GlUnit U;
-    if (!gl_unit(descs, segs, U)) return;
+    if (!gl_unit(descs, arg, U)) return;
     const ReqDesc& d = *U.d;
     const int N = d.N, S = d.S, R = d.R, Cpad = d.Cpad, tile = U.tile, tiles = U.tiles;
     const NodeTriple nt = U.nt;
@@ -648,10 +728,15 @@ __global__ __launch_bounds__(64 * W) void post_gl_kernel(const ReqDesc* __restri
     // P(t) tables of the children: by branch, or by slot in per-chunk tables
     const int ti = d.level_tables ? 2 * U.node_ix : nt.i, tj = d.level_tables ? 2 * U.node_ix + 1 : nt.j;
     GLOBAL T* out_base = part + (static_cast<size_t>(nt.k - N) * tiles + tile) * tstride;
-    const bool root = U.sg.flags & 1;
+    const bool root = U.root;
+    uint32_t target = 0;
+    if constexpr (kQ) {
+        target = queue::epoch(arg);
+        gl_wait(arg, U, false, w, lane, target);
+    }
     {
         const int kids[2] = {U.fi ? -1 : nt.i, U.fj ? -1 : nt.j};   // a folded child's exponent is 0
-        stage_exps<TP, 2>(esh, kids, d, tile);      // read after the first barrier below
+        stage_exps<TP, 2, kQ>(esh, kids, d, tile);      // read after the first barrier below
     }
     const Input<T, RB> si{vb[0], nullptr}, sj{vb[1], nullptr};
     T mx[RB][4] = {};
@@ -660,11 +745,11 @@ __global__ __launch_bounds__(64 * W) void post_gl_kernel(const ReqDesc* __restri
         if (U.fi)
             stage_folded<T, TP, KIT>(vb[0], d, nt.i, r, tile, bstride, ge);
         else if (pi_base)
-            stage_vec<T, TP, KIT>(vb[0], pi_base + r * rstride, ge);
+            stage_vec<T, TP, KIT, kQ>(vb[0], pi_base + r * rstride, ge);
         if (U.fj)
             stage_folded<T, TP, KIT>(vb[1], d, nt.j, r, tile, bstride, ge);
         else if (pj_base)
-            stage_vec<T, TP, KIT>(vb[1], pj_base + r * rstride, ge);
+            stage_vec<T, TP, KIT, kQ>(vb[1], pj_base + r * rstride, ge);
         __syncthreads();
         Cols<T, RB, NBW> mi, mj, unused;
         if (pi_base) {
@@ -686,7 +771,7 @@ __global__ __launch_bounds__(64 * W) void post_gl_kernel(const ReqDesc* __restri
         mul_cols<T, RB, NBW>(mi, mj);
         if (!root) {
             max_cols<T, RB, NBW>(mi, mx);
-            store_cols<T, RB, NBW>(out_base + r * rstride, ge, cb0, lane, mi);
+            store_cols<T, RB, NBW, kQ>(out_base + r * rstride, ge, cb0, lane, mi);
         } else {
             const double wr = g(d.cweights)[r];
 #pragma unroll
@@ -707,8 +792,8 @@ __global__ __launch_bounds__(64 * W) void post_gl_kernel(const ReqDesc* __restri
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int c = tile * TP + opat<T>(rb, gq, i);
-            ec[rb][i] = (tip_i || U.fi ? 0 : g(d.expo)[static_cast<size_t>(nt.i - N) * Cpad + c]) +
-                        (tip_j || U.fj ? 0 : g(d.expo)[static_cast<size_t>(nt.j - N) * Cpad + c]);
+            ec[rb][i] = (tip_i || U.fi ? 0 : ld_int<kQ>(g(d.expo) + static_cast<size_t>(nt.i - N) * Cpad + c)) +
+                        (tip_j || U.fj ? 0 : ld_int<kQ>(g(d.expo) + static_cast<size_t>(nt.j - N) * Cpad + c));
         }
     if (!root) {
         // a node whose children are both tips given by codes is never
@@ -733,8 +818,8 @@ __global__ __launch_bounds__(64 * W) void post_gl_kernel(const ReqDesc* __restri
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
                     const size_t c = static_cast<size_t>(nt.k - N) * Cpad + tile * TP + opat<T>(rb, gq, i);
-                    g(d.eloc)[c] = e[rb][i];
-                    g(d.expo)[c] = e[rb][i] + ec[rb][i];
+                    st_int<kQ>(g(d.eloc) + c, e[rb][i]);
+                    st_int<kQ>(g(d.expo) + c, e[rb][i] + ec[rb][i]);
                 }
         }
     } else {
@@ -774,15 +859,25 @@ __global__ __launch_bounds__(64 * W) void post_gl_kernel(const ReqDesc* __restri
             if (lane == 0) g(d.lpart)[tile] = tsum;
         }
     }
+    if constexpr (kQ) gl_done(arg, U, false, target);
+}
+
+template <typename T, int RB, int NBW, int W>
+__global__ __launch_bounds__(64 * W) void post_gl_kernel(const ReqDesc* __restrict__ descs, const SegTable segs) {
+    post_gl_body<T, RB, NBW, W, false>(descs, segs);
+}
+// The same over a work-queue launch's items.
+template <typename T, int RB, int NBW, int W>
+__global__ __launch_bounds__(64 * W) void post_gl_queue_kernel(const ReqDesc* __restrict__ descs, const QueueArgs q) {
+    post_gl_body<T, RB, NBW, W, true>(descs, q);
 }
 
 // ---------------------------------------------------------------- pre-order + gradient
 
 // Up to 32 states in FP32 with one row block the kernel fits in 128
 // registers: ask for 4 waves per SIMD.
-template <typename T, int RB, int NBW, int W>
-__global__ __launch_bounds__(64 * W, (W == 2 && RB == 1 && sizeof(T) == 4) ? 4 : 1) void pre_gl_kernel(const ReqDesc* __restrict__ descs,
-                                                        const SegTable segs) {
+template <typename T, int RB, int NBW, int W, bool kQ, typename Arg>
+__device__ __forceinline__ void pre_gl_body(const ReqDesc* __restrict__ descs, const Arg& arg) {
     constexpr int TP = 16 * RB;
     constexpr int G = (NBW == 1 && W <= 2) ? 2 : 4;   // gl_vec: 2 up to 32 states
     constexpr int SP = 16 * NBW * W;                // padded states (>= the row length)
@@ -800,7 +895,7 @@ __global__ __launch_bounds__(64 * W, (W == 2 && RB == 1 && sizeof(T) == 4) ? 4 :
     const int lane = threadIdx.x & 63;
     const int gq = lane >> 4, n = lane & 15;
     GlUnit U;
-    if (!gl_unit(descs, segs, U)) return;
+    if (!gl_unit(descs, arg, U)) return;
     const ReqDesc& d = *U.d;
     const int N = d.N, S = d.S, R = d.R, Cpad = d.Cpad, tile = U.tile, tiles = U.tiles;
     const NodeTriple nt = U.nt;
@@ -828,10 +923,15 @@ __global__ __launch_bounds__(64 * W, (W == 2 && RB == 1 && sizeof(T) == 4) ? 4 :
     // inputs (q is written over p for internal children only)
     const GLOBAL T* pi_src = tip_src<T>(d, nt.i, tile, tiles, tstride, part);
     const GLOBAL T* pj_src = tip_src<T>(d, nt.j, tile, tiles, tstride, part);
+    uint32_t target = 0;
+    if constexpr (kQ) {
+        target = queue::epoch(arg);
+        gl_wait(arg, U, true, w, lane, target);
+    }
     {
         // a folded child's exponent is 0 (folding happens only where kStage)
         const int nodes[3] = {U.fi ? -1 : nt.i, U.fj ? -1 : nt.j, is_root ? -1 : nt.k};
-        stage_exps<TP, 3>(esh, nodes, d, tile);
+        stage_exps<TP, 3, kQ>(esh, nodes, d, tile);
     }
     if constexpr (!kStage) __syncthreads();    // exponents in LDS (staging has its own barrier)
     si.lds = kStage && pi_src ? vb[0] : nullptr;
@@ -849,7 +949,7 @@ __global__ __launch_bounds__(64 * W, (W == 2 && RB == 1 && sizeof(T) == 4) ? 4 :
                 stage_folded<T, TP, KIT>(vb[1], d, nt.j, r, tile, bstride, ge);
             else if (pj_src)
                 stage_vec<T, TP, KIT>(vb[1], pj_src + r * rstride, ge);
-            if (!is_root) stage_vec<T, TP, KIT>(vb[kStage ? 2 : 0], qk_base + r * rstride, ge);
+            if (!is_root) stage_vec<T, TP, KIT, kQ>(vb[kStage ? 2 : 0], qk_base + r * rstride, ge);
             __syncthreads();  // inputs of category r staged
         }
         const size_t mo_i = (static_cast<size_t>(ti) * R + r) * mstride;
@@ -870,7 +970,7 @@ __global__ __launch_bounds__(64 * W, (W == 2 && RB == 1 && sizeof(T) == 4) ? 4 :
             if constexpr (kStage)
                 vbuf_to_cols<T, RB, NBW>(vb[kStage ? 2 : 0], ge, cb0, lane, qk);
             else
-                load_cols<T, RB, NBW>(qk_base + r * rstride, ge, cb0, lane, qk);
+                load_cols<T, RB, NBW, kQ>(qk_base + r * rstride, ge, cb0, lane, qk);
             scale_rows<T, RB, NBW>(qk, esh[2], lane);
         }
         if (pj_src) {
@@ -912,12 +1012,12 @@ __global__ __launch_bounds__(64 * W, (W == 2 && RB == 1 && sizeof(T) == 4) ? 4 :
         if (!tip_i) {
             bwd<T, RB, NBW, G>(PB + bo_i, vb[0], ge, cb0, lane, acc);    // q_i = P_i^T u_i, stored over p_i
             max_cols<T, RB, NBW>(acc, mxi);
-            store_cols<T, RB, NBW>(pi_base + r * rstride, ge, cb0, lane, acc);
+            store_cols<T, RB, NBW, kQ>(pi_base + r * rstride, ge, cb0, lane, acc);
         }
         if (!tip_j) {
             bwd<T, RB, NBW, G>(PB + bo_j, vb[1], ge, cb0, lane, acc);
             max_cols<T, RB, NBW>(acc, mxj);
-            store_cols<T, RB, NBW>(pj_base + r * rstride, ge, cb0, lane, acc);
+            store_cols<T, RB, NBW, kQ>(pj_base + r * rstride, ge, cb0, lane, acc);
         }
         __syncthreads();      // before the next category's staging overwrites u
     }
@@ -937,7 +1037,8 @@ __global__ __launch_bounds__(64 * W, (W == 2 && RB == 1 && sizeof(T) == 4) ? 4 :
             for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
                 for (int i = 0; i < 4; ++i)
-                    g(d.eloc)[static_cast<size_t>(nt.i - N) * Cpad + tile * TP + opat<T>(rb, gq, i)] = e[rb][i];
+                    st_int<kQ>(g(d.eloc) + static_cast<size_t>(nt.i - N) * Cpad + tile * TP + opat<T>(rb, gq, i),
+                               e[rb][i]);
         }
     }
     if (!tip_j) {
@@ -956,7 +1057,8 @@ __global__ __launch_bounds__(64 * W, (W == 2 && RB == 1 && sizeof(T) == 4) ? 4 :
             for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
                 for (int i = 0; i < 4; ++i)
-                    g(d.eloc)[static_cast<size_t>(nt.j - N) * Cpad + tile * TP + opat<T>(rb, gq, i)] = e[rb][i];
+                    st_int<kQ>(g(d.eloc) + static_cast<size_t>(nt.j - N) * Cpad + tile * TP + opat<T>(rb, gq, i),
+                               e[rb][i]);
         }
     }
     // per-pattern sums over all states: this wave's part, then the waves in order
@@ -1012,6 +1114,19 @@ __global__ __launch_bounds__(64 * W, (W == 2 && RB == 1 && sizeof(T) == 4) ? 4 :
             g(d.gpart)[static_cast<size_t>(nt.j) * tiles + tile] = gj;
         }
     }
+    if constexpr (kQ) gl_done(arg, U, true, target);
+}
+
+template <typename T, int RB, int NBW, int W>
+__global__ __launch_bounds__(64 * W, (W == 2 && RB == 1 && sizeof(T) == 4) ? 4 : 1)
+void pre_gl_kernel(const ReqDesc* __restrict__ descs, const SegTable segs) {
+    pre_gl_body<T, RB, NBW, W, false>(descs, segs);
+}
+// The same over a work-queue launch's items.
+template <typename T, int RB, int NBW, int W>
+__global__ __launch_bounds__(64 * W, (W == 2 && RB == 1 && sizeof(T) == 4) ? 4 : 1)
+void pre_gl_queue_kernel(const ReqDesc* __restrict__ descs, const QueueArgs q) {
+    pre_gl_body<T, RB, NBW, W, true>(descs, q);
 }
 
 // ---------------------------------------------------------------- P(t) tables
@@ -1033,6 +1148,9 @@ __global__ __launch_bounds__(256) void pmat_gl_kernel(const ReqDesc* __restrict_
     __shared__ double ex[256], dex[256], wsum[256];
     __shared__ __align__(16) double As[kPmK][kPmTile], Be[kPmK][kPmTile], Bd[kPmK][kPmTile];
     const int unit = blockIdx.x;
+    // a new evaluation of a work-queue context
+    if (unit == 0 && blockIdx.y == 0 && threadIdx.x == 0 && descs[segs.seg[0].desc].qctr)
+        queue::new_evaluation(descs[segs.seg[0].desc].qctr);
     if (unit >= segs.unit_begin[segs.n]) return;
     const int sidx = seg_of(segs, unit);
     const Segment& sg = segs.seg[sidx];
@@ -1142,9 +1260,13 @@ __global__ __launch_bounds__(256) void pmat_gl_kernel(const ReqDesc* __restrict_
         }
 }
 
-template <typename T>
-hipError_t launch_gl_t(KernelClass k, int S, int rb, const ReqDesc* descs, const SegTable& t, hipStream_t st) {
-    const int n_units = t.unit_begin[t.n];
+template <typename T, bool kQ = false, typename Arg>
+hipError_t launch_gl_t(KernelClass k, int S, int rb, const ReqDesc* descs, const Arg& t, hipStream_t st) {
+    int n_units = 0;
+    if constexpr (kQ)
+        n_units = t.t1 - t.t0;
+    else
+        n_units = t.unit_begin[t.n];
     // up to 128 states: one 16-state block per wave, ceil(S / 16) waves (at
     // 65..128 eight waves of one block beat four of two: fewer registers and
     // matrix loads per wave).  Above: FP32 four waves of ceil(S / 64) blocks
@@ -1155,12 +1277,21 @@ hipError_t launch_gl_t(KernelClass k, int S, int rb, const ReqDesc* descs, const
     const int w = S <= 128 ? (S + 15) / 16 : (f32 ? 4 : (S + 31) / 32);
 #define PHG_GL_CASE(RBV, NBV, WV)                                                                           \
     if (rb == RBV && nbw == NBV && w == WV) {                                                             \
-        if (k == kPost)                                                                                     \
-            hipLaunchKernelGGL((post_gl_kernel<T, RBV, NBV, WV>), dim3(n_units), dim3(64 * WV), 0, st, descs, \
-                               t);                                                                          \
-        else                                                                                                \
-            hipLaunchKernelGGL((pre_gl_kernel<T, RBV, NBV, WV>), dim3(n_units), dim3(64 * WV), 0, st, descs,  \
-                               t);                                                                          \
+        if constexpr (kQ) {                                                                                 \
+            if (k == kPost)                                                                                 \
+                hipLaunchKernelGGL((post_gl_queue_kernel<T, RBV, NBV, WV>), dim3(n_units), dim3(64 * WV), 0, \
+                                   st, descs, t);                                                           \
+            else                                                                                            \
+                hipLaunchKernelGGL((pre_gl_queue_kernel<T, RBV, NBV, WV>), dim3(n_units), dim3(64 * WV), 0,  \
+                                   st, descs, t);                                                           \
+        } else {                                                                                            \
+            if (k == kPost)                                                                                 \
+                hipLaunchKernelGGL((post_gl_kernel<T, RBV, NBV, WV>), dim3(n_units), dim3(64 * WV), 0, st,  \
+                                   descs, t);                                                               \
+            else                                                                                            \
+                hipLaunchKernelGGL((pre_gl_kernel<T, RBV, NBV, WV>), dim3(n_units), dim3(64 * WV), 0, st,   \
+                                   descs, t);                                                               \
+        }                                                                                                   \
         return hipGetLastError();                                                                           \
     }
     if constexpr (sizeof(T) == 4) {
@@ -1218,6 +1349,16 @@ hipError_t launch_level_gl(KernelClass k, const ReqDesc& shape, const ReqDesc* d
     const int rb = shape.Cpad / shape.tiles / 16;   // the context's own tile
     if (shape.fp32) return launch_gl_t<float>(k, shape.S, rb, descs, t, st);
     return launch_gl_t<double>(k, shape.S, rb, descs, t, st);
+}
+
+hipError_t launch_gl_queue(const ReqDesc& shape, const ReqDesc* descs, const QueueArgs& q, int pass,
+                           hipStream_t st) {
+    if (q.t1 <= q.t0) return hipSuccess;
+    if (pass != 1 && pass != 2) return hipErrorInvalidValue;
+    const KernelClass k = pass == 1 ? kPost : kPre;
+    const int rb = shape.Cpad / shape.tiles / 16;
+    if (shape.fp32) return launch_gl_t<float, true>(k, shape.S, rb, descs, q, st);
+    return launch_gl_t<double, true>(k, shape.S, rb, descs, q, st);
 }
 
 }  // namespace phg

@@ -226,9 +226,10 @@ def test_queue_schedule_is_opt_in_and_checked():
         assert e.value.status == B.PHG_ERR_ARG
     finally:
         B.phg_destroy(ctx)
-    # 4 states: FP32 and R in {1, 2, 4, 8}; else the vector-ALU kernels' shapes
-    for S, R, prec in ((4, 4, B.PHG_FP64), (4, 3, B.PHG_FP32_SCALED), (20, 3, B.PHG_FP32_SCALED),
-                       (61, 4, B.PHG_FP32_SCALED), (32, 4, B.PHG_FP64)):
+    # 4 states: FP32 and R in {1, 2, 4, 8}; else the vector-ALU and MFMA
+    # kernels' shapes (17..256 states), not the small-state MFMA kernels
+    for S, R, prec in ((4, 4, B.PHG_FP64), (4, 3, B.PHG_FP32_SCALED), (8, 4, B.PHG_FP32_SCALED),
+                       (16, 2, B.PHG_FP64), (4, 16, B.PHG_FP32_SCALED)):
         ctx = B.phg_create(30, 10, S, R, prec, 0)
         try:
             with pytest.raises(B.PhgError) as e:
@@ -236,7 +237,8 @@ def test_queue_schedule_is_opt_in_and_checked():
             assert e.value.status == B.PHG_ERR_ARG
         finally:
             B.phg_destroy(ctx)
-    for S, prec in ((20, B.PHG_FP32_SCALED), (32, B.PHG_FP32_SCALED), (20, B.PHG_FP64)):
+    for S, prec in ((20, B.PHG_FP32_SCALED), (32, B.PHG_FP32_SCALED), (20, B.PHG_FP64), (61, B.PHG_FP32_SCALED),
+                    (200, B.PHG_FP64)):
         ctx = B.phg_create(30, 10, S, 4, prec, 0)
         try:
             B.phg_set_topology(ctx, synth.yule_topology(30, np.random.default_rng(5)))

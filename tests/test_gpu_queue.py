@@ -2,9 +2,8 @@
 
 4 states (FP32): the blocked schedule's arithmetic in one launch per pass
 (or one for both), items waiting on per-(block, tile) completion marks
-instead of level launches.  17..32 states on the vector-ALU kernels (FP32,
-and FP64 to 24 states): the level schedule's records as items, one launch
-per pass.  Results must equal the level-launched schedule's bit for bit --
+instead of level launches.  17..256 states on the vector-ALU and MFMA
+kernels: the level schedule's records as items, one launch per pass.  Results must equal the level-launched schedule's bit for bit --
 which the oracle parity tests hold to their bars -- on every tree shape,
 category count, launch mode, repeated evaluations (the marks' epochs),
 library-owned graph replays and the log-likelihood-only path.  Some cases
@@ -143,3 +142,20 @@ def test_queue_vector_alu_tip_vectors():
             assert B.phg_get_schedule(ctx.handle) == schedule
             outs.append(ctx.gradient())
     assert outs[0][0] == outs[1][0] and np.array_equal(outs[0][1], outs[1][1])
+
+
+# MFMA kernels (17..256 states outside the vector-ALU shapes): one and two
+# row blocks, FP32 and FP64, folded tip-tip nodes above 32 states, R = 3
+@pytest.mark.parametrize("N,C,S,R,prec,seed", [(9, 64, 61, 4, F32, 41), (70, 130, 61, 4, F32, 42),
+                                               (70, 130, 61, 4, B.PHG_FP64, 43), (40, 90, 33, 3, F32, 44),
+                                               (50, 70, 20, 3, F32, 45), (30, 40, 122, 2, F32, 46),
+                                               (20, 33, 200, 2, B.PHG_FP64, 47), (2, 20, 61, 1, F32, 48)])
+def test_queue_mfma_equals_levels(N, C, S, R, prec, seed):
+    _same(f"mfma-N{N}-C{C}", _problem(N, C, R, seed, S=S, mean_b=0.1), prec)
+
+
+def test_queue_mfma_caterpillar_and_oracle():
+    _same("mfma-caterpillar80", _problem(80, 50, 2, 49, caterpillar=True, mean_b=0.05, S=61))
+    prob = _problem(60, 100, 4, 50, S=61, mean_b=0.1)
+    ref = _same("mfma-N60-C100", prob)
+    check("queue/mfma-N60-C100", ref[0], ref[1], oracle.evaluate_problem(prob), 1e-6, 1e-4)
