@@ -235,7 +235,10 @@ typedef enum {
                                    that takes the one-round-trip narrow variant */
     PHG_TUNE_QUEUE_LAUNCHES = 2,  /* 4 states, QUEUE schedule: launches per evaluation with the
                                      gradient (1: both passes in one; 2, the default: one per pass) */
-    PHG_TUNE_PARAMS = 3
+    PHG_TUNE_QUEUE_WAIT_US = 3,   /* QUEUE schedule: microseconds a work item waits on another before
+                                     the evaluation is abandoned as faulty (NaN results,
+                                     PHG_ERR_NUMERIC); default 2 s.  A tiny value forces that path. */
+    PHG_TUNE_PARAMS = 4
 } phg_tune_param;
 
 /* n_categories = 0: any category count.  PHG_ERR_ARG for an unknown

@@ -386,6 +386,7 @@ def phg_graph_stats(ctx):
 PHG_TUNE_ROW_BLOCKS = 0
 PHG_TUNE_NARROW_UNITS = 1
 PHG_TUNE_QUEUE_LAUNCHES = 2
+PHG_TUNE_QUEUE_WAIT_US = 3
 
 
 def phg_set_tuning(n_states: int, n_categories: int, prec: int, param: int, value: int):

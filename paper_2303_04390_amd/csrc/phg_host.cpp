@@ -193,6 +193,7 @@ bool tune_value_ok(int S, int R, bool fp32, int param, int value) {
         return S > 16 && phg::gl_row_blocks_allowed(S, fp32, value);   // read by the MFMA kernels only
     if (param == PHG_TUNE_NARROW_UNITS) return S == 4 && fp32;
     if (param == PHG_TUNE_QUEUE_LAUNCHES) return S == 4 && fp32 && value <= 2;
+    if (param == PHG_TUNE_QUEUE_WAIT_US) return phg::queue_supported(S, R, fp32);
     return false;
 }
 
@@ -756,8 +757,9 @@ int tuned_value(int S, int R, bool fp32, int param) {
     return it == g_tune.end() ? 0 : it->second;
 }
 
-// kQueueWaitMs of the device's constant clock, in its ticks.
-uint64_t queue_wait_ticks(int device) {
+// The wait bound of a work item in ticks of the device's constant clock:
+// kQueueWaitMs, or the tuned microseconds.
+uint64_t queue_wait_ticks(int device, int S, int R, bool fp32) {
     static std::atomic<int> khz[64];
     const int dev = device >= 0 && device < 64 ? device : 0;
     int rate = khz[dev].load();
@@ -766,7 +768,9 @@ uint64_t queue_wait_ticks(int device) {
             rate = 100000;                                   // 100 MHz
         khz[dev].store(rate);
     }
-    return static_cast<uint64_t>(rate) * kQueueWaitMs;
+    const int us = tuned_value(S, R, fp32, PHG_TUNE_QUEUE_WAIT_US);
+    return us > 0 ? std::max<uint64_t>(1, static_cast<uint64_t>(rate) * us / 1000)
+                  : static_cast<uint64_t>(rate) * kQueueWaitMs;
 }
 
 int queue_launches(int S, int R, bool fp32) {
@@ -814,7 +818,7 @@ phg_status ctx_enqueue_eval(phg_context* ctx, double* d_logl, double* d_grad) {
         q.ctr = reinterpret_cast<uint32_t*>(a + pl.qctr);
         q.n_blocks = ctx->q_blocks;
         q.root_rec = ctx->pre_lv.front().first;
-        q.wait_ticks = queue_wait_ticks(ctx->device);
+        q.wait_ticks = queue_wait_ticks(ctx->device, d.S, d.R, d.fp32 != 0);
         const int n_items = static_cast<int>(ctx->qitems.size() / 2);
         const bool one_launch =
             d_grad && !ctx->prof_on && d.S == 4 && queue_launches(d.S, d.R, d.fp32 != 0) == 1;

@@ -176,7 +176,7 @@ constexpr int kQueueEpoch = 0, kQueueFault = 16, kQueueWords = 32;
 // Milliseconds before a dependency wait gives up: far above any legitimate
 // wait (an item waits only on items already running).
 constexpr int kQueueWaitMs = 2000;
-uint64_t queue_wait_ticks(int device);
+uint64_t queue_wait_ticks(int device, int S, int R, bool fp32);
 // Launches per evaluation with the gradient (1: both passes in one, 2: one per
 // pass) unless tuned (PHG_TUNE_QUEUE_LAUNCHES).
 constexpr int kQueueLaunchesDefault = 2;

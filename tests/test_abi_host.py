@@ -256,6 +256,13 @@ def test_queue_schedule_is_opt_in_and_checked():
     for S, prec, v in ((4, B.PHG_FP32_SCALED, 3), (4, B.PHG_FP64, 1), (20, B.PHG_FP32_SCALED, 1)):
         with pytest.raises(B.PhgError):
             B.phg_set_tuning(S, 0, prec, B.PHG_TUNE_QUEUE_LAUNCHES, v)
+    # the wait bound: wherever the queue runs
+    for S, prec in ((4, B.PHG_FP32_SCALED), (20, B.PHG_FP64), (61, B.PHG_FP32_SCALED)):
+        B.phg_set_tuning(S, 0, prec, B.PHG_TUNE_QUEUE_WAIT_US, 5)
+        assert B.phg_get_tuning(S, 0, prec, B.PHG_TUNE_QUEUE_WAIT_US) == 5
+        B.phg_set_tuning(S, 0, prec, B.PHG_TUNE_QUEUE_WAIT_US, 0)
+    with pytest.raises(B.PhgError):
+        B.phg_set_tuning(4, 0, B.PHG_FP64, B.PHG_TUNE_QUEUE_WAIT_US, 5)
 
 
 def test_time_tree_and_branch_set_validation():

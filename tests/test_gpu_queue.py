@@ -159,3 +159,27 @@ def test_queue_mfma_caterpillar_and_oracle():
     prob = _problem(60, 100, 4, 50, S=61, mean_b=0.1)
     ref = _same("mfma-N60-C100", prob)
     check("queue/mfma-N60-C100", ref[0], ref[1], oracle.evaluate_problem(prob), 1e-6, 1e-4)
+
+
+@pytest.mark.parametrize("S", [4, 20])
+def test_queue_wait_bound_fault_path(S):
+    # a work item that waits past the bound abandons the evaluation: the final
+    # sums turn to NaN and the synchronous call reports PHG_ERR_NUMERIC; with
+    # the default bound the next evaluation through the same context is exact
+    # again (its P(t) launch clears the fault word).  A caterpillar makes every
+    # item wait on the one before, so a 1 us bound is always exceeded; the
+    # kernels exit normally either way.
+    prob = _problem(300 if S == 4 else 120, 64, 4, 60, caterpillar=True, mean_b=0.02, S=S)
+    (ref, *_), _ = _run(prob, B.PHG_SCHEDULE_BLOCKS if S == 4 else B.PHG_SCHEDULE_LEVELS, repeats=1)
+    with B.Context.for_problem(prob, F32, schedule=B.PHG_SCHEDULE_QUEUE) as ctx:
+        B.phg_set_fp32_guard(ctx.handle, 0.0)
+        B.phg_set_graphs(ctx.handle, False)
+        B.phg_set_tuning(S, 0, F32, B.PHG_TUNE_QUEUE_WAIT_US, 1)
+        try:
+            with pytest.raises(B.PhgError) as e:
+                ctx.gradient()
+            assert e.value.status == B.PHG_ERR_NUMERIC
+        finally:
+            B.phg_set_tuning(S, 0, F32, B.PHG_TUNE_QUEUE_WAIT_US, 0)
+        logl, grad = ctx.gradient()
+        assert logl == ref[0] and np.array_equal(grad, ref[1])
