@@ -49,10 +49,12 @@ def row_block_candidates(S, fp32):
     return [2] if fp32 else [1]
 
 
-def _time_evals(B, prob, prec, steps, warmup, stream, out):
+def _time_evals(B, prob, prec, steps, warmup, stream, out, schedule=0):
     import torch
     h = B.phg_create(prob.n_tips, prob.n_patterns, prob.n_states, prob.n_categories, prec, 0)
     try:
+        if schedule:
+            B.phg_set_schedule(h, schedule)
         B.phg_bind_stream(h, stream.cuda_stream)
         B.set_problem(h, prob)
         B.phg_prepare(h)
@@ -83,30 +85,35 @@ def tune(workloads, steps=10, warmup=2, reps=3, log=print):
         cfg, kw = WORKLOADS[name]
         prob = synth.config_problem(cfg, seed=0, **kw)
         S, R = prob.n_states, prob.n_categories
+        sweeps = []
         for prec in (B.PHG_FP32_SCALED, B.PHG_FP64):
             fp32 = prec == B.PHG_FP32_SCALED
             if S == 4:
                 if not fp32:
                     continue
-                param = B.PHG_TUNE_NARROW_UNITS
-                # the default rule admits launches that fit at 5 waves per SIMD
+                # level launches: the default rule admits launches that fit at
+                # 5 waves per SIMD; work-queue traversal: one launch per pass (0)
+                # or both in one
                 base = 256 * 4 * 5 // R
-                cands = [0, 1, base // 2, base * 2, base * 4]
+                sweeps.append((prec, B.PHG_TUNE_NARROW_UNITS, [0, 1, base // 2, base * 2, base * 4], 0))
+                sweeps.append((prec, B.PHG_TUNE_QUEUE_LAUNCHES, [0, 1], B.PHG_SCHEDULE_QUEUE))
             else:
                 # row blocks exist only on the MFMA kernels
                 if B.phg_kernel_family_of(S, R, prec) != B.PHG_KERNELS_MFMA:
                     continue
-                param = B.PHG_TUNE_ROW_BLOCKS
                 cands = [0] + row_block_candidates(S, fp32)
                 if len(cands) < 3:
                     continue
+                sweeps.append((prec, B.PHG_TUNE_ROW_BLOCKS, cands, 0))
+        for prec, param, cands, schedule in sweeps:
+            fp32 = prec == B.PHG_FP32_SCALED
             # candidates timed in interleaved rounds; each keeps its median
             times = {v: [] for v in cands}
             ref_logl = None
             for _ in range(reps):
                 for v in cands:
                     B.phg_set_tuning(S, 0, prec, param, v)
-                    ms, logl = _time_evals(B, prob, prec, steps, warmup, stream, out)
+                    ms, logl = _time_evals(B, prob, prec, steps, warmup, stream, out, schedule)
                     if ref_logl is None:
                         ref_logl = logl
                     elif abs(logl - ref_logl) > 1e-6 * abs(ref_logl):
