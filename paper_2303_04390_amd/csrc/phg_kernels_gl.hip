@@ -862,20 +862,27 @@ __device__ __forceinline__ void post_gl_body(const ReqDesc* __restrict__ descs, 
     if constexpr (kQ) gl_done(arg, U, false, target);
 }
 
+// FP32, one row block, four waves: 78 registers, so 6 waves per SIMD fit
+// without spilling (1% on the 61-state level launches).
 template <typename T, int RB, int NBW, int W>
-__global__ __launch_bounds__(64 * W) void post_gl_kernel(const ReqDesc* __restrict__ descs, const SegTable segs) {
+__global__ __launch_bounds__(64 * W, (RB == 1 && W == 4 && sizeof(T) == 4) ? 6 : 1)
+void post_gl_kernel(const ReqDesc* __restrict__ descs, const SegTable segs) {
     post_gl_body<T, RB, NBW, W, false>(descs, segs);
 }
 // The same over a work-queue launch's items.
 template <typename T, int RB, int NBW, int W>
-__global__ __launch_bounds__(64 * W) void post_gl_queue_kernel(const ReqDesc* __restrict__ descs, const QueueArgs q) {
+__global__ __launch_bounds__(64 * W, (RB == 1 && W == 4 && sizeof(T) == 4) ? 6 : 1)
+void post_gl_queue_kernel(const ReqDesc* __restrict__ descs, const QueueArgs q) {
     post_gl_body<T, RB, NBW, W, true>(descs, q);
 }
 
 // ---------------------------------------------------------------- pre-order + gradient
 
-// Up to 32 states in FP32 with one row block the kernel fits in 128
-// registers: ask for 4 waves per SIMD.
+// FP32 with one row block and two or four waves (up to 32 states, and 49..64
+// states where one row block is chosen) the kernel fits in 128 registers:
+// ask for 4 waves per SIMD (61 states: 3 waves at 136 registers before,
+// 2.29 -> 2.17 ms per 128-taxon evaluation).  FP64 asked for 3 waves spills
+// and is slower.
 template <typename T, int RB, int NBW, int W, bool kQ, typename Arg>
 __device__ __forceinline__ void pre_gl_body(const ReqDesc* __restrict__ descs, const Arg& arg) {
     constexpr int TP = 16 * RB;
@@ -1118,13 +1125,13 @@ __device__ __forceinline__ void pre_gl_body(const ReqDesc* __restrict__ descs, c
 }
 
 template <typename T, int RB, int NBW, int W>
-__global__ __launch_bounds__(64 * W, (W == 2 && RB == 1 && sizeof(T) == 4) ? 4 : 1)
+__global__ __launch_bounds__(64 * W, (RB == 1 && sizeof(T) == 4 && (W == 2 || W == 4)) ? 4 : 1)
 void pre_gl_kernel(const ReqDesc* __restrict__ descs, const SegTable segs) {
     pre_gl_body<T, RB, NBW, W, false>(descs, segs);
 }
 // The same over a work-queue launch's items.
 template <typename T, int RB, int NBW, int W>
-__global__ __launch_bounds__(64 * W, (W == 2 && RB == 1 && sizeof(T) == 4) ? 4 : 1)
+__global__ __launch_bounds__(64 * W, (RB == 1 && sizeof(T) == 4 && (W == 2 || W == 4)) ? 4 : 1)
 void pre_gl_queue_kernel(const ReqDesc* __restrict__ descs, const QueueArgs q) {
     pre_gl_body<T, RB, NBW, W, true>(descs, q);
 }
