@@ -561,9 +561,12 @@ __global__ __launch_bounds__(kLanes * R) void post_blk_kernel(const ReqDesc* __r
     }
 }
 
+// FP64 asks for 4 waves per SIMD: 133-139 registers otherwise (3 waves);
+// at 128 it spills 20-52 bytes per lane and still runs faster (1000-taxon
+// HKY+G4 evaluation 1.074 -> 1.008 ms, results bit for bit the same).
 template <typename T, int R>
-__global__ __launch_bounds__(kLanes * R) void pre_blk_kernel(const ReqDesc* __restrict__ descs,
-                                                             const SegTable segs) {
+__global__ __launch_bounds__(kLanes * R, sizeof(T) == 8 ? 4 : 1) void pre_blk_kernel(const ReqDesc* __restrict__ descs,
+                                                                                     const SegTable segs) {
     __shared__ Xch<T, R> xch;
     const int r = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & (kLanes - 1);
