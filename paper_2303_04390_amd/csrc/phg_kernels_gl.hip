@@ -159,10 +159,15 @@ struct Input {
 
 // k-steps whose operands are loaded together before their MFMAs run (one
 // memory round trip per chunk instead of one per step): 8, or 4 for f64 with
-// three or more column blocks per wave and for four (registers).
-template <typename T, int NBW>
+// two row blocks or three or more column blocks per wave, and for four
+// column blocks (registers).  With two f64 row blocks at eight waves the
+// smaller chunk ends most of the pre-order spill (192 -> 48 bytes per lane)
+// and fits two post-order workgroups per CU (160 -> 128 registers): 122
+// states 131 -> 148 evaluations/s; with two f64 column blocks (240 states)
+// it measured slower (61 -> 51).
+template <typename T, int RB, int NBW>
 constexpr int chunk_of() {
-    return ((sizeof(T) == 8 && NBW >= 3) || NBW >= 4) ? 4 : 8;
+    return ((sizeof(T) == 8 && (RB >= 2 || NBW >= 3)) || NBW >= 4) ? 4 : 8;
 }
 
 // Operand geometry shared by the products of one kernel.
@@ -276,7 +281,7 @@ template <typename T, int RB, int NBW, int G, bool kTwo, bool kLds = true>
 __device__ __forceinline__ void fwd(const GLOBAL T* __restrict__ M1, const GLOBAL T* __restrict__ M2,
                                     const Input<T, RB>& in, const Geo& ge, int cb0, int lane,
                                     Cols<T, RB, NBW>& out1, Cols<T, RB, NBW>& out2) {
-    constexpr int kChunk = chunk_of<T, NBW>();
+    constexpr int kChunk = chunk_of<T, RB, NBW>();
     const int gq = lane >> 4, n = lane & 15;
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb)
@@ -347,7 +352,7 @@ __device__ __forceinline__ void fwd(const GLOBAL T* __restrict__ M1, const GLOBA
 template <typename T, int RB, int NBW, int G>
 __device__ __forceinline__ void bwd(const GLOBAL T* __restrict__ MB, const T* U, const Geo& ge, int cb0,
                                     int lane, Cols<T, RB, NBW>& out) {
-    constexpr int kChunk = chunk_of<T, NBW>();
+    constexpr int kChunk = chunk_of<T, RB, NBW>();
     const int gq = lane >> 4, n = lane & 15;
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb)
