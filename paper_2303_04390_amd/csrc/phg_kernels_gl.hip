@@ -158,16 +158,18 @@ struct Input {
 };
 
 // k-steps whose operands are loaded together before their MFMAs run (one
-// memory round trip per chunk instead of one per step): 8, or 4 for f64 with
-// two row blocks or three or more column blocks per wave, and for four
+// memory round trip per chunk instead of one per step): 8, or 4 for f64
+// except with one row block of two column blocks per wave, and for four
 // column blocks (registers).  With two f64 row blocks at eight waves the
-// smaller chunk ends most of the pre-order spill (192 -> 48 bytes per lane)
-// and fits two post-order workgroups per CU (160 -> 128 registers): 122
-// states 131 -> 148 evaluations/s; with two f64 column blocks (240 states)
-// it measured slower (61 -> 51).
+// smaller chunk ends most of the pre-order spill (192 -> 48 bytes per
+// lane) and fits two post-order workgroups per CU (160 -> 128 registers):
+// 122 states 131 -> 148 evaluations/s.  With one f64 row block and column
+// block it takes the pre-order kernel to 158 registers, 3 waves per SIMD
+// without spilling (61 states 227 -> 238).  With two f64 column blocks
+// (240 states) it measured slower (61 -> 51).
 template <typename T, int RB, int NBW>
 constexpr int chunk_of() {
-    return ((sizeof(T) == 8 && (RB >= 2 || NBW >= 3)) || NBW >= 4) ? 4 : 8;
+    return ((sizeof(T) == 8 && (RB >= 2 || NBW != 2)) || NBW >= 4) ? 4 : 8;
 }
 
 // Operand geometry shared by the products of one kernel.
@@ -886,8 +888,8 @@ void post_gl_queue_kernel(const ReqDesc* __restrict__ descs, const QueueArgs q) 
 // FP32 with one row block and two or four waves (up to 32 states, and 49..64
 // states where one row block is chosen) the kernel fits in 128 registers:
 // ask for 4 waves per SIMD (61 states: 3 waves at 136 registers before,
-// 2.29 -> 2.17 ms per 128-taxon evaluation).  FP64 asked for 3 waves spills
-// and is slower.
+// 2.29 -> 2.17 ms per 128-taxon evaluation).  FP64 with one row block and
+// four waves asks for 3 (158 registers with operand chunks of 4).
 template <typename T, int RB, int NBW, int W, bool kQ, typename Arg>
 __device__ __forceinline__ void pre_gl_body(const ReqDesc* __restrict__ descs, const Arg& arg) {
     constexpr int TP = 16 * RB;
@@ -1130,13 +1132,13 @@ __device__ __forceinline__ void pre_gl_body(const ReqDesc* __restrict__ descs, c
 }
 
 template <typename T, int RB, int NBW, int W>
-__global__ __launch_bounds__(64 * W, (RB == 1 && sizeof(T) == 4 && (W == 2 || W == 4)) ? 4 : 1)
+__global__ __launch_bounds__(64 * W, (RB == 1 && sizeof(T) == 4 && (W == 2 || W == 4)) ? 4 : (RB == 1 && W == 4 && sizeof(T) == 8) ? 3 : 1)
 void pre_gl_kernel(const ReqDesc* __restrict__ descs, const SegTable segs) {
     pre_gl_body<T, RB, NBW, W, false>(descs, segs);
 }
 // The same over a work-queue launch's items.
 template <typename T, int RB, int NBW, int W>
-__global__ __launch_bounds__(64 * W, (RB == 1 && sizeof(T) == 4 && (W == 2 || W == 4)) ? 4 : 1)
+__global__ __launch_bounds__(64 * W, (RB == 1 && sizeof(T) == 4 && (W == 2 || W == 4)) ? 4 : (RB == 1 && W == 4 && sizeof(T) == 8) ? 3 : 1)
 void pre_gl_queue_kernel(const ReqDesc* __restrict__ descs, const QueueArgs q) {
     pre_gl_body<T, RB, NBW, W, true>(descs, q);
 }
